@@ -1,0 +1,463 @@
+"""Pins of the CPU oracle to facts fixed by the paper and by mathematics.
+
+Each test checks the oracle against something other than itself: a value the
+paper prints, a closed form, an invariant, a dense eigendecomposition built by
+numpy, or a library routine (numpy.fft, scipy.linalg.expm, scipy.special.jv).
+"""
+
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.optimize
+import scipy.special
+
+import oracle
+import oracle.dense as dense
+from workloads import (circular_ladder_edges, erdos_renyi_edges, maxcut_qualities,
+                       portfolio_qualities, random_regular_edges, ring_edges,
+                       random_symmetric_lambda)
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rand_state(rng, N):
+    v = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    return v / np.linalg.norm(v)
+
+
+# ------------------------------------------------------------------ paper
+def _example1():
+    with open(os.path.join(GOLDEN, "example1_maxcut_cl4.json")) as fh:
+        return json.load(fh)
+
+
+def test_example1_printed_objective(oracle_mod):
+    """Sec. 5.1.1: CL_4 max-cut at depth 2 ends near f = 2.30 at x = (3.59, 6.88,
+    3.95, 5.92); the optimal state 90 (q_90 = 0) is the most probable one."""
+    g = _example1()
+    edges = circular_ladder_edges(4)
+    q = oracle.maxcut_quality_loop(8, edges, uncut=True)
+    x = np.array(g["x_printed"])
+    psi, f, nrm = oracle.evolve("x", q, x[0::2], x[1::2])
+    assert abs(f - g["f_printed_approx"]) < 0.01
+    assert q[g["optimal_state_index"]] == g["optimal_state_quality"]
+    bits = [(g["optimal_state_index"] >> v) & 1 for v in range(8)]
+    assert bits == g["optimal_state_bits_printed"]
+    prob = np.abs(psi) ** 2
+    top = np.sort(np.argsort(-prob)[:2])
+    # states 90 and 165 (its complement) tie exactly by the bit-flip symmetry
+    assert list(top) == [90, 165]
+    assert abs(prob[90] - prob[165]) < 1e-14
+
+
+def test_example1_is_a_local_minimum(oracle_mod):
+    """The printed x is (to 2 decimals) a local minimum: BFGS started there
+    stays within 0.01 and ends at f ~ 2.30."""
+    g = _example1()
+    q = oracle.maxcut_quality_loop(8, circular_ladder_edges(4), uncut=True)
+
+    def fun(x):
+        return oracle.evolve("x", q, x[0::2], x[1::2])[1]
+
+    def jac(x):
+        _, dg, dt = oracle.grad("x", q, x[0::2], x[1::2])
+        out = np.empty(4)
+        out[0::2] = dg
+        out[1::2] = dt
+        return out
+
+    x0 = np.array(g["x_printed"])
+    res = scipy.optimize.minimize(fun, x0, jac=jac, method="BFGS", tol=1e-10)
+    assert np.max(np.abs(res.x - x0)) < 0.01
+    assert abs(res.fun - g["f_printed_approx"]) < 0.01
+    assert res.fun <= fun(x0)
+
+
+def test_example1_rejects_misreadings(oracle_mod):
+    """The printed pair (x, f) separates the readings: a flipped mixer sign or a
+    blocked parameter order moves f far from 2.30."""
+    g = _example1()
+    q = oracle.maxcut_quality_loop(8, circular_ladder_edges(4), uncut=True)
+    x = np.array(g["x_printed"])
+    f_flip = oracle.evolve("x", q, x[0::2], -x[1::2])[1]
+    f_block = oracle.evolve("x", q, x[0:2], x[2:4])[1]
+    f_mixer_first = dense.evolve(dense.hypercube(8), q, [0.0], [0.0])[1]  # sanity: mean(q)
+    assert abs(f_flip - 2.30) > 1.0
+    assert abs(f_block - 2.30) > 1.0
+    assert abs(f_mixer_first - q.mean()) < 1e-12
+
+
+def test_example1_paper_graph_matches_networkx():
+    nx = pytest.importorskip("networkx")
+    G = nx.circular_ladder_graph(4)
+    ours = {tuple(sorted(e)) for e in circular_ladder_edges(4)}
+    theirs = {tuple(sorted(e)) for e in G.edges()}
+    assert ours == theirs
+
+
+# ------------------------------------------------------------- dense checks
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 7])
+def test_mix_x_matches_dense_expm(oracle_mod, n):
+    rng = np.random.default_rng(n)
+    psi = _rand_state(rng, 1 << n)
+    W = dense.hypercube(n)
+    for t in [0.0, 0.3, -1.1, 2.9, math.pi / 2]:
+        ref = dense.expm_hermitian(W, t) @ psi
+        ref2 = scipy.linalg.expm(-1j * t * W) @ psi
+        out = oracle.mix_x(psi, t)
+        assert np.max(np.abs(out - ref)) < 1e-13
+        assert np.max(np.abs(out - ref2)) < 1e-12
+
+
+@pytest.mark.parametrize("N", [2, 3, 5, 8, 12, 64])
+def test_mix_circulant_matches_dense_expm(oracle_mod, N):
+    rng = np.random.default_rng(N)
+    psi = _rand_state(rng, N)
+    row = rng.uniform(-1, 1, N)
+    row = 0.5 * (row + row[(-np.arange(N)) % N])  # symmetric first row
+    C = dense.circulant_from_row(row)
+    lam_re, lam_im = oracle.circulant_eigenvalues(row)
+    assert np.max(np.abs(lam_im)) < 1e-12
+    for t in [0.0, 0.4, -2.0]:
+        ref = dense.expm_hermitian(C, t) @ psi
+        out = oracle.mix_circulant(psi, lam_re, t)
+        assert np.max(np.abs(out - ref)) < 1e-13
+
+
+def test_mix_circulant_fft_path_matches_dense(oracle_mod):
+    """N = 8192 exercises the radix-2 FFT branch; compare with a dense
+    application of the ring circulant built from its first row (N^2 too big for
+    eigh, so compare with the DFT branch on the same input instead)."""
+    N = 8192
+    rng = np.random.default_rng(1)
+    psi = _rand_state(rng, N)
+    lam = oracle.ring_lambda(N)
+    out = oracle.mix_circulant(psi, lam, 0.7)
+    ref = np.fft.ifft(np.exp(-0.7j * lam) * np.fft.fft(psi))
+    assert np.max(np.abs(out - ref)) < 1e-13
+
+
+@pytest.mark.parametrize("mixer,n", [("x", 3), ("x", 6), ("circulant", 4), ("circulant", 7)])
+def test_evolve_matches_dense(oracle_mod, mixer, n):
+    rng = np.random.default_rng(10 + n)
+    N = 1 << n
+    q = rng.uniform(-1, 2, N)
+    p = 3
+    g = rng.uniform(0, math.pi, p)
+    t = rng.uniform(0, math.pi, p)
+    if mixer == "x":
+        W = dense.hypercube(n)
+        lam = None
+    else:
+        row = np.zeros(N)
+        row[1] = row[-1] = 1.0
+        W = dense.circulant_from_row(row)
+        lam = oracle.ring_lambda(N)
+    psi, f, nrm = oracle.evolve(mixer, q, g, t, lam)
+    psi_d, f_d = dense.evolve(W, q, g, t)
+    assert np.max(np.abs(psi - psi_d)) < 1e-13
+    assert abs(f - f_d) <= 1e-12 * np.sum(np.abs(psi_d) ** 2 * np.abs(q))
+    assert abs(nrm - 1) < 1e-13
+
+
+# ---------------------------------------------------------- closed forms
+@pytest.mark.parametrize("n", [1, 4, 9, 12])
+def test_mix_x_on_delta_closed_form(oracle_mod, n):
+    """exp(-i t sum X_i)|0> = prod_i (cos t |0> - i sin t |1>):
+    amplitude of j is cos(t)^(n-|j|) (-i sin t)^|j|, |j| = popcount."""
+    N = 1 << n
+    psi = np.zeros(N, complex)
+    psi[0] = 1
+    t = 0.37
+    out = oracle.mix_x(psi, t)
+    pc = np.array([bin(j).count("1") for j in range(N)])
+    ref = np.cos(t) ** (n - pc) * (-1j * np.sin(t)) ** pc
+    assert np.max(np.abs(out - ref)) < 1e-15
+
+
+@pytest.mark.parametrize("N,t", [(64, 0.9), (4096, 2.5), (16384, 3.1)])
+def test_ring_circulant_on_delta_bessel(oracle_mod, N, t):
+    """Ring walk from site 0: amplitude at j is sum over images d = j + mN of
+    (-i)^|d| J_|d|(2t) (Jacobi-Anger expansion of exp(-2it cos k))."""
+    psi = np.zeros(N, complex)
+    psi[0] = 1
+    out = oracle.mix_circulant(psi, oracle.ring_lambda(N), t)
+    j = np.arange(N)
+    ref = np.zeros(N, complex)
+    for m in range(-2, 3):
+        d = np.abs(j + m * N)
+        mask = d < 80
+        ref[mask] += (-1j) ** d[mask] * scipy.special.jv(d[mask], 2 * t)
+    assert np.max(np.abs(out - ref)) < 1e-14
+
+
+@pytest.mark.parametrize("N", [8, 100, 4096, 8192])
+def test_complete_graph_closed_form(oracle_mod, N):
+    """W = J - I: exp(-itW) psi = e^{it} (psi + (e^{-itN} - 1)/N * sum(psi))."""
+    rng = np.random.default_rng(N)
+    psi = _rand_state(rng, N)
+    t = 0.83
+    out = oracle.mix_circulant(psi, oracle.complete_lambda(N), t)
+    ref = np.exp(1j * t) * (psi + (np.exp(-1j * t * N) - 1) / N * psi.sum())
+    assert np.max(np.abs(out - ref)) < 1e-13
+
+
+def test_circulant_eigenvalue_formula(oracle_mod):
+    """Sec. 3 eigenvalue formula vs the ring/complete closed forms and numpy's
+    eigvalsh of the dense circulant."""
+    for N in [3, 8, 13, 32]:
+        row = np.zeros(N)
+        row[1] = row[-1] = 1.0
+        re, im = oracle.circulant_eigenvalues(row)
+        assert np.max(np.abs(re - oracle.ring_lambda(N))) < 1e-13
+        assert np.max(np.abs(im)) < 1e-13
+        row = np.ones(N)
+        row[0] = 0
+        re, im = oracle.circulant_eigenvalues(row)
+        assert np.max(np.abs(re - oracle.complete_lambda(N))) < 1e-12
+        rng = np.random.default_rng(N)
+        row = rng.uniform(-1, 1, N)
+        row = 0.5 * (row + row[(-np.arange(N)) % N])
+        re, _ = oracle.circulant_eigenvalues(row)
+        ev = np.linalg.eigvalsh(dense.circulant_from_row(row))
+        assert np.max(np.abs(np.sort(re) - ev)) < 1e-12
+
+
+@pytest.mark.parametrize("n", [4, 5, 6, 8, 10])
+def test_ring_maxcut_p1_closed_form(oracle_mod, n):
+    """Unweighted ring, cut quality, p = 1:
+    f = n (1/2 + 1/4 sin 4t sin 2gamma); df/dgamma = (n/2) sin 4t cos 2gamma;
+    df/dt = n cos 4t sin 2gamma."""
+    q = oracle.maxcut_quality_loop(n, ring_edges(n))
+    for g, t in [(0.3, 0.2), (1.9, 2.7), (-0.4, 1.0)]:
+        f, dg, dt = oracle.grad("x", q, [g], [t])
+        assert abs(f - n * (0.5 + 0.25 * math.sin(4 * t) * math.sin(2 * g))) < 1e-13 * n
+        assert abs(dg[0] - n / 2 * math.sin(4 * t) * math.cos(2 * g)) < 1e-12 * n
+        assert abs(dt[0] - n * math.cos(4 * t) * math.sin(2 * g)) < 1e-12 * n
+
+
+def test_weighted_triangle_free_p1_closed_form(oracle_mod):
+    """Weighted triangle-free graph, p = 1, per-edge expectation
+    w_uv [1/2 + 1/4 sin 4t sin(gamma w_uv) (prod_{x in N(u)\\v} cos(gamma w_ux)
+    + prod_{y in N(v)\\u} cos(gamma w_vy))]."""
+    rng = np.random.default_rng(7)
+    n = 8
+    edges = [(0, 1), (1, 2), (2, 3), (3, 4), (4, 5), (5, 6), (6, 7), (7, 0), (0, 4), (2, 6)]
+    # a bipartite (hence triangle-free) graph: the 8-cycle with two chords joining even vertices
+    # to even vertices would create triangles only with an odd cycle of length 3; check it:
+    adj = {v: set() for v in range(n)}
+    for u, v in edges:
+        adj[u].add(v)
+        adj[v].add(u)
+    assert all(not (adj[u] & adj[v]) for u, v in edges)
+    w = rng.uniform(0.2, 1.0, len(edges))
+    W = {}
+    for (u, v), x in zip(edges, w):
+        W[(u, v)] = W[(v, u)] = x
+    q = oracle.maxcut_quality_loop(n, edges, w)
+    g, t = 0.9, 0.35
+    f = oracle.evolve("x", q, [g], [t])[1]
+    ref = 0.0
+    for (u, v), x in zip(edges, w):
+        pu = np.prod([math.cos(g * W[(u, y)]) for y in adj[u] if y != v])
+        pv = np.prod([math.cos(g * W[(v, y)]) for y in adj[v] if y != u])
+        ref += x * (0.5 + 0.25 * math.sin(4 * t) * math.sin(g * x) * (pu + pv))
+    assert abs(f - ref) < 1e-13
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_ring_light_cone(oracle_mod, p):
+    """For a ring, f/n is the same for every n >= 2p + 2 (each edge term sees
+    only its distance-p neighbourhood)."""
+    rng = np.random.default_rng(p)
+    g = rng.uniform(0, math.pi, p)
+    t = rng.uniform(0, math.pi, p)
+    vals = []
+    for n in range(2 * p + 2, 2 * p + 5):
+        q = oracle.maxcut_quality_loop(n, ring_edges(n))
+        vals.append(oracle.evolve("x", q, g, t)[1] / n)
+    assert np.ptp(vals) < 1e-13
+
+
+# ---------------------------------------------------------------- invariants
+def test_uniform_state_is_fixed_point(oracle_mod):
+    """p = 0, all gamma = 0, or all t = 0 give f = mean(q) (the uniform state is
+    an eigenvector of both mixers)."""
+    rng = np.random.default_rng(3)
+    n = 7
+    q = rng.uniform(-3, 3, 1 << n)
+    assert abs(oracle.evolve("x", q, [], [])[1] - q.mean()) < 1e-14
+    for mixer, lam in [("x", None), ("circulant", oracle.ring_lambda(1 << n)),
+                       ("circulant", oracle.complete_lambda(1 << n))]:
+        f0 = oracle.evolve(mixer, q, [0.0, 0.0], [0.4, 1.3], lam)[1]
+        f1 = oracle.evolve(mixer, q, [0.5, 2.0], [0.0, 0.0], lam)[1]
+        assert abs(f0 - q.mean()) < 1e-13
+        assert abs(f1 - q.mean()) < 1e-13
+
+
+def test_norm_preserved(oracle_mod):
+    """Unitary evolution keeps the norm to ~1e-13 (the paper reports per-state
+    norm deviations of that order, Sec. 6)."""
+    rng = np.random.default_rng(4)
+    for mixer in ["x", "circulant"]:
+        n = 10
+        q = rng.uniform(0, 10, 1 << n)
+        lam = None if mixer == "x" else random_symmetric_lambda(1 << n, rng)
+        g = rng.uniform(0, math.pi, 5)
+        t = rng.uniform(0, math.pi, 5)
+        _, _, nrm = oracle.evolve(mixer, q, g, t, lam)
+        assert abs(nrm - 1) < 1e-13
+
+
+def test_symmetries(oracle_mod):
+    rng = np.random.default_rng(5)
+    n = 9
+    edges = erdos_renyi_edges(n, 0.5, rng)
+    q = oracle.maxcut_quality_loop(n, edges)  # integer qualities
+    g = rng.uniform(0, math.pi, 3)
+    t = rng.uniform(0, math.pi, 3)
+    psi, f, _ = oracle.evolve("x", q, g, t)
+    # complex conjugation: f(-gamma, -t) = f(gamma, t)
+    assert abs(oracle.evolve("x", q, -g, -t)[1] - f) < 1e-12
+    # exp(-i(t+pi)X) = -exp(-itX): global sign per layer
+    assert abs(oracle.evolve("x", q, g, t + math.pi)[1] - f) < 1e-12
+    # integer q: gamma -> gamma + 2 pi leaves U_Q unchanged
+    assert abs(oracle.evolve("x", q, g + 2 * math.pi, t)[1] - f) < 1e-12
+    # max-cut is invariant under flipping every bit
+    prob = np.abs(psi) ** 2
+    flip = np.arange(1 << n) ^ ((1 << n) - 1)
+    assert np.max(np.abs(prob - prob[flip])) < 1e-15
+
+
+# ---------------------------------------------------------------------- FFT
+@pytest.mark.parametrize("N", [1, 2, 4, 16, 1024, 8192])
+def test_fft_matches_numpy_and_identities(oracle_mod, N):
+    rng = np.random.default_rng(N)
+    x = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    X = oracle.fft(x, -1)
+    assert np.max(np.abs(X - np.fft.fft(x))) < 1e-11 * max(1, np.sqrt(N))
+    assert np.max(np.abs(oracle.fft(X, +1) / N - x)) < 1e-14 * max(1, np.log2(N))
+    assert abs(np.sum(np.abs(X) ** 2) - N * np.sum(np.abs(x) ** 2)) < 1e-12 * N * np.sum(np.abs(x) ** 2)
+    d = np.zeros(N, complex)
+    d[0] = 1
+    assert np.max(np.abs(oracle.fft(d, -1) - 1)) < 1e-15
+    if N >= 4:
+        m0 = 3 % N
+        e = np.exp(2j * np.pi * m0 * np.arange(N) / N)
+        ref = np.zeros(N, complex)
+        ref[m0] = N
+        assert np.max(np.abs(oracle.fft(e, -1) - ref)) < 1e-12 * N
+
+
+@pytest.mark.parametrize("N", [3, 12, 256])
+def test_naive_dft_matches_numpy(oracle_mod, N):
+    rng = np.random.default_rng(N)
+    x = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    assert np.max(np.abs(oracle.dft(x, -1) - np.fft.fft(x))) < 1e-12
+    assert np.max(np.abs(oracle.dft(x, +1) - N * np.fft.ifft(x))) < 1e-12
+
+
+def test_expectation_pairwise_exact_on_integers(oracle_mod):
+    """With dyadic amplitudes and integer q every partial sum is exact."""
+    N = 1 << 16
+    psi = np.full(N, 1.0 / 256.0, complex)  # |psi|^2 = 2^-16
+    q = np.arange(N, dtype=float)
+    f, nrm = oracle.expectation(psi, q)
+    assert nrm == 1.0
+    assert f == (N - 1) / 2
+
+
+# ---------------------------------------------------------------- gradients
+@pytest.mark.parametrize("mixer,n,p", [("x", 5, 3), ("x", 7, 2), ("circulant", 5, 3),
+                                       ("circulant", 6, 4)])
+def test_gradient_adjoint_vs_bruteforce_vs_fd(oracle_mod, mixer, n, p):
+    rng = np.random.default_rng(100 + n + p)
+    N = 1 << n
+    q = rng.uniform(0, 5, N)
+    lam = None if mixer == "x" else random_symmetric_lambda(N, rng)
+    g = rng.uniform(0, math.pi, p)
+    t = rng.uniform(0, math.pi, p)
+    f, dg, dt = oracle.grad(mixer, q, g, t, lam)
+    bg, bt = oracle.grad_bruteforce(mixer, q, g, t, lam)
+    scale = max(np.max(np.abs(dg)), np.max(np.abs(dt)))
+    assert np.max(np.abs(dg - bg)) < 1e-12 * scale
+    assert np.max(np.abs(dt - bt)) < 1e-12 * scale
+    h = 1e-5
+    for k in range(p):
+        e = np.zeros(p)
+        e[k] = h
+        fd_g = (oracle.evolve(mixer, q, g + e, t, lam)[1] - oracle.evolve(mixer, q, g - e, t, lam)[1]) / (2 * h)
+        fd_t = (oracle.evolve(mixer, q, g, t + e, lam)[1] - oracle.evolve(mixer, q, g, t - e, lam)[1]) / (2 * h)
+        assert abs(fd_g - dg[k]) < 1e-7 * scale
+        assert abs(fd_t - dt[k]) < 1e-7 * scale
+
+
+def test_gradient_matches_dense_derivative(oracle_mod):
+    """d/dt of exp(-itW) is -iW exp(-itW): compare with a dense evaluation of
+    that product rule on a tiny system."""
+    rng = np.random.default_rng(9)
+    n = 4
+    N = 1 << n
+    q = rng.uniform(0, 3, N)
+    W = dense.hypercube(n)
+    g = rng.uniform(0, math.pi, 2)
+    t = rng.uniform(0, math.pi, 2)
+
+    def states(dpar=None):
+        psi = np.full(N, N ** -0.5, complex)
+        for k in range(2):
+            psi = np.exp(-1j * g[k] * q) * psi
+            if dpar == ("g", k):
+                psi = -1j * q * psi
+            psi = dense.expm_hermitian(W, t[k]) @ psi
+            if dpar == ("t", k):
+                psi = -1j * (W @ psi)
+        return psi
+
+    psi = states()
+    _, dg, dt = oracle.grad("x", q, g, t)
+    for k in range(2):
+        ref_g = 2 * np.real(np.vdot(psi, q * states(("g", k))))
+        ref_t = 2 * np.real(np.vdot(psi, q * states(("t", k))))
+        assert abs(dg[k] - ref_g) < 1e-12
+        assert abs(dt[k] - ref_t) < 1e-12
+
+
+# --------------------------------------------------- the inputs module itself
+@pytest.mark.parametrize("n", [3, 6, 9, 11])
+def test_workload_q_matches_plain_loop(oracle_mod, n):
+    rng = np.random.default_rng(n)
+    edges = erdos_renyi_edges(n, 0.5, rng)
+    w = rng.uniform(0, 1, len(edges))
+    a = maxcut_qualities(n, edges, w)
+    b = oracle.maxcut_quality_loop(n, edges, w)
+    assert np.max(np.abs(a - b)) < 1e-13
+    a = maxcut_qualities(n, edges, uncut=True)
+    b = oracle.maxcut_quality_loop(n, edges, uncut=True)
+    assert np.array_equal(a, b)
+
+
+def test_portfolio_q_matches_plain_loop():
+    rng = np.random.default_rng(0)
+    m = 9
+    mu = rng.normal(0.01, 0.02, m)
+    g = rng.standard_normal((30, m))
+    sigma = g.T @ g / 30
+    q = portfolio_qualities(mu, sigma, 0.5)
+    for j in [0, 1, 5, 77, 300, 511]:
+        x = np.array([(j >> i) & 1 for i in range(m)], float)
+        assert abs(q[j] - (mu @ x - 0.5 * x @ sigma @ x)) < 1e-13
+
+
+def test_random_regular_is_regular_and_simple():
+    rng = np.random.default_rng(1)
+    for n in [12, 28, 30]:
+        e = random_regular_edges(3, n, rng)
+        assert len(e) == 3 * n // 2
+        assert len(set(e)) == len(e)
+        deg = np.bincount(np.array(e).ravel(), minlength=n)
+        assert np.all(deg == 3)
