@@ -1,0 +1,168 @@
+/*
+ * qva.h -- C ABI of libqva, the MI355X (gfx950) state-vector engine for
+ * quantum variational algorithms (QAOA with the hypercube mixer, QWOA with a
+ * circulant mixer), after Matwiejew & Wang, "QuOp_MPI: a framework for
+ * parallel simulation of quantum variational algorithms".
+ *
+ * The library evaluates
+ *
+ *     f(gamma, t) = <psi_p| Q |psi_p>,
+ *     psi_p = U_W(t_p) U_Q(gamma_p) ... U_W(t_1) U_Q(gamma_1) psi_0,
+ *
+ * (paper Sec. 2.1 eqs. variational_generic and objective_generic; Sec. 2.3.1
+ * eq. qaoa; Sec. 2.4.2 eq. qwoa), with
+ *     U_Q(gamma) = diag(exp(-i gamma q_j))            (eq. phase_shift_qaoa),
+ *     U_W(t)     = exp(-i t W)                         (eq. mixing_generic),
+ *     psi_0      = N^(-1/2) sum_j |j>                  (eq. qaoa_initial_state),
+ * and its gradient with respect to every gamma_k and t_k.
+ *
+ * Conventions shared by every entry point
+ *   - Amplitudes are complex128, stored as interleaved (re, im) doubles: the
+ *     layout of torch.complex128 / hipDoubleComplex.  Qualities q and
+ *     eigenvalues lambda are float64.  All of them live in device memory.
+ *   - Basis index j of an n-qubit register: bit i of j is the state of qubit i.
+ *   - Every pointer named *_dev or documented "device" is a device pointer
+ *     owned by the caller; the library never retains a pointer after a call
+ *     returns and never allocates device memory.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the default
+ *     stream.  Calls only enqueue work on that stream (no host
+ *     synchronisation), so results are ready after the stream is synchronised,
+ *     and every call can be captured into a HIP graph.
+ *   - Arguments are validated on the host before anything is enqueued; on a
+ *     negative status nothing was launched.  QVA_ERR_HIP reports a failed
+ *     kernel launch.
+ *   - Device pointers must be 16-byte aligned for complex arrays and 8-byte
+ *     aligned for double arrays (QVA_ERR_ALIGN otherwise).
+ */
+#ifndef QVA_H
+#define QVA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    double re, im;
+} qva_c128;
+
+typedef enum {
+    QVA_OK = 0,
+    QVA_ERR_ARG = -1,         /* null pointer, bad enum, p < 0, ...          */
+    QVA_ERR_SIZE = -2,        /* N or n_qubits outside the supported range   */
+    QVA_ERR_ALIGN = -3,       /* misaligned device pointer                   */
+    QVA_ERR_WORKSPACE = -4,   /* workspace missing or smaller than required  */
+    QVA_ERR_HIP = -5,         /* a HIP launch or runtime call failed         */
+    QVA_ERR_UNSUPPORTED = -6  /* well-formed request this build cannot serve */
+} qva_status;
+
+typedef enum {
+    QVA_MIX_X = 0,        /* W = sum_i X_i, the n-cube adjacency (eq. mixing_qaoa)   */
+    QVA_MIX_CIRCULANT = 1 /* W circulant, given by its eigenvalues (Sec. 3)          */
+} qva_mixer;
+
+typedef enum {
+    QVA_LAMBDA_ARRAY = 0,   /* lambda[m], m = 0..N-1, natural (DFT) order             */
+    QVA_LAMBDA_RING = 1,    /* cycle graph: lambda_m = 2 cos(2 pi m / N)              */
+    QVA_LAMBDA_COMPLETE = 2 /* complete graph: lambda_0 = N - 1, lambda_m = -1        */
+} qva_lambda_kind;
+
+/* Problem descriptor (caller-owned, read during the call only).
+ *   mixer       QVA_MIX_X or QVA_MIX_CIRCULANT
+ *   n_qubits    log2 N; 1 <= n_qubits <= QVA_MAX_QUBITS
+ *   q           device, N doubles: the diagonal of Q (paper Sec. 2.2)
+ *   lambda      device, N doubles, eigenvalues of W in natural order; read only
+ *               when mixer == QVA_MIX_CIRCULANT and lambda_kind == QVA_LAMBDA_ARRAY
+ *   lambda_kind a qva_lambda_kind (ignored for QVA_MIX_X)                      */
+typedef struct {
+    int mixer;
+    int n_qubits;
+    const double *q;
+    const double *lambda;
+    int lambda_kind;
+} qva_problem;
+
+#define QVA_MAX_QUBITS 33
+
+/* qva_evolve flags */
+#define QVA_EVOLVE_SKIP_FINAL_STATE 1 /* psi need not hold psi_p on return */
+
+/* Human-readable text for a status code (static storage). */
+const char *qva_status_string(int status);
+
+/* Library version string (static storage). */
+const char *qva_version(void);
+
+/* psi_j = N^(-1/2) for j < N: the equal superposition of eq.
+ * qaoa_initial_state (and eq. qwoa_initial_state over N solutions).
+ * psi: device, N complex.  N >= 1. */
+int qva_init_uniform(qva_c128 *psi, int64_t N, void *stream);
+
+/* psi_j <- exp(-i gamma q_j) psi_j: the phase-shift unitary of eq.
+ * phase_shift_generic applied elementwise (Sec. 3).
+ * psi: device, N complex, in place.  q: device, N doubles.  N >= 1. */
+int qva_phase(qva_c128 *psi, const double *q, int64_t N, double gamma, void *stream);
+
+/* psi <- exp(-i t sum_i X_i) psi on n_qubits qubits: the QAOA mixer of eq.
+ * mixing_qaoa, i.e. the product over qubits of exp(-i t X_i).
+ * psi: device, 2^n_qubits complex, in place. */
+int qva_mix_x(qva_c128 *psi, int n_qubits, double t, void *stream);
+
+/* psi <- F^-1 diag(exp(-i t lambda_m)) F psi: a circulant mixer exp(-i t W)
+ * through its eigensystem (Sec. 3), F the unnormalised DFT
+ * (F_mj = exp(-2 pi i j m / N)), F^-1 = conj(F)/N.
+ * psi: device, N complex, in place; N = 2^k, 1 <= k <= QVA_MAX_QUBITS.
+ * lambda: device, N doubles in natural order when lambda_kind ==
+ * QVA_LAMBDA_ARRAY, else ignored (may be NULL). */
+int qva_mix_circulant(qva_c128 *psi, const double *lambda, int lambda_kind, int64_t N,
+                      double t, void *stream);
+
+/* Bytes of device workspace that qva_evolve (for_grad = 0) or qva_grad
+ * (for_grad = 1) needs for problem P at depth p.  Returns 0 when no workspace
+ * is needed or the arguments are invalid (the call itself reports which). */
+size_t qva_workspace_bytes(const qva_problem *P, int p, int for_grad);
+
+/* Bytes of device workspace that qva_expectation needs for N amplitudes. */
+size_t qva_expectation_workspace_bytes(int64_t N);
+
+/* f = sum_j |psi_j|^2 q_j (eq. objective_generic) and, if out_norm_dev is not
+ * NULL, sum_j |psi_j|^2.  psi: device, N complex; q: device, N doubles;
+ * out_f_dev, out_norm_dev: device doubles.  Deterministic (fixed reduction
+ * order).  work: device, >= qva_expectation_workspace_bytes(N) bytes. */
+int qva_expectation(const qva_c128 *psi, const double *q, int64_t N, double *out_f_dev,
+                    double *out_norm_dev, void *work, size_t work_bytes, void *stream);
+
+/* The whole p-layer evolution from psi_0 and its expectation (eqs. qaoa /
+ * qwoa, objective_generic), fused into as few passes over the state as the
+ * operator structure allows.
+ *   gammas_dev, ts_dev  device, p doubles each (layer k uses gammas_dev[k],
+ *                       ts_dev[k]; layer 0 acts first)
+ *   p                   depth >= 0 (p = 0 gives f = mean(q))
+ *   psi                 device, N complex; working state, holds psi_p on return
+ *                       unless flags has QVA_EVOLVE_SKIP_FINAL_STATE
+ *   out_f_dev           device double: f.  out_norm_dev (nullable): sum |psi_p|^2
+ *   work, work_bytes    device workspace >= qva_workspace_bytes(P, p, 0)      */
+int qva_evolve(const qva_problem *P, const double *gammas_dev, const double *ts_dev, int p,
+               qva_c128 *psi, double *out_f_dev, double *out_norm_dev, int flags, void *work,
+               size_t work_bytes, void *stream);
+
+/* f and its gradient by the adjoint method: df/dtheta_l = 2 Im <chi_l|H_l|phi_l>
+ * with phi_l the state after unitary l and chi_l = U_{l+1}^dag...U_2p^dag Q psi_p,
+ * both walked back from psi_p by inverse layers (no stored intermediate
+ * states).  Replaces the finite-difference gradients of the paper's Sec. 4.
+ *   psi, chi            device, N complex each: working states (contents on
+ *                       return unspecified)
+ *   out_f_dev           device double
+ *   dgammas_dev, dts_dev device, p doubles each
+ *   work                >= qva_workspace_bytes(P, p, 1) bytes                  */
+int qva_grad(const qva_problem *P, const double *gammas_dev, const double *ts_dev, int p,
+             qva_c128 *psi, qva_c128 *chi, double *out_f_dev, double *dgammas_dev,
+             double *dts_dev, void *work, size_t work_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QVA_H */

@@ -1,0 +1,95 @@
+"""ctypes binding of libqva.so (the C ABI declared in include/qva.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of the library.  Importing this module loads the in-tree library and
+fails loudly when it has not been built.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libqva.so")
+
+QVA_OK = 0
+QVA_ERR_ARG = -1
+QVA_ERR_SIZE = -2
+QVA_ERR_ALIGN = -3
+QVA_ERR_WORKSPACE = -4
+QVA_ERR_HIP = -5
+QVA_ERR_UNSUPPORTED = -6
+
+QVA_MIX_X = 0
+QVA_MIX_CIRCULANT = 1
+QVA_LAMBDA_ARRAY = 0
+QVA_LAMBDA_RING = 1
+QVA_LAMBDA_COMPLETE = 2
+QVA_MAX_QUBITS = 33
+QVA_EVOLVE_SKIP_FINAL_STATE = 1
+
+
+class QvaProblem(ctypes.Structure):
+    _fields_ = [
+        ("mixer", ctypes.c_int),
+        ("n_qubits", ctypes.c_int),
+        ("q", ctypes.c_void_p),
+        ("lam", ctypes.c_void_p),
+        ("lambda_kind", ctypes.c_int),
+    ]
+
+
+class QvaError(RuntimeError):
+    def __init__(self, fn: str, status: int, text: str):
+        super().__init__(f"{fn}: {text} (status {status})")
+        self.status = status
+
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_D = ctypes.c_double
+_I = ctypes.c_int
+_SZ = ctypes.c_size_t
+_PROB = ctypes.POINTER(QvaProblem)
+
+# name -> (restype, argtypes); one entry per function declared in include/qva.h
+SIGNATURES = {
+    "qva_status_string": (ctypes.c_char_p, [_I]),
+    "qva_version": (ctypes.c_char_p, []),
+    "qva_init_uniform": (_I, [_P, _I64, _P]),
+    "qva_phase": (_I, [_P, _P, _I64, _D, _P]),
+    "qva_mix_x": (_I, [_P, _I, _D, _P]),
+    "qva_mix_circulant": (_I, [_P, _P, _I, _I64, _D, _P]),
+    "qva_workspace_bytes": (_SZ, [_PROB, _I, _I]),
+    "qva_expectation_workspace_bytes": (_SZ, [_I64]),
+    "qva_expectation": (_I, [_P, _P, _I64, _P, _P, _P, _SZ, _P]),
+    "qva_evolve": (_I, [_PROB, _P, _P, _I, _P, _P, _P, _I, _P, _SZ, _P]),
+    "qva_grad": (_I, [_PROB, _P, _P, _I, _P, _P, _P, _P, _P, _P, _SZ, _P]),
+}
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load the in-tree libqva.so; raise if it is missing (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is not built; run `python -m paper_2110_03963_amd.build` "
+            "(or __graft_entry__.build()) first")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(fn: str, status: int) -> None:
+    if status != QVA_OK:
+        text = load().qva_status_string(status).decode()
+        raise QvaError(fn, status, text)

@@ -1,0 +1,308 @@
+// qva_api.cpp -- the C ABI of libqva: argument validation, pass planning and
+// kernel enqueueing.  Declared in include/qva.h.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <vector>
+
+#include "qva.h"
+#include "qva_internal.h"
+#include "qva_plan.h"
+
+using namespace qva;
+
+namespace {
+
+bool aligned(const void* p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+int hip_status(hipError_t e) { return e == hipSuccess ? QVA_OK : QVA_ERR_HIP; }
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+int log2_exact(int64_t N)
+{
+    if (N < 1)
+        return -1;
+    int n = 0;
+    while ((int64_t(1) << n) < N)
+        ++n;
+    return (int64_t(1) << n) == N ? n : -1;
+}
+
+int check_problem(const qva_problem* P, int p)
+{
+    if (!P || p < 0)
+        return QVA_ERR_ARG;
+    if (P->mixer != QVA_MIX_X && P->mixer != QVA_MIX_CIRCULANT)
+        return QVA_ERR_ARG;
+    if (P->n_qubits < 1 || P->n_qubits > QVA_MAX_QUBITS)
+        return QVA_ERR_SIZE;
+    if (!P->q)
+        return QVA_ERR_ARG;
+    if (!aligned(P->q, 8))
+        return QVA_ERR_ALIGN;
+    if (P->mixer == QVA_MIX_CIRCULANT) {
+        if (P->lambda_kind != QVA_LAMBDA_ARRAY && P->lambda_kind != QVA_LAMBDA_RING &&
+            P->lambda_kind != QVA_LAMBDA_COMPLETE)
+            return QVA_ERR_ARG;
+        if (P->lambda_kind == QVA_LAMBDA_ARRAY) {
+            if (!P->lambda)
+                return QVA_ERR_ARG;
+            if (!aligned(P->lambda, 8))
+                return QVA_ERR_ALIGN;
+        }
+    }
+    return QVA_OK;
+}
+
+// ----------------------------------------------------- hypercube evolution
+Angle dev_angle(const double* ptr, int idx)
+{
+    Angle a;
+    a.ptr = ptr;
+    a.idx = idx;
+    a.val = 0.0;
+    return a;
+}
+
+Angle host_angle(double v)
+{
+    Angle a;
+    a.ptr = nullptr;
+    a.idx = 0;
+    a.val = v;
+    return a;
+}
+
+XPassParams xpass_base(double2* psi, const double* q, int n, const XGroup& g)
+{
+    XPassParams x{};
+    x.psi = psi;
+    x.q = q;
+    x.n = n;
+    x.k = g.k;
+    x.col_bits = g.col_bits;
+    x.mix1 = x.mix2 = x.phase = host_angle(0.0);
+    x.partials = nullptr;
+    return x;
+}
+
+int evolve_x(const qva_problem* P, const double* gammas, const double* ts, int p, double2* psi,
+             double* out_f, double* out_norm, bool store, double2* partials, hipStream_t s)
+{
+    const int n = P->n_qubits;
+    if (n <= kTileBits) {
+        SmallParams sp{};
+        sp.psi = psi;
+        sp.q = P->q;
+        sp.gammas = gammas;
+        sp.ts = ts;
+        sp.n = n;
+        sp.p = p;
+        sp.flags = SM_INIT | SM_EVOLVE | SM_EXPECT | (store ? SM_STORE : 0);
+        sp.out_f = out_f;
+        sp.out_norm = out_norm;
+        return hip_status(launch_small(sp, s));
+    }
+    const int64_t N = int64_t(1) << n;
+    if (p == 0) {
+        hipError_t e = launch_init_uniform(psi, N, s);
+        if (e == hipSuccess)
+            e = launch_expect_partials(psi, P->q, N, partials, s);
+        if (e == hipSuccess)
+            e = launch_final_reduce(partials, expect_partial_count(N), out_f, out_norm, s);
+        return hip_status(e);
+    }
+    const std::vector<XGroup> groups = x_groups(n);
+    const std::vector<XPass> plan = x_evolve_plan((int)groups.size(), p, store);
+    for (const XPass& ps : plan) {
+        XPassParams x = xpass_base(psi, P->q, n, groups[ps.group]);
+        x.flags = ps.flags;
+        x.mix1 = dev_angle(ts, ps.layer1);
+        x.mix2 = dev_angle(ts, ps.layer2 >= 0 ? ps.layer2 : 0);
+        x.phase = dev_angle(gammas, ps.phase_layer >= 0 ? ps.phase_layer : 0);
+        x.partials = partials;
+        hipError_t e = launch_xpass(x, s);
+        if (e != hipSuccess)
+            return QVA_ERR_HIP;
+    }
+    return hip_status(launch_final_reduce(partials, int64_t(1) << (n - kTileBits), out_f, out_norm, s));
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* qva_status_string(int status)
+{
+    switch (status) {
+    case QVA_OK:
+        return "ok";
+    case QVA_ERR_ARG:
+        return "invalid argument";
+    case QVA_ERR_SIZE:
+        return "size out of the supported range";
+    case QVA_ERR_ALIGN:
+        return "misaligned device pointer";
+    case QVA_ERR_WORKSPACE:
+        return "workspace missing or too small";
+    case QVA_ERR_HIP:
+        return "HIP launch or runtime error";
+    case QVA_ERR_UNSUPPORTED:
+        return "unsupported request";
+    default:
+        return "unknown status";
+    }
+}
+
+const char* qva_version(void) { return "libqva 0.1 (gfx950)"; }
+
+int qva_init_uniform(qva_c128* psi, int64_t N, void* stream)
+{
+    if (!psi || N < 1)
+        return psi ? QVA_ERR_SIZE : QVA_ERR_ARG;
+    if (!aligned(psi, 16))
+        return QVA_ERR_ALIGN;
+    return hip_status(launch_init_uniform(reinterpret_cast<double2*>(psi), N, as_stream(stream)));
+}
+
+int qva_phase(qva_c128* psi, const double* q, int64_t N, double gamma, void* stream)
+{
+    if (!psi || !q)
+        return QVA_ERR_ARG;
+    if (N < 1)
+        return QVA_ERR_SIZE;
+    if (!aligned(psi, 16) || !aligned(q, 8))
+        return QVA_ERR_ALIGN;
+    return hip_status(launch_phase(reinterpret_cast<double2*>(psi), q, N, gamma, as_stream(stream)));
+}
+
+int qva_mix_x(qva_c128* psi, int n_qubits, double t, void* stream)
+{
+    if (!psi)
+        return QVA_ERR_ARG;
+    if (n_qubits < 1 || n_qubits > QVA_MAX_QUBITS)
+        return QVA_ERR_SIZE;
+    if (!aligned(psi, 16))
+        return QVA_ERR_ALIGN;
+    double2* d = reinterpret_cast<double2*>(psi);
+    hipStream_t s = as_stream(stream);
+    if (n_qubits <= kTileBits) {
+        SmallParams sp{};
+        sp.psi = d;
+        sp.n = n_qubits;
+        sp.t_val = t;
+        sp.flags = SM_MIX_ONCE | SM_STORE;
+        return hip_status(launch_small(sp, s));
+    }
+    const std::vector<XGroup> groups = x_groups(n_qubits);
+    for (size_t i = 0; i < groups.size(); ++i) {
+        XPassParams x = xpass_base(d, nullptr, n_qubits, groups[i]);
+        x.flags = XP_MIX1 | XP_STORE | (i + 1 == groups.size() ? XP_FINAL_SCALE : 0);
+        x.mix1 = host_angle(t);
+        if (launch_xpass(x, s) != hipSuccess)
+            return QVA_ERR_HIP;
+    }
+    return QVA_OK;
+}
+
+int qva_mix_circulant(qva_c128* psi, const double* lambda, int lambda_kind, int64_t N, double t,
+                      void* stream)
+{
+    (void)psi;
+    (void)lambda;
+    (void)lambda_kind;
+    (void)N;
+    (void)t;
+    (void)stream;
+    return QVA_ERR_UNSUPPORTED;
+}
+
+size_t qva_expectation_workspace_bytes(int64_t N)
+{
+    if (N < 1)
+        return 0;
+    return (size_t)expect_partial_count(N) * sizeof(double2);
+}
+
+size_t qva_workspace_bytes(const qva_problem* P, int p, int for_grad)
+{
+    (void)for_grad;
+    if (check_problem(P, p) != QVA_OK)
+        return 0;
+    const int n = P->n_qubits;
+    if (P->mixer == QVA_MIX_X && n <= kTileBits)
+        return 0;
+    const int64_t tiles = n > kTileBits ? (int64_t(1) << (n - kTileBits)) : 1;
+    return (size_t)tiles * sizeof(double2);
+}
+
+int qva_expectation(const qva_c128* psi, const double* q, int64_t N, double* out_f_dev,
+                    double* out_norm_dev, void* work, size_t work_bytes, void* stream)
+{
+    if (!psi || !q || !out_f_dev)
+        return QVA_ERR_ARG;
+    if (N < 1)
+        return QVA_ERR_SIZE;
+    if (!aligned(psi, 16) || !aligned(q, 8) || !aligned(out_f_dev, 8) ||
+        (out_norm_dev && !aligned(out_norm_dev, 8)))
+        return QVA_ERR_ALIGN;
+    const size_t need = qva_expectation_workspace_bytes(N);
+    if (!work || work_bytes < need)
+        return QVA_ERR_WORKSPACE;
+    if (!aligned(work, 16))
+        return QVA_ERR_ALIGN;
+    hipStream_t s = as_stream(stream);
+    double2* partials = reinterpret_cast<double2*>(work);
+    hipError_t e = launch_expect_partials(reinterpret_cast<const double2*>(psi), q, N, partials, s);
+    if (e == hipSuccess)
+        e = launch_final_reduce(partials, expect_partial_count(N), out_f_dev, out_norm_dev, s);
+    return hip_status(e);
+}
+
+int qva_evolve(const qva_problem* P, const double* gammas_dev, const double* ts_dev, int p,
+               qva_c128* psi, double* out_f_dev, double* out_norm_dev, int flags, void* work,
+               size_t work_bytes, void* stream)
+{
+    int st = check_problem(P, p);
+    if (st != QVA_OK)
+        return st;
+    if (!psi || !out_f_dev || (p > 0 && (!gammas_dev || !ts_dev)))
+        return QVA_ERR_ARG;
+    if (flags & ~QVA_EVOLVE_SKIP_FINAL_STATE)
+        return QVA_ERR_ARG;
+    if (!aligned(psi, 16) || !aligned(out_f_dev, 8) || (out_norm_dev && !aligned(out_norm_dev, 8)) ||
+        (gammas_dev && !aligned(gammas_dev, 8)) || (ts_dev && !aligned(ts_dev, 8)))
+        return QVA_ERR_ALIGN;
+    const size_t need = qva_workspace_bytes(P, p, 0);
+    if (need && (!work || work_bytes < need))
+        return QVA_ERR_WORKSPACE;
+    if (work && !aligned(work, 16))
+        return QVA_ERR_ALIGN;
+    const bool store = !(flags & QVA_EVOLVE_SKIP_FINAL_STATE);
+    if (P->mixer == QVA_MIX_X)
+        return evolve_x(P, gammas_dev, ts_dev, p, reinterpret_cast<double2*>(psi), out_f_dev,
+                        out_norm_dev, store, reinterpret_cast<double2*>(work), as_stream(stream));
+    return QVA_ERR_UNSUPPORTED;
+}
+
+int qva_grad(const qva_problem* P, const double* gammas_dev, const double* ts_dev, int p,
+             qva_c128* psi, qva_c128* chi, double* out_f_dev, double* dgammas_dev,
+             double* dts_dev, void* work, size_t work_bytes, void* stream)
+{
+    (void)P;
+    (void)gammas_dev;
+    (void)ts_dev;
+    (void)p;
+    (void)psi;
+    (void)chi;
+    (void)out_f_dev;
+    (void)dgammas_dev;
+    (void)dts_dev;
+    (void)work;
+    (void)work_bytes;
+    (void)stream;
+    return QVA_ERR_UNSUPPORTED;
+}
+
+}  // extern "C"

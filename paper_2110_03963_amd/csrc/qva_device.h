@@ -1,0 +1,148 @@
+// qva_device.h -- device helpers shared by the libqva kernels (gfx950, wave64).
+//
+// Amplitudes are double2 (x = re, y = im).  All arithmetic is IEEE double.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qva {
+
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+
+// Streaming (non-temporal) 16-byte load/store of one amplitude: every
+// amplitude is touched once per pass, so there is nothing to keep in cache.
+__device__ __forceinline__ double2 ld_nt(const double2* p)
+{
+    dvec2 v = __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(p));
+    return make_double2(v.x, v.y);
+}
+
+__device__ __forceinline__ void st_nt(double2* p, double2 a)
+{
+    dvec2 v;
+    v.x = a.x;
+    v.y = a.y;
+    __builtin_nontemporal_store(v, reinterpret_cast<dvec2*>(p));
+}
+
+__device__ __forceinline__ double ld_nt(const double* p) { return __builtin_nontemporal_load(p); }
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// exp(-i x) = (cos x, -sin x)
+__device__ __forceinline__ double2 expmi(double x)
+{
+    double s, c;
+    sincos(x, &s, &c);
+    return make_double2(c, -s);
+}
+
+// A scalar parameter that is read from a device array when `ptr` is set,
+// otherwise taken by value (host scalars of the primitive entry points).
+struct Angle {
+    const double* ptr;
+    int idx;
+    double val;
+};
+
+__device__ __forceinline__ double angle_value(const Angle& a) { return a.ptr ? a.ptr[a.idx] : a.val; }
+
+// exp(-i t X) on one qubit pair, factored as sigma * B where B has a unit
+// entry on the larger of |cos t|, |sin t|:
+//   |cos t| >= |sin t|:  sigma = cos t,     B = [[1, -i tan t], [-i tan t, 1]]
+//   otherwise:           sigma = -i sin t,  B = [[i cot t, 1], [1, i cot t]]
+// B costs four FMAs per pair; the sigma of every qubit of a layer is collected
+// into one complex factor sigma^n applied once (B / |sigma| is unitary up to a
+// real factor, so the factoring does not change the conditioning).
+struct MixCoef {
+    double k;       // tan t or cot t
+    bool tanform;
+    double2 sigma;  // per-qubit scalar factor
+};
+
+__device__ __forceinline__ MixCoef mix_coef(double t)
+{
+    double s, c;
+    sincos(t, &s, &c);
+    MixCoef m;
+    if (fabs(c) >= fabs(s)) {
+        m.k = s / c;
+        m.tanform = true;
+        m.sigma = make_double2(c, 0.0);
+    } else {
+        m.k = c / s;
+        m.tanform = false;
+        m.sigma = make_double2(0.0, -s);
+    }
+    return m;
+}
+
+// sigma^n by repeated multiplication (n <= 34; identical in every thread).
+__device__ __forceinline__ double2 cpow_int(double2 s, int n)
+{
+    double2 r = make_double2(1.0, 0.0);
+    for (int i = 0; i < n; ++i)
+        r = cmul(r, s);
+    return r;
+}
+
+// B applied to the pair (a, b), tan form: a' = a - i k b, b' = b - i k a.
+__device__ __forceinline__ void bfly_tan(double2& a, double2& b, double k)
+{
+    double2 a2, b2;
+    a2.x = fma(k, b.y, a.x);
+    a2.y = fma(-k, b.x, a.y);
+    b2.x = fma(k, a.y, b.x);
+    b2.y = fma(-k, a.x, b.y);
+    a = a2;
+    b = b2;
+}
+
+// B applied to the pair (a, b), cot form: a' = i k a + b, b' = a + i k b.
+__device__ __forceinline__ void bfly_cot(double2& a, double2& b, double k)
+{
+    double2 a2, b2;
+    a2.x = fma(-k, a.y, b.x);
+    a2.y = fma(k, a.x, b.y);
+    b2.x = fma(-k, b.y, a.x);
+    b2.y = fma(k, b.x, a.y);
+    a = a2;
+    b = b2;
+}
+
+// Sum over the 64 lanes of a wave (butterfly shuffles; same order in every
+// wave, so the result is deterministic).
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Deterministic block sum of two doubles; every thread gets the result.
+// `red` must hold 2 * (blockDim.x / 64) doubles of shared memory.
+__device__ __forceinline__ double2 block_sum2(double a, double b, double* red)
+{
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if (lane == 0) {
+        red[2 * wid] = a;
+        red[2 * wid + 1] = b;
+    }
+    __syncthreads();
+    double sa = 0.0, sb = 0.0;
+    for (int w = 0; w < nw; ++w) {
+        sa += red[2 * w];
+        sb += red[2 * w + 1];
+    }
+    return make_double2(sa, sb);
+}
+
+}  // namespace qva

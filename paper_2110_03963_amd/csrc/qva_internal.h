@@ -1,0 +1,77 @@
+// qva_internal.h -- launch descriptors shared by the C ABI layer and the
+// kernel translation units of libqva.  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "qva_device.h"
+
+namespace qva {
+
+// Tile geometry of the grouped passes: a tile is 2^kTileBits amplitudes,
+// held as kRegs amplitudes in each of kThreads threads.
+constexpr int kTileBits = 12;
+constexpr int kThreads = 256;
+constexpr int kRegs = 16;
+// Largest qubit group handled by a strided (high) pass: the tile keeps at
+// least 2^3 contiguous amplitudes (128 bytes) per row.
+constexpr int kMinColBits = 3;
+constexpr int kMaxHighBits = kTileBits - kMinColBits;
+
+// Pass flags of the hypercube-mixer tile pass.
+enum : int {
+    XP_INIT = 1,         // start from the uniform state instead of loading psi
+    XP_PHASE_PRE = 2,    // phase before the first mixer application
+    XP_MIX1 = 4,         // first mixer application (angle mix1)
+    XP_PHASE_MID = 8,    // phase between the two mixer applications
+    XP_MIX2 = 16,        // second mixer application (angle mix2)
+    XP_EXPECT = 32,      // accumulate sum |psi|^2 q and sum |psi|^2
+    XP_STORE = 64,       // write psi back
+    XP_FINAL_SCALE = 128 // multiply by the layer factor of mix1 (all qubits)
+};
+
+struct XPassParams {
+    double2* psi;
+    const double* q;
+    Angle mix1, mix2, phase;
+    int n;        // qubits of the register
+    int k;        // first target qubit of the tile's group
+    int col_bits; // contiguous low index bits per tile row (0 for the low group)
+    int flags;
+    double2* partials;  // one (f, norm) pair per tile when XP_EXPECT
+};
+
+struct SmallParams {
+    double2* psi;        // in/out (read unless SM_INIT, written if SM_STORE)
+    const double* q;
+    const double* gammas;
+    const double* ts;
+    double t_val;        // angle for SM_MIX_ONCE
+    int n;
+    int p;
+    int flags;
+    double* out_f;
+    double* out_norm;
+};
+
+enum : int {
+    SM_INIT = 1,
+    SM_EVOLVE = 2,    // p layers with gammas/ts
+    SM_MIX_ONCE = 4,  // one hypercube mixer with t_val
+    SM_EXPECT = 8,
+    SM_STORE = 16
+};
+
+hipError_t launch_xpass(const XPassParams& P, hipStream_t s);
+hipError_t launch_small(const SmallParams& P, hipStream_t s);
+hipError_t launch_init_uniform(double2* psi, int64_t N, hipStream_t s);
+hipError_t launch_phase(double2* psi, const double* q, int64_t N, double gamma, hipStream_t s);
+// Per-block partial (f, norm) over [0, N), then a fixed-order final sum.
+int64_t expect_partial_count(int64_t N);
+hipError_t launch_expect_partials(const double2* psi, const double* q, int64_t N,
+                                  double2* partials, hipStream_t s);
+hipError_t launch_final_reduce(const double2* partials, int64_t count, double* out_f,
+                               double* out_norm, hipStream_t s);
+
+}  // namespace qva

@@ -1,0 +1,334 @@
+// qva_xmix.hip -- hypercube-mixer (QAOA) passes over the state vector.
+//
+// The mixer exp(-i t sum_i X_i) is the product of commuting single-qubit
+// rotations exp(-i t X_i) (paper Sec. 2.3.1, eq. mixing_qaoa with the
+// hypercube W_X of its coupling figure).  Qubits are processed in groups: one
+// pass loads a tile of 2^12 amplitudes whose index bits cover a whole group,
+// applies every rotation of the group in registers (with LDS exchanges
+// between register layouts), and stores the tile back in place.  A tile of
+// the low group is 4096 contiguous amplitudes; a tile of a high group with g
+// qubits starting at bit k is 2^g rows (stride 2^k) of 2^(12-g) contiguous
+// amplitudes, so every global access is a run of >= 128 bytes.
+//
+// Elementwise work is fused into the passes: the initial state, the phase
+// exp(-i gamma q_j) (eq. phase_shift_qaoa), and the expectation sum
+// |psi_j|^2 q_j (eq. objective_generic).
+#include "qva_internal.h"
+
+namespace qva {
+namespace {
+
+// Register layouts of a 4096-amplitude tile over 256 threads x 16 registers.
+// Element index e (12 bits); the 4 register bits of a layout sit at element
+// bits [8,12) (A), [4,8) (B) or [0,4) (C); the thread index fills the rest
+// in ascending order.
+enum { LA = 0, LB = 1, LC = 2 };
+
+template <int L>
+__device__ __forceinline__ int elem(int t, int r)
+{
+    if constexpr (L == LA)
+        return t | (r << 8);
+    else if constexpr (L == LB)
+        return (t & 15) | (r << 4) | ((t >> 4) << 8);
+    else
+        return r | (t << 4);
+}
+
+template <int L>
+constexpr int reg_base()
+{
+    return L == LA ? 8 : (L == LB ? 4 : 0);
+}
+
+// Register bits of layout L that are target qubits when the tile's first C
+// element bits are plain columns.
+template <int C, int L>
+constexpr int target_mask()
+{
+    int m = 0;
+    for (int j = 0; j < 4; ++j)
+        if (reg_base<L>() + j >= C)
+            m |= 1 << j;
+    return m;
+}
+
+// LDS slot of element e: the low three bits are XOR-folded with the higher
+// bit triples, so that any 8 lanes stepping through 3 consecutive element
+// bits hit 8 distinct 16-byte bank groups.
+__device__ __forceinline__ int swz(int e) { return e ^ (((e >> 3) ^ (e >> 6) ^ (e >> 9)) & 7); }
+
+template <int FROM, int TO>
+__device__ __forceinline__ void exchange(double2 (&v)[kRegs], double2* lds, int t)
+{
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRegs; ++r)
+        lds[swz(elem<FROM>(t, r))] = v[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRegs; ++r)
+        v[r] = lds[swz(elem<TO>(t, r))];
+}
+
+template <int MASK, bool TAN>
+__device__ __forceinline__ void rotate_regs(double2 (&v)[kRegs], double k)
+{
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if (!((MASK >> j) & 1))
+            continue;
+#pragma unroll
+        for (int r = 0; r < kRegs; ++r) {
+            if (r & (1 << j))
+                continue;
+            if constexpr (TAN)
+                bfly_tan(v[r], v[r | (1 << j)], k);
+            else
+                bfly_cot(v[r], v[r | (1 << j)], k);
+        }
+    }
+}
+
+// Layout in which the first mixer application ends: B when the tile has
+// target bits in [4,8), else A.
+template <int C>
+constexpr int last_layout()
+{
+    return C < 8 ? LB : LA;
+}
+
+// Rotations of every target qubit of the tile; enters in A, leaves in
+// last_layout<C>().  Order A, C, B.
+template <int C, bool TAN>
+__device__ __forceinline__ void mix_forward(double2 (&v)[kRegs], double2* lds, int t, double k)
+{
+    rotate_regs<target_mask<C, LA>(), TAN>(v, k);
+    if constexpr (C < 4) {
+        exchange<LA, LC>(v, lds, t);
+        rotate_regs<target_mask<C, LC>(), TAN>(v, k);
+        exchange<LC, LB>(v, lds, t);
+        rotate_regs<target_mask<C, LB>(), TAN>(v, k);
+    } else if constexpr (C < 8) {
+        exchange<LA, LB>(v, lds, t);
+        rotate_regs<target_mask<C, LB>(), TAN>(v, k);
+    }
+}
+
+// Same rotations in reverse layout order; enters in last_layout<C>(), leaves in A.
+template <int C, bool TAN>
+__device__ __forceinline__ void mix_reverse(double2 (&v)[kRegs], double2* lds, int t, double k)
+{
+    if constexpr (C < 4) {
+        rotate_regs<target_mask<C, LB>(), TAN>(v, k);
+        exchange<LB, LC>(v, lds, t);
+        rotate_regs<target_mask<C, LC>(), TAN>(v, k);
+        exchange<LC, LA>(v, lds, t);
+    } else if constexpr (C < 8) {
+        rotate_regs<target_mask<C, LB>(), TAN>(v, k);
+        exchange<LB, LA>(v, lds, t);
+    }
+    rotate_regs<target_mask<C, LA>(), TAN>(v, k);
+}
+
+struct TileMap {
+    int64_t base;
+    int k;
+    int C;
+    __device__ __forceinline__ int64_t operator()(int e) const
+    {
+        return base + (e & ((1 << C) - 1)) + ((int64_t)(e >> C) << k);
+    }
+};
+
+// psi <- scale * exp(-i gamma q) psi in layout L
+template <int L>
+__device__ __forceinline__ void phase_regs(double2 (&v)[kRegs], const double* q, const TileMap& g,
+                                           int t, double gamma, double2 scale)
+{
+    double qq[kRegs];
+#pragma unroll
+    for (int r = 0; r < kRegs; ++r)
+        qq[r] = ld_nt(q + g(elem<L>(t, r)));
+#pragma unroll
+    for (int r = 0; r < kRegs; ++r)
+        v[r] = cmul(v[r], cmul(scale, expmi(gamma * qq[r])));
+}
+
+template <int L>
+__device__ __forceinline__ void tail(double2 (&v)[kRegs], const XPassParams& P, const TileMap& g,
+                                     int t, double2 fs, double* red)
+{
+    if (P.flags & XP_EXPECT) {
+        double qq[kRegs];
+#pragma unroll
+        for (int r = 0; r < kRegs; ++r)
+            qq[r] = ld_nt(P.q + g(elem<L>(t, r)));
+        double f = 0.0, nr = 0.0;
+#pragma unroll
+        for (int r = 0; r < kRegs; ++r) {
+            double a = v[r].x * v[r].x + v[r].y * v[r].y;
+            f = fma(a, qq[r], f);
+            nr += a;
+        }
+        const double s2 = fs.x * fs.x + fs.y * fs.y;
+        double2 tot = block_sum2(f * s2, nr * s2, red);
+        if (t == 0)
+            P.partials[blockIdx.x] = tot;
+    }
+    if (P.flags & XP_STORE) {
+        const bool sc = P.flags & XP_FINAL_SCALE;
+#pragma unroll
+        for (int r = 0; r < kRegs; ++r)
+            st_nt(P.psi + g(elem<L>(t, r)), sc ? cmul(v[r], fs) : v[r]);
+    }
+}
+
+template <int C>
+__global__ __launch_bounds__(kThreads, 2) void xpass_kernel(XPassParams P)
+{
+    __shared__ double2 lds[1 << kTileBits];
+    __shared__ double red[2 * (kThreads / 64)];
+    const int t = threadIdx.x;
+    const int64_t tile = blockIdx.x;
+    const int lobits = P.k - C;
+    TileMap g;
+    g.k = P.k;
+    g.C = C;
+    g.base = ((tile & ((int64_t(1) << lobits) - 1)) << C) |
+             ((tile >> lobits) << (P.k + kTileBits - C));
+
+    double2 v[kRegs];
+    const int flags = P.flags;
+    if (flags & XP_INIT) {
+        const double a0 = 1.0 / sqrt((double)(int64_t(1) << P.n));
+#pragma unroll
+        for (int r = 0; r < kRegs; ++r)
+            v[r] = make_double2(a0, 0.0);
+    } else {
+#pragma unroll
+        for (int r = 0; r < kRegs; ++r)
+            v[r] = ld_nt(P.psi + g(elem<LA>(t, r)));
+    }
+    if (flags & XP_PHASE_PRE)
+        phase_regs<LA>(v, P.q, g, t, angle_value(P.phase), make_double2(1.0, 0.0));
+
+    double2 S1 = make_double2(1.0, 0.0);
+    if (flags & XP_MIX1) {
+        const MixCoef m = mix_coef(angle_value(P.mix1));
+        if (m.tanform)
+            mix_forward<C, true>(v, lds, t, m.k);
+        else
+            mix_forward<C, false>(v, lds, t, m.k);
+        S1 = cpow_int(m.sigma, P.n);
+    }
+    if (flags & XP_PHASE_MID)
+        phase_regs<last_layout<C>()>(v, P.q, g, t, angle_value(P.phase), S1);
+    if (flags & XP_MIX2) {
+        const MixCoef m = mix_coef(angle_value(P.mix2));
+        if (m.tanform)
+            mix_reverse<C, true>(v, lds, t, m.k);
+        else
+            mix_reverse<C, false>(v, lds, t, m.k);
+    }
+    const double2 fs = (flags & XP_FINAL_SCALE) ? S1 : make_double2(1.0, 0.0);
+    if ((flags & XP_MIX2) || !(flags & XP_MIX1))
+        tail<LA>(v, P, g, t, fs, red);
+    else
+        tail<last_layout<C>()>(v, P, g, t, fs, red);
+}
+
+// ---------------------------------------------------------------------------
+// Whole state in one workgroup (n <= 12): every layer in a single launch.
+// ---------------------------------------------------------------------------
+__device__ void small_mix(double2* s, int n, double t)
+{
+    double sn, c;
+    sincos(t, &sn, &c);
+    const int N = 1 << n;
+    for (int i = 0; i < n; ++i) {
+        const int bit = 1 << i;
+        for (int m = threadIdx.x; m < N / 2; m += blockDim.x) {
+            const int j = ((m >> i) << (i + 1)) | (m & (bit - 1));
+            const double2 a = s[j], b = s[j | bit];
+            s[j] = make_double2(c * a.x + sn * b.y, c * a.y - sn * b.x);
+            s[j | bit] = make_double2(c * b.x + sn * a.y, c * b.y - sn * a.x);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void small_kernel(SmallParams P)
+{
+    __shared__ double2 s[1 << kTileBits];
+    __shared__ double red[2 * (kThreads / 64)];
+    const int N = 1 << P.n;
+    const int t = threadIdx.x;
+    const double a0 = 1.0 / sqrt((double)N);
+    for (int j = t; j < N; j += blockDim.x)
+        s[j] = (P.flags & SM_INIT) ? make_double2(a0, 0.0) : P.psi[j];
+    __syncthreads();
+    if (P.flags & SM_MIX_ONCE)
+        small_mix(s, P.n, P.t_val);
+    if (P.flags & SM_EVOLVE) {
+        for (int layer = 0; layer < P.p; ++layer) {
+            const double gam = P.gammas[layer];
+            for (int j = t; j < N; j += blockDim.x)
+                s[j] = cmul(s[j], expmi(gam * P.q[j]));
+            __syncthreads();
+            small_mix(s, P.n, P.ts[layer]);
+        }
+    }
+    if (P.flags & SM_EXPECT) {
+        double f = 0.0, nr = 0.0;
+        for (int j = t; j < N; j += blockDim.x) {
+            const double a = s[j].x * s[j].x + s[j].y * s[j].y;
+            f = fma(a, P.q[j], f);
+            nr += a;
+        }
+        const double2 tot = block_sum2(f, nr, red);
+        if (t == 0) {
+            P.out_f[0] = tot.x;
+            if (P.out_norm)
+                P.out_norm[0] = tot.y;
+        }
+    }
+    if (P.flags & SM_STORE)
+        for (int j = t; j < N; j += blockDim.x)
+            P.psi[j] = s[j];
+}
+
+}  // namespace
+
+hipError_t launch_xpass(const XPassParams& P, hipStream_t s)
+{
+    const unsigned grid = (unsigned)(int64_t(1) << (P.n - kTileBits));
+    switch (P.col_bits) {
+#define QVA_XPASS_CASE(CB)                                                        \
+    case CB:                                                                      \
+        hipLaunchKernelGGL(xpass_kernel<CB>, dim3(grid), dim3(kThreads), 0, s, P); \
+        break;
+        QVA_XPASS_CASE(0)
+        QVA_XPASS_CASE(3)
+        QVA_XPASS_CASE(4)
+        QVA_XPASS_CASE(5)
+        QVA_XPASS_CASE(6)
+        QVA_XPASS_CASE(7)
+        QVA_XPASS_CASE(8)
+        QVA_XPASS_CASE(9)
+        QVA_XPASS_CASE(10)
+        QVA_XPASS_CASE(11)
+#undef QVA_XPASS_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_small(const SmallParams& P, hipStream_t s)
+{
+    hipLaunchKernelGGL(small_kernel, dim3(1), dim3(kThreads), 0, s, P);
+    return hipGetLastError();
+}
+
+}  // namespace qva

@@ -1,0 +1,246 @@
+"""PyTorch-facing API of libqva.
+
+Tensors provide device memory and the current HIP stream; all arithmetic runs
+in the library's HIP kernels.  Amplitudes are torch.complex128, qualities and
+eigenvalues torch.float64, all on the same GPU.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import math
+
+import torch
+
+from . import _lib
+
+MIXERS = {"x": _lib.QVA_MIX_X, "circulant": _lib.QVA_MIX_CIRCULANT}
+LAMBDA_KINDS = {"array": _lib.QVA_LAMBDA_ARRAY, "ring": _lib.QVA_LAMBDA_RING,
+                "complete": _lib.QVA_LAMBDA_COMPLETE}
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else t.data_ptr()
+
+
+def _need(t: torch.Tensor, dtype: torch.dtype, name: str) -> None:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on a GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _log2(N: int) -> int:
+    n = int(N).bit_length() - 1
+    if N < 1 or (1 << n) != N:
+        raise ValueError(f"length {N} is not a power of two")
+    return n
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor | None:
+    if nbytes == 0:
+        return None
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+# ---------------------------------------------------------------- primitives
+def init_uniform(psi: torch.Tensor) -> torch.Tensor:
+    """psi <- N^(-1/2) (1, ..., 1), in place."""
+    _need(psi, torch.complex128, "psi")
+    _lib.check("qva_init_uniform", _lib.load().qva_init_uniform(_ptr(psi), psi.numel(), _stream()))
+    return psi
+
+
+def phase(psi: torch.Tensor, q: torch.Tensor, gamma: float) -> torch.Tensor:
+    """psi <- exp(-i gamma q) psi, in place."""
+    _need(psi, torch.complex128, "psi")
+    _need(q, torch.float64, "q")
+    if q.numel() != psi.numel():
+        raise ValueError("q and psi differ in length")
+    _lib.check("qva_phase", _lib.load().qva_phase(_ptr(psi), _ptr(q), psi.numel(), float(gamma),
+                                                  _stream()))
+    return psi
+
+
+def mix_x(psi: torch.Tensor, t: float) -> torch.Tensor:
+    """psi <- exp(-i t sum_i X_i) psi, in place."""
+    _need(psi, torch.complex128, "psi")
+    n = _log2(psi.numel())
+    _lib.check("qva_mix_x", _lib.load().qva_mix_x(_ptr(psi), n, float(t), _stream()))
+    return psi
+
+
+def mix_circulant(psi: torch.Tensor, t: float, lam: torch.Tensor | None = None,
+                  kind: str = "array") -> torch.Tensor:
+    """psi <- F^-1 diag(exp(-i t lambda)) F psi, in place."""
+    _need(psi, torch.complex128, "psi")
+    if kind == "array":
+        _need(lam, torch.float64, "lam")
+        if lam.numel() != psi.numel():
+            raise ValueError("lam and psi differ in length")
+    _lib.check("qva_mix_circulant",
+               _lib.load().qva_mix_circulant(_ptr(psi), _ptr(lam) if kind == "array" else None,
+                                             LAMBDA_KINDS[kind], psi.numel(), float(t), _stream()))
+    return psi
+
+
+def expectation(psi: torch.Tensor, q: torch.Tensor) -> tuple[torch.Tensor, torch.Tensor]:
+    """(sum |psi|^2 q, sum |psi|^2) as 0-d float64 device tensors."""
+    _need(psi, torch.complex128, "psi")
+    _need(q, torch.float64, "q")
+    if q.numel() != psi.numel():
+        raise ValueError("q and psi differ in length")
+    lib = _lib.load()
+    out = torch.empty(2, dtype=torch.float64, device=psi.device)
+    ws = _workspace(lib.qva_expectation_workspace_bytes(psi.numel()), psi.device)
+    _lib.check("qva_expectation",
+               lib.qva_expectation(_ptr(psi), _ptr(q), psi.numel(), out.data_ptr(),
+                                   out.data_ptr() + 8, _ptr(ws), 0 if ws is None else ws.numel(),
+                                   _stream()))
+    return out[0], out[1]
+
+
+# ------------------------------------------------------------- problem
+class Problem:
+    """A QVA instance: quality vector q (device float64) and the mixer.
+
+    mixer "x": W = sum_i X_i on log2(len(q)) qubits.
+    mixer "circulant": W circulant with eigenvalues lam (natural order) or
+    lambda_kind "ring" / "complete".
+    """
+
+    def __init__(self, q: torch.Tensor, mixer: str = "x", lam: torch.Tensor | None = None,
+                 lambda_kind: str = "array"):
+        _need(q, torch.float64, "q")
+        self.q = q
+        self.n = _log2(q.numel())
+        self.mixer = mixer
+        self.lambda_kind = lambda_kind if mixer == "circulant" else "array"
+        self.lam = lam
+        if mixer == "circulant" and lambda_kind == "array":
+            _need(lam, torch.float64, "lam")
+            if lam.numel() != q.numel():
+                raise ValueError("lam and q differ in length")
+        self._c = _lib.QvaProblem(MIXERS[mixer], self.n, _ptr(q),
+                                  _ptr(lam) if (mixer == "circulant" and lambda_kind == "array") else None,
+                                  LAMBDA_KINDS[self.lambda_kind])
+
+    @property
+    def N(self) -> int:
+        return 1 << self.n
+
+    @property
+    def device(self):
+        return self.q.device
+
+    def cstruct(self):
+        return ctypes.byref(self._c)
+
+    def workspace_bytes(self, p: int, for_grad: bool = False) -> int:
+        return int(_lib.load().qva_workspace_bytes(self.cstruct(), int(p), int(for_grad)))
+
+
+def _angles(x, device) -> torch.Tensor:
+    if isinstance(x, torch.Tensor):
+        x = x.detach().to(device=device, dtype=torch.float64).contiguous()
+        return x
+    return torch.tensor(list(x), dtype=torch.float64, device=device)
+
+
+def evolve(problem: Problem, gammas, ts, psi: torch.Tensor | None = None, store: bool = True,
+           workspace: torch.Tensor | None = None):
+    """Run the p-layer evolution from the uniform state.
+
+    Returns (f, norm, psi) with f, norm 0-d device tensors and psi the final
+    state (a new tensor unless one is passed in).
+    """
+    dev = problem.device
+    g = _angles(gammas, dev)
+    t = _angles(ts, dev)
+    if g.numel() != t.numel():
+        raise ValueError("one gamma and one t per layer")
+    p = g.numel()
+    if psi is None:
+        psi = torch.empty(problem.N, dtype=torch.complex128, device=dev)
+    else:
+        _need(psi, torch.complex128, "psi")
+        if psi.numel() != problem.N:
+            raise ValueError("psi has the wrong length")
+    lib = _lib.load()
+    need = problem.workspace_bytes(p)
+    if workspace is None or workspace.numel() < need:
+        workspace = _workspace(need, dev)
+    out = torch.empty(2, dtype=torch.float64, device=dev)
+    flags = 0 if store else _lib.QVA_EVOLVE_SKIP_FINAL_STATE
+    _lib.check("qva_evolve",
+               lib.qva_evolve(problem.cstruct(), g.data_ptr(), t.data_ptr(), p, psi.data_ptr(),
+                              out.data_ptr(), out.data_ptr() + 8, flags, _ptr(workspace),
+                              0 if workspace is None else workspace.numel(), _stream()))
+    return out[0], out[1], psi
+
+
+def grad(problem: Problem, gammas, ts, psi: torch.Tensor | None = None,
+         chi: torch.Tensor | None = None, workspace: torch.Tensor | None = None):
+    """(f, df/dgamma, df/dt) by the adjoint method (device tensors)."""
+    dev = problem.device
+    g = _angles(gammas, dev)
+    t = _angles(ts, dev)
+    if g.numel() != t.numel():
+        raise ValueError("one gamma and one t per layer")
+    p = g.numel()
+    if psi is None:
+        psi = torch.empty(problem.N, dtype=torch.complex128, device=dev)
+    if chi is None:
+        chi = torch.empty(problem.N, dtype=torch.complex128, device=dev)
+    _need(psi, torch.complex128, "psi")
+    _need(chi, torch.complex128, "chi")
+    lib = _lib.load()
+    need = problem.workspace_bytes(p, True)
+    if workspace is None or workspace.numel() < need:
+        workspace = _workspace(need, dev)
+    f = torch.empty((), dtype=torch.float64, device=dev)
+    dg = torch.empty(p, dtype=torch.float64, device=dev)
+    dt = torch.empty(p, dtype=torch.float64, device=dev)
+    _lib.check("qva_grad",
+               lib.qva_grad(problem.cstruct(), g.data_ptr(), t.data_ptr(), p, psi.data_ptr(),
+                            chi.data_ptr(), f.data_ptr(), dg.data_ptr(), dt.data_ptr(),
+                            _ptr(workspace), 0 if workspace is None else workspace.numel(),
+                            _stream()))
+    return f, dg, dt
+
+
+class QVAExpectation(torch.autograd.Function):
+    """f(gamma, t) = <psi_p|Q|psi_p> with the adjoint gradient as backward.
+
+    forward runs the adjoint sweep at once (it yields f too) and saves the
+    gradient; backward scales it by the incoming gradient.
+    """
+
+    @staticmethod
+    def forward(ctx, gammas: torch.Tensor, ts: torch.Tensor, problem: Problem):
+        if ctx.needs_input_grad[0] or ctx.needs_input_grad[1]:
+            f, dg, dt = grad(problem, gammas, ts)
+            ctx.save_for_backward(dg, dt)
+        else:
+            f, _, _ = evolve(problem, gammas, ts, store=False)
+            ctx.save_for_backward(None, None)
+        return f.clone()
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        dg, dt = ctx.saved_tensors
+        return (None if dg is None else grad_out * dg,
+                None if dt is None else grad_out * dt, None)
+
+
+def expectation_value(problem: Problem, gammas: torch.Tensor, ts: torch.Tensor) -> torch.Tensor:
+    """Differentiable f(gamma, t) (float64 device tensors in, 0-d tensor out)."""
+    return QVAExpectation.apply(gammas, ts, problem)
