@@ -161,6 +161,52 @@ int qva_grad(const qva_problem *P, const double *gammas_dev, const double *ts_de
              qva_c128 *psi, qva_c128 *chi, double *out_f_dev, double *dgammas_dev,
              double *dts_dev, void *work, size_t work_bytes, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Plan introspection and per-launch timing (for cost models and profilers).
+ * ---------------------------------------------------------------------- */
+
+/* Kinds of the launches that make up a plan. */
+typedef enum {
+    QVA_PASS_WHOLE = 0,      /* whole state in one workgroup (n <= 12), all layers  */
+    QVA_PASS_FIRST = 1,      /* psi_0, phase of layer 1, first qubit group           */
+    QVA_PASS_MIDDLE = 2,     /* one qubit group of one layer                         */
+    QVA_PASS_BOUNDARY = 3,   /* group of layer k, phase of layer k+1, group of k+1   */
+    QVA_PASS_LAST = 4,       /* last group of the last layer + <Q> partial sums      */
+    QVA_PASS_LAST_STORE = 5, /* as QVA_PASS_LAST, also writes psi_p                  */
+    QVA_PASS_INIT = 6,       /* elementwise psi_0                                    */
+    QVA_PASS_EXPECT = 7,     /* elementwise <Q> partial sums                         */
+    QVA_PASS_REDUCE = 8      /* fixed-order sum of the partial sums                  */
+} qva_pass_kind;
+
+/* One launch of a plan.  `bytes` is the algorithmic HBM traffic of the
+ * launch: every array element the launch must read or write, counted once
+ * (16 bytes per amplitude, 8 per quality or eigenvalue). */
+typedef struct {
+    int kind;        /* a qva_pass_kind                                  */
+    int group_first; /* first qubit of the launch's qubit group (or -1)  */
+    int group_bits;  /* qubits in the group (or 0)                       */
+    int col_bits;    /* contiguous low index bits per tile row            */
+    int mix_layer;   /* layer (0-based) of the first mixer application, or -1 */
+    int mix_layer2;  /* layer of the second mixer application, or -1          */
+    int phase_layer; /* layer whose phase the launch applies, or -1           */
+    double bytes;    /* algorithmic HBM bytes of the launch               */
+} qva_pass_info;
+
+/* Number of launches qva_evolve (for_grad = 0, with `flags` as given to it)
+ * or qva_grad (for_grad = 1) enqueues for P at depth p; the first min(count,
+ * max_out) launches are described in out (out may be NULL when max_out = 0).
+ * Returns a negative qva_status on invalid arguments. */
+int qva_plan(const qva_problem *P, int p, int for_grad, int flags, qva_pass_info *out,
+             int max_out);
+
+/* qva_evolve that also records events[2i] (hipEvent_t, passed as void*)
+ * before launch i of the plan and events[2i+1] after it, for i < n_events/2.
+ * Events are created and owned by the caller.  Same results as qva_evolve. */
+int qva_evolve_timed(const qva_problem *P, const double *gammas_dev, const double *ts_dev, int p,
+                     qva_c128 *psi, double *out_f_dev, double *out_norm_dev, int flags,
+                     void *work, size_t work_bytes, void *const *events, int n_events,
+                     void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -40,6 +40,23 @@ class QvaProblem(ctypes.Structure):
     ]
 
 
+class QvaPassInfo(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int),
+        ("group_first", ctypes.c_int),
+        ("group_bits", ctypes.c_int),
+        ("col_bits", ctypes.c_int),
+        ("mix_layer", ctypes.c_int),
+        ("mix_layer2", ctypes.c_int),
+        ("phase_layer", ctypes.c_int),
+        ("bytes", ctypes.c_double),
+    ]
+
+
+PASS_KINDS = {0: "whole", 1: "first", 2: "middle", 3: "boundary", 4: "last", 5: "last_store",
+              6: "init", 7: "expect", 8: "reduce"}
+
+
 class QvaError(RuntimeError):
     def __init__(self, fn: str, status: int, text: str):
         super().__init__(f"{fn}: {text} (status {status})")
@@ -66,6 +83,9 @@ SIGNATURES = {
     "qva_expectation": (_I, [_P, _P, _I64, _P, _P, _P, _SZ, _P]),
     "qva_evolve": (_I, [_PROB, _P, _P, _I, _P, _P, _P, _I, _P, _SZ, _P]),
     "qva_grad": (_I, [_PROB, _P, _P, _I, _P, _P, _P, _P, _P, _P, _SZ, _P]),
+    "qva_plan": (_I, [_PROB, _I, _I, _I, ctypes.POINTER(QvaPassInfo), _I]),
+    "qva_evolve_timed": (_I, [_PROB, _P, _P, _I, _P, _P, _P, _I, _P, _SZ,
+                              ctypes.POINTER(ctypes.c_void_p), _I, _P]),
 }
 
 _lib = None

@@ -2,6 +2,7 @@
 // kernel enqueueing.  Declared in include/qva.h.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <stdint.h>
 #include <vector>
 
@@ -18,16 +19,6 @@ bool aligned(const void* p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p
 int hip_status(hipError_t e) { return e == hipSuccess ? QVA_OK : QVA_ERR_HIP; }
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
-
-int log2_exact(int64_t N)
-{
-    if (N < 1)
-        return -1;
-    int n = 0;
-    while ((int64_t(1) << n) < N)
-        ++n;
-    return (int64_t(1) << n) == N ? n : -1;
-}
 
 int check_problem(const qva_problem* P, int p)
 {
@@ -87,47 +78,148 @@ XPassParams xpass_base(double2* psi, const double* q, int n, const XGroup& g)
     return x;
 }
 
+// One launch of a plan (see qva_pass_info).
+struct Launch {
+    int kind;
+    int group;        // index into x_groups(n), or -1
+    int xmode;        // XMODE_* for tile passes
+    int layer1, layer2, phase_layer;
+};
+
+std::vector<Launch> x_launches(int n, int p, bool store)
+{
+    std::vector<Launch> L;
+    if (n <= kTileBits) {
+        L.push_back({QVA_PASS_WHOLE, 0, 0, -1, -1, -1});
+        return L;
+    }
+    if (p == 0) {
+        L.push_back({QVA_PASS_INIT, -1, 0, -1, -1, -1});
+        L.push_back({QVA_PASS_EXPECT, -1, 0, -1, -1, -1});
+        L.push_back({QVA_PASS_REDUCE, -1, 0, -1, -1, -1});
+        return L;
+    }
+    const int P = (int)x_groups(n).size();
+    for (const XPass& ps : x_evolve_plan(P, p, store)) {
+        int kind = QVA_PASS_MIDDLE;
+        if (ps.flags == XMODE_FIRST)
+            kind = QVA_PASS_FIRST;
+        else if (ps.flags == XMODE_BOUNDARY)
+            kind = QVA_PASS_BOUNDARY;
+        else if (ps.flags == XMODE_LAST)
+            kind = QVA_PASS_LAST;
+        else if (ps.flags == XMODE_LAST_STORE)
+            kind = QVA_PASS_LAST_STORE;
+        L.push_back({kind, ps.group, ps.flags, ps.layer1, ps.layer2, ps.phase_layer});
+    }
+    L.push_back({QVA_PASS_REDUCE, -1, 0, -1, -1, -1});
+    return L;
+}
+
+// Algorithmic HBM bytes of a launch (each element read or written once).
+double launch_bytes(const Launch& l, int n, bool store)
+{
+    const double N = std::ldexp(1.0, n);
+    const double amp = 16.0, real = 8.0;
+    switch (l.kind) {
+    case QVA_PASS_WHOLE:
+        return real * N + (store ? amp * N : 0.0);
+    case QVA_PASS_FIRST:
+        return (real + amp) * N;
+    case QVA_PASS_MIDDLE:
+        return 2 * amp * N;
+    case QVA_PASS_BOUNDARY:
+        return (2 * amp + real) * N;
+    case QVA_PASS_LAST:
+        return (amp + real) * N;
+    case QVA_PASS_LAST_STORE:
+        return (2 * amp + real) * N;
+    case QVA_PASS_INIT:
+        return amp * N;
+    case QVA_PASS_EXPECT:
+        return (amp + real) * N;
+    case QVA_PASS_REDUCE:
+        return n > kTileBits ? 16.0 * std::ldexp(1.0, n - kTileBits) : 16.0;
+    default:
+        return 0.0;
+    }
+}
+
+// Records an event pair around every launch when the caller asked for it.
+struct EventHook {
+    void* const* ev = nullptr;
+    int n = 0;
+    int i = 0;
+    void before(hipStream_t s)
+    {
+        if (ev && 2 * i + 1 < n)
+            (void)hipEventRecord(reinterpret_cast<hipEvent_t>(ev[2 * i]), s);
+    }
+    void after(hipStream_t s)
+    {
+        if (ev && 2 * i + 1 < n)
+            (void)hipEventRecord(reinterpret_cast<hipEvent_t>(ev[2 * i + 1]), s);
+        ++i;
+    }
+};
+
 int evolve_x(const qva_problem* P, const double* gammas, const double* ts, int p, double2* psi,
-             double* out_f, double* out_norm, bool store, double2* partials, hipStream_t s)
+             double* out_f, double* out_norm, bool store, double2* partials, hipStream_t s,
+             EventHook& hook)
 {
     const int n = P->n_qubits;
-    if (n <= kTileBits) {
-        SmallParams sp{};
-        sp.psi = psi;
-        sp.q = P->q;
-        sp.gammas = gammas;
-        sp.ts = ts;
-        sp.n = n;
-        sp.p = p;
-        sp.flags = SM_INIT | SM_EVOLVE | SM_EXPECT | (store ? SM_STORE : 0);
-        sp.out_f = out_f;
-        sp.out_norm = out_norm;
-        return hip_status(launch_small(sp, s));
-    }
     const int64_t N = int64_t(1) << n;
-    if (p == 0) {
-        hipError_t e = launch_init_uniform(psi, N, s);
-        if (e == hipSuccess)
-            e = launch_expect_partials(psi, P->q, N, partials, s);
-        if (e == hipSuccess)
-            e = launch_final_reduce(partials, expect_partial_count(N), out_f, out_norm, s);
-        return hip_status(e);
-    }
     const std::vector<XGroup> groups = x_groups(n);
-    const std::vector<XPass> plan = x_evolve_plan((int)groups.size(), p, store);
-    for (const XPass& ps : plan) {
-        XPassParams x = xpass_base(psi, P->q, n, groups[ps.group]);
-        x.flags = ps.flags;
-        x.mix1 = dev_angle(ts, ps.layer1);
-        x.mix2 = dev_angle(ts, ps.layer2 >= 0 ? ps.layer2 : 0);
-        x.phase = dev_angle(gammas, ps.phase_layer >= 0 ? ps.phase_layer : 0);
-        x.partials = partials;
-        hipError_t e = launch_xpass(x, s);
+    for (const Launch& l : x_launches(n, p, store)) {
+        hipError_t e = hipSuccess;
+        hook.before(s);
+        switch (l.kind) {
+        case QVA_PASS_WHOLE: {
+            SmallParams sp{};
+            sp.psi = psi;
+            sp.q = P->q;
+            sp.gammas = gammas;
+            sp.ts = ts;
+            sp.n = n;
+            sp.p = p;
+            sp.flags = SM_INIT | SM_EVOLVE | SM_EXPECT | (store ? SM_STORE : 0);
+            sp.out_f = out_f;
+            sp.out_norm = out_norm;
+            e = launch_small(sp, s);
+            break;
+        }
+        case QVA_PASS_INIT:
+            e = launch_init_uniform(psi, N, s);
+            break;
+        case QVA_PASS_EXPECT:
+            e = launch_expect_partials(psi, P->q, N, partials, s);
+            break;
+        case QVA_PASS_REDUCE: {
+            const int64_t count = p == 0 ? expect_partial_count(N) : (int64_t(1) << (n - kTileBits));
+            e = launch_final_reduce(partials, count, out_f, out_norm, s);
+            break;
+        }
+        default: {
+            XPassParams x = xpass_base(psi, P->q, n, groups[l.group]);
+            x.flags = l.xmode;
+            x.mix1 = dev_angle(ts, l.layer1);
+            x.mix2 = dev_angle(ts, l.layer2 >= 0 ? l.layer2 : 0);
+            x.phase = dev_angle(gammas, l.phase_layer >= 0 ? l.phase_layer : 0);
+            x.partials = partials;
+            e = launch_xpass(x, s);
+            break;
+        }
+        }
+        hook.after(s);
         if (e != hipSuccess)
             return QVA_ERR_HIP;
     }
-    return hip_status(launch_final_reduce(partials, int64_t(1) << (n - kTileBits), out_f, out_norm, s));
+    return QVA_OK;
 }
+
+int evolve_common(const qva_problem* P, const double* gammas_dev, const double* ts_dev, int p,
+                  qva_c128* psi, double* out_f_dev, double* out_norm_dev, int flags, void* work,
+                  size_t work_bytes, void* stream, EventHook& hook);
 
 }  // namespace
 
@@ -264,26 +356,49 @@ int qva_evolve(const qva_problem* P, const double* gammas_dev, const double* ts_
                qva_c128* psi, double* out_f_dev, double* out_norm_dev, int flags, void* work,
                size_t work_bytes, void* stream)
 {
+    EventHook hook;
+    return evolve_common(P, gammas_dev, ts_dev, p, psi, out_f_dev, out_norm_dev, flags, work,
+                         work_bytes, stream, hook);
+}
+
+int qva_evolve_timed(const qva_problem* P, const double* gammas_dev, const double* ts_dev, int p,
+                     qva_c128* psi, double* out_f_dev, double* out_norm_dev, int flags, void* work,
+                     size_t work_bytes, void* const* events, int n_events, void* stream)
+{
+    if (!events || n_events < 0)
+        return QVA_ERR_ARG;
+    EventHook hook;
+    hook.ev = events;
+    hook.n = n_events;
+    return evolve_common(P, gammas_dev, ts_dev, p, psi, out_f_dev, out_norm_dev, flags, work,
+                         work_bytes, stream, hook);
+}
+
+int qva_plan(const qva_problem* P, int p, int for_grad, int flags, qva_pass_info* out, int max_out)
+{
     int st = check_problem(P, p);
     if (st != QVA_OK)
         return st;
-    if (!psi || !out_f_dev || (p > 0 && (!gammas_dev || !ts_dev)))
+    if (max_out < 0 || (max_out > 0 && !out) || (flags & ~QVA_EVOLVE_SKIP_FINAL_STATE))
         return QVA_ERR_ARG;
-    if (flags & ~QVA_EVOLVE_SKIP_FINAL_STATE)
-        return QVA_ERR_ARG;
-    if (!aligned(psi, 16) || !aligned(out_f_dev, 8) || (out_norm_dev && !aligned(out_norm_dev, 8)) ||
-        (gammas_dev && !aligned(gammas_dev, 8)) || (ts_dev && !aligned(ts_dev, 8)))
-        return QVA_ERR_ALIGN;
-    const size_t need = qva_workspace_bytes(P, p, 0);
-    if (need && (!work || work_bytes < need))
-        return QVA_ERR_WORKSPACE;
-    if (work && !aligned(work, 16))
-        return QVA_ERR_ALIGN;
+    if (for_grad || P->mixer != QVA_MIX_X)
+        return QVA_ERR_UNSUPPORTED;
     const bool store = !(flags & QVA_EVOLVE_SKIP_FINAL_STATE);
-    if (P->mixer == QVA_MIX_X)
-        return evolve_x(P, gammas_dev, ts_dev, p, reinterpret_cast<double2*>(psi), out_f_dev,
-                        out_norm_dev, store, reinterpret_cast<double2*>(work), as_stream(stream));
-    return QVA_ERR_UNSUPPORTED;
+    const int n = P->n_qubits;
+    const std::vector<XGroup> groups = x_groups(n);
+    const std::vector<Launch> L = x_launches(n, p, store);
+    for (int i = 0; i < (int)L.size() && i < max_out; ++i) {
+        const Launch& l = L[i];
+        out[i].kind = l.kind;
+        out[i].group_first = l.group >= 0 ? groups[l.group].k : -1;
+        out[i].group_bits = l.group >= 0 ? groups[l.group].bits : 0;
+        out[i].col_bits = l.group >= 0 ? groups[l.group].col_bits : 0;
+        out[i].mix_layer = l.layer1;
+        out[i].mix_layer2 = l.layer2;
+        out[i].phase_layer = l.phase_layer;
+        out[i].bytes = launch_bytes(l, n, store);
+    }
+    return (int)L.size();
 }
 
 int qva_grad(const qva_problem* P, const double* gammas_dev, const double* ts_dev, int p,
@@ -306,3 +421,34 @@ int qva_grad(const qva_problem* P, const double* gammas_dev, const double* ts_de
 }
 
 }  // extern "C"
+
+namespace {
+
+int evolve_common(const qva_problem* P, const double* gammas_dev, const double* ts_dev, int p,
+                  qva_c128* psi, double* out_f_dev, double* out_norm_dev, int flags, void* work,
+                  size_t work_bytes, void* stream, EventHook& hook)
+{
+    int st = check_problem(P, p);
+    if (st != QVA_OK)
+        return st;
+    if (!psi || !out_f_dev || (p > 0 && (!gammas_dev || !ts_dev)))
+        return QVA_ERR_ARG;
+    if (flags & ~QVA_EVOLVE_SKIP_FINAL_STATE)
+        return QVA_ERR_ARG;
+    if (!aligned(psi, 16) || !aligned(out_f_dev, 8) || (out_norm_dev && !aligned(out_norm_dev, 8)) ||
+        (gammas_dev && !aligned(gammas_dev, 8)) || (ts_dev && !aligned(ts_dev, 8)))
+        return QVA_ERR_ALIGN;
+    const size_t need = qva_workspace_bytes(P, p, 0);
+    if (need && (!work || work_bytes < need))
+        return QVA_ERR_WORKSPACE;
+    if (work && !aligned(work, 16))
+        return QVA_ERR_ALIGN;
+    const bool store = !(flags & QVA_EVOLVE_SKIP_FINAL_STATE);
+    if (P->mixer == QVA_MIX_X)
+        return evolve_x(P, gammas_dev, ts_dev, p, reinterpret_cast<double2*>(psi), out_f_dev,
+                        out_norm_dev, store, reinterpret_cast<double2*>(work), as_stream(stream),
+                        hook);
+    return QVA_ERR_UNSUPPORTED;
+}
+
+}  // namespace

@@ -31,6 +31,16 @@ enum : int {
     XP_FINAL_SCALE = 128 // multiply by the layer factor of mix1 (all qubits)
 };
 
+// The flag combinations the passes are compiled for.
+enum : int {
+    XMODE_FIRST = XP_INIT | XP_PHASE_PRE | XP_MIX1 | XP_STORE,
+    XMODE_MIDDLE = XP_MIX1 | XP_STORE,
+    XMODE_BOUNDARY = XP_MIX1 | XP_PHASE_MID | XP_MIX2 | XP_STORE,
+    XMODE_LAST = XP_MIX1 | XP_EXPECT | XP_FINAL_SCALE,
+    XMODE_LAST_STORE = XP_MIX1 | XP_EXPECT | XP_FINAL_SCALE | XP_STORE,
+    XMODE_MIX_SCALE = XP_MIX1 | XP_FINAL_SCALE | XP_STORE
+};
+
 struct XPassParams {
     double2* psi;
     const double* q;

@@ -155,11 +155,11 @@ __device__ __forceinline__ void phase_regs(double2 (&v)[kRegs], const double* q,
         v[r] = cmul(v[r], cmul(scale, expmi(gamma * qq[r])));
 }
 
-template <int L>
+template <int L, int FLAGS>
 __device__ __forceinline__ void tail(double2 (&v)[kRegs], const XPassParams& P, const TileMap& g,
                                      int t, double2 fs, double* red)
 {
-    if (P.flags & XP_EXPECT) {
+    if constexpr (FLAGS & XP_EXPECT) {
         double qq[kRegs];
 #pragma unroll
         for (int r = 0; r < kRegs; ++r)
@@ -176,15 +176,15 @@ __device__ __forceinline__ void tail(double2 (&v)[kRegs], const XPassParams& P, 
         if (t == 0)
             P.partials[blockIdx.x] = tot;
     }
-    if (P.flags & XP_STORE) {
-        const bool sc = P.flags & XP_FINAL_SCALE;
+    if constexpr (FLAGS & XP_STORE) {
+        constexpr bool sc = FLAGS & XP_FINAL_SCALE;
 #pragma unroll
         for (int r = 0; r < kRegs; ++r)
             st_nt(P.psi + g(elem<L>(t, r)), sc ? cmul(v[r], fs) : v[r]);
     }
 }
 
-template <int C>
+template <int C, int FLAGS>
 __global__ __launch_bounds__(kThreads, 2) void xpass_kernel(XPassParams P)
 {
     __shared__ double2 lds[1 << kTileBits];
@@ -199,8 +199,8 @@ __global__ __launch_bounds__(kThreads, 2) void xpass_kernel(XPassParams P)
              ((tile >> lobits) << (P.k + kTileBits - C));
 
     double2 v[kRegs];
-    const int flags = P.flags;
-    if (flags & XP_INIT) {
+    constexpr int flags = FLAGS;
+    if constexpr (flags & XP_INIT) {
         const double a0 = 1.0 / sqrt((double)(int64_t(1) << P.n));
 #pragma unroll
         for (int r = 0; r < kRegs; ++r)
@@ -210,11 +210,11 @@ __global__ __launch_bounds__(kThreads, 2) void xpass_kernel(XPassParams P)
         for (int r = 0; r < kRegs; ++r)
             v[r] = ld_nt(P.psi + g(elem<LA>(t, r)));
     }
-    if (flags & XP_PHASE_PRE)
+    if constexpr (flags & XP_PHASE_PRE)
         phase_regs<LA>(v, P.q, g, t, angle_value(P.phase), make_double2(1.0, 0.0));
 
     double2 S1 = make_double2(1.0, 0.0);
-    if (flags & XP_MIX1) {
+    if constexpr (flags & XP_MIX1) {
         const MixCoef m = mix_coef(angle_value(P.mix1));
         if (m.tanform)
             mix_forward<C, true>(v, lds, t, m.k);
@@ -222,9 +222,9 @@ __global__ __launch_bounds__(kThreads, 2) void xpass_kernel(XPassParams P)
             mix_forward<C, false>(v, lds, t, m.k);
         S1 = cpow_int(m.sigma, P.n);
     }
-    if (flags & XP_PHASE_MID)
+    if constexpr (flags & XP_PHASE_MID)
         phase_regs<last_layout<C>()>(v, P.q, g, t, angle_value(P.phase), S1);
-    if (flags & XP_MIX2) {
+    if constexpr (flags & XP_MIX2) {
         const MixCoef m = mix_coef(angle_value(P.mix2));
         if (m.tanform)
             mix_reverse<C, true>(v, lds, t, m.k);
@@ -232,10 +232,10 @@ __global__ __launch_bounds__(kThreads, 2) void xpass_kernel(XPassParams P)
             mix_reverse<C, false>(v, lds, t, m.k);
     }
     const double2 fs = (flags & XP_FINAL_SCALE) ? S1 : make_double2(1.0, 0.0);
-    if ((flags & XP_MIX2) || !(flags & XP_MIX1))
-        tail<LA>(v, P, g, t, fs, red);
+    if constexpr ((flags & XP_MIX2) || !(flags & XP_MIX1))
+        tail<LA, flags>(v, P, g, t, fs, red);
     else
-        tail<last_layout<C>()>(v, P, g, t, fs, red);
+        tail<last_layout<C>(), flags>(v, P, g, t, fs, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -300,29 +300,58 @@ __global__ __launch_bounds__(kThreads) void small_kernel(SmallParams P)
 
 }  // namespace
 
-hipError_t launch_xpass(const XPassParams& P, hipStream_t s)
+namespace {
+
+template <int C>
+hipError_t launch_xpass_c(const XPassParams& P, unsigned grid, hipStream_t s)
 {
-    const unsigned grid = (unsigned)(int64_t(1) << (P.n - kTileBits));
-    switch (P.col_bits) {
-#define QVA_XPASS_CASE(CB)                                                        \
-    case CB:                                                                      \
-        hipLaunchKernelGGL(xpass_kernel<CB>, dim3(grid), dim3(kThreads), 0, s, P); \
+    switch (P.flags) {
+#define QVA_XPASS_MODE(F)                                                            \
+    case F:                                                                          \
+        hipLaunchKernelGGL((xpass_kernel<C, F>), dim3(grid), dim3(kThreads), 0, s, P); \
         break;
-        QVA_XPASS_CASE(0)
-        QVA_XPASS_CASE(3)
-        QVA_XPASS_CASE(4)
-        QVA_XPASS_CASE(5)
-        QVA_XPASS_CASE(6)
-        QVA_XPASS_CASE(7)
-        QVA_XPASS_CASE(8)
-        QVA_XPASS_CASE(9)
-        QVA_XPASS_CASE(10)
-        QVA_XPASS_CASE(11)
-#undef QVA_XPASS_CASE
+        QVA_XPASS_MODE(XMODE_FIRST)
+        QVA_XPASS_MODE(XMODE_MIDDLE)
+        QVA_XPASS_MODE(XMODE_BOUNDARY)
+        QVA_XPASS_MODE(XMODE_LAST)
+        QVA_XPASS_MODE(XMODE_LAST_STORE)
+        QVA_XPASS_MODE(XMODE_MIX_SCALE)
+#undef QVA_XPASS_MODE
     default:
         return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_xpass(const XPassParams& P, hipStream_t s)
+{
+    const unsigned grid = (unsigned)(int64_t(1) << (P.n - kTileBits));
+    switch (P.col_bits) {
+    case 0:
+        return launch_xpass_c<0>(P, grid, s);
+    case 3:
+        return launch_xpass_c<3>(P, grid, s);
+    case 4:
+        return launch_xpass_c<4>(P, grid, s);
+    case 5:
+        return launch_xpass_c<5>(P, grid, s);
+    case 6:
+        return launch_xpass_c<6>(P, grid, s);
+    case 7:
+        return launch_xpass_c<7>(P, grid, s);
+    case 8:
+        return launch_xpass_c<8>(P, grid, s);
+    case 9:
+        return launch_xpass_c<9>(P, grid, s);
+    case 10:
+        return launch_xpass_c<10>(P, grid, s);
+    case 11:
+        return launch_xpass_c<11>(P, grid, s);
+    default:
+        return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_small(const SmallParams& P, hipStream_t s)

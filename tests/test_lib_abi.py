@@ -1,0 +1,162 @@
+"""Host-side checks of libqva (no GPU needed, nothing is launched).
+
+* the library loads and exports every function include/qva.h declares;
+* argument validation returns the documented status before any launch;
+* the pass planner covers every qubit once per layer, orders phases between
+  layers, and has the documented pass count p(P-1)+1.
+"""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qva.h")
+
+_lib = pytest.importorskip("paper_2110_03963_amd._lib")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2110_03963_amd import build
+        build.build()
+    return _lib.load()
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qva_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared_functions()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(_lib.SIGNATURES), "binding and header disagree"
+
+
+def test_status_strings(lib):
+    for st in [0, -1, -2, -3, -4, -5, -6]:
+        assert lib.qva_status_string(st)
+    assert lib.qva_status_string(-4) == b"workspace missing or too small"
+    assert b"gfx950" in lib.qva_version()
+
+
+FAKE = 0x7F0000001000  # never dereferenced: every call below fails validation first
+
+
+def _prob(mixer=0, n=20, q=FAKE, lam=None, kind=0):
+    return _lib.QvaProblem(mixer, n, q, lam, kind)
+
+
+def test_validation_errors(lib):
+    S = _lib
+    assert lib.qva_init_uniform(None, 16, None) == S.QVA_ERR_ARG
+    assert lib.qva_init_uniform(FAKE, 0, None) == S.QVA_ERR_SIZE
+    assert lib.qva_init_uniform(FAKE + 8, 16, None) == S.QVA_ERR_ALIGN
+    assert lib.qva_phase(FAKE, None, 16, 0.1, None) == S.QVA_ERR_ARG
+    assert lib.qva_phase(FAKE, FAKE + 4, 16, 0.1, None) == S.QVA_ERR_ALIGN
+    assert lib.qva_mix_x(FAKE, 0, 0.1, None) == S.QVA_ERR_SIZE
+    assert lib.qva_mix_x(FAKE, 34, 0.1, None) == S.QVA_ERR_SIZE
+    assert lib.qva_mix_x(FAKE + 8, 5, 0.1, None) == S.QVA_ERR_ALIGN
+    assert lib.qva_mix_x(None, 5, 0.1, None) == S.QVA_ERR_ARG
+    assert lib.qva_expectation(FAKE, FAKE, 1 << 20, FAKE, None, None, 0, None) == S.QVA_ERR_WORKSPACE
+    assert lib.qva_expectation(FAKE, FAKE, 0, FAKE, None, FAKE, 1 << 20, None) == S.QVA_ERR_SIZE
+
+
+def test_evolve_validation(lib):
+    S = _lib
+    pr = _prob(n=20)
+    ref = ctypes.byref
+    ws = lib.qva_workspace_bytes(ref(pr), 3, 0)
+    assert ws == 16 * (1 << 8)
+    # workspace too small / missing
+    assert lib.qva_evolve(ref(pr), FAKE, FAKE, 3, FAKE, FAKE, None, 0, FAKE, ws - 16, None) == S.QVA_ERR_WORKSPACE
+    assert lib.qva_evolve(ref(pr), FAKE, FAKE, 3, FAKE, FAKE, None, 0, None, 0, None) == S.QVA_ERR_WORKSPACE
+    # bad depth, bad flags, null parameters, misaligned outputs
+    assert lib.qva_evolve(ref(pr), FAKE, FAKE, -1, FAKE, FAKE, None, 0, FAKE, ws, None) == S.QVA_ERR_ARG
+    assert lib.qva_evolve(ref(pr), FAKE, FAKE, 3, FAKE, FAKE, None, 4, FAKE, ws, None) == S.QVA_ERR_ARG
+    assert lib.qva_evolve(ref(pr), None, FAKE, 3, FAKE, FAKE, None, 0, FAKE, ws, None) == S.QVA_ERR_ARG
+    assert lib.qva_evolve(ref(pr), FAKE, FAKE, 3, FAKE, FAKE + 4, None, 0, FAKE, ws, None) == S.QVA_ERR_ALIGN
+    assert lib.qva_evolve(ref(pr), FAKE, FAKE, 3, FAKE + 8, FAKE, None, 0, FAKE, ws, None) == S.QVA_ERR_ALIGN
+    # problem descriptor errors
+    for bad, st in [(_prob(n=0), S.QVA_ERR_SIZE), (_prob(n=34), S.QVA_ERR_SIZE),
+                    (_prob(mixer=7), S.QVA_ERR_ARG), (_prob(q=None), S.QVA_ERR_ARG),
+                    (_prob(q=FAKE + 2), S.QVA_ERR_ALIGN),
+                    (_prob(mixer=1, kind=0, lam=None), S.QVA_ERR_ARG),
+                    (_prob(mixer=1, kind=9, lam=FAKE), S.QVA_ERR_ARG)]:
+        assert lib.qva_evolve(ref(bad), FAKE, FAKE, 3, FAKE, FAKE, None, 0, FAKE, 1 << 30, None) == st
+    assert lib.qva_evolve(None, FAKE, FAKE, 3, FAKE, FAKE, None, 0, FAKE, 1 << 30, None) == S.QVA_ERR_ARG
+    assert lib.qva_workspace_bytes(None, 3, 0) == 0
+
+
+def _plan(lib, n, p, flags=0):
+    pr = _prob(n=n)
+    cnt = lib.qva_plan(ctypes.byref(pr), p, 0, flags, None, 0)
+    assert cnt > 0
+    arr = (_lib.QvaPassInfo * cnt)()
+    assert lib.qva_plan(ctypes.byref(pr), p, 0, flags, arr, cnt) == cnt
+    return list(arr)
+
+
+@pytest.mark.parametrize("n", [13, 20, 21, 22, 26, 28, 30, 33])
+@pytest.mark.parametrize("p", [1, 2, 3, 8, 12])
+def test_plan_schedule(lib, n, p):
+    plan = _plan(lib, n, p)
+    assert plan[-1].kind == 8  # final reduce
+    passes = plan[:-1]
+    groups = sorted({(x.group_first, x.group_bits) for x in passes})
+    # groups tile the qubits [0, n) exactly
+    covered = []
+    for k, b in groups:
+        covered.extend(range(k, k + b))
+    assert covered == list(range(n))
+    P = len(groups)
+    assert len(passes) == p * (P - 1) + 1
+    # replay: each layer applies every group once, phase k between layers k-1 and k
+    done = {L: set() for L in range(p)}
+    phased = set()
+    for x in passes:
+        if x.phase_layer >= 0 and x.kind == 1:
+            assert x.phase_layer == 0
+            phased.add(0)
+        if x.mix_layer >= 0:
+            L = x.mix_layer
+            assert L in phased
+            assert (x.group_first, x.group_bits) not in done[L]
+            done[L].add((x.group_first, x.group_bits))
+        if x.kind == 3:
+            L2 = x.phase_layer
+            assert L2 == x.mix_layer + 1 == x.mix_layer2
+            assert len(done[L2 - 1]) == P, "phase before the previous layer finished"
+            phased.add(L2)
+            done[L2].add((x.group_first, x.group_bits))
+    for L in range(p):
+        assert len(done[L]) == P
+    assert passes[0].kind == 1 and passes[-1].kind in (4, 5)
+    # high groups keep >= 8 contiguous amplitudes (128 bytes) per row
+    for x in passes:
+        if x.group_first > 0:
+            assert x.col_bits >= 3 and x.col_bits + x.group_bits == 12
+
+
+def test_plan_bytes(lib):
+    N = 1 << 28
+    plan = _plan(lib, 28, 8, flags=1)
+    total = sum(x.bytes for x in plan[:-1])
+    # 1 first (24 B/amp) + 8 middle (32) + 7 boundary (40) + 1 last (24)
+    assert total == N * (24 + 8 * 32 + 7 * 40 + 24)
+    plan = _plan(lib, 28, 8, flags=0)
+    assert plan[-2].kind == 5 and plan[-2].bytes == 40 * N
+
+
+def test_plan_small_and_depth_zero(lib):
+    plan = _plan(lib, 10, 4)
+    assert [x.kind for x in plan] == [0]
+    plan = _plan(lib, 20, 0)
+    assert [x.kind for x in plan] == [6, 7, 8]
