@@ -175,7 +175,16 @@ typedef enum {
     QVA_PASS_LAST_STORE = 5, /* as QVA_PASS_LAST, also writes psi_p                  */
     QVA_PASS_INIT = 6,       /* elementwise psi_0                                    */
     QVA_PASS_EXPECT = 7,     /* elementwise <Q> partial sums                         */
-    QVA_PASS_REDUCE = 8      /* fixed-order sum of the partial sums                  */
+    QVA_PASS_REDUCE = 8,     /* fixed-order sum of the partial sums                  */
+    /* circulant mixer: in-place mixed-radix FFT over qubit groups (Sec. 3) */
+    QVA_PASS_FFT_FIRST = 9,     /* psi_0, phase of layer 1, forward FFT of the top group */
+    QVA_PASS_FFT_DIF = 10,      /* forward FFT over one group                           */
+    QVA_PASS_FFT_LOWDIAG = 11,  /* low group forward, diag(exp(-i t lambda)), inverse   */
+    QVA_PASS_FFT_DIT = 12,      /* inverse FFT over one group                           */
+    QVA_PASS_FFT_BOUNDARY = 13, /* inverse top group, 1/N, phase of k+1, forward top    */
+    QVA_PASS_FFT_LAST = 14,     /* inverse top group, 1/N, <Q> partial sums             */
+    QVA_PASS_FFT_LAST_STORE = 15, /* as QVA_PASS_FFT_LAST, also writes psi_p            */
+    QVA_PASS_LAMBDA_PREP = 16   /* lambda copied into the per-tile order of the diag    */
 } qva_pass_kind;
 
 /* One launch of a plan.  `bytes` is the algorithmic HBM traffic of the

@@ -145,6 +145,85 @@ double launch_bytes(const Launch& l, int n, bool store)
     }
 }
 
+// ---------------------------------------------------------- circulant plan
+int fft_pass_kind(int mode)
+{
+    switch (mode) {
+    case FMODE_FIRST:
+        return QVA_PASS_FFT_FIRST;
+    case FMODE_DIF:
+        return QVA_PASS_FFT_DIF;
+    case FMODE_LOWDIAG:
+        return QVA_PASS_FFT_LOWDIAG;
+    case FMODE_DIT:
+    case FMODE_DIT_SCALE:
+        return QVA_PASS_FFT_DIT;
+    case FMODE_BOUNDARY:
+        return QVA_PASS_FFT_BOUNDARY;
+    case FMODE_LAST:
+        return QVA_PASS_FFT_LAST;
+    default:
+        return QVA_PASS_FFT_LAST_STORE;
+    }
+}
+
+bool lambda_tiled(const qva_problem* P)
+{
+    return P->lambda_kind == QVA_LAMBDA_ARRAY && P->n_qubits > kTileBits;
+}
+
+std::vector<Launch> fft_launches(const qva_problem* P, int p, bool store)
+{
+    const int n = P->n_qubits;
+    std::vector<Launch> L;
+    if (n <= kTileBits) {
+        L.push_back({QVA_PASS_WHOLE, 0, 0, -1, -1, -1});
+        return L;
+    }
+    if (p == 0) {
+        L.push_back({QVA_PASS_INIT, -1, 0, -1, -1, -1});
+        L.push_back({QVA_PASS_EXPECT, -1, 0, -1, -1, -1});
+        L.push_back({QVA_PASS_REDUCE, -1, 0, -1, -1, -1});
+        return L;
+    }
+    if (lambda_tiled(P))
+        L.push_back({QVA_PASS_LAMBDA_PREP, -1, 0, -1, -1, -1});
+    const int G = (int)x_groups(n).size();
+    for (const FPass& f : fft_evolve_plan(G, p, store))
+        L.push_back({fft_pass_kind(f.mode), f.group, f.mode, f.layer, -1, f.phase_layer});
+    L.push_back({QVA_PASS_REDUCE, -1, 0, -1, -1, -1});
+    return L;
+}
+
+double fft_launch_bytes(const Launch& l, int n, bool store, bool tiled)
+{
+    const double N = std::ldexp(1.0, n);
+    const double amp = 16.0, real = 8.0;
+    switch (l.kind) {
+    case QVA_PASS_WHOLE:
+        return real * N + (tiled ? real * N : 0.0) + (store ? amp * N : 0.0);
+    case QVA_PASS_FFT_FIRST:
+        return (real + amp) * N;
+    case QVA_PASS_FFT_DIF:
+    case QVA_PASS_FFT_DIT:
+        return 2 * amp * N;
+    case QVA_PASS_FFT_LOWDIAG:
+        return 2 * amp * N + (tiled ? real * N : 0.0);
+    case QVA_PASS_FFT_BOUNDARY:
+        return (2 * amp + real) * N;
+    case QVA_PASS_FFT_LAST:
+        return (amp + real) * N;
+    case QVA_PASS_FFT_LAST_STORE:
+        return (2 * amp + real) * N;
+    case QVA_PASS_LAMBDA_PREP:
+        return 2 * real * N;
+    default: {
+        Launch x = l;
+        return launch_bytes(x, n, store);
+    }
+    }
+}
+
 // Records an event pair around every launch when the caller asked for it.
 struct EventHook {
     void* const* ev = nullptr;
@@ -207,6 +286,85 @@ int evolve_x(const qva_problem* P, const double* gammas, const double* ts, int p
             x.phase = dev_angle(gammas, l.phase_layer >= 0 ? l.phase_layer : 0);
             x.partials = partials;
             e = launch_xpass(x, s);
+            break;
+        }
+        }
+        hook.after(s);
+        if (e != hipSuccess)
+            return QVA_ERR_HIP;
+    }
+    return QVA_OK;
+}
+
+int small_lambda_kind(int kind)
+{
+    return kind == QVA_LAMBDA_RING ? FFT_LAMBDA_RING
+                                   : (kind == QVA_LAMBDA_COMPLETE ? FFT_LAMBDA_COMPLETE : FFT_LAMBDA_NATURAL);
+}
+
+// Workspace of the circulant evolution: partial sums, then (array lambda)
+// the per-tile copy of lambda.
+size_t circ_partials_bytes(int n) { return (size_t)(int64_t(1) << (n - kTileBits)) * sizeof(double2); }
+
+int evolve_circ(const qva_problem* P, const double* gammas, const double* ts, int p, double2* psi,
+                double* out_f, double* out_norm, bool store, char* work, hipStream_t s,
+                EventHook& hook)
+{
+    const int n = P->n_qubits;
+    const int64_t N = int64_t(1) << n;
+    const std::vector<XGroup> groups = x_groups(n);
+    double2* partials = reinterpret_cast<double2*>(work);
+    double* lam_tiles = n > kTileBits ? reinterpret_cast<double*>(work + circ_partials_bytes(n)) : nullptr;
+    const bool tiled = lambda_tiled(P);
+    for (const Launch& l : fft_launches(P, p, store)) {
+        hipError_t e = hipSuccess;
+        hook.before(s);
+        switch (l.kind) {
+        case QVA_PASS_WHOLE: {
+            SmallFftParams sp{};
+            sp.psi = psi;
+            sp.q = P->q;
+            sp.gammas = gammas;
+            sp.ts = ts;
+            sp.lam = P->lambda;
+            sp.lambda_kind = small_lambda_kind(P->lambda_kind);
+            sp.n = n;
+            sp.p = p;
+            sp.flags = SM_INIT | SM_EVOLVE | SM_EXPECT | (store ? SM_STORE : 0);
+            sp.out_f = out_f;
+            sp.out_norm = out_norm;
+            e = launch_small_fft(sp, s);
+            break;
+        }
+        case QVA_PASS_INIT:
+            e = launch_init_uniform(psi, N, s);
+            break;
+        case QVA_PASS_EXPECT:
+            e = launch_expect_partials(psi, P->q, N, partials, s);
+            break;
+        case QVA_PASS_REDUCE: {
+            const int64_t count = p == 0 ? expect_partial_count(N) : (int64_t(1) << (n - kTileBits));
+            e = launch_final_reduce(partials, count, out_f, out_norm, s);
+            break;
+        }
+        case QVA_PASS_LAMBDA_PREP:
+            e = launch_lambda_tiles(P->lambda, lam_tiles, n, s);
+            break;
+        default: {
+            const XGroup& g = groups[l.group];
+            FftPassParams f{};
+            f.psi = psi;
+            f.q = P->q;
+            f.lam = tiled ? lam_tiles : P->lambda;
+            f.lambda_kind = tiled ? FFT_LAMBDA_TILED : small_lambda_kind(P->lambda_kind);
+            f.mix1 = dev_angle(ts, l.layer1 >= 0 ? l.layer1 : 0);
+            f.phase = dev_angle(gammas, l.phase_layer >= 0 ? l.phase_layer : 0);
+            f.n = n;
+            f.k = g.k;
+            f.col_bits = g.col_bits;
+            f.flags = l.xmode;
+            f.partials = partials;
+            e = launch_fftpass(f, s);
             break;
         }
         }
@@ -301,13 +459,49 @@ int qva_mix_x(qva_c128* psi, int n_qubits, double t, void* stream)
 int qva_mix_circulant(qva_c128* psi, const double* lambda, int lambda_kind, int64_t N, double t,
                       void* stream)
 {
-    (void)psi;
-    (void)lambda;
-    (void)lambda_kind;
-    (void)N;
-    (void)t;
-    (void)stream;
-    return QVA_ERR_UNSUPPORTED;
+    if (!psi)
+        return QVA_ERR_ARG;
+    if (lambda_kind != QVA_LAMBDA_ARRAY && lambda_kind != QVA_LAMBDA_RING &&
+        lambda_kind != QVA_LAMBDA_COMPLETE)
+        return QVA_ERR_ARG;
+    if (lambda_kind == QVA_LAMBDA_ARRAY && !lambda)
+        return QVA_ERR_ARG;
+    int n = 0;
+    while (n <= QVA_MAX_QUBITS && (int64_t(1) << n) < N)
+        ++n;
+    if (N < 2 || n > QVA_MAX_QUBITS || (int64_t(1) << n) != N)
+        return N >= 2 && (int64_t(1) << n) != N ? QVA_ERR_UNSUPPORTED : QVA_ERR_SIZE;
+    if (!aligned(psi, 16) || (lambda_kind == QVA_LAMBDA_ARRAY && !aligned(lambda, 8)))
+        return QVA_ERR_ALIGN;
+    double2* d = reinterpret_cast<double2*>(psi);
+    hipStream_t s = as_stream(stream);
+    const int lk = small_lambda_kind(lambda_kind);
+    if (n <= kTileBits) {
+        SmallFftParams sp{};
+        sp.psi = d;
+        sp.lam = lambda;
+        sp.lambda_kind = lk;
+        sp.n = n;
+        sp.t_val = t;
+        sp.flags = SM_MIX_ONCE | SM_STORE;
+        return hip_status(launch_small_fft(sp, s));
+    }
+    const std::vector<XGroup> groups = x_groups(n);
+    for (const FPass& fp : fft_mix_plan((int)groups.size())) {
+        FftPassParams f{};
+        f.psi = d;
+        f.lam = lambda;
+        f.lambda_kind = lk;
+        f.mix1 = host_angle(t);
+        f.phase = host_angle(0.0);
+        f.n = n;
+        f.k = groups[fp.group].k;
+        f.col_bits = groups[fp.group].col_bits;
+        f.flags = fp.mode;
+        if (launch_fftpass(f, s) != hipSuccess)
+            return QVA_ERR_HIP;
+    }
+    return QVA_OK;
 }
 
 size_t qva_expectation_workspace_bytes(int64_t N)
@@ -323,10 +517,12 @@ size_t qva_workspace_bytes(const qva_problem* P, int p, int for_grad)
     if (check_problem(P, p) != QVA_OK)
         return 0;
     const int n = P->n_qubits;
-    if (P->mixer == QVA_MIX_X && n <= kTileBits)
+    if (n <= kTileBits)
         return 0;
-    const int64_t tiles = n > kTileBits ? (int64_t(1) << (n - kTileBits)) : 1;
-    return (size_t)tiles * sizeof(double2);
+    size_t bytes = circ_partials_bytes(n);
+    if (P->mixer == QVA_MIX_CIRCULANT && lambda_tiled(P))
+        bytes += (size_t)(int64_t(1) << n) * sizeof(double);
+    return bytes;
 }
 
 int qva_expectation(const qva_c128* psi, const double* q, int64_t N, double* out_f_dev,
@@ -381,12 +577,13 @@ int qva_plan(const qva_problem* P, int p, int for_grad, int flags, qva_pass_info
         return st;
     if (max_out < 0 || (max_out > 0 && !out) || (flags & ~QVA_EVOLVE_SKIP_FINAL_STATE))
         return QVA_ERR_ARG;
-    if (for_grad || P->mixer != QVA_MIX_X)
+    if (for_grad)
         return QVA_ERR_UNSUPPORTED;
     const bool store = !(flags & QVA_EVOLVE_SKIP_FINAL_STATE);
     const int n = P->n_qubits;
+    const bool circ = P->mixer == QVA_MIX_CIRCULANT;
     const std::vector<XGroup> groups = x_groups(n);
-    const std::vector<Launch> L = x_launches(n, p, store);
+    const std::vector<Launch> L = circ ? fft_launches(P, p, store) : x_launches(n, p, store);
     for (int i = 0; i < (int)L.size() && i < max_out; ++i) {
         const Launch& l = L[i];
         out[i].kind = l.kind;
@@ -396,7 +593,7 @@ int qva_plan(const qva_problem* P, int p, int for_grad, int flags, qva_pass_info
         out[i].mix_layer = l.layer1;
         out[i].mix_layer2 = l.layer2;
         out[i].phase_layer = l.phase_layer;
-        out[i].bytes = launch_bytes(l, n, store);
+        out[i].bytes = circ ? fft_launch_bytes(l, n, store, lambda_tiled(P)) : launch_bytes(l, n, store);
     }
     return (int)L.size();
 }
@@ -448,7 +645,8 @@ int evolve_common(const qva_problem* P, const double* gammas_dev, const double* 
         return evolve_x(P, gammas_dev, ts_dev, p, reinterpret_cast<double2*>(psi), out_f_dev,
                         out_norm_dev, store, reinterpret_cast<double2*>(work), as_stream(stream),
                         hook);
-    return QVA_ERR_UNSUPPORTED;
+    return evolve_circ(P, gammas_dev, ts_dev, p, reinterpret_cast<double2*>(psi), out_f_dev,
+                       out_norm_dev, store, reinterpret_cast<char*>(work), as_stream(stream), hook);
 }
 
 }  // namespace

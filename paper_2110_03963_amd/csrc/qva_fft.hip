@@ -1,0 +1,581 @@
+// qva_fft.hip -- circulant-mixer (QWOA) passes: F^-1 diag(exp(-i t lambda)) F.
+//
+// The eigensystem of a circulant W is the discrete Fourier transform (paper
+// Sec. 3), so exp(-i t W) = F^-1 diag(exp(-i t lambda_m)) F with F the
+// unnormalised DFT, F_mj = exp(-2 pi i j m / N).
+//
+// F is computed in place as a mixed-radix decimation-in-frequency transform
+// over the same 4096-amplitude tiles as the hypercube mixer.  The index bits
+// of a tile that lie in one register layout form a "digit" (up to 4 bits,
+// radix up to 16).  One DIF step over the digit at global bits [gb, gb+w) is
+//   y[j_lo + 2^gb m + ...] = W_{2^(gb+w)}^(j_lo m) sum_d x[j_lo + 2^gb d + ...] W_{2^w}^(d m)
+// with j_lo the index bits below gb: a 2^w-point DFT in registers (radix-2
+// stages with constant twiddles) followed by one exact twiddle per element
+// (sincospi of a dyadic rational).  Digits are taken from the top bit down.
+// The register DFT leaves each digit bit-reversed and the digit order is
+// reversed, so position p ends up holding X[bitrev_n(p)]: the diagonal is
+// applied with lambda at the bit-reversed index, and the inverse transform
+// (the same steps undone in reverse order, conjugate twiddles, 1/N at the
+// end) restores natural order.  No permutation pass is needed.
+#include "qva_internal.h"
+
+namespace qva {
+namespace {
+
+// Register layouts of a 4096-amplitude tile (256 threads x 16 registers).
+// A: registers = element bits [8,12); B: [4,8); C: [0,4);
+// A3: registers = element bits {3, 9, 10, 11} (for tiles with 3 column bits).
+enum { LA = 0, LB = 1, LC = 2, LA3 = 3 };
+
+template <int L>
+__device__ __forceinline__ int elem(int t, int r)
+{
+    if constexpr (L == LA)
+        return t | (r << 8);
+    else if constexpr (L == LB)
+        return (t & 15) | (r << 4) | ((t >> 4) << 8);
+    else if constexpr (L == LC)
+        return r | (t << 4);
+    else
+        return (t & 7) | ((r & 1) << 3) | ((t >> 3) << 4) | ((r >> 1) << 9);
+}
+
+// Element bit held by register bit j of layout L.
+template <int L>
+constexpr int reg_elem_bit(int j)
+{
+    if (L == LA)
+        return 8 + j;
+    if (L == LB)
+        return 4 + j;
+    if (L == LC)
+        return j;
+    return j == 0 ? 3 : 8 + j;
+}
+
+// Digit of layout L for a tile whose first C element bits are columns: the
+// register bits holding target (transform) bits, [dlo, dlo + dw).
+template <int C, int L>
+constexpr int digit_lo()
+{
+    int j = 0;
+    while (j < 4 && reg_elem_bit<L>(j) < C)
+        ++j;
+    return j;
+}
+
+template <int C, int L>
+constexpr int digit_w()
+{
+    if (L == LA3)
+        return C == 3 ? 1 : 0;
+    return 4 - digit_lo<C, L>();
+}
+
+__device__ __forceinline__ int swz(int e) { return e ^ (((e >> 3) ^ (e >> 6) ^ (e >> 9)) & 7); }
+
+template <int FROM, int TO>
+__device__ __forceinline__ void exchange(double2 (&v)[kRegs], double2* lds, int t)
+{
+    if constexpr (FROM != TO) {
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kRegs; ++r)
+            lds[swz(elem<FROM>(t, r))] = v[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kRegs; ++r)
+            v[r] = lds[swz(elem<TO>(t, r))];
+    }
+}
+
+// exp(-2 pi i k / 16), k = 0..7
+__device__ __forceinline__ double2 w16(int k)
+{
+    constexpr double c1 = 0.92387953251128675613;  // cos(pi/8)
+    constexpr double s1 = 0.38268343236508977173;  // sin(pi/8)
+    constexpr double h = 0.70710678118654752440;   // sqrt(1/2)
+    switch (k & 7) {
+    case 0:
+        return make_double2(1.0, 0.0);
+    case 1:
+        return make_double2(c1, -s1);
+    case 2:
+        return make_double2(h, -h);
+    case 3:
+        return make_double2(s1, -c1);
+    case 4:
+        return make_double2(0.0, -1.0);
+    case 5:
+        return make_double2(-s1, -c1);
+    case 6:
+        return make_double2(-h, -h);
+    default:
+        return make_double2(-c1, -s1);
+    }
+}
+
+__device__ __forceinline__ double2 cmul_conj(double2 a, double2 w)  // a * conj(w)
+{
+    return make_double2(a.x * w.x + a.y * w.y, a.y * w.x - a.x * w.y);
+}
+
+// 2^W-point DFT (DIF radix-2 stages) over register bits [LO, LO+W); output
+// bit-reversed within the digit.
+template <int LO, int W>
+__device__ __forceinline__ void local_dif(double2 (&v)[kRegs])
+{
+#pragma unroll
+    for (int bb = W - 1; bb >= 0; --bb) {
+        const int b = LO + bb;
+#pragma unroll
+        for (int r = 0; r < kRegs; ++r) {
+            if (r & (1 << b))
+                continue;
+            const int l = (r >> LO) & ((1 << bb) - 1);
+            const int k = l << (3 - bb);  // W_{2^(bb+1)}^l = W_16^(l 2^(3-bb))
+            const double2 a = v[r], c = v[r | (1 << b)];
+            v[r] = make_double2(a.x + c.x, a.y + c.y);
+            const double2 d = make_double2(a.x - c.x, a.y - c.y);
+            v[r | (1 << b)] = k == 0 ? d : (k == 4 ? make_double2(d.y, -d.x) : cmul(d, w16(k)));
+        }
+    }
+}
+
+// Inverse of local_dif up to the factor 2^W (conjugate twiddles, ascending).
+template <int LO, int W>
+__device__ __forceinline__ void local_dit(double2 (&v)[kRegs])
+{
+#pragma unroll
+    for (int bb = 0; bb < W; ++bb) {
+        const int b = LO + bb;
+#pragma unroll
+        for (int r = 0; r < kRegs; ++r) {
+            if (r & (1 << b))
+                continue;
+            const int l = (r >> LO) & ((1 << bb) - 1);
+            const int k = l << (3 - bb);
+            const double2 a = v[r];
+            double2 c = v[r | (1 << b)];
+            c = k == 0 ? c : (k == 4 ? make_double2(-c.y, c.x) : cmul_conj(c, w16(k)));
+            v[r] = make_double2(a.x + c.x, a.y + c.y);
+            v[r | (1 << b)] = make_double2(a.x - c.x, a.y - c.y);
+        }
+    }
+}
+
+struct TileMap {
+    int64_t base;
+    int k;
+    int C;
+    __device__ __forceinline__ int64_t operator()(int e) const
+    {
+        return base + (e & ((1 << C) - 1)) + ((int64_t)(e >> C) << k);
+    }
+};
+
+__device__ __forceinline__ int rev_bits(int x, int w) { return (int)(__brev((unsigned)x) >> (32 - w)); }
+
+// Twiddle W_{2^(gb+w)}^(j_lo * m) per element after (forward) or before
+// (inverse, conjugated) the digit's register DFT.
+template <int C, int L, bool INV>
+__device__ __forceinline__ void digit_twiddle(double2 (&v)[kRegs], const TileMap& g, int t)
+{
+    constexpr int LO = digit_lo<C, L>(), W = digit_w<C, L>();
+    if constexpr (W > 0) {
+        const int gb = g.k + (reg_elem_bit<L>(LO) - C);  // global bit of the digit's lowest bit
+        if (gb == 0)
+            return;  // no index bits below the digit: all twiddles are 1
+        const int64_t lomask = (int64_t(1) << gb) - 1;
+#pragma unroll
+        for (int r = 0; r < kRegs; ++r) {
+            const int m = rev_bits((r >> LO) & ((1 << W) - 1), W);
+            if (m == 0)
+                continue;
+            const int64_t jlo = g(elem<L>(t, r)) & lomask;
+            const double y = ldexp((double)(jlo * m), -(gb + W - 1));
+            double s, c;
+            sincospi(y, &s, &c);
+            v[r] = INV ? cmul(v[r], make_double2(c, s)) : cmul(v[r], make_double2(c, -s));
+        }
+    }
+}
+
+template <int C, int L>
+__device__ __forceinline__ void dif_digit(double2 (&v)[kRegs], const TileMap& g, int t)
+{
+    constexpr int LO = digit_lo<C, L>(), W = digit_w<C, L>();
+    if constexpr (W > 0) {
+        local_dif<LO, W>(v);
+        digit_twiddle<C, L, false>(v, g, t);
+    }
+}
+
+template <int C, int L>
+__device__ __forceinline__ void dit_digit(double2 (&v)[kRegs], const TileMap& g, int t)
+{
+    constexpr int LO = digit_lo<C, L>(), W = digit_w<C, L>();
+    if constexpr (W > 0) {
+        digit_twiddle<C, L, true>(v, g, t);
+        local_dit<LO, W>(v);
+    }
+}
+
+// Layout sequences of the forward transform of one tile (digits top-down).
+template <int C>
+constexpr int dif_last()
+{
+    return C == 0 ? LC : (C == 3 ? LA3 : (C < 8 ? LB : LA));
+}
+
+// Forward (DIF) over every target bit of the tile: enters in A, leaves in dif_last<C>().
+template <int C>
+__device__ __forceinline__ void dif_tile(double2 (&v)[kRegs], double2* lds, const TileMap& g, int t)
+{
+    dif_digit<C, LA>(v, g, t);
+    if constexpr (C < 8) {
+        exchange<LA, LB>(v, lds, t);
+        dif_digit<C, LB>(v, g, t);
+        if constexpr (C == 0) {
+            exchange<LB, LC>(v, lds, t);
+            dif_digit<C, LC>(v, g, t);
+        } else if constexpr (C == 3) {
+            exchange<LB, LA3>(v, lds, t);
+            dif_digit<C, LA3>(v, g, t);
+        }
+    }
+}
+
+// Inverse (DIT): enters in dif_last<C>(), leaves in A.
+template <int C>
+__device__ __forceinline__ void dit_tile(double2 (&v)[kRegs], double2* lds, const TileMap& g, int t)
+{
+    if constexpr (C < 8) {
+        if constexpr (C == 0) {
+            dit_digit<C, LC>(v, g, t);
+            exchange<LC, LB>(v, lds, t);
+        } else if constexpr (C == 3) {
+            dit_digit<C, LA3>(v, g, t);
+            exchange<LA3, LB>(v, lds, t);
+        }
+        dit_digit<C, LB>(v, g, t);
+        exchange<LB, LA>(v, lds, t);
+    }
+    dit_digit<C, LA>(v, g, t);
+}
+
+template <int L>
+__device__ __forceinline__ void load_tile(double2 (&v)[kRegs], const double2* psi, const TileMap& g, int t)
+{
+#pragma unroll
+    for (int r = 0; r < kRegs; ++r)
+        v[r] = ld_nt(psi + g(elem<L>(t, r)));
+}
+
+template <int L>
+__device__ __forceinline__ void store_tile(const double2 (&v)[kRegs], double2* psi, const TileMap& g,
+                                           int t, double scale)
+{
+#pragma unroll
+    for (int r = 0; r < kRegs; ++r)
+        st_nt(psi + g(elem<L>(t, r)), make_double2(v[r].x * scale, v[r].y * scale));
+}
+
+// psi <- scale * exp(-i gamma q) psi in layout A
+__device__ __forceinline__ void phase_a(double2 (&v)[kRegs], const double* q, const TileMap& g, int t,
+                                        double gamma, double scale)
+{
+    double qq[kRegs];
+#pragma unroll
+    for (int r = 0; r < kRegs; ++r)
+        qq[r] = ld_nt(q + g(elem<LA>(t, r)));
+#pragma unroll
+    for (int r = 0; r < kRegs; ++r) {
+        const double2 ph = expmi(gamma * qq[r]);
+        v[r] = cmul(v[r], make_double2(scale * ph.x, scale * ph.y));
+    }
+}
+
+// exp(-i t lambda_m) at bit-reversed positions, in layout C of a low-group tile.
+__device__ __forceinline__ void diag_c(double2 (&v)[kRegs], const FftPassParams& P, int64_t tile, int t,
+                                       double tt)
+{
+    const int n = P.n;
+#pragma unroll
+    for (int r = 0; r < kRegs; ++r) {
+        const int64_t pos = (tile << kTileBits) | elem<LC>(t, r);
+        double lam;
+        if (P.lambda_kind == FFT_LAMBDA_TILED) {
+            lam = ld_nt(P.lam + (tile << kTileBits) + r * kThreads + t);
+        } else {
+            const uint64_t m = __brevll((uint64_t)pos) >> (64 - n);
+            if (P.lambda_kind == FFT_LAMBDA_NATURAL) {
+                lam = P.lam[m];
+            } else if (P.lambda_kind == FFT_LAMBDA_RING) {
+                lam = 2.0 * cospi(ldexp((double)m, 1 - n));  // 2 cos(2 pi m / N)
+            } else {
+                lam = m == 0 ? (double)((int64_t(1) << n) - 1) : -1.0;
+            }
+        }
+        v[r] = cmul(v[r], expmi(tt * lam));
+    }
+}
+
+template <int FLAGS>
+__device__ __forceinline__ void expect_store_a(double2 (&v)[kRegs], const FftPassParams& P,
+                                               const TileMap& g, int t, double scale, double* red)
+{
+    if constexpr (FLAGS & FP_EXPECT) {
+        double qq[kRegs];
+#pragma unroll
+        for (int r = 0; r < kRegs; ++r)
+            qq[r] = ld_nt(P.q + g(elem<LA>(t, r)));
+        double f = 0.0, nr = 0.0;
+#pragma unroll
+        for (int r = 0; r < kRegs; ++r) {
+            const double a = v[r].x * v[r].x + v[r].y * v[r].y;
+            f = fma(a, qq[r], f);
+            nr += a;
+        }
+        const double s2 = scale * scale;
+        const double2 tot = block_sum2(f * s2, nr * s2, red);
+        if (t == 0)
+            P.partials[blockIdx.x] = tot;
+    }
+    if constexpr (FLAGS & FP_STORE)
+        store_tile<LA>(v, P.psi, g, t, scale);
+}
+
+template <int C, int FLAGS>
+__global__ __launch_bounds__(kThreads, 2) void fftpass_kernel(FftPassParams P)
+{
+    __shared__ double2 lds[1 << kTileBits];
+    __shared__ double red[2 * (kThreads / 64)];
+    const int t = threadIdx.x;
+    const int64_t tile = blockIdx.x;
+    const int lobits = P.k - C;
+    TileMap g;
+    g.k = P.k;
+    g.C = C;
+    g.base = ((tile & ((int64_t(1) << lobits) - 1)) << C) | ((tile >> lobits) << (P.k + kTileBits - C));
+    const double invN = ldexp(1.0, -P.n);
+    double2 v[kRegs];
+
+    if constexpr (FLAGS == FMODE_FIRST) {
+        const double a0 = 1.0 / sqrt((double)(int64_t(1) << P.n));
+#pragma unroll
+        for (int r = 0; r < kRegs; ++r)
+            v[r] = make_double2(a0, 0.0);
+        phase_a(v, P.q, g, t, angle_value(P.phase), 1.0);
+        dif_tile<C>(v, lds, g, t);
+        store_tile<dif_last<C>()>(v, P.psi, g, t, 1.0);
+    } else if constexpr (FLAGS == FMODE_DIF) {
+        load_tile<LA>(v, P.psi, g, t);
+        dif_tile<C>(v, lds, g, t);
+        store_tile<dif_last<C>()>(v, P.psi, g, t, 1.0);
+    } else if constexpr (FLAGS == FMODE_DIT || FLAGS == FMODE_DIT_SCALE) {
+        load_tile<dif_last<C>()>(v, P.psi, g, t);
+        dit_tile<C>(v, lds, g, t);
+        store_tile<LA>(v, P.psi, g, t, FLAGS == FMODE_DIT_SCALE ? invN : 1.0);
+    } else if constexpr (FLAGS == FMODE_LOWDIAG) {
+        load_tile<LA>(v, P.psi, g, t);
+        dif_tile<C>(v, lds, g, t);
+        diag_c(v, P, tile, t, angle_value(P.mix1));
+        dit_tile<C>(v, lds, g, t);
+        store_tile<LA>(v, P.psi, g, t, 1.0);
+    } else if constexpr (FLAGS == FMODE_BOUNDARY) {
+        load_tile<dif_last<C>()>(v, P.psi, g, t);
+        dit_tile<C>(v, lds, g, t);
+        phase_a(v, P.q, g, t, angle_value(P.phase), invN);
+        dif_tile<C>(v, lds, g, t);
+        store_tile<dif_last<C>()>(v, P.psi, g, t, 1.0);
+    } else {  // FMODE_LAST, FMODE_LAST_STORE
+        load_tile<dif_last<C>()>(v, P.psi, g, t);
+        dit_tile<C>(v, lds, g, t);
+        expect_store_a<FLAGS>(v, P, g, t, invN, red);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Whole state in one workgroup (n <= 12): radix-2 DIF / DIT in LDS.
+// ---------------------------------------------------------------------------
+__device__ void small_fft(double2* s, int n, bool inverse)
+{
+    const int N = 1 << n;
+    for (int it = 0; it < n; ++it) {
+        const int st = inverse ? it : n - 1 - it;  // DIF: top bit first; DIT: bottom first
+        const int h = 1 << st;
+        for (int m = threadIdx.x; m < N / 2; m += blockDim.x) {
+            const int j = ((m >> st) << (st + 1)) | (m & (h - 1));
+            const int u = j & (h - 1);
+            double sn, cs;
+            sincospi(ldexp((double)u, -st), &sn, &cs);  // angle pi u / h = 2 pi u / (2h)
+            const double2 w = make_double2(cs, inverse ? sn : -sn);
+            const double2 a = s[j];
+            double2 b = s[j + h];
+            if (!inverse) {
+                s[j] = make_double2(a.x + b.x, a.y + b.y);
+                s[j + h] = cmul(make_double2(a.x - b.x, a.y - b.y), w);
+            } else {
+                b = cmul(b, w);
+                s[j] = make_double2(a.x + b.x, a.y + b.y);
+                s[j + h] = make_double2(a.x - b.x, a.y - b.y);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__device__ void small_circulant(double2* s, const SmallFftParams& P, double tt)
+{
+    const int n = P.n, N = 1 << n;
+    small_fft(s, n, false);
+    for (int j = threadIdx.x; j < N; j += blockDim.x) {
+        const unsigned m = __brev((unsigned)j) >> (32 - n);
+        double lam;
+        if (P.lambda_kind == FFT_LAMBDA_NATURAL)
+            lam = P.lam[m];
+        else if (P.lambda_kind == FFT_LAMBDA_RING)
+            lam = 2.0 * cospi(ldexp((double)m, 1 - n));
+        else
+            lam = m == 0 ? (double)(N - 1) : -1.0;
+        s[j] = cmul(s[j], expmi(tt * lam));
+    }
+    __syncthreads();
+    small_fft(s, n, true);
+    const double invN = ldexp(1.0, -n);
+    for (int j = threadIdx.x; j < N; j += blockDim.x)
+        s[j] = make_double2(s[j].x * invN, s[j].y * invN);
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kThreads) void small_fft_kernel(SmallFftParams P)
+{
+    __shared__ double2 s[1 << kTileBits];
+    __shared__ double red[2 * (kThreads / 64)];
+    const int N = 1 << P.n;
+    const int t = threadIdx.x;
+    const double a0 = 1.0 / sqrt((double)N);
+    for (int j = t; j < N; j += blockDim.x)
+        s[j] = (P.flags & SM_INIT) ? make_double2(a0, 0.0) : P.psi[j];
+    __syncthreads();
+    if (P.flags & SM_MIX_ONCE)
+        small_circulant(s, P, P.t_val);
+    if (P.flags & SM_EVOLVE) {
+        for (int layer = 0; layer < P.p; ++layer) {
+            const double gam = P.gammas[layer];
+            for (int j = t; j < N; j += blockDim.x)
+                s[j] = cmul(s[j], expmi(gam * P.q[j]));
+            __syncthreads();
+            small_circulant(s, P, P.ts[layer]);
+        }
+    }
+    if (P.flags & SM_EXPECT) {
+        double f = 0.0, nr = 0.0;
+        for (int j = t; j < N; j += blockDim.x) {
+            const double a = s[j].x * s[j].x + s[j].y * s[j].y;
+            f = fma(a, P.q[j], f);
+            nr += a;
+        }
+        const double2 tot = block_sum2(f, nr, red);
+        if (t == 0) {
+            P.out_f[0] = tot.x;
+            if (P.out_norm)
+                P.out_norm[0] = tot.y;
+        }
+    }
+    if (P.flags & SM_STORE)
+        for (int j = t; j < N; j += blockDim.x)
+            P.psi[j] = s[j];
+}
+
+// lam_tiled[tile][r][t] = lambda[bitrev_n(tile * 4096 + r + 16 t)]: the
+// eigenvalue each low-group tile needs in layout C, laid out for coalesced reads.
+__global__ __launch_bounds__(256) void lambda_tile_kernel(const double* lam, double* out, int n)
+{
+    const int64_t N = int64_t(1) << n;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) {
+        const int64_t tile = i >> kTileBits;
+        const int w = (int)(i & ((1 << kTileBits) - 1));
+        const int r = w / kThreads, t = w % kThreads;
+        const int64_t pos = (tile << kTileBits) | elem<LC>(t, r);
+        const uint64_t m = __brevll((uint64_t)pos) >> (64 - n);
+        out[i] = lam[m];
+    }
+}
+
+template <int C>
+hipError_t launch_fft_c(const FftPassParams& P, unsigned grid, hipStream_t s)
+{
+    switch (P.flags) {
+#define QVA_FFT_MODE(F)                                                                 \
+    case F:                                                                             \
+        hipLaunchKernelGGL((fftpass_kernel<C, F>), dim3(grid), dim3(kThreads), 0, s, P); \
+        break;
+        QVA_FFT_MODE(FMODE_FIRST)
+        QVA_FFT_MODE(FMODE_DIF)
+        QVA_FFT_MODE(FMODE_DIT)
+        QVA_FFT_MODE(FMODE_DIT_SCALE)
+        QVA_FFT_MODE(FMODE_BOUNDARY)
+        QVA_FFT_MODE(FMODE_LAST)
+        QVA_FFT_MODE(FMODE_LAST_STORE)
+#undef QVA_FFT_MODE
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_fftpass(const FftPassParams& P, hipStream_t s)
+{
+    const unsigned grid = (unsigned)(int64_t(1) << (P.n - kTileBits));
+    if (P.col_bits == 0) {
+        if (P.flags != FMODE_LOWDIAG)
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL((fftpass_kernel<0, FMODE_LOWDIAG>), dim3(grid), dim3(kThreads), 0, s, P);
+        return hipGetLastError();
+    }
+    switch (P.col_bits) {
+    case 3:
+        return launch_fft_c<3>(P, grid, s);
+    case 4:
+        return launch_fft_c<4>(P, grid, s);
+    case 5:
+        return launch_fft_c<5>(P, grid, s);
+    case 6:
+        return launch_fft_c<6>(P, grid, s);
+    case 7:
+        return launch_fft_c<7>(P, grid, s);
+    case 8:
+        return launch_fft_c<8>(P, grid, s);
+    case 9:
+        return launch_fft_c<9>(P, grid, s);
+    case 10:
+        return launch_fft_c<10>(P, grid, s);
+    case 11:
+        return launch_fft_c<11>(P, grid, s);
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_small_fft(const SmallFftParams& P, hipStream_t s)
+{
+    hipLaunchKernelGGL(small_fft_kernel, dim3(1), dim3(kThreads), 0, s, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_lambda_tiles(const double* lam, double* out, int n, hipStream_t s)
+{
+    const int64_t N = int64_t(1) << n;
+    int64_t g = (N + 255) / 256;
+    if (g > 65536)
+        g = 65536;
+    hipLaunchKernelGGL(lambda_tile_kernel, dim3((unsigned)g), dim3(256), 0, s, lam, out, n);
+    return hipGetLastError();
+}
+
+}  // namespace qva

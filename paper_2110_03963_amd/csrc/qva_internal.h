@@ -84,4 +84,59 @@ hipError_t launch_expect_partials(const double2* psi, const double* q, int64_t N
 hipError_t launch_final_reduce(const double2* partials, int64_t count, double* out_f,
                                double* out_norm, hipStream_t s);
 
+// ---------------------------------------------------------------- circulant
+// Where the FFT passes take lambda from.
+enum : int {
+    FFT_LAMBDA_NATURAL = 0,  // lambda[m], natural order (whole-state kernel only)
+    FFT_LAMBDA_RING = 1,     // 2 cos(2 pi m / N), computed
+    FFT_LAMBDA_COMPLETE = 2, // N - 1 for m = 0, else -1, computed
+    FFT_LAMBDA_TILED = 3     // workspace copy laid out per low-group tile
+};
+
+enum : int { FP_EXPECT = 1, FP_STORE = 2 };
+
+// Pass kinds of the circulant mixer (compile-time modes of fftpass_kernel).
+enum : int {
+    FMODE_FIRST = 16,           // psi_0, phase, forward transform of the top group
+    FMODE_DIF = 32,             // forward transform of one group
+    FMODE_DIT = 48,             // inverse transform of one group
+    FMODE_DIT_SCALE = 64,       // inverse transform of the top group, times 1/N
+    FMODE_LOWDIAG = 80,         // low group: forward, diag(exp(-i t lambda)), inverse
+    FMODE_BOUNDARY = 96,        // inverse top group, 1/N, phase, forward top group
+    FMODE_LAST = 112 | FP_EXPECT,              // inverse top group, 1/N, <Q> partials
+    FMODE_LAST_STORE = 112 | FP_EXPECT | FP_STORE
+};
+
+struct FftPassParams {
+    double2* psi;
+    const double* q;
+    const double* lam;   // FFT_LAMBDA_TILED: the per-tile copy
+    Angle mix1, phase;   // mix1: the diag's t (LOWDIAG); phase: gamma
+    int n;
+    int k;
+    int col_bits;
+    int flags;
+    int lambda_kind;
+    double2* partials;
+};
+
+struct SmallFftParams {
+    double2* psi;
+    const double* q;
+    const double* gammas;
+    const double* ts;
+    const double* lam;   // natural order, FFT_LAMBDA_NATURAL
+    int lambda_kind;
+    double t_val;
+    int n;
+    int p;
+    int flags;           // SM_* flags
+    double* out_f;
+    double* out_norm;
+};
+
+hipError_t launch_fftpass(const FftPassParams& P, hipStream_t s);
+hipError_t launch_small_fft(const SmallFftParams& P, hipStream_t s);
+hipError_t launch_lambda_tiles(const double* lam, double* out, int n, hipStream_t s);
+
 }  // namespace qva

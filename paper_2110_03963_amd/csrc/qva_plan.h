@@ -78,4 +78,48 @@ inline std::vector<XPass> x_evolve_plan(int P, int p, bool store)
     return plan;
 }
 
+// ------------------------------------------------------------- circulant
+// A circulant mixer is F^-1 diag F.  Layer k: forward transform top group
+// down to the low group, the low group's pass applies the diagonal between
+// its forward and inverse halves, then the inverse transform back up.  The
+// top group's inverse of layer k, the phase of layer k+1 and the top group's
+// forward transform of layer k+1 share one pass: 2(P-1) passes per layer + 1.
+struct FPass {
+    int group;
+    int mode;         // FMODE_*
+    int layer;        // layer whose t the pass's diagonal uses, or -1
+    int phase_layer;  // layer whose gamma the pass applies, or -1
+};
+
+inline std::vector<FPass> fft_evolve_plan(int P, int p, bool store)
+{
+    std::vector<FPass> plan;
+    const int c = P - 1;
+    plan.push_back({c, FMODE_FIRST, -1, 0});
+    for (int L = 0; L < p; ++L) {
+        for (int g = P - 2; g >= 1; --g)
+            plan.push_back({g, FMODE_DIF, -1, -1});
+        plan.push_back({0, FMODE_LOWDIAG, L, -1});
+        for (int g = 1; g <= P - 2; ++g)
+            plan.push_back({g, FMODE_DIT, -1, -1});
+        if (L + 1 < p)
+            plan.push_back({c, FMODE_BOUNDARY, -1, L + 1});
+        else
+            plan.push_back({c, store ? FMODE_LAST_STORE : FMODE_LAST, -1, -1});
+    }
+    return plan;
+}
+
+// One circulant mixer application (P >= 2 groups).
+inline std::vector<FPass> fft_mix_plan(int P)
+{
+    std::vector<FPass> plan;
+    for (int g = P - 1; g >= 1; --g)
+        plan.push_back({g, FMODE_DIF, -1, -1});
+    plan.push_back({0, FMODE_LOWDIAG, 0, -1});
+    for (int g = 1; g <= P - 1; ++g)
+        plan.push_back({g, g == P - 1 ? FMODE_DIT_SCALE : FMODE_DIT, -1, -1});
+    return plan;
+}
+
 }  // namespace qva
