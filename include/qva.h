@@ -184,7 +184,17 @@ typedef enum {
     QVA_PASS_FFT_BOUNDARY = 13, /* inverse top group, 1/N, phase of k+1, forward top    */
     QVA_PASS_FFT_LAST = 14,     /* inverse top group, 1/N, <Q> partial sums             */
     QVA_PASS_FFT_LAST_STORE = 15, /* as QVA_PASS_FFT_LAST, also writes psi_p            */
-    QVA_PASS_LAMBDA_PREP = 16   /* lambda copied into the per-tile order of the diag    */
+    QVA_PASS_LAMBDA_PREP = 16,  /* lambda copied into the per-tile order of the diag    */
+    /* adjoint gradient (qva_grad): two vectors (phi, chi) walked backwards */
+    QVA_PASS_GRAD_WHOLE = 17,   /* forward + adjoint in one workgroup (n <= 12)         */
+    QVA_PASS_GRAD_TURN = 18,    /* last forward group, <Q>, chi = Q psi, first inverse  */
+    QVA_PASS_GRAD_MID = 19,     /* inverse rotations of one qubit group + <chi|X|phi>   */
+    QVA_PASS_GRAD_BOUND = 20,   /* inverse group, <chi|Q|phi>, inverse phase, group     */
+    QVA_PASS_GRAD_FINAL = 21,   /* inverse of the first forward pass, accumulate only   */
+    QVA_PASS_GRAD_DIF = 22,     /* forward FFT of one group, both vectors               */
+    QVA_PASS_GRAD_DIT = 23,     /* inverse FFT of one group, both vectors               */
+    QVA_PASS_GRAD_LOWDIAG = 24, /* low group, <chi^|lambda|phi^>/N, inverse diagonal    */
+    QVA_PASS_GRAD_REDUCE = 25   /* fixed-order sums of the gradient partials            */
 } qva_pass_kind;
 
 /* One launch of a plan.  `bytes` is the algorithmic HBM traffic of the
@@ -215,6 +225,12 @@ int qva_evolve_timed(const qva_problem *P, const double *gammas_dev, const doubl
                      qva_c128 *psi, double *out_f_dev, double *out_norm_dev, int flags,
                      void *work, size_t work_bytes, void *const *events, int n_events,
                      void *stream);
+
+/* qva_grad with per-launch events, as qva_evolve_timed. */
+int qva_grad_timed(const qva_problem *P, const double *gammas_dev, const double *ts_dev, int p,
+                   qva_c128 *psi, qva_c128 *chi, double *out_f_dev, double *dgammas_dev,
+                   double *dts_dev, void *work, size_t work_bytes, void *const *events,
+                   int n_events, void *stream);
 
 #ifdef __cplusplus
 }

@@ -54,7 +54,11 @@ class QvaPassInfo(ctypes.Structure):
 
 
 PASS_KINDS = {0: "whole", 1: "first", 2: "middle", 3: "boundary", 4: "last", 5: "last_store",
-              6: "init", 7: "expect", 8: "reduce"}
+              6: "init", 7: "expect", 8: "reduce", 9: "fft_first", 10: "fft_dif", 11: "fft_lowdiag",
+              12: "fft_dit", 13: "fft_boundary", 14: "fft_last", 15: "fft_last_store",
+              16: "lambda_prep", 17: "grad_whole", 18: "grad_turn", 19: "grad_mid",
+              20: "grad_bound", 21: "grad_final", 22: "grad_dif", 23: "grad_dit",
+              24: "grad_lowdiag", 25: "grad_reduce"}
 
 
 class QvaError(RuntimeError):
@@ -86,6 +90,8 @@ SIGNATURES = {
     "qva_plan": (_I, [_PROB, _I, _I, _I, ctypes.POINTER(QvaPassInfo), _I]),
     "qva_evolve_timed": (_I, [_PROB, _P, _P, _I, _P, _P, _P, _I, _P, _SZ,
                               ctypes.POINTER(ctypes.c_void_p), _I, _P]),
+    "qva_grad_timed": (_I, [_PROB, _P, _P, _I, _P, _P, _P, _P, _P, _P, _SZ,
+                            ctypes.POINTER(ctypes.c_void_p), _I, _P]),
 }
 
 _lib = None

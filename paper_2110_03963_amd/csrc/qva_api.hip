@@ -375,9 +375,275 @@ int evolve_circ(const qva_problem* P, const double* gammas, const double* ts, in
     return QVA_OK;
 }
 
+// ------------------------------------------------------------- gradient
+// Workspace of qva_grad (n > 12): per-tile (f, norm) partials, per-tile
+// partials of every (parameter, group) slot, the slot sums, and for an array
+// lambda the per-tile copy of lambda.
+struct GradLayout {
+    int64_t tiles = 0;
+    int G = 1;       // t-slots per layer: qubit groups (hypercube) or 1 (circulant)
+    int nslots = 0;  // p * (G + 1)
+    size_t fpart = 0, slots = 0, sums = 0, lam = 0, total = 0;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+GradLayout grad_layout(const qva_problem* P, int p)
+{
+    GradLayout g;
+    const int n = P->n_qubits;
+    if (n <= kTileBits)
+        return g;
+    g.tiles = int64_t(1) << (n - kTileBits);
+    g.G = P->mixer == QVA_MIX_X ? (int)x_groups(n).size() : 1;
+    g.nslots = p * (g.G + 1);
+    size_t off = 0;
+    g.fpart = off;
+    off = align256(off + (size_t)g.tiles * sizeof(double2));
+    g.slots = off;
+    off = align256(off + (size_t)g.nslots * (size_t)g.tiles * sizeof(double));
+    g.sums = off;
+    off = align256(off + (size_t)(g.nslots > 0 ? g.nslots : 1) * sizeof(double));
+    g.lam = off;
+    if (P->mixer == QVA_MIX_CIRCULANT && lambda_tiled(P))
+        off = align256(off + (size_t)(int64_t(1) << n) * sizeof(double));
+    g.total = off;
+    return g;
+}
+
+// One launch of the gradient plan.
+struct GLaunch {
+    int kind;               // qva_pass_kind
+    int group;              // qubit group, or -1
+    int mode;               // XMODE_* / FMODE_* (forward) or GMODE_* (backward)
+    int t1, t2, gamma;      // layers of the angles (-1: none)
+    int slot_t1, slot_g, slot_t2;  // slot indices (-1: none)
+};
+
+std::vector<GLaunch> grad_launches(const qva_problem* P, int p)
+{
+    std::vector<GLaunch> L;
+    const int n = P->n_qubits;
+    const bool circ = P->mixer == QVA_MIX_CIRCULANT;
+    if (n <= kTileBits) {
+        L.push_back({QVA_PASS_GRAD_WHOLE, -1, 0, -1, -1, -1, -1, -1, -1});
+        return L;
+    }
+    if (p == 0) {
+        L.push_back({QVA_PASS_INIT, -1, 0, -1, -1, -1, -1, -1, -1});
+        L.push_back({QVA_PASS_EXPECT, -1, 0, -1, -1, -1, -1, -1, -1});
+        L.push_back({QVA_PASS_REDUCE, -1, 0, -1, -1, -1, -1, -1, -1});
+        return L;
+    }
+    const int PG = (int)x_groups(n).size();
+    const int G = circ ? 1 : PG;
+    auto tslot = [&](int layer, int g) { return layer * G + (circ ? 0 : g); };
+    auto gslot = [&](int layer) { return p * G + layer; };
+    if (!circ) {
+        const std::vector<XPass> fw = x_evolve_plan(PG, p, false);
+        const int m = (int)fw.size();
+        for (int i = 0; i + 1 < m; ++i) {
+            const XPass& f = fw[i];
+            const int kind = f.flags == XMODE_FIRST ? QVA_PASS_FIRST
+                                                    : (f.flags == XMODE_BOUNDARY ? QVA_PASS_BOUNDARY : QVA_PASS_MIDDLE);
+            L.push_back({kind, f.group, f.flags, f.layer1, f.layer2, f.phase_layer, -1, -1, -1});
+        }
+        const XPass& last = fw[m - 1];
+        L.push_back({QVA_PASS_GRAD_TURN, last.group, GMODE_TURN, last.layer1, -1, -1,
+                     tslot(last.layer1, last.group), -1, -1});
+        for (int i = m - 2; i >= 1; --i) {
+            const XPass& f = fw[i];
+            if (f.flags == XMODE_MIDDLE)
+                L.push_back({QVA_PASS_GRAD_MID, f.group, GMODE_MID, f.layer1, -1, -1,
+                             tslot(f.layer1, f.group), -1, -1});
+            else
+                L.push_back({QVA_PASS_GRAD_BOUND, f.group, GMODE_BOUND, f.layer2, f.layer1, f.phase_layer,
+                             tslot(f.layer2, f.group), gslot(f.phase_layer), tslot(f.layer1, f.group)});
+        }
+        const XPass& first = fw[0];
+        L.push_back({QVA_PASS_GRAD_FINAL, first.group, GMODE_FINAL, 0, -1, 0, tslot(0, first.group), gslot(0), -1});
+    } else {
+        if (lambda_tiled(P))
+            L.push_back({QVA_PASS_LAMBDA_PREP, -1, 0, -1, -1, -1, -1, -1, -1});
+        const std::vector<FPass> fw = fft_evolve_plan(PG, p, false);
+        const int m = (int)fw.size();
+        for (int i = 0; i + 1 < m; ++i) {
+            const FPass& f = fw[i];
+            L.push_back({fft_pass_kind(f.mode), f.group, f.mode, f.layer, -1, f.phase_layer, -1, -1, -1});
+        }
+        const FPass& last = fw[m - 1];
+        L.push_back({QVA_PASS_GRAD_TURN, last.group, GMODE_TURN, -1, -1, -1, -1, -1, -1});
+        for (int i = m - 2; i >= 1; --i) {
+            const FPass& f = fw[i];
+            if (f.mode == FMODE_DIF)
+                L.push_back({QVA_PASS_GRAD_DIT, f.group, GMODE_DIT, -1, -1, -1, -1, -1, -1});
+            else if (f.mode == FMODE_DIT)
+                L.push_back({QVA_PASS_GRAD_DIF, f.group, GMODE_DIF, -1, -1, -1, -1, -1, -1});
+            else if (f.mode == FMODE_LOWDIAG)
+                L.push_back({QVA_PASS_GRAD_LOWDIAG, f.group, GMODE_LOWDIAG, f.layer, -1, -1,
+                             tslot(f.layer, 0), -1, -1});
+            else  // FMODE_BOUNDARY
+                L.push_back({QVA_PASS_GRAD_BOUND, f.group, GMODE_BOUND, -1, -1, f.phase_layer, -1,
+                             gslot(f.phase_layer), -1});
+        }
+        const FPass& first = fw[0];
+        L.push_back({QVA_PASS_GRAD_FINAL, first.group, GMODE_FINAL, -1, -1, 0, -1, gslot(0), -1});
+    }
+    L.push_back({QVA_PASS_REDUCE, -1, 0, -1, -1, -1, -1, -1, -1});
+    L.push_back({QVA_PASS_GRAD_REDUCE, -1, 0, -1, -1, -1, -1, -1, -1});
+    return L;
+}
+
+double grad_launch_bytes(const GLaunch& l, const qva_problem* P, int p)
+{
+    const int n = P->n_qubits;
+    const double N = std::ldexp(1.0, n);
+    const bool tiled = P->mixer == QVA_MIX_CIRCULANT && lambda_tiled(P);
+    switch (l.kind) {
+    case QVA_PASS_GRAD_WHOLE:
+        return 8.0 * N * (tiled ? 2 : 1);
+    case QVA_PASS_GRAD_TURN:
+        return 56.0 * N;
+    case QVA_PASS_GRAD_MID:
+    case QVA_PASS_GRAD_DIF:
+    case QVA_PASS_GRAD_DIT:
+        return 64.0 * N;
+    case QVA_PASS_GRAD_LOWDIAG:
+        return 64.0 * N + (tiled ? 8.0 * N : 0.0);
+    case QVA_PASS_GRAD_BOUND:
+        return 72.0 * N;
+    case QVA_PASS_GRAD_FINAL:
+        return 40.0 * N;
+    case QVA_PASS_GRAD_REDUCE: {
+        const GradLayout g = grad_layout(P, p);
+        return 8.0 * (double)g.nslots * (double)g.tiles;
+    }
+    default: {
+        Launch x{l.kind, l.group, l.mode, l.t1, l.t2, l.gamma};
+        return P->mixer == QVA_MIX_CIRCULANT ? fft_launch_bytes(x, n, false, tiled) : launch_bytes(x, n, false);
+    }
+    }
+}
+
+int grad_run(const qva_problem* P, const double* gammas, const double* ts, int p, double2* psi, double2* chi,
+             double* out_f, double* dgammas, double* dts, char* work, hipStream_t s, EventHook& hook)
+{
+    const int n = P->n_qubits;
+    const int64_t N = int64_t(1) << n;
+    const bool circ = P->mixer == QVA_MIX_CIRCULANT;
+    const std::vector<XGroup> groups = x_groups(n);
+    const GradLayout W = grad_layout(P, p);
+    double2* fpart = reinterpret_cast<double2*>(work + W.fpart);
+    double* slots = reinterpret_cast<double*>(work + W.slots);
+    double* sums = reinterpret_cast<double*>(work + W.sums);
+    double* lam_tiles = reinterpret_cast<double*>(work + W.lam);
+    const bool tiled = circ && lambda_tiled(P);
+    auto slot_ptr = [&](int idx) -> double* { return idx >= 0 ? slots + (int64_t)idx * W.tiles : nullptr; };
+    for (const GLaunch& l : grad_launches(P, p)) {
+        hipError_t e = hipSuccess;
+        hook.before(s);
+        switch (l.kind) {
+        case QVA_PASS_GRAD_WHOLE: {
+            SmallGradParams sp{};
+            sp.q = P->q;
+            sp.gammas = gammas;
+            sp.ts = ts;
+            sp.lam = P->lambda;
+            sp.lambda_kind = small_lambda_kind(P->lambda_kind);
+            sp.circulant = circ ? 1 : 0;
+            sp.n = n;
+            sp.p = p;
+            sp.out_f = out_f;
+            sp.dgammas = dgammas;
+            sp.dts = dts;
+            e = launch_small_grad(sp, s);
+            break;
+        }
+        case QVA_PASS_INIT:
+            e = launch_init_uniform(psi, N, s);
+            break;
+        case QVA_PASS_EXPECT:
+            e = launch_expect_partials(psi, P->q, N, fpart, s);
+            break;
+        case QVA_PASS_REDUCE: {
+            const int64_t count = p == 0 ? expect_partial_count(N) : W.tiles;
+            e = launch_final_reduce(fpart, count, out_f, nullptr, s);
+            break;
+        }
+        case QVA_PASS_GRAD_REDUCE:
+            e = launch_grad_reduce(slots, W.nslots, W.tiles, sums, p, W.G, dgammas, dts, s);
+            break;
+        case QVA_PASS_LAMBDA_PREP:
+            e = launch_lambda_tiles(P->lambda, lam_tiles, n, s);
+            break;
+        case QVA_PASS_FIRST:
+        case QVA_PASS_MIDDLE:
+        case QVA_PASS_BOUNDARY: {
+            XPassParams x = xpass_base(psi, P->q, n, groups[l.group]);
+            x.flags = l.mode;
+            x.mix1 = dev_angle(ts, l.t1);
+            x.mix2 = dev_angle(ts, l.t2 >= 0 ? l.t2 : 0);
+            x.phase = dev_angle(gammas, l.gamma >= 0 ? l.gamma : 0);
+            e = launch_xpass(x, s);
+            break;
+        }
+        case QVA_PASS_FFT_FIRST:
+        case QVA_PASS_FFT_DIF:
+        case QVA_PASS_FFT_LOWDIAG:
+        case QVA_PASS_FFT_DIT:
+        case QVA_PASS_FFT_BOUNDARY: {
+            const XGroup& g = groups[l.group];
+            FftPassParams f{};
+            f.psi = psi;
+            f.q = P->q;
+            f.lam = tiled ? lam_tiles : P->lambda;
+            f.lambda_kind = tiled ? FFT_LAMBDA_TILED : small_lambda_kind(P->lambda_kind);
+            f.mix1 = dev_angle(ts, l.t1 >= 0 ? l.t1 : 0);
+            f.phase = dev_angle(gammas, l.gamma >= 0 ? l.gamma : 0);
+            f.n = n;
+            f.k = g.k;
+            f.col_bits = g.col_bits;
+            f.flags = l.mode;
+            e = launch_fftpass(f, s);
+            break;
+        }
+        default: {  // backward passes
+            const XGroup& g = groups[l.group];
+            GradPassParams gp{};
+            gp.phi = psi;
+            gp.chi = chi;
+            gp.q = P->q;
+            gp.lam = tiled ? lam_tiles : P->lambda;
+            gp.lambda_kind = tiled ? FFT_LAMBDA_TILED : small_lambda_kind(P->lambda_kind);
+            gp.t1 = dev_angle(ts, l.t1 >= 0 ? l.t1 : 0);
+            gp.t2 = dev_angle(ts, l.t2 >= 0 ? l.t2 : 0);
+            gp.gamma = dev_angle(gammas, l.gamma >= 0 ? l.gamma : 0);
+            gp.n = n;
+            gp.k = g.k;
+            gp.col_bits = g.col_bits;
+            gp.flags = l.mode;
+            gp.slot_t1 = slot_ptr(l.slot_t1);
+            gp.slot_g = slot_ptr(l.slot_g);
+            gp.slot_t2 = slot_ptr(l.slot_t2);
+            gp.fpart = fpart;
+            e = launch_gradpass(gp, circ, s);
+            break;
+        }
+        }
+        hook.after(s);
+        if (e != hipSuccess)
+            return QVA_ERR_HIP;
+    }
+    return QVA_OK;
+}
+
 int evolve_common(const qva_problem* P, const double* gammas_dev, const double* ts_dev, int p,
                   qva_c128* psi, double* out_f_dev, double* out_norm_dev, int flags, void* work,
                   size_t work_bytes, void* stream, EventHook& hook);
+
+int grad_common(const qva_problem* P, const double* gammas_dev, const double* ts_dev, int p,
+                qva_c128* psi, qva_c128* chi, double* out_f_dev, double* dgammas_dev, double* dts_dev,
+                void* work, size_t work_bytes, void* stream, EventHook& hook);
 
 }  // namespace
 
@@ -513,12 +779,13 @@ size_t qva_expectation_workspace_bytes(int64_t N)
 
 size_t qva_workspace_bytes(const qva_problem* P, int p, int for_grad)
 {
-    (void)for_grad;
     if (check_problem(P, p) != QVA_OK)
         return 0;
     const int n = P->n_qubits;
     if (n <= kTileBits)
         return 0;
+    if (for_grad && p > 0)
+        return grad_layout(P, p).total;
     size_t bytes = circ_partials_bytes(n);
     if (P->mixer == QVA_MIX_CIRCULANT && lambda_tiled(P))
         bytes += (size_t)(int64_t(1) << n) * sizeof(double);
@@ -577,8 +844,22 @@ int qva_plan(const qva_problem* P, int p, int for_grad, int flags, qva_pass_info
         return st;
     if (max_out < 0 || (max_out > 0 && !out) || (flags & ~QVA_EVOLVE_SKIP_FINAL_STATE))
         return QVA_ERR_ARG;
-    if (for_grad)
-        return QVA_ERR_UNSUPPORTED;
+    if (for_grad) {
+        const std::vector<XGroup> groups = x_groups(P->n_qubits);
+        const std::vector<GLaunch> L = grad_launches(P, p);
+        for (int i = 0; i < (int)L.size() && i < max_out; ++i) {
+            const GLaunch& l = L[i];
+            out[i].kind = l.kind;
+            out[i].group_first = l.group >= 0 ? groups[l.group].k : -1;
+            out[i].group_bits = l.group >= 0 ? groups[l.group].bits : 0;
+            out[i].col_bits = l.group >= 0 ? groups[l.group].col_bits : 0;
+            out[i].mix_layer = l.t1;
+            out[i].mix_layer2 = l.t2;
+            out[i].phase_layer = l.gamma;
+            out[i].bytes = grad_launch_bytes(l, P, p);
+        }
+        return (int)L.size();
+    }
     const bool store = !(flags & QVA_EVOLVE_SKIP_FINAL_STATE);
     const int n = P->n_qubits;
     const bool circ = P->mixer == QVA_MIX_CIRCULANT;
@@ -602,19 +883,23 @@ int qva_grad(const qva_problem* P, const double* gammas_dev, const double* ts_de
              qva_c128* psi, qva_c128* chi, double* out_f_dev, double* dgammas_dev,
              double* dts_dev, void* work, size_t work_bytes, void* stream)
 {
-    (void)P;
-    (void)gammas_dev;
-    (void)ts_dev;
-    (void)p;
-    (void)psi;
-    (void)chi;
-    (void)out_f_dev;
-    (void)dgammas_dev;
-    (void)dts_dev;
-    (void)work;
-    (void)work_bytes;
-    (void)stream;
-    return QVA_ERR_UNSUPPORTED;
+    EventHook hook;
+    return grad_common(P, gammas_dev, ts_dev, p, psi, chi, out_f_dev, dgammas_dev, dts_dev, work,
+                       work_bytes, stream, hook);
+}
+
+int qva_grad_timed(const qva_problem* P, const double* gammas_dev, const double* ts_dev, int p,
+                   qva_c128* psi, qva_c128* chi, double* out_f_dev, double* dgammas_dev,
+                   double* dts_dev, void* work, size_t work_bytes, void* const* events, int n_events,
+                   void* stream)
+{
+    if (!events || n_events < 0)
+        return QVA_ERR_ARG;
+    EventHook hook;
+    hook.ev = events;
+    hook.n = n_events;
+    return grad_common(P, gammas_dev, ts_dev, p, psi, chi, out_f_dev, dgammas_dev, dts_dev, work,
+                       work_bytes, stream, hook);
 }
 
 }  // extern "C"
@@ -647,6 +932,34 @@ int evolve_common(const qva_problem* P, const double* gammas_dev, const double* 
                         hook);
     return evolve_circ(P, gammas_dev, ts_dev, p, reinterpret_cast<double2*>(psi), out_f_dev,
                        out_norm_dev, store, reinterpret_cast<char*>(work), as_stream(stream), hook);
+}
+
+}  // namespace
+
+namespace {
+
+int grad_common(const qva_problem* P, const double* gammas_dev, const double* ts_dev, int p,
+                qva_c128* psi, qva_c128* chi, double* out_f_dev, double* dgammas_dev, double* dts_dev,
+                void* work, size_t work_bytes, void* stream, EventHook& hook)
+{
+    int st = check_problem(P, p);
+    if (st != QVA_OK)
+        return st;
+    if (!psi || !chi || !out_f_dev || (p > 0 && (!gammas_dev || !ts_dev || !dgammas_dev || !dts_dev)))
+        return QVA_ERR_ARG;
+    if (psi == chi)
+        return QVA_ERR_ARG;
+    if (!aligned(psi, 16) || !aligned(chi, 16) || !aligned(out_f_dev, 8) ||
+        (gammas_dev && !aligned(gammas_dev, 8)) || (ts_dev && !aligned(ts_dev, 8)) ||
+        (dgammas_dev && !aligned(dgammas_dev, 8)) || (dts_dev && !aligned(dts_dev, 8)))
+        return QVA_ERR_ALIGN;
+    const size_t need = qva_workspace_bytes(P, p, 1);
+    if (need && (!work || work_bytes < need))
+        return QVA_ERR_WORKSPACE;
+    if (work && !aligned(work, 256))
+        return QVA_ERR_ALIGN;
+    return grad_run(P, gammas_dev, ts_dev, p, reinterpret_cast<double2*>(psi), reinterpret_cast<double2*>(chi),
+                    out_f_dev, dgammas_dev, dts_dev, reinterpret_cast<char*>(work), as_stream(stream), hook);
 }
 
 }  // namespace

@@ -17,269 +17,12 @@
 // applied with lambda at the bit-reversed index, and the inverse transform
 // (the same steps undone in reverse order, conjugate twiddles, 1/N at the
 // end) restores natural order.  No permutation pass is needed.
-#include "qva_internal.h"
+#include "qva_tile.h"
 
 namespace qva {
 namespace {
 
-// Register layouts of a 4096-amplitude tile (256 threads x 16 registers).
-// A: registers = element bits [8,12); B: [4,8); C: [0,4);
-// A3: registers = element bits {3, 9, 10, 11} (for tiles with 3 column bits).
-enum { LA = 0, LB = 1, LC = 2, LA3 = 3 };
-
-template <int L>
-__device__ __forceinline__ int elem(int t, int r)
-{
-    if constexpr (L == LA)
-        return t | (r << 8);
-    else if constexpr (L == LB)
-        return (t & 15) | (r << 4) | ((t >> 4) << 8);
-    else if constexpr (L == LC)
-        return r | (t << 4);
-    else
-        return (t & 7) | ((r & 1) << 3) | ((t >> 3) << 4) | ((r >> 1) << 9);
-}
-
-// Element bit held by register bit j of layout L.
-template <int L>
-constexpr int reg_elem_bit(int j)
-{
-    if (L == LA)
-        return 8 + j;
-    if (L == LB)
-        return 4 + j;
-    if (L == LC)
-        return j;
-    return j == 0 ? 3 : 8 + j;
-}
-
-// Digit of layout L for a tile whose first C element bits are columns: the
-// register bits holding target (transform) bits, [dlo, dlo + dw).
-template <int C, int L>
-constexpr int digit_lo()
-{
-    int j = 0;
-    while (j < 4 && reg_elem_bit<L>(j) < C)
-        ++j;
-    return j;
-}
-
-template <int C, int L>
-constexpr int digit_w()
-{
-    if (L == LA3)
-        return C == 3 ? 1 : 0;
-    return 4 - digit_lo<C, L>();
-}
-
-__device__ __forceinline__ int swz(int e) { return e ^ (((e >> 3) ^ (e >> 6) ^ (e >> 9)) & 7); }
-
-template <int FROM, int TO>
-__device__ __forceinline__ void exchange(double2 (&v)[kRegs], double2* lds, int t)
-{
-    if constexpr (FROM != TO) {
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < kRegs; ++r)
-            lds[swz(elem<FROM>(t, r))] = v[r];
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < kRegs; ++r)
-            v[r] = lds[swz(elem<TO>(t, r))];
-    }
-}
-
-// exp(-2 pi i k / 16), k = 0..7
-__device__ __forceinline__ double2 w16(int k)
-{
-    constexpr double c1 = 0.92387953251128675613;  // cos(pi/8)
-    constexpr double s1 = 0.38268343236508977173;  // sin(pi/8)
-    constexpr double h = 0.70710678118654752440;   // sqrt(1/2)
-    switch (k & 7) {
-    case 0:
-        return make_double2(1.0, 0.0);
-    case 1:
-        return make_double2(c1, -s1);
-    case 2:
-        return make_double2(h, -h);
-    case 3:
-        return make_double2(s1, -c1);
-    case 4:
-        return make_double2(0.0, -1.0);
-    case 5:
-        return make_double2(-s1, -c1);
-    case 6:
-        return make_double2(-h, -h);
-    default:
-        return make_double2(-c1, -s1);
-    }
-}
-
-__device__ __forceinline__ double2 cmul_conj(double2 a, double2 w)  // a * conj(w)
-{
-    return make_double2(a.x * w.x + a.y * w.y, a.y * w.x - a.x * w.y);
-}
-
-// 2^W-point DFT (DIF radix-2 stages) over register bits [LO, LO+W); output
-// bit-reversed within the digit.
-template <int LO, int W>
-__device__ __forceinline__ void local_dif(double2 (&v)[kRegs])
-{
-#pragma unroll
-    for (int bb = W - 1; bb >= 0; --bb) {
-        const int b = LO + bb;
-#pragma unroll
-        for (int r = 0; r < kRegs; ++r) {
-            if (r & (1 << b))
-                continue;
-            const int l = (r >> LO) & ((1 << bb) - 1);
-            const int k = l << (3 - bb);  // W_{2^(bb+1)}^l = W_16^(l 2^(3-bb))
-            const double2 a = v[r], c = v[r | (1 << b)];
-            v[r] = make_double2(a.x + c.x, a.y + c.y);
-            const double2 d = make_double2(a.x - c.x, a.y - c.y);
-            v[r | (1 << b)] = k == 0 ? d : (k == 4 ? make_double2(d.y, -d.x) : cmul(d, w16(k)));
-        }
-    }
-}
-
-// Inverse of local_dif up to the factor 2^W (conjugate twiddles, ascending).
-template <int LO, int W>
-__device__ __forceinline__ void local_dit(double2 (&v)[kRegs])
-{
-#pragma unroll
-    for (int bb = 0; bb < W; ++bb) {
-        const int b = LO + bb;
-#pragma unroll
-        for (int r = 0; r < kRegs; ++r) {
-            if (r & (1 << b))
-                continue;
-            const int l = (r >> LO) & ((1 << bb) - 1);
-            const int k = l << (3 - bb);
-            const double2 a = v[r];
-            double2 c = v[r | (1 << b)];
-            c = k == 0 ? c : (k == 4 ? make_double2(-c.y, c.x) : cmul_conj(c, w16(k)));
-            v[r] = make_double2(a.x + c.x, a.y + c.y);
-            v[r | (1 << b)] = make_double2(a.x - c.x, a.y - c.y);
-        }
-    }
-}
-
-struct TileMap {
-    int64_t base;
-    int k;
-    int C;
-    __device__ __forceinline__ int64_t operator()(int e) const
-    {
-        return base + (e & ((1 << C) - 1)) + ((int64_t)(e >> C) << k);
-    }
-};
-
-__device__ __forceinline__ int rev_bits(int x, int w) { return (int)(__brev((unsigned)x) >> (32 - w)); }
-
-// Twiddle W_{2^(gb+w)}^(j_lo * m) per element after (forward) or before
-// (inverse, conjugated) the digit's register DFT.
-template <int C, int L, bool INV>
-__device__ __forceinline__ void digit_twiddle(double2 (&v)[kRegs], const TileMap& g, int t)
-{
-    constexpr int LO = digit_lo<C, L>(), W = digit_w<C, L>();
-    if constexpr (W > 0) {
-        const int gb = g.k + (reg_elem_bit<L>(LO) - C);  // global bit of the digit's lowest bit
-        if (gb == 0)
-            return;  // no index bits below the digit: all twiddles are 1
-        const int64_t lomask = (int64_t(1) << gb) - 1;
-#pragma unroll
-        for (int r = 0; r < kRegs; ++r) {
-            const int m = rev_bits((r >> LO) & ((1 << W) - 1), W);
-            if (m == 0)
-                continue;
-            const int64_t jlo = g(elem<L>(t, r)) & lomask;
-            const double y = ldexp((double)(jlo * m), -(gb + W - 1));
-            double s, c;
-            sincospi(y, &s, &c);
-            v[r] = INV ? cmul(v[r], make_double2(c, s)) : cmul(v[r], make_double2(c, -s));
-        }
-    }
-}
-
-template <int C, int L>
-__device__ __forceinline__ void dif_digit(double2 (&v)[kRegs], const TileMap& g, int t)
-{
-    constexpr int LO = digit_lo<C, L>(), W = digit_w<C, L>();
-    if constexpr (W > 0) {
-        local_dif<LO, W>(v);
-        digit_twiddle<C, L, false>(v, g, t);
-    }
-}
-
-template <int C, int L>
-__device__ __forceinline__ void dit_digit(double2 (&v)[kRegs], const TileMap& g, int t)
-{
-    constexpr int LO = digit_lo<C, L>(), W = digit_w<C, L>();
-    if constexpr (W > 0) {
-        digit_twiddle<C, L, true>(v, g, t);
-        local_dit<LO, W>(v);
-    }
-}
-
-// Layout sequences of the forward transform of one tile (digits top-down).
-template <int C>
-constexpr int dif_last()
-{
-    return C == 0 ? LC : (C == 3 ? LA3 : (C < 8 ? LB : LA));
-}
-
-// Forward (DIF) over every target bit of the tile: enters in A, leaves in dif_last<C>().
-template <int C>
-__device__ __forceinline__ void dif_tile(double2 (&v)[kRegs], double2* lds, const TileMap& g, int t)
-{
-    dif_digit<C, LA>(v, g, t);
-    if constexpr (C < 8) {
-        exchange<LA, LB>(v, lds, t);
-        dif_digit<C, LB>(v, g, t);
-        if constexpr (C == 0) {
-            exchange<LB, LC>(v, lds, t);
-            dif_digit<C, LC>(v, g, t);
-        } else if constexpr (C == 3) {
-            exchange<LB, LA3>(v, lds, t);
-            dif_digit<C, LA3>(v, g, t);
-        }
-    }
-}
-
-// Inverse (DIT): enters in dif_last<C>(), leaves in A.
-template <int C>
-__device__ __forceinline__ void dit_tile(double2 (&v)[kRegs], double2* lds, const TileMap& g, int t)
-{
-    if constexpr (C < 8) {
-        if constexpr (C == 0) {
-            dit_digit<C, LC>(v, g, t);
-            exchange<LC, LB>(v, lds, t);
-        } else if constexpr (C == 3) {
-            dit_digit<C, LA3>(v, g, t);
-            exchange<LA3, LB>(v, lds, t);
-        }
-        dit_digit<C, LB>(v, g, t);
-        exchange<LB, LA>(v, lds, t);
-    }
-    dit_digit<C, LA>(v, g, t);
-}
-
-template <int L>
-__device__ __forceinline__ void load_tile(double2 (&v)[kRegs], const double2* psi, const TileMap& g, int t)
-{
-#pragma unroll
-    for (int r = 0; r < kRegs; ++r)
-        v[r] = ld_nt(psi + g(elem<L>(t, r)));
-}
-
-template <int L>
-__device__ __forceinline__ void store_tile(const double2 (&v)[kRegs], double2* psi, const TileMap& g,
-                                           int t, double scale)
-{
-#pragma unroll
-    for (int r = 0; r < kRegs; ++r)
-        st_nt(psi + g(elem<L>(t, r)), make_double2(v[r].x * scale, v[r].y * scale));
-}
+using namespace tile;
 
 // psi <- scale * exp(-i gamma q) psi in layout A
 __device__ __forceinline__ void phase_a(double2 (&v)[kRegs], const double* q, const TileMap& g, int t,
@@ -353,11 +96,7 @@ __global__ __launch_bounds__(kThreads, 2) void fftpass_kernel(FftPassParams P)
     __shared__ double red[2 * (kThreads / 64)];
     const int t = threadIdx.x;
     const int64_t tile = blockIdx.x;
-    const int lobits = P.k - C;
-    TileMap g;
-    g.k = P.k;
-    g.C = C;
-    g.base = ((tile & ((int64_t(1) << lobits) - 1)) << C) | ((tile >> lobits) << (P.k + kTileBits - C));
+    const TileMap g = tile_map(tile, P.k, C);
     const double invN = ldexp(1.0, -P.n);
     double2 v[kRegs];
 

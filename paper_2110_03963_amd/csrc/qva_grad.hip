@@ -1,0 +1,752 @@
+// qva_grad.hip -- adjoint gradient of f = <psi_p|Q|psi_p> over all 2p angles.
+//
+// With psi_p = U_2p ... U_1 psi_0 and U_l = exp(-i theta_l H_l),
+//   df/dtheta_l = 2 Im <chi_l| H_l |phi_l>,
+// phi_l = U_l ... U_1 psi_0 and chi_l = U_{l+1}^dag ... U_2p^dag Q psi_p.
+// Both are walked back from phi = psi_p, chi = Q psi_p by applying the
+// inverse of every forward pass in reverse order (the state is uncomputed,
+// never stored per layer).  Each pass accumulates the inner products whose
+// operands it holds:
+//   hypercube mixer: <chi|X_i|phi> = sum over pairs (j, j^2^i) of
+//     conj(chi_j) phi_{j^2^i} + conj(chi_{j^2^i}) phi_j, in the pass that
+//     rotates qubit i (the other rotations of the layer commute with X_i and
+//     leave it unchanged);
+//   circulant mixer: <chi|W|phi> = (1/N) sum_m conj(chi^_m) lambda_m phi^_m,
+//     in the low-group pass where both spectra are present;
+//   phase: <chi|Q|phi> = sum_j q_j conj(chi_j) phi_j, in the pass that
+//     undoes the phase.
+// Each (parameter, qubit group, tile) partial is written by exactly one pass
+// and reduced afterwards in a fixed order, so results are deterministic.
+#include "qva_tile.h"
+
+namespace qva {
+namespace {
+
+using namespace tile;
+
+// Deterministic block sum of K doubles (every thread gets the sums).
+// `red` holds K * (blockDim.x / 64) doubles.
+template <int K>
+__device__ __forceinline__ void block_sum_k(double (&v)[K], double* red)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+        v[i] = wave_sum(v[i]);
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+            red[K * wid + i] = v[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w)
+            s += red[K * w + i];
+        v[i] = s;
+    }
+}
+
+// Im(conj(chi_a) phi_b + conj(chi_b) phi_a)
+__device__ __forceinline__ double im_pair(double2 a, double2 b, double2 ca, double2 cb)
+{
+    double s = ca.x * b.y;
+    s = fma(-ca.y, b.x, s);
+    s = fma(cb.x, a.y, s);
+    s = fma(-cb.y, a.x, s);
+    return s;
+}
+
+// exp(-i th X) with (c, s) = (cos th, sin th) applied to the pair (a, b).
+__device__ __forceinline__ void rot_pair(double2& a, double2& b, double c, double s)
+{
+    const double2 a0 = a, b0 = b;
+    a = make_double2(fma(c, a0.x, s * b0.y), fma(c, a0.y, -s * b0.x));
+    b = make_double2(fma(c, b0.x, s * a0.y), fma(c, b0.y, -s * a0.x));
+}
+
+// Rotate both vectors on the target register bits of MASK, accumulating
+// Im <chi|X_i|phi> over those qubits first.
+template <int MASK>
+__device__ __forceinline__ void rot2_regs(double2 (&p)[kRegs], double2 (&x)[kRegs], double c, double s,
+                                          double& acc)
+{
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if (!((MASK >> j) & 1))
+            continue;
+#pragma unroll
+        for (int r = 0; r < kRegs; ++r) {
+            if (r & (1 << j))
+                continue;
+            const int r1 = r | (1 << j);
+            acc += im_pair(p[r], p[r1], x[r], x[r1]);
+            rot_pair(p[r], p[r1], c, s);
+            rot_pair(x[r], x[r1], c, s);
+        }
+    }
+}
+
+template <int FROM, int TO>
+__device__ __forceinline__ void exchange2(double2 (&p)[kRegs], double2 (&x)[kRegs], double2* lds, int t)
+{
+    exchange<FROM, TO>(p, lds, t);
+    exchange<FROM, TO>(x, lds, t);
+}
+
+// Rotations of every target qubit on both vectors; A -> last_layout<C>().
+template <int C>
+__device__ __forceinline__ void mix2_forward(double2 (&p)[kRegs], double2 (&x)[kRegs], double2* lds, int t,
+                                             double c, double s, double& acc)
+{
+    rot2_regs<target_mask<C, LA>()>(p, x, c, s, acc);
+    if constexpr (C < 4) {
+        exchange2<LA, LC>(p, x, lds, t);
+        rot2_regs<target_mask<C, LC>()>(p, x, c, s, acc);
+        exchange2<LC, LB>(p, x, lds, t);
+        rot2_regs<target_mask<C, LB>()>(p, x, c, s, acc);
+    } else if constexpr (C < 8) {
+        exchange2<LA, LB>(p, x, lds, t);
+        rot2_regs<target_mask<C, LB>()>(p, x, c, s, acc);
+    }
+}
+
+// Same, last_layout<C>() -> A.
+template <int C>
+__device__ __forceinline__ void mix2_reverse(double2 (&p)[kRegs], double2 (&x)[kRegs], double2* lds, int t,
+                                             double c, double s, double& acc)
+{
+    if constexpr (C < 4) {
+        rot2_regs<target_mask<C, LB>()>(p, x, c, s, acc);
+        exchange2<LB, LC>(p, x, lds, t);
+        rot2_regs<target_mask<C, LC>()>(p, x, c, s, acc);
+        exchange2<LC, LA>(p, x, lds, t);
+    } else if constexpr (C < 8) {
+        rot2_regs<target_mask<C, LB>()>(p, x, c, s, acc);
+        exchange2<LB, LA>(p, x, lds, t);
+    }
+    rot2_regs<target_mask<C, LA>()>(p, x, c, s, acc);
+}
+
+// (cos, sin) of the inverse rotation exp(+i t X) = exp(-i (-t) X)
+__device__ __forceinline__ void inv_cs(double t, double& c, double& s)
+{
+    double sn, cs;
+    sincos(t, &sn, &cs);
+    c = cs;
+    s = -sn;
+}
+
+// sum_j q_j Im(conj(chi_j) phi_j) over the registers of layout L, and the
+// inverse phase exp(+i gamma q) applied to both vectors.
+template <int L>
+__device__ __forceinline__ double unphase2(double2 (&p)[kRegs], double2 (&x)[kRegs], const double* q,
+                                           const TileMap& g, int t, double gamma, double scale)
+{
+    double qq[kRegs];
+#pragma unroll
+    for (int r = 0; r < kRegs; ++r)
+        qq[r] = ld_nt(q + g(elem<L>(t, r)));
+    double acc = 0.0;
+#pragma unroll
+    for (int r = 0; r < kRegs; ++r) {
+        p[r] = make_double2(p[r].x * scale, p[r].y * scale);
+        x[r] = make_double2(x[r].x * scale, x[r].y * scale);
+        acc = fma(qq[r], x[r].x * p[r].y - x[r].y * p[r].x, acc);
+        const double2 ph = expmi(-gamma * qq[r]);
+        p[r] = cmul(p[r], ph);
+        x[r] = cmul(x[r], ph);
+    }
+    return acc;
+}
+
+template <int L>
+__device__ __forceinline__ void store2(const double2 (&p)[kRegs], const double2 (&x)[kRegs],
+                                       const GradPassParams& P, const TileMap& g, int t)
+{
+    store_tile<L>(p, P.phi, g, t, 1.0);
+    store_tile<L>(x, P.chi, g, t, 1.0);
+}
+
+template <int L>
+__device__ __forceinline__ void load2(double2 (&p)[kRegs], double2 (&x)[kRegs], const GradPassParams& P,
+                                      const TileMap& g, int t)
+{
+    load_tile<L>(p, P.phi, g, t);
+    load_tile<L>(x, P.chi, g, t);
+}
+
+// Write the block sums of the accumulators to their per-tile slots.
+__device__ __forceinline__ void write_slots(const GradPassParams& P, double a1, double ag, double a2,
+                                            double* red)
+{
+    double v[3] = {a1, ag, a2};
+    block_sum_k<3>(v, red);
+    if (threadIdx.x == 0) {
+        if (P.slot_t1)
+            P.slot_t1[blockIdx.x] = v[0];
+        if (P.slot_g)
+            P.slot_g[blockIdx.x] = v[1];
+        if (P.slot_t2)
+            P.slot_t2[blockIdx.x] = v[2];
+    }
+}
+
+// ------------------------------------------------ hypercube-mixer passes
+template <int C, int MODE>
+__global__ __launch_bounds__(kThreads, 2) void gradx_kernel(GradPassParams P)
+{
+    __shared__ double2 lds[1 << kTileBits];
+    __shared__ double red[4 * (kThreads / 64)];
+    const int t = threadIdx.x;
+    const TileMap g = tile_map(blockIdx.x, P.k, C);
+    double2 p[kRegs], x[kRegs];
+    double a1 = 0.0, ag = 0.0, a2 = 0.0;
+
+    if constexpr (MODE == GMODE_TURN) {
+        // last forward group of the last layer, <Q>, chi = Q psi_p, then the
+        // inverse of the same rotations on both vectors
+        load_tile<LA>(p, P.phi, g, t);
+        const double tt = angle_value(P.t1);
+        const MixCoef m = mix_coef(tt);
+        if (m.tanform)
+            mix_forward<C, true>(p, lds, t, m.k);
+        else
+            mix_forward<C, false>(p, lds, t, m.k);
+        const double2 S = cpow_int(m.sigma, P.n);
+        constexpr int L = last_layout<C>();
+        double qq[kRegs];
+#pragma unroll
+        for (int r = 0; r < kRegs; ++r)
+            qq[r] = ld_nt(P.q + g(elem<L>(t, r)));
+        double f = 0.0, nr = 0.0;
+#pragma unroll
+        for (int r = 0; r < kRegs; ++r) {
+            p[r] = cmul(p[r], S);
+            const double a = p[r].x * p[r].x + p[r].y * p[r].y;
+            f = fma(a, qq[r], f);
+            nr += a;
+            x[r] = make_double2(qq[r] * p[r].x, qq[r] * p[r].y);
+        }
+        double fv[2] = {f, nr};
+        block_sum_k<2>(fv, red);
+        if (t == 0)
+            P.fpart[blockIdx.x] = make_double2(fv[0], fv[1]);
+        double c, s;
+        inv_cs(tt, c, s);
+        mix2_reverse<C>(p, x, lds, t, c, s, a1);
+        write_slots(P, a1, 0.0, 0.0, red);
+        store2<LA>(p, x, P, g, t);
+    } else {
+        load2<LA>(p, x, P, g, t);
+        double c, s;
+        inv_cs(angle_value(P.t1), c, s);
+        mix2_forward<C>(p, x, lds, t, c, s, a1);
+        if constexpr (MODE == GMODE_MID) {
+            write_slots(P, a1, 0.0, 0.0, red);
+            store2<last_layout<C>()>(p, x, P, g, t);
+        } else {
+            // the forward pass applied the layer's scalar factor together with
+            // the phase; the direct-form inverse rotations need none
+            ag = unphase2<last_layout<C>()>(p, x, P.q, g, t, angle_value(P.gamma), 1.0);
+            if constexpr (MODE == GMODE_BOUND) {
+                inv_cs(angle_value(P.t2), c, s);
+                mix2_reverse<C>(p, x, lds, t, c, s, a2);
+                write_slots(P, a1, ag, a2, red);
+                store2<LA>(p, x, P, g, t);
+            } else {  // GMODE_FINAL
+                write_slots(P, a1, ag, 0.0, red);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------ circulant-mixer passes
+template <int C, int L>
+__device__ __forceinline__ void digit_twiddle2(double2 (&p)[kRegs], double2 (&x)[kRegs], const TileMap& g,
+                                               int t, bool inv)
+{
+    constexpr int LO = digit_lo<C, L>(), W = digit_w<C, L>();
+    if constexpr (W > 0) {
+        const int gb = g.k + (reg_elem_bit<L>(LO) - C);
+        if (gb == 0)
+            return;
+        const int64_t lomask = (int64_t(1) << gb) - 1;
+#pragma unroll
+        for (int r = 0; r < kRegs; ++r) {
+            const int m = rev_bits((r >> LO) & ((1 << W) - 1), W);
+            if (m == 0)
+                continue;
+            const int64_t jlo = g(elem<L>(t, r)) & lomask;
+            const double y = ldexp((double)(jlo * m), -(gb + W - 1));
+            double sn, cs;
+            sincospi(y, &sn, &cs);
+            const double2 w = make_double2(cs, inv ? sn : -sn);
+            p[r] = cmul(p[r], w);
+            x[r] = cmul(x[r], w);
+        }
+    }
+}
+
+template <int C, int L>
+__device__ __forceinline__ void dif_digit2(double2 (&p)[kRegs], double2 (&x)[kRegs], const TileMap& g, int t)
+{
+    constexpr int LO = digit_lo<C, L>(), W = digit_w<C, L>();
+    if constexpr (W > 0) {
+        local_dif<LO, W>(p);
+        local_dif<LO, W>(x);
+        digit_twiddle2<C, L>(p, x, g, t, false);
+    }
+}
+
+template <int C, int L>
+__device__ __forceinline__ void dit_digit2(double2 (&p)[kRegs], double2 (&x)[kRegs], const TileMap& g, int t)
+{
+    constexpr int LO = digit_lo<C, L>(), W = digit_w<C, L>();
+    if constexpr (W > 0) {
+        digit_twiddle2<C, L>(p, x, g, t, true);
+        local_dit<LO, W>(p);
+        local_dit<LO, W>(x);
+    }
+}
+
+template <int C>
+__device__ __forceinline__ void dif_tile2(double2 (&p)[kRegs], double2 (&x)[kRegs], double2* lds,
+                                          const TileMap& g, int t)
+{
+    dif_digit2<C, LA>(p, x, g, t);
+    if constexpr (C < 8) {
+        exchange2<LA, LB>(p, x, lds, t);
+        dif_digit2<C, LB>(p, x, g, t);
+        if constexpr (C == 0) {
+            exchange2<LB, LC>(p, x, lds, t);
+            dif_digit2<C, LC>(p, x, g, t);
+        } else if constexpr (C == 3) {
+            exchange2<LB, LA3>(p, x, lds, t);
+            dif_digit2<C, LA3>(p, x, g, t);
+        }
+    }
+}
+
+template <int C>
+__device__ __forceinline__ void dit_tile2(double2 (&p)[kRegs], double2 (&x)[kRegs], double2* lds,
+                                          const TileMap& g, int t)
+{
+    if constexpr (C < 8) {
+        if constexpr (C == 0) {
+            dit_digit2<C, LC>(p, x, g, t);
+            exchange2<LC, LB>(p, x, lds, t);
+        } else if constexpr (C == 3) {
+            dit_digit2<C, LA3>(p, x, g, t);
+            exchange2<LA3, LB>(p, x, lds, t);
+        }
+        dit_digit2<C, LB>(p, x, g, t);
+        exchange2<LB, LA>(p, x, lds, t);
+    }
+    dit_digit2<C, LA>(p, x, g, t);
+}
+
+// lambda_m at bit-reversed position pos (see the forward low-group pass)
+__device__ __forceinline__ double lambda_at(const GradPassParams& P, int64_t tile, int t, int r)
+{
+    const int64_t pos = (tile << kTileBits) | elem<LC>(t, r);
+    if (P.lambda_kind == FFT_LAMBDA_TILED)
+        return ld_nt(P.lam + (tile << kTileBits) + r * kThreads + t);
+    const uint64_t m = __brevll((uint64_t)pos) >> (64 - P.n);
+    if (P.lambda_kind == FFT_LAMBDA_NATURAL)
+        return P.lam[m];
+    if (P.lambda_kind == FFT_LAMBDA_RING)
+        return 2.0 * cospi(ldexp((double)m, 1 - P.n));
+    return m == 0 ? (double)((int64_t(1) << P.n) - 1) : -1.0;
+}
+
+template <int C, int MODE>
+__global__ __launch_bounds__(kThreads, 2) void gradf_kernel(GradPassParams P)
+{
+    __shared__ double2 lds[1 << kTileBits];
+    __shared__ double red[4 * (kThreads / 64)];
+    const int t = threadIdx.x;
+    const int64_t tile = blockIdx.x;
+    const TileMap g = tile_map(tile, P.k, C);
+    const double invN = ldexp(1.0, -P.n);
+    double2 p[kRegs], x[kRegs];
+
+    if constexpr (MODE == GMODE_TURN) {
+        load_tile<dif_last<C>()>(p, P.phi, g, t);
+        dit_tile<C>(p, lds, g, t);
+        double qq[kRegs];
+#pragma unroll
+        for (int r = 0; r < kRegs; ++r)
+            qq[r] = ld_nt(P.q + g(elem<LA>(t, r)));
+        double f = 0.0, nr = 0.0;
+#pragma unroll
+        for (int r = 0; r < kRegs; ++r) {
+            p[r] = make_double2(p[r].x * invN, p[r].y * invN);
+            const double a = p[r].x * p[r].x + p[r].y * p[r].y;
+            f = fma(a, qq[r], f);
+            nr += a;
+            x[r] = make_double2(qq[r] * p[r].x, qq[r] * p[r].y);
+        }
+        double fv[2] = {f, nr};
+        block_sum_k<2>(fv, red);
+        if (t == 0)
+            P.fpart[blockIdx.x] = make_double2(fv[0], fv[1]);
+        dif_tile2<C>(p, x, lds, g, t);
+        store2<dif_last<C>()>(p, x, P, g, t);
+    } else if constexpr (MODE == GMODE_DIF) {
+        load2<LA>(p, x, P, g, t);
+        dif_tile2<C>(p, x, lds, g, t);
+        store2<dif_last<C>()>(p, x, P, g, t);
+    } else if constexpr (MODE == GMODE_DIT) {
+        load2<dif_last<C>()>(p, x, P, g, t);
+        dit_tile2<C>(p, x, lds, g, t);
+        store2<LA>(p, x, P, g, t);
+    } else if constexpr (MODE == GMODE_LOWDIAG) {
+        load2<LA>(p, x, P, g, t);
+        dif_tile2<C>(p, x, lds, g, t);
+        const double tt = angle_value(P.t1);
+        double a1 = 0.0;
+#pragma unroll
+        for (int r = 0; r < kRegs; ++r) {
+            const double lam = lambda_at(P, tile, t, r);
+            a1 = fma(lam, x[r].x * p[r].y - x[r].y * p[r].x, a1);
+            const double2 d = expmi(-tt * lam);  // exp(+i t lambda): the inverse diagonal
+            p[r] = cmul(p[r], d);
+            x[r] = cmul(x[r], d);
+        }
+        write_slots(P, a1 * invN, 0.0, 0.0, red);
+        dit_tile2<C>(p, x, lds, g, t);
+        store2<LA>(p, x, P, g, t);
+    } else {  // GMODE_BOUND, GMODE_FINAL
+        load2<dif_last<C>()>(p, x, P, g, t);
+        dit_tile2<C>(p, x, lds, g, t);
+        const double ag = unphase2<LA>(p, x, P.q, g, t, angle_value(P.gamma), invN);
+        if constexpr (MODE == GMODE_BOUND) {
+            write_slots(P, 0.0, ag, 0.0, red);
+            dif_tile2<C>(p, x, lds, g, t);
+            store2<dif_last<C>()>(p, x, P, g, t);
+        } else {
+            write_slots(P, 0.0, ag, 0.0, red);
+        }
+    }
+}
+
+// ------------------------------------------------ whole state in one workgroup
+// phi and chi both in LDS (n <= 12).  Same walk, plain radix-2 loops.
+__device__ double small_unrotate_x(double2* ph, double2* ch, int n, double tt)
+{
+    double c, s;
+    inv_cs(tt, c, s);
+    const int N = 1 << n;
+    double acc = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const int bit = 1 << i;
+        for (int m = threadIdx.x; m < N / 2; m += blockDim.x) {
+            const int j = ((m >> i) << (i + 1)) | (m & (bit - 1));
+            double2 a = ph[j], b = ph[j | bit], ca = ch[j], cb = ch[j | bit];
+            acc += im_pair(a, b, ca, cb);
+            rot_pair(a, b, c, s);
+            rot_pair(ca, cb, c, s);
+            ph[j] = a;
+            ph[j | bit] = b;
+            ch[j] = ca;
+            ch[j | bit] = cb;
+        }
+        __syncthreads();
+    }
+    return acc;
+}
+
+__device__ void small_rotate_x(double2* s, int n, double tt)
+{
+    double sn, c;
+    sincos(tt, &sn, &c);
+    const int N = 1 << n;
+    for (int i = 0; i < n; ++i) {
+        const int bit = 1 << i;
+        for (int m = threadIdx.x; m < N / 2; m += blockDim.x) {
+            const int j = ((m >> i) << (i + 1)) | (m & (bit - 1));
+            rot_pair(s[j], s[j | bit], c, sn);
+        }
+        __syncthreads();
+    }
+}
+
+__device__ void small_dft(double2* s, int n, bool inverse)
+{
+    const int N = 1 << n;
+    for (int it = 0; it < n; ++it) {
+        const int st = inverse ? it : n - 1 - it;
+        const int h = 1 << st;
+        for (int m = threadIdx.x; m < N / 2; m += blockDim.x) {
+            const int j = ((m >> st) << (st + 1)) | (m & (h - 1));
+            double sn, cs;
+            sincospi(ldexp((double)(j & (h - 1)), -st), &sn, &cs);
+            const double2 w = make_double2(cs, inverse ? sn : -sn);
+            const double2 a = s[j];
+            double2 b = s[j + h];
+            if (!inverse) {
+                s[j] = make_double2(a.x + b.x, a.y + b.y);
+                s[j + h] = cmul(make_double2(a.x - b.x, a.y - b.y), w);
+            } else {
+                b = cmul(b, w);
+                s[j] = make_double2(a.x + b.x, a.y + b.y);
+                s[j + h] = make_double2(a.x - b.x, a.y - b.y);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__device__ double small_lambda(const SmallGradParams& P, int j)
+{
+    const int n = P.n;
+    const unsigned m = __brev((unsigned)j) >> (32 - n);
+    if (P.lambda_kind == FFT_LAMBDA_NATURAL)
+        return P.lam[m];
+    if (P.lambda_kind == FFT_LAMBDA_RING)
+        return 2.0 * cospi(ldexp((double)m, 1 - n));
+    return m == 0 ? (double)((1 << n) - 1) : -1.0;
+}
+
+// exp(-i tt W) on s (circulant); with chi given, also returns
+// Im sum conj(chi^) lambda phi^ / N before the diagonal (s = phi).
+__device__ double small_circ(double2* s, double2* c2, const SmallGradParams& P, double tt)
+{
+    const int n = P.n, N = 1 << n;
+    small_dft(s, n, false);
+    if (c2)
+        small_dft(c2, n, false);
+    double acc = 0.0;
+    for (int j = threadIdx.x; j < N; j += blockDim.x) {
+        const double lam = small_lambda(P, j);
+        const double2 d = expmi(tt * lam);
+        if (c2) {
+            acc = fma(lam, c2[j].x * s[j].y - c2[j].y * s[j].x, acc);
+            c2[j] = cmul(c2[j], d);
+        }
+        s[j] = cmul(s[j], d);
+    }
+    __syncthreads();
+    small_dft(s, n, true);
+    if (c2)
+        small_dft(c2, n, true);
+    const double invN = ldexp(1.0, -n);
+    for (int j = threadIdx.x; j < N; j += blockDim.x) {
+        s[j] = make_double2(s[j].x * invN, s[j].y * invN);
+        if (c2)
+            c2[j] = make_double2(c2[j].x * invN, c2[j].y * invN);
+    }
+    __syncthreads();
+    return acc * invN;
+}
+
+__global__ __launch_bounds__(kThreads) void small_grad_kernel(SmallGradParams P)
+{
+    __shared__ double2 ph[1 << kTileBits];
+    __shared__ double2 ch[1 << kTileBits];
+    __shared__ double red[2 * (kThreads / 64)];
+    const int n = P.n, N = 1 << n;
+    const int t = threadIdx.x;
+    const bool circ = P.circulant;
+    const double a0 = 1.0 / sqrt((double)N);
+    for (int j = t; j < N; j += blockDim.x)
+        ph[j] = make_double2(a0, 0.0);
+    __syncthreads();
+    for (int L = 0; L < P.p; ++L) {
+        const double gam = P.gammas[L];
+        for (int j = t; j < N; j += blockDim.x)
+            ph[j] = cmul(ph[j], expmi(gam * P.q[j]));
+        __syncthreads();
+        if (circ)
+            small_circ(ph, nullptr, P, P.ts[L]);
+        else
+            small_rotate_x(ph, n, P.ts[L]);
+    }
+    double f = 0.0, nr = 0.0;
+    for (int j = t; j < N; j += blockDim.x) {
+        const double a = ph[j].x * ph[j].x + ph[j].y * ph[j].y;
+        f = fma(a, P.q[j], f);
+        nr += a;
+        ch[j] = make_double2(P.q[j] * ph[j].x, P.q[j] * ph[j].y);
+    }
+    const double2 tot = block_sum2(f, nr, red);
+    if (t == 0)
+        P.out_f[0] = tot.x;
+    __syncthreads();
+    for (int L = P.p - 1; L >= 0; --L) {
+        const double tt = P.ts[L];
+        const double at = circ ? small_circ(ph, ch, P, -tt) : small_unrotate_x(ph, ch, n, tt);
+        double ag = 0.0;
+        const double gam = P.gammas[L];
+        for (int j = t; j < N; j += blockDim.x) {
+            const double qj = P.q[j];
+            ag = fma(qj, ch[j].x * ph[j].y - ch[j].y * ph[j].x, ag);
+            const double2 u = expmi(-gam * qj);
+            ph[j] = cmul(ph[j], u);
+            ch[j] = cmul(ch[j], u);
+        }
+        const double2 sums = block_sum2(at, ag, red);
+        if (t == 0) {
+            P.dts[L] = 2.0 * sums.x;
+            P.dgammas[L] = 2.0 * sums.y;
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------ fixed-order reductions
+// block s: out[s] = sum over tiles of slots[s * tiles + i]
+__global__ __launch_bounds__(256) void slot_reduce_kernel(const double* slots, int64_t tiles, double* out)
+{
+    __shared__ double red[2 * (256 / 64)];
+    const double* base = slots + (int64_t)blockIdx.x * tiles;
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < tiles; i += blockDim.x)
+        s += base[i];
+    const double2 tot = block_sum2(s, 0.0, red);
+    if (threadIdx.x == 0)
+        out[blockIdx.x] = tot.x;
+}
+
+// dts[L] = 2 sum_g sums[L * G + g] (g ascending); dgammas[L] = 2 sums[p G + L]
+__global__ void grad_finalize_kernel(const double* sums, int p, int G, double* dgammas, double* dts)
+{
+    for (int L = threadIdx.x; L < p; L += blockDim.x) {
+        double s = 0.0;
+        for (int g = 0; g < G; ++g)
+            s += sums[L * G + g];
+        dts[L] = 2.0 * s;
+        dgammas[L] = 2.0 * sums[p * G + L];
+    }
+}
+
+template <int C>
+hipError_t launch_gradx_c(const GradPassParams& P, unsigned grid, hipStream_t s)
+{
+    switch (P.flags) {
+    case GMODE_TURN:
+        hipLaunchKernelGGL((gradx_kernel<C, GMODE_TURN>), dim3(grid), dim3(kThreads), 0, s, P);
+        break;
+    case GMODE_MID:
+        hipLaunchKernelGGL((gradx_kernel<C, GMODE_MID>), dim3(grid), dim3(kThreads), 0, s, P);
+        break;
+    case GMODE_BOUND:
+        hipLaunchKernelGGL((gradx_kernel<C, GMODE_BOUND>), dim3(grid), dim3(kThreads), 0, s, P);
+        break;
+    case GMODE_FINAL:
+        hipLaunchKernelGGL((gradx_kernel<C, GMODE_FINAL>), dim3(grid), dim3(kThreads), 0, s, P);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int C>
+hipError_t launch_gradf_c(const GradPassParams& P, unsigned grid, hipStream_t s)
+{
+    switch (P.flags) {
+    case GMODE_TURN:
+        hipLaunchKernelGGL((gradf_kernel<C, GMODE_TURN>), dim3(grid), dim3(kThreads), 0, s, P);
+        break;
+    case GMODE_DIF:
+        hipLaunchKernelGGL((gradf_kernel<C, GMODE_DIF>), dim3(grid), dim3(kThreads), 0, s, P);
+        break;
+    case GMODE_DIT:
+        hipLaunchKernelGGL((gradf_kernel<C, GMODE_DIT>), dim3(grid), dim3(kThreads), 0, s, P);
+        break;
+    case GMODE_BOUND:
+        hipLaunchKernelGGL((gradf_kernel<C, GMODE_BOUND>), dim3(grid), dim3(kThreads), 0, s, P);
+        break;
+    case GMODE_FINAL:
+        hipLaunchKernelGGL((gradf_kernel<C, GMODE_FINAL>), dim3(grid), dim3(kThreads), 0, s, P);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_gradpass(const GradPassParams& P, bool circulant, hipStream_t s)
+{
+    const unsigned grid = (unsigned)(int64_t(1) << (P.n - kTileBits));
+    if (circulant) {
+        if (P.col_bits == 0) {
+            if (P.flags != GMODE_LOWDIAG)
+                return hipErrorInvalidValue;
+            hipLaunchKernelGGL((gradf_kernel<0, GMODE_LOWDIAG>), dim3(grid), dim3(kThreads), 0, s, P);
+            return hipGetLastError();
+        }
+        switch (P.col_bits) {
+        case 3:
+            return launch_gradf_c<3>(P, grid, s);
+        case 4:
+            return launch_gradf_c<4>(P, grid, s);
+        case 5:
+            return launch_gradf_c<5>(P, grid, s);
+        case 6:
+            return launch_gradf_c<6>(P, grid, s);
+        case 7:
+            return launch_gradf_c<7>(P, grid, s);
+        case 8:
+            return launch_gradf_c<8>(P, grid, s);
+        case 9:
+            return launch_gradf_c<9>(P, grid, s);
+        case 10:
+            return launch_gradf_c<10>(P, grid, s);
+        case 11:
+            return launch_gradf_c<11>(P, grid, s);
+        default:
+            return hipErrorInvalidValue;
+        }
+    }
+    switch (P.col_bits) {
+    case 0:
+        return launch_gradx_c<0>(P, grid, s);
+    case 3:
+        return launch_gradx_c<3>(P, grid, s);
+    case 4:
+        return launch_gradx_c<4>(P, grid, s);
+    case 5:
+        return launch_gradx_c<5>(P, grid, s);
+    case 6:
+        return launch_gradx_c<6>(P, grid, s);
+    case 7:
+        return launch_gradx_c<7>(P, grid, s);
+    case 8:
+        return launch_gradx_c<8>(P, grid, s);
+    case 9:
+        return launch_gradx_c<9>(P, grid, s);
+    case 10:
+        return launch_gradx_c<10>(P, grid, s);
+    case 11:
+        return launch_gradx_c<11>(P, grid, s);
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_small_grad(const SmallGradParams& P, hipStream_t s)
+{
+    hipLaunchKernelGGL(small_grad_kernel, dim3(1), dim3(kThreads), 0, s, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_reduce(const double* slots, int nslots, int64_t tiles, double* sums, int p, int G,
+                              double* dgammas, double* dts, hipStream_t s)
+{
+    if (nslots > 0) {
+        hipLaunchKernelGGL(slot_reduce_kernel, dim3(nslots), dim3(256), 0, s, slots, tiles, sums);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    hipLaunchKernelGGL(grad_finalize_kernel, dim3(1), dim3(64), 0, s, sums, p, G, dgammas, dts);
+    return hipGetLastError();
+}
+
+}  // namespace qva

@@ -139,4 +139,52 @@ hipError_t launch_fftpass(const FftPassParams& P, hipStream_t s);
 hipError_t launch_small_fft(const SmallFftParams& P, hipStream_t s);
 hipError_t launch_lambda_tiles(const double* lam, double* out, int n, hipStream_t s);
 
+// ---------------------------------------------------------------- gradient
+// Pass modes of the adjoint walk (see qva_grad.hip).
+enum : int {
+    GMODE_TURN = 1,    // last forward group, <Q>, chi = Q psi_p, first inverse group
+    GMODE_MID = 2,     // inverse rotations of one group (hypercube)
+    GMODE_BOUND = 3,   // inverse group, <chi|Q|phi>, inverse phase, inverse group
+    GMODE_FINAL = 4,   // inverse of the first forward pass (accumulate only)
+    GMODE_DIF = 5,     // forward transform of one group, both vectors (circulant)
+    GMODE_DIT = 6,     // inverse transform of one group, both vectors
+    GMODE_LOWDIAG = 7  // low group: forward, <chi^|lambda|phi^>, inverse diagonal, inverse
+};
+
+struct GradPassParams {
+    double2* phi;
+    double2* chi;
+    const double* q;
+    const double* lam;
+    Angle t1, t2, gamma;
+    int n;
+    int k;
+    int col_bits;
+    int flags;        // GMODE_*
+    int lambda_kind;  // FFT_LAMBDA_*
+    double* slot_t1;  // per-tile partials, or null
+    double* slot_g;
+    double* slot_t2;
+    double2* fpart;   // per-tile (f, norm) partials (GMODE_TURN)
+};
+
+struct SmallGradParams {
+    const double* q;
+    const double* gammas;
+    const double* ts;
+    const double* lam;
+    int lambda_kind;
+    int circulant;
+    int n;
+    int p;
+    double* out_f;
+    double* dgammas;
+    double* dts;
+};
+
+hipError_t launch_gradpass(const GradPassParams& P, bool circulant, hipStream_t s);
+hipError_t launch_small_grad(const SmallGradParams& P, hipStream_t s);
+hipError_t launch_grad_reduce(const double* slots, int nslots, int64_t tiles, double* sums, int p, int G,
+                              double* dgammas, double* dts, hipStream_t s);
+
 }  // namespace qva

@@ -13,133 +13,12 @@
 // Elementwise work is fused into the passes: the initial state, the phase
 // exp(-i gamma q_j) (eq. phase_shift_qaoa), and the expectation sum
 // |psi_j|^2 q_j (eq. objective_generic).
-#include "qva_internal.h"
+#include "qva_tile.h"
 
 namespace qva {
 namespace {
 
-// Register layouts of a 4096-amplitude tile over 256 threads x 16 registers.
-// Element index e (12 bits); the 4 register bits of a layout sit at element
-// bits [8,12) (A), [4,8) (B) or [0,4) (C); the thread index fills the rest
-// in ascending order.
-enum { LA = 0, LB = 1, LC = 2 };
-
-template <int L>
-__device__ __forceinline__ int elem(int t, int r)
-{
-    if constexpr (L == LA)
-        return t | (r << 8);
-    else if constexpr (L == LB)
-        return (t & 15) | (r << 4) | ((t >> 4) << 8);
-    else
-        return r | (t << 4);
-}
-
-template <int L>
-constexpr int reg_base()
-{
-    return L == LA ? 8 : (L == LB ? 4 : 0);
-}
-
-// Register bits of layout L that are target qubits when the tile's first C
-// element bits are plain columns.
-template <int C, int L>
-constexpr int target_mask()
-{
-    int m = 0;
-    for (int j = 0; j < 4; ++j)
-        if (reg_base<L>() + j >= C)
-            m |= 1 << j;
-    return m;
-}
-
-// LDS slot of element e: the low three bits are XOR-folded with the higher
-// bit triples, so that any 8 lanes stepping through 3 consecutive element
-// bits hit 8 distinct 16-byte bank groups.
-__device__ __forceinline__ int swz(int e) { return e ^ (((e >> 3) ^ (e >> 6) ^ (e >> 9)) & 7); }
-
-template <int FROM, int TO>
-__device__ __forceinline__ void exchange(double2 (&v)[kRegs], double2* lds, int t)
-{
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < kRegs; ++r)
-        lds[swz(elem<FROM>(t, r))] = v[r];
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < kRegs; ++r)
-        v[r] = lds[swz(elem<TO>(t, r))];
-}
-
-template <int MASK, bool TAN>
-__device__ __forceinline__ void rotate_regs(double2 (&v)[kRegs], double k)
-{
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        if (!((MASK >> j) & 1))
-            continue;
-#pragma unroll
-        for (int r = 0; r < kRegs; ++r) {
-            if (r & (1 << j))
-                continue;
-            if constexpr (TAN)
-                bfly_tan(v[r], v[r | (1 << j)], k);
-            else
-                bfly_cot(v[r], v[r | (1 << j)], k);
-        }
-    }
-}
-
-// Layout in which the first mixer application ends: B when the tile has
-// target bits in [4,8), else A.
-template <int C>
-constexpr int last_layout()
-{
-    return C < 8 ? LB : LA;
-}
-
-// Rotations of every target qubit of the tile; enters in A, leaves in
-// last_layout<C>().  Order A, C, B.
-template <int C, bool TAN>
-__device__ __forceinline__ void mix_forward(double2 (&v)[kRegs], double2* lds, int t, double k)
-{
-    rotate_regs<target_mask<C, LA>(), TAN>(v, k);
-    if constexpr (C < 4) {
-        exchange<LA, LC>(v, lds, t);
-        rotate_regs<target_mask<C, LC>(), TAN>(v, k);
-        exchange<LC, LB>(v, lds, t);
-        rotate_regs<target_mask<C, LB>(), TAN>(v, k);
-    } else if constexpr (C < 8) {
-        exchange<LA, LB>(v, lds, t);
-        rotate_regs<target_mask<C, LB>(), TAN>(v, k);
-    }
-}
-
-// Same rotations in reverse layout order; enters in last_layout<C>(), leaves in A.
-template <int C, bool TAN>
-__device__ __forceinline__ void mix_reverse(double2 (&v)[kRegs], double2* lds, int t, double k)
-{
-    if constexpr (C < 4) {
-        rotate_regs<target_mask<C, LB>(), TAN>(v, k);
-        exchange<LB, LC>(v, lds, t);
-        rotate_regs<target_mask<C, LC>(), TAN>(v, k);
-        exchange<LC, LA>(v, lds, t);
-    } else if constexpr (C < 8) {
-        rotate_regs<target_mask<C, LB>(), TAN>(v, k);
-        exchange<LB, LA>(v, lds, t);
-    }
-    rotate_regs<target_mask<C, LA>(), TAN>(v, k);
-}
-
-struct TileMap {
-    int64_t base;
-    int k;
-    int C;
-    __device__ __forceinline__ int64_t operator()(int e) const
-    {
-        return base + (e & ((1 << C) - 1)) + ((int64_t)(e >> C) << k);
-    }
-};
+using namespace tile;
 
 // psi <- scale * exp(-i gamma q) psi in layout L
 template <int L>
@@ -191,12 +70,7 @@ __global__ __launch_bounds__(kThreads, 2) void xpass_kernel(XPassParams P)
     __shared__ double red[2 * (kThreads / 64)];
     const int t = threadIdx.x;
     const int64_t tile = blockIdx.x;
-    const int lobits = P.k - C;
-    TileMap g;
-    g.k = P.k;
-    g.C = C;
-    g.base = ((tile & ((int64_t(1) << lobits) - 1)) << C) |
-             ((tile >> lobits) << (P.k + kTileBits - C));
+    const TileMap g = tile_map(tile, P.k, C);
 
     double2 v[kRegs];
     constexpr int flags = FLAGS;

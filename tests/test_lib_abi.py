@@ -160,3 +160,59 @@ def test_plan_small_and_depth_zero(lib):
     assert [x.kind for x in plan] == [0]
     plan = _plan(lib, 20, 0)
     assert [x.kind for x in plan] == [6, 7, 8]
+
+
+def _grad_plan(lib, mixer, n, p, kind=1):
+    pr = _prob(mixer=mixer, n=n, lam=FAKE if kind == 0 else None, kind=kind)
+    cnt = lib.qva_plan(ctypes.byref(pr), p, 1, 0, None, 0)
+    assert cnt > 0
+    arr = (_lib.QvaPassInfo * cnt)()
+    assert lib.qva_plan(ctypes.byref(pr), p, 1, 0, arr, cnt) == cnt
+    return list(arr)
+
+
+@pytest.mark.parametrize("n", [13, 21, 22, 28, 30])
+@pytest.mark.parametrize("p", [1, 2, 5, 12])
+def test_grad_plan_hypercube(lib, n, p):
+    """Every (layer, qubit group) rotation of the forward is undone by exactly
+    one backward pass, and every phase by exactly one."""
+    plan = _grad_plan(lib, 0, n, p)
+    kinds = [x.kind for x in plan]
+    assert kinds[-2:] == [8, 25]
+    assert kinds.count(18) == 1 and kinds.count(21) == 1
+    back = plan[kinds.index(18):-2]
+    fwd = plan[:kinds.index(18)]
+    assert all(x.kind in (1, 2, 3) for x in fwd)
+    undone = []
+    phases = []
+    for x in back:
+        g = (x.group_first, x.group_bits)
+        if x.kind in (18, 19):
+            undone.append((x.mix_layer, g))
+        elif x.kind == 20:
+            undone += [(x.mix_layer, g), (x.mix_layer2, g)]
+            phases.append(x.phase_layer)
+            assert x.mix_layer == x.phase_layer == x.mix_layer2 + 1
+        elif x.kind == 21:
+            undone.append((0, g))
+            phases.append(0)
+    groups = {(x.group_first, x.group_bits) for x in plan if x.group_first >= 0}
+    assert sorted(undone) == sorted((L, g) for L in range(p) for g in groups)
+    assert sorted(phases) == list(range(p))
+    # backward layers are visited from the last layer down
+    layers = [x.mix_layer for x in back]
+    assert layers == sorted(layers, reverse=True)
+
+
+@pytest.mark.parametrize("n", [13, 22, 26])
+@pytest.mark.parametrize("p", [1, 3, 6])
+def test_grad_plan_circulant(lib, n, p):
+    plan = _grad_plan(lib, 1, n, p, kind=1)
+    kinds = [x.kind for x in plan]
+    back = plan[kinds.index(18):-2]
+    assert sorted(x.mix_layer for x in back if x.kind == 24) == list(range(p))
+    assert sorted(x.phase_layer for x in back if x.kind in (20, 21)) == list(range(p))
+    # forward DIF passes are undone by DIT passes and vice versa
+    fwd = plan[:kinds.index(18)]
+    assert sum(x.kind == 10 for x in fwd) == sum(x.kind == 23 for x in back)
+    assert sum(x.kind == 12 for x in fwd) == sum(x.kind == 22 for x in back)

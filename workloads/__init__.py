@@ -22,6 +22,7 @@ from .graphs import (
 )
 from .problems import (
     maxcut_qualities,
+    ring_cut_qualities_device,
     portfolio_qualities,
     draw_angles,
     random_symmetric_lambda,
@@ -38,6 +39,7 @@ __all__ = [
     "erdos_renyi_edges",
     "random_regular_edges",
     "maxcut_qualities",
+    "ring_cut_qualities_device",
     "portfolio_qualities",
     "draw_angles",
     "random_symmetric_lambda",

@@ -95,6 +95,21 @@ def maxcut_qualities(n: int, edges, weights=None, *, uncut: bool = False,
     return q.astype(dtype, copy=False)
 
 
+def ring_cut_qualities_device(n: int, device):
+    """Unweighted ring MaxCut cut sizes, built with torch on `device` (for
+    full-size inputs that are too slow to build on the host):
+    q_j = sum_v [bit v of j != bit (v+1 mod n) of j]."""
+    import torch
+
+    j = torch.arange(1 << n, dtype=torch.int64, device=device)
+    q = torch.zeros(1 << n, dtype=torch.float64, device=device)
+    for v in range(n):
+        w = (v + 1) % n
+        q += (((j >> v) ^ (j >> w)) & 1).to(torch.float64)
+    del j
+    return q
+
+
 def portfolio_qualities(mu: np.ndarray, sigma: np.ndarray, risk: float) -> np.ndarray:
     """q_j = mu . x - risk * x^T Sigma x with x_i = bit i of j (all 2^m subsets).
 
