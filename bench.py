@@ -6,8 +6,10 @@ p = 8 layers): psi_0, p x (phase + hypercube mixer), <Q>.  Inputs are seeded
 synthetic data resident in HBM before the timed region.
 
 Prints one JSON line: layer-applications/s, the roofline of the dominant
-kernel (per-launch HIP events over the timed steps), and the CPU oracle timed
-on a bounded sample (rank 0, N = 1 only).
+kernel (per-launch HIP events over the timed steps), the CPU oracle timed on
+a bounded sample (rank 0, N = 1 only), and secondary measurements of the
+other workloads (QWOA circulant mixer, adjoint gradient vs finite
+differences) under "extras".
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
                        [--no-extras]
@@ -19,7 +21,6 @@ import argparse
 import ctypes
 import hashlib
 import json
-import math
 import os
 import platform
 import sys
@@ -33,8 +34,9 @@ HBM_PEAK_GBS = 8000.0
 PROFILES = os.path.join(ROOT, "profiles")
 TRAFFIC_FILE = os.path.join(PROFILES, "xpass_traffic_qaoa_n28.json")
 
-KIND_NAMES = {0: "whole", 1: "first", 2: "middle", 3: "boundary", 4: "last", 5: "last_store",
-              6: "init", 7: "expect", 8: "reduce"}
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 class HipEvents:
@@ -54,6 +56,10 @@ class HipEvents:
             self.ev.append(h.value)
         self.array = (ctypes.c_void_p * count)(*self.ev)
 
+    def slice(self, start: int):
+        return ctypes.cast(ctypes.byref(self.array, ctypes.sizeof(ctypes.c_void_p) * start),
+                           ctypes.POINTER(ctypes.c_void_p))
+
     def elapsed_ms(self, a: int, b: int) -> float:
         ms = ctypes.c_float()
         if self.hip.hipEventElapsedTime(ctypes.byref(ms), self.ev[a], self.ev[b]) != 0:
@@ -65,12 +71,19 @@ class HipEvents:
             self.hip.hipEventDestroy(h)
 
 
-def kernel_symbol(kind: int, col_bits: int) -> str:
-    mode = {1: "XMODE_FIRST", 2: "XMODE_MIDDLE", 3: "XMODE_BOUNDARY", 4: "XMODE_LAST",
-            5: "XMODE_LAST_STORE"}.get(kind)
-    if mode is None:
-        return KIND_NAMES[kind]
-    return f"xpass_kernel<{col_bits}, {mode}>"
+MODE_NAMES = {1: "XMODE_FIRST", 2: "XMODE_MIDDLE", 3: "XMODE_BOUNDARY", 4: "XMODE_LAST",
+              5: "XMODE_LAST_STORE"}
+
+
+def kernel_name(kind: int, col_bits: int) -> str:
+    from paper_2110_03963_amd import _lib
+
+    if kind in MODE_NAMES:
+        return f"xpass_kernel<{col_bits}, {MODE_NAMES[kind]}>"
+    name = _lib.PASS_KINDS[kind]
+    if name.startswith(("fft_", "grad_")) and name not in ("grad_reduce", "grad_whole"):
+        return f"{name}<{col_bits}>"
+    return name
 
 
 def source_digest(*paths) -> str:
@@ -81,6 +94,65 @@ def source_digest(*paths) -> str:
     return h.hexdigest()[:16]
 
 
+def plan_of(lib, prob, p: int, for_grad: bool, flags: int):
+    from paper_2110_03963_amd import _lib
+
+    n = lib.qva_plan(prob.cstruct(), p, int(for_grad), flags, None, 0)
+    infos = (_lib.QvaPassInfo * n)()
+    lib.qva_plan(prob.cstruct(), p, int(for_grad), flags, infos, n)
+    return list(infos)
+
+
+def per_kernel_profile(run_timed, infos, steps: int):
+    """Run `steps` timed executions of a plan and aggregate the per-launch
+    event durations by kernel."""
+    import torch
+
+    npl = len(infos)
+    evs = HipEvents(2 * npl * steps)
+    for s in range(steps):
+        run_timed(evs.slice(2 * npl * s), 2 * npl)
+    torch.cuda.synchronize()
+    per: dict[str, dict] = {}
+    for s in range(steps):
+        for i, info in enumerate(infos):
+            name = kernel_name(info.kind, info.col_bits)
+            d = per.setdefault(name, {"launches": 0, "ms": 0.0, "bytes": 0.0})
+            d["launches"] += 1
+            d["ms"] += evs.elapsed_ms(2 * (s * npl + i), 2 * (s * npl + i) + 1)
+            d["bytes"] += info.bytes
+    evs.close()
+    return per
+
+
+def roofline_of(per: dict, steps: int) -> dict:
+    name, d = max(per.items(), key=lambda kv: kv[1]["ms"])
+    avg_ms = d["ms"] / d["launches"]
+    bpl = d["bytes"] / d["launches"]
+    achieved = bpl / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": name,
+            "launches_per_step": d["launches"] // steps, "avg_launch_ms": round(avg_ms, 4),
+            "algorithmic_bytes_per_launch": bpl}
+
+
+def time_calls(fn, warmup: int, steps: int) -> float:
+    """Mean milliseconds per call of fn() between torch events."""
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
 def cpu_baseline(wl) -> dict:
     """The oracle (single-threaded C) on one layer of the same n = 28 instance."""
     import oracle
@@ -88,9 +160,148 @@ def cpu_baseline(wl) -> dict:
     t0 = time.perf_counter()
     oracle.evolve("x", wl.q, wl.gammas[:1], wl.ts[:1])
     dt = time.perf_counter() - t0
-    return {"value": 1.0 / dt, "unit": "layer-applications/s", "cores": 1, "kind": "oracle",
-            "sample": f"one layer (phase + hypercube mixer + <Q>) of the same n=28 instance, "
-                      f"full size, {dt:.1f} s on 1 host core ({platform.processor() or 'cpu'})"}
+    return {"value": round(1.0 / dt, 5), "unit": "layer-applications/s", "cores": 1, "kind": "oracle",
+            "sample": f"one layer (phase + hypercube mixer + <Q>) of the same n=28 instance at full "
+                      f"size: {dt:.1f} s on 1 host core ({platform.processor() or 'cpu'}); "
+                      f"value = 1 layer / that time",
+            "host_cpus": os.cpu_count()}
+
+
+# ------------------------------------------------------------------ extras
+def extra_qwoa(lib, steps: int) -> dict:
+    """QWOA portfolio over all subsets of 26 assets, ring mixer, p = 6."""
+    import torch
+
+    import paper_2110_03963_amd as qva
+    from paper_2110_03963_amd import _lib
+    from workloads import CONFIG_SEEDS, qwoa_portfolio_workload
+
+    n, p = 26, 6
+    wl = qwoa_portfolio_workload(n, p, seed=CONFIG_SEEDS["qwoa_n26"], lambda_kind="ring")
+    prob = qva.Problem(torch.from_numpy(wl.q).cuda(), "circulant", None, "ring")
+    g = torch.tensor(wl.gammas, device="cuda")
+    t = torch.tensor(wl.ts, device="cuda")
+    psi = torch.empty(1 << n, dtype=torch.complex128, device="cuda")
+    ws = torch.empty(max(prob.workspace_bytes(p), 16), dtype=torch.uint8, device="cuda")
+    out = torch.empty(2, dtype=torch.float64, device="cuda")
+    flags = _lib.QVA_EVOLVE_SKIP_FINAL_STATE
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def run():
+        _lib.check("qva_evolve", lib.qva_evolve(prob.cstruct(), g.data_ptr(), t.data_ptr(), p,
+                                                psi.data_ptr(), out.data_ptr(), out.data_ptr() + 8,
+                                                flags, ws.data_ptr(), ws.numel(), stream))
+
+    ms = time_calls(run, 2, steps)
+    infos = plan_of(lib, prob, p, False, flags)
+
+    def run_timed(ev, nev):
+        _lib.check("qva_evolve_timed",
+                   lib.qva_evolve_timed(prob.cstruct(), g.data_ptr(), t.data_ptr(), p, psi.data_ptr(),
+                                        out.data_ptr(), out.data_ptr() + 8, flags, ws.data_ptr(),
+                                        ws.numel(), ev, nev, stream))
+
+    per = per_kernel_profile(run_timed, infos, steps)
+    plan_bytes = sum(i.bytes for i in infos)
+    return {"workload": "qwoa_portfolio_n26_p6_ring", "ms_per_evolve": round(ms, 4),
+            "layer_applications_per_s": round(p / (ms * 1e-3), 2), "launches": len(infos),
+            "effective_GBps": round(plan_bytes / (ms * 1e-3) / 1e9, 1),
+            "f": out[0].item(), "roofline": roofline_of(per, steps),
+            "per_kernel_ms_per_evolve": {k: round(v["ms"] / steps, 4) for k, v in sorted(per.items())}}
+
+
+def extra_adjoint(lib, reps: int) -> dict:
+    """Adjoint gradient, weighted 3-regular MaxCut n = 30, p = 12 (24 params),
+    against 4p central-difference and 2p+1 forward-difference evaluations of
+    the same fused forward on the same GPU."""
+    import numpy as np
+    import torch
+
+    import paper_2110_03963_amd as qva
+    from paper_2110_03963_amd import _lib
+    from workloads import CONFIG_SEEDS, maxcut_qualities_device, qaoa_maxcut_workload
+
+    n, p = 30, 12
+    wl = qaoa_maxcut_workload(n, p, graph="regular3", weighted=True, seed=CONFIG_SEEDS["grad_n30"],
+                              build_q=False)
+    q = maxcut_qualities_device(n, wl.edges, wl.weights, "cuda")
+    prob = qva.Problem(q, "x")
+    g = torch.tensor(wl.gammas, device="cuda")
+    t = torch.tensor(wl.ts, device="cuda")
+    psi = torch.empty(1 << n, dtype=torch.complex128, device="cuda")
+    chi = torch.empty(1 << n, dtype=torch.complex128, device="cuda")
+    wsg = torch.empty(max(prob.workspace_bytes(p, True), 256), dtype=torch.uint8, device="cuda")
+    wse = torch.empty(max(prob.workspace_bytes(p), 16), dtype=torch.uint8, device="cuda")
+    f = torch.empty((), dtype=torch.float64, device="cuda")
+    dg = torch.empty(p, dtype=torch.float64, device="cuda")
+    dt = torch.empty(p, dtype=torch.float64, device="cuda")
+    out = torch.empty(2, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    flags = _lib.QVA_EVOLVE_SKIP_FINAL_STATE
+
+    def adjoint():
+        _lib.check("qva_grad", lib.qva_grad(prob.cstruct(), g.data_ptr(), t.data_ptr(), p, psi.data_ptr(),
+                                            chi.data_ptr(), f.data_ptr(), dg.data_ptr(), dt.data_ptr(),
+                                            wsg.data_ptr(), wsg.numel(), stream))
+
+    gp = torch.empty(p, dtype=torch.float64, device="cuda")
+    tp = torch.empty(p, dtype=torch.float64, device="cuda")
+
+    def forward():
+        _lib.check("qva_evolve", lib.qva_evolve(prob.cstruct(), gp.data_ptr(), tp.data_ptr(), p,
+                                                psi.data_ptr(), out.data_ptr(), out.data_ptr() + 8,
+                                                flags, wse.data_ptr(), wse.numel(), stream))
+
+    h = 1e-5
+    fd_vals = torch.empty(4 * p, dtype=torch.float64, device="cuda")
+
+    def central():
+        # 4p fused forward evaluations f(theta +- h e_k), results kept on device
+        for k in range(2 * p):
+            for sgn in (1.0, -1.0):
+                gp.copy_(g)
+                tp.copy_(t)
+                (gp if k < p else tp)[k % p] += sgn * h
+                forward()
+                fd_vals[2 * k + (0 if sgn > 0 else 1)] = out[0]
+
+    def forward_diff():
+        for k in range(2 * p + 1):
+            gp.copy_(g)
+            tp.copy_(t)
+            if k < 2 * p:
+                (gp if k < p else tp)[k % p] += h
+            forward()
+
+    ms_adj = time_calls(adjoint, 1, reps)
+    ms_cfd = time_calls(central, 1, reps)
+    ms_ffd = time_calls(forward_diff, 0, reps)
+    adj = torch.cat([dg, dt]).cpu().numpy()
+    fdv = fd_vals.cpu().numpy()
+    cfd = (fdv[0::2] - fdv[1::2]) / (2 * h)
+    rel = float(np.max(np.abs(adj - cfd)) / np.max(np.abs(adj)))
+    infos = plan_of(lib, prob, p, True, 0)
+
+    def run_timed(ev, nev):
+        _lib.check("qva_grad_timed",
+                   lib.qva_grad_timed(prob.cstruct(), g.data_ptr(), t.data_ptr(), p, psi.data_ptr(),
+                                      chi.data_ptr(), f.data_ptr(), dg.data_ptr(), dt.data_ptr(),
+                                      wsg.data_ptr(), wsg.numel(), ev, nev, stream))
+
+    per = per_kernel_profile(run_timed, infos, 1)
+    plan_bytes = sum(i.bytes for i in infos)
+    return {"workload": "adjoint_qaoa_maxcut_n30_p12", "params": 2 * p,
+            "ms_per_adjoint_gradient": round(ms_adj, 2),
+            "adjoint_gradients_per_s": round(1e3 / ms_adj, 3),
+            "ms_per_central_fd_gradient": round(ms_cfd, 2),
+            "ms_per_forward_fd_gradient": round(ms_ffd, 2),
+            "speedup_vs_central_fd": round(ms_cfd / ms_adj, 2),
+            "speedup_vs_forward_fd": round(ms_ffd / ms_adj, 2),
+            "max_rel_diff_adjoint_vs_central_fd_h1e-5": rel,
+            "f": f.item(), "launches": len(infos),
+            "effective_GBps": round(plan_bytes / (ms_adj * 1e-3) / 1e9, 1),
+            "roofline": roofline_of(per, 1),
+            "per_kernel_ms": {k: round(v["ms"], 3) for k, v in sorted(per.items())}}
 
 
 def main() -> int:
@@ -106,7 +317,6 @@ def main() -> int:
               "(the sharded multi-GPU path is a design, not part of this build)", file=sys.stderr)
         return 2
 
-    import numpy as np
     import torch
 
     import paper_2110_03963_amd as qva
@@ -122,8 +332,7 @@ def main() -> int:
     n, p = 28, 8
     t_gen = time.perf_counter()
     wl = qaoa_maxcut_workload(n, p, graph="regular3", weighted=True, seed=CONFIG_SEEDS["qaoa_n28"])
-    t_gen = time.perf_counter() - t_gen
-    print(f"[bench] workload n={n} p={p} generated in {t_gen:.1f}s", file=sys.stderr, flush=True)
+    log(f"workload n={n} p={p} generated in {time.perf_counter() - t_gen:.1f}s")
     q = torch.from_numpy(wl.q).to(dev)
     prob = qva.Problem(q, "x")
     g = torch.tensor(wl.gammas, dtype=torch.float64, device=dev)
@@ -144,60 +353,36 @@ def main() -> int:
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    t_wall = time.perf_counter()
     e0.record()
     for _ in range(args.steps):
         step()
     e1.record()
     torch.cuda.synchronize()
-    t_wall = time.perf_counter() - t_wall
     ms_total = e0.elapsed_time(e1)
     ms_step = ms_total / args.steps
     f_val, norm_val = out[0].item(), out[1].item()
     value = p * args.steps / (ms_total * 1e-3)
-    print(f"[bench] timed {args.steps} steps: {ms_step:.3f} ms/step, f={f_val:.15f}, "
-          f"norm={norm_val:.15f}", file=sys.stderr, flush=True)
+    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step, f={f_val:.15f}, norm={norm_val:.15f}")
 
-    # ---- per-launch timing of the same plan (HIP events on the same stream)
-    npl = lib.qva_plan(prob.cstruct(), p, 0, flags, None, 0)
-    infos = (_lib.QvaPassInfo * npl)()
-    lib.qva_plan(prob.cstruct(), p, 0, flags, infos, npl)
-    evs = HipEvents(2 * npl * args.steps)
-    for s in range(args.steps):
-        arr = ctypes.cast(ctypes.byref(evs.array, ctypes.sizeof(ctypes.c_void_p) * 2 * npl * s),
-                          ctypes.POINTER(ctypes.c_void_p))
+    # per-launch timing of the same plan (HIP events on the same stream)
+    infos = plan_of(lib, prob, p, False, flags)
+
+    def run_timed(ev, nev):
         _lib.check("qva_evolve_timed",
-                   lib.qva_evolve_timed(prob.cstruct(), g.data_ptr(), t.data_ptr(), p,
-                                        psi.data_ptr(), out.data_ptr(), out.data_ptr() + 8, flags,
-                                        ws.data_ptr(), ws.numel(), arr, 2 * npl, stream))
-    torch.cuda.synchronize()
-    per_kernel: dict[str, dict] = {}
-    for s in range(args.steps):
-        for i in range(npl):
-            info = infos[i]
-            name = kernel_symbol(info.kind, info.col_bits)
-            d = per_kernel.setdefault(name, {"launches": 0, "ms": 0.0, "bytes": 0.0})
-            d["launches"] += 1
-            d["ms"] += evs.elapsed_ms(2 * (s * npl + i), 2 * (s * npl + i) + 1)
-            d["bytes"] += info.bytes
-    evs.close()
-    dom_name, dom = max(per_kernel.items(), key=lambda kv: kv[1]["ms"])
-    avg_ms = dom["ms"] / dom["launches"]
-    bytes_per_launch = dom["bytes"] / dom["launches"]
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    plan_bytes = sum(infos[i].bytes for i in range(npl))
-    traffic = None
+                   lib.qva_evolve_timed(prob.cstruct(), g.data_ptr(), t.data_ptr(), p, psi.data_ptr(),
+                                        out.data_ptr(), out.data_ptr() + 8, flags, ws.data_ptr(),
+                                        ws.numel(), ev, nev, stream))
+
+    per = per_kernel_profile(run_timed, infos, args.steps)
+    roofline = roofline_of(per, args.steps)
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as fh:
             tr = json.load(fh)
-        digest = source_digest(os.path.join(ROOT, "paper_2110_03963_amd", "csrc", "qva_xmix.hip"))
-        if tr.get("source_digest") == digest and tr.get("kernel") == dom_name:
-            traffic = tr.get("bytes_per_launch")
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": dom_name, "launches_per_step": dom["launches"] // args.steps,
-                "avg_launch_ms": round(avg_ms, 4),
-                "algorithmic_bytes_per_launch": bytes_per_launch}
+        digest = source_digest(os.path.join(ROOT, "paper_2110_03963_amd", "csrc", "qva_xmix.hip"),
+                               os.path.join(ROOT, "paper_2110_03963_amd", "csrc", "qva_tile.h"))
+        if tr.get("source_digest") == digest and tr.get("kernel") == roofline["kernel"]:
+            roofline["traffic"] = tr.get("bytes_per_launch")
+    plan_bytes = sum(i.bytes for i in infos)
 
     result = {
         "metric": METRIC,
@@ -216,18 +401,30 @@ def main() -> int:
                    "graph": "random 3-regular, weights U(0,1)", "quality": "weighted cut",
                    "seed": CONFIG_SEEDS["qaoa_n28"], "output": "<Q> (final state not stored)"},
         "roofline": roofline,
-        "plan": {"launches": npl, "algorithmic_bytes": plan_bytes,
+        "plan": {"launches": len(infos), "algorithmic_bytes": plan_bytes,
                  "effective_GBps": round(plan_bytes / (ms_step * 1e-3) / 1e9, 1),
                  "per_kernel_ms_per_step": {k: round(v["ms"] / args.steps, 4)
-                                            for k, v in sorted(per_kernel.items())}},
+                                            for k, v in sorted(per.items())}},
         "f": f_val,
         "norm": norm_val,
         "device": torch.cuda.get_device_name(0),
     }
+    del psi, ws, q, prob
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        extras = {}
+        for name, fn in [("qwoa_circulant", lambda: extra_qwoa(lib, max(3, args.steps // 2))),
+                         ("adjoint_vs_fd", lambda: extra_adjoint(lib, 2))]:
+            log(f"extra: {name} ...")
+            try:
+                extras[name] = fn()
+            except Exception as exc:  # reported, not fatal: the headline line still prints
+                extras[name] = {"error": repr(exc)}
+            torch.cuda.empty_cache()
+        result["extras"] = extras
     if not args.no_cpu_baseline:
-        print("[bench] timing the CPU oracle on one layer ...", file=sys.stderr, flush=True)
+        log("timing the CPU oracle on one layer ...")
         result["cpu_baseline"] = cpu_baseline(wl)
-        result["cpu_baseline"]["host_cpus"] = os.cpu_count()
     print(json.dumps(result), flush=True)
     return 0
 

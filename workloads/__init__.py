@@ -22,6 +22,7 @@ from .graphs import (
 )
 from .problems import (
     maxcut_qualities,
+    maxcut_qualities_device,
     ring_cut_qualities_device,
     portfolio_qualities,
     draw_angles,
@@ -39,6 +40,7 @@ __all__ = [
     "erdos_renyi_edges",
     "random_regular_edges",
     "maxcut_qualities",
+    "maxcut_qualities_device",
     "ring_cut_qualities_device",
     "portfolio_qualities",
     "draw_angles",

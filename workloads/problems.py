@@ -95,6 +95,21 @@ def maxcut_qualities(n: int, edges, weights=None, *, uncut: bool = False,
     return q.astype(dtype, copy=False)
 
 
+def maxcut_qualities_device(n: int, edges, weights, device):
+    """maxcut_qualities built with torch on `device` (full-size inputs that
+    are slow to build on the host).  Edge contributions are added in edge
+    order, so the result is deterministic; it may differ from the host
+    version in the last bit (different summation order)."""
+    import torch
+
+    j = torch.arange(1 << n, dtype=torch.int64, device=device)
+    q = torch.zeros(1 << n, dtype=torch.float64, device=device)
+    for (u, v), w in zip(edges, weights):
+        q += (((j >> u) ^ (j >> v)) & 1).to(torch.float64) * float(w)
+    del j
+    return q
+
+
 def ring_cut_qualities_device(n: int, device):
     """Unweighted ring MaxCut cut sizes, built with torch on `device` (for
     full-size inputs that are too slow to build on the host):
@@ -181,8 +196,12 @@ class Workload:
 
 
 def qaoa_maxcut_workload(n: int, p: int, *, graph: str = "regular3", weighted: bool = True,
-                         seed: int = 0, edge_prob: float = 0.5, name: str = "") -> Workload:
-    """QAOA MaxCut instance: graph -> weights -> gammas -> ts from one Generator."""
+                         seed: int = 0, edge_prob: float = 0.5, name: str = "",
+                         build_q: bool = True) -> Workload:
+    """QAOA MaxCut instance: graph -> weights -> gammas -> ts from one Generator.
+
+    With build_q=False the quality vector is left as None (build it with
+    maxcut_qualities or maxcut_qualities_device from edges and weights)."""
     rng = np.random.default_rng(seed)
     if graph == "regular3":
         edges = random_regular_edges(3, n, rng)
@@ -194,7 +213,7 @@ def qaoa_maxcut_workload(n: int, p: int, *, graph: str = "regular3", weighted: b
         raise ValueError(graph)
     weights = rng.uniform(0.0, 1.0, len(edges)) if weighted else np.ones(len(edges))
     gammas, ts = draw_angles(rng, p)
-    q = maxcut_qualities(n, edges, weights)
+    q = maxcut_qualities(n, edges, weights) if build_q else None
     return Workload(name=name or f"qaoa_maxcut_n{n}_p{p}", mixer="x", n=n, q=q,
                     gammas=gammas, ts=ts, edges=edges, weights=weights, seed=seed)
 
