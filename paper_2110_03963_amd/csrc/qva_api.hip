@@ -607,6 +607,23 @@ int grad_run(const qva_problem* P, const double* gammas, const double* ts, int p
             e = launch_fftpass(f, s);
             break;
         }
+        case QVA_PASS_GRAD_DIF:
+        case QVA_PASS_GRAD_DIT: {
+            // no inner product here: the single-vector transform, once per vector
+            const XGroup& g = groups[l.group];
+            FftPassParams f{};
+            f.n = n;
+            f.k = g.k;
+            f.col_bits = g.col_bits;
+            f.flags = l.kind == QVA_PASS_GRAD_DIF ? FMODE_DIF : FMODE_DIT;
+            f.psi = psi;
+            e = launch_fftpass(f, s);
+            if (e == hipSuccess) {
+                f.psi = chi;
+                e = launch_fftpass(f, s);
+            }
+            break;
+        }
         default: {  // backward passes
             const XGroup& g = groups[l.group];
             GradPassParams gp{};

@@ -8,6 +8,11 @@
 
 namespace qva {
 
+// Scheduling fence: the unrolled iterations of a register-heavy loop body
+// (an inlined sincos, say) are not interleaved across it, which keeps their
+// temporaries from being live all at once.
+#define QVA_SCHED_FENCE() __builtin_amdgcn_sched_barrier(0)
+
 typedef double dvec2 __attribute__((ext_vector_type(2)));
 
 // Streaming (non-temporal) 16-byte load/store of one amplitude: every
@@ -33,11 +38,36 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b)
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
+// sin x and cos x without the large-argument reduction path of the library
+// sincos (whose code, inlined into every unrolled phase loop, costs registers
+// even when it never runs).  Cody-Waite style reduction onto sincospi:
+// 1/pi = kInvPiHi + kInvPiLo to about 2^-109 relative, y = fl(x kInvPiHi),
+// e = x/pi - y from the exact product error (one fma) plus x kInvPiLo, so
+// x = pi (y + e).  sincospi(y) reduces y exactly; the remaining angle
+// d = pi e (|d| < 1e-3 for |x| < 2^41) is applied by its Taylor series to
+// order 7 (truncation below 1e-24).
+__device__ __forceinline__ void sincos_red(double x, double* sn, double* cs)
+{
+    constexpr double kInvPiHi = 0.3183098861837907;      // 1/pi rounded to double
+    constexpr double kInvPiLo = -1.9678676675182486e-17;  // 1/pi - kInvPiHi
+    constexpr double kPi = 3.141592653589793;
+    const double y = x * kInvPiHi;
+    const double e = fma(x, kInvPiLo, fma(x, kInvPiHi, -y));
+    double s, c;
+    sincospi(y, &s, &c);
+    const double d = kPi * e;
+    const double d2 = d * d;
+    const double sd = d * fma(d2, fma(d2, fma(d2, -1.0 / 5040.0, 1.0 / 120.0), -1.0 / 6.0), 1.0);
+    const double cd = fma(d2, fma(d2, fma(d2, -1.0 / 720.0, 1.0 / 24.0), -0.5), 1.0);
+    *sn = fma(s, cd, c * sd);
+    *cs = fma(c, cd, -s * sd);
+}
+
 // exp(-i x) = (cos x, -sin x)
 __device__ __forceinline__ double2 expmi(double x)
 {
     double s, c;
-    sincos(x, &s, &c);
+    sincos_red(x, &s, &c);
     return make_double2(c, -s);
 }
 
@@ -67,7 +97,7 @@ struct MixCoef {
 __device__ __forceinline__ MixCoef mix_coef(double t)
 {
     double s, c;
-    sincos(t, &s, &c);
+    sincos_red(t, &s, &c);
     MixCoef m;
     if (fabs(c) >= fabs(s)) {
         m.k = s / c;

@@ -36,6 +36,7 @@ __device__ __forceinline__ void phase_a(double2 (&v)[kRegs], const double* q, co
     for (int r = 0; r < kRegs; ++r) {
         const double2 ph = expmi(gamma * qq[r]);
         v[r] = cmul(v[r], make_double2(scale * ph.x, scale * ph.y));
+        QVA_SCHED_FENCE();
     }
 }
 
@@ -61,6 +62,7 @@ __device__ __forceinline__ void diag_c(double2 (&v)[kRegs], const FftPassParams&
             }
         }
         v[r] = cmul(v[r], expmi(tt * lam));
+        QVA_SCHED_FENCE();
     }
 }
 

@@ -19,6 +19,16 @@
 // and reduced afterwards in a fixed order, so results are deterministic.
 #include "qva_tile.h"
 
+// Two vectors plus per-element twiddles need more than the 256 registers a
+// wave gets at two waves per SIMD; at one wave per SIMD the overflow stays
+// in accumulation registers instead of scratch memory.
+#ifndef QVA_GRADF_WAVES
+#define QVA_GRADF_WAVES 1
+#endif
+#ifndef QVA_GRADX_WAVES
+#define QVA_GRADX_WAVES 2
+#endif
+
 namespace qva {
 namespace {
 
@@ -133,14 +143,14 @@ __device__ __forceinline__ void mix2_reverse(double2 (&p)[kRegs], double2 (&x)[k
 __device__ __forceinline__ void inv_cs(double t, double& c, double& s)
 {
     double sn, cs;
-    sincos(t, &sn, &cs);
+    sincos_red(t, &sn, &cs);
     c = cs;
     s = -sn;
 }
 
 // sum_j q_j Im(conj(chi_j) phi_j) over the registers of layout L, and the
 // inverse phase exp(+i gamma q) applied to both vectors.
-template <int L>
+template <int L, bool SCALE>
 __device__ __forceinline__ double unphase2(double2 (&p)[kRegs], double2 (&x)[kRegs], const double* q,
                                            const TileMap& g, int t, double gamma, double scale)
 {
@@ -151,12 +161,15 @@ __device__ __forceinline__ double unphase2(double2 (&p)[kRegs], double2 (&x)[kRe
     double acc = 0.0;
 #pragma unroll
     for (int r = 0; r < kRegs; ++r) {
-        p[r] = make_double2(p[r].x * scale, p[r].y * scale);
-        x[r] = make_double2(x[r].x * scale, x[r].y * scale);
+        if constexpr (SCALE) {
+            p[r] = make_double2(p[r].x * scale, p[r].y * scale);
+            x[r] = make_double2(x[r].x * scale, x[r].y * scale);
+        }
         acc = fma(qq[r], x[r].x * p[r].y - x[r].y * p[r].x, acc);
         const double2 ph = expmi(-gamma * qq[r]);
         p[r] = cmul(p[r], ph);
         x[r] = cmul(x[r], ph);
+        QVA_SCHED_FENCE();
     }
     return acc;
 }
@@ -195,7 +208,7 @@ __device__ __forceinline__ void write_slots(const GradPassParams& P, double a1, 
 
 // ------------------------------------------------ hypercube-mixer passes
 template <int C, int MODE>
-__global__ __launch_bounds__(kThreads, 2) void gradx_kernel(GradPassParams P)
+__global__ __launch_bounds__(kThreads, QVA_GRADX_WAVES) void gradx_kernel(GradPassParams P)
 {
     __shared__ double2 lds[1 << kTileBits];
     __shared__ double red[4 * (kThreads / 64)];
@@ -207,9 +220,11 @@ __global__ __launch_bounds__(kThreads, 2) void gradx_kernel(GradPassParams P)
     if constexpr (MODE == GMODE_TURN) {
         // last forward group of the last layer, <Q>, chi = Q psi_p, then the
         // inverse of the same rotations on both vectors
-        load_tile<LA>(p, P.phi, g, t);
         const double tt = angle_value(P.t1);
         const MixCoef m = mix_coef(tt);
+        double c, s;
+        inv_cs(tt, c, s);
+        load_tile<LA>(p, P.phi, g, t);
         if (m.tanform)
             mix_forward<C, true>(p, lds, t, m.k);
         else
@@ -233,15 +248,19 @@ __global__ __launch_bounds__(kThreads, 2) void gradx_kernel(GradPassParams P)
         block_sum_k<2>(fv, red);
         if (t == 0)
             P.fpart[blockIdx.x] = make_double2(fv[0], fv[1]);
-        double c, s;
-        inv_cs(tt, c, s);
         mix2_reverse<C>(p, x, lds, t, c, s, a1);
         write_slots(P, a1, 0.0, 0.0, red);
         store2<LA>(p, x, P, g, t);
     } else {
-        load2<LA>(p, x, P, g, t);
-        double c, s;
+        // every angle and its sine/cosine before the data is loaded: computed
+        // mid-pass they extend register live ranges across the whole tile
+        double c, s, c2 = 1.0, s2 = 0.0, gam = 0.0;
         inv_cs(angle_value(P.t1), c, s);
+        if constexpr (MODE == GMODE_BOUND)
+            inv_cs(angle_value(P.t2), c2, s2);
+        if constexpr (MODE != GMODE_MID)
+            gam = angle_value(P.gamma);
+        load2<LA>(p, x, P, g, t);
         mix2_forward<C>(p, x, lds, t, c, s, a1);
         if constexpr (MODE == GMODE_MID) {
             write_slots(P, a1, 0.0, 0.0, red);
@@ -249,10 +268,9 @@ __global__ __launch_bounds__(kThreads, 2) void gradx_kernel(GradPassParams P)
         } else {
             // the forward pass applied the layer's scalar factor together with
             // the phase; the direct-form inverse rotations need none
-            ag = unphase2<last_layout<C>()>(p, x, P.q, g, t, angle_value(P.gamma), 1.0);
+            ag = unphase2<last_layout<C>(), false>(p, x, P.q, g, t, gam, 1.0);
             if constexpr (MODE == GMODE_BOUND) {
-                inv_cs(angle_value(P.t2), c, s);
-                mix2_reverse<C>(p, x, lds, t, c, s, a2);
+                mix2_reverse<C>(p, x, lds, t, c2, s2, a2);
                 write_slots(P, a1, ag, a2, red);
                 store2<LA>(p, x, P, g, t);
             } else {  // GMODE_FINAL
@@ -285,6 +303,7 @@ __device__ __forceinline__ void digit_twiddle2(double2 (&p)[kRegs], double2 (&x)
             const double2 w = make_double2(cs, inv ? sn : -sn);
             p[r] = cmul(p[r], w);
             x[r] = cmul(x[r], w);
+            QVA_SCHED_FENCE();
         }
     }
 }
@@ -362,7 +381,7 @@ __device__ __forceinline__ double lambda_at(const GradPassParams& P, int64_t til
 }
 
 template <int C, int MODE>
-__global__ __launch_bounds__(kThreads, 2) void gradf_kernel(GradPassParams P)
+__global__ __launch_bounds__(kThreads, QVA_GRADF_WAVES) void gradf_kernel(GradPassParams P)
 {
     __shared__ double2 lds[1 << kTileBits];
     __shared__ double red[4 * (kThreads / 64)];
@@ -370,6 +389,8 @@ __global__ __launch_bounds__(kThreads, 2) void gradf_kernel(GradPassParams P)
     const int64_t tile = blockIdx.x;
     const TileMap g = tile_map(tile, P.k, C);
     const double invN = ldexp(1.0, -P.n);
+    const double tt = (MODE == GMODE_LOWDIAG) ? angle_value(P.t1) : 0.0;
+    const double gam = (MODE == GMODE_BOUND || MODE == GMODE_FINAL) ? angle_value(P.gamma) : 0.0;
     double2 p[kRegs], x[kRegs];
 
     if constexpr (MODE == GMODE_TURN) {
@@ -394,18 +415,9 @@ __global__ __launch_bounds__(kThreads, 2) void gradf_kernel(GradPassParams P)
             P.fpart[blockIdx.x] = make_double2(fv[0], fv[1]);
         dif_tile2<C>(p, x, lds, g, t);
         store2<dif_last<C>()>(p, x, P, g, t);
-    } else if constexpr (MODE == GMODE_DIF) {
-        load2<LA>(p, x, P, g, t);
-        dif_tile2<C>(p, x, lds, g, t);
-        store2<dif_last<C>()>(p, x, P, g, t);
-    } else if constexpr (MODE == GMODE_DIT) {
-        load2<dif_last<C>()>(p, x, P, g, t);
-        dit_tile2<C>(p, x, lds, g, t);
-        store2<LA>(p, x, P, g, t);
     } else if constexpr (MODE == GMODE_LOWDIAG) {
         load2<LA>(p, x, P, g, t);
         dif_tile2<C>(p, x, lds, g, t);
-        const double tt = angle_value(P.t1);
         double a1 = 0.0;
 #pragma unroll
         for (int r = 0; r < kRegs; ++r) {
@@ -414,6 +426,7 @@ __global__ __launch_bounds__(kThreads, 2) void gradf_kernel(GradPassParams P)
             const double2 d = expmi(-tt * lam);  // exp(+i t lambda): the inverse diagonal
             p[r] = cmul(p[r], d);
             x[r] = cmul(x[r], d);
+            QVA_SCHED_FENCE();
         }
         write_slots(P, a1 * invN, 0.0, 0.0, red);
         dit_tile2<C>(p, x, lds, g, t);
@@ -421,7 +434,7 @@ __global__ __launch_bounds__(kThreads, 2) void gradf_kernel(GradPassParams P)
     } else {  // GMODE_BOUND, GMODE_FINAL
         load2<dif_last<C>()>(p, x, P, g, t);
         dit_tile2<C>(p, x, lds, g, t);
-        const double ag = unphase2<LA>(p, x, P.q, g, t, angle_value(P.gamma), invN);
+        const double ag = unphase2<LA, true>(p, x, P.q, g, t, gam, invN);
         if constexpr (MODE == GMODE_BOUND) {
             write_slots(P, 0.0, ag, 0.0, red);
             dif_tile2<C>(p, x, lds, g, t);
@@ -461,7 +474,7 @@ __device__ double small_unrotate_x(double2* ph, double2* ch, int n, double tt)
 __device__ void small_rotate_x(double2* s, int n, double tt)
 {
     double sn, c;
-    sincos(tt, &sn, &c);
+    sincos_red(tt, &sn, &c);
     const int N = 1 << n;
     for (int i = 0; i < n; ++i) {
         const int bit = 1 << i;
@@ -650,12 +663,6 @@ hipError_t launch_gradf_c(const GradPassParams& P, unsigned grid, hipStream_t s)
     switch (P.flags) {
     case GMODE_TURN:
         hipLaunchKernelGGL((gradf_kernel<C, GMODE_TURN>), dim3(grid), dim3(kThreads), 0, s, P);
-        break;
-    case GMODE_DIF:
-        hipLaunchKernelGGL((gradf_kernel<C, GMODE_DIF>), dim3(grid), dim3(kThreads), 0, s, P);
-        break;
-    case GMODE_DIT:
-        hipLaunchKernelGGL((gradf_kernel<C, GMODE_DIT>), dim3(grid), dim3(kThreads), 0, s, P);
         break;
     case GMODE_BOUND:
         hipLaunchKernelGGL((gradf_kernel<C, GMODE_BOUND>), dim3(grid), dim3(kThreads), 0, s, P);

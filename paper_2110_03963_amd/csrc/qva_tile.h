@@ -188,6 +188,7 @@ __device__ __forceinline__ void digit_twiddle(double2 (&v)[kRegs], const TileMap
             double s, c;
             sincospi(y, &s, &c);
             v[r] = INV ? cmul(v[r], make_double2(c, s)) : cmul(v[r], make_double2(c, -s));
+            QVA_SCHED_FENCE();
         }
     }
 }

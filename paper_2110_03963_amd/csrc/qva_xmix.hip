@@ -32,6 +32,7 @@ __device__ __forceinline__ void phase_regs(double2 (&v)[kRegs], const double* q,
 #pragma unroll
     for (int r = 0; r < kRegs; ++r)
         v[r] = cmul(v[r], cmul(scale, expmi(gamma * qq[r])));
+        QVA_SCHED_FENCE();
 }
 
 template <int L, int FLAGS>
@@ -118,7 +119,7 @@ __global__ __launch_bounds__(kThreads, 2) void xpass_kernel(XPassParams P)
 __device__ void small_mix(double2* s, int n, double t)
 {
     double sn, c;
-    sincos(t, &sn, &c);
+    sincos_red(t, &sn, &c);
     const int N = 1 << n;
     for (int i = 0; i < n; ++i) {
         const int bit = 1 << i;
