@@ -232,6 +232,70 @@ int qva_grad_timed(const qva_problem *P, const double *gammas_dev, const double 
                    double *dts_dev, void *work, size_t work_bytes, void *const *events,
                    int n_events, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Batched instances: many independent QAOA problems (hypercube mixer), f and
+ * the adjoint gradient of all of them per call, plus a plain gradient step.
+ * The passes of all instances are grouped into rounds (round r = pass r of
+ * every instance that still has one); one call enqueues a fixed sequence of
+ * launches and no host work, so it can be captured into a HIP graph together
+ * with qva_batch_sgd and replayed.
+ * ---------------------------------------------------------------------- */
+
+/* One instance.  All pointers are device pointers owned by the caller and
+ * must stay valid for the lifetime of the plan.  n_qubits in [12, 30],
+ * p in [1, QVA_BATCH_MAX_DEPTH]. */
+typedef struct {
+    int n_qubits;
+    int p;
+    const double *q;   /* 2^n qualities                                   */
+    double *gammas;    /* p angles (updated in place by qva_batch_sgd)      */
+    double *ts;        /* p angles (updated in place by qva_batch_sgd)      */
+    qva_c128 *psi;     /* 2^n working amplitudes                          */
+    qva_c128 *chi;     /* 2^n working amplitudes (adjoint state)          */
+    double *out_f;     /* 1 double: f                                     */
+    double *dgammas;   /* p doubles: df/dgamma                            */
+    double *dts;       /* p doubles: df/dt                                */
+} qva_batch_item;
+
+#define QVA_BATCH_MAX_DEPTH 64
+
+/* Round alignment of the instances (load balance of the launches). */
+typedef enum {
+    QVA_BATCH_ALIGN_START = 0, /* every instance starts in round 0                  */
+    QVA_BATCH_ALIGN_END = 1,   /* every instance finishes in the last round         */
+    QVA_BATCH_ALIGN_SPREAD = 2 /* start rounds chosen to even out tiles per round   */
+} qva_batch_align;
+
+typedef struct qva_batch_plan_s *qva_batch_plan;
+
+/* Build a plan on the host (no device work).  items: host array of count
+ * instances.  Returns QVA_OK and *out, or an error (nothing allocated). */
+int qva_batch_create(const qva_batch_item *items, int count, int align, qva_batch_plan *out);
+
+/* Device workspace the plan needs (tables and per-tile partial sums). */
+size_t qva_batch_workspace_bytes(qva_batch_plan plan);
+
+/* Copy the plan's tables into `work` (device, >= qva_batch_workspace_bytes,
+ * 256-byte aligned) on `stream` and wait for the copy.  Later calls must pass
+ * the same workspace. */
+int qva_batch_upload(qva_batch_plan plan, void *work, size_t work_bytes, void *stream);
+
+/* f and the gradient of every instance.  Enqueues qva_batch_launches() kernel
+ * launches on `stream`. */
+int qva_batch_grad(qva_batch_plan plan, void *work, size_t work_bytes, void *stream);
+
+/* gammas -= lr * dgammas and ts -= lr * dts for every instance. */
+int qva_batch_sgd(qva_batch_plan plan, double lr, void *work, size_t work_bytes, void *stream);
+
+/* Number of rounds and of kernel launches one qva_batch_grad enqueues, and the
+ * total tile count over all rounds (for cost models). */
+int qva_batch_rounds(qva_batch_plan plan);
+int qva_batch_launches(qva_batch_plan plan);
+int64_t qva_batch_tiles(qva_batch_plan plan);
+
+/* Release the host plan (does not touch device memory). */
+int qva_batch_destroy(qva_batch_plan plan);
+
 #ifdef __cplusplus
 }
 #endif

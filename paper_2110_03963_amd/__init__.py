@@ -7,6 +7,7 @@ memory and streams to it.
 
 from ._lib import QvaError, load as load_library  # noqa: F401
 from .qva import (  # noqa: F401
+    Batch,
     Problem,
     QVAExpectation,
     evolve,

@@ -61,6 +61,27 @@ PASS_KINDS = {0: "whole", 1: "first", 2: "middle", 3: "boundary", 4: "last", 5: 
               24: "grad_lowdiag", 25: "grad_reduce"}
 
 
+class QvaBatchItem(ctypes.Structure):
+    _fields_ = [
+        ("n_qubits", ctypes.c_int),
+        ("p", ctypes.c_int),
+        ("q", ctypes.c_void_p),
+        ("gammas", ctypes.c_void_p),
+        ("ts", ctypes.c_void_p),
+        ("psi", ctypes.c_void_p),
+        ("chi", ctypes.c_void_p),
+        ("out_f", ctypes.c_void_p),
+        ("dgammas", ctypes.c_void_p),
+        ("dts", ctypes.c_void_p),
+    ]
+
+
+QVA_BATCH_ALIGN_START = 0
+QVA_BATCH_ALIGN_END = 1
+QVA_BATCH_ALIGN_SPREAD = 2
+QVA_BATCH_MAX_DEPTH = 64
+
+
 class QvaError(RuntimeError):
     def __init__(self, fn: str, status: int, text: str):
         super().__init__(f"{fn}: {text} (status {status})")
@@ -92,6 +113,15 @@ SIGNATURES = {
                               ctypes.POINTER(ctypes.c_void_p), _I, _P]),
     "qva_grad_timed": (_I, [_PROB, _P, _P, _I, _P, _P, _P, _P, _P, _P, _SZ,
                             ctypes.POINTER(ctypes.c_void_p), _I, _P]),
+    "qva_batch_create": (_I, [ctypes.POINTER(QvaBatchItem), _I, _I, ctypes.POINTER(ctypes.c_void_p)]),
+    "qva_batch_workspace_bytes": (_SZ, [_P]),
+    "qva_batch_upload": (_I, [_P, _P, _SZ, _P]),
+    "qva_batch_grad": (_I, [_P, _P, _SZ, _P]),
+    "qva_batch_sgd": (_I, [_P, _D, _P, _SZ, _P]),
+    "qva_batch_rounds": (_I, [_P]),
+    "qva_batch_launches": (_I, [_P]),
+    "qva_batch_tiles": (_I64, [_P]),
+    "qva_batch_destroy": (_I, [_P]),
 }
 
 _lib = None

@@ -2,8 +2,11 @@
 // kernel enqueueing.  Declared in include/qva.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <stdint.h>
+#include <tuple>
 #include <vector>
 
 #include "qva.h"
@@ -980,3 +983,287 @@ int grad_common(const qva_problem* P, const double* gammas_dev, const double* ts
 }
 
 }  // namespace
+
+// ----------------------------------------------------------------- batched
+struct qva_batch_plan_s {
+    struct Group {
+        int first, count, kind, mode, col_bits;
+    };
+    std::vector<BatchInst> inst;
+    std::vector<BatchPass> pass;
+    std::vector<BatchItem> items;
+    std::vector<Group> groups;
+    std::vector<size_t> fpart_off, slots_off;  // per instance, from the scratch start
+    size_t off_inst = 0, off_pass = 0, off_items = 0, off_scratch = 0, total = 0;
+    int rounds = 0;
+    int64_t tiles_total = 0;
+    void* uploaded = nullptr;
+};
+
+namespace {
+
+int batch_check_item(const qva_batch_item& it)
+{
+    if (it.n_qubits < 12 || it.n_qubits > 30)
+        return QVA_ERR_SIZE;
+    if (it.p < 1 || it.p > QVA_BATCH_MAX_DEPTH)
+        return QVA_ERR_SIZE;
+    if (!it.q || !it.gammas || !it.ts || !it.psi || !it.chi || !it.out_f || !it.dgammas || !it.dts)
+        return QVA_ERR_ARG;
+    if (!aligned(it.q, 8) || !aligned(it.gammas, 8) || !aligned(it.ts, 8) || !aligned(it.psi, 16) ||
+        !aligned(it.chi, 16) || !aligned(it.out_f, 8) || !aligned(it.dgammas, 8) || !aligned(it.dts, 8))
+        return QVA_ERR_ALIGN;
+    if (it.psi == it.chi)
+        return QVA_ERR_ARG;
+    return QVA_OK;
+}
+
+// Passes of one instance in execution order (forward, turn, backward, reduce).
+std::vector<BatchPass> batch_passes(const qva_batch_item& it)
+{
+    std::vector<BatchPass> out;
+    if (it.n_qubits == kTileBits) {
+        out.push_back({BP_WHOLE, 0, 0, 0, -1, -1, -1, -1, -1, -1});
+        return out;
+    }
+    qva_problem P{QVA_MIX_X, it.n_qubits, it.q, nullptr, 0};
+    const std::vector<XGroup> groups = x_groups(it.n_qubits);
+    for (const GLaunch& l : grad_launches(&P, it.p)) {
+        BatchPass b{};
+        b.t1 = l.t1;
+        b.t2 = l.t2;
+        b.gamma = l.gamma;
+        b.slot_t1 = l.slot_t1;
+        b.slot_g = l.slot_g;
+        b.slot_t2 = l.slot_t2;
+        b.mode = l.mode;
+        if (l.group >= 0) {
+            b.k = groups[l.group].k;
+            b.col_bits = groups[l.group].col_bits;
+        }
+        switch (l.kind) {
+        case QVA_PASS_FIRST:
+        case QVA_PASS_MIDDLE:
+        case QVA_PASS_BOUNDARY:
+            b.kind = BP_FWD;
+            break;
+        case QVA_PASS_GRAD_TURN:
+        case QVA_PASS_GRAD_MID:
+        case QVA_PASS_GRAD_BOUND:
+        case QVA_PASS_GRAD_FINAL:
+            b.kind = BP_BWD;
+            break;
+        case QVA_PASS_GRAD_REDUCE:
+            b.kind = BP_REDUCE;
+            break;
+        default:  // the f reduction is part of the per-instance reduce
+            continue;
+        }
+        out.push_back(b);
+    }
+    return out;
+}
+
+int64_t pass_tiles(const BatchPass& b, int n)
+{
+    return (b.kind == BP_FWD || b.kind == BP_BWD) ? (int64_t(1) << (n - kTileBits)) : 1;
+}
+
+}  // namespace
+
+extern "C" {
+
+int qva_batch_create(const qva_batch_item* items, int count, int align, qva_batch_plan* out)
+{
+    if (!out || !items || count < 1)
+        return QVA_ERR_ARG;
+    if (align != QVA_BATCH_ALIGN_START && align != QVA_BATCH_ALIGN_END && align != QVA_BATCH_ALIGN_SPREAD)
+        return QVA_ERR_ARG;
+    for (int i = 0; i < count; ++i) {
+        int st = batch_check_item(items[i]);
+        if (st != QVA_OK)
+            return st;
+    }
+    qva_batch_plan_s* B = new qva_batch_plan_s();
+    std::vector<std::vector<BatchPass>> per(count);
+    std::vector<int64_t> load_of(count);
+    int maxpass = 0;
+    for (int i = 0; i < count; ++i) {
+        per[i] = batch_passes(items[i]);
+        maxpass = std::max(maxpass, (int)per[i].size());
+        int64_t l = 0;
+        for (const BatchPass& b : per[i])
+            l += pass_tiles(b, items[i].n_qubits);
+        load_of[i] = l;
+    }
+    // start round of every instance
+    std::vector<int> start(count, 0);
+    int R = maxpass;
+    if (align == QVA_BATCH_ALIGN_END) {
+        for (int i = 0; i < count; ++i)
+            start[i] = maxpass - (int)per[i].size();
+    } else if (align == QVA_BATCH_ALIGN_SPREAD) {
+        // largest instances first; each takes the offset that keeps the
+        // busiest round least loaded (ties: earliest)
+        std::vector<int> order(count);
+        for (int i = 0; i < count; ++i)
+            order[i] = i;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return load_of[a] > load_of[b]; });
+        std::vector<int64_t> round_load(R, 0);
+        for (int i : order) {
+            const int np = (int)per[i].size();
+            int best = 0;
+            int64_t best_peak = -1;
+            for (int s0 = 0; s0 + np <= R; ++s0) {
+                int64_t peak = 0;
+                for (int j = 0; j < np; ++j)
+                    peak = std::max(peak, round_load[s0 + j] + pass_tiles(per[i][j], items[i].n_qubits));
+                if (best_peak < 0 || peak < best_peak) {
+                    best_peak = peak;
+                    best = s0;
+                }
+            }
+            start[i] = best;
+            for (int j = 0; j < np; ++j)
+                round_load[best + j] += pass_tiles(per[i][j], items[i].n_qubits);
+        }
+    }
+    B->rounds = R;
+    // instance and pass tables, per-instance scratch layout
+    size_t scratch = 0;
+    for (int i = 0; i < count; ++i) {
+        const qva_batch_item& it = items[i];
+        BatchInst d{};
+        d.psi = reinterpret_cast<double2*>(it.psi);
+        d.chi = reinterpret_cast<double2*>(it.chi);
+        d.q = it.q;
+        d.gammas = it.gammas;
+        d.ts = it.ts;
+        d.out_f = it.out_f;
+        d.dgammas = it.dgammas;
+        d.dts = it.dts;
+        d.n = it.n_qubits;
+        d.p = it.p;
+        d.tiles = it.n_qubits > kTileBits ? (int64_t(1) << (it.n_qubits - kTileBits)) : 1;
+        d.G = (int)x_groups(it.n_qubits).size();
+        d.nslots = it.n_qubits > kTileBits ? it.p * (d.G + 1) : 0;
+        d.pass_off = (int)B->pass.size();
+        d.npass = (int)per[i].size();
+        B->pass.insert(B->pass.end(), per[i].begin(), per[i].end());
+        B->fpart_off.push_back(scratch);
+        scratch = align256(scratch + (size_t)d.tiles * sizeof(double2));
+        B->slots_off.push_back(scratch);
+        scratch = align256(scratch + (size_t)d.nslots * (size_t)d.tiles * sizeof(double));
+        B->inst.push_back(d);
+    }
+    // work items, ordered by (round, kind, mode, tile geometry, instance, tile)
+    using Key = std::tuple<int, int, int, int, int, int>;
+    std::vector<std::pair<Key, BatchItem>> all;
+    for (int i = 0; i < count; ++i) {
+        for (int j = 0; j < (int)per[i].size(); ++j) {
+            const BatchPass& b = per[i][j];
+            const int64_t nt = pass_tiles(b, items[i].n_qubits);
+            for (int64_t tl = 0; tl < nt; ++tl)
+                all.push_back({Key(start[i] + j, b.kind, b.mode, b.col_bits, i, (int)tl),
+                               BatchItem{i, j, (int)tl, 0}});
+        }
+    }
+    std::sort(all.begin(), all.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+    for (size_t x = 0; x < all.size(); ++x) {
+        const Key& k = all[x].first;
+        B->items.push_back(all[x].second);
+        const bool same = !B->groups.empty() && x > 0 && std::get<0>(all[x - 1].first) == std::get<0>(k) &&
+                          std::get<1>(all[x - 1].first) == std::get<1>(k) &&
+                          std::get<2>(all[x - 1].first) == std::get<2>(k) &&
+                          std::get<3>(all[x - 1].first) == std::get<3>(k);
+        if (same)
+            B->groups.back().count += 1;
+        else
+            B->groups.push_back({(int)x, 1, std::get<1>(k), std::get<2>(k), std::get<3>(k)});
+    }
+    B->tiles_total = (int64_t)B->items.size();
+    size_t off = 0;
+    B->off_inst = off;
+    off = align256(off + B->inst.size() * sizeof(BatchInst));
+    B->off_pass = off;
+    off = align256(off + B->pass.size() * sizeof(BatchPass));
+    B->off_items = off;
+    off = align256(off + B->items.size() * sizeof(BatchItem));
+    B->off_scratch = off;
+    B->total = off + scratch;
+    *out = B;
+    return QVA_OK;
+}
+
+size_t qva_batch_workspace_bytes(qva_batch_plan plan) { return plan ? plan->total : 0; }
+
+int qva_batch_rounds(qva_batch_plan plan) { return plan ? plan->rounds : QVA_ERR_ARG; }
+
+int qva_batch_launches(qva_batch_plan plan) { return plan ? (int)plan->groups.size() : QVA_ERR_ARG; }
+
+int64_t qva_batch_tiles(qva_batch_plan plan) { return plan ? plan->tiles_total : QVA_ERR_ARG; }
+
+int qva_batch_upload(qva_batch_plan plan, void* work, size_t work_bytes, void* stream)
+{
+    if (!plan || !work)
+        return QVA_ERR_ARG;
+    if (work_bytes < plan->total)
+        return QVA_ERR_WORKSPACE;
+    if (!aligned(work, 256))
+        return QVA_ERR_ALIGN;
+    char* base = reinterpret_cast<char*>(work);
+    std::vector<BatchInst> inst = plan->inst;
+    for (size_t i = 0; i < inst.size(); ++i) {
+        inst[i].fpart = reinterpret_cast<double2*>(base + plan->off_scratch + plan->fpart_off[i]);
+        inst[i].slots = reinterpret_cast<double*>(base + plan->off_scratch + plan->slots_off[i]);
+    }
+    std::vector<char> host(plan->off_scratch, 0);
+    std::memcpy(host.data() + plan->off_inst, inst.data(), inst.size() * sizeof(BatchInst));
+    std::memcpy(host.data() + plan->off_pass, plan->pass.data(), plan->pass.size() * sizeof(BatchPass));
+    std::memcpy(host.data() + plan->off_items, plan->items.data(), plan->items.size() * sizeof(BatchItem));
+    hipStream_t s = as_stream(stream);
+    if (hipMemcpyAsync(work, host.data(), host.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+        return QVA_ERR_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess)
+        return QVA_ERR_HIP;
+    plan->uploaded = work;
+    return QVA_OK;
+}
+
+int qva_batch_grad(qva_batch_plan plan, void* work, size_t work_bytes, void* stream)
+{
+    if (!plan || !work)
+        return QVA_ERR_ARG;
+    if (work != plan->uploaded || work_bytes < plan->total)
+        return QVA_ERR_WORKSPACE;
+    char* base = reinterpret_cast<char*>(work);
+    BatchRoundParams R;
+    R.inst = reinterpret_cast<const BatchInst*>(base + plan->off_inst);
+    R.pass = reinterpret_cast<const BatchPass*>(base + plan->off_pass);
+    R.items = reinterpret_cast<const BatchItem*>(base + plan->off_items);
+    hipStream_t s = as_stream(stream);
+    for (const auto& gr : plan->groups) {
+        R.first = gr.first;
+        if (launch_batch_group(R, gr.kind, gr.mode, gr.col_bits, gr.count, s) != hipSuccess)
+            return QVA_ERR_HIP;
+    }
+    return QVA_OK;
+}
+
+int qva_batch_sgd(qva_batch_plan plan, double lr, void* work, size_t work_bytes, void* stream)
+{
+    if (!plan || !work)
+        return QVA_ERR_ARG;
+    if (work != plan->uploaded || work_bytes < plan->total)
+        return QVA_ERR_WORKSPACE;
+    const BatchInst* inst = reinterpret_cast<const BatchInst*>(reinterpret_cast<char*>(work) + plan->off_inst);
+    return hip_status(launch_batch_sgd(inst, (int)plan->inst.size(), 0, lr, as_stream(stream)));
+}
+
+int qva_batch_destroy(qva_batch_plan plan)
+{
+    delete plan;
+    return QVA_OK;
+}
+
+}  // extern "C"

@@ -17,7 +17,7 @@
 //     undoes the phase.
 // Each (parameter, qubit group, tile) partial is written by exactly one pass
 // and reduced afterwards in a fixed order, so results are deterministic.
-#include "qva_tile.h"
+#include "qva_passes.h"
 
 // Two vectors plus per-element twiddles need more than the 256 registers a
 // wave gets at two waves per SIMD; at one wave per SIMD the overflow stays
@@ -33,178 +33,7 @@ namespace qva {
 namespace {
 
 using namespace tile;
-
-// Deterministic block sum of K doubles (every thread gets the sums).
-// `red` holds K * (blockDim.x / 64) doubles.
-template <int K>
-__device__ __forceinline__ void block_sum_k(double (&v)[K], double* red)
-{
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-#pragma unroll
-    for (int i = 0; i < K; ++i)
-        v[i] = wave_sum(v[i]);
-    __syncthreads();
-    if (lane == 0)
-#pragma unroll
-        for (int i = 0; i < K; ++i)
-            red[K * wid + i] = v[i];
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < K; ++i) {
-        double s = 0.0;
-        for (int w = 0; w < nw; ++w)
-            s += red[K * w + i];
-        v[i] = s;
-    }
-}
-
-// Im(conj(chi_a) phi_b + conj(chi_b) phi_a)
-__device__ __forceinline__ double im_pair(double2 a, double2 b, double2 ca, double2 cb)
-{
-    double s = ca.x * b.y;
-    s = fma(-ca.y, b.x, s);
-    s = fma(cb.x, a.y, s);
-    s = fma(-cb.y, a.x, s);
-    return s;
-}
-
-// exp(-i th X) with (c, s) = (cos th, sin th) applied to the pair (a, b).
-__device__ __forceinline__ void rot_pair(double2& a, double2& b, double c, double s)
-{
-    const double2 a0 = a, b0 = b;
-    a = make_double2(fma(c, a0.x, s * b0.y), fma(c, a0.y, -s * b0.x));
-    b = make_double2(fma(c, b0.x, s * a0.y), fma(c, b0.y, -s * a0.x));
-}
-
-// Rotate both vectors on the target register bits of MASK, accumulating
-// Im <chi|X_i|phi> over those qubits first.
-template <int MASK>
-__device__ __forceinline__ void rot2_regs(double2 (&p)[kRegs], double2 (&x)[kRegs], double c, double s,
-                                          double& acc)
-{
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        if (!((MASK >> j) & 1))
-            continue;
-#pragma unroll
-        for (int r = 0; r < kRegs; ++r) {
-            if (r & (1 << j))
-                continue;
-            const int r1 = r | (1 << j);
-            acc += im_pair(p[r], p[r1], x[r], x[r1]);
-            rot_pair(p[r], p[r1], c, s);
-            rot_pair(x[r], x[r1], c, s);
-        }
-    }
-}
-
-template <int FROM, int TO>
-__device__ __forceinline__ void exchange2(double2 (&p)[kRegs], double2 (&x)[kRegs], double2* lds, int t)
-{
-    exchange<FROM, TO>(p, lds, t);
-    exchange<FROM, TO>(x, lds, t);
-}
-
-// Rotations of every target qubit on both vectors; A -> last_layout<C>().
-template <int C>
-__device__ __forceinline__ void mix2_forward(double2 (&p)[kRegs], double2 (&x)[kRegs], double2* lds, int t,
-                                             double c, double s, double& acc)
-{
-    rot2_regs<target_mask<C, LA>()>(p, x, c, s, acc);
-    if constexpr (C < 4) {
-        exchange2<LA, LC>(p, x, lds, t);
-        rot2_regs<target_mask<C, LC>()>(p, x, c, s, acc);
-        exchange2<LC, LB>(p, x, lds, t);
-        rot2_regs<target_mask<C, LB>()>(p, x, c, s, acc);
-    } else if constexpr (C < 8) {
-        exchange2<LA, LB>(p, x, lds, t);
-        rot2_regs<target_mask<C, LB>()>(p, x, c, s, acc);
-    }
-}
-
-// Same, last_layout<C>() -> A.
-template <int C>
-__device__ __forceinline__ void mix2_reverse(double2 (&p)[kRegs], double2 (&x)[kRegs], double2* lds, int t,
-                                             double c, double s, double& acc)
-{
-    if constexpr (C < 4) {
-        rot2_regs<target_mask<C, LB>()>(p, x, c, s, acc);
-        exchange2<LB, LC>(p, x, lds, t);
-        rot2_regs<target_mask<C, LC>()>(p, x, c, s, acc);
-        exchange2<LC, LA>(p, x, lds, t);
-    } else if constexpr (C < 8) {
-        rot2_regs<target_mask<C, LB>()>(p, x, c, s, acc);
-        exchange2<LB, LA>(p, x, lds, t);
-    }
-    rot2_regs<target_mask<C, LA>()>(p, x, c, s, acc);
-}
-
-// (cos, sin) of the inverse rotation exp(+i t X) = exp(-i (-t) X)
-__device__ __forceinline__ void inv_cs(double t, double& c, double& s)
-{
-    double sn, cs;
-    sincos_red(t, &sn, &cs);
-    c = cs;
-    s = -sn;
-}
-
-// sum_j q_j Im(conj(chi_j) phi_j) over the registers of layout L, and the
-// inverse phase exp(+i gamma q) applied to both vectors.
-template <int L, bool SCALE>
-__device__ __forceinline__ double unphase2(double2 (&p)[kRegs], double2 (&x)[kRegs], const double* q,
-                                           const TileMap& g, int t, double gamma, double scale)
-{
-    double qq[kRegs];
-#pragma unroll
-    for (int r = 0; r < kRegs; ++r)
-        qq[r] = ld_nt(q + g(elem<L>(t, r)));
-    double acc = 0.0;
-#pragma unroll
-    for (int r = 0; r < kRegs; ++r) {
-        if constexpr (SCALE) {
-            p[r] = make_double2(p[r].x * scale, p[r].y * scale);
-            x[r] = make_double2(x[r].x * scale, x[r].y * scale);
-        }
-        acc = fma(qq[r], x[r].x * p[r].y - x[r].y * p[r].x, acc);
-        const double2 ph = expmi(-gamma * qq[r]);
-        p[r] = cmul(p[r], ph);
-        x[r] = cmul(x[r], ph);
-        QVA_SCHED_FENCE();
-    }
-    return acc;
-}
-
-template <int L>
-__device__ __forceinline__ void store2(const double2 (&p)[kRegs], const double2 (&x)[kRegs],
-                                       const GradPassParams& P, const TileMap& g, int t)
-{
-    store_tile<L>(p, P.phi, g, t, 1.0);
-    store_tile<L>(x, P.chi, g, t, 1.0);
-}
-
-template <int L>
-__device__ __forceinline__ void load2(double2 (&p)[kRegs], double2 (&x)[kRegs], const GradPassParams& P,
-                                      const TileMap& g, int t)
-{
-    load_tile<L>(p, P.phi, g, t);
-    load_tile<L>(x, P.chi, g, t);
-}
-
-// Write the block sums of the accumulators to their per-tile slots.
-__device__ __forceinline__ void write_slots(const GradPassParams& P, double a1, double ag, double a2,
-                                            double* red)
-{
-    double v[3] = {a1, ag, a2};
-    block_sum_k<3>(v, red);
-    if (threadIdx.x == 0) {
-        if (P.slot_t1)
-            P.slot_t1[blockIdx.x] = v[0];
-        if (P.slot_g)
-            P.slot_g[blockIdx.x] = v[1];
-        if (P.slot_t2)
-            P.slot_t2[blockIdx.x] = v[2];
-    }
-}
+using namespace passes;
 
 // ------------------------------------------------ hypercube-mixer passes
 template <int C, int MODE>
@@ -212,72 +41,7 @@ __global__ __launch_bounds__(kThreads, QVA_GRADX_WAVES) void gradx_kernel(GradPa
 {
     __shared__ double2 lds[1 << kTileBits];
     __shared__ double red[4 * (kThreads / 64)];
-    const int t = threadIdx.x;
-    const TileMap g = tile_map(blockIdx.x, P.k, C);
-    double2 p[kRegs], x[kRegs];
-    double a1 = 0.0, ag = 0.0, a2 = 0.0;
-
-    if constexpr (MODE == GMODE_TURN) {
-        // last forward group of the last layer, <Q>, chi = Q psi_p, then the
-        // inverse of the same rotations on both vectors
-        const double tt = angle_value(P.t1);
-        const MixCoef m = mix_coef(tt);
-        double c, s;
-        inv_cs(tt, c, s);
-        load_tile<LA>(p, P.phi, g, t);
-        if (m.tanform)
-            mix_forward<C, true>(p, lds, t, m.k);
-        else
-            mix_forward<C, false>(p, lds, t, m.k);
-        const double2 S = cpow_int(m.sigma, P.n);
-        constexpr int L = last_layout<C>();
-        double qq[kRegs];
-#pragma unroll
-        for (int r = 0; r < kRegs; ++r)
-            qq[r] = ld_nt(P.q + g(elem<L>(t, r)));
-        double f = 0.0, nr = 0.0;
-#pragma unroll
-        for (int r = 0; r < kRegs; ++r) {
-            p[r] = cmul(p[r], S);
-            const double a = p[r].x * p[r].x + p[r].y * p[r].y;
-            f = fma(a, qq[r], f);
-            nr += a;
-            x[r] = make_double2(qq[r] * p[r].x, qq[r] * p[r].y);
-        }
-        double fv[2] = {f, nr};
-        block_sum_k<2>(fv, red);
-        if (t == 0)
-            P.fpart[blockIdx.x] = make_double2(fv[0], fv[1]);
-        mix2_reverse<C>(p, x, lds, t, c, s, a1);
-        write_slots(P, a1, 0.0, 0.0, red);
-        store2<LA>(p, x, P, g, t);
-    } else {
-        // every angle and its sine/cosine before the data is loaded: computed
-        // mid-pass they extend register live ranges across the whole tile
-        double c, s, c2 = 1.0, s2 = 0.0, gam = 0.0;
-        inv_cs(angle_value(P.t1), c, s);
-        if constexpr (MODE == GMODE_BOUND)
-            inv_cs(angle_value(P.t2), c2, s2);
-        if constexpr (MODE != GMODE_MID)
-            gam = angle_value(P.gamma);
-        load2<LA>(p, x, P, g, t);
-        mix2_forward<C>(p, x, lds, t, c, s, a1);
-        if constexpr (MODE == GMODE_MID) {
-            write_slots(P, a1, 0.0, 0.0, red);
-            store2<last_layout<C>()>(p, x, P, g, t);
-        } else {
-            // the forward pass applied the layer's scalar factor together with
-            // the phase; the direct-form inverse rotations need none
-            ag = unphase2<last_layout<C>(), false>(p, x, P.q, g, t, gam, 1.0);
-            if constexpr (MODE == GMODE_BOUND) {
-                mix2_reverse<C>(p, x, lds, t, c2, s2, a2);
-                write_slots(P, a1, ag, a2, red);
-                store2<LA>(p, x, P, g, t);
-            } else {  // GMODE_FINAL
-                write_slots(P, a1, ag, 0.0, red);
-            }
-        }
-    }
+    gradx_tile<C, MODE>(P, blockIdx.x, lds, red);
 }
 
 // ------------------------------------------------ circulant-mixer passes
@@ -428,7 +192,7 @@ __global__ __launch_bounds__(kThreads, QVA_GRADF_WAVES) void gradf_kernel(GradPa
             x[r] = cmul(x[r], d);
             QVA_SCHED_FENCE();
         }
-        write_slots(P, a1 * invN, 0.0, 0.0, red);
+        write_slots(P, a1 * invN, 0.0, 0.0, red, tile);
         dit_tile2<C>(p, x, lds, g, t);
         store2<LA>(p, x, P, g, t);
     } else {  // GMODE_BOUND, GMODE_FINAL
@@ -436,11 +200,11 @@ __global__ __launch_bounds__(kThreads, QVA_GRADF_WAVES) void gradf_kernel(GradPa
         dit_tile2<C>(p, x, lds, g, t);
         const double ag = unphase2<LA, true>(p, x, P.q, g, t, gam, invN);
         if constexpr (MODE == GMODE_BOUND) {
-            write_slots(P, 0.0, ag, 0.0, red);
+            write_slots(P, 0.0, ag, 0.0, red, tile);
             dif_tile2<C>(p, x, lds, g, t);
             store2<dif_last<C>()>(p, x, P, g, t);
         } else {
-            write_slots(P, 0.0, ag, 0.0, red);
+            write_slots(P, 0.0, ag, 0.0, red, tile);
         }
     }
 }

@@ -187,4 +187,56 @@ hipError_t launch_small_grad(const SmallGradParams& P, hipStream_t s);
 hipError_t launch_grad_reduce(const double* slots, int nslots, int64_t tiles, double* sums, int p, int G,
                               double* dgammas, double* dts, hipStream_t s);
 
+// ---------------------------------------------------------------- batched
+// Many independent hypercube-mixer instances, forward + adjoint: the passes
+// of every instance are grouped into rounds (round r = pass r of every
+// instance that has one) and one launch runs all tiles of a round.
+enum : int {
+    BP_FWD = 0,     // forward tile pass (XMODE_*)
+    BP_BWD = 1,     // backward tile pass (GMODE_*)
+    BP_WHOLE = 2,   // n = 12: whole forward + adjoint in one workgroup
+    BP_REDUCE = 3   // per-instance fixed-order sums: f and the gradient
+};
+
+struct BatchInst {
+    double2* psi;
+    double2* chi;
+    const double* q;
+    double* gammas;
+    double* ts;
+    double* out_f;
+    double* dgammas;
+    double* dts;
+    double2* fpart;   // per-tile (f, norm) partials
+    double* slots;    // nslots x tiles partials
+    int64_t tiles;
+    int n, p, G, nslots, pass_off, npass;
+};
+
+struct BatchPass {
+    int kind;       // BP_*
+    int mode;       // XMODE_* or GMODE_*
+    int k, col_bits;
+    int t1, t2, gamma;             // layers of the angles, or -1
+    int slot_t1, slot_g, slot_t2;  // slot indices, or -1
+};
+
+struct BatchItem {
+    int inst;
+    int pass;
+    int tile;
+    int pad;
+};
+
+struct BatchRoundParams {
+    const BatchInst* inst;
+    const BatchPass* pass;
+    const BatchItem* items;
+    int first;    // first item of the round
+};
+
+hipError_t launch_batch_group(const BatchRoundParams& R, int kind, int mode, int col_bits, int nitems,
+                              hipStream_t s);
+hipError_t launch_batch_sgd(const BatchInst* inst, int count, int max_p, double lr, hipStream_t s);
+
 }  // namespace qva

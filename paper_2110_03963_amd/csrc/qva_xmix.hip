@@ -13,104 +13,20 @@
 // Elementwise work is fused into the passes: the initial state, the phase
 // exp(-i gamma q_j) (eq. phase_shift_qaoa), and the expectation sum
 // |psi_j|^2 q_j (eq. objective_generic).
-#include "qva_tile.h"
+#include "qva_passes.h"
 
 namespace qva {
 namespace {
 
 using namespace tile;
-
-// psi <- scale * exp(-i gamma q) psi in layout L
-template <int L>
-__device__ __forceinline__ void phase_regs(double2 (&v)[kRegs], const double* q, const TileMap& g,
-                                           int t, double gamma, double2 scale)
-{
-    double qq[kRegs];
-#pragma unroll
-    for (int r = 0; r < kRegs; ++r)
-        qq[r] = ld_nt(q + g(elem<L>(t, r)));
-#pragma unroll
-    for (int r = 0; r < kRegs; ++r)
-        v[r] = cmul(v[r], cmul(scale, expmi(gamma * qq[r])));
-        QVA_SCHED_FENCE();
-}
-
-template <int L, int FLAGS>
-__device__ __forceinline__ void tail(double2 (&v)[kRegs], const XPassParams& P, const TileMap& g,
-                                     int t, double2 fs, double* red)
-{
-    if constexpr (FLAGS & XP_EXPECT) {
-        double qq[kRegs];
-#pragma unroll
-        for (int r = 0; r < kRegs; ++r)
-            qq[r] = ld_nt(P.q + g(elem<L>(t, r)));
-        double f = 0.0, nr = 0.0;
-#pragma unroll
-        for (int r = 0; r < kRegs; ++r) {
-            double a = v[r].x * v[r].x + v[r].y * v[r].y;
-            f = fma(a, qq[r], f);
-            nr += a;
-        }
-        const double s2 = fs.x * fs.x + fs.y * fs.y;
-        double2 tot = block_sum2(f * s2, nr * s2, red);
-        if (t == 0)
-            P.partials[blockIdx.x] = tot;
-    }
-    if constexpr (FLAGS & XP_STORE) {
-        constexpr bool sc = FLAGS & XP_FINAL_SCALE;
-#pragma unroll
-        for (int r = 0; r < kRegs; ++r)
-            st_nt(P.psi + g(elem<L>(t, r)), sc ? cmul(v[r], fs) : v[r]);
-    }
-}
+using namespace passes;
 
 template <int C, int FLAGS>
 __global__ __launch_bounds__(kThreads, 2) void xpass_kernel(XPassParams P)
 {
     __shared__ double2 lds[1 << kTileBits];
     __shared__ double red[2 * (kThreads / 64)];
-    const int t = threadIdx.x;
-    const int64_t tile = blockIdx.x;
-    const TileMap g = tile_map(tile, P.k, C);
-
-    double2 v[kRegs];
-    constexpr int flags = FLAGS;
-    if constexpr (flags & XP_INIT) {
-        const double a0 = 1.0 / sqrt((double)(int64_t(1) << P.n));
-#pragma unroll
-        for (int r = 0; r < kRegs; ++r)
-            v[r] = make_double2(a0, 0.0);
-    } else {
-#pragma unroll
-        for (int r = 0; r < kRegs; ++r)
-            v[r] = ld_nt(P.psi + g(elem<LA>(t, r)));
-    }
-    if constexpr (flags & XP_PHASE_PRE)
-        phase_regs<LA>(v, P.q, g, t, angle_value(P.phase), make_double2(1.0, 0.0));
-
-    double2 S1 = make_double2(1.0, 0.0);
-    if constexpr (flags & XP_MIX1) {
-        const MixCoef m = mix_coef(angle_value(P.mix1));
-        if (m.tanform)
-            mix_forward<C, true>(v, lds, t, m.k);
-        else
-            mix_forward<C, false>(v, lds, t, m.k);
-        S1 = cpow_int(m.sigma, P.n);
-    }
-    if constexpr (flags & XP_PHASE_MID)
-        phase_regs<last_layout<C>()>(v, P.q, g, t, angle_value(P.phase), S1);
-    if constexpr (flags & XP_MIX2) {
-        const MixCoef m = mix_coef(angle_value(P.mix2));
-        if (m.tanform)
-            mix_reverse<C, true>(v, lds, t, m.k);
-        else
-            mix_reverse<C, false>(v, lds, t, m.k);
-    }
-    const double2 fs = (flags & XP_FINAL_SCALE) ? S1 : make_double2(1.0, 0.0);
-    if constexpr ((flags & XP_MIX2) || !(flags & XP_MIX1))
-        tail<LA, flags>(v, P, g, t, fs, red);
-    else
-        tail<last_layout<C>(), flags>(v, P, g, t, fs, red);
+    xpass_tile<C, FLAGS>(P, blockIdx.x, lds, red);
 }
 
 // ---------------------------------------------------------------------------

@@ -244,3 +244,109 @@ class QVAExpectation(torch.autograd.Function):
 def expectation_value(problem: Problem, gammas: torch.Tensor, ts: torch.Tensor) -> torch.Tensor:
     """Differentiable f(gamma, t) (float64 device tensors in, 0-d tensor out)."""
     return QVAExpectation.apply(gammas, ts, problem)
+
+
+# ------------------------------------------------------------------ batched
+_ALIGN = {"start": _lib.QVA_BATCH_ALIGN_START, "end": _lib.QVA_BATCH_ALIGN_END,
+          "spread": _lib.QVA_BATCH_ALIGN_SPREAD}
+
+
+class Batch:
+    """Many independent QAOA instances (hypercube mixer): f and the adjoint
+    gradient of all of them with one call, and a gradient-descent step.
+
+    qs: list of device float64 quality vectors (lengths 2^n, 12 <= n <= 30);
+    gammas, ts: lists of per-instance angle sequences (same length p_i).
+    The angles live in two flat device tensors (`gammas`, `ts`) updated in
+    place by `sgd`; results land in `f` (one per instance) and the flat
+    `dgammas`, `dts` tensors (instance i at `offsets[i]:offsets[i] + p[i]`).
+    `grad()` and `sgd()` only enqueue kernels on the current stream, so both
+    can be captured into a torch.cuda.CUDAGraph and replayed.
+    """
+
+    def __init__(self, qs, gammas, ts, align: str = "spread"):
+        if not (len(qs) == len(gammas) == len(ts)) or not qs:
+            raise ValueError("one q, gammas and ts per instance")
+        dev = qs[0].device
+        self.count = len(qs)
+        self.n = []
+        self.p = [len(g) for g in gammas]
+        self.offsets = []
+        off = 0
+        for g, t in zip(gammas, ts):
+            if len(g) != len(t):
+                raise ValueError("one gamma and one t per layer")
+            self.offsets.append(off)
+            off += len(g)
+        self.gammas = torch.cat([_angles(g, dev) for g in gammas]).contiguous()
+        self.ts = torch.cat([_angles(t, dev) for t in ts]).contiguous()
+        self.dgammas = torch.zeros_like(self.gammas)
+        self.dts = torch.zeros_like(self.ts)
+        self.f = torch.zeros(self.count, dtype=torch.float64, device=dev)
+        self.qs = []
+        amp = 0
+        amp_off = []
+        for q in qs:
+            _need(q, torch.float64, "q")
+            self.qs.append(q)
+            self.n.append(_log2(q.numel()))
+            amp_off.append(amp)
+            amp += q.numel()
+        self.psi = torch.empty(amp, dtype=torch.complex128, device=dev)
+        self.chi = torch.empty(amp, dtype=torch.complex128, device=dev)
+        items = (_lib.QvaBatchItem * self.count)()
+        for i in range(self.count):
+            o, a = self.offsets[i], amp_off[i]
+            items[i] = _lib.QvaBatchItem(
+                self.n[i], self.p[i], self.qs[i].data_ptr(),
+                self.gammas.data_ptr() + 8 * o, self.ts.data_ptr() + 8 * o,
+                self.psi.data_ptr() + 16 * a, self.chi.data_ptr() + 16 * a,
+                self.f.data_ptr() + 8 * i,
+                self.dgammas.data_ptr() + 8 * o, self.dts.data_ptr() + 8 * o)
+        lib = _lib.load()
+        plan = ctypes.c_void_p()
+        _lib.check("qva_batch_create", lib.qva_batch_create(items, self.count, _ALIGN[align],
+                                                            ctypes.byref(plan)))
+        self._plan = plan
+        nbytes = lib.qva_batch_workspace_bytes(plan)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        _lib.check("qva_batch_upload", lib.qva_batch_upload(plan, self.workspace.data_ptr(),
+                                                            nbytes, _stream()))
+
+    @property
+    def rounds(self) -> int:
+        return int(_lib.load().qva_batch_rounds(self._plan))
+
+    @property
+    def launches(self) -> int:
+        return int(_lib.load().qva_batch_launches(self._plan))
+
+    @property
+    def tiles(self) -> int:
+        return int(_lib.load().qva_batch_tiles(self._plan))
+
+    def grad(self) -> None:
+        """Enqueue f and the gradient of every instance."""
+        lib = _lib.load()
+        _lib.check("qva_batch_grad", lib.qva_batch_grad(self._plan, self.workspace.data_ptr(),
+                                                        self.workspace.numel(), _stream()))
+
+    def sgd(self, lr: float) -> None:
+        """Enqueue gammas -= lr * dgammas, ts -= lr * dts."""
+        lib = _lib.load()
+        _lib.check("qva_batch_sgd", lib.qva_batch_sgd(self._plan, float(lr), self.workspace.data_ptr(),
+                                                      self.workspace.numel(), _stream()))
+
+    def instance(self, i: int):
+        """(f, dgammas, dts) of instance i as device tensors (views)."""
+        o, p = self.offsets[i], self.p[i]
+        return self.f[i], self.dgammas[o:o + p], self.dts[o:o + p]
+
+    def __del__(self):
+        plan = getattr(self, "_plan", None)
+        if plan is not None and plan.value:
+            try:
+                _lib.load().qva_batch_destroy(plan)
+            except Exception:
+                pass
+            self._plan = None

@@ -216,3 +216,56 @@ def test_grad_plan_circulant(lib, n, p):
     fwd = plan[:kinds.index(18)]
     assert sum(x.kind == 10 for x in fwd) == sum(x.kind == 23 for x in back)
     assert sum(x.kind == 12 for x in fwd) == sum(x.kind == 22 for x in back)
+
+
+def _batch_items(specs):
+    arr = (_lib.QvaBatchItem * len(specs))()
+    for i, (n, p) in enumerate(specs):
+        arr[i] = _lib.QvaBatchItem(n, p, FAKE, FAKE, FAKE, FAKE, FAKE + 4096, FAKE, FAKE, FAKE)
+    return arr
+
+
+@pytest.mark.parametrize("align", [0, 1, 2])
+def test_batch_plan_counts(lib, align):
+    """Host-side batch plan: every tile of every pass appears once; rounds are
+    the deepest instance's pass count; n = 12 instances are single items."""
+    specs = [(12, 3), (13, 1), (14, 2), (17, 5), (21, 8), (22, 4), (12, 1)]
+    arr = _batch_items(specs)
+    plan = ctypes.c_void_p()
+    assert lib.qva_batch_create(arr, len(specs), align, ctypes.byref(plan)) == 0
+    try:
+        def npass(n, p):
+            if n == 12:
+                return 1
+            P = 2 if n <= 21 else 3
+            m = p * (P - 1) + 1  # forward passes of the evolution
+            return 2 * m  # m - 1 forward, the turnaround, m - 1 backward, the reduce
+
+        def tiles(n, p):
+            if n == 12:
+                return 1
+            P = 2 if n <= 21 else 3
+            m = p * (P - 1) + 1
+            return (2 * m - 1) * (1 << (n - 12)) + 1
+
+        assert lib.qva_batch_rounds(plan) == max(npass(n, p) for n, p in specs)
+        assert lib.qva_batch_tiles(plan) == sum(tiles(n, p) for n, p in specs)
+        assert lib.qva_batch_launches(plan) >= lib.qva_batch_rounds(plan)
+        assert lib.qva_batch_workspace_bytes(plan) > 0
+    finally:
+        lib.qva_batch_destroy(plan)
+
+
+def test_batch_validation(lib):
+    plan = ctypes.c_void_p()
+    for specs, st in [([(11, 2)], _lib.QVA_ERR_SIZE), ([(31, 2)], _lib.QVA_ERR_SIZE),
+                      ([(14, 0)], _lib.QVA_ERR_SIZE), ([(14, 65)], _lib.QVA_ERR_SIZE)]:
+        assert lib.qva_batch_create(_batch_items(specs), 1, 0, ctypes.byref(plan)) == st
+    arr = _batch_items([(14, 2)])
+    arr[0].psi = arr[0].chi
+    assert lib.qva_batch_create(arr, 1, 0, ctypes.byref(plan)) == _lib.QVA_ERR_ARG
+    arr = _batch_items([(14, 2)])
+    arr[0].psi = FAKE + 8
+    assert lib.qva_batch_create(arr, 1, 0, ctypes.byref(plan)) == _lib.QVA_ERR_ALIGN
+    assert lib.qva_batch_create(_batch_items([(14, 2)]), 1, 7, ctypes.byref(plan)) == _lib.QVA_ERR_ARG
+    assert lib.qva_batch_create(_batch_items([(14, 2)]), 0, 0, ctypes.byref(plan)) == _lib.QVA_ERR_ARG

@@ -237,11 +237,11 @@ def qwoa_portfolio_workload(m: int, p: int, *, seed: int = 0, risk: float = 0.5,
 
 
 def batched_workloads(count: int, *, seed: int, n_range=(12, 22), p_range=(1, 8),
-                      edge_prob: float = 0.4) -> list[Workload]:
+                      edge_prob: float = 0.4, build_q: bool = True) -> list[Workload]:
     """Independent QAOA MaxCut instances with n ~ U{n_range}, p ~ U{p_range}.
 
     Instance i draws its own (n, p) and then graph -> weights -> gammas -> ts
-    from default_rng(seed + i).
+    from default_rng(seed + i).  With build_q=False q is left as None.
     """
     out = []
     for i in range(count):
@@ -251,7 +251,7 @@ def batched_workloads(count: int, *, seed: int, n_range=(12, 22), p_range=(1, 8)
         edges = erdos_renyi_edges(n, edge_prob, rng)
         weights = rng.uniform(0.0, 1.0, len(edges))
         gammas, ts = draw_angles(rng, p)
-        q = maxcut_qualities(n, edges, weights)
+        q = maxcut_qualities(n, edges, weights) if build_q else None
         out.append(Workload(name=f"batch{i}", mixer="x", n=n, q=q, gammas=gammas, ts=ts,
                             edges=edges, weights=weights, seed=seed + i))
     return out
