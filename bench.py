@@ -304,6 +304,77 @@ def extra_adjoint(lib, reps: int) -> dict:
             "per_kernel_ms": {k: round(v["ms"], 3) for k, v in sorted(per.items())}}
 
 
+def extra_batch(lib) -> dict:
+    """512 independent QAOA MaxCut instances (n ~ U{12..22}, p ~ U{1..8},
+    G(n, 0.4), weights U(0,1)): f and the adjoint gradient of every instance
+    plus a gradient step, replayed as one captured HIP graph; compared with
+    one qva_grad call per instance."""
+    import torch
+
+    import paper_2110_03963_amd as qva
+    from paper_2110_03963_amd import _lib
+    from paper_2110_03963_amd.autotune import time_batch_grad, tune_batch
+    from workloads import CONFIG_SEEDS, batched_workloads, maxcut_qualities_device
+
+    wls = batched_workloads(512, seed=CONFIG_SEEDS["batch512"], build_q=False)
+    qs = [maxcut_qualities_device(w.n, w.edges, w.weights, "cuda") for w in wls]
+    gs = [w.gammas for w in wls]
+    ts = [w.ts for w in wls]
+    tune = tune_batch(qs, gs, ts, reps=2)
+    b = qva.Batch(qs, gs, ts, align=tune["align"])
+    ms_eager = time_batch_grad(b, reps=3)
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=stream):
+        b.grad()
+        b.sgd(1e-3)
+    torch.cuda.synchronize()
+    graph.replay()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = 5
+    e0.record()
+    for _ in range(reps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_graph = e0.elapsed_time(e1) / reps
+    # one qva_grad per instance, back to back
+    probs = [qva.Problem(q, "x") for q in qs]
+    psi = torch.empty(1 << 22, dtype=torch.complex128, device="cuda")
+    chi = torch.empty_like(psi)
+    ws = torch.empty(max(max(pr.workspace_bytes(w.p, True) for pr, w in zip(probs, wls)), 256),
+                     dtype=torch.uint8, device="cuda")
+    gd = [torch.tensor(w.gammas, device="cuda") for w in wls]
+    td = [torch.tensor(w.ts, device="cuda") for w in wls]
+    fo = torch.empty(512, dtype=torch.float64, device="cuda")
+    dg = torch.empty(8, dtype=torch.float64, device="cuda")
+    dt = torch.empty(8, dtype=torch.float64, device="cuda")
+    st = torch.cuda.current_stream().cuda_stream
+
+    def per_instance():
+        for i, (pr, w) in enumerate(zip(probs, wls)):
+            _lib.check("qva_grad", lib.qva_grad(pr.cstruct(), gd[i].data_ptr(), td[i].data_ptr(), w.p,
+                                                psi.data_ptr(), chi.data_ptr(), fo.data_ptr() + 8 * i,
+                                                dg.data_ptr(), dt.data_ptr(), ws.data_ptr(), ws.numel(), st))
+
+    ms_single = time_calls(per_instance, 1, 2)
+    total_bytes = 0.0
+    for pr, w in zip(probs, wls):
+        total_bytes += sum(i.bytes for i in plan_of(lib, pr, w.p, True, 0))
+    return {"workload": "batch512_qaoa_maxcut_n12-22_p1-8", "instances": 512,
+            "amplitudes": int(sum(1 << w.n for w in wls)),
+            "autotune": tune, "rounds": b.rounds, "launches_per_batch": b.launches, "tiles": b.tiles,
+            "ms_per_batch_graph_replay": round(ms_graph, 3),
+            "ms_per_batch_eager": round(ms_eager, 3),
+            "instance_gradients_per_s": round(512 / (ms_graph * 1e-3), 1),
+            "ms_per_batch_one_call_per_instance": round(ms_single, 3),
+            "speedup_vs_one_call_per_instance": round(ms_single / ms_graph, 2),
+            "effective_GBps": round(total_bytes / (ms_graph * 1e-3) / 1e9, 1)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -414,7 +485,8 @@ def main() -> int:
     if not args.no_extras:
         extras = {}
         for name, fn in [("qwoa_circulant", lambda: extra_qwoa(lib, max(3, args.steps // 2))),
-                         ("adjoint_vs_fd", lambda: extra_adjoint(lib, 2))]:
+                         ("adjoint_vs_fd", lambda: extra_adjoint(lib, 2)),
+                         ("batched", lambda: extra_batch(lib))]:
             log(f"extra: {name} ...")
             try:
                 extras[name] = fn()
