@@ -50,15 +50,38 @@ struct XPass {
     int phase_layer;  // layer whose phase is applied, or -1
 };
 
+// Order in which even layers visit the groups (odd layers reverse it).  The
+// two ends of the order are the boundary groups, whose passes also carry the
+// phase; the low (contiguous, 12-qubit) group is placed in the middle when
+// there are three or more groups, so the phase rides on the smaller strided
+// groups and per-pass arithmetic stays balanced.
+inline std::vector<int> x_layer_order(int P)
+{
+    std::vector<int> order;
+    if (P < 3) {
+        for (int i = 0; i < P; ++i)
+            order.push_back(i);
+        return order;
+    }
+    const int mid = P / 2;
+    for (int i = 1; i <= mid; ++i)
+        order.push_back(i);
+    order.push_back(0);
+    for (int i = mid + 1; i < P; ++i)
+        order.push_back(i);
+    return order;
+}
+
 // Pass list of a p-layer evolution (p >= 1) over P >= 2 groups.  The first
 // pass generates psi_0 and applies the first phase; the last pass reduces
 // <Q> and applies the last layer's scalar factor.
 inline std::vector<XPass> x_evolve_plan(int P, int p, bool store)
 {
+    const std::vector<int> order = x_layer_order(P);
     std::vector<std::pair<int, int>> seq;  // (group, layer) in application order
     for (int L = 0; L < p; ++L)
         for (int i = 0; i < P; ++i)
-            seq.push_back({(L % 2 == 0) ? i : P - 1 - i, L});
+            seq.push_back({order[(L % 2 == 0) ? i : P - 1 - i], L});
     std::vector<XPass> plan;
     plan.push_back({seq[0].first, XP_INIT | XP_PHASE_PRE | XP_MIX1, 0, -1, 0});
     size_t i = 1;
