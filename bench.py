@@ -33,6 +33,13 @@ METRIC = "layer-applications/s and HBM GB/s vs peak; adjoint gradients/s vs fini
 HBM_PEAK_GBS = 8000.0
 PROFILES = os.path.join(ROOT, "profiles")
 TRAFFIC_FILE = os.path.join(PROFILES, "xpass_traffic_qaoa_n28.json")
+CSRC = os.path.join(ROOT, "paper_2110_03963_amd", "csrc")
+# Sources the hypercube-mixer passes are built and launched from: a stored
+# traffic measurement holds only while these are unchanged.
+TRAFFIC_SOURCES = [os.path.join(CSRC, f) for f in
+                   ("qva_xmix.hip", "qva_tile.h", "qva_passes.h", "qva_device.h", "qva_internal.h",
+                    "qva_plan.h", "qva_api.hip")]
+CALIB_ELEMS = 1 << 27  # calibration copy: 2^27 float64 = 1 GiB read + 1 GiB written
 
 
 def log(msg: str) -> None:
@@ -73,6 +80,10 @@ class HipEvents:
 
 MODE_NAMES = {1: "XMODE_FIRST", 2: "XMODE_MIDDLE", 3: "XMODE_BOUNDARY", 4: "XMODE_LAST",
               5: "XMODE_LAST_STORE"}
+# xpass_kernel's second template argument (pass flag bits) per mode, as the
+# profiler prints it.
+XMODE_FLAGS = {"XMODE_FIRST": 71, "XMODE_MIDDLE": 68, "XMODE_BOUNDARY": 92, "XMODE_LAST": 164,
+               "XMODE_LAST_STORE": 228}
 
 
 def kernel_name(kind: int, col_bits: int) -> str:
@@ -134,6 +145,134 @@ def roofline_of(per: dict, steps: int) -> dict:
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": name,
             "launches_per_step": d["launches"] // steps, "avg_launch_ms": round(avg_ms, 4),
             "algorithmic_bytes_per_launch": bpl}
+
+
+def profiler_label(name: str) -> str | None:
+    """Map a profiler kernel name to the names used here: xpass kernels to
+    kernel_name()'s form, the runtime's device-to-device copy to "copy"."""
+    import re
+
+    if "copyBuffer" in name:
+        return "copy"
+    m = re.search(r"xpass_kernel<(\d+), (\d+)>", name)
+    if m:
+        flags = int(m.group(2))
+        for mode, v in XMODE_FLAGS.items():
+            if v == flags:
+                return f"xpass_kernel<{m.group(1)}, {mode}>"
+    for short in ("phase_kernel", "init_uniform_kernel"):
+        if f"::{short}(" in name:
+            return short
+    return None
+
+
+def read_counter_csv(folder: str, counter: str) -> dict:
+    """Per-dispatch values of one counter from rocprofv3's counter_collection
+    CSV(s) under `folder`: {label: [value, ...]} (values in the counter's
+    unit, KiB for FETCH_SIZE / WRITE_SIZE)."""
+    import csv
+    import glob
+
+    files = glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no counter_collection.csv under {folder}")
+    out: dict[str, list] = {}
+    for fn in files:
+        with open(fn, newline="") as fh:
+            for row in csv.DictReader(fh):
+                if row.get("Counter_Name") != counter:
+                    continue
+                label = profiler_label(row.get("Kernel_Name", ""))
+                if label:
+                    out.setdefault(label, []).append(float(row["Counter_Value"]))
+    return out
+
+
+def pmc_pass() -> int:
+    """The program profiled by the two counter runs: one calibration copy of
+    known size, one standalone phase (reads psi and q, writes psi), then two
+    fused n = 28, p = 8 evolutions as in the timed step."""
+    import torch
+
+    import paper_2110_03963_amd as qva
+    from paper_2110_03963_amd import _lib
+    from workloads import CONFIG_SEEDS, maxcut_qualities_device, qaoa_maxcut_workload
+
+    lib = qva.load_library()
+    n, p = 28, 8
+    wl = qaoa_maxcut_workload(n, p, graph="regular3", weighted=True, seed=CONFIG_SEEDS["qaoa_n28"],
+                              build_q=False)
+    src = torch.ones(CALIB_ELEMS, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    q = maxcut_qualities_device(n, wl.edges, wl.weights, "cuda")
+    psi = torch.empty(1 << n, dtype=torch.complex128, device="cuda")
+    qva.init_uniform(psi)
+    qva.phase(psi, q, 0.3)
+    prob = qva.Problem(q, "x")
+    g = torch.tensor(wl.gammas, dtype=torch.float64, device="cuda")
+    t = torch.tensor(wl.ts, dtype=torch.float64, device="cuda")
+    ws = torch.empty(max(prob.workspace_bytes(p), 16), dtype=torch.uint8, device="cuda")
+    out = torch.empty(2, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    for _ in range(2):
+        _lib.check("qva_evolve", lib.qva_evolve(prob.cstruct(), g.data_ptr(), t.data_ptr(), p,
+                                                psi.data_ptr(), out.data_ptr(), out.data_ptr() + 8,
+                                                _lib.QVA_EVOLVE_SKIP_FINAL_STATE, ws.data_ptr(),
+                                                ws.numel(), stream))
+    torch.cuda.synchronize()
+    log(f"pmc pass done: f={out[0].item():.15f}")
+    return 0
+
+
+def write_traffic(fetch_dir: str, write_dir: str) -> int:
+    """Turn the FETCH_SIZE and WRITE_SIZE runs of pmc_pass into HBM bytes per
+    launch of each xpass kernel, each counter scaled by what it reads on the
+    calibration copy (known bytes), and store them with the sources' digest."""
+    fetch = read_counter_csv(fetch_dir, "FETCH_SIZE")
+    write = read_counter_csv(write_dir, "WRITE_SIZE")
+    calib_kib = CALIB_ELEMS * 8 / 1024.0
+    if "copy" not in fetch or "copy" not in write:
+        raise RuntimeError("calibration copy not found in the counter runs")
+    f_copy, w_copy = max(fetch["copy"]), max(write["copy"])
+    ff, fw = calib_kib / f_copy, calib_kib / w_copy
+    n = 28
+    amps = 1 << n
+    kernels = {}
+    for label in sorted(set(fetch) & set(write)):
+        if not label.startswith("xpass_kernel"):
+            continue
+        fb = sum(fetch[label]) / len(fetch[label]) * 1024 * ff
+        wb = sum(write[label]) / len(write[label]) * 1024 * fw
+        kernels[label] = {"fetch_bytes": round(fb), "write_bytes": round(wb),
+                          "bytes_per_launch": round(fb + wb), "dispatches": len(fetch[label]),
+                          "fetch_bytes_per_amplitude": round(fb / amps, 3),
+                          "write_bytes_per_amplitude": round(wb / amps, 3)}
+    check = {}
+    if "phase_kernel" in fetch and "phase_kernel" in write:
+        check = {"phase_kernel_fetch_bytes_per_amplitude":
+                 round(max(fetch["phase_kernel"]) * 1024 * ff / amps, 3),
+                 "phase_kernel_write_bytes_per_amplitude":
+                 round(max(write["phase_kernel"]) * 1024 * fw / amps, 3),
+                 "expected": "24 read (psi 16 + q 8), 16 written"}
+    data = {"source_digest": source_digest(*TRAFFIC_SOURCES), "workload": "qaoa_maxcut_n28_p8",
+            "calibration": {"kernel": "__amd_rocclr_copyBuffer", "bytes_each_way": CALIB_ELEMS * 8,
+                            "fetch_kib_read": f_copy, "write_kib_read": w_copy,
+                            "fetch_scale": ff, "write_scale": fw, **check},
+            "commands": ["timeout -s KILL 150 rocprofv3 --pmc FETCH_SIZE --output-format csv "
+                         "-d gpurun_out/pmc_fetch -o pmc -- python3 -u bench.py --pmc-pass",
+                         "timeout -s KILL 150 rocprofv3 --pmc WRITE_SIZE --output-format csv "
+                         "-d gpurun_out/pmc_write -o pmc -- python3 -u bench.py --pmc-pass",
+                         "python bench.py --write-traffic gpurun_out/pmc_fetch gpurun_out/pmc_write"],
+            "kernels": kernels}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(data, fh, indent=1, sort_keys=True)
+        fh.write("\n")
+    print(json.dumps(data, indent=1, sort_keys=True))
+    return 0
 
 
 def time_calls(fn, warmup: int, steps: int) -> float:
@@ -382,11 +521,19 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--pmc-pass", action="store_true",
+                    help="run the short program profiled by the HBM-traffic counter runs")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="store per-launch HBM traffic from the two counter runs' CSV output")
     args = ap.parse_args()
+    if args.write_traffic:
+        return write_traffic(*args.write_traffic)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the sharded multi-GPU path is a design, not part of this build)", file=sys.stderr)
         return 2
+    if args.pmc_pass:
+        return pmc_pass()
 
     import torch
 
@@ -449,10 +596,9 @@ def main() -> int:
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as fh:
             tr = json.load(fh)
-        digest = source_digest(os.path.join(ROOT, "paper_2110_03963_amd", "csrc", "qva_xmix.hip"),
-                               os.path.join(ROOT, "paper_2110_03963_amd", "csrc", "qva_tile.h"))
-        if tr.get("source_digest") == digest and tr.get("kernel") == roofline["kernel"]:
-            roofline["traffic"] = tr.get("bytes_per_launch")
+        entry = tr.get("kernels", {}).get(roofline["kernel"])
+        if tr.get("source_digest") == source_digest(*TRAFFIC_SOURCES) and entry:
+            roofline["traffic"] = entry["bytes_per_launch"]
     plan_bytes = sum(i.bytes for i in infos)
 
     result = {

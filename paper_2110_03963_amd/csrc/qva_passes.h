@@ -11,15 +11,19 @@ namespace passes {
 using namespace tile;
 
 // ------------------------------------------------------------ forward
-// psi <- scale * exp(-i gamma q) psi in layout L
+// q at the tile's elements in layout L.
 template <int L>
-__device__ __forceinline__ void phase_regs(double2 (&v)[kRegs], const double* q, const TileMap& g,
-                                           int t, double gamma, double2 scale)
+__device__ __forceinline__ void load_q(double (&qq)[kRegs], const double* q, const TileMap& g, int t)
 {
-    double qq[kRegs];
 #pragma unroll
     for (int r = 0; r < kRegs; ++r)
         qq[r] = ld_nt(q + g(elem<L>(t, r)));
+}
+
+// psi <- scale * exp(-i gamma q) psi with q already in registers.
+__device__ __forceinline__ void phase_vals(double2 (&v)[kRegs], const double (&qq)[kRegs], double gamma,
+                                           double2 scale)
+{
 #pragma unroll
     for (int r = 0; r < kRegs; ++r) {
         v[r] = cmul(v[r], cmul(scale, expmi(gamma * qq[r])));
@@ -27,15 +31,23 @@ __device__ __forceinline__ void phase_regs(double2 (&v)[kRegs], const double* q,
     }
 }
 
+// psi <- scale * exp(-i gamma q) psi in layout L
+template <int L>
+__device__ __forceinline__ void phase_regs(double2 (&v)[kRegs], const double* q, const TileMap& g,
+                                           int t, double gamma, double2 scale)
+{
+    double qq[kRegs];
+    load_q<L>(qq, q, g, t);
+    phase_vals(v, qq, gamma, scale);
+}
+
+// qq: q in layout L (read only with XP_EXPECT).
 template <int L, int FLAGS>
 __device__ __forceinline__ void tail(double2 (&v)[kRegs], const XPassParams& P, const TileMap& g,
-                                     int t, double2 fs, double* red, int64_t tile)
+                                     int t, double2 fs, double* red, int64_t tile,
+                                     const double (&qq)[kRegs])
 {
     if constexpr (FLAGS & XP_EXPECT) {
-        double qq[kRegs];
-#pragma unroll
-        for (int r = 0; r < kRegs; ++r)
-            qq[r] = ld_nt(P.q + g(elem<L>(t, r)));
         double f = 0.0, nr = 0.0;
 #pragma unroll
         for (int r = 0; r < kRegs; ++r) {
@@ -58,14 +70,24 @@ __device__ __forceinline__ void tail(double2 (&v)[kRegs], const XPassParams& P, 
 
 // One tile of a hypercube-mixer pass (see XPassParams and the XP_* flags).
 // lds: 4096 amplitudes of shared memory; red: 8 doubles of shared memory.
+// Every global read of the tile (psi, and q where the pass needs it) is
+// issued before any arithmetic, so the tile's whole input is in flight at once.
 template <int C, int FLAGS>
 __device__ __forceinline__ void xpass_tile(const XPassParams& P, int64_t tile, double2* lds, double* red)
 {
+    constexpr int flags = FLAGS;
+    static_assert(((flags & XP_PHASE_PRE) ? 1 : 0) + ((flags & XP_PHASE_MID) ? 1 : 0) +
+                          ((flags & XP_EXPECT) ? 1 : 0) <= 1,
+                  "one use of q per pass");
+    // layout of the tail (store / expectation) and of the pass's use of q
+    constexpr int LT = ((flags & XP_MIX2) || !(flags & XP_MIX1)) ? LA : last_layout<C>();
+    constexpr int LQ = (flags & XP_PHASE_PRE) ? LA : (flags & XP_PHASE_MID) ? last_layout<C>() : LT;
+    constexpr bool use_q = flags & (XP_PHASE_PRE | XP_PHASE_MID | XP_EXPECT);
+
     const int t = threadIdx.x;
     const TileMap g = tile_map(tile, P.k, C);
 
     double2 v[kRegs];
-    constexpr int flags = FLAGS;
     if constexpr (flags & XP_INIT) {
         const double a0 = 1.0 / sqrt((double)(int64_t(1) << P.n));
 #pragma unroll
@@ -76,8 +98,12 @@ __device__ __forceinline__ void xpass_tile(const XPassParams& P, int64_t tile, d
         for (int r = 0; r < kRegs; ++r)
             v[r] = ld_nt(P.psi + g(elem<LA>(t, r)));
     }
+    double qq[kRegs];
+    if constexpr (use_q)
+        load_q<LQ>(qq, P.q, g, t);
+
     if constexpr (flags & XP_PHASE_PRE)
-        phase_regs<LA>(v, P.q, g, t, angle_value(P.phase), make_double2(1.0, 0.0));
+        phase_vals(v, qq, angle_value(P.phase), make_double2(1.0, 0.0));
 
     double2 S1 = make_double2(1.0, 0.0);
     if constexpr (flags & XP_MIX1) {
@@ -89,7 +115,7 @@ __device__ __forceinline__ void xpass_tile(const XPassParams& P, int64_t tile, d
         S1 = cpow_int(m.sigma, P.n);
     }
     if constexpr (flags & XP_PHASE_MID)
-        phase_regs<last_layout<C>()>(v, P.q, g, t, angle_value(P.phase), S1);
+        phase_vals(v, qq, angle_value(P.phase), S1);
     if constexpr (flags & XP_MIX2) {
         const MixCoef m = mix_coef(angle_value(P.mix2));
         if (m.tanform)
@@ -98,10 +124,7 @@ __device__ __forceinline__ void xpass_tile(const XPassParams& P, int64_t tile, d
             mix_reverse<C, false>(v, lds, t, m.k);
     }
     const double2 fs = (flags & XP_FINAL_SCALE) ? S1 : make_double2(1.0, 0.0);
-    if constexpr ((flags & XP_MIX2) || !(flags & XP_MIX1))
-        tail<LA, flags>(v, P, g, t, fs, red, tile);
-    else
-        tail<last_layout<C>(), flags>(v, P, g, t, fs, red, tile);
+    tail<LT, flags>(v, P, g, t, fs, red, tile, qq);
 }
 
 

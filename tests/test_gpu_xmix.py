@@ -53,6 +53,23 @@ def test_phase(N):
         assert np.max(np.abs(psi.cpu().numpy() - ref)) < 1e-15
 
 
+@pytest.mark.parametrize("span", [4.0, 1e3, 1e7, 1e12])
+def test_phase_factor_accuracy(span):
+    """The phase factor exp(-i x) itself: psi = 1, gamma = 1, q = x spread over
+    [-span, span] plus points next to multiples of pi/2; compared with the
+    oracle's libm cexp, as complex numbers, to 1.6e-16 absolute."""
+    rng = np.random.default_rng(int(np.log10(span)) + 11)
+    x = rng.uniform(-span, span, 1 << 18)
+    k = rng.integers(-10**6, 10**6, 1 << 12)
+    near = np.nextafter(k * (np.pi / 2), np.where(rng.random(k.size) < 0.5, -np.inf, np.inf))
+    x = np.concatenate([x, near, [0.0, -0.0, 1e-300, np.pi, -np.pi / 2]])
+    ones = np.ones(x.size, dtype=np.complex128)
+    psi = to_dev(ones)
+    qva.phase(psi, to_dev(x), 1.0)
+    ref = oracle.phase(ones, x, 1.0)
+    assert np.max(np.abs(psi.cpu().numpy() - ref)) <= 1.6e-16
+
+
 @pytest.mark.parametrize("n", [1, 2, 3, 6, 11, 12, 13, 14, 15, 17, 20, 21, 22])
 def test_mix_x(n):
     rng = np.random.default_rng(n)
