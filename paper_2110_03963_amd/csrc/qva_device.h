@@ -38,30 +38,13 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b)
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// sin x and cos x from the series, with no library call.
-//
-// Reduction by quarter turns: 1/pi = kInvPiHi + kInvPiLo to about 2^-109
-// relative, y = fl(x kInvPiHi), and e = x/pi - y from the exact product
-// error (one fma) plus x kInvPiLo, so x = pi (y + e).  With j = rint(2y),
-// t = y - j/2 is exact (|t| <= 1/4) and z = pi (t + e), evaluated with pi
-// split in two doubles, lies in [-pi/4, pi/4] up to rounding; x = j pi/2 + z.
-// The Maclaurin series are summed through z^17 (sin) and z^16 (cos); the
-// first omitted terms are below 2.1e-18 on |z| <= pi/4.  The quadrant j mod 4
-// swaps the two and sets their signs.  The result is within about 1.5e-16
-// absolute of sin x, cos x for |x| < 2^41 (rounding of z and of the sums),
-// checked on the host against long double.
-__host__ __device__ __forceinline__ void sincos_red(double x, double* sn, double* cs)
+// sin and cos of x = j pi/2 + z, |z| <= pi/4 (j an integer-valued double,
+// |j| < 2^51).  The Maclaurin series are summed through z^17 (sin) and z^16
+// (cos); the first omitted terms are below 2.1e-18 on |z| <= pi/4.  The
+// quadrant j mod 4 swaps the two and sets their signs.
+__host__ __device__ __forceinline__ void sincos_quadrant(double z, double j, double* sn, double* cs)
 {
-    constexpr double kInvPiHi = 0.3183098861837907;      // 1/pi rounded to double
-    constexpr double kInvPiLo = -1.9678676675182486e-17;  // 1/pi - kInvPiHi
-    constexpr double kPiHi = 3.141592653589793;           // pi rounded to double
-    constexpr double kPiLo = 1.2246467991473532e-16;      // pi - kPiHi
-    constexpr double kRound = 6755399441055744.0;         // 1.5 * 2^52
-    const double y = x * kInvPiHi;
-    const double e = fma(x, kInvPiLo, fma(x, kInvPiHi, -y));
-    const double j = rint(y + y);
-    const double t = fma(-0.5, j, y);
-    const double z = fma(kPiHi, t, fma(kPiLo, t, kPiHi * e));
+    constexpr double kRound = 6755399441055744.0;  // 1.5 * 2^52
     const double z2 = z * z;
     // sin z = z + z^3 (-1/3! + z^2 (1/5! - ...)), coefficients (-1)^k / (2k+1)!
     double s = 1.0 / 355687428096000.0;
@@ -83,15 +66,50 @@ __host__ __device__ __forceinline__ void sincos_red(double x, double* sn, double
     c = fma(c, z2, 1.0 / 24.0);
     c = fma(c, z2, -0.5);
     const double cz = fma(c, z2, 1.0);
-    // j + 1.5 * 2^52 holds j in its low mantissa bits (|j| < 2^51); the low
-    // two are the quadrant: (sin x, cos x) = (sz, cz), (cz, -sz), (-sz, -cz),
-    // (-cz, sz) for quadrants 0..3.
+    // j + 1.5 * 2^52 holds j in its low mantissa bits; the low two are the
+    // quadrant: (sin x, cos x) = (sz, cz), (cz, -sz), (-sz, -cz), (-cz, sz).
     const uint32_t q = (uint32_t)__builtin_bit_cast(uint64_t, j + kRound);
     const bool swap = q & 1u;
     const uint64_t s_neg = (uint64_t)((q >> 1) & 1u) << 63;
     const uint64_t c_neg = (uint64_t)(((q + 1u) >> 1) & 1u) << 63;
     *sn = __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, swap ? cz : sz) ^ s_neg);
     *cs = __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, swap ? sz : cz) ^ c_neg);
+}
+
+// sin x and cos x, with no library call.
+//
+// Reduction by quarter turns: 1/pi = kInvPiHi + kInvPiLo to about 2^-109
+// relative, y = fl(x kInvPiHi), and e = x/pi - y from the exact product
+// error (one fma) plus x kInvPiLo, so x = pi (y + e).  With j = rint(2y),
+// t = y - j/2 is exact (|t| <= 1/4) and z = pi (t + e), evaluated with pi
+// split in two doubles, lies in [-pi/4, pi/4] up to rounding; x = j pi/2 + z.
+// The result is within about 1.5e-16 absolute of sin x, cos x for
+// |x| < 2^41 (rounding of z and of the sums), checked on the host against
+// long double.
+__host__ __device__ __forceinline__ void sincos_red(double x, double* sn, double* cs)
+{
+    constexpr double kInvPiHi = 0.3183098861837907;      // 1/pi rounded to double
+    constexpr double kInvPiLo = -1.9678676675182486e-17;  // 1/pi - kInvPiHi
+    constexpr double kPiHi = 3.141592653589793;           // pi rounded to double
+    constexpr double kPiLo = 1.2246467991473532e-16;      // pi - kPiHi
+    const double y = x * kInvPiHi;
+    const double e = fma(x, kInvPiLo, fma(x, kInvPiHi, -y));
+    const double j = rint(y + y);
+    const double t = fma(-0.5, j, y);
+    const double z = fma(kPiHi, t, fma(kPiLo, t, kPiHi * e));
+    sincos_quadrant(z, j, sn, cs);
+}
+
+// sin(pi y) and cos(pi y) (twiddle factors: y is a dyadic rational, so the
+// reduction t = y - j/2 is exact and only z = pi t is rounded).
+__host__ __device__ __forceinline__ void sincospi_red(double y, double* sn, double* cs)
+{
+    constexpr double kPiHi = 3.141592653589793;
+    constexpr double kPiLo = 1.2246467991473532e-16;
+    const double j = rint(y + y);
+    const double t = fma(-0.5, j, y);
+    const double z = fma(kPiHi, t, kPiLo * t);
+    sincos_quadrant(z, j, sn, cs);
 }
 
 // exp(-i x) = (cos x, -sin x)

@@ -45,21 +45,21 @@ __device__ __forceinline__ void diag_c(double2 (&v)[kRegs], const FftPassParams&
                                        double tt)
 {
     const int n = P.n;
+    const double2 u = P.lambda_kind == FFT_LAMBDA_RING ? ring_lambda_base(tile, t, n) : make_double2(0.0, 0.0);
 #pragma unroll
     for (int r = 0; r < kRegs; ++r) {
-        const int64_t pos = (tile << kTileBits) | elem<LC>(t, r);
         double lam;
         if (P.lambda_kind == FFT_LAMBDA_TILED) {
             lam = ld_nt(P.lam + (tile << kTileBits) + r * kThreads + t);
+        } else if (P.lambda_kind == FFT_LAMBDA_RING) {
+            lam = ring_lambda(u, r);
         } else {
+            const int64_t pos = (tile << kTileBits) | elem<LC>(t, r);
             const uint64_t m = __brevll((uint64_t)pos) >> (64 - n);
-            if (P.lambda_kind == FFT_LAMBDA_NATURAL) {
+            if (P.lambda_kind == FFT_LAMBDA_NATURAL)
                 lam = P.lam[m];
-            } else if (P.lambda_kind == FFT_LAMBDA_RING) {
-                lam = 2.0 * cospi(ldexp((double)m, 1 - n));  // 2 cos(2 pi m / N)
-            } else {
+            else
                 lam = m == 0 ? (double)((int64_t(1) << n) - 1) : -1.0;
-            }
         }
         v[r] = cmul(v[r], expmi(tt * lam));
         QVA_SCHED_FENCE();
@@ -150,7 +150,7 @@ __device__ void small_fft(double2* s, int n, bool inverse)
             const int j = ((m >> st) << (st + 1)) | (m & (h - 1));
             const int u = j & (h - 1);
             double sn, cs;
-            sincospi(ldexp((double)u, -st), &sn, &cs);  // angle pi u / h = 2 pi u / (2h)
+            sincospi_red(ldexp((double)u, -st), &sn, &cs);  // angle pi u / h = 2 pi u / (2h)
             const double2 w = make_double2(cs, inverse ? sn : -sn);
             const double2 a = s[j];
             double2 b = s[j + h];
@@ -177,7 +177,7 @@ __device__ void small_circulant(double2* s, const SmallFftParams& P, double tt)
         if (P.lambda_kind == FFT_LAMBDA_NATURAL)
             lam = P.lam[m];
         else if (P.lambda_kind == FFT_LAMBDA_RING)
-            lam = 2.0 * cospi(ldexp((double)m, 1 - n));
+            lam = ring_lambda_m(m, n);
         else
             lam = m == 0 ? (double)(N - 1) : -1.0;
         s[j] = cmul(s[j], expmi(tt * lam));

@@ -49,27 +49,11 @@ template <int C, int L>
 __device__ __forceinline__ void digit_twiddle2(double2 (&p)[kRegs], double2 (&x)[kRegs], const TileMap& g,
                                                int t, bool inv)
 {
-    constexpr int LO = digit_lo<C, L>(), W = digit_w<C, L>();
-    if constexpr (W > 0) {
-        const int gb = g.k + (reg_elem_bit<L>(LO) - C);
-        if (gb == 0)
-            return;
-        const int64_t lomask = (int64_t(1) << gb) - 1;
-#pragma unroll
-        for (int r = 0; r < kRegs; ++r) {
-            const int m = rev_bits((r >> LO) & ((1 << W) - 1), W);
-            if (m == 0)
-                continue;
-            const int64_t jlo = g(elem<L>(t, r)) & lomask;
-            const double y = ldexp((double)(jlo * m), -(gb + W - 1));
-            double sn, cs;
-            sincospi(y, &sn, &cs);
-            const double2 w = make_double2(cs, inv ? sn : -sn);
-            p[r] = cmul(p[r], w);
-            x[r] = cmul(x[r], w);
-            QVA_SCHED_FENCE();
-        }
-    }
+    digit_twiddles<C, L>(g, t, [&](int r, double2 tw) {
+        const double2 w = make_double2(tw.x, inv ? -tw.y : tw.y);
+        p[r] = cmul(p[r], w);
+        x[r] = cmul(x[r], w);
+    });
 }
 
 template <int C, int L>
@@ -130,17 +114,18 @@ __device__ __forceinline__ void dit_tile2(double2 (&p)[kRegs], double2 (&x)[kReg
     dit_digit2<C, LA>(p, x, g, t);
 }
 
-// lambda_m at bit-reversed position pos (see the forward low-group pass)
-__device__ __forceinline__ double lambda_at(const GradPassParams& P, int64_t tile, int t, int r)
+// lambda_m at bit-reversed position pos (see the forward low-group pass);
+// u: ring_lambda_base of the tile and thread when the kind is the ring.
+__device__ __forceinline__ double lambda_at(const GradPassParams& P, int64_t tile, int t, int r, double2 u)
 {
-    const int64_t pos = (tile << kTileBits) | elem<LC>(t, r);
     if (P.lambda_kind == FFT_LAMBDA_TILED)
         return ld_nt(P.lam + (tile << kTileBits) + r * kThreads + t);
+    if (P.lambda_kind == FFT_LAMBDA_RING)
+        return ring_lambda(u, r);
+    const int64_t pos = (tile << kTileBits) | elem<LC>(t, r);
     const uint64_t m = __brevll((uint64_t)pos) >> (64 - P.n);
     if (P.lambda_kind == FFT_LAMBDA_NATURAL)
         return P.lam[m];
-    if (P.lambda_kind == FFT_LAMBDA_RING)
-        return 2.0 * cospi(ldexp((double)m, 1 - P.n));
     return m == 0 ? (double)((int64_t(1) << P.n) - 1) : -1.0;
 }
 
@@ -183,9 +168,10 @@ __global__ __launch_bounds__(kThreads, QVA_GRADF_WAVES) void gradf_kernel(GradPa
         load2<LA>(p, x, P, g, t);
         dif_tile2<C>(p, x, lds, g, t);
         double a1 = 0.0;
+        const double2 u = P.lambda_kind == FFT_LAMBDA_RING ? ring_lambda_base(tile, t, P.n) : make_double2(0.0, 0.0);
 #pragma unroll
         for (int r = 0; r < kRegs; ++r) {
-            const double lam = lambda_at(P, tile, t, r);
+            const double lam = lambda_at(P, tile, t, r, u);
             a1 = fma(lam, x[r].x * p[r].y - x[r].y * p[r].x, a1);
             const double2 d = expmi(-tt * lam);  // exp(+i t lambda): the inverse diagonal
             p[r] = cmul(p[r], d);
@@ -259,7 +245,7 @@ __device__ void small_dft(double2* s, int n, bool inverse)
         for (int m = threadIdx.x; m < N / 2; m += blockDim.x) {
             const int j = ((m >> st) << (st + 1)) | (m & (h - 1));
             double sn, cs;
-            sincospi(ldexp((double)(j & (h - 1)), -st), &sn, &cs);
+            sincospi_red(ldexp((double)(j & (h - 1)), -st), &sn, &cs);
             const double2 w = make_double2(cs, inverse ? sn : -sn);
             const double2 a = s[j];
             double2 b = s[j + h];
@@ -283,7 +269,7 @@ __device__ double small_lambda(const SmallGradParams& P, int j)
     if (P.lambda_kind == FFT_LAMBDA_NATURAL)
         return P.lam[m];
     if (P.lambda_kind == FFT_LAMBDA_RING)
-        return 2.0 * cospi(ldexp((double)m, 1 - n));
+        return ring_lambda_m(m, n);
     return m == 0 ? (double)((1 << n) - 1) : -1.0;
 }
 

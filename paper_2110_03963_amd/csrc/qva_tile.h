@@ -167,10 +167,26 @@ struct TileMap {
 
 __device__ __forceinline__ int rev_bits(int x, int w) { return (int)(__brev((unsigned)x) >> (32 - w)); }
 
-// Twiddle W_{2^(gb+w)}^(j_lo * m) per element after (forward) or before
-// (inverse, conjugated) the digit's register DFT.
-template <int C, int L, bool INV>
-__device__ __forceinline__ void digit_twiddle(double2 (&v)[kRegs], const TileMap& g, int t)
+// w-bit reversal of a compile-time register digit.
+constexpr int rev_c(int x, int w)
+{
+    int y = 0;
+    for (int i = 0; i < w; ++i)
+        y |= ((x >> i) & 1) << (w - 1 - i);
+    return y;
+}
+
+// Twiddles of one digit: W_{2^(gb+w)}^(j_lo * m) for the register holding
+// digit value m (bit-reversed digit bits) and index bits j_lo below the
+// digit (global bit gb).  j_lo does not depend on the digit bits, only on the
+// thread and on the column register bits below the digit, so for each such
+// column value b the twiddles are the powers w^m of one root
+// w = exp(-i pi j_lo / 2^(gb+w-1)).  The w roots w^(2^i) are computed exactly
+// (sincospi_red of a dyadic rational) and w^m is their product over the set
+// bits of m: at most w - 1 complex products, about 1 ulp each.
+// apply(r, tw) is called for every register r with m != 0 (forward sign).
+template <int C, int L, typename F>
+__device__ __forceinline__ void digit_twiddles(const TileMap& g, int t, F&& apply)
 {
     constexpr int LO = digit_lo<C, L>(), W = digit_w<C, L>();
     if constexpr (W > 0) {
@@ -178,19 +194,78 @@ __device__ __forceinline__ void digit_twiddle(double2 (&v)[kRegs], const TileMap
         if (gb == 0)
             return;  // no index bits below the digit: all twiddles are 1
         const int64_t lomask = (int64_t(1) << gb) - 1;
+        constexpr int NB = 1 << LO;  // values of the column register bits below the digit
 #pragma unroll
-        for (int r = 0; r < kRegs; ++r) {
-            const int m = rev_bits((r >> LO) & ((1 << W) - 1), W);
-            if (m == 0)
-                continue;
-            const int64_t jlo = g(elem<L>(t, r)) & lomask;
-            const double y = ldexp((double)(jlo * m), -(gb + W - 1));
-            double s, c;
-            sincospi(y, &s, &c);
-            v[r] = INV ? cmul(v[r], make_double2(c, s)) : cmul(v[r], make_double2(c, -s));
-            QVA_SCHED_FENCE();
+        for (int b = 0; b < NB; ++b) {
+            const int64_t jlo = g(elem<L>(t, b)) & lomask;
+            double2 pw[W];  // w^(2^i)
+#pragma unroll
+            for (int i = 0; i < W; ++i) {
+                double s, c;
+                sincospi_red(ldexp((double)jlo, i - (gb + W - 1)), &s, &c);
+                pw[i] = make_double2(c, -s);
+            }
+#pragma unroll
+            for (int m = 1; m < (1 << W); ++m) {
+                double2 tw = make_double2(1.0, 0.0);
+                bool first = true;
+#pragma unroll
+                for (int i = 0; i < W; ++i) {
+                    if ((m >> i) & 1) {
+                        tw = first ? pw[i] : cmul(tw, pw[i]);
+                        first = false;
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < kRegs; ++r) {
+                    if ((r & (NB - 1)) == b && rev_c((r >> LO) & ((1 << W) - 1), W) == m)
+                        apply(r, tw);
+                }
+                QVA_SCHED_FENCE();
+            }
         }
     }
+}
+
+// Twiddles after (forward) or before (inverse, conjugated) the digit's
+// register DFT.
+template <int C, int L, bool INV>
+__device__ __forceinline__ void digit_twiddle(double2 (&v)[kRegs], const TileMap& g, int t)
+{
+    digit_twiddles<C, L>(g, t, [&](int r, double2 tw) {
+        v[r] = INV ? cmul_conj(v[r], tw) : cmul(v[r], tw);
+    });
+}
+
+// Ring eigenvalues lambda_m = 2 cos(2 pi m / N) at the bit-reversed
+// positions of a low-group tile in layout C.  Position (tile, elem<LC>(t, r))
+// holds m = rev4(r) 2^(n-4) + rev8(t) 2^(n-12) + rev_{n-12}(tile), so with
+// u = exp(2 pi i (rev8(t) 2^(n-12) + rev_{n-12}(tile)) / N), computed once per
+// thread, lambda = 2 Re(u exp(2 pi i rev4(r) / 16)) = 2 Re(u conj(W_16^rev4(r))).
+__device__ __forceinline__ double2 ring_lambda_base(int64_t tile, int t, int n)
+{
+    const int hb = n - kTileBits;
+    const int64_t rt = hb > 0 ? (int64_t)(__brevll((uint64_t)tile) >> (64 - hb)) : 0;
+    const int64_t a = ((int64_t)rev_bits(t, 8) << hb) | rt;
+    double s, c;
+    sincospi_red(ldexp((double)a, 1 - n), &s, &c);
+    return make_double2(c, s);
+}
+
+// lambda_m = 2 cos(2 pi m / N) for a single index m (whole-state paths).
+__device__ __forceinline__ double ring_lambda_m(uint64_t m, int n)
+{
+    double s, c;
+    sincospi_red(ldexp((double)m, 1 - n), &s, &c);
+    return 2.0 * c;
+}
+
+__device__ __forceinline__ double ring_lambda(double2 u, int r)
+{
+    const int k = rev_c(r, 4);
+    const double2 w = w16(k & 7);  // W_16^k = -W_16^(k-8) for k >= 8
+    const double l = 2.0 * fma(u.x, w.x, u.y * w.y);
+    return (k & 8) ? -l : l;
 }
 
 template <int C, int L>
