@@ -307,8 +307,9 @@ def cpu_baseline(wl) -> dict:
 
 
 # ------------------------------------------------------------------ extras
-def extra_qwoa(lib, steps: int) -> dict:
-    """QWOA portfolio over all subsets of 26 assets, ring mixer, p = 6."""
+def extra_qwoa(lib, steps: int, kind: str = "ring") -> dict:
+    """QWOA portfolio over all subsets of 26 assets, p = 6; ring mixer
+    (transform passes) or complete graph (closed-form passes)."""
     import torch
 
     import paper_2110_03963_amd as qva
@@ -316,8 +317,8 @@ def extra_qwoa(lib, steps: int) -> dict:
     from workloads import CONFIG_SEEDS, qwoa_portfolio_workload
 
     n, p = 26, 6
-    wl = qwoa_portfolio_workload(n, p, seed=CONFIG_SEEDS["qwoa_n26"], lambda_kind="ring")
-    prob = qva.Problem(torch.from_numpy(wl.q).cuda(), "circulant", None, "ring")
+    wl = qwoa_portfolio_workload(n, p, seed=CONFIG_SEEDS["qwoa_n26"], lambda_kind=kind)
+    prob = qva.Problem(torch.from_numpy(wl.q).cuda(), "circulant", None, kind)
     g = torch.tensor(wl.gammas, device="cuda")
     t = torch.tensor(wl.ts, device="cuda")
     psi = torch.empty(1 << n, dtype=torch.complex128, device="cuda")
@@ -342,7 +343,7 @@ def extra_qwoa(lib, steps: int) -> dict:
 
     per = per_kernel_profile(run_timed, infos, steps)
     plan_bytes = sum(i.bytes for i in infos)
-    return {"workload": "qwoa_portfolio_n26_p6_ring", "ms_per_evolve": round(ms, 4),
+    return {"workload": f"qwoa_portfolio_n26_p6_{kind}", "ms_per_evolve": round(ms, 4),
             "layer_applications_per_s": round(p / (ms * 1e-3), 2), "launches": len(infos),
             "effective_GBps": round(plan_bytes / (ms * 1e-3) / 1e9, 1),
             "f": out[0].item(), "roofline": roofline_of(per, steps),
@@ -631,6 +632,7 @@ def main() -> int:
     if not args.no_extras:
         extras = {}
         for name, fn in [("qwoa_circulant", lambda: extra_qwoa(lib, max(3, args.steps // 2))),
+                         ("qwoa_complete", lambda: extra_qwoa(lib, max(3, args.steps // 2), "complete")),
                          ("adjoint_vs_fd", lambda: extra_adjoint(lib, 2)),
                          ("batched", lambda: extra_batch(lib))]:
             log(f"extra: {name} ...")

@@ -194,7 +194,20 @@ typedef enum {
     QVA_PASS_GRAD_DIF = 22,     /* forward FFT of one group, both vectors               */
     QVA_PASS_GRAD_DIT = 23,     /* inverse FFT of one group, both vectors               */
     QVA_PASS_GRAD_LOWDIAG = 24, /* low group, <chi^|lambda|phi^>/N, inverse diagonal    */
-    QVA_PASS_GRAD_REDUCE = 25   /* fixed-order sums of the gradient partials            */
+    QVA_PASS_GRAD_REDUCE = 25,  /* fixed-order sums of the gradient partials            */
+    /* circulant mixer of the complete graph in closed form (qva_evolve with
+     * QVA_LAMBDA_COMPLETE, n > 12): W = J - I has J^2 = N J, so
+     * exp(-i t W) = e^{i t} (I + (e^{-i t N} - 1)/N J) (Sec. 3 eigenvalues
+     * N - 1 once and -1): one reduction plus one streaming pass per layer */
+    QVA_PASS_CPL_FIRST = 26,      /* psi_0 with the phase of layer 1, written, + sums     */
+    QVA_PASS_CPL_LAYER = 27,      /* mixer of layer k, phase of layer k+1, written, + sums */
+    QVA_PASS_CPL_LAST = 28,       /* mixer of the last layer, <Q> partial sums            */
+    QVA_PASS_CPL_LAST_STORE = 29, /* as QVA_PASS_CPL_LAST, also writes psi_p              */
+    QVA_PASS_CPL_SUM = 30,        /* fixed-order sum of the state's partial sums          */
+    /* qva_grad with the closed-form complete-graph mixer (n > 12) */
+    QVA_PASS_GRAD_CPL_TURN = 31,  /* last mixer, <Q>, chi = Q psi_p, sums for dt_p         */
+    QVA_PASS_GRAD_CPL_BACK = 32,  /* inverse mixer k, <chi|Q|phi>, inverse phase k, sums   */
+    QVA_PASS_GRAD_CPL_SUM = 33    /* fixed-order sums: state sums, dt_k and dgamma_k terms */
 } qva_pass_kind;
 
 /* One launch of a plan.  `bytes` is the algorithmic HBM traffic of the

@@ -30,6 +30,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 MIX_X = 0
 MIX_CIRCULANT = 1
+MIX_COMPLETE = 2
 
 _lib = None
 
@@ -64,6 +65,8 @@ def _load():
     lib.oracle_fft.argtypes = [I64, P, Ci]
     lib.oracle_mix_circulant.argtypes = [I64, P, P, D]
     lib.oracle_apply_circulant.argtypes = [I64, P, P, P]
+    lib.oracle_mix_complete.argtypes = [I64, P, D]
+    lib.oracle_apply_complete.argtypes = [I64, P, P]
     lib.oracle_circulant_eigenvalues.argtypes = [I64, P, P, P]
     lib.oracle_expectation.argtypes = [I64, P, P, P, P]
     lib.oracle_evolve.argtypes = [Ci, I64, P, P, Ci, P, P, P, P, P]
@@ -143,6 +146,21 @@ def mix_circulant(psi, lam, t: float) -> np.ndarray:
     return psi
 
 
+def mix_complete(psi, t: float) -> np.ndarray:
+    """exp(-i t (J - I)) psi from the definition (closed form)."""
+    psi = _c128(psi).copy()
+    _load().oracle_mix_complete(len(psi), _ptr(psi), float(t))
+    return psi
+
+
+def apply_complete(psi) -> np.ndarray:
+    """(J - I) psi = sum(psi) - psi."""
+    psi = _c128(psi)
+    out = np.empty_like(psi)
+    _load().oracle_apply_complete(len(psi), _ptr(psi), _ptr(out))
+    return out
+
+
 def apply_circulant(psi, lam) -> np.ndarray:
     psi = _c128(psi)
     lam = _f64(lam)
@@ -198,7 +216,7 @@ def lambda_for(kind: str, N: int, lam=None) -> np.ndarray:
 
 # ------------------------------------------------------------- evolution
 def _kind(mixer: str) -> int:
-    return {"x": MIX_X, "circulant": MIX_CIRCULANT}[mixer]
+    return {"x": MIX_X, "circulant": MIX_CIRCULANT, "complete": MIX_COMPLETE}[mixer]
 
 
 def evolve(mixer: str, q, gammas, ts, lam=None) -> tuple[np.ndarray, float, float]:

@@ -19,7 +19,8 @@
  * W is either the hypercube adjacency sum_i X_i (QAOA; U_W is then the product
  * of independent single-qubit rotations exp(-i t X_i)), or a circulant with
  * eigenvalues lambda_m, applied as F^-1 diag(exp(-i t lambda_m)) F with F the
- * unnormalised DFT (Sec. 3, circulant eigensystem).
+ * unnormalised DFT (Sec. 3, circulant eigensystem), or the complete graph's
+ * adjacency J - I, applied from its definition (closed form, no transform).
  *
  * Readings of the paper taken here (each one listed with its reason in the
  * design notes): W_X = sum_i X_i (hypercube, the figure of Sec. 2.3.1);
@@ -42,7 +43,7 @@ typedef double complex cplx;
 /* pi to double precision (M_PI is not part of strict C11). */
 static const double PI = 3.14159265358979323846264338327950288;
 
-enum { ORACLE_MIX_X = 0, ORACLE_MIX_CIRCULANT = 1 };
+enum { ORACLE_MIX_X = 0, ORACLE_MIX_CIRCULANT = 1, ORACLE_MIX_COMPLETE = 2 };
 
 /* ---------------------------------------------------------------------- */
 /* Pairwise (recursive halving) summation.                                 */
@@ -250,6 +251,38 @@ void oracle_apply_circulant(int64_t N, const cplx *psi, const double *lambda, cp
         out[j] /= (double)N;
 }
 
+/* ---------------------------------------------------------------------- */
+/* Complete-graph mixer (the QWOA default W; Sec. 3 eigenvalues N - 1 once,  */
+/* -1 otherwise), from its definition W = J - I with J the all-ones matrix:  */
+/*   W psi = S 1 - psi,  S = sum_j psi_j;                                    */
+/*   J^2 = N J  =>  exp(-i t W) = e^{i t} (I + (e^{-i t N} - 1)/N J).        */
+/* For N a power of two t N is exact; otherwise it is rounded once.         */
+/* ---------------------------------------------------------------------- */
+
+static double term_re(int64_t j, const void *c) { return creal(((const cplx *)c)[j]); }
+static double term_im(int64_t j, const void *c) { return cimag(((const cplx *)c)[j]); }
+
+static cplx state_sum(int64_t N, const cplx *psi)
+{
+    return pairwise_sum_fn(term_re, psi, 0, N) + I * pairwise_sum_fn(term_im, psi, 0, N);
+}
+
+void oracle_mix_complete(int64_t N, cplx *psi, double t)
+{
+    const cplx S = state_sum(N, psi);
+    const cplx c = (cexp(-I * (t * (double)N)) - 1.0) / (double)N;
+    const cplx e = cexp(I * t);
+    for (int64_t j = 0; j < N; ++j)
+        psi[j] = e * (psi[j] + c * S);
+}
+
+void oracle_apply_complete(int64_t N, const cplx *psi, cplx *out)
+{
+    const cplx S = state_sum(N, psi);
+    for (int64_t j = 0; j < N; ++j)
+        out[j] = S - psi[j];
+}
+
 /* Eigenvalues of the circulant whose first row is w (Sec. 3):              */
 /*   lambda_m = w_0 + w_{N-1} omega^m + w_{N-2} omega^{2m} + ...            */
 /*            = sum_l w_{(N-l) mod N} omega^{l m},  omega = exp(2 pi i / N). */
@@ -347,6 +380,8 @@ static void apply_mixer(int kind, int64_t N, cplx *psi, const double *lambda, do
 {
     if (kind == ORACLE_MIX_X)
         oracle_mix_x(log2_exact(N), psi, t);
+    else if (kind == ORACLE_MIX_COMPLETE)
+        oracle_mix_complete(N, psi, t);
     else
         oracle_mix_circulant(N, psi, lambda, t);
 }
@@ -355,6 +390,8 @@ static void apply_W(int kind, int64_t N, const cplx *psi, const double *lambda, 
 {
     if (kind == ORACLE_MIX_X)
         oracle_apply_hypercube(log2_exact(N), psi, out);
+    else if (kind == ORACLE_MIX_COMPLETE)
+        oracle_apply_complete(N, psi, out);
     else
         oracle_apply_circulant(N, psi, lambda, out);
 }
@@ -367,7 +404,7 @@ static int check_args(int kind, int64_t N)
         return -1;
     if (kind == ORACLE_MIX_CIRCULANT && N > 4096 && log2_exact(N) < 0)
         return -1;
-    if (kind != ORACLE_MIX_X && kind != ORACLE_MIX_CIRCULANT)
+    if (kind != ORACLE_MIX_X && kind != ORACLE_MIX_CIRCULANT && kind != ORACLE_MIX_COMPLETE)
         return -1;
     return 0;
 }

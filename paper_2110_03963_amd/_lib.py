@@ -58,7 +58,9 @@ PASS_KINDS = {0: "whole", 1: "first", 2: "middle", 3: "boundary", 4: "last", 5: 
               12: "fft_dit", 13: "fft_boundary", 14: "fft_last", 15: "fft_last_store",
               16: "lambda_prep", 17: "grad_whole", 18: "grad_turn", 19: "grad_mid",
               20: "grad_bound", 21: "grad_final", 22: "grad_dif", 23: "grad_dit",
-              24: "grad_lowdiag", 25: "grad_reduce"}
+              24: "grad_lowdiag", 25: "grad_reduce", 26: "cpl_first", 27: "cpl_layer",
+              28: "cpl_last", 29: "cpl_last_store", 30: "cpl_sum", 31: "grad_cpl_turn",
+              32: "grad_cpl_back", 33: "grad_cpl_sum"}
 
 
 class QvaBatchItem(ctypes.Structure):

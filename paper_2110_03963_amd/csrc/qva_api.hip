@@ -175,6 +175,13 @@ bool lambda_tiled(const qva_problem* P)
     return P->lambda_kind == QVA_LAMBDA_ARRAY && P->n_qubits > kTileBits;
 }
 
+// The complete graph's mixer in closed form (no transform) for n > 12.
+bool complete_closed_form(const qva_problem* P)
+{
+    return P->mixer == QVA_MIX_CIRCULANT && P->lambda_kind == QVA_LAMBDA_COMPLETE &&
+           P->n_qubits > kTileBits;
+}
+
 std::vector<Launch> fft_launches(const qva_problem* P, int p, bool store)
 {
     const int n = P->n_qubits;
@@ -186,6 +193,18 @@ std::vector<Launch> fft_launches(const qva_problem* P, int p, bool store)
     if (p == 0) {
         L.push_back({QVA_PASS_INIT, -1, 0, -1, -1, -1});
         L.push_back({QVA_PASS_EXPECT, -1, 0, -1, -1, -1});
+        L.push_back({QVA_PASS_REDUCE, -1, 0, -1, -1, -1});
+        return L;
+    }
+    if (complete_closed_form(P)) {
+        L.push_back({QVA_PASS_CPL_FIRST, -1, CPMODE_FIRST, -1, -1, 0});
+        L.push_back({QVA_PASS_CPL_SUM, -1, 0, -1, -1, -1});
+        for (int k = 0; k + 1 < p; ++k) {
+            L.push_back({QVA_PASS_CPL_LAYER, -1, CPMODE_LAYER, k, -1, k + 1});
+            L.push_back({QVA_PASS_CPL_SUM, -1, 0, -1, -1, -1});
+        }
+        L.push_back({store ? QVA_PASS_CPL_LAST_STORE : QVA_PASS_CPL_LAST, -1,
+                     store ? CPMODE_LAST_STORE : CPMODE_LAST, p - 1, -1, -1});
         L.push_back({QVA_PASS_REDUCE, -1, 0, -1, -1, -1});
         return L;
     }
@@ -220,6 +239,16 @@ double fft_launch_bytes(const Launch& l, int n, bool store, bool tiled)
         return (2 * amp + real) * N;
     case QVA_PASS_LAMBDA_PREP:
         return 2 * real * N;
+    case QVA_PASS_CPL_FIRST:
+        return (real + amp) * N + 16.0 * std::ldexp(1.0, n - kTileBits);
+    case QVA_PASS_CPL_LAYER:
+        return (2 * amp + real) * N + 16.0 * std::ldexp(1.0, n - kTileBits);
+    case QVA_PASS_CPL_LAST:
+        return (amp + real) * N + 16.0 * std::ldexp(1.0, n - kTileBits);
+    case QVA_PASS_CPL_LAST_STORE:
+        return (2 * amp + real) * N + 16.0 * std::ldexp(1.0, n - kTileBits);
+    case QVA_PASS_CPL_SUM:
+        return 16.0 * std::ldexp(1.0, n - kTileBits);
     default: {
         Launch x = l;
         return launch_bytes(x, n, store);
@@ -318,6 +347,8 @@ int evolve_circ(const qva_problem* P, const double* gammas, const double* ts, in
     const std::vector<XGroup> groups = x_groups(n);
     double2* partials = reinterpret_cast<double2*>(work);
     double* lam_tiles = n > kTileBits ? reinterpret_cast<double*>(work + circ_partials_bytes(n)) : nullptr;
+    // complete graph in closed form: the running state sum follows the partials
+    double2* state_sum = n > kTileBits ? reinterpret_cast<double2*>(work + circ_partials_bytes(n)) : nullptr;
     const bool tiled = lambda_tiled(P);
     for (const Launch& l : fft_launches(P, p, store)) {
         hipError_t e = hipSuccess;
@@ -353,6 +384,28 @@ int evolve_circ(const qva_problem* P, const double* gammas, const double* ts, in
         case QVA_PASS_LAMBDA_PREP:
             e = launch_lambda_tiles(P->lambda, lam_tiles, n, s);
             break;
+        case QVA_PASS_CPL_SUM:
+            e = launch_final_reduce(partials, int64_t(1) << (n - kTileBits), &state_sum->x,
+                                    &state_sum->y, s);
+            break;
+        case QVA_PASS_CPL_FIRST:
+        case QVA_PASS_CPL_LAYER:
+        case QVA_PASS_CPL_LAST:
+        case QVA_PASS_CPL_LAST_STORE: {
+            CompleteParams c{};
+            c.psi = psi;
+            c.q = P->q;
+            c.gammas = gammas;
+            c.ts = ts;
+            c.sum_in = state_sum;
+            c.partials = partials;
+            c.n = n;
+            c.mix_layer = l.layer1;
+            c.phase_layer = l.phase_layer;
+            c.flags = l.xmode;
+            e = launch_complete(c, s);
+            break;
+        }
         default: {
             const XGroup& g = groups[l.group];
             FftPassParams f{};
@@ -385,8 +438,8 @@ int evolve_circ(const qva_problem* P, const double* gammas, const double* ts, in
 struct GradLayout {
     int64_t tiles = 0;
     int G = 1;       // t-slots per layer: qubit groups (hypercube) or 1 (circulant)
-    int nslots = 0;  // p * (G + 1)
-    size_t fpart = 0, slots = 0, sums = 0, lam = 0, total = 0;
+    int nslots = 0;  // p * (G + 1) per-tile slot arrays (none for the closed-form mixer)
+    size_t fpart = 0, slots = 0, sums = 0, lam = 0, part = 0, state = 0, total = 0;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -399,6 +452,21 @@ GradLayout grad_layout(const qva_problem* P, int p)
         return g;
     g.tiles = int64_t(1) << (n - kTileBits);
     g.G = P->mixer == QVA_MIX_X ? (int)x_groups(n).size() : 1;
+    if (complete_closed_form(P)) {
+        // (f, norm) partials, per-block parts, running sums, then 2p slot sums
+        size_t off = 0;
+        g.fpart = off;
+        off = align256(off + (size_t)g.tiles * sizeof(double2));
+        g.part = off;
+        off = align256(off + (size_t)g.tiles * kCompleteParts * sizeof(double));
+        g.state = off;
+        off = align256(off + 4 * sizeof(double2));
+        g.sums = off;
+        off = align256(off + (size_t)(2 * (p > 0 ? p : 1)) * sizeof(double));
+        g.lam = g.slots = off;
+        g.total = off;
+        return g;
+    }
     g.nslots = p * (g.G + 1);
     size_t off = 0;
     g.fpart = off;
@@ -436,6 +504,24 @@ std::vector<GLaunch> grad_launches(const qva_problem* P, int p)
         L.push_back({QVA_PASS_INIT, -1, 0, -1, -1, -1, -1, -1, -1});
         L.push_back({QVA_PASS_EXPECT, -1, 0, -1, -1, -1, -1, -1, -1});
         L.push_back({QVA_PASS_REDUCE, -1, 0, -1, -1, -1, -1, -1, -1});
+        return L;
+    }
+    if (complete_closed_form(P)) {
+        // forward without the last mixer, then the walk back (slots index the sums)
+        L.push_back({QVA_PASS_CPL_FIRST, -1, CPMODE_FIRST, -1, -1, 0, -1, -1, -1});
+        L.push_back({QVA_PASS_CPL_SUM, -1, 0, -1, -1, -1, -1, -1, -1});
+        for (int k = 0; k + 1 < p; ++k) {
+            L.push_back({QVA_PASS_CPL_LAYER, -1, CPMODE_LAYER, k, -1, k + 1, -1, -1, -1});
+            L.push_back({QVA_PASS_CPL_SUM, -1, 0, -1, -1, -1, -1, -1, -1});
+        }
+        L.push_back({QVA_PASS_GRAD_CPL_TURN, -1, GCMODE_TURN, p - 1, -1, -1, -1, -1, -1});
+        L.push_back({QVA_PASS_GRAD_CPL_SUM, -1, 0, -1, -1, -1, p - 1, -1, -1});
+        for (int k = p - 1; k >= 0; --k) {
+            L.push_back({QVA_PASS_GRAD_CPL_BACK, -1, k > 0 ? GCMODE_BACK : GCMODE_BACK_LAST, k, -1, k, -1, -1, -1});
+            L.push_back({QVA_PASS_GRAD_CPL_SUM, -1, 0, -1, -1, -1, k > 0 ? k - 1 : -1, p + k, -1});
+        }
+        L.push_back({QVA_PASS_REDUCE, -1, 0, -1, -1, -1, -1, -1, -1});
+        L.push_back({QVA_PASS_GRAD_REDUCE, -1, 0, -1, -1, -1, -1, -1, -1});
         return L;
     }
     const int PG = (int)x_groups(n).size();
@@ -521,6 +607,12 @@ double grad_launch_bytes(const GLaunch& l, const qva_problem* P, int p)
         const GradLayout g = grad_layout(P, p);
         return 8.0 * (double)g.nslots * (double)g.tiles;
     }
+    case QVA_PASS_GRAD_CPL_TURN:
+        return 56.0 * N + 16.0 * (1 + kCompleteParts / 2) * std::ldexp(1.0, n - kTileBits);
+    case QVA_PASS_GRAD_CPL_BACK:
+        return (l.mode == GCMODE_BACK ? 72.0 : 40.0) * N + 8.0 * kCompleteParts * std::ldexp(1.0, n - kTileBits);
+    case QVA_PASS_GRAD_CPL_SUM:
+        return 8.0 * kCompleteParts * std::ldexp(1.0, n - kTileBits);
     default: {
         Launch x{l.kind, l.group, l.mode, l.t1, l.t2, l.gamma};
         return P->mixer == QVA_MIX_CIRCULANT ? fft_launch_bytes(x, n, false, tiled) : launch_bytes(x, n, false);
@@ -540,6 +632,8 @@ int grad_run(const qva_problem* P, const double* gammas, const double* ts, int p
     double* slots = reinterpret_cast<double*>(work + W.slots);
     double* sums = reinterpret_cast<double*>(work + W.sums);
     double* lam_tiles = reinterpret_cast<double*>(work + W.lam);
+    double* cpart = reinterpret_cast<double*>(work + W.part);
+    double2* cstate = reinterpret_cast<double2*>(work + W.state);  // [0]: forward sum, [1..2]: backward
     const bool tiled = circ && lambda_tiled(P);
     auto slot_ptr = [&](int idx) -> double* { return idx >= 0 ? slots + (int64_t)idx * W.tiles : nullptr; };
     for (const GLaunch& l : grad_launches(P, p)) {
@@ -575,6 +669,45 @@ int grad_run(const qva_problem* P, const double* gammas, const double* ts, int p
         }
         case QVA_PASS_GRAD_REDUCE:
             e = launch_grad_reduce(slots, W.nslots, W.tiles, sums, p, W.G, dgammas, dts, s);
+            break;
+        case QVA_PASS_CPL_FIRST:
+        case QVA_PASS_CPL_LAYER: {
+            CompleteParams c{};
+            c.psi = psi;
+            c.q = P->q;
+            c.gammas = gammas;
+            c.ts = ts;
+            c.sum_in = cstate;
+            c.partials = fpart;
+            c.n = n;
+            c.mix_layer = l.t1;
+            c.phase_layer = l.gamma;
+            c.flags = l.mode;
+            e = launch_complete(c, s);
+            break;
+        }
+        case QVA_PASS_CPL_SUM:
+            e = launch_final_reduce(fpart, W.tiles, &cstate->x, &cstate->y, s);
+            break;
+        case QVA_PASS_GRAD_CPL_TURN:
+        case QVA_PASS_GRAD_CPL_BACK: {
+            CompleteGradParams c{};
+            c.phi = psi;
+            c.chi = chi;
+            c.q = P->q;
+            c.gammas = gammas;
+            c.ts = ts;
+            c.sums_in = l.kind == QVA_PASS_GRAD_CPL_TURN ? cstate : cstate + 1;
+            c.part = cpart;
+            c.fpart = fpart;
+            c.n = n;
+            c.layer = l.t1;
+            c.flags = l.mode;
+            e = launch_complete_grad(c, s);
+            break;
+        }
+        case QVA_PASS_GRAD_CPL_SUM:
+            e = launch_complete_gsum(cpart, W.tiles, cstate + 1, sums, l.slot_t1, l.slot_g, s);
             break;
         case QVA_PASS_LAMBDA_PREP:
             e = launch_lambda_tiles(P->lambda, lam_tiles, n, s);
@@ -809,6 +942,8 @@ size_t qva_workspace_bytes(const qva_problem* P, int p, int for_grad)
     size_t bytes = circ_partials_bytes(n);
     if (P->mixer == QVA_MIX_CIRCULANT && lambda_tiled(P))
         bytes += (size_t)(int64_t(1) << n) * sizeof(double);
+    if (complete_closed_form(P))
+        bytes += 256;  // the running state sum
     return bytes;
 }
 

@@ -45,6 +45,13 @@ __device__ __forceinline__ void diag_c(double2 (&v)[kRegs], const FftPassParams&
                                        double tt)
 {
     const int n = P.n;
+    if (P.lambda_kind == FFT_LAMBDA_COMPLETE) {
+        // position (tile, elem) holds m = 0 only at tile 0, element 0
+#pragma unroll
+        for (int r = 0; r < kRegs; ++r)
+            v[r] = cmul(v[r], complete_diag(tile == 0 && elem<LC>(t, r) == 0, tt, n));
+        return;
+    }
     const double2 u = P.lambda_kind == FFT_LAMBDA_RING ? ring_lambda_base(tile, t, n) : make_double2(0.0, 0.0);
 #pragma unroll
     for (int r = 0; r < kRegs; ++r) {
@@ -56,10 +63,7 @@ __device__ __forceinline__ void diag_c(double2 (&v)[kRegs], const FftPassParams&
         } else {
             const int64_t pos = (tile << kTileBits) | elem<LC>(t, r);
             const uint64_t m = __brevll((uint64_t)pos) >> (64 - n);
-            if (P.lambda_kind == FFT_LAMBDA_NATURAL)
-                lam = P.lam[m];
-            else
-                lam = m == 0 ? (double)((int64_t(1) << n) - 1) : -1.0;
+            lam = P.lam[m];
         }
         v[r] = cmul(v[r], expmi(tt * lam));
         QVA_SCHED_FENCE();
@@ -173,13 +177,11 @@ __device__ void small_circulant(double2* s, const SmallFftParams& P, double tt)
     small_fft(s, n, false);
     for (int j = threadIdx.x; j < N; j += blockDim.x) {
         const unsigned m = __brev((unsigned)j) >> (32 - n);
-        double lam;
-        if (P.lambda_kind == FFT_LAMBDA_NATURAL)
-            lam = P.lam[m];
-        else if (P.lambda_kind == FFT_LAMBDA_RING)
-            lam = ring_lambda_m(m, n);
-        else
-            lam = m == 0 ? (double)(N - 1) : -1.0;
+        if (P.lambda_kind == FFT_LAMBDA_COMPLETE) {
+            s[j] = cmul(s[j], complete_diag(m == 0, tt, n));
+            continue;
+        }
+        const double lam = P.lambda_kind == FFT_LAMBDA_NATURAL ? P.lam[m] : ring_lambda_m(m, n);
         s[j] = cmul(s[j], expmi(tt * lam));
     }
     __syncthreads();

@@ -173,7 +173,10 @@ __global__ __launch_bounds__(kThreads, QVA_GRADF_WAVES) void gradf_kernel(GradPa
         for (int r = 0; r < kRegs; ++r) {
             const double lam = lambda_at(P, tile, t, r, u);
             a1 = fma(lam, x[r].x * p[r].y - x[r].y * p[r].x, a1);
-            const double2 d = expmi(-tt * lam);  // exp(+i t lambda): the inverse diagonal
+            // exp(+i t lambda): the inverse diagonal
+            const double2 d = P.lambda_kind == FFT_LAMBDA_COMPLETE
+                                  ? complete_diag(tile == 0 && elem<LC>(t, r) == 0, -tt, P.n)
+                                  : expmi(-tt * lam);
             p[r] = cmul(p[r], d);
             x[r] = cmul(x[r], d);
             QVA_SCHED_FENCE();
@@ -284,7 +287,8 @@ __device__ double small_circ(double2* s, double2* c2, const SmallGradParams& P, 
     double acc = 0.0;
     for (int j = threadIdx.x; j < N; j += blockDim.x) {
         const double lam = small_lambda(P, j);
-        const double2 d = expmi(tt * lam);
+        const double2 d = P.lambda_kind == FFT_LAMBDA_COMPLETE ? complete_diag(lam != -1.0, tt, n)
+                                                               : expmi(tt * lam);
         if (c2) {
             acc = fma(lam, c2[j].x * s[j].y - c2[j].y * s[j].x, acc);
             c2[j] = cmul(c2[j], d);

@@ -139,6 +139,67 @@ hipError_t launch_fftpass(const FftPassParams& P, hipStream_t s);
 hipError_t launch_small_fft(const SmallFftParams& P, hipStream_t s);
 hipError_t launch_lambda_tiles(const double* lam, double* out, int n, hipStream_t s);
 
+// ------------------------------------------- complete-graph mixer, closed form
+// Pass flags (see qva_complete.hip).
+enum : int {
+    CP_INIT = 1,    // start from the uniform state instead of loading psi
+    CP_MIX = 2,     // psi <- e^{it} (psi + c S), c = (e^{-itN} - 1)/N, S = *sum_in
+    CP_PHASE = 4,   // psi <- exp(-i gamma q) psi
+    CP_SUM = 8,     // per-block sums of the output state
+    CP_EXPECT = 16, // per-block sum |psi|^2 q and sum |psi|^2
+    CP_STORE = 32   // write psi back
+};
+enum : int {
+    CPMODE_FIRST = CP_INIT | CP_PHASE | CP_SUM | CP_STORE,
+    CPMODE_LAYER = CP_MIX | CP_PHASE | CP_SUM | CP_STORE,
+    CPMODE_LAST = CP_MIX | CP_EXPECT,
+    CPMODE_LAST_STORE = CP_MIX | CP_EXPECT | CP_STORE
+};
+
+struct CompleteParams {
+    double2* psi;         // N amplitudes, blocks of kCompleteChunk
+    const double* q;
+    const double* gammas;  // device, p
+    const double* ts;      // device, p
+    const double2* sum_in; // device: sum over the input state (CP_MIX)
+    double2* partials;     // one per block: sums (CP_SUM) or (<Q>, norm) (CP_EXPECT)
+    int n;
+    int mix_layer;         // layer of the mixer (CP_MIX)
+    int phase_layer;       // layer of the phase (CP_PHASE)
+    int flags;
+};
+
+constexpr int kCompleteChunk = 1 << kTileBits;  // amplitudes per block
+hipError_t launch_complete(const CompleteParams& P, hipStream_t s);
+
+// Adjoint walk with the closed-form mixer (see qva_complete.hip).
+enum : int {
+    GCMODE_TURN = 1,      // last mixer, <Q> partials, chi = Q psi_p, sums for dt_{p-1}
+    GCMODE_BACK = 2,      // inverse mixer k, Im<chi|Q|phi>, inverse phase k, sums for dt_{k-1}
+    GCMODE_BACK_LAST = 3  // inverse mixer 0, Im<chi|Q|phi> (nothing written)
+};
+constexpr int kCompleteParts = 8;  // doubles per block: S_phi, S_chi, Im<chi|phi>, Im<chi|Q|phi>
+
+struct CompleteGradParams {
+    double2* phi;
+    double2* chi;
+    const double* q;
+    const double* gammas;
+    const double* ts;
+    const double2* sums_in;  // TURN: sum of the input phi; BACK: (S_phi, S_chi) of the input
+    double* part;            // kCompleteParts per block
+    double2* fpart;          // TURN: per-block (<Q>, norm)
+    int n;
+    int layer;
+    int flags;               // GCMODE_*
+};
+hipError_t launch_complete_grad(const CompleteGradParams& P, hipStream_t s);
+// Fixed-order sums of the per-block parts: (S_phi, S_chi) -> state_out,
+// sums[t_slot] = Im(conj(S_chi) S_phi) - Im<chi|phi> and sums[g_slot] = Im<chi|Q|phi>
+// (a slot < 0 is skipped).
+hipError_t launch_complete_gsum(const double* part, int64_t blocks, double2* state_out, double* sums,
+                                int t_slot, int g_slot, hipStream_t s);
+
 // ---------------------------------------------------------------- gradient
 // Pass modes of the adjoint walk (see qva_grad.hip).
 enum : int {

@@ -252,6 +252,15 @@ __device__ __forceinline__ double2 ring_lambda_base(int64_t tile, int t, int n)
     return make_double2(c, s);
 }
 
+// exp(-i t lambda_m) for the complete graph's eigenvalues (N - 1 at m = 0,
+// -1 elsewhere; N = 2^n), with t N formed exactly:
+// exp(-i t (N - 1)) = exp(-i t N) e^{i t}.
+__device__ __forceinline__ double2 complete_diag(bool m0, double t, int n)
+{
+    const double2 e1 = expmi(-t);
+    return m0 ? cmul(expmi(t * ldexp(1.0, n)), e1) : e1;
+}
+
 // lambda_m = 2 cos(2 pi m / N) for a single index m (whole-state paths).
 __device__ __forceinline__ double ring_lambda_m(uint64_t m, int n)
 {

@@ -39,7 +39,30 @@ def qwoa_n26():
             "f": f, "norm": nrm, "oracle_seconds": time.time() - t0}
 
 
-GENERATORS = {"qaoa_n28_p8": qaoa_n28, "qwoa_n26_p6": qwoa_n26}
+def qwoa_n26_complete():
+    # the complete graph's mixer from its definition (closed form): the
+    # transform route would round t (N - 1) for the eigenvalue N - 1
+    wl = qwoa_portfolio_workload(26, 6, seed=CONFIG_SEEDS["qwoa_n26"], lambda_kind="complete")
+    t0 = time.time()
+    _, f, nrm = oracle.evolve("complete", wl.q, wl.gammas, wl.ts)
+    secs = time.time() - t0
+    # the same spectrum through the transform route (eigenvalue array)
+    _, f_tr, _ = oracle.evolve("circulant", wl.q, wl.gammas, wl.ts, oracle.complete_lambda(wl.N))
+    return {"recipe": "qwoa_portfolio_workload(26, 6, seed=103, lambda_kind='complete')",
+            "f": f, "norm": nrm, "oracle_seconds": secs, "f_transform": f_tr}
+
+
+def qwoa_n26_complete_grad():
+    wl = qwoa_portfolio_workload(26, 6, seed=CONFIG_SEEDS["qwoa_n26"], lambda_kind="complete")
+    t0 = time.time()
+    f, dg, dt = oracle.grad("complete", wl.q, wl.gammas, wl.ts)
+    return {"recipe": "qwoa_portfolio_workload(26, 6, seed=103, lambda_kind='complete'); oracle.grad",
+            "f": f, "dgammas": list(map(float, dg)), "dts": list(map(float, dt)),
+            "oracle_seconds": time.time() - t0}
+
+
+GENERATORS = {"qaoa_n28_p8": qaoa_n28, "qwoa_n26_p6": qwoa_n26, "qwoa_n26_p6_complete": qwoa_n26_complete,
+              "qwoa_n26_p6_complete_grad": qwoa_n26_complete_grad}
 
 
 def main(names):

@@ -55,14 +55,17 @@ def test_mix_circulant(n, kind):
     for t in [0.37, -2.1]:
         psi = to_dev(psi0)
         qva.mix_circulant(psi, t, to_dev(lam) if api_kind == "array" else None, api_kind)
-        ref = oracle.mix_circulant(psi0, lam, t)
+        ref = oracle.mix_complete(psi0, t) if kind == "complete" else oracle.mix_circulant(psi0, lam, t)
         assert state_err(psi.cpu().numpy(), ref) < PSI_TOL, (n, kind, t)
 
 
 def _check_evolve(q, gammas, ts, kind, lam, store=True):
     prob = qva.Problem(to_dev(q), "circulant", to_dev(lam) if kind == "array" else None, kind)
     f, nrm, psi = qva.evolve(prob, gammas, ts, store=store)
-    psi_ref, f_ref, n_ref = oracle.evolve("circulant", q, gammas, ts, lam)
+    if kind == "complete":  # the oracle's closed form (definition of the mixer)
+        psi_ref, f_ref, n_ref = oracle.evolve("complete", q, gammas, ts)
+    else:
+        psi_ref, f_ref, n_ref = oracle.evolve("circulant", q, gammas, ts, lam)
     assert f_rel_err(f.item(), f_ref, psi_ref, q) < F_TOL
     assert abs(nrm.item() - n_ref) < 1e-13
     if store:
@@ -114,6 +117,42 @@ def test_ring_delta_bessel_full_size(n, t):
     rest = out[61:N - 60]
     assert np.max(np.abs(rest)) < 1e-13
     assert abs(np.sum(np.abs(out) ** 2) - 1) < 1e-12
+
+
+@pytest.mark.parametrize("n,p", [(13, 1), (13, 4), (15, 2), (16, 5), (19, 3)])
+def test_evolve_complete_closed_form(n, p):
+    """qva_evolve with the complete graph runs the closed-form passes for
+    n > 12: against the oracle (transform-based) with and without the final
+    state, and the same spectrum as an array (transform passes) agrees."""
+    rng = np.random.default_rng(31 * n + p)
+    N = 1 << n
+    q = rng.uniform(-2, 5, N)
+    g = rng.uniform(0, math.pi, p)
+    t = rng.uniform(0, math.pi, p)
+    lam = oracle.complete_lambda(N)
+    f1, f_ref = _check_evolve(q, g, t, "complete", lam, store=True)
+    f2, _ = _check_evolve(q, g, t, "complete", lam, store=False)
+    assert f1 == f2
+    # the spectrum as an array: transform passes, against the oracle's transform route
+    prob_a = qva.Problem(to_dev(q), "circulant", to_dev(lam), "array")
+    f_a, _, _ = qva.evolve(prob_a, g, t, store=False)
+    f_tr = oracle.evolve("circulant", q, g, t, lam)[1]
+    assert abs(f_a.item() - f_tr) <= F_TOL * np.mean(np.abs(q))
+
+
+@pytest.mark.parametrize("n", [13, 17])
+def test_evolve_complete_degenerate_angles(n):
+    """t = 0 and t N a multiple of 2 pi (c = 0) leave only global phases: f
+    equals the value of the phases alone, i.e. mean(q); gamma = 0 everywhere
+    keeps the uniform state, f = mean(q)."""
+    rng = np.random.default_rng(n)
+    N = 1 << n
+    q = rng.uniform(0, 3, N)
+    lam = oracle.complete_lambda(N)
+    for g, t in [([0.4, 1.3], [0.0, 0.0]), ([0.9, 0.2, 2.0], [2 * math.pi / N, 0.0, 4 * math.pi / N]),
+                 ([0.0, 0.0], [0.7, 2.2])]:
+        f, f_ref = _check_evolve(q, np.array(g), np.array(t), "complete", lam)
+        assert abs(f - q.mean()) < 1e-12 * abs(q.mean())
 
 
 def test_complete_graph_closed_form_full_size():

@@ -79,3 +79,39 @@ def test_qwoa_n26_p6_matches_oracle(golden):
     prob_a = qva.Problem(prob.q, "circulant", lam, "array")
     f_a, _, _ = qva.evolve(prob_a, wl.gammas, wl.ts, store=False)
     assert abs(f_a.item() - ref["f"]) < 1e-12 * abs(ref["f"])
+
+
+def test_qwoa_n26_p6_complete_matches_oracle(golden):
+    """Complete-graph mixer at N = 2^26: the closed-form passes against the
+    oracle's closed form, and the same spectrum given as an array (so the
+    transform passes run) against the oracle's transform route."""
+    if "qwoa_n26_p6_complete" not in golden:
+        pytest.skip("golden value not generated")
+    wl = qwoa_portfolio_workload(26, 6, seed=CONFIG_SEEDS["qwoa_n26"], lambda_kind="complete")
+    ref = golden["qwoa_n26_p6_complete"]
+    prob = qva.Problem(torch.from_numpy(wl.q).cuda(), "circulant", None, "complete")
+    f, nrm, _ = qva.evolve(prob, wl.gammas, wl.ts, store=False)
+    assert abs(f.item() - ref["f"]) < 1e-12 * abs(ref["f"])
+    assert abs(nrm.item() - 1.0) < 1e-12
+    # as an eigenvalue array the transform passes round t (N - 1) as the
+    # oracle's transform route does: compared with that route's value
+    lam = torch.full((wl.N,), -1.0, dtype=torch.float64, device="cuda")
+    lam[0] = wl.N - 1
+    prob_a = qva.Problem(prob.q, "circulant", lam, "array")
+    f_a, _, _ = qva.evolve(prob_a, wl.gammas, wl.ts, store=False)
+    assert abs(f_a.item() - ref["f_transform"]) < 1e-12 * abs(ref["f_transform"])
+
+
+def test_qwoa_n26_p6_complete_gradient_matches_oracle(golden):
+    """Closed-form adjoint at N = 2^26, p = 6 against the oracle's gradient
+    (f to 1e-12, gradient to 1e-10 relative)."""
+    if "qwoa_n26_p6_complete_grad" not in golden:
+        pytest.skip("golden value not generated")
+    wl = qwoa_portfolio_workload(26, 6, seed=CONFIG_SEEDS["qwoa_n26"], lambda_kind="complete")
+    ref = golden["qwoa_n26_p6_complete_grad"]
+    prob = qva.Problem(torch.from_numpy(wl.q).cuda(), "circulant", None, "complete")
+    f, dg, dt = qva.grad(prob, wl.gammas, wl.ts)
+    assert abs(f.item() - ref["f"]) < 1e-12 * abs(ref["f"])
+    g = np.concatenate([dg.cpu().numpy(), dt.cpu().numpy()])
+    r = np.concatenate([ref["dgammas"], ref["dts"]])
+    assert np.max(np.abs(g - r)) < 1e-10 * np.max(np.abs(r))

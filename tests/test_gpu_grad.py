@@ -46,7 +46,10 @@ def _check(mixer, q, g, t, lam=None, kind="array"):
         prob = qva.Problem(to_dev(q), "circulant", to_dev(lam) if kind == "array" else None, kind)
         lam = oracle.lambda_for(kind, len(q), lam)
     f, dg, dt = qva.grad(prob, g, t)
-    f_ref, rg, rt = oracle.grad(mixer, q, g, t, lam)
+    if mixer == "circulant" and kind == "complete":  # the oracle's closed form
+        f_ref, rg, rt = oracle.grad("complete", q, g, t)
+    else:
+        f_ref, rg, rt = oracle.grad(mixer, q, g, t, lam)
     assert abs(f.item() - f_ref) <= F_TOL * max(abs(f_ref), np.mean(np.abs(q)))
     err = _gerr(dg.cpu().numpy(), dt.cpu().numpy(), rg, rt)
     assert err < G_TOL, err
@@ -73,6 +76,23 @@ def test_grad_circulant(n, p, kind):
     g = rng.uniform(0, math.pi, p)
     t = rng.uniform(0, math.pi, p)
     _check("circulant", q, g, t, lam, kind)
+
+
+@pytest.mark.parametrize("n,p", [(13, 1), (16, 3), (20, 4)])
+def test_grad_complete_closed_form(n, p):
+    """Complete graph, n > 12: the closed-form adjoint passes against the
+    oracle's closed-form adjoint (f to 1e-12, gradient to 1e-10); at n = 20
+    the transform route would already be off by ~1e-10 (eigenvalue N - 1)."""
+    rng = np.random.default_rng(5 * n + p)
+    N = 1 << n
+    q = rng.uniform(-1, 3, N)
+    g = rng.uniform(0, math.pi, p)
+    t = rng.uniform(0, math.pi, p)
+    f, dg, dt = _check("circulant", q, g, t, None, "complete")
+    # repeatable bit for bit
+    prob = qva.Problem(to_dev(q), "circulant", None, "complete")
+    f2, dg2, dt2 = qva.grad(prob, g, t)
+    assert f2.item() == f and np.array_equal(dg2.cpu().numpy(), dg) and np.array_equal(dt2.cpu().numpy(), dt)
 
 
 def test_grad_n12_regular3_p12():

@@ -162,6 +162,55 @@ def test_plan_small_and_depth_zero(lib):
     assert [x.kind for x in plan] == [6, 7, 8]
 
 
+@pytest.mark.parametrize("n", [13, 20, 26, 33])
+@pytest.mark.parametrize("p", [1, 2, 6])
+def test_plan_complete_closed_form(lib, n, p):
+    """Complete graph (lambda kind 2), n > 12: one streaming pass per layer
+    plus a reduction of the state sum after every pass that writes."""
+    pr = _prob(mixer=1, n=n, kind=2, lam=None)
+    N = 1 << n
+    for flags, last in [(1, 28), (0, 29)]:
+        cnt = lib.qva_plan(ctypes.byref(pr), p, 0, flags, None, 0)
+        arr = (_lib.QvaPassInfo * cnt)()
+        assert lib.qva_plan(ctypes.byref(pr), p, 0, flags, arr, cnt) == cnt
+        kinds = [x.kind for x in arr]
+        assert kinds == [26, 30] + [27, 30] * (p - 1) + [last, 8]
+        layers = [(x.mix_layer, x.phase_layer) for x in arr if x.kind in (26, 27, 28, 29)]
+        assert layers == [(-1, 0)] + [(k, k + 1) for k in range(p - 1)] + [(p - 1, -1)]
+        parts = 16 * (N >> 12)
+        bytes_ = [x.bytes for x in arr if x.kind in (26, 27, 28, 29)]
+        assert bytes_ == [24 * N + parts] + [40 * N + parts] * (p - 1) + [(24 if flags else 40) * N + parts]
+    # the running state sum needs 256 bytes after the partials
+    assert lib.qva_workspace_bytes(ctypes.byref(pr), p, 0) == 16 * (N >> 12) + 256
+    # depth 0 and small n keep their plans
+    assert [x for x in [lib.qva_plan(ctypes.byref(pr), 0, 0, 0, None, 0)]] == [3]
+    small = _prob(mixer=1, n=12, kind=2, lam=None)
+    assert lib.qva_plan(ctypes.byref(small), p, 0, 0, None, 0) == 1
+
+
+@pytest.mark.parametrize("n", [13, 26])
+@pytest.mark.parametrize("p", [1, 3, 6])
+def test_grad_plan_complete_closed_form(lib, n, p):
+    """qva_grad with the complete graph: forward without the last mixer, the
+    turn, one backward pass per layer, each followed by its fixed-order sums."""
+    pr = _prob(mixer=1, n=n, kind=2, lam=None)
+    cnt = lib.qva_plan(ctypes.byref(pr), p, 1, 0, None, 0)
+    arr = (_lib.QvaPassInfo * cnt)()
+    assert lib.qva_plan(ctypes.byref(pr), p, 1, 0, arr, cnt) == cnt
+    kinds = [x.kind for x in arr]
+    assert kinds == ([26, 30] + [27, 30] * (p - 1) + [31, 33] + [32, 33] * p + [8, 25])
+    back = [(x.mix_layer, x.phase_layer) for x in arr if x.kind == 32]
+    assert back == [(k, k) for k in range(p - 1, -1, -1)]
+    N = 1 << n
+    bytes_ = [x.bytes for x in arr if x.kind in (31, 32)]
+    parts = 64 * (N >> 12)
+    assert bytes_[0] == 56 * N + 16 * 5 * (N >> 12)
+    assert bytes_[1:] == [72 * N + parts] * (p - 1) + [40 * N + parts]
+    # workspace: (f, norm) partials, 8 doubles per block, running sums, 2p sums
+    ws = lib.qva_workspace_bytes(ctypes.byref(pr), p, 1)
+    assert ws >= 16 * (N >> 12) + 64 * (N >> 12) + 64 + 16 * p
+
+
 def _grad_plan(lib, mixer, n, p, kind=1):
     pr = _prob(mixer=mixer, n=n, lam=FAKE if kind == 0 else None, kind=kind)
     cnt = lib.qva_plan(ctypes.byref(pr), p, 1, 0, None, 0)

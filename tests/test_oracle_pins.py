@@ -206,6 +206,87 @@ def test_complete_graph_closed_form(oracle_mod, N):
     assert np.max(np.abs(out - ref)) < 1e-13
 
 
+@pytest.mark.parametrize("N", [1, 2, 3, 7, 16, 33])
+def test_complete_mixer_definition_matches_dense_expm(oracle_mod, N):
+    """The oracle's complete-graph mixer (written from W = J - I) against a
+    dense eigendecomposition of the complete graph's adjacency, and W psi
+    against the dense matrix product."""
+    rng = np.random.default_rng(N + 7)
+    psi = _rand_state(rng, N)
+    W = np.ones((N, N)) - np.eye(N)
+    for t in [0.0, 0.45, -1.7, 2 * math.pi / N, 11.3]:
+        ref = dense.expm_hermitian(W, t) @ psi
+        assert np.max(np.abs(oracle.mix_complete(psi, t) - ref)) < 1e-13
+    assert np.max(np.abs(oracle.apply_complete(psi) - W @ psi)) < 1e-14
+
+
+@pytest.mark.parametrize("N", [8, 100, 4096, 8192])
+def test_complete_mixer_matches_transform(oracle_mod, N):
+    """The same mixer through the circulant route (Sec. 3 eigenvalues N - 1,
+    -1, DFT for N <= 4096, FFT above) and numpy's expm-free closed form."""
+    rng = np.random.default_rng(N)
+    psi = _rand_state(rng, N)
+    for t in [0.83, -0.2]:
+        a = oracle.mix_complete(psi, t)
+        b = oracle.mix_circulant(psi, oracle.complete_lambda(N), t)
+        assert np.max(np.abs(a - b)) < 1e-13
+        assert abs(np.linalg.norm(a) - 1) < 1e-14
+
+
+@pytest.mark.parametrize("n,p", [(3, 2), (6, 3), (9, 4)])
+def test_complete_evolve_and_gradient(oracle_mod, n, p):
+    """evolve / grad with the closed-form mixer: equal to the transform route
+    at small N, adjoint == brute-force differentiation, central differences."""
+    rng = np.random.default_rng(40 + n)
+    N = 1 << n
+    q = rng.uniform(-1, 4, N)
+    g = rng.uniform(0, math.pi, p)
+    t = rng.uniform(0, math.pi, p)
+    lam = oracle.complete_lambda(N)
+    psi_a, f_a, _ = oracle.evolve("complete", q, g, t)
+    psi_b, f_b, _ = oracle.evolve("circulant", q, g, t, lam)
+    assert np.max(np.abs(psi_a - psi_b)) < 1e-12
+    assert abs(f_a - f_b) < 1e-12 * np.max(np.abs(q))
+    f, dg, dt = oracle.grad("complete", q, g, t)
+    assert f == f_a
+    bg, bt = oracle.grad_bruteforce("complete", q, g, t)
+    _, cg, ct = oracle.grad("circulant", q, g, t, lam)
+    scale = max(np.max(np.abs(dg)), np.max(np.abs(dt)))
+    for ref_g, ref_t in [(bg, bt), (cg, ct)]:
+        assert np.max(np.abs(dg - ref_g)) < 1e-11 * scale
+        assert np.max(np.abs(dt - ref_t)) < 1e-11 * scale
+    _check_complete_fd(q, g, t, dg, dt, scale, 1e-7)
+
+
+def _check_complete_fd(q, g, t, dg, dt, scale, tol):
+    """Central differences; f oscillates in t_k at frequency N (through
+    e^{-i t N}), so the t step is taken as 1e-5 / N."""
+    N, p = len(q), len(g)
+    for k in range(p):
+        e = np.zeros(p)
+        e[k] = 1e-5
+        fd_g = (oracle.evolve("complete", q, g + e, t)[1] - oracle.evolve("complete", q, g - e, t)[1]) / 2e-5
+        e[k] = 1e-5 / N
+        fd_t = (oracle.evolve("complete", q, g, t + e)[1] - oracle.evolve("complete", q, g, t - e)[1]) / (2e-5 / N)
+        assert abs(fd_g - dg[k]) < tol * scale, (k, fd_g, dg[k])
+        assert abs(fd_t - dt[k]) < tol * scale, (k, fd_t, dt[k])
+
+
+def test_complete_gradient_central_differences_large(oracle_mod):
+    """At N = 2^16, where the transform route loses accuracy through the
+    eigenvalue N - 1, the closed-form adjoint still agrees with central
+    differences of the closed-form evolution."""
+    rng = np.random.default_rng(16)
+    N = 1 << 16
+    p = 3
+    q = rng.uniform(-1, 3, N)
+    g = rng.uniform(0, math.pi, p)
+    t = rng.uniform(0, math.pi, p)
+    _, dg, dt = oracle.grad("complete", q, g, t)
+    scale = max(np.max(np.abs(dg)), np.max(np.abs(dt)))
+    _check_complete_fd(q, g, t, dg, dt, scale, 1e-6)
+
+
 def test_circulant_eigenvalue_formula(oracle_mod):
     """Sec. 3 eigenvalue formula vs the ring/complete closed forms and numpy's
     eigvalsh of the dense circulant."""
