@@ -350,22 +350,33 @@ def extra_qwoa(lib, steps: int, kind: str = "ring") -> dict:
             "per_kernel_ms_per_evolve": {k: round(v["ms"] / steps, 4) for k, v in sorted(per.items())}}
 
 
-def extra_adjoint(lib, reps: int) -> dict:
-    """Adjoint gradient, weighted 3-regular MaxCut n = 30, p = 12 (24 params),
-    against 4p central-difference and 2p+1 forward-difference evaluations of
-    the same fused forward on the same GPU."""
+def extra_adjoint(lib, reps: int, workload: str = "qaoa") -> dict:
+    """Adjoint gradient against 4p central-difference and 2p+1 forward-difference
+    evaluations of the same fused forward on the same GPU.  Workloads: weighted
+    3-regular MaxCut n = 30, p = 12 (24 params), or the QWOA portfolio over 2^26
+    subsets with the complete-graph mixer, p = 6 (closed-form passes)."""
     import numpy as np
     import torch
 
     import paper_2110_03963_amd as qva
     from paper_2110_03963_amd import _lib
-    from workloads import CONFIG_SEEDS, maxcut_qualities_device, qaoa_maxcut_workload
+    from workloads import (CONFIG_SEEDS, maxcut_qualities_device, qaoa_maxcut_workload,
+                           qwoa_portfolio_workload)
 
-    n, p = 30, 12
-    wl = qaoa_maxcut_workload(n, p, graph="regular3", weighted=True, seed=CONFIG_SEEDS["grad_n30"],
-                              build_q=False)
-    q = maxcut_qualities_device(n, wl.edges, wl.weights, "cuda")
-    prob = qva.Problem(q, "x")
+    if workload == "qaoa":
+        n, p = 30, 12
+        wl = qaoa_maxcut_workload(n, p, graph="regular3", weighted=True, seed=CONFIG_SEEDS["grad_n30"],
+                                  build_q=False)
+        q = maxcut_qualities_device(n, wl.edges, wl.weights, "cuda")
+        prob = qva.Problem(q, "x")
+        name = "adjoint_qaoa_maxcut_n30_p12"
+        h_t = 1e-5
+    else:
+        n, p = 26, 6
+        wl = qwoa_portfolio_workload(n, p, seed=CONFIG_SEEDS["qwoa_n26"], lambda_kind="complete")
+        prob = qva.Problem(torch.from_numpy(wl.q).cuda(), "circulant", None, "complete")
+        name = "adjoint_qwoa_portfolio_n26_p6_complete"
+        h_t = 1e-5 / (1 << n)  # f oscillates in t at frequency N (e^{-i t N})
     g = torch.tensor(wl.gammas, device="cuda")
     t = torch.tensor(wl.ts, device="cuda")
     psi = torch.empty(1 << n, dtype=torch.complex128, device="cuda")
@@ -401,7 +412,7 @@ def extra_adjoint(lib, reps: int) -> dict:
             for sgn in (1.0, -1.0):
                 gp.copy_(g)
                 tp.copy_(t)
-                (gp if k < p else tp)[k % p] += sgn * h
+                (gp if k < p else tp)[k % p] += sgn * (h if k < p else h_t)
                 forward()
                 fd_vals[2 * k + (0 if sgn > 0 else 1)] = out[0]
 
@@ -410,7 +421,7 @@ def extra_adjoint(lib, reps: int) -> dict:
             gp.copy_(g)
             tp.copy_(t)
             if k < 2 * p:
-                (gp if k < p else tp)[k % p] += h
+                (gp if k < p else tp)[k % p] += h if k < p else h_t
             forward()
 
     ms_adj = time_calls(adjoint, 1, reps)
@@ -418,7 +429,11 @@ def extra_adjoint(lib, reps: int) -> dict:
     ms_ffd = time_calls(forward_diff, 0, reps)
     adj = torch.cat([dg, dt]).cpu().numpy()
     fdv = fd_vals.cpu().numpy()
-    cfd = (fdv[0::2] - fdv[1::2]) / (2 * h)
+    # the step actually taken: (x + h) - (x - h), exact in double (the t step
+    # of the complete graph, 1e-5 / N, is only a few hundred ulps of t)
+    x = np.concatenate([np.asarray(wl.gammas, np.float64), np.asarray(wl.ts, np.float64)])
+    hs = np.array([h] * p + [h_t] * p)
+    cfd = (fdv[0::2] - fdv[1::2]) / ((x + hs) - (x - hs))
     rel = float(np.max(np.abs(adj - cfd)) / np.max(np.abs(adj)))
     infos = plan_of(lib, prob, p, True, 0)
 
@@ -430,14 +445,14 @@ def extra_adjoint(lib, reps: int) -> dict:
 
     per = per_kernel_profile(run_timed, infos, 1)
     plan_bytes = sum(i.bytes for i in infos)
-    return {"workload": "adjoint_qaoa_maxcut_n30_p12", "params": 2 * p,
+    return {"workload": name, "params": 2 * p,
             "ms_per_adjoint_gradient": round(ms_adj, 2),
             "adjoint_gradients_per_s": round(1e3 / ms_adj, 3),
             "ms_per_central_fd_gradient": round(ms_cfd, 2),
             "ms_per_forward_fd_gradient": round(ms_ffd, 2),
             "speedup_vs_central_fd": round(ms_cfd / ms_adj, 2),
             "speedup_vs_forward_fd": round(ms_ffd / ms_adj, 2),
-            "max_rel_diff_adjoint_vs_central_fd_h1e-5": rel,
+            "max_rel_diff_adjoint_vs_central_fd": rel, "fd_steps": {"gamma": h, "t": h_t},
             "f": f.item(), "launches": len(infos),
             "effective_GBps": round(plan_bytes / (ms_adj * 1e-3) / 1e9, 1),
             "roofline": roofline_of(per, 1),
@@ -515,6 +530,16 @@ def extra_batch(lib) -> dict:
             "effective_GBps": round(total_bytes / (ms_graph * 1e-3) / 1e9, 1)}
 
 
+# Secondary measurements: name -> fn(lib, steps).
+EXTRAS = {
+    "qwoa_circulant": lambda lib, steps: extra_qwoa(lib, max(3, steps // 2)),
+    "qwoa_complete": lambda lib, steps: extra_qwoa(lib, max(3, steps // 2), "complete"),
+    "adjoint_vs_fd": lambda lib, steps: extra_adjoint(lib, 2),
+    "adjoint_qwoa_complete": lambda lib, steps: extra_adjoint(lib, 3, "qwoa_complete"),
+    "batched": lambda lib, steps: extra_batch(lib),
+}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -526,6 +551,8 @@ def main() -> int:
                     help="run the short program profiled by the HBM-traffic counter runs")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="store per-launch HBM traffic from the two counter runs' CSV output")
+    ap.add_argument("--extra", choices=sorted(EXTRAS),
+                    help="run one secondary measurement alone and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.write_traffic:
         return write_traffic(*args.write_traffic)
@@ -535,6 +562,16 @@ def main() -> int:
         return 2
     if args.pmc_pass:
         return pmc_pass()
+    if args.extra:
+        import torch
+
+        import paper_2110_03963_amd as qva
+
+        if not torch.cuda.is_available():
+            print("bench.py needs a GPU", file=sys.stderr)
+            return 1
+        print(json.dumps({args.extra: EXTRAS[args.extra](qva.load_library(), args.steps)}), flush=True)
+        return 0
 
     import torch
 
@@ -631,13 +668,10 @@ def main() -> int:
     torch.cuda.empty_cache()
     if not args.no_extras:
         extras = {}
-        for name, fn in [("qwoa_circulant", lambda: extra_qwoa(lib, max(3, args.steps // 2))),
-                         ("qwoa_complete", lambda: extra_qwoa(lib, max(3, args.steps // 2), "complete")),
-                         ("adjoint_vs_fd", lambda: extra_adjoint(lib, 2)),
-                         ("batched", lambda: extra_batch(lib))]:
+        for name, fn in EXTRAS.items():
             log(f"extra: {name} ...")
             try:
-                extras[name] = fn()
+                extras[name] = fn(lib, args.steps)
             except Exception as exc:  # reported, not fatal: the headline line still prints
                 extras[name] = {"error": repr(exc)}
             torch.cuda.empty_cache()
