@@ -71,17 +71,23 @@ typedef enum {
 
 /* Problem descriptor (caller-owned, read during the call only).
  *   mixer       QVA_MIX_X or QVA_MIX_CIRCULANT
- *   n_qubits    log2 N; 1 <= n_qubits <= QVA_MAX_QUBITS
+ *   n_qubits    log2 N rounded up; 1 <= n_qubits <= QVA_MAX_QUBITS
  *   q           device, N doubles: the diagonal of Q (paper Sec. 2.2)
  *   lambda      device, N doubles, eigenvalues of W in natural order; read only
  *               when mixer == QVA_MIX_CIRCULANT and lambda_kind == QVA_LAMBDA_ARRAY
- *   lambda_kind a qva_lambda_kind (ignored for QVA_MIX_X)                      */
+ *   lambda_kind a qva_lambda_kind (ignored for QVA_MIX_X)
+ *   n_states    N when it is not a power of two (the solution count |S'| of a
+ *               constrained QWOA, Sec. 2.4.2), else 0 (N = 2^n_qubits).  A
+ *               non-power-of-two N needs 2^(n_qubits-1) < N < 2^n_qubits and is
+ *               supported for the complete-graph mixer (QVA_ERR_UNSUPPORTED
+ *               otherwise).                                                    */
 typedef struct {
     int mixer;
     int n_qubits;
     const double *q;
     const double *lambda;
     int lambda_kind;
+    int64_t n_states;
 } qva_problem;
 
 #define QVA_MAX_QUBITS 33

@@ -37,6 +37,7 @@ class QvaProblem(ctypes.Structure):
         ("q", ctypes.c_void_p),
         ("lam", ctypes.c_void_p),
         ("lambda_kind", ctypes.c_int),
+        ("n_states", ctypes.c_int64),
     ]
 
 

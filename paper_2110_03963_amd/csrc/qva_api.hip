@@ -23,6 +23,14 @@ int hip_status(hipError_t e) { return e == hipSuccess ? QVA_OK : QVA_ERR_HIP; }
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// N of a problem: n_states when given, else 2^n_qubits.
+int64_t problem_N(const qva_problem* P)
+{
+    return P->n_states > 0 ? P->n_states : (int64_t(1) << P->n_qubits);
+}
+
 int check_problem(const qva_problem* P, int p)
 {
     if (!P || p < 0)
@@ -31,6 +39,15 @@ int check_problem(const qva_problem* P, int p)
         return QVA_ERR_ARG;
     if (P->n_qubits < 1 || P->n_qubits > QVA_MAX_QUBITS)
         return QVA_ERR_SIZE;
+    if (P->n_states < 0)
+        return QVA_ERR_SIZE;
+    if (P->n_states > 0 && P->n_states != (int64_t(1) << P->n_qubits)) {
+        // 2^(n-1) < N < 2^n, complete-graph mixer only
+        if (P->n_states <= (int64_t(1) << (P->n_qubits - 1)) || P->n_states > (int64_t(1) << P->n_qubits))
+            return QVA_ERR_SIZE;
+        if (P->mixer != QVA_MIX_CIRCULANT || P->lambda_kind != QVA_LAMBDA_COMPLETE)
+            return QVA_ERR_UNSUPPORTED;
+    }
     if (!P->q)
         return QVA_ERR_ARG;
     if (!aligned(P->q, 8))
@@ -175,18 +192,33 @@ bool lambda_tiled(const qva_problem* P)
     return P->lambda_kind == QVA_LAMBDA_ARRAY && P->n_qubits > kTileBits;
 }
 
-// The complete graph's mixer in closed form (no transform) for n > 12.
+// The complete graph's mixer in closed form (no transform): n > 12, or any
+// N that is not a power of two.
 bool complete_closed_form(const qva_problem* P)
 {
     return P->mixer == QVA_MIX_CIRCULANT && P->lambda_kind == QVA_LAMBDA_COMPLETE &&
-           P->n_qubits > kTileBits;
+           (P->n_qubits > kTileBits || problem_N(P) != (int64_t(1) << P->n_qubits));
+}
+
+// Blocks of the closed-form passes (kCompleteChunk amplitudes each, the last
+// one possibly partial).
+int64_t cpl_blocks(const qva_problem* P)
+{
+    return (problem_N(P) + kCompleteChunk - 1) / kCompleteChunk;
+}
+
+// Bytes of the closed-form evolution's partial sums (also the p = 0 path).
+size_t cpl_partials_bytes(const qva_problem* P)
+{
+    const int64_t b = cpl_blocks(P), e = expect_partial_count(problem_N(P));
+    return (size_t)(b > e ? b : e) * sizeof(double2);
 }
 
 std::vector<Launch> fft_launches(const qva_problem* P, int p, bool store)
 {
     const int n = P->n_qubits;
     std::vector<Launch> L;
-    if (n <= kTileBits) {
+    if (n <= kTileBits && !complete_closed_form(P)) {
         L.push_back({QVA_PASS_WHOLE, 0, 0, -1, -1, -1});
         return L;
     }
@@ -239,20 +271,37 @@ double fft_launch_bytes(const Launch& l, int n, bool store, bool tiled)
         return (2 * amp + real) * N;
     case QVA_PASS_LAMBDA_PREP:
         return 2 * real * N;
-    case QVA_PASS_CPL_FIRST:
-        return (real + amp) * N + 16.0 * std::ldexp(1.0, n - kTileBits);
-    case QVA_PASS_CPL_LAYER:
-        return (2 * amp + real) * N + 16.0 * std::ldexp(1.0, n - kTileBits);
-    case QVA_PASS_CPL_LAST:
-        return (amp + real) * N + 16.0 * std::ldexp(1.0, n - kTileBits);
-    case QVA_PASS_CPL_LAST_STORE:
-        return (2 * amp + real) * N + 16.0 * std::ldexp(1.0, n - kTileBits);
-    case QVA_PASS_CPL_SUM:
-        return 16.0 * std::ldexp(1.0, n - kTileBits);
     default: {
         Launch x = l;
         return launch_bytes(x, n, store);
     }
+    }
+}
+
+// Algorithmic bytes of the closed-form complete-graph launches (any N).
+double cpl_launch_bytes(const Launch& l, const qva_problem* P, int p)
+{
+    const double N = (double)problem_N(P), parts = 16.0 * (double)cpl_blocks(P);
+    const double amp = 16.0, real = 8.0;
+    switch (l.kind) {
+    case QVA_PASS_CPL_FIRST:
+        return (real + amp) * N + parts;
+    case QVA_PASS_CPL_LAYER:
+        return (2 * amp + real) * N + parts;
+    case QVA_PASS_CPL_LAST:
+        return (amp + real) * N + parts;
+    case QVA_PASS_CPL_LAST_STORE:
+        return (2 * amp + real) * N + parts;
+    case QVA_PASS_CPL_SUM:
+        return parts;
+    case QVA_PASS_INIT:
+        return amp * N;
+    case QVA_PASS_EXPECT:
+        return (amp + real) * N;
+    case QVA_PASS_REDUCE:
+        return 16.0 * (double)(p == 0 ? expect_partial_count(problem_N(P)) : cpl_blocks(P));
+    default:
+        return 0.0;
     }
 }
 
@@ -343,12 +392,13 @@ int evolve_circ(const qva_problem* P, const double* gammas, const double* ts, in
                 EventHook& hook)
 {
     const int n = P->n_qubits;
-    const int64_t N = int64_t(1) << n;
+    const int64_t N = problem_N(P);
+    const bool closed = complete_closed_form(P);
     const std::vector<XGroup> groups = x_groups(n);
     double2* partials = reinterpret_cast<double2*>(work);
     double* lam_tiles = n > kTileBits ? reinterpret_cast<double*>(work + circ_partials_bytes(n)) : nullptr;
     // complete graph in closed form: the running state sum follows the partials
-    double2* state_sum = n > kTileBits ? reinterpret_cast<double2*>(work + circ_partials_bytes(n)) : nullptr;
+    double2* state_sum = closed ? reinterpret_cast<double2*>(work + align256(cpl_partials_bytes(P))) : nullptr;
     const bool tiled = lambda_tiled(P);
     for (const Launch& l : fft_launches(P, p, store)) {
         hipError_t e = hipSuccess;
@@ -377,7 +427,8 @@ int evolve_circ(const qva_problem* P, const double* gammas, const double* ts, in
             e = launch_expect_partials(psi, P->q, N, partials, s);
             break;
         case QVA_PASS_REDUCE: {
-            const int64_t count = p == 0 ? expect_partial_count(N) : (int64_t(1) << (n - kTileBits));
+            const int64_t count = p == 0 ? expect_partial_count(N)
+                                         : (closed ? cpl_blocks(P) : (int64_t(1) << (n - kTileBits)));
             e = launch_final_reduce(partials, count, out_f, out_norm, s);
             break;
         }
@@ -385,8 +436,7 @@ int evolve_circ(const qva_problem* P, const double* gammas, const double* ts, in
             e = launch_lambda_tiles(P->lambda, lam_tiles, n, s);
             break;
         case QVA_PASS_CPL_SUM:
-            e = launch_final_reduce(partials, int64_t(1) << (n - kTileBits), &state_sum->x,
-                                    &state_sum->y, s);
+            e = launch_final_reduce(partials, cpl_blocks(P), &state_sum->x, &state_sum->y, s);
             break;
         case QVA_PASS_CPL_FIRST:
         case QVA_PASS_CPL_LAYER:
@@ -399,7 +449,7 @@ int evolve_circ(const qva_problem* P, const double* gammas, const double* ts, in
             c.ts = ts;
             c.sum_in = state_sum;
             c.partials = partials;
-            c.n = n;
+            c.N = N;
             c.mix_layer = l.layer1;
             c.phase_layer = l.phase_layer;
             c.flags = l.xmode;
@@ -442,21 +492,18 @@ struct GradLayout {
     size_t fpart = 0, slots = 0, sums = 0, lam = 0, part = 0, state = 0, total = 0;
 };
 
-size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 GradLayout grad_layout(const qva_problem* P, int p)
 {
     GradLayout g;
     const int n = P->n_qubits;
-    if (n <= kTileBits)
-        return g;
-    g.tiles = int64_t(1) << (n - kTileBits);
-    g.G = P->mixer == QVA_MIX_X ? (int)x_groups(n).size() : 1;
     if (complete_closed_form(P)) {
         // (f, norm) partials, per-block parts, running sums, then 2p slot sums
+        g.tiles = cpl_blocks(P);
+        g.G = 1;
         size_t off = 0;
         g.fpart = off;
-        off = align256(off + (size_t)g.tiles * sizeof(double2));
+        off = align256(off + cpl_partials_bytes(P));
         g.part = off;
         off = align256(off + (size_t)g.tiles * kCompleteParts * sizeof(double));
         g.state = off;
@@ -467,6 +514,10 @@ GradLayout grad_layout(const qva_problem* P, int p)
         g.total = off;
         return g;
     }
+    if (n <= kTileBits)
+        return g;
+    g.tiles = int64_t(1) << (n - kTileBits);
+    g.G = P->mixer == QVA_MIX_X ? (int)x_groups(n).size() : 1;
     g.nslots = p * (g.G + 1);
     size_t off = 0;
     g.fpart = off;
@@ -496,7 +547,7 @@ std::vector<GLaunch> grad_launches(const qva_problem* P, int p)
     std::vector<GLaunch> L;
     const int n = P->n_qubits;
     const bool circ = P->mixer == QVA_MIX_CIRCULANT;
-    if (n <= kTileBits) {
+    if (n <= kTileBits && !complete_closed_form(P)) {
         L.push_back({QVA_PASS_GRAD_WHOLE, -1, 0, -1, -1, -1, -1, -1, -1});
         return L;
     }
@@ -586,8 +637,9 @@ std::vector<GLaunch> grad_launches(const qva_problem* P, int p)
 double grad_launch_bytes(const GLaunch& l, const qva_problem* P, int p)
 {
     const int n = P->n_qubits;
-    const double N = std::ldexp(1.0, n);
+    const double N = (double)problem_N(P);
     const bool tiled = P->mixer == QVA_MIX_CIRCULANT && lambda_tiled(P);
+    const double blocks = (double)cpl_blocks(P);
     switch (l.kind) {
     case QVA_PASS_GRAD_WHOLE:
         return 8.0 * N * (tiled ? 2 : 1);
@@ -608,13 +660,15 @@ double grad_launch_bytes(const GLaunch& l, const qva_problem* P, int p)
         return 8.0 * (double)g.nslots * (double)g.tiles;
     }
     case QVA_PASS_GRAD_CPL_TURN:
-        return 56.0 * N + 16.0 * (1 + kCompleteParts / 2) * std::ldexp(1.0, n - kTileBits);
+        return 56.0 * N + 16.0 * (1 + kCompleteParts / 2) * blocks;
     case QVA_PASS_GRAD_CPL_BACK:
-        return (l.mode == GCMODE_BACK ? 72.0 : 40.0) * N + 8.0 * kCompleteParts * std::ldexp(1.0, n - kTileBits);
+        return (l.mode == GCMODE_BACK ? 72.0 : 40.0) * N + 8.0 * kCompleteParts * blocks;
     case QVA_PASS_GRAD_CPL_SUM:
-        return 8.0 * kCompleteParts * std::ldexp(1.0, n - kTileBits);
+        return 8.0 * kCompleteParts * blocks;
     default: {
         Launch x{l.kind, l.group, l.mode, l.t1, l.t2, l.gamma};
+        if (complete_closed_form(P))
+            return cpl_launch_bytes(x, P, p);
         return P->mixer == QVA_MIX_CIRCULANT ? fft_launch_bytes(x, n, false, tiled) : launch_bytes(x, n, false);
     }
     }
@@ -624,7 +678,7 @@ int grad_run(const qva_problem* P, const double* gammas, const double* ts, int p
              double* out_f, double* dgammas, double* dts, char* work, hipStream_t s, EventHook& hook)
 {
     const int n = P->n_qubits;
-    const int64_t N = int64_t(1) << n;
+    const int64_t N = problem_N(P);
     const bool circ = P->mixer == QVA_MIX_CIRCULANT;
     const std::vector<XGroup> groups = x_groups(n);
     const GradLayout W = grad_layout(P, p);
@@ -679,7 +733,7 @@ int grad_run(const qva_problem* P, const double* gammas, const double* ts, int p
             c.ts = ts;
             c.sum_in = cstate;
             c.partials = fpart;
-            c.n = n;
+            c.N = N;
             c.mix_layer = l.t1;
             c.phase_layer = l.gamma;
             c.flags = l.mode;
@@ -700,7 +754,7 @@ int grad_run(const qva_problem* P, const double* gammas, const double* ts, int p
             c.sums_in = l.kind == QVA_PASS_GRAD_CPL_TURN ? cstate : cstate + 1;
             c.part = cpart;
             c.fpart = fpart;
-            c.n = n;
+            c.N = N;
             c.layer = l.t1;
             c.flags = l.mode;
             e = launch_complete_grad(c, s);
@@ -935,6 +989,11 @@ size_t qva_workspace_bytes(const qva_problem* P, int p, int for_grad)
     if (check_problem(P, p) != QVA_OK)
         return 0;
     const int n = P->n_qubits;
+    if (complete_closed_form(P)) {
+        if (for_grad && p > 0)
+            return grad_layout(P, p).total;
+        return align256(cpl_partials_bytes(P)) + 256;  // partials, then the running state sum
+    }
     if (n <= kTileBits)
         return 0;
     if (for_grad && p > 0)
@@ -942,8 +1001,6 @@ size_t qva_workspace_bytes(const qva_problem* P, int p, int for_grad)
     size_t bytes = circ_partials_bytes(n);
     if (P->mixer == QVA_MIX_CIRCULANT && lambda_tiled(P))
         bytes += (size_t)(int64_t(1) << n) * sizeof(double);
-    if (complete_closed_form(P))
-        bytes += 256;  // the running state sum
     return bytes;
 }
 
@@ -1029,7 +1086,8 @@ int qva_plan(const qva_problem* P, int p, int for_grad, int flags, qva_pass_info
         out[i].mix_layer = l.layer1;
         out[i].mix_layer2 = l.layer2;
         out[i].phase_layer = l.phase_layer;
-        out[i].bytes = circ ? fft_launch_bytes(l, n, store, lambda_tiled(P)) : launch_bytes(l, n, store);
+        out[i].bytes = complete_closed_form(P) ? cpl_launch_bytes(l, P, p)
+                       : circ ? fft_launch_bytes(l, n, store, lambda_tiled(P)) : launch_bytes(l, n, store);
     }
     return (int)L.size();
 }

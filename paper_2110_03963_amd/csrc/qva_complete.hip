@@ -13,6 +13,11 @@
 // it; a fixed-order reduction of those sums (final_reduce) gives S_{k+1},
 // which stays in device memory for the next pass.  The first pass generates
 // psi_0 = N^{-1/2} and the last one reduces <Q> instead of writing.
+//
+// Any N >= 1 works (the solution count of a constrained problem need not be a
+// power of two): blocks hold kCompleteChunk amplitudes and the last block's
+// lanes beyond N load zeros, add nothing to the sums and store nothing.  For
+// N = 2^n, t N is exact; otherwise it is rounded once.
 #include "qva_internal.h"
 
 namespace qva {
@@ -20,41 +25,45 @@ namespace {
 
 constexpr int kRegsC = kCompleteChunk / kThreads;
 
+// Amplitude r of a thread is in range (the last block may be partial).
+__device__ __forceinline__ bool in_range(int64_t base, int r, int64_t N) { return base + r * kThreads < N; }
+
 template <int FLAGS>
 __global__ __launch_bounds__(kThreads) void complete_kernel(CompleteParams P)
 {
     __shared__ double red[2 * (kThreads / 64)];
     const int t = threadIdx.x;
     const int64_t base = (int64_t)blockIdx.x * kCompleteChunk + t;
+    const double Nd = (double)P.N;
 
     double2 v[kRegsC];
     double qq[kRegsC];
     if constexpr (FLAGS & CP_INIT) {
-        const double a0 = 1.0 / sqrt(ldexp(1.0, P.n));
+        const double a0 = 1.0 / sqrt(Nd);
 #pragma unroll
         for (int r = 0; r < kRegsC; ++r)
-            v[r] = make_double2(a0, 0.0);
+            v[r] = in_range(base, r, P.N) ? make_double2(a0, 0.0) : make_double2(0.0, 0.0);
     } else {
 #pragma unroll
         for (int r = 0; r < kRegsC; ++r)
-            v[r] = ld_nt(P.psi + base + r * kThreads);
+            v[r] = in_range(base, r, P.N) ? ld_nt(P.psi + base + r * kThreads) : make_double2(0.0, 0.0);
     }
     if constexpr (FLAGS & (CP_PHASE | CP_EXPECT)) {
 #pragma unroll
         for (int r = 0; r < kRegsC; ++r)
-            qq[r] = ld_nt(P.q + base + r * kThreads);
+            qq[r] = in_range(base, r, P.N) ? ld_nt(P.q + base + r * kThreads) : 0.0;
     }
     if constexpr (FLAGS & CP_MIX) {
         const double tm = P.ts[P.mix_layer];
-        const double2 eit = expmi(-tm);                    // e^{i t}
-        const double2 e = expmi(tm * ldexp(1.0, P.n));     // e^{-i t N}, t N exact
-        const double invN = ldexp(1.0, -P.n);
+        const double2 eit = expmi(-tm);   // e^{i t}
+        const double2 e = expmi(tm * Nd);  // e^{-i t N}
+        const double invN = 1.0 / Nd;
         const double2 c = make_double2((e.x - 1.0) * invN, e.y * invN);
         const double2 d = cmul(eit, cmul(c, *P.sum_in));  // e^{it} c S, the same for every j
 #pragma unroll
         for (int r = 0; r < kRegsC; ++r) {
             const double2 w = cmul(eit, v[r]);
-            v[r] = make_double2(w.x + d.x, w.y + d.y);
+            v[r] = in_range(base, r, P.N) ? make_double2(w.x + d.x, w.y + d.y) : make_double2(0.0, 0.0);
         }
     }
     if constexpr (FLAGS & CP_PHASE) {
@@ -91,7 +100,8 @@ __global__ __launch_bounds__(kThreads) void complete_kernel(CompleteParams P)
     if constexpr (FLAGS & CP_STORE) {
 #pragma unroll
         for (int r = 0; r < kRegsC; ++r)
-            st_nt(P.psi + base + r * kThreads, v[r]);
+            if (in_range(base, r, P.N))
+                st_nt(P.psi + base + r * kThreads, v[r]);
     }
 }
 
@@ -109,33 +119,37 @@ __global__ __launch_bounds__(kThreads) void complete_grad_kernel(CompleteGradPar
     __shared__ double red[kCompleteParts * (kThreads / 64)];
     const int t = threadIdx.x;
     const int64_t base = (int64_t)blockIdx.x * kCompleteChunk + t;
-    const double invN = ldexp(1.0, -P.n);
+    const double Nd = (double)P.N;
+    const double invN = 1.0 / Nd;
     const double tm = P.ts[P.layer];
 
+    // lanes beyond N hold zeros, which every update below keeps at zero
+    // (no term is added to them) and which add nothing to any sum
     double2 a[kRegsC], b[kRegsC];
     double qq[kRegsC];
 #pragma unroll
     for (int r = 0; r < kRegsC; ++r) {
-        a[r] = ld_nt(P.phi + base + r * kThreads);
-        qq[r] = ld_nt(P.q + base + r * kThreads);
+        const bool in = in_range(base, r, P.N);
+        a[r] = in ? ld_nt(P.phi + base + r * kThreads) : make_double2(0.0, 0.0);
+        qq[r] = in ? ld_nt(P.q + base + r * kThreads) : 0.0;
     }
     if constexpr (MODE != GCMODE_TURN) {
 #pragma unroll
         for (int r = 0; r < kRegsC; ++r)
-            b[r] = ld_nt(P.chi + base + r * kThreads);
+            b[r] = in_range(base, r, P.N) ? ld_nt(P.chi + base + r * kThreads) : make_double2(0.0, 0.0);
     }
     double parts[kCompleteParts] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if constexpr (MODE == GCMODE_TURN) {
         // psi_p = e^{it} (phi + c S), c = (e^{-itN} - 1)/N; chi = Q psi_p
         const double2 eit = expmi(-tm);
-        const double2 e = expmi(tm * ldexp(1.0, P.n));
+        const double2 e = expmi(tm * Nd);
         const double2 c = make_double2((e.x - 1.0) * invN, e.y * invN);
         const double2 d = cmul(eit, cmul(c, P.sums_in[0]));
         double f = 0.0, nr = 0.0;
 #pragma unroll
         for (int r = 0; r < kRegsC; ++r) {
             const double2 w = cmul(eit, a[r]);
-            a[r] = make_double2(w.x + d.x, w.y + d.y);
+            a[r] = in_range(base, r, P.N) ? make_double2(w.x + d.x, w.y + d.y) : make_double2(0.0, 0.0);
             b[r] = make_double2(qq[r] * a[r].x, qq[r] * a[r].y);
             const double pr = a[r].x * a[r].x + a[r].y * a[r].y;
             f = fma(pr, qq[r], f);
@@ -147,7 +161,7 @@ __global__ __launch_bounds__(kThreads) void complete_grad_kernel(CompleteGradPar
     } else {
         // inverse mixer: e^{-it} (x + conj(c) S_x)
         const double2 emit = expmi(tm);                                  // e^{-it}
-        const double2 e = expmi(-tm * ldexp(1.0, P.n));                  // e^{+itN}
+        const double2 e = expmi(-tm * Nd);                               // e^{+itN}
         const double2 cb = make_double2((e.x - 1.0) * invN, e.y * invN);  // conj(c)
         const double2 da = cmul(emit, cmul(cb, P.sums_in[0]));
         const double2 db = cmul(emit, cmul(cb, P.sums_in[1]));
@@ -155,10 +169,11 @@ __global__ __launch_bounds__(kThreads) void complete_grad_kernel(CompleteGradPar
         double gq = 0.0;
 #pragma unroll
         for (int r = 0; r < kRegsC; ++r) {
+            const bool in = in_range(base, r, P.N);
             double2 w = cmul(emit, a[r]);
-            a[r] = make_double2(w.x + da.x, w.y + da.y);
+            a[r] = in ? make_double2(w.x + da.x, w.y + da.y) : make_double2(0.0, 0.0);
             w = cmul(emit, b[r]);
-            b[r] = make_double2(w.x + db.x, w.y + db.y);
+            b[r] = in ? make_double2(w.x + db.x, w.y + db.y) : make_double2(0.0, 0.0);
             gq = fma(qq[r], b[r].x * a[r].y - b[r].y * a[r].x, gq);
             const double2 ph = expmi(-gamma * qq[r]);  // exp(+i gamma q)
             a[r] = cmul(a[r], ph);
@@ -199,8 +214,10 @@ __global__ __launch_bounds__(kThreads) void complete_grad_kernel(CompleteGradPar
     if constexpr (MODE != GCMODE_BACK_LAST) {
 #pragma unroll
         for (int r = 0; r < kRegsC; ++r) {
-            st_nt(P.phi + base + r * kThreads, a[r]);
-            st_nt(P.chi + base + r * kThreads, b[r]);
+            if (in_range(base, r, P.N)) {
+                st_nt(P.phi + base + r * kThreads, a[r]);
+                st_nt(P.chi + base + r * kThreads, b[r]);
+            }
         }
     }
 }
@@ -253,9 +270,9 @@ __global__ __launch_bounds__(kGsumThreads) void complete_gsum_kernel(const doubl
 
 hipError_t launch_complete_grad(const CompleteGradParams& P, hipStream_t s)
 {
-    if (P.n <= kTileBits)
+    if (P.N < 1)
         return hipErrorInvalidValue;
-    const dim3 grid((unsigned)(int64_t(1) << (P.n - kTileBits)));
+    const dim3 grid((unsigned)((P.N + kCompleteChunk - 1) / kCompleteChunk));
     switch (P.flags) {
     case GCMODE_TURN:
         hipLaunchKernelGGL(complete_grad_kernel<GCMODE_TURN>, grid, dim3(kThreads), 0, s, P);
@@ -282,9 +299,9 @@ hipError_t launch_complete_gsum(const double* part, int64_t blocks, double2* sta
 
 hipError_t launch_complete(const CompleteParams& P, hipStream_t s)
 {
-    if (P.n <= kTileBits)
+    if (P.N < 1)
         return hipErrorInvalidValue;
-    const dim3 grid((unsigned)(int64_t(1) << (P.n - kTileBits)));
+    const dim3 grid((unsigned)((P.N + kCompleteChunk - 1) / kCompleteChunk));
     switch (P.flags) {
     case CPMODE_FIRST:
         hipLaunchKernelGGL(complete_kernel<CPMODE_FIRST>, grid, dim3(kThreads), 0, s, P);

@@ -163,7 +163,7 @@ struct CompleteParams {
     const double* ts;      // device, p
     const double2* sum_in; // device: sum over the input state (CP_MIX)
     double2* partials;     // one per block: sums (CP_SUM) or (<Q>, norm) (CP_EXPECT)
-    int n;
+    int64_t N;             // amplitudes (any N >= 1; the last block may be partial)
     int mix_layer;         // layer of the mixer (CP_MIX)
     int phase_layer;       // layer of the phase (CP_PHASE)
     int flags;
@@ -189,7 +189,7 @@ struct CompleteGradParams {
     const double2* sums_in;  // TURN: sum of the input phi; BACK: (S_phi, S_chi) of the input
     double* part;            // kCompleteParts per block
     double2* fpart;          // TURN: per-block (<Q>, norm)
-    int n;
+    int64_t N;
     int layer;
     int flags;               // GCMODE_*
 };

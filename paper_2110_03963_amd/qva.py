@@ -114,14 +114,23 @@ class Problem:
 
     mixer "x": W = sum_i X_i on log2(len(q)) qubits.
     mixer "circulant": W circulant with eigenvalues lam (natural order) or
-    lambda_kind "ring" / "complete".
+    lambda_kind "ring" / "complete".  With the complete graph len(q) may be
+    any N >= 2 (the solution count of a constrained problem); the other
+    mixers need a power of two.
     """
 
     def __init__(self, q: torch.Tensor, mixer: str = "x", lam: torch.Tensor | None = None,
                  lambda_kind: str = "array"):
         _need(q, torch.float64, "q")
         self.q = q
-        self.n = _log2(q.numel())
+        N = q.numel()
+        self._N = N
+        if mixer == "circulant" and lambda_kind == "complete" and N >= 2 and (N & (N - 1)):
+            self.n = int(N - 1).bit_length()  # log2 N rounded up
+            n_states = N
+        else:
+            self.n = _log2(N)
+            n_states = 0
         self.mixer = mixer
         self.lambda_kind = lambda_kind if mixer == "circulant" else "array"
         self.lam = lam
@@ -131,11 +140,11 @@ class Problem:
                 raise ValueError("lam and q differ in length")
         self._c = _lib.QvaProblem(MIXERS[mixer], self.n, _ptr(q),
                                   _ptr(lam) if (mixer == "circulant" and lambda_kind == "array") else None,
-                                  LAMBDA_KINDS[self.lambda_kind])
+                                  LAMBDA_KINDS[self.lambda_kind], n_states)
 
     @property
     def N(self) -> int:
-        return 1 << self.n
+        return self._N
 
     @property
     def device(self):

@@ -140,6 +140,35 @@ def test_evolve_complete_closed_form(n, p):
     assert abs(f_a.item() - f_tr) <= F_TOL * np.mean(np.abs(q))
 
 
+@pytest.mark.parametrize("N", [2, 3, 5, 1000, 4095, 4097, 100003, 3000017])
+@pytest.mark.parametrize("p", [0, 1, 3])
+def test_evolve_complete_any_n(N, p):
+    """Complete graph on N solutions, N not a power of two (a constrained
+    problem's |S'|): closed-form passes with a partial last block, against the
+    oracle's closed form; state, f and norm."""
+    rng = np.random.default_rng(N + 7 * p)
+    q = rng.uniform(-1, 4, N)
+    g = rng.uniform(0, math.pi, p)
+    t = rng.uniform(0, math.pi, p)
+    prob = qva.Problem(to_dev(q), "circulant", None, "complete")
+    assert prob.N == N
+    f, nrm, psi = qva.evolve(prob, g, t, store=True)
+    psi_ref, f_ref, n_ref = oracle.evolve("complete", q, g, t)
+    assert psi.numel() == N
+    assert f_rel_err(f.item(), f_ref, psi_ref, q) < F_TOL
+    assert abs(nrm.item() - n_ref) < 1e-13
+    assert state_err(psi.cpu().numpy(), psi_ref) < PSI_TOL
+    f2, _, _ = qva.evolve(prob, g, t, store=False)
+    assert f2.item() == f.item()
+
+
+def test_non_power_of_two_needs_complete_graph():
+    q = to_dev(np.ones(1000))
+    for mixer, kind in [("x", "array"), ("circulant", "ring")]:
+        with pytest.raises(ValueError):
+            qva.Problem(q, mixer, None, kind)
+
+
 @pytest.mark.parametrize("n", [13, 17])
 def test_evolve_complete_degenerate_angles(n):
     """t = 0 and t N a multiple of 2 pi (c = 0) leave only global phases: f

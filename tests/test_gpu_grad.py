@@ -95,6 +95,21 @@ def test_grad_complete_closed_form(n, p):
     assert f2.item() == f and np.array_equal(dg2.cpu().numpy(), dg) and np.array_equal(dt2.cpu().numpy(), dt)
 
 
+@pytest.mark.parametrize("N,p", [(7, 2), (5000, 3), (200003, 4), (1000003, 2)])
+def test_grad_complete_any_n(N, p):
+    """Closed-form adjoint on N solutions, N not a power of two, against the
+    oracle's closed-form adjoint."""
+    rng = np.random.default_rng(N + p)
+    q = rng.uniform(-1, 3, N)
+    g = rng.uniform(0, math.pi, p)
+    t = rng.uniform(0, math.pi, p)
+    prob = qva.Problem(to_dev(q), "circulant", None, "complete")
+    f, dg, dt = qva.grad(prob, g, t)
+    f_ref, rg, rt = oracle.grad("complete", q, g, t)
+    assert abs(f.item() - f_ref) <= F_TOL * max(abs(f_ref), np.mean(np.abs(q)))
+    assert _gerr(dg.cpu().numpy(), dt.cpu().numpy(), rg, rt) < G_TOL
+
+
 def test_grad_n12_regular3_p12():
     """The adjoint-gradient workload's oracle-parity size: weighted 3-regular
     MaxCut, n = 12, p = 12 (24 parameters)."""

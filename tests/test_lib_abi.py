@@ -50,8 +50,8 @@ def test_status_strings(lib):
 FAKE = 0x7F0000001000  # never dereferenced: every call below fails validation first
 
 
-def _prob(mixer=0, n=20, q=FAKE, lam=None, kind=0):
-    return _lib.QvaProblem(mixer, n, q, lam, kind)
+def _prob(mixer=0, n=20, q=FAKE, lam=None, kind=0, n_states=0):
+    return _lib.QvaProblem(mixer, n, q, lam, kind, n_states)
 
 
 def test_validation_errors(lib):
@@ -180,8 +180,8 @@ def test_plan_complete_closed_form(lib, n, p):
         parts = 16 * (N >> 12)
         bytes_ = [x.bytes for x in arr if x.kind in (26, 27, 28, 29)]
         assert bytes_ == [24 * N + parts] + [40 * N + parts] * (p - 1) + [(24 if flags else 40) * N + parts]
-    # the running state sum needs 256 bytes after the partials
-    assert lib.qva_workspace_bytes(ctypes.byref(pr), p, 0) == 16 * (N >> 12) + 256
+    # the running state sum takes 256 bytes after the (256-aligned) partials
+    assert lib.qva_workspace_bytes(ctypes.byref(pr), p, 0) == ((16 * (N >> 12) + 255) // 256) * 256 + 256
     # depth 0 and small n keep their plans
     assert [x for x in [lib.qva_plan(ctypes.byref(pr), 0, 0, 0, None, 0)]] == [3]
     small = _prob(mixer=1, n=12, kind=2, lam=None)
@@ -209,6 +209,56 @@ def test_grad_plan_complete_closed_form(lib, n, p):
     # workspace: (f, norm) partials, 8 doubles per block, running sums, 2p sums
     ws = lib.qva_workspace_bytes(ctypes.byref(pr), p, 1)
     assert ws >= 16 * (N >> 12) + 64 * (N >> 12) + 64 + 16 * p
+
+
+def test_n_states_validation(lib):
+    """A non-power-of-two N must satisfy 2^(n-1) < N < 2^n and is accepted
+    for the complete-graph mixer only."""
+    S = _lib
+    ref = ctypes.byref
+    ws = 1 << 30
+    ok = _prob(mixer=1, n=17, kind=2, n_states=100003)
+    assert lib.qva_plan(ref(ok), 3, 0, 0, None, 0) > 0
+    for bad, st in [(_prob(mixer=1, n=17, kind=2, n_states=65536), S.QVA_ERR_SIZE),
+                    (_prob(mixer=1, n=17, kind=2, n_states=131073), S.QVA_ERR_SIZE),
+                    (_prob(mixer=1, n=17, kind=2, n_states=-5), S.QVA_ERR_SIZE),
+                    (_prob(mixer=1, n=17, kind=1, n_states=100003), S.QVA_ERR_UNSUPPORTED),
+                    (_prob(mixer=1, n=17, kind=0, lam=FAKE, n_states=100003), S.QVA_ERR_UNSUPPORTED),
+                    (_prob(mixer=0, n=17, n_states=100003), S.QVA_ERR_UNSUPPORTED)]:
+        assert lib.qva_evolve(ref(bad), FAKE, FAKE, 3, FAKE, FAKE, None, 0, FAKE, ws, None) == st
+        assert lib.qva_plan(ref(bad), 3, 0, 0, None, 0) == st
+    # n_states equal to 2^n is the same as 0
+    same = _prob(mixer=1, n=17, kind=2, n_states=1 << 17)
+    assert lib.qva_workspace_bytes(ref(same), 3, 0) == lib.qva_workspace_bytes(ref(_prob(mixer=1, n=17, kind=2)), 3, 0)
+
+
+@pytest.mark.parametrize("N,n", [(3, 2), (1000, 10), (4097, 13), (100003, 17), (5000011, 23)])
+@pytest.mark.parametrize("p", [0, 1, 4])
+def test_plan_complete_any_n(lib, N, n, p):
+    """Closed-form plans for a non-power-of-two N (the solution count of a
+    constrained problem): one pass per layer, ceil(N / 4096) blocks."""
+    pr = _prob(mixer=1, n=n, kind=2, n_states=N)
+    blocks = -(-N // 4096)
+    parts = 16 * blocks
+    cnt = lib.qva_plan(ctypes.byref(pr), p, 0, 1, None, 0)
+    arr = (_lib.QvaPassInfo * cnt)()
+    assert lib.qva_plan(ctypes.byref(pr), p, 0, 1, arr, cnt) == cnt
+    kinds = [x.kind for x in arr]
+    if p == 0:
+        assert kinds == [6, 7, 8]
+    else:
+        assert kinds == [26, 30] + [27, 30] * (p - 1) + [28, 8]
+        b = [x.bytes for x in arr if x.kind in (26, 27, 28)]
+        assert b == [24 * N + parts] + [40 * N + parts] * (p - 1) + [24 * N + parts]
+    expect_parts = min(-(-N // 4096), 4096)
+    ws = lib.qva_workspace_bytes(ctypes.byref(pr), p, 0)
+    assert ws == ((16 * max(blocks, expect_parts) + 255) // 256) * 256 + 256
+    if p > 0:
+        cnt = lib.qva_plan(ctypes.byref(pr), p, 1, 0, None, 0)
+        arr = (_lib.QvaPassInfo * cnt)()
+        assert lib.qva_plan(ctypes.byref(pr), p, 1, 0, arr, cnt) == cnt
+        assert [x.kind for x in arr] == [26, 30] + [27, 30] * (p - 1) + [31, 33] + [32, 33] * p + [8, 25]
+        assert lib.qva_workspace_bytes(ctypes.byref(pr), p, 1) > 0
 
 
 def _grad_plan(lib, mixer, n, p, kind=1):
