@@ -63,6 +63,7 @@ def _load():
     lib.oracle_apply_hypercube.argtypes = [Ci, P, P]
     lib.oracle_dft.argtypes = [I64, P, P, Ci]
     lib.oracle_fft.argtypes = [I64, P, Ci]
+    lib.oracle_bluestein.argtypes = [I64, P, Ci]
     lib.oracle_mix_circulant.argtypes = [I64, P, P, D]
     lib.oracle_apply_circulant.argtypes = [I64, P, P, P]
     lib.oracle_mix_complete.argtypes = [I64, P, D]
@@ -144,6 +145,13 @@ def mix_circulant(psi, lam, t: float) -> np.ndarray:
     lam = _f64(lam)
     _load().oracle_mix_circulant(len(psi), _ptr(psi), _ptr(lam), float(t))
     return psi
+
+
+def bluestein(x, sign: int = -1) -> np.ndarray:
+    """sum_j x_j exp(sign 2 pi i j m / N) for any N (chirp-z over radix-2 FFTs)."""
+    x = _c128(x).copy()
+    _load().oracle_bluestein(len(x), _ptr(x), int(sign))
+    return x
 
 
 def mix_complete(psi, t: float) -> np.ndarray:

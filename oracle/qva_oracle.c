@@ -139,6 +139,8 @@ void oracle_apply_hypercube(int n, const cplx *psi, cplx *out)
 /* transform uses sign = -1, the inverse sign = +1 (and a 1/N elsewhere).   */
 /* ---------------------------------------------------------------------- */
 
+static int log2_exact(int64_t N);
+
 static cplx root_of_unity(int64_t k, int64_t N, int sign)
 {
     /* exp(sign * 2 pi i k / N) computed directly from the reduced integer
@@ -210,8 +212,43 @@ void oracle_fft(int64_t N, cplx *x, int sign)
     free(w);
 }
 
+/* Bluestein's chirp-z transform: the same sum as oracle_dft for any N       */
+/* (here N < 2^31), through three radix-2 FFTs of a power of two M >= 2N-1.  */
+/* With u_k = exp(sign i pi k^2 / N), jm = (j^2 + m^2 - (m-j)^2) / 2 gives    */
+/*   out_m = u_m sum_j (x_j u_j) conj(u_{m-j}),                               */
+/* a linear convolution, done cyclically in length M with conj(u_k) placed   */
+/* at k and M - k.  k^2 is reduced mod 2N exactly before the angle.  In place. */
+void oracle_bluestein(int64_t N, cplx *x, int sign)
+{
+    int64_t M = 1;
+    while (M < 2 * N - 1)
+        M <<= 1;
+    cplx *u = malloc(sizeof(cplx) * (size_t)N);
+    cplx *a = calloc((size_t)M, sizeof(cplx));
+    cplx *v = calloc((size_t)M, sizeof(cplx));
+    for (int64_t k = 0; k < N; ++k) {
+        const int64_t r = (int64_t)(((uint64_t)k * (uint64_t)k) % (uint64_t)(2 * N));
+        u[k] = cexp((double)sign * I * PI * (double)r / (double)N);
+    }
+    for (int64_t j = 0; j < N; ++j)
+        a[j] = x[j] * u[j];
+    v[0] = conj(u[0]);
+    for (int64_t k = 1; k < N; ++k)
+        v[k] = v[M - k] = conj(u[k]);
+    oracle_fft(M, a, -1);
+    oracle_fft(M, v, -1);
+    for (int64_t i = 0; i < M; ++i)
+        a[i] *= v[i];
+    oracle_fft(M, a, +1);
+    for (int64_t m = 0; m < N; ++m)
+        x[m] = u[m] * a[m] / (double)M;
+    free(u);
+    free(a);
+    free(v);
+}
+
 /* Forward/inverse transform used by the circulant mixer: naive DFT for     */
-/* small N, the radix-2 FFT otherwise (N a power of two).                    */
+/* small N, the radix-2 FFT for larger powers of two, Bluestein otherwise.   */
 static void transform(int64_t N, cplx *x, int sign)
 {
     if (N <= 4096) {
@@ -219,8 +256,10 @@ static void transform(int64_t N, cplx *x, int sign)
         oracle_dft(N, x, tmp, sign);
         memcpy(x, tmp, sizeof(cplx) * (size_t)N);
         free(tmp);
-    } else {
+    } else if (log2_exact(N) >= 0) {
         oracle_fft(N, x, sign);
+    } else {
+        oracle_bluestein(N, x, sign);
     }
 }
 
@@ -402,7 +441,7 @@ static int check_args(int kind, int64_t N)
         return -1;
     if (kind == ORACLE_MIX_X && log2_exact(N) < 0)
         return -1;
-    if (kind == ORACLE_MIX_CIRCULANT && N > 4096 && log2_exact(N) < 0)
+    if (kind == ORACLE_MIX_CIRCULANT && N >= ((int64_t)1 << 31))
         return -1;
     if (kind != ORACLE_MIX_X && kind != ORACLE_MIX_CIRCULANT && kind != ORACLE_MIX_COMPLETE)
         return -1;

@@ -434,6 +434,38 @@ def test_fft_matches_numpy_and_identities(oracle_mod, N):
         assert np.max(np.abs(oracle.fft(e, -1) - ref)) < 1e-12 * N
 
 
+@pytest.mark.parametrize("N", [3, 5, 12, 1000, 4097, 5000, 65537, 100003])
+def test_bluestein_matches_numpy_and_dft(oracle_mod, N):
+    """Chirp-z transform for any N: against numpy.fft (both signs) and, up to
+    N = 5000, against the naive DFT."""
+    rng = np.random.default_rng(N)
+    x = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    fwd = oracle.bluestein(x, -1)
+    inv = oracle.bluestein(x, +1)
+    scale = np.linalg.norm(x) * math.sqrt(N)
+    assert np.max(np.abs(fwd - np.fft.fft(x))) < 1e-13 * scale
+    assert np.max(np.abs(inv - N * np.fft.ifft(x))) < 1e-13 * scale
+    if N <= 5000:
+        assert np.max(np.abs(fwd - oracle.dft(x, -1))) < 1e-13 * scale
+
+
+@pytest.mark.parametrize("N", [5000, 20011])
+def test_circulant_non_power_of_two(oracle_mod, N):
+    """The circulant mixer at N > 4096, N not a power of two (Bluestein route):
+    ring against the closed-form DFT of numpy, and the complete graph's
+    spectrum against the oracle's closed form."""
+    rng = np.random.default_rng(N)
+    psi = _rand_state(rng, N)
+    t = 0.71
+    lam = oracle.ring_lambda(N)
+    ref = np.fft.ifft(np.exp(-1j * t * lam) * np.fft.fft(psi))
+    out = oracle.mix_circulant(psi, lam, t)
+    assert np.max(np.abs(out - ref)) < 1e-13
+    out_c = oracle.mix_circulant(psi, oracle.complete_lambda(N), t)
+    assert np.max(np.abs(out_c - oracle.mix_complete(psi, t))) < 1e-11
+    assert abs(np.linalg.norm(out) - 1) < 1e-13
+
+
 @pytest.mark.parametrize("N", [3, 12, 256])
 def test_naive_dft_matches_numpy(oracle_mod, N):
     rng = np.random.default_rng(N)
