@@ -78,9 +78,10 @@ typedef enum {
  *   lambda_kind a qva_lambda_kind (ignored for QVA_MIX_X)
  *   n_states    N when it is not a power of two (the solution count |S'| of a
  *               constrained QWOA, Sec. 2.4.2), else 0 (N = 2^n_qubits).  A
- *               non-power-of-two N needs 2^(n_qubits-1) < N < 2^n_qubits and is
- *               supported for the complete-graph mixer (QVA_ERR_UNSUPPORTED
- *               otherwise).                                                    */
+ *               non-power-of-two N needs 2^(n_qubits-1) < N < 2^n_qubits and a
+ *               circulant mixer: the complete graph (any N), or the ring or an
+ *               eigenvalue array (N < 2^31; qva_evolve only, through Bluestein's
+ *               transform).  Otherwise QVA_ERR_UNSUPPORTED.                    */
 typedef struct {
     int mixer;
     int n_qubits;
@@ -213,7 +214,18 @@ typedef enum {
     /* qva_grad with the closed-form complete-graph mixer (n > 12) */
     QVA_PASS_GRAD_CPL_TURN = 31,  /* last mixer, <Q>, chi = Q psi_p, sums for dt_p         */
     QVA_PASS_GRAD_CPL_BACK = 32,  /* inverse mixer k, <chi|Q|phi>, inverse phase k, sums   */
-    QVA_PASS_GRAD_CPL_SUM = 33    /* fixed-order sums: state sums, dt_k and dgamma_k terms */
+    QVA_PASS_GRAD_CPL_SUM = 33,   /* fixed-order sums: state sums, dt_k and dgamma_k terms */
+    /* qva_evolve with a circulant (ring or eigenvalue array) over N solutions,
+     * N not a power of two: Bluestein's chirp-z form over a padded power of two
+     * M >= 2N - 1 (middle groups use QVA_PASS_FFT_DIF / QVA_PASS_FFT_DIT) */
+    QVA_PASS_BLU_CHIRP = 34,      /* chirp filter, forward transform of the top group     */
+    QVA_PASS_BLU_TILE = 35,       /* low group forward, filter spectrum stored per tile   */
+    QVA_PASS_BLU_FIRST = 36,      /* psi_0, phase of layer 1, chirp, forward top group    */
+    QVA_PASS_BLU_MUL = 37,        /* low group forward, times the filter spectrum, inverse */
+    QVA_PASS_BLU_LAMBDA = 38,     /* inverse top group, exp(-i t lambda), forward top     */
+    QVA_PASS_BLU_PHASE = 39,      /* inverse top group, exp(-i gamma q) / N, forward top  */
+    QVA_PASS_BLU_LAST = 40,       /* inverse top group, <Q> partial sums                  */
+    QVA_PASS_BLU_LAST_STORE = 41  /* as QVA_PASS_BLU_LAST, also writes psi_p              */
 } qva_pass_kind;
 
 /* One launch of a plan.  `bytes` is the algorithmic HBM traffic of the

@@ -61,7 +61,9 @@ PASS_KINDS = {0: "whole", 1: "first", 2: "middle", 3: "boundary", 4: "last", 5: 
               20: "grad_bound", 21: "grad_final", 22: "grad_dif", 23: "grad_dit",
               24: "grad_lowdiag", 25: "grad_reduce", 26: "cpl_first", 27: "cpl_layer",
               28: "cpl_last", 29: "cpl_last_store", 30: "cpl_sum", 31: "grad_cpl_turn",
-              32: "grad_cpl_back", 33: "grad_cpl_sum"}
+              32: "grad_cpl_back", 33: "grad_cpl_sum", 34: "blu_chirp", 35: "blu_tile",
+              36: "blu_first", 37: "blu_mul", 38: "blu_lambda", 39: "blu_phase", 40: "blu_last",
+              41: "blu_last_store"}
 
 
 class QvaBatchItem(ctypes.Structure):

@@ -42,10 +42,13 @@ int check_problem(const qva_problem* P, int p)
     if (P->n_states < 0)
         return QVA_ERR_SIZE;
     if (P->n_states > 0 && P->n_states != (int64_t(1) << P->n_qubits)) {
-        // 2^(n-1) < N < 2^n, complete-graph mixer only
+        // 2^(n-1) < N < 2^n; a circulant mixer (the ring and arrays through
+        // Bluestein's transform, N < 2^31)
         if (P->n_states <= (int64_t(1) << (P->n_qubits - 1)) || P->n_states > (int64_t(1) << P->n_qubits))
             return QVA_ERR_SIZE;
-        if (P->mixer != QVA_MIX_CIRCULANT || P->lambda_kind != QVA_LAMBDA_COMPLETE)
+        if (P->mixer != QVA_MIX_CIRCULANT)
+            return QVA_ERR_UNSUPPORTED;
+        if (P->lambda_kind != QVA_LAMBDA_COMPLETE && P->n_states >= (int64_t(1) << 31))
             return QVA_ERR_UNSUPPORTED;
     }
     if (!P->q)
@@ -200,6 +203,45 @@ bool complete_closed_form(const qva_problem* P)
            (P->n_qubits > kTileBits || problem_N(P) != (int64_t(1) << P->n_qubits));
 }
 
+// A ring or eigenvalue-array circulant over N solutions, N not a power of
+// two: Bluestein's chirp-z transform over a padded power of two M.
+bool bluestein_path(const qva_problem* P)
+{
+    return P->mixer == QVA_MIX_CIRCULANT && P->lambda_kind != QVA_LAMBDA_COMPLETE &&
+           problem_N(P) != (int64_t(1) << P->n_qubits);
+}
+
+// log2 M: the smallest power of two >= 2N - 1, and at least 2^13 (tile passes).
+int blu_bits(const qva_problem* P)
+{
+    int b = kTileBits + 1;
+    while ((int64_t(1) << b) < 2 * problem_N(P) - 1)
+        ++b;
+    return b;
+}
+
+// Workspace of a Bluestein evolution: partials, then the padded buffer and the
+// two filter spectra (M amplitudes each).
+struct BluLayout {
+    size_t parts = 0, pad = 0, b0 = 0, b1 = 0, total = 0;
+};
+
+BluLayout blu_layout(const qva_problem* P)
+{
+    BluLayout L;
+    const int64_t M = int64_t(1) << blu_bits(P);
+    const int64_t e = expect_partial_count(problem_N(P)), tiles = M >> kTileBits;
+    size_t off = align256((size_t)(e > tiles ? e : tiles) * sizeof(double2));
+    L.pad = off;
+    off += (size_t)M * sizeof(double2);
+    L.b0 = off;
+    off += (size_t)M * sizeof(double2);
+    L.b1 = off;
+    off += (size_t)M * sizeof(double2);
+    L.total = off;
+    return L;
+}
+
 // Blocks of the closed-form passes (kCompleteChunk amplitudes each, the last
 // one possibly partial).
 int64_t cpl_blocks(const qva_problem* P)
@@ -218,7 +260,7 @@ std::vector<Launch> fft_launches(const qva_problem* P, int p, bool store)
 {
     const int n = P->n_qubits;
     std::vector<Launch> L;
-    if (n <= kTileBits && !complete_closed_form(P)) {
+    if (n <= kTileBits && !complete_closed_form(P) && !bluestein_path(P)) {
         L.push_back({QVA_PASS_WHOLE, 0, 0, -1, -1, -1});
         return L;
     }
@@ -237,6 +279,40 @@ std::vector<Launch> fft_launches(const qva_problem* P, int p, bool store)
         }
         L.push_back({store ? QVA_PASS_CPL_LAST_STORE : QVA_PASS_CPL_LAST, -1,
                      store ? CPMODE_LAST_STORE : CPMODE_LAST, p - 1, -1, -1});
+        L.push_back({QVA_PASS_REDUCE, -1, 0, -1, -1, -1});
+        return L;
+    }
+    if (bluestein_path(P)) {
+        // groups of the padded transform: top c, middles 1..c-1, low 0
+        const int c = (int)x_groups(blu_bits(P)).size() - 1;
+        auto conv_front = [&](std::vector<Launch>& V) {
+            for (int g = c - 1; g >= 1; --g)
+                V.push_back({QVA_PASS_FFT_DIF, g, FMODE_DIF, -1, -1, -1});
+        };
+        auto conv_back = [&](std::vector<Launch>& V) {
+            for (int g = 1; g <= c - 1; ++g)
+                V.push_back({QVA_PASS_FFT_DIT, g, FMODE_DIT, -1, -1, -1});
+        };
+        for (int which = 0; which < 2; ++which) {  // the filters w and conj(w)
+            L.push_back({QVA_PASS_BLU_CHIRP, c, FMODE_B_CHIRP, -1, which, -1});
+            conv_front(L);
+            L.push_back({QVA_PASS_BLU_TILE, 0, FMODE_LOWDIF_TILED, -1, which, -1});
+        }
+        L.push_back({QVA_PASS_BLU_FIRST, c, FMODE_B_FIRST, -1, -1, 0});
+        for (int k = 0; k < p; ++k) {
+            conv_front(L);
+            L.push_back({QVA_PASS_BLU_MUL, 0, FMODE_LOWMUL, -1, 0, -1});
+            conv_back(L);
+            L.push_back({QVA_PASS_BLU_LAMBDA, c, FMODE_B_BOUND_LAM, k, -1, -1});
+            conv_front(L);
+            L.push_back({QVA_PASS_BLU_MUL, 0, FMODE_LOWMUL, -1, 1, -1});
+            conv_back(L);
+            if (k + 1 < p)
+                L.push_back({QVA_PASS_BLU_PHASE, c, FMODE_B_BOUND_Q, -1, -1, k + 1});
+            else
+                L.push_back({store ? QVA_PASS_BLU_LAST_STORE : QVA_PASS_BLU_LAST, c,
+                             store ? FMODE_B_LAST_STORE : FMODE_B_LAST, -1, -1, -1});
+        }
         L.push_back({QVA_PASS_REDUCE, -1, 0, -1, -1, -1});
         return L;
     }
@@ -300,6 +376,44 @@ double cpl_launch_bytes(const Launch& l, const qva_problem* P, int p)
         return (amp + real) * N;
     case QVA_PASS_REDUCE:
         return 16.0 * (double)(p == 0 ? expect_partial_count(problem_N(P)) : cpl_blocks(P));
+    default:
+        return 0.0;
+    }
+}
+
+// Algorithmic bytes of the Bluestein launches (M-amplitude passes; q and
+// lambda over the N solutions).
+double blu_launch_bytes(const Launch& l, const qva_problem* P, int p)
+{
+    const double N = (double)problem_N(P), M = std::ldexp(1.0, blu_bits(P));
+    const double amp = 16.0, real = 8.0;
+    const double lam = P->lambda_kind == QVA_LAMBDA_ARRAY ? real * N : 0.0;
+    switch (l.kind) {
+    case QVA_PASS_FFT_DIF:
+    case QVA_PASS_FFT_DIT:
+        return 2 * amp * M;
+    case QVA_PASS_BLU_CHIRP:
+        return amp * M;
+    case QVA_PASS_BLU_TILE:
+        return 2 * amp * M;
+    case QVA_PASS_BLU_FIRST:
+        return amp * M + real * N;
+    case QVA_PASS_BLU_MUL:
+        return 3 * amp * M;
+    case QVA_PASS_BLU_LAMBDA:
+        return 2 * amp * M + lam;
+    case QVA_PASS_BLU_PHASE:
+        return 2 * amp * M + real * N;
+    case QVA_PASS_BLU_LAST:
+        return amp * M + real * N;
+    case QVA_PASS_BLU_LAST_STORE:
+        return amp * M + (real + amp) * N;
+    case QVA_PASS_INIT:
+        return amp * N;
+    case QVA_PASS_EXPECT:
+        return (amp + real) * N;
+    case QVA_PASS_REDUCE:
+        return 16.0 * (double)(p == 0 ? expect_partial_count(problem_N(P)) : (int64_t(M) >> kTileBits));
     default:
         return 0.0;
     }
@@ -387,6 +501,49 @@ int small_lambda_kind(int kind)
 // the per-tile copy of lambda.
 size_t circ_partials_bytes(int n) { return (size_t)(int64_t(1) << (n - kTileBits)) * sizeof(double2); }
 
+// Bluestein evolution (N not a power of two, ring or eigenvalue array).
+int evolve_bluestein(const qva_problem* P, const double* gammas, const double* ts, int p, double2* psi,
+                     double* out_f, double* out_norm, bool store, char* work, hipStream_t s,
+                     EventHook& hook)
+{
+    const int nb = blu_bits(P);
+    const std::vector<XGroup> groups = x_groups(nb);
+    const BluLayout W = blu_layout(P);
+    double2* partials = reinterpret_cast<double2*>(work);
+    double2* pad = reinterpret_cast<double2*>(work + W.pad);
+    double2* spec[2] = {reinterpret_cast<double2*>(work + W.b0), reinterpret_cast<double2*>(work + W.b1)};
+    for (const Launch& l : fft_launches(P, p, store)) {
+        hipError_t e = hipSuccess;
+        hook.before(s);
+        if (l.kind == QVA_PASS_REDUCE) {
+            e = launch_final_reduce(partials, int64_t(1) << (nb - kTileBits), out_f, out_norm, s);
+        } else {
+            const XGroup& g = groups[l.group];
+            FftPassParams f{};
+            f.psi = pad;
+            f.q = P->q;
+            f.lam = P->lambda;
+            f.lambda_kind = P->lambda_kind == QVA_LAMBDA_RING ? FFT_LAMBDA_RING : FFT_LAMBDA_NATURAL;
+            f.mix1 = dev_angle(ts, l.layer1 >= 0 ? l.layer1 : 0);
+            f.phase = dev_angle(gammas, l.phase_layer >= 0 ? l.phase_layer : 0);
+            f.n = nb;
+            f.k = g.k;
+            f.col_bits = g.col_bits;
+            f.flags = l.xmode;
+            f.partials = partials;
+            f.nb = problem_N(P);
+            f.bt = spec[l.layer2 > 0 ? 1 : 0];
+            f.out = l.kind == QVA_PASS_BLU_TILE ? spec[l.layer2 > 0 ? 1 : 0] : psi;
+            f.conj = l.layer2 > 0 ? 1 : 0;
+            e = launch_fftpass(f, s);
+        }
+        hook.after(s);
+        if (e != hipSuccess)
+            return QVA_ERR_HIP;
+    }
+    return QVA_OK;
+}
+
 int evolve_circ(const qva_problem* P, const double* gammas, const double* ts, int p, double2* psi,
                 double* out_f, double* out_norm, bool store, char* work, hipStream_t s,
                 EventHook& hook)
@@ -394,6 +551,9 @@ int evolve_circ(const qva_problem* P, const double* gammas, const double* ts, in
     const int n = P->n_qubits;
     const int64_t N = problem_N(P);
     const bool closed = complete_closed_form(P);
+    const bool blu = bluestein_path(P);
+    if (blu && p > 0)
+        return evolve_bluestein(P, gammas, ts, p, psi, out_f, out_norm, store, work, s, hook);
     const std::vector<XGroup> groups = x_groups(n);
     double2* partials = reinterpret_cast<double2*>(work);
     double* lam_tiles = n > kTileBits ? reinterpret_cast<double*>(work + circ_partials_bytes(n)) : nullptr;
@@ -994,6 +1154,11 @@ size_t qva_workspace_bytes(const qva_problem* P, int p, int for_grad)
             return grad_layout(P, p).total;
         return align256(cpl_partials_bytes(P)) + 256;  // partials, then the running state sum
     }
+    if (bluestein_path(P)) {
+        if (p == 0)
+            return (size_t)expect_partial_count(problem_N(P)) * sizeof(double2);
+        return for_grad ? 0 : blu_layout(P).total;
+    }
     if (n <= kTileBits)
         return 0;
     if (for_grad && p > 0)
@@ -1056,6 +1221,8 @@ int qva_plan(const qva_problem* P, int p, int for_grad, int flags, qva_pass_info
         return st;
     if (max_out < 0 || (max_out > 0 && !out) || (flags & ~QVA_EVOLVE_SKIP_FINAL_STATE))
         return QVA_ERR_ARG;
+    if (for_grad && bluestein_path(P) && p > 0)
+        return QVA_ERR_UNSUPPORTED;
     if (for_grad) {
         const std::vector<XGroup> groups = x_groups(P->n_qubits);
         const std::vector<GLaunch> L = grad_launches(P, p);
@@ -1075,7 +1242,7 @@ int qva_plan(const qva_problem* P, int p, int for_grad, int flags, qva_pass_info
     const bool store = !(flags & QVA_EVOLVE_SKIP_FINAL_STATE);
     const int n = P->n_qubits;
     const bool circ = P->mixer == QVA_MIX_CIRCULANT;
-    const std::vector<XGroup> groups = x_groups(n);
+    const std::vector<XGroup> groups = x_groups(bluestein_path(P) ? blu_bits(P) : n);
     const std::vector<Launch> L = circ ? fft_launches(P, p, store) : x_launches(n, p, store);
     for (int i = 0; i < (int)L.size() && i < max_out; ++i) {
         const Launch& l = L[i];
@@ -1087,6 +1254,7 @@ int qva_plan(const qva_problem* P, int p, int for_grad, int flags, qva_pass_info
         out[i].mix_layer2 = l.layer2;
         out[i].phase_layer = l.phase_layer;
         out[i].bytes = complete_closed_form(P) ? cpl_launch_bytes(l, P, p)
+                       : bluestein_path(P) ? blu_launch_bytes(l, P, p)
                        : circ ? fft_launch_bytes(l, n, store, lambda_tiled(P)) : launch_bytes(l, n, store);
     }
     return (int)L.size();
@@ -1158,6 +1326,8 @@ int grad_common(const qva_problem* P, const double* gammas_dev, const double* ts
     int st = check_problem(P, p);
     if (st != QVA_OK)
         return st;
+    if (bluestein_path(P) && p > 0)
+        return QVA_ERR_UNSUPPORTED;  // the adjoint through Bluestein's transform is not built
     if (!psi || !chi || !out_f_dev || (p > 0 && (!gammas_dev || !ts_dev || !dgammas_dev || !dts_dev)))
         return QVA_ERR_ARG;
     if (psi == chi)

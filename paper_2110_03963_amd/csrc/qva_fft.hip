@@ -95,6 +95,52 @@ __device__ __forceinline__ void expect_store_a(double2 (&v)[kRegs], const FftPas
         store_tile<LA>(v, P.psi, g, t, scale);
 }
 
+// ---------------------------------------------------------------- Bluestein
+// For N not a power of two the transform is the chirp-z form: with
+// w_k = exp(i pi k^2 / N) and jm = (j^2 + m^2 - (m - j)^2) / 2,
+//   DFT_N(x)_m = conj(w_m) sum_j (x_j conj(w_j)) w_{m-j},
+//   DFT_N^-1(X)_j = (1/N) w_j sum_m (X_m w_m) conj(w_{j-m}),
+// each a linear convolution done cyclically over M = 2^n >= 2N - 1 (the
+// filter w_k, |k| < N, sits at k and M - k).  Inside one mixer the chirps
+// between the two convolutions cancel (conj(w_m) w_m = 1), and so do those
+// between the inverse of layer k and the forward of layer k + 1, so the
+// evolution stays in the padded buffer: convolve with w, multiply by
+// exp(-i t lambda_m) (m < N, zero above), convolve with conj(w), multiply by
+// exp(-i gamma q_j) / N (j < N, zero above), ...  The filters' spectra
+// (times 1/M, the inverse transform's factor) are computed once per call.
+
+// w_k = exp(i pi k^2 / N), k < N < 2^31, with k^2 reduced mod 2N exactly.
+__device__ __forceinline__ double2 chirp(int64_t k, int64_t N)
+{
+    const uint64_t r = ((uint64_t)k * (uint64_t)k) % (uint64_t)(2 * N);
+    double s, c;
+    sincospi_red((double)r / (double)N, &s, &c);
+    return make_double2(c, s);
+}
+
+// Element-wise factor of a Bluestein boundary pass at natural index j.
+template <int FLAGS>
+__device__ __forceinline__ double2 bluestein_factor(const FftPassParams& P, int64_t j, double ang,
+                                                    double invN)
+{
+    if (j >= P.nb)
+        return make_double2(0.0, 0.0);
+    if constexpr (FLAGS == FMODE_B_BOUND_LAM) {
+        double lam;
+        if (P.lambda_kind == FFT_LAMBDA_RING) {
+            double s, c;
+            sincospi_red((double)(2 * j) / (double)P.nb, &s, &c);  // lambda_j = 2 cos(2 pi j / N)
+            lam = 2.0 * c;
+        } else {
+            lam = P.lam[j];
+        }
+        return expmi(ang * lam);
+    } else {
+        const double2 e = expmi(ang * ld_nt(P.q + j));
+        return make_double2(e.x * invN, e.y * invN);
+    }
+}
+
 template <int C, int FLAGS>
 __global__ __launch_bounds__(kThreads, 2) void fftpass_kernel(FftPassParams P)
 {
@@ -134,10 +180,86 @@ __global__ __launch_bounds__(kThreads, 2) void fftpass_kernel(FftPassParams P)
         phase_a(v, P.q, g, t, angle_value(P.phase), invN);
         dif_tile<C>(v, lds, g, t);
         store_tile<dif_last<C>()>(v, P.psi, g, t, 1.0);
-    } else {  // FMODE_LAST, FMODE_LAST_STORE
+    } else if constexpr (FLAGS == FMODE_LAST || FLAGS == FMODE_LAST_STORE) {
         load_tile<dif_last<C>()>(v, P.psi, g, t);
         dit_tile<C>(v, lds, g, t);
         expect_store_a<FLAGS>(v, P, g, t, invN, red);
+    } else if constexpr (FLAGS == FMODE_B_CHIRP) {
+        const int64_t M = int64_t(1) << P.n;
+#pragma unroll
+        for (int r = 0; r < kRegs; ++r) {
+            const int64_t i = g(elem<LA>(t, r));
+            const int64_t k = i < P.nb ? i : (i > M - P.nb ? M - i : -1);
+            double2 w = k >= 0 ? chirp(k, P.nb) : make_double2(0.0, 0.0);
+            v[r] = P.conj ? make_double2(w.x, -w.y) : w;
+        }
+        dif_tile<C>(v, lds, g, t);
+        store_tile<dif_last<C>()>(v, P.psi, g, t, 1.0);
+    } else if constexpr (FLAGS == FMODE_B_FIRST) {
+        const double a0 = 1.0 / sqrt((double)P.nb);
+        const double gam = angle_value(P.phase);
+#pragma unroll
+        for (int r = 0; r < kRegs; ++r) {
+            const int64_t j = g(elem<LA>(t, r));
+            if (j < P.nb) {
+                const double2 w = chirp(j, P.nb);
+                const double2 ph = cmul(expmi(gam * ld_nt(P.q + j)), make_double2(w.x, -w.y));
+                v[r] = make_double2(a0 * ph.x, a0 * ph.y);
+            } else {
+                v[r] = make_double2(0.0, 0.0);
+            }
+        }
+        dif_tile<C>(v, lds, g, t);
+        store_tile<dif_last<C>()>(v, P.psi, g, t, 1.0);
+    } else if constexpr (FLAGS == FMODE_B_BOUND_LAM || FLAGS == FMODE_B_BOUND_Q) {
+        const double ang = FLAGS == FMODE_B_BOUND_LAM ? angle_value(P.mix1) : angle_value(P.phase);
+        const double invNb = 1.0 / (double)P.nb;
+        load_tile<dif_last<C>()>(v, P.psi, g, t);
+        dit_tile<C>(v, lds, g, t);
+#pragma unroll
+        for (int r = 0; r < kRegs; ++r) {
+            v[r] = cmul(v[r], bluestein_factor<FLAGS>(P, g(elem<LA>(t, r)), ang, invNb));
+            QVA_SCHED_FENCE();
+        }
+        dif_tile<C>(v, lds, g, t);
+        store_tile<dif_last<C>()>(v, P.psi, g, t, 1.0);
+    } else if constexpr (FLAGS == FMODE_B_LAST || FLAGS == FMODE_B_LAST_STORE) {
+        // x_j after the second convolution; psi_j = w_j x_j / N for j < N
+        const double invNb = 1.0 / (double)P.nb;
+        load_tile<dif_last<C>()>(v, P.psi, g, t);
+        dit_tile<C>(v, lds, g, t);
+        double f = 0.0, nr = 0.0;
+#pragma unroll
+        for (int r = 0; r < kRegs; ++r) {
+            const int64_t j = g(elem<LA>(t, r));
+            if (j < P.nb) {
+                const double2 x = make_double2(v[r].x * invNb, v[r].y * invNb);
+                const double a = x.x * x.x + x.y * x.y;
+                f = fma(a, ld_nt(P.q + j), f);
+                nr += a;
+                if constexpr (FLAGS & FP_STORE)
+                    st_nt(P.out + j, cmul(chirp(j, P.nb), x));
+            }
+        }
+        const double2 tot = block_sum2(f, nr, red);
+        if (t == 0)
+            P.partials[blockIdx.x] = tot;
+    } else if constexpr (FLAGS == FMODE_LOWMUL) {
+        load_tile<LA>(v, P.psi, g, t);
+        dif_tile<C>(v, lds, g, t);
+#pragma unroll
+        for (int r = 0; r < kRegs; ++r)
+            v[r] = cmul(v[r], ld_nt(P.bt + (tile << kTileBits) + r * kThreads + t));
+        dit_tile<C>(v, lds, g, t);
+        store_tile<LA>(v, P.psi, g, t, 1.0);
+    } else if constexpr (FLAGS == FMODE_LOWDIF_TILED) {
+        // the filter's spectrum in the order FMODE_LOWMUL reads it, times 1/M
+        const double invM = ldexp(1.0, -P.n);
+        load_tile<LA>(v, P.psi, g, t);
+        dif_tile<C>(v, lds, g, t);
+#pragma unroll
+        for (int r = 0; r < kRegs; ++r)
+            st_nt(P.out + (tile << kTileBits) + r * kThreads + t, make_double2(v[r].x * invM, v[r].y * invM));
     }
 }
 
@@ -263,6 +385,12 @@ hipError_t launch_fft_c(const FftPassParams& P, unsigned grid, hipStream_t s)
         QVA_FFT_MODE(FMODE_BOUNDARY)
         QVA_FFT_MODE(FMODE_LAST)
         QVA_FFT_MODE(FMODE_LAST_STORE)
+        QVA_FFT_MODE(FMODE_B_CHIRP)
+        QVA_FFT_MODE(FMODE_B_FIRST)
+        QVA_FFT_MODE(FMODE_B_BOUND_LAM)
+        QVA_FFT_MODE(FMODE_B_BOUND_Q)
+        QVA_FFT_MODE(FMODE_B_LAST)
+        QVA_FFT_MODE(FMODE_B_LAST_STORE)
 #undef QVA_FFT_MODE
     default:
         return hipErrorInvalidValue;
@@ -276,9 +404,19 @@ hipError_t launch_fftpass(const FftPassParams& P, hipStream_t s)
 {
     const unsigned grid = (unsigned)(int64_t(1) << (P.n - kTileBits));
     if (P.col_bits == 0) {
-        if (P.flags != FMODE_LOWDIAG)
+        switch (P.flags) {
+        case FMODE_LOWDIAG:
+            hipLaunchKernelGGL((fftpass_kernel<0, FMODE_LOWDIAG>), dim3(grid), dim3(kThreads), 0, s, P);
+            break;
+        case FMODE_LOWMUL:
+            hipLaunchKernelGGL((fftpass_kernel<0, FMODE_LOWMUL>), dim3(grid), dim3(kThreads), 0, s, P);
+            break;
+        case FMODE_LOWDIF_TILED:
+            hipLaunchKernelGGL((fftpass_kernel<0, FMODE_LOWDIF_TILED>), dim3(grid), dim3(kThreads), 0, s, P);
+            break;
+        default:
             return hipErrorInvalidValue;
-        hipLaunchKernelGGL((fftpass_kernel<0, FMODE_LOWDIAG>), dim3(grid), dim3(kThreads), 0, s, P);
+        }
         return hipGetLastError();
     }
     switch (P.col_bits) {

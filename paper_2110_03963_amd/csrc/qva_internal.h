@@ -104,7 +104,17 @@ enum : int {
     FMODE_LOWDIAG = 80,         // low group: forward, diag(exp(-i t lambda)), inverse
     FMODE_BOUNDARY = 96,        // inverse top group, 1/N, phase, forward top group
     FMODE_LAST = 112 | FP_EXPECT,              // inverse top group, 1/N, <Q> partials
-    FMODE_LAST_STORE = 112 | FP_EXPECT | FP_STORE
+    FMODE_LAST_STORE = 112 | FP_EXPECT | FP_STORE,
+    // Bluestein (chirp-z) evolution for N not a power of two, over a padded
+    // buffer of M = 2^n >= 2N - 1 amplitudes (see qva_fft.hip)
+    FMODE_B_CHIRP = 128,      // chirp filter w_k (or its conjugate), forward top group
+    FMODE_B_FIRST = 144,      // psi_0, phase of layer 1, conj chirp, zero pad, forward top group
+    FMODE_B_BOUND_LAM = 160,  // inverse top group, exp(-i t lambda) (j < N, else 0), forward top
+    FMODE_B_BOUND_Q = 176,    // inverse top group, exp(-i gamma q) / N (j < N, else 0), forward top
+    FMODE_B_LAST = 192 | FP_EXPECT,            // inverse top group, <Q> over j < N
+    FMODE_B_LAST_STORE = 192 | FP_EXPECT | FP_STORE,  // ... and psi_j = w_j x_j / N
+    FMODE_LOWMUL = 208,       // low group: forward, times a complex per-tile array, inverse
+    FMODE_LOWDIF_TILED = 224  // low group: forward, written per tile (times 1/M)
 };
 
 struct FftPassParams {
@@ -118,6 +128,11 @@ struct FftPassParams {
     int flags;
     int lambda_kind;
     double2* partials;
+    // Bluestein passes
+    int64_t nb;           // the logical N (< 2^31); n above is log2 of the padded M
+    const double2* bt;    // FMODE_LOWMUL: complex multiplier in per-tile order
+    double2* out;         // FMODE_LOWDIF_TILED: its output; FMODE_B_LAST_STORE: psi (nb amplitudes)
+    int conj;             // FMODE_B_CHIRP: conjugate filter
 };
 
 struct SmallFftParams {

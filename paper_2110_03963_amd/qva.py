@@ -114,9 +114,10 @@ class Problem:
 
     mixer "x": W = sum_i X_i on log2(len(q)) qubits.
     mixer "circulant": W circulant with eigenvalues lam (natural order) or
-    lambda_kind "ring" / "complete".  With the complete graph len(q) may be
-    any N >= 2 (the solution count of a constrained problem); the other
-    mixers need a power of two.
+    lambda_kind "ring" / "complete".  A circulant may have any N >= 2 (the
+    solution count of a constrained problem): closed-form passes for the
+    complete graph, Bluestein's transform for the ring or an array (forward
+    only).  The hypercube mixer needs a power of two.
     """
 
     def __init__(self, q: torch.Tensor, mixer: str = "x", lam: torch.Tensor | None = None,
@@ -125,7 +126,7 @@ class Problem:
         self.q = q
         N = q.numel()
         self._N = N
-        if mixer == "circulant" and lambda_kind == "complete" and N >= 2 and (N & (N - 1)):
+        if mixer == "circulant" and N >= 2 and (N & (N - 1)):
             self.n = int(N - 1).bit_length()  # log2 N rounded up
             n_states = N
         else:

@@ -162,11 +162,31 @@ def test_evolve_complete_any_n(N, p):
     assert f2.item() == f.item()
 
 
-def test_non_power_of_two_needs_complete_graph():
-    q = to_dev(np.ones(1000))
-    for mixer, kind in [("x", "array"), ("circulant", "ring")]:
-        with pytest.raises(ValueError):
-            qva.Problem(q, mixer, None, kind)
+def test_non_power_of_two_needs_circulant():
+    with pytest.raises(ValueError):
+        qva.Problem(to_dev(np.ones(1000)), "x")
+
+
+@pytest.mark.parametrize("N", [5, 1000, 4097, 12289, 100003, 1000003])
+@pytest.mark.parametrize("kind", ["ring", "array"])
+@pytest.mark.parametrize("p", [1, 3])
+def test_evolve_bluestein(N, kind, p):
+    """Ring or eigenvalue-array circulant over N solutions, N not a power of
+    two (Bluestein's chirp-z transform over a padded power of two), against
+    the oracle (naive DFT up to 4096, its own chirp-z transform above)."""
+    rng = np.random.default_rng(N + p + len(kind))
+    q = rng.uniform(-1, 3, N)
+    g = rng.uniform(0, math.pi, p)
+    t = rng.uniform(0, math.pi, p)
+    lam = oracle.ring_lambda(N) if kind == "ring" else random_symmetric_lambda(N, rng)
+    prob = qva.Problem(to_dev(q), "circulant", to_dev(lam) if kind == "array" else None, kind)
+    f, nrm, psi = qva.evolve(prob, g, t, store=True)
+    psi_ref, f_ref, n_ref = oracle.evolve("circulant", q, g, t, lam)
+    assert f_rel_err(f.item(), f_ref, psi_ref, q) < F_TOL
+    assert abs(nrm.item() - n_ref) < 1e-12
+    assert state_err(psi.cpu().numpy(), psi_ref) < PSI_TOL
+    f2, _, _ = qva.evolve(prob, g, t, store=False)
+    assert f2.item() == f.item()
 
 
 @pytest.mark.parametrize("n", [13, 17])

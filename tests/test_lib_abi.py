@@ -222,8 +222,7 @@ def test_n_states_validation(lib):
     for bad, st in [(_prob(mixer=1, n=17, kind=2, n_states=65536), S.QVA_ERR_SIZE),
                     (_prob(mixer=1, n=17, kind=2, n_states=131073), S.QVA_ERR_SIZE),
                     (_prob(mixer=1, n=17, kind=2, n_states=-5), S.QVA_ERR_SIZE),
-                    (_prob(mixer=1, n=17, kind=1, n_states=100003), S.QVA_ERR_UNSUPPORTED),
-                    (_prob(mixer=1, n=17, kind=0, lam=FAKE, n_states=100003), S.QVA_ERR_UNSUPPORTED),
+                    (_prob(mixer=1, n=32, kind=1, n_states=(1 << 31) + 5), S.QVA_ERR_UNSUPPORTED),
                     (_prob(mixer=0, n=17, n_states=100003), S.QVA_ERR_UNSUPPORTED)]:
         assert lib.qva_evolve(ref(bad), FAKE, FAKE, 3, FAKE, FAKE, None, 0, FAKE, ws, None) == st
         assert lib.qva_plan(ref(bad), 3, 0, 0, None, 0) == st
@@ -259,6 +258,41 @@ def test_plan_complete_any_n(lib, N, n, p):
         assert lib.qva_plan(ctypes.byref(pr), p, 1, 0, arr, cnt) == cnt
         assert [x.kind for x in arr] == [26, 30] + [27, 30] * (p - 1) + [31, 33] + [32, 33] * p + [8, 25]
         assert lib.qva_workspace_bytes(ctypes.byref(pr), p, 1) > 0
+
+
+@pytest.mark.parametrize("N,n", [(1000, 10), (4097, 13), (100003, 17), (3000017, 22)])
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("p", [1, 3])
+def test_plan_bluestein(lib, N, n, kind, p):
+    """Ring / array circulant over N (not a power of two): two filter spectra,
+    psi_0, then per layer two convolutions over the padded M >= 2N - 1."""
+    pr = _prob(mixer=1, n=n, kind=kind, lam=FAKE if kind == 0 else None, n_states=N)
+    M = 1 << max(13, (2 * N - 2).bit_length())
+    for flags, last in [(1, 40), (0, 41)]:
+        cnt = lib.qva_plan(ctypes.byref(pr), p, 0, flags, None, 0)
+        arr = (_lib.QvaPassInfo * cnt)()
+        assert lib.qva_plan(ctypes.byref(pr), p, 0, flags, arr, cnt) == cnt
+        kinds = [x.kind for x in arr]
+        mids = sorted({x.group_first for x in arr if x.kind == 10})
+        nm = len(mids)
+        conv = [10] * nm
+        back = [12] * nm
+        layer = conv + [37] + back + [38] + conv + [37] + back
+        expect = ([34] + conv + [35]) * 2 + [36]
+        for k in range(p):
+            expect += layer + ([39] if k + 1 < p else [last])
+        assert kinds == expect + [8]
+        # the groups tile the padded index bits
+        bits = sorted({(x.group_first, x.group_bits) for x in arr if x.group_first >= 0})
+        covered = []
+        for k0, b in bits:
+            covered.extend(range(k0, k0 + b))
+        assert covered == list(range(M.bit_length() - 1))
+        mul = [x.bytes for x in arr if x.kind == 37]
+        assert mul == [48 * M] * (2 * p)
+    assert lib.qva_workspace_bytes(ctypes.byref(pr), p, 0) >= 3 * 16 * M
+    # the adjoint is not built for this path
+    assert lib.qva_plan(ctypes.byref(pr), p, 1, 0, None, 0) == _lib.QVA_ERR_UNSUPPORTED
 
 
 def _grad_plan(lib, mixer, n, p, kind=1):
