@@ -307,21 +307,29 @@ def cpu_baseline(wl) -> dict:
 
 
 # ------------------------------------------------------------------ extras
-def extra_qwoa(lib, steps: int, kind: str = "ring") -> dict:
+def extra_qwoa(lib, steps: int, kind: str = "ring", constrained: bool = False) -> dict:
     """QWOA portfolio over all subsets of 26 assets, p = 6; ring mixer
-    (transform passes) or complete graph (closed-form passes)."""
+    (transform passes) or complete graph (closed-form passes).  constrained:
+    only the C(26, 13) = 10,400,600 subsets of exactly 13 assets (N not a
+    power of two: Bluestein's transform for the ring, the closed form for the
+    complete graph)."""
     import torch
 
     import paper_2110_03963_amd as qva
     from paper_2110_03963_amd import _lib
     from workloads import CONFIG_SEEDS, qwoa_portfolio_workload
 
+    from workloads import qwoa_constrained_workload
+
     n, p = 26, 6
-    wl = qwoa_portfolio_workload(n, p, seed=CONFIG_SEEDS["qwoa_n26"], lambda_kind=kind)
+    if constrained:
+        wl = qwoa_constrained_workload(n, 13, p, seed=CONFIG_SEEDS["qwoa_n26"], lambda_kind=kind)
+    else:
+        wl = qwoa_portfolio_workload(n, p, seed=CONFIG_SEEDS["qwoa_n26"], lambda_kind=kind)
     prob = qva.Problem(torch.from_numpy(wl.q).cuda(), "circulant", None, kind)
     g = torch.tensor(wl.gammas, device="cuda")
     t = torch.tensor(wl.ts, device="cuda")
-    psi = torch.empty(1 << n, dtype=torch.complex128, device="cuda")
+    psi = torch.empty(prob.N, dtype=torch.complex128, device="cuda")
     ws = torch.empty(max(prob.workspace_bytes(p), 16), dtype=torch.uint8, device="cuda")
     out = torch.empty(2, dtype=torch.float64, device="cuda")
     flags = _lib.QVA_EVOLVE_SKIP_FINAL_STATE
@@ -343,7 +351,8 @@ def extra_qwoa(lib, steps: int, kind: str = "ring") -> dict:
 
     per = per_kernel_profile(run_timed, infos, steps)
     plan_bytes = sum(i.bytes for i in infos)
-    return {"workload": f"qwoa_portfolio_n26_p6_{kind}", "ms_per_evolve": round(ms, 4),
+    name = f"qwoa_portfolio_m26_k13_p6_{kind}" if constrained else f"qwoa_portfolio_n26_p6_{kind}"
+    return {"workload": name, "N": prob.N, "ms_per_evolve": round(ms, 4),
             "layer_applications_per_s": round(p / (ms * 1e-3), 2), "launches": len(infos),
             "effective_GBps": round(plan_bytes / (ms * 1e-3) / 1e9, 1),
             "f": out[0].item(), "roofline": roofline_of(per, steps),
@@ -534,6 +543,8 @@ def extra_batch(lib) -> dict:
 EXTRAS = {
     "qwoa_circulant": lambda lib, steps: extra_qwoa(lib, max(3, steps // 2)),
     "qwoa_complete": lambda lib, steps: extra_qwoa(lib, max(3, steps // 2), "complete"),
+    "qwoa_constrained_ring": lambda lib, steps: extra_qwoa(lib, max(3, steps // 2), "ring", True),
+    "qwoa_constrained_complete": lambda lib, steps: extra_qwoa(lib, max(3, steps // 2), "complete", True),
     "adjoint_vs_fd": lambda lib, steps: extra_adjoint(lib, 2),
     "adjoint_qwoa_complete": lambda lib, steps: extra_adjoint(lib, 3, "qwoa_complete"),
     "batched": lambda lib, steps: extra_batch(lib),

@@ -554,6 +554,19 @@ def test_workload_q_matches_plain_loop(oracle_mod, n):
     assert np.array_equal(a, b)
 
 
+def test_constrained_workload_selects_k_subsets():
+    """The constrained QWOA inputs are the full portfolio q at the indices with
+    exactly k assets, in ascending order: N = C(m, k)."""
+    from workloads import qwoa_constrained_workload, qwoa_portfolio_workload
+    m, k = 12, 5
+    full = qwoa_portfolio_workload(m, 3, seed=9)
+    sub = qwoa_constrained_workload(m, k, 3, seed=9)
+    idx = [j for j in range(1 << m) if bin(j).count("1") == k]
+    assert sub.N == math.comb(m, k) == len(idx)
+    assert np.array_equal(sub.q, full.q[idx])
+    assert np.array_equal(sub.gammas, full.gammas) and np.array_equal(sub.ts, full.ts)
+
+
 def test_portfolio_q_matches_plain_loop():
     rng = np.random.default_rng(0)
     m = 9

@@ -30,6 +30,7 @@ from .problems import (
     Workload,
     qaoa_maxcut_workload,
     qwoa_portfolio_workload,
+    qwoa_constrained_workload,
     batched_workloads,
     CONFIG_SEEDS,
 )
@@ -48,6 +49,7 @@ __all__ = [
     "Workload",
     "qaoa_maxcut_workload",
     "qwoa_portfolio_workload",
+    "qwoa_constrained_workload",
     "batched_workloads",
     "CONFIG_SEEDS",
 ]

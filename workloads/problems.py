@@ -188,7 +188,7 @@ class Workload:
 
     @property
     def N(self) -> int:
-        return 1 << self.n
+        return len(self.q) if self.q is not None else 1 << self.n
 
     @property
     def p(self) -> int:
@@ -234,6 +234,18 @@ def qwoa_portfolio_workload(m: int, p: int, *, seed: int = 0, risk: float = 0.5,
     q = portfolio_qualities(mu, sigma, risk)
     return Workload(name=name or f"qwoa_portfolio_m{m}_p{p}", mixer="circulant", n=m, q=q,
                     gammas=gammas, ts=ts, lam=None, lambda_kind=lambda_kind, seed=seed)
+
+
+def qwoa_constrained_workload(m: int, k: int, p: int, *, seed: int = 0, risk: float = 0.5,
+                              lambda_kind: str = "ring") -> Workload:
+    """QWOA portfolio restricted to the subsets of exactly k of m assets: the
+    same draws as qwoa_portfolio_workload(m, p, seed), with q kept at the
+    indices of popcount k (ascending), so N = C(m, k) is not a power of two."""
+    wl = qwoa_portfolio_workload(m, p, seed=seed, risk=risk, lambda_kind=lambda_kind)
+    idx = np.flatnonzero(np.bitwise_count(np.arange(1 << m, dtype=np.uint64)) == k)
+    return Workload(name=f"qwoa_portfolio_m{m}_k{k}_p{p}", mixer="circulant", n=int(len(idx) - 1).bit_length(),
+                    q=np.ascontiguousarray(wl.q[idx]), gammas=wl.gammas, ts=wl.ts, lam=None,
+                    lambda_kind=lambda_kind, seed=seed)
 
 
 def batched_workloads(count: int, *, seed: int, n_range=(12, 22), p_range=(1, 8),
