@@ -76,6 +76,11 @@ def _load():
     lib.oracle_grad.restype = Ci
     lib.oracle_grad_bruteforce.argtypes = [Ci, I64, P, P, Ci, P, P, P, P]
     lib.oracle_grad_bruteforce.restype = Ci
+    lib.oracle_phase_terms.argtypes = [I64, P, Ci, P, P, P]
+    lib.oracle_evolve_terms.argtypes = [I64, P, Ci, P, P, Ci, P, P, P, P, P]
+    lib.oracle_evolve_terms.restype = Ci
+    lib.oracle_grad_terms.argtypes = [I64, P, Ci, P, P, Ci, P, P, P, P, P]
+    lib.oracle_grad_terms.restype = Ci
     _lib = lib
     return lib
 
@@ -295,3 +300,54 @@ def maxcut_quality_loop(n: int, edges, weights=None, uncut: bool = False) -> np.
                 s += w
         q[j] = s
     return q
+
+
+# ------------------------------------------------------------ extended QAOA
+def _terms(support, coef):
+    S = np.ascontiguousarray(np.asarray(support, dtype=np.uint64))
+    c = _f64(coef)
+    if S.shape != c.shape:
+        raise ValueError("one coefficient per term")
+    return S, c
+
+
+def phase_terms(psi, support, coef, gamma) -> np.ndarray:
+    """psi_j <- exp(-i sum_e gamma_e c_e (-1)^popcount(j & S_e)) psi_j
+    (eq. phase_shift_qaoa_ex with Z-string terms)."""
+    S, c = _terms(support, coef)
+    psi = _c128(psi).copy()
+    _load().oracle_phase_terms(len(psi), _ptr(psi), len(S), _ptr(S), _ptr(c), _ptr(_f64(gamma)))
+    return psi
+
+
+def evolve_terms(q, support, coef, gammas, ts) -> tuple[np.ndarray, float, float]:
+    """Extended QAOA (eq. qaoa_ex): gammas is p x n_terms; q the observable."""
+    S, c = _terms(support, coef)
+    q = _f64(q)
+    g = np.ascontiguousarray(np.asarray(gammas, dtype=np.float64).reshape(len(ts), len(S)))
+    ts = _f64(ts)
+    psi = np.empty(len(q), np.complex128)
+    f = ctypes.c_double()
+    nrm = ctypes.c_double()
+    rc = _load().oracle_evolve_terms(len(q), _ptr(q), len(S), _ptr(S), _ptr(c), len(ts), _ptr(g), _ptr(ts),
+                                     _ptr(psi), ctypes.byref(f), ctypes.byref(nrm))
+    if rc:
+        raise ValueError("oracle_evolve_terms: bad arguments")
+    return psi, f.value, nrm.value
+
+
+def grad_terms(q, support, coef, gammas, ts) -> tuple[float, np.ndarray, np.ndarray]:
+    """(f, df/dgamma (p x n_terms), df/dt) by the adjoint walk."""
+    S, c = _terms(support, coef)
+    q = _f64(q)
+    p = len(ts)
+    g = np.ascontiguousarray(np.asarray(gammas, dtype=np.float64).reshape(p, len(S)))
+    ts = _f64(ts)
+    dg = np.empty((p, len(S)))
+    dt = np.empty(p)
+    f = ctypes.c_double()
+    rc = _load().oracle_grad_terms(len(q), _ptr(q), len(S), _ptr(S), _ptr(c), p, _ptr(g), _ptr(ts),
+                                   ctypes.byref(f), _ptr(dg), _ptr(dt))
+    if rc:
+        raise ValueError("oracle_grad_terms: bad arguments")
+    return f.value, dg, dt

@@ -100,6 +100,31 @@ void oracle_phase(int64_t N, cplx *psi, const double *q, double gamma)
 }
 
 /* ---------------------------------------------------------------------- */
+/* Extended QAOA phase (eq. phase_shift_qaoa_ex):                           */
+/*   U_Qext(gamma) = prod_e exp(-i gamma_e Sigma_e),                        */
+/* with Sigma_e = c_e Z^{S_e} a term of a Pauli decomposition of Q: for a   */
+/* diagonal Q every term is a Z string, on the qubits set in the mask S_e,  */
+/* so Sigma_e(j) = c_e (-1)^popcount(j & S_e).  The terms commute and the   */
+/* product is exp(-i sum_e gamma_e Sigma_e(j)) on basis state j.            */
+/* ---------------------------------------------------------------------- */
+
+static double zterm(int64_t j, uint64_t S, double c)
+{
+    return (__builtin_popcountll((uint64_t)j & S) & 1) ? -c : c;
+}
+
+void oracle_phase_terms(int64_t N, cplx *psi, int n_terms, const uint64_t *S, const double *c,
+                        const double *gamma)
+{
+    for (int64_t j = 0; j < N; ++j) {
+        double ph = 0.0;
+        for (int e = 0; e < n_terms; ++e)
+            ph += gamma[e] * zterm(j, S[e], c[e]);
+        psi[j] *= cexp(-I * ph);
+    }
+}
+
+/* ---------------------------------------------------------------------- */
 /* Hypercube mixer (eq. mixing_qaoa with W_X = sum_i X_i).                  */
 /* The X_i commute, so exp(-i t sum_i X_i) = prod_i exp(-i t X_i), and      */
 /* exp(-i t X) = cos t I - i sin t X acts on each pair (j, j ^ 2^i).        */
@@ -499,6 +524,71 @@ int oracle_grad(int kind, int64_t N, const double *q, const double *lambda, int 
     free(phi);
     free(chi);
     free(wphi);
+    return 0;
+}
+
+/* Extended QAOA (eq. qaoa_ex): hypercube mixer, per-term phases; gammas is */
+/* p x n_terms (layer-major), q the observable.  Returns 0 or -1.            */
+int oracle_evolve_terms(int64_t N, const double *q, int n_terms, const uint64_t *S, const double *c, int p,
+                        const double *gammas, const double *ts, cplx *psi, double *f, double *norm)
+{
+    if (log2_exact(N) < 0 || p < 0 || n_terms < 0)
+        return -1;
+    oracle_init_uniform(N, psi);
+    for (int k = 0; k < p; ++k) {
+        oracle_phase_terms(N, psi, n_terms, S, c, gammas + (size_t)k * n_terms);
+        oracle_mix_x(log2_exact(N), psi, ts[k]);
+    }
+    oracle_expectation(N, psi, q, f, norm);
+    return 0;
+}
+
+/* Im <chi| Sigma_e |phi>, pairwise. */
+struct zterm_ctx {
+    const cplx *chi, *phi;
+    uint64_t S;
+    double c;
+};
+
+static double term_zinner(int64_t j, const void *ctx)
+{
+    const struct zterm_ctx *x = ctx;
+    return zterm(j, x->S, x->c) * cimag(conj(x->chi[j]) * x->phi[j]);
+}
+
+/* Adjoint gradient of the extended QAOA: dts[k] as for QAOA, and          */
+/* dgammas[k * n_terms + e] = 2 Im <chi_l| Sigma_e |phi_l> at the phase of   */
+/* layer k (the terms commute with U_Qext, so one state pair serves all e).  */
+int oracle_grad_terms(int64_t N, const double *q, int n_terms, const uint64_t *S, const double *c, int p,
+                      const double *gammas, const double *ts, double *f, double *dgammas, double *dts)
+{
+    if (log2_exact(N) < 0 || p < 0 || n_terms < 0)
+        return -1;
+    const int n = log2_exact(N);
+    cplx *phi = malloc(sizeof(cplx) * (size_t)N);
+    cplx *chi = malloc(sizeof(cplx) * (size_t)N);
+    cplx *wphi = malloc(sizeof(cplx) * (size_t)N);
+    double *neg = malloc(sizeof(double) * (size_t)(n_terms > 0 ? n_terms : 1));
+    oracle_evolve_terms(N, q, n_terms, S, c, p, gammas, ts, phi, f, NULL);
+    for (int64_t j = 0; j < N; ++j)
+        chi[j] = q[j] * phi[j];
+    for (int k = p - 1; k >= 0; --k) {
+        oracle_apply_hypercube(n, phi, wphi);
+        dts[k] = 2.0 * cimag(inner(N, chi, wphi, NULL));
+        oracle_mix_x(n, phi, -ts[k]);
+        oracle_mix_x(n, chi, -ts[k]);
+        for (int e = 0; e < n_terms; ++e) {
+            struct zterm_ctx ctx = {chi, phi, S[e], c[e]};
+            dgammas[(size_t)k * n_terms + e] = 2.0 * pairwise_sum_fn(term_zinner, &ctx, 0, N);
+            neg[e] = -gammas[(size_t)k * n_terms + e];
+        }
+        oracle_phase_terms(N, phi, n_terms, S, c, neg);
+        oracle_phase_terms(N, chi, n_terms, S, c, neg);
+    }
+    free(phi);
+    free(chi);
+    free(wphi);
+    free(neg);
     return 0;
 }
 

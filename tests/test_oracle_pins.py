@@ -587,3 +587,97 @@ def test_random_regular_is_regular_and_simple():
         assert len(set(e)) == len(e)
         deg = np.bincount(np.array(e).ravel(), minlength=n)
         assert np.all(deg == 3)
+
+
+# ------------------------------------------------------------ extended QAOA
+def _maxcut_terms(n, edges, weights):
+    """q_cut = sum_e w_e (1 - Z_u Z_v) / 2 = W / 2 + sum_e (-w_e / 2) Z_u Z_v."""
+    S = [(1 << u) | (1 << v) for u, v in edges]
+    c = [-w / 2 for w in weights]
+    return S, c
+
+
+def test_extended_qaoa_equal_angles_is_qaoa(oracle_mod):
+    """With every term of a layer at the same angle, U_Qext(gamma) is U_Q(gamma)
+    up to a global phase (eq. phase_shift_qaoa_ex vs eq. phase_shift_qaoa), so
+    f matches plain QAOA, and the per-term gradients sum to dgamma_k."""
+    n, p = 8, 3
+    edges = circular_ladder_edges(4)
+    rng = np.random.default_rng(5)
+    w = rng.uniform(0.2, 1.0, len(edges))
+    q = maxcut_qualities(n, edges, w)
+    S, c = _maxcut_terms(n, edges, w)
+    g = rng.uniform(0, math.pi, p)
+    t = rng.uniform(0, math.pi, p)
+    G = np.repeat(g[:, None], len(S), axis=1)
+    psi_e, f_e, _ = oracle.evolve_terms(q, S, c, G, t)
+    psi_q, f_q, _ = oracle.evolve("x", q, g, t)
+    assert abs(f_e - f_q) < 1e-13 * abs(f_q)
+    ov = np.vdot(psi_q, psi_e)
+    assert abs(abs(ov) - 1) < 1e-13
+    _, dG, dT = oracle.grad_terms(q, S, c, G, t)
+    _, dg, dt = oracle.grad("x", q, g, t)
+    assert np.max(np.abs(dG.sum(axis=1) - dg)) < 1e-12 * np.max(np.abs(dg))
+    assert np.max(np.abs(dT - dt)) < 1e-12 * np.max(np.abs(dt))
+
+
+def test_extended_qaoa_phase_definition(oracle_mod):
+    """The per-term phase against a direct evaluation of the Z strings on
+    basis states (bits read one by one), including 1- and 3-qubit strings."""
+    n = 6
+    N = 1 << n
+    rng = np.random.default_rng(2)
+    psi = _rand_state(rng, N)
+    S = [0b1, 0b11, 0b101000, 0b100110, 0b111111]
+    c = [0.3, -1.1, 0.25, 0.7, -0.4]
+    gam = rng.uniform(-2, 2, len(S))
+    out = oracle.phase_terms(psi, S, c, gam)
+    ref = psi.copy()
+    for j in range(N):
+        ph = 0.0
+        for s, ce, ge in zip(S, c, gam):
+            parity = sum((j >> b) & 1 for b in range(n) if (s >> b) & 1) % 2
+            ph += ge * ce * (-1 if parity else 1)
+        ref[j] *= np.exp(-1j * ph)
+    assert np.max(np.abs(out - ref)) < 1e-14
+
+
+@pytest.mark.parametrize("n,p", [(5, 2), (7, 3)])
+def test_extended_qaoa_gradient_central_differences(oracle_mod, n, p):
+    """Per-term adjoint gradient against central differences of the forward,
+    and against a dense evaluation of the state at small n."""
+    rng = np.random.default_rng(10 + n)
+    N = 1 << n
+    edges = [(i, (i + 1) % n) for i in range(n)]
+    S = [(1 << u) | (1 << v) for u, v in edges] + [1 << 2, 0b10011]
+    c = list(rng.uniform(-1, 1, len(S)))
+    q = rng.uniform(0, 4, N)
+    G = rng.uniform(0, math.pi, (p, len(S)))
+    t = rng.uniform(0, math.pi, p)
+    f, dG, dT = oracle.grad_terms(q, S, c, G, t)
+    scale = max(np.max(np.abs(dG)), np.max(np.abs(dT)))
+    h = 1e-5
+    for k in range(p):
+        for e in range(len(S)):
+            Gp = G.copy()
+            Gm = G.copy()
+            Gp[k, e] += h
+            Gm[k, e] -= h
+            fd = (oracle.evolve_terms(q, S, c, Gp, t)[1] - oracle.evolve_terms(q, S, c, Gm, t)[1]) / (2 * h)
+            assert abs(fd - dG[k, e]) < 1e-7 * scale
+        tp = t.copy()
+        tm = t.copy()
+        tp[k] += h
+        tm[k] -= h
+        fd = (oracle.evolve_terms(q, S, c, G, tp)[1] - oracle.evolve_terms(q, S, c, G, tm)[1]) / (2 * h)
+        assert abs(fd - dT[k]) < 1e-7 * scale
+    # dense: diag phases and expm of the hypercube
+    W = dense.hypercube(n)
+    psi = np.full(N, N ** -0.5, dtype=complex)
+    for k in range(p):
+        ph = np.zeros(N)
+        for s, ce, ge in zip(S, c, G[k]):
+            par = np.array([bin(j & s).count("1") % 2 for j in range(N)])
+            ph += ge * ce * (1 - 2 * par)
+        psi = dense.expm_hermitian(W, t[k]) @ (np.exp(-1j * ph) * psi)
+    assert abs(np.sum(np.abs(psi) ** 2 * q) - f) < 1e-12 * abs(f)
