@@ -69,6 +69,17 @@ typedef enum {
     QVA_LAMBDA_COMPLETE = 2 /* complete graph: lambda_0 = N - 1, lambda_m = -1        */
 } qva_lambda_kind;
 
+/* One term of a Pauli decomposition of a diagonal Q (extended QAOA, eq.
+ * phase_shift_qaoa_ex): the Z string on the qubits set in `support`, times
+ * `coef`, i.e. Sigma(j) = coef * (-1)^popcount(j & support) on basis state j. */
+typedef struct {
+    uint64_t support; /* qubit mask; bits at or above n_qubits never meet a basis
+                         index and are ignored (0: the identity, a global phase) */
+    double coef;
+} qva_zterm;
+
+#define QVA_MAX_TERMS 1024
+
 /* Problem descriptor (caller-owned, read during the call only).
  *   mixer       QVA_MIX_X or QVA_MIX_CIRCULANT
  *   n_qubits    log2 N rounded up; 1 <= n_qubits <= QVA_MAX_QUBITS
@@ -81,7 +92,17 @@ typedef enum {
  *               non-power-of-two N needs 2^(n_qubits-1) < N < 2^n_qubits and a
  *               circulant mixer: the complete graph (any N), or the ring or an
  *               eigenvalue array (N < 2^31; qva_evolve only, through Bluestein's
- *               transform).  Otherwise QVA_ERR_UNSUPPORTED.                    */
+ *               transform).  Otherwise QVA_ERR_UNSUPPORTED.
+ *   terms       device, n_terms qva_zterm, or NULL.  With n_terms > 0 (mixer
+ *               QVA_MIX_X only) the phase of layer k is the extended-QAOA
+ *               product prod_e exp(-i gamma_{k,e} Sigma_e) (eqs.
+ *               phase_shift_qaoa_ex, qaoa_ex): gammas and dgammas then hold
+ *               p * n_terms values, layer-major, and q is only the observable.
+ *   n_terms     0 (plain QAOA phase exp(-i gamma_k q)) or 1..QVA_MAX_TERMS;
+ *               outside 0..QVA_MAX_TERMS QVA_ERR_ARG, terms NULL with
+ *               n_terms > 0 QVA_ERR_ARG, terms not 8-byte aligned
+ *               QVA_ERR_ALIGN, a circulant mixer QVA_ERR_UNSUPPORTED.  Batched
+ *               plans (qva_batch_*) take no terms.                             */
 typedef struct {
     int mixer;
     int n_qubits;
@@ -89,6 +110,8 @@ typedef struct {
     const double *lambda;
     int lambda_kind;
     int64_t n_states;
+    const qva_zterm *terms;
+    int n_terms;
 } qva_problem;
 
 #define QVA_MAX_QUBITS 33
@@ -145,7 +168,9 @@ int qva_expectation(const qva_c128 *psi, const double *q, int64_t N, double *out
  * qwoa, objective_generic), fused into as few passes over the state as the
  * operator structure allows.
  *   gammas_dev, ts_dev  device, p doubles each (layer k uses gammas_dev[k],
- *                       ts_dev[k]; layer 0 acts first)
+ *                       ts_dev[k]; layer 0 acts first).  With Z-string terms
+ *                       gammas_dev holds p * n_terms: layer k's angles at
+ *                       gammas_dev[k * n_terms ...] (eq. qaoa_ex)
  *   p                   depth >= 0 (p = 0 gives f = mean(q))
  *   psi                 device, N complex; working state, holds psi_p on return
  *                       unless flags has QVA_EVOLVE_SKIP_FINAL_STATE
@@ -162,7 +187,9 @@ int qva_evolve(const qva_problem *P, const double *gammas_dev, const double *ts_
  *   psi, chi            device, N complex each: working states (contents on
  *                       return unspecified)
  *   out_f_dev           device double
- *   dgammas_dev, dts_dev device, p doubles each
+ *   dgammas_dev, dts_dev device, p doubles each (dgammas: p * n_terms with
+ *                       Z-string terms, dgammas_dev[k * n_terms + e] =
+ *                       2 Im <chi|Sigma_e|phi> at the phase of layer k)
  *   work                >= qva_workspace_bytes(P, p, 1) bytes                  */
 int qva_grad(const qva_problem *P, const double *gammas_dev, const double *ts_dev, int p,
              qva_c128 *psi, qva_c128 *chi, double *out_f_dev, double *dgammas_dev,

@@ -27,6 +27,7 @@ QVA_LAMBDA_ARRAY = 0
 QVA_LAMBDA_RING = 1
 QVA_LAMBDA_COMPLETE = 2
 QVA_MAX_QUBITS = 33
+QVA_MAX_TERMS = 1024
 QVA_EVOLVE_SKIP_FINAL_STATE = 1
 
 
@@ -38,6 +39,8 @@ class QvaProblem(ctypes.Structure):
         ("lam", ctypes.c_void_p),
         ("lambda_kind", ctypes.c_int),
         ("n_states", ctypes.c_int64),
+        ("terms", ctypes.c_void_p),
+        ("n_terms", ctypes.c_int),
     ]
 
 

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <stdint.h>
 #include <tuple>
@@ -31,10 +32,26 @@ int64_t problem_N(const qva_problem* P)
     return P->n_states > 0 ? P->n_states : (int64_t(1) << P->n_qubits);
 }
 
+static_assert(sizeof(ZTerm) == sizeof(qva_zterm) && offsetof(qva_zterm, coef) == offsetof(ZTerm, coef),
+              "ZTerm mirrors qva_zterm");
+
+// Z-string terms of an extended-QAOA phase (0: the plain phase exp(-i gamma q)).
+int problem_terms(const qva_problem* P) { return P->n_terms > 0 ? P->n_terms : 0; }
+
 int check_problem(const qva_problem* P, int p)
 {
     if (!P || p < 0)
         return QVA_ERR_ARG;
+    if (P->n_terms < 0 || P->n_terms > QVA_MAX_TERMS)
+        return QVA_ERR_ARG;
+    if (P->n_terms > 0) {
+        if (P->mixer != QVA_MIX_X)
+            return QVA_ERR_UNSUPPORTED;
+        if (!P->terms)
+            return QVA_ERR_ARG;
+        if (!aligned(P->terms, 8))
+            return QVA_ERR_ALIGN;
+    }
     if (P->mixer != QVA_MIX_X && P->mixer != QVA_MIX_CIRCULANT)
         return QVA_ERR_ARG;
     if (P->n_qubits < 1 || P->n_qubits > QVA_MAX_QUBITS)
@@ -109,7 +126,8 @@ struct Launch {
     int layer1, layer2, phase_layer;
 };
 
-std::vector<Launch> x_launches(int n, int p, bool store)
+// zterms: the phases are extended-QAOA Z-string products (XP_ZTERMS).
+std::vector<Launch> x_launches(int n, int p, bool store, bool zterms = false)
 {
     std::vector<Launch> L;
     if (n <= kTileBits) {
@@ -133,7 +151,8 @@ std::vector<Launch> x_launches(int n, int p, bool store)
             kind = QVA_PASS_LAST;
         else if (ps.flags == XMODE_LAST_STORE)
             kind = QVA_PASS_LAST_STORE;
-        L.push_back({kind, ps.group, ps.flags, ps.layer1, ps.layer2, ps.phase_layer});
+        const int zf = (zterms && ps.phase_layer >= 0) ? XP_ZTERMS : 0;
+        L.push_back({kind, ps.group, ps.flags | zf, ps.layer1, ps.layer2, ps.phase_layer});
     }
     L.push_back({QVA_PASS_REDUCE, -1, 0, -1, -1, -1});
     return L;
@@ -147,12 +166,12 @@ double launch_bytes(const Launch& l, int n, bool store)
     switch (l.kind) {
     case QVA_PASS_WHOLE:
         return real * N + (store ? amp * N : 0.0);
-    case QVA_PASS_FIRST:
-        return (real + amp) * N;
+    case QVA_PASS_FIRST:  // the Z-string phase reads no q
+        return ((l.xmode & XP_ZTERMS) ? 0.0 : real) * N + amp * N;
     case QVA_PASS_MIDDLE:
         return 2 * amp * N;
     case QVA_PASS_BOUNDARY:
-        return (2 * amp + real) * N;
+        return ((l.xmode & XP_ZTERMS) ? 0.0 : real) * N + 2 * amp * N;
     case QVA_PASS_LAST:
         return (amp + real) * N;
     case QVA_PASS_LAST_STORE:
@@ -443,8 +462,9 @@ int evolve_x(const qva_problem* P, const double* gammas, const double* ts, int p
 {
     const int n = P->n_qubits;
     const int64_t N = int64_t(1) << n;
+    const int E = problem_terms(P);
     const std::vector<XGroup> groups = x_groups(n);
-    for (const Launch& l : x_launches(n, p, store)) {
+    for (const Launch& l : x_launches(n, p, store, E > 0)) {
         hipError_t e = hipSuccess;
         hook.before(s);
         switch (l.kind) {
@@ -452,6 +472,8 @@ int evolve_x(const qva_problem* P, const double* gammas, const double* ts, int p
             SmallParams sp{};
             sp.psi = psi;
             sp.q = P->q;
+            sp.terms = reinterpret_cast<const ZTerm*>(P->terms);
+            sp.n_terms = E;
             sp.gammas = gammas;
             sp.ts = ts;
             sp.n = n;
@@ -478,7 +500,9 @@ int evolve_x(const qva_problem* P, const double* gammas, const double* ts, int p
             x.flags = l.xmode;
             x.mix1 = dev_angle(ts, l.layer1);
             x.mix2 = dev_angle(ts, l.layer2 >= 0 ? l.layer2 : 0);
-            x.phase = dev_angle(gammas, l.phase_layer >= 0 ? l.phase_layer : 0);
+            x.phase = dev_angle(gammas, l.phase_layer >= 0 ? l.phase_layer * (E > 0 ? E : 1) : 0);
+            x.terms = reinterpret_cast<const ZTerm*>(P->terms);
+            x.n_terms = E;
             x.partials = partials;
             e = launch_xpass(x, s);
             break;
@@ -648,7 +672,8 @@ int evolve_circ(const qva_problem* P, const double* gammas, const double* ts, in
 struct GradLayout {
     int64_t tiles = 0;
     int G = 1;       // t-slots per layer: qubit groups (hypercube) or 1 (circulant)
-    int nslots = 0;  // p * (G + 1) per-tile slot arrays (none for the closed-form mixer)
+    int E = 1;       // gamma slots per layer: 1, or the number of Z-string terms
+    int nslots = 0;  // p * (G + E) per-tile slot arrays (none for the closed-form mixer)
     size_t fpart = 0, slots = 0, sums = 0, lam = 0, part = 0, state = 0, total = 0;
 };
 
@@ -678,7 +703,8 @@ GradLayout grad_layout(const qva_problem* P, int p)
         return g;
     g.tiles = int64_t(1) << (n - kTileBits);
     g.G = P->mixer == QVA_MIX_X ? (int)x_groups(n).size() : 1;
-    g.nslots = p * (g.G + 1);
+    g.E = problem_terms(P) > 0 ? problem_terms(P) : 1;
+    g.nslots = p * (g.G + g.E);
     size_t off = 0;
     g.fpart = off;
     off = align256(off + (size_t)g.tiles * sizeof(double2));
@@ -737,8 +763,11 @@ std::vector<GLaunch> grad_launches(const qva_problem* P, int p)
     }
     const int PG = (int)x_groups(n).size();
     const int G = circ ? 1 : PG;
+    const int E = problem_terms(P);
+    const int zf = E > 0 ? XP_ZTERMS : 0, gz = E > 0 ? GM_ZTERMS : 0;
     auto tslot = [&](int layer, int g) { return layer * G + (circ ? 0 : g); };
-    auto gslot = [&](int layer) { return p * G + layer; };
+    // gamma slot of a layer (with Z-string terms, the first of its E slots)
+    auto gslot = [&](int layer) { return p * G + layer * (E > 0 ? E : 1); };
     if (!circ) {
         const std::vector<XPass> fw = x_evolve_plan(PG, p, false);
         const int m = (int)fw.size();
@@ -746,7 +775,8 @@ std::vector<GLaunch> grad_launches(const qva_problem* P, int p)
             const XPass& f = fw[i];
             const int kind = f.flags == XMODE_FIRST ? QVA_PASS_FIRST
                                                     : (f.flags == XMODE_BOUNDARY ? QVA_PASS_BOUNDARY : QVA_PASS_MIDDLE);
-            L.push_back({kind, f.group, f.flags, f.layer1, f.layer2, f.phase_layer, -1, -1, -1});
+            L.push_back({kind, f.group, f.flags | (f.phase_layer >= 0 ? zf : 0), f.layer1, f.layer2, f.phase_layer,
+                         -1, -1, -1});
         }
         const XPass& last = fw[m - 1];
         L.push_back({QVA_PASS_GRAD_TURN, last.group, GMODE_TURN, last.layer1, -1, -1,
@@ -757,11 +787,12 @@ std::vector<GLaunch> grad_launches(const qva_problem* P, int p)
                 L.push_back({QVA_PASS_GRAD_MID, f.group, GMODE_MID, f.layer1, -1, -1,
                              tslot(f.layer1, f.group), -1, -1});
             else
-                L.push_back({QVA_PASS_GRAD_BOUND, f.group, GMODE_BOUND, f.layer2, f.layer1, f.phase_layer,
+                L.push_back({QVA_PASS_GRAD_BOUND, f.group, GMODE_BOUND | gz, f.layer2, f.layer1, f.phase_layer,
                              tslot(f.layer2, f.group), gslot(f.phase_layer), tslot(f.layer1, f.group)});
         }
         const XPass& first = fw[0];
-        L.push_back({QVA_PASS_GRAD_FINAL, first.group, GMODE_FINAL, 0, -1, 0, tslot(0, first.group), gslot(0), -1});
+        L.push_back({QVA_PASS_GRAD_FINAL, first.group, GMODE_FINAL | gz, 0, -1, 0, tslot(0, first.group), gslot(0),
+                     -1});
     } else {
         if (lambda_tiled(P))
             L.push_back({QVA_PASS_LAMBDA_PREP, -1, 0, -1, -1, -1, -1, -1, -1});
@@ -811,10 +842,10 @@ double grad_launch_bytes(const GLaunch& l, const qva_problem* P, int p)
         return 64.0 * N;
     case QVA_PASS_GRAD_LOWDIAG:
         return 64.0 * N + (tiled ? 8.0 * N : 0.0);
-    case QVA_PASS_GRAD_BOUND:
-        return 72.0 * N;
+    case QVA_PASS_GRAD_BOUND:  // the Z-string phase reads no q; one slot per term and tile
+        return (l.mode & GM_ZTERMS) ? 64.0 * N + 8.0 * problem_terms(P) * (N / 4096.0) : 72.0 * N;
     case QVA_PASS_GRAD_FINAL:
-        return 40.0 * N;
+        return (l.mode & GM_ZTERMS) ? 32.0 * N + 8.0 * problem_terms(P) * (N / 4096.0) : 40.0 * N;
     case QVA_PASS_GRAD_REDUCE: {
         const GradLayout g = grad_layout(P, p);
         return 8.0 * (double)g.nslots * (double)g.tiles;
@@ -857,6 +888,8 @@ int grad_run(const qva_problem* P, const double* gammas, const double* ts, int p
         case QVA_PASS_GRAD_WHOLE: {
             SmallGradParams sp{};
             sp.q = P->q;
+            sp.terms = reinterpret_cast<const ZTerm*>(P->terms);
+            sp.n_terms = problem_terms(P);
             sp.gammas = gammas;
             sp.ts = ts;
             sp.lam = P->lambda;
@@ -882,7 +915,7 @@ int grad_run(const qva_problem* P, const double* gammas, const double* ts, int p
             break;
         }
         case QVA_PASS_GRAD_REDUCE:
-            e = launch_grad_reduce(slots, W.nslots, W.tiles, sums, p, W.G, dgammas, dts, s);
+            e = launch_grad_reduce(slots, W.nslots, W.tiles, sums, p, W.G, W.E, dgammas, dts, s);
             break;
         case QVA_PASS_CPL_FIRST:
         case QVA_PASS_CPL_LAYER: {
@@ -933,7 +966,9 @@ int grad_run(const qva_problem* P, const double* gammas, const double* ts, int p
             x.flags = l.mode;
             x.mix1 = dev_angle(ts, l.t1);
             x.mix2 = dev_angle(ts, l.t2 >= 0 ? l.t2 : 0);
-            x.phase = dev_angle(gammas, l.gamma >= 0 ? l.gamma : 0);
+            x.phase = dev_angle(gammas, l.gamma >= 0 ? l.gamma * W.E : 0);
+            x.terms = reinterpret_cast<const ZTerm*>(P->terms);
+            x.n_terms = problem_terms(P);
             e = launch_xpass(x, s);
             break;
         }
@@ -984,15 +1019,18 @@ int grad_run(const qva_problem* P, const double* gammas, const double* ts, int p
             gp.lambda_kind = tiled ? FFT_LAMBDA_TILED : small_lambda_kind(P->lambda_kind);
             gp.t1 = dev_angle(ts, l.t1 >= 0 ? l.t1 : 0);
             gp.t2 = dev_angle(ts, l.t2 >= 0 ? l.t2 : 0);
-            gp.gamma = dev_angle(gammas, l.gamma >= 0 ? l.gamma : 0);
+            gp.gamma = dev_angle(gammas, l.gamma >= 0 ? l.gamma * W.E : 0);
             gp.n = n;
             gp.k = g.k;
             gp.col_bits = g.col_bits;
             gp.flags = l.mode;
             gp.slot_t1 = slot_ptr(l.slot_t1);
-            gp.slot_g = slot_ptr(l.slot_g);
+            gp.slot_g = (l.mode & GM_ZTERMS) ? nullptr : slot_ptr(l.slot_g);
             gp.slot_t2 = slot_ptr(l.slot_t2);
             gp.fpart = fpart;
+            gp.terms = reinterpret_cast<const ZTerm*>(P->terms);
+            gp.n_terms = problem_terms(P);
+            gp.slot_terms = (l.mode & GM_ZTERMS) ? slot_ptr(l.slot_g) : nullptr;
             e = launch_gradpass(gp, circ, s);
             break;
         }
@@ -1243,7 +1281,7 @@ int qva_plan(const qva_problem* P, int p, int for_grad, int flags, qva_pass_info
     const int n = P->n_qubits;
     const bool circ = P->mixer == QVA_MIX_CIRCULANT;
     const std::vector<XGroup> groups = x_groups(bluestein_path(P) ? blu_bits(P) : n);
-    const std::vector<Launch> L = circ ? fft_launches(P, p, store) : x_launches(n, p, store);
+    const std::vector<Launch> L = circ ? fft_launches(P, p, store) : x_launches(n, p, store, problem_terms(P) > 0);
     for (int i = 0; i < (int)L.size() && i < max_out; ++i) {
         const Launch& l = L[i];
         out[i].kind = l.kind;

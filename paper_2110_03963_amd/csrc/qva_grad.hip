@@ -14,7 +14,9 @@
 //   circulant mixer: <chi|W|phi> = (1/N) sum_m conj(chi^_m) lambda_m phi^_m,
 //     in the low-group pass where both spectra are present;
 //   phase: <chi|Q|phi> = sum_j q_j conj(chi_j) phi_j, in the pass that
-//     undoes the phase.
+//     undoes the phase; with one angle per Z-string term (extended QAOA),
+//     <chi|Sigma_e|phi> for every term e, read off a Walsh-Hadamard transform
+//     of conj(chi_j) phi_j over each tile.
 // Each (parameter, qubit group, tile) partial is written by exactly one pass
 // and reduced afterwards in a fixed order, so results are deterministic.
 #include "qva_passes.h"
@@ -38,6 +40,17 @@ using namespace passes;
 // ------------------------------------------------ hypercube-mixer passes
 template <int C, int MODE>
 __global__ __launch_bounds__(kThreads, QVA_GRADX_WAVES) void gradx_kernel(GradPassParams P)
+{
+    __shared__ double2 lds[1 << kTileBits];
+    __shared__ double red[4 * (kThreads / 64)];
+    gradx_tile<C, MODE>(P, blockIdx.x, lds, red);
+}
+
+// The extended-QAOA phase passes hold the term coefficients and the
+// transform operand beside both vectors: one wave per SIMD keeps them in
+// registers.
+template <int C, int MODE>
+__global__ __launch_bounds__(kThreads, QVA_GRADF_WAVES) void gradxz_kernel(GradPassParams P)
 {
     __shared__ double2 lds[1 << kTileBits];
     __shared__ double red[4 * (kThreads / 64)];
@@ -322,9 +335,15 @@ __global__ __launch_bounds__(kThreads) void small_grad_kernel(SmallGradParams P)
         ph[j] = make_double2(a0, 0.0);
     __syncthreads();
     for (int L = 0; L < P.p; ++L) {
-        const double gam = P.gammas[L];
-        for (int j = t; j < N; j += blockDim.x)
-            ph[j] = cmul(ph[j], expmi(gam * P.q[j]));
+        if (P.n_terms > 0) {
+            const double* row = P.gammas + (int64_t)L * P.n_terms;
+            for (int j = t; j < N; j += blockDim.x)
+                ph[j] = cmul(ph[j], expmi(zterm_angle(j, P.terms, P.n_terms, row)));
+        } else {
+            const double gam = P.gammas[L];
+            for (int j = t; j < N; j += blockDim.x)
+                ph[j] = cmul(ph[j], expmi(gam * P.q[j]));
+        }
         __syncthreads();
         if (circ)
             small_circ(ph, nullptr, P, P.ts[L]);
@@ -345,6 +364,51 @@ __global__ __launch_bounds__(kThreads) void small_grad_kernel(SmallGradParams P)
     for (int L = P.p - 1; L >= 0; --L) {
         const double tt = P.ts[L];
         const double at = circ ? small_circ(ph, ch, P, -tt) : small_unrotate_x(ph, ch, n, tt);
+        if (P.n_terms > 0) {
+            // extended QAOA: Im(conj(chi_j) phi_j) of the thread's states, the
+            // inverse phase, then one block sum per term (two at a time)
+            const int E = P.n_terms;
+            const double* row = P.gammas + (int64_t)L * E;
+            double dj[kRegs];  // N <= kRegs * kThreads
+#pragma unroll
+            for (int i = 0; i < kRegs; ++i) {
+                const int j = t + i * kThreads;
+                dj[i] = 0.0;
+                if (j < N) {
+                    dj[i] = ch[j].x * ph[j].y - ch[j].y * ph[j].x;
+                    const double2 u = expmi(-zterm_angle(j, P.terms, E, row));
+                    ph[j] = cmul(ph[j], u);
+                    ch[j] = cmul(ch[j], u);
+                }
+            }
+            const double2 ts_sum = block_sum2(at, 0.0, red);
+            if (t == 0)
+                P.dts[L] = 2.0 * ts_sum.x;
+            for (int e = 0; e < E; e += 2) {
+                double a[2] = {0.0, 0.0};
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    if (e + h >= E)
+                        continue;
+                    const uint64_t S = P.terms[e + h].support;
+#pragma unroll
+                    for (int i = 0; i < kRegs; ++i) {
+                        const int j = t + i * kThreads;
+                        if (j < N)
+                            a[h] += (__popcll((uint64_t)j & S) & 1) ? -dj[i] : dj[i];
+                    }
+                    a[h] *= P.terms[e + h].coef;
+                }
+                const double2 sm = block_sum2(a[0], a[1], red);
+                if (t == 0) {
+                    P.dgammas[(int64_t)L * E + e] = 2.0 * sm.x;
+                    if (e + 1 < E)
+                        P.dgammas[(int64_t)L * E + e + 1] = 2.0 * sm.y;
+                }
+            }
+            __syncthreads();
+            continue;
+        }
         double ag = 0.0;
         const double gam = P.gammas[L];
         for (int j = t; j < N; j += blockDim.x) {
@@ -377,16 +441,17 @@ __global__ __launch_bounds__(256) void slot_reduce_kernel(const double* slots, i
         out[blockIdx.x] = tot.x;
 }
 
-// dts[L] = 2 sum_g sums[L * G + g] (g ascending); dgammas[L] = 2 sums[p G + L]
-__global__ void grad_finalize_kernel(const double* sums, int p, int G, double* dgammas, double* dts)
+// dts[L] = 2 sum_g sums[L * G + g] (g ascending); dgammas[i] = 2 sums[p G + i], i < p E
+__global__ void grad_finalize_kernel(const double* sums, int p, int G, int E, double* dgammas, double* dts)
 {
     for (int L = threadIdx.x; L < p; L += blockDim.x) {
         double s = 0.0;
         for (int g = 0; g < G; ++g)
             s += sums[L * G + g];
         dts[L] = 2.0 * s;
-        dgammas[L] = 2.0 * sums[p * G + L];
     }
+    for (int i = threadIdx.x; i < p * E; i += blockDim.x)
+        dgammas[i] = 2.0 * sums[p * G + i];
 }
 
 template <int C>
@@ -404,6 +469,12 @@ hipError_t launch_gradx_c(const GradPassParams& P, unsigned grid, hipStream_t s)
         break;
     case GMODE_FINAL:
         hipLaunchKernelGGL((gradx_kernel<C, GMODE_FINAL>), dim3(grid), dim3(kThreads), 0, s, P);
+        break;
+    case GMODE_BOUND_Z:
+        hipLaunchKernelGGL((gradxz_kernel<C, GMODE_BOUND_Z>), dim3(grid), dim3(kThreads), 0, s, P);
+        break;
+    case GMODE_FINAL_Z:
+        hipLaunchKernelGGL((gradxz_kernel<C, GMODE_FINAL_Z>), dim3(grid), dim3(kThreads), 0, s, P);
         break;
     default:
         return hipErrorInvalidValue;
@@ -498,7 +569,7 @@ hipError_t launch_small_grad(const SmallGradParams& P, hipStream_t s)
 }
 
 hipError_t launch_grad_reduce(const double* slots, int nslots, int64_t tiles, double* sums, int p, int G,
-                              double* dgammas, double* dts, hipStream_t s)
+                              int E, double* dgammas, double* dts, hipStream_t s)
 {
     if (nslots > 0) {
         hipLaunchKernelGGL(slot_reduce_kernel, dim3(nslots), dim3(256), 0, s, slots, tiles, sums);
@@ -506,7 +577,7 @@ hipError_t launch_grad_reduce(const double* slots, int nslots, int64_t tiles, do
         if (e != hipSuccess)
             return e;
     }
-    hipLaunchKernelGGL(grad_finalize_kernel, dim3(1), dim3(64), 0, s, sums, p, G, dgammas, dts);
+    hipLaunchKernelGGL(grad_finalize_kernel, dim3(1), dim3(64), 0, s, sums, p, G, E, dgammas, dts);
     return hipGetLastError();
 }
 

@@ -28,7 +28,8 @@ enum : int {
     XP_MIX2 = 16,        // second mixer application (angle mix2)
     XP_EXPECT = 32,      // accumulate sum |psi|^2 q and sum |psi|^2
     XP_STORE = 64,       // write psi back
-    XP_FINAL_SCALE = 128 // multiply by the layer factor of mix1 (all qubits)
+    XP_FINAL_SCALE = 128, // multiply by the layer factor of mix1 (all qubits)
+    XP_ZTERMS = 256      // the phase is the extended-QAOA product over Z-string terms
 };
 
 // The flag combinations the passes are compiled for.
@@ -38,13 +39,24 @@ enum : int {
     XMODE_BOUNDARY = XP_MIX1 | XP_PHASE_MID | XP_MIX2 | XP_STORE,
     XMODE_LAST = XP_MIX1 | XP_EXPECT | XP_FINAL_SCALE,
     XMODE_LAST_STORE = XP_MIX1 | XP_EXPECT | XP_FINAL_SCALE | XP_STORE,
-    XMODE_MIX_SCALE = XP_MIX1 | XP_FINAL_SCALE | XP_STORE
+    XMODE_MIX_SCALE = XP_MIX1 | XP_FINAL_SCALE | XP_STORE,
+    XMODE_FIRST_Z = XMODE_FIRST | XP_ZTERMS,
+    XMODE_BOUNDARY_Z = XMODE_BOUNDARY | XP_ZTERMS
+};
+
+// A term of a Pauli decomposition of Q (same layout as qva_zterm):
+// Sigma(j) = coef (-1)^popcount(j & support).
+struct ZTerm {
+    uint64_t support;
+    double coef;
 };
 
 struct XPassParams {
     double2* psi;
     const double* q;
-    Angle mix1, mix2, phase;
+    Angle mix1, mix2, phase;  // XP_ZTERMS: phase.ptr + phase.idx is the layer's angle row
+    const ZTerm* terms;       // XP_ZTERMS
+    int n_terms;
     int n;        // qubits of the register
     int k;        // first target qubit of the tile's group
     int col_bits; // contiguous low index bits per tile row (0 for the low group)
@@ -55,6 +67,8 @@ struct XPassParams {
 struct SmallParams {
     double2* psi;        // in/out (read unless SM_INIT, written if SM_STORE)
     const double* q;
+    const ZTerm* terms;  // extended-QAOA phases (gammas then p x n_terms), or null
+    int n_terms;
     const double* gammas;
     const double* ts;
     double t_val;        // angle for SM_MIX_ONCE
@@ -224,7 +238,10 @@ enum : int {
     GMODE_FINAL = 4,   // inverse of the first forward pass (accumulate only)
     GMODE_DIF = 5,     // forward transform of one group, both vectors (circulant)
     GMODE_DIT = 6,     // inverse transform of one group, both vectors
-    GMODE_LOWDIAG = 7  // low group: forward, <chi^|lambda|phi^>, inverse diagonal, inverse
+    GMODE_LOWDIAG = 7, // low group: forward, <chi^|lambda|phi^>, inverse diagonal, inverse
+    GM_ZTERMS = 16,    // with GMODE_BOUND / GMODE_FINAL: extended-QAOA phase, one slot per term
+    GMODE_BOUND_Z = GMODE_BOUND | GM_ZTERMS,
+    GMODE_FINAL_Z = GMODE_FINAL | GM_ZTERMS
 };
 
 struct GradPassParams {
@@ -242,10 +259,15 @@ struct GradPassParams {
     double* slot_g;
     double* slot_t2;
     double2* fpart;   // per-tile (f, norm) partials (GMODE_TURN)
+    const ZTerm* terms;   // GM_ZTERMS: gamma.ptr + gamma.idx is the layer's angle row
+    int n_terms;
+    double* slot_terms;   // GM_ZTERMS: term e of tile i at slot_terms[e * tiles + i]
 };
 
 struct SmallGradParams {
     const double* q;
+    const ZTerm* terms;  // extended-QAOA phases (gammas and dgammas p x n_terms), or null
+    int n_terms;
     const double* gammas;
     const double* ts;
     const double* lam;
@@ -260,8 +282,10 @@ struct SmallGradParams {
 
 hipError_t launch_gradpass(const GradPassParams& P, bool circulant, hipStream_t s);
 hipError_t launch_small_grad(const SmallGradParams& P, hipStream_t s);
+// Slot sums, then dts[L] = 2 sum_g sums[L G + g] and dgammas[i] = 2 sums[p G + i]
+// for i < p E (E gamma slots per layer: 1, or the number of Z-string terms).
 hipError_t launch_grad_reduce(const double* slots, int nslots, int64_t tiles, double* sums, int p, int G,
-                              double* dgammas, double* dts, hipStream_t s);
+                              int E, double* dgammas, double* dts, hipStream_t s);
 
 // ---------------------------------------------------------------- batched
 // Many independent hypercube-mixer instances, forward + adjoint: the passes

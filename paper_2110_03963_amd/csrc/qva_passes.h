@@ -3,6 +3,8 @@
 // (multi-instance) kernel call the same code.
 #pragma once
 
+#include <type_traits>
+
 #include "qva_tile.h"
 
 namespace qva {
@@ -31,6 +33,21 @@ __device__ __forceinline__ void phase_vals(double2 (&v)[kRegs], const double (&q
     }
 }
 
+// In-register Walsh-Hadamard transform over the 4 register bits:
+// a[r] <- sum_m (-1)^popcount(m & r) a[m].
+__device__ __forceinline__ void wht16(double (&a)[kRegs])
+{
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int r = 0; r < kRegs; ++r)
+            if (!(r & (1 << b))) {
+                const double u = a[r], w = a[r | (1 << b)];
+                a[r] = u + w;
+                a[r | (1 << b)] = u - w;
+            }
+}
+
 // psi <- scale * exp(-i gamma q) psi in layout L
 template <int L>
 __device__ __forceinline__ void phase_regs(double2 (&v)[kRegs], const double* q, const TileMap& g,
@@ -39,6 +56,61 @@ __device__ __forceinline__ void phase_regs(double2 (&v)[kRegs], const double* q,
     double qq[kRegs];
     load_q<L>(qq, q, g, t);
     phase_vals(v, qq, gamma, scale);
+}
+
+// sum_e gam[e] c_e (-1)^popcount(j & S_e), e ascending (one basis state)
+__device__ __forceinline__ double zterm_angle(int64_t j, const ZTerm* terms, int n_terms, const double* gam)
+{
+    double a = 0.0;
+    for (int e = 0; e < n_terms; ++e) {
+        const double v = gam[e] * terms[e].coef;
+        a += (__popcll((uint64_t)j & terms[e].support) & 1) ? -v : v;
+    }
+    return a;
+}
+
+// Global index bit of register bit b of layout L in a tile with C column bits.
+template <int L, int C>
+__device__ __forceinline__ int reg_global_bit(const TileMap& g, int b)
+{
+    const int eb = reg_elem_bit<L>(b);
+    return eb < C ? eb : g.k + eb - C;
+}
+
+// Extended-QAOA phase angles of the registers of layout L (eq.
+// phase_shift_qaoa_ex with Z-string terms):
+//   ph[r] = sum_e gam[e] c_e (-1)^popcount(j_r & S_e).
+// The register bits of j_r are global bits that no other part of j_r sets, so
+// (-1)^popcount(j_r & S_e) = (-1)^popcount(j_0 & S_e) (-1)^popcount(r & m_e),
+// where m_e (the register bits S_e covers) is the same for every thread.  Each
+// term adds its signed value to the coefficient cf[m_e], and ph is the
+// 16-point Walsh-Hadamard transform of cf.  cf is a register vector indexed
+// by the wave-uniform m_e (relative register addressing, no branches).
+template <int L, int C>
+__device__ __forceinline__ void zterm_angles(double (&ph)[kRegs], const ZTerm* terms, int n_terms,
+                                             const double* gam, const TileMap& g, int t)
+{
+    typedef double dvec16 __attribute__((ext_vector_type(16)));
+    int gb[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+        gb[b] = reg_global_bit<L, C>(g, b);
+    const uint64_t j0 = (uint64_t)g(elem<L>(t, 0));
+    dvec16 cf = 0.0;
+    for (int e = 0; e < n_terms; ++e) {
+        const uint64_t S = terms[e].support;
+        const double v0 = gam[e] * terms[e].coef;
+        const double v = (__popcll(j0 & S) & 1) ? -v0 : v0;
+        int m = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            m |= (int)((S >> gb[b]) & 1) << b;
+        cf[__builtin_amdgcn_readfirstlane(m)] += v;
+    }
+#pragma unroll
+    for (int r = 0; r < kRegs; ++r)
+        ph[r] = cf[r];
+    wht16(ph);
 }
 
 // qq: q in layout L (read only with XP_EXPECT).
@@ -79,10 +151,12 @@ __device__ __forceinline__ void xpass_tile(const XPassParams& P, int64_t tile, d
     static_assert(((flags & XP_PHASE_PRE) ? 1 : 0) + ((flags & XP_PHASE_MID) ? 1 : 0) +
                           ((flags & XP_EXPECT) ? 1 : 0) <= 1,
                   "one use of q per pass");
-    // layout of the tail (store / expectation) and of the pass's use of q
+    constexpr bool zterms = flags & XP_ZTERMS;
+    static_assert(!zterms || (flags & (XP_PHASE_PRE | XP_PHASE_MID)), "Z-string terms need a phase");
+    // layout of the tail (store / expectation) and of the pass's phase / use of q
     constexpr int LT = ((flags & XP_MIX2) || !(flags & XP_MIX1)) ? LA : last_layout<C>();
     constexpr int LQ = (flags & XP_PHASE_PRE) ? LA : (flags & XP_PHASE_MID) ? last_layout<C>() : LT;
-    constexpr bool use_q = flags & (XP_PHASE_PRE | XP_PHASE_MID | XP_EXPECT);
+    constexpr bool use_q = zterms ? bool(flags & XP_EXPECT) : bool(flags & (XP_PHASE_PRE | XP_PHASE_MID | XP_EXPECT));
 
     const int t = threadIdx.x;
     const TileMap g = tile_map(tile, P.k, C);
@@ -101,9 +175,13 @@ __device__ __forceinline__ void xpass_tile(const XPassParams& P, int64_t tile, d
     double qq[kRegs];
     if constexpr (use_q)
         load_q<LQ>(qq, P.q, g, t);
+    // Z-string terms: the phase angles themselves stand in for q (gamma = 1)
+    if constexpr (zterms)
+        zterm_angles<LQ, C>(qq, P.terms, P.n_terms, P.phase.ptr + P.phase.idx, g, t);
+    const double gam = zterms ? 1.0 : ((flags & (XP_PHASE_PRE | XP_PHASE_MID)) ? angle_value(P.phase) : 0.0);
 
     if constexpr (flags & XP_PHASE_PRE)
-        phase_vals(v, qq, angle_value(P.phase), make_double2(1.0, 0.0));
+        phase_vals(v, qq, gam, make_double2(1.0, 0.0));
 
     double2 S1 = make_double2(1.0, 0.0);
     if constexpr (flags & XP_MIX1) {
@@ -115,7 +193,7 @@ __device__ __forceinline__ void xpass_tile(const XPassParams& P, int64_t tile, d
         S1 = cpow_int(m.sigma, P.n);
     }
     if constexpr (flags & XP_PHASE_MID)
-        phase_vals(v, qq, angle_value(P.phase), S1);
+        phase_vals(v, qq, gam, S1);
     if constexpr (flags & XP_MIX2) {
         const MixCoef m = mix_coef(angle_value(P.mix2));
         if (m.tanform)
@@ -301,6 +379,78 @@ __device__ __forceinline__ void write_slots(const GradPassParams& P, double a1, 
     }
 }
 
+// Walsh-Hadamard transform of a tile of reals over its 12 element bits.  d
+// holds the tile in layout L; afterwards lds[swz(m)].x = sum_e (-1)^popcount(e & m) d_e
+// for every element mask m (visible to the whole block).  lds: the tile
+// exchange buffer (the first write waits for the block); the reals sit in
+// the amplitude slots, so the addresses are the exchanges' own.  The register
+// bits of LC, LB and LA are element bits [0,4), [4,8) and [8,12); L's own
+// register bits are transformed in place first when L is one of them.
+template <int L>
+__device__ __forceinline__ void wht_tile(double (&d)[kRegs], double2* lds, int t)
+{
+    constexpr bool own = L != LA3;
+    if constexpr (own)
+        wht16(d);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRegs; ++r)
+        lds[swz(elem<L>(t, r))].x = d[r];
+    auto stage = [&](auto lw) {
+        constexpr int W = decltype(lw)::value;
+        if constexpr (!(own && W == L)) {
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < kRegs; ++r)
+                d[r] = lds[swz(elem<W>(t, r))].x;
+            wht16(d);
+#pragma unroll
+            for (int r = 0; r < kRegs; ++r)
+                lds[swz(elem<W>(t, r))].x = d[r];
+        }
+    };
+    stage(std::integral_constant<int, LC>());
+    stage(std::integral_constant<int, LB>());
+    stage(std::integral_constant<int, LA>());
+    __syncthreads();
+}
+
+// Per-term slots of the extended-QAOA gradient: for every term e,
+//   slot_terms[e * tiles + tile] = sum over the tile of c_e (-1)^popcount(j & S_e) d_j,
+// d_j = Im(conj(chi_j) phi_j) held in layout L.  Within the tile j = base + j(e)
+// with j(e) the global bits of element index e, so the sign splits into a
+// constant (-1)^popcount(base & S_e) and (-1)^popcount(e & m_e), m_e the
+// element bits whose global bits S_e covers: the sum is one value of the
+// tile's Walsh-Hadamard transform.  Every term is read off the same
+// transform, with no per-term reduction.
+template <int C, int L>
+__device__ __forceinline__ void zterm_slots(double (&d)[kRegs], const GradPassParams& P, const TileMap& g,
+                                            int t, int64_t tile, double2* lds)
+{
+    wht_tile<L>(d, lds, t);
+    const int64_t tiles = int64_t(1) << (P.n - kTileBits);
+    for (int e = t; e < P.n_terms; e += kThreads) {
+        const uint64_t S = P.terms[e].support;
+        int m = 0;
+#pragma unroll
+        for (int eb = 0; eb < kTileBits; ++eb) {
+            const int gb = eb < C ? eb : g.k + eb - C;
+            m |= (int)((S >> gb) & 1) << eb;
+        }
+        const double v = P.terms[e].coef * lds[swz(m)].x;
+        P.slot_terms[(int64_t)e * tiles + tile] = (__popcll((uint64_t)g.base & S) & 1) ? -v : v;
+    }
+}
+
+// Block sum of one accumulator to its per-tile slot (skipped when null).
+__device__ __forceinline__ void write_slot(double* slot, double a, double* red, int64_t tile)
+{
+    double v[1] = {a};
+    block_sum_k<1>(v, red);
+    if (slot && threadIdx.x == 0)
+        slot[tile] = v[0];
+}
+
 // ------------------------------------------------ hypercube-mixer passes
 // One tile of a backward hypercube-mixer pass (see GradPassParams and GMODE_*).
 // lds: 4096 amplitudes of shared memory; red: 16 doubles of shared memory.
@@ -347,28 +497,56 @@ __device__ __forceinline__ void gradx_tile(const GradPassParams& P, int64_t tile
         write_slots(P, a1, 0.0, 0.0, red, tile);
         store2<LA>(p, x, P, g, t);
     } else {
+        constexpr int BM = MODE & ~GM_ZTERMS;
+        constexpr bool zterms = MODE & GM_ZTERMS;
+        static_assert(!zterms || BM == GMODE_BOUND || BM == GMODE_FINAL, "Z-string terms at a phase only");
+        constexpr int L = last_layout<C>();
         // every angle and its sine/cosine before the data is loaded: computed
         // mid-pass they extend register live ranges across the whole tile
         double c, s, c2 = 1.0, s2 = 0.0, gam = 0.0;
         inv_cs(angle_value(P.t1), c, s);
-        if constexpr (MODE == GMODE_BOUND)
+        if constexpr (BM == GMODE_BOUND)
             inv_cs(angle_value(P.t2), c2, s2);
-        if constexpr (MODE != GMODE_MID)
+        if constexpr (BM != GMODE_MID && !zterms)
             gam = angle_value(P.gamma);
         load2<LA>(p, x, P, g, t);
         mix2_forward<C>(p, x, lds, t, c, s, a1);
-        if constexpr (MODE == GMODE_MID) {
+        if constexpr (BM == GMODE_MID) {
             write_slots(P, a1, 0.0, 0.0, red, tile);
-            store2<last_layout<C>()>(p, x, P, g, t);
+            store2<L>(p, x, P, g, t);
         } else {
             // the forward pass applied the layer's scalar factor together with
             // the phase; the direct-form inverse rotations need none
-            ag = unphase2<last_layout<C>(), false>(p, x, P.q, g, t, gam, 1.0);
-            if constexpr (MODE == GMODE_BOUND) {
+            if constexpr (zterms) {
+                // the mixer slot first: its sum is then taken here, not
+                // deferred past the term loop with every rotation's operands
+                write_slot(P.slot_t1, a1, red, tile);
+                // the angles, then register by register the inverse phase on
+                // both vectors and Im(conj(chi) phi) in place of the angle
+                // (taken after the phase, which it does not change, so that
+                // the phase is not deferred past the transform)
+                double dv[kRegs];
+                zterm_angles<L, C>(dv, P.terms, P.n_terms, P.gamma.ptr + P.gamma.idx, g, t);
+#pragma unroll
+                for (int r = 0; r < kRegs; ++r) {
+                    const double2 u = expmi(-dv[r]);
+                    p[r] = cmul(p[r], u);
+                    x[r] = cmul(x[r], u);
+                    dv[r] = x[r].x * p[r].y - x[r].y * p[r].x;
+                    QVA_SCHED_FENCE();
+                }
+                zterm_slots<C, L>(dv, P, g, t, tile, lds);
+            } else {
+                ag = unphase2<L, false>(p, x, P.q, g, t, gam, 1.0);
+            }
+            if constexpr (BM == GMODE_BOUND) {
                 mix2_reverse<C>(p, x, lds, t, c2, s2, a2);
-                write_slots(P, a1, ag, a2, red, tile);
+                if constexpr (zterms)
+                    write_slot(P.slot_t2, a2, red, tile);
+                else
+                    write_slots(P, a1, ag, a2, red, tile);
                 store2<LA>(p, x, P, g, t);
-            } else {  // GMODE_FINAL
+            } else if constexpr (!zterms) {  // GMODE_FINAL
                 write_slots(P, a1, ag, 0.0, red, tile);
             }
         }

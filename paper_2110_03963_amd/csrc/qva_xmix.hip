@@ -11,7 +11,8 @@
 // amplitudes, so every global access is a run of >= 128 bytes.
 //
 // Elementwise work is fused into the passes: the initial state, the phase
-// exp(-i gamma q_j) (eq. phase_shift_qaoa), and the expectation sum
+// exp(-i gamma q_j) (eq. phase_shift_qaoa) or its extended form with one angle
+// per Z-string term of Q (eq. phase_shift_qaoa_ex), and the expectation sum
 // |psi_j|^2 q_j (eq. objective_generic).
 #include "qva_passes.h"
 
@@ -63,9 +64,15 @@ __global__ __launch_bounds__(kThreads) void small_kernel(SmallParams P)
         small_mix(s, P.n, P.t_val);
     if (P.flags & SM_EVOLVE) {
         for (int layer = 0; layer < P.p; ++layer) {
-            const double gam = P.gammas[layer];
-            for (int j = t; j < N; j += blockDim.x)
-                s[j] = cmul(s[j], expmi(gam * P.q[j]));
+            if (P.n_terms > 0) {
+                const double* row = P.gammas + (int64_t)layer * P.n_terms;
+                for (int j = t; j < N; j += blockDim.x)
+                    s[j] = cmul(s[j], expmi(zterm_angle(j, P.terms, P.n_terms, row)));
+            } else {
+                const double gam = P.gammas[layer];
+                for (int j = t; j < N; j += blockDim.x)
+                    s[j] = cmul(s[j], expmi(gam * P.q[j]));
+            }
             __syncthreads();
             small_mix(s, P.n, P.ts[layer]);
         }
@@ -107,6 +114,8 @@ hipError_t launch_xpass_c(const XPassParams& P, unsigned grid, hipStream_t s)
         QVA_XPASS_MODE(XMODE_LAST)
         QVA_XPASS_MODE(XMODE_LAST_STORE)
         QVA_XPASS_MODE(XMODE_MIX_SCALE)
+        QVA_XPASS_MODE(XMODE_FIRST_Z)
+        QVA_XPASS_MODE(XMODE_BOUNDARY_Z)
 #undef QVA_XPASS_MODE
     default:
         return hipErrorInvalidValue;

@@ -10,6 +10,7 @@ from __future__ import annotations
 import ctypes
 import math
 
+import numpy as np
 import torch
 
 from . import _lib
@@ -118,10 +119,15 @@ class Problem:
     solution count of a constrained problem): closed-form passes for the
     complete graph, Bluestein's transform for the ring or an array (forward
     only).  The hypercube mixer needs a power of two.
+
+    terms (hypercube mixer only): the extended QAOA, one phase angle per term
+    of a Z-string decomposition of the cost, given as (supports, coefs) with
+    Sigma_e(j) = coefs[e] (-1)^popcount(j & supports[e]); gammas are then
+    p x n_terms and q is only the observable.
     """
 
     def __init__(self, q: torch.Tensor, mixer: str = "x", lam: torch.Tensor | None = None,
-                 lambda_kind: str = "array"):
+                 lambda_kind: str = "array", terms=None):
         _need(q, torch.float64, "q")
         self.q = q
         N = q.numel()
@@ -139,9 +145,21 @@ class Problem:
             _need(lam, torch.float64, "lam")
             if lam.numel() != q.numel():
                 raise ValueError("lam and q differ in length")
+        self.terms = None
+        self.n_terms = 0
+        if terms is not None:
+            supports, coefs = terms
+            packed = np.zeros(len(supports), dtype=[("support", "<u8"), ("coef", "<f8")])
+            packed["support"] = np.asarray(supports, dtype=np.uint64)
+            packed["coef"] = np.asarray(coefs, dtype=np.float64)
+            if len(packed) != len(coefs):
+                raise ValueError("one coefficient per support")
+            self.n_terms = len(packed)
+            if self.n_terms:
+                self.terms = torch.from_numpy(packed.view(np.uint8).copy()).to(q.device)
         self._c = _lib.QvaProblem(MIXERS[mixer], self.n, _ptr(q),
                                   _ptr(lam) if (mixer == "circulant" and lambda_kind == "array") else None,
-                                  LAMBDA_KINDS[self.lambda_kind], n_states)
+                                  LAMBDA_KINDS[self.lambda_kind], n_states, _ptr(self.terms), self.n_terms)
 
     @property
     def N(self) -> int:
@@ -162,7 +180,17 @@ def _angles(x, device) -> torch.Tensor:
     if isinstance(x, torch.Tensor):
         x = x.detach().to(device=device, dtype=torch.float64).contiguous()
         return x
-    return torch.tensor(list(x), dtype=torch.float64, device=device)
+    return torch.tensor(np.asarray(x, dtype=np.float64), dtype=torch.float64, device=device)
+
+
+def _layer_angles(problem: Problem, gammas, ts, dev):
+    """Flat device gammas (p, or p x n_terms with terms), ts and p."""
+    g = _angles(gammas, dev).reshape(-1)
+    t = _angles(ts, dev).reshape(-1)
+    per = problem.n_terms if problem.n_terms > 0 else 1
+    if g.numel() != t.numel() * per:
+        raise ValueError("one gamma per layer (per term with terms) and one t per layer")
+    return g, t, t.numel()
 
 
 def evolve(problem: Problem, gammas, ts, psi: torch.Tensor | None = None, store: bool = True,
@@ -173,11 +201,7 @@ def evolve(problem: Problem, gammas, ts, psi: torch.Tensor | None = None, store:
     state (a new tensor unless one is passed in).
     """
     dev = problem.device
-    g = _angles(gammas, dev)
-    t = _angles(ts, dev)
-    if g.numel() != t.numel():
-        raise ValueError("one gamma and one t per layer")
-    p = g.numel()
+    g, t, p = _layer_angles(problem, gammas, ts, dev)
     if psi is None:
         psi = torch.empty(problem.N, dtype=torch.complex128, device=dev)
     else:
@@ -199,13 +223,10 @@ def evolve(problem: Problem, gammas, ts, psi: torch.Tensor | None = None, store:
 
 def grad(problem: Problem, gammas, ts, psi: torch.Tensor | None = None,
          chi: torch.Tensor | None = None, workspace: torch.Tensor | None = None):
-    """(f, df/dgamma, df/dt) by the adjoint method (device tensors)."""
+    """(f, df/dgamma, df/dt) by the adjoint method (device tensors); with
+    terms, df/dgamma is p x n_terms."""
     dev = problem.device
-    g = _angles(gammas, dev)
-    t = _angles(ts, dev)
-    if g.numel() != t.numel():
-        raise ValueError("one gamma and one t per layer")
-    p = g.numel()
+    g, t, p = _layer_angles(problem, gammas, ts, dev)
     if psi is None:
         psi = torch.empty(problem.N, dtype=torch.complex128, device=dev)
     if chi is None:
@@ -217,13 +238,15 @@ def grad(problem: Problem, gammas, ts, psi: torch.Tensor | None = None,
     if workspace is None or workspace.numel() < need:
         workspace = _workspace(need, dev)
     f = torch.empty((), dtype=torch.float64, device=dev)
-    dg = torch.empty(p, dtype=torch.float64, device=dev)
+    dg = torch.empty(g.numel(), dtype=torch.float64, device=dev)
     dt = torch.empty(p, dtype=torch.float64, device=dev)
     _lib.check("qva_grad",
                lib.qva_grad(problem.cstruct(), g.data_ptr(), t.data_ptr(), p, psi.data_ptr(),
                             chi.data_ptr(), f.data_ptr(), dg.data_ptr(), dt.data_ptr(),
                             _ptr(workspace), 0 if workspace is None else workspace.numel(),
                             _stream()))
+    if problem.n_terms > 0:
+        dg = dg.view(p, problem.n_terms)
     return f, dg, dt
 
 
@@ -238,7 +261,7 @@ class QVAExpectation(torch.autograd.Function):
     def forward(ctx, gammas: torch.Tensor, ts: torch.Tensor, problem: Problem):
         if ctx.needs_input_grad[0] or ctx.needs_input_grad[1]:
             f, dg, dt = grad(problem, gammas, ts)
-            ctx.save_for_backward(dg, dt)
+            ctx.save_for_backward(dg.reshape(gammas.shape), dt.reshape(ts.shape))
         else:
             f, _, _ = evolve(problem, gammas, ts, store=False)
             ctx.save_for_backward(None, None)

@@ -50,8 +50,8 @@ def test_status_strings(lib):
 FAKE = 0x7F0000001000  # never dereferenced: every call below fails validation first
 
 
-def _prob(mixer=0, n=20, q=FAKE, lam=None, kind=0, n_states=0):
-    return _lib.QvaProblem(mixer, n, q, lam, kind, n_states)
+def _prob(mixer=0, n=20, q=FAKE, lam=None, kind=0, n_states=0, terms=None, n_terms=0):
+    return _lib.QvaProblem(mixer, n, q, lam, kind, n_states, terms, n_terms)
 
 
 def test_validation_errors(lib):
@@ -402,3 +402,61 @@ def test_batch_validation(lib):
     assert lib.qva_batch_create(arr, 1, 0, ctypes.byref(plan)) == _lib.QVA_ERR_ALIGN
     assert lib.qva_batch_create(_batch_items([(14, 2)]), 1, 7, ctypes.byref(plan)) == _lib.QVA_ERR_ARG
     assert lib.qva_batch_create(_batch_items([(14, 2)]), 0, 0, ctypes.byref(plan)) == _lib.QVA_ERR_ARG
+
+
+# ------------------------------------------------------------ extended QAOA
+def test_zterm_validation(lib):
+    """Z-string terms: hypercube mixer only, 1..QVA_MAX_TERMS, non-null and
+    8-byte aligned; checked before anything is launched."""
+    S = _lib
+    assert S.QVA_MAX_TERMS == 1024
+    ok = _prob(n=20, terms=FAKE, n_terms=5)
+    assert lib.qva_plan(ctypes.byref(ok), 2, 0, 0, None, 0) > 0
+    assert lib.qva_plan(ctypes.byref(ok), 2, 1, 0, None, 0) > 0
+    for bad, st in [(_prob(n=20, terms=None, n_terms=5), S.QVA_ERR_ARG),
+                    (_prob(n=20, terms=FAKE, n_terms=-1), S.QVA_ERR_ARG),
+                    (_prob(n=20, terms=FAKE, n_terms=1025), S.QVA_ERR_ARG),
+                    (_prob(n=20, terms=FAKE + 4, n_terms=3), S.QVA_ERR_ALIGN),
+                    (_prob(mixer=1, n=20, kind=1, terms=FAKE, n_terms=3), S.QVA_ERR_UNSUPPORTED)]:
+        assert lib.qva_plan(ctypes.byref(bad), 2, 0, 0, None, 0) == st
+        assert lib.qva_workspace_bytes(ctypes.byref(bad), 2, 1) == 0
+        assert lib.qva_evolve(ctypes.byref(bad), FAKE, FAKE, 2, FAKE, FAKE, None, 0, None, 0, None) == st
+    # n_terms = 0 ignores the pointer
+    plain = _prob(n=20, terms=FAKE + 4, n_terms=0)
+    assert lib.qva_plan(ctypes.byref(plain), 2, 0, 0, None, 0) > 0
+
+
+@pytest.mark.parametrize("n,p", [(13, 1), (20, 3), (28, 8)])
+def test_zterm_plan(lib, n, p):
+    """With terms the passes are those of QAOA; the phase passes read no q
+    (first pass 16 B/amp, boundary 32 B/amp), and the gradient has one slot
+    array per term and layer: workspace grows by p E tiles doubles."""
+    E = 37
+    zt = _prob(n=n, terms=FAKE, n_terms=E)
+    pl = _prob(n=n)
+    N = 1 << n
+    for flags in (0, 1):
+        a = _plan(lib, n, p, flags=flags)
+        cnt = lib.qva_plan(ctypes.byref(zt), p, 0, flags, None, 0)
+        arr = (_lib.QvaPassInfo * cnt)()
+        assert lib.qva_plan(ctypes.byref(zt), p, 0, flags, arr, cnt) == cnt == len(a)
+        for x, y in zip(arr, a):
+            assert (x.kind, x.group_first, x.mix_layer, x.mix_layer2, x.phase_layer) == \
+                   (y.kind, y.group_first, y.mix_layer, y.mix_layer2, y.phase_layer)
+            assert x.bytes == y.bytes - (8 * N if y.kind in (1, 3) else 0)
+    tiles = N >> 12
+    w_plain = lib.qva_workspace_bytes(ctypes.byref(pl), p, 1)
+    w_z = lib.qva_workspace_bytes(ctypes.byref(zt), p, 1)
+    assert w_z - w_plain >= 8 * p * (E - 1) * tiles
+    cnt = lib.qva_plan(ctypes.byref(zt), p, 1, 0, None, 0)
+    g = (_lib.QvaPassInfo * cnt)()
+    assert lib.qva_plan(ctypes.byref(zt), p, 1, 0, g, cnt) == cnt
+    gp = _grad_plan(lib, 0, n, p)
+    assert [x.kind for x in g] == [x.kind for x in gp]
+    for x, y in zip(g, gp):
+        if x.kind in (20, 21):  # phase undone with per-term slots, no q read
+            assert x.bytes == y.bytes - 8 * N + 8 * E * tiles
+        elif x.kind == 25:      # the slot reduction covers p (G + E) slots
+            assert x.bytes == y.bytes + 8 * p * (E - 1) * tiles
+        else:
+            assert x.bytes == y.bytes - (8 * N if x.kind in (1, 3) else 0)

@@ -31,6 +31,8 @@ from .problems import (
     qaoa_maxcut_workload,
     qwoa_portfolio_workload,
     qwoa_constrained_workload,
+    maxcut_zterms,
+    exqaoa_maxcut_workload,
     batched_workloads,
     CONFIG_SEEDS,
 )
@@ -50,6 +52,8 @@ __all__ = [
     "qaoa_maxcut_workload",
     "qwoa_portfolio_workload",
     "qwoa_constrained_workload",
+    "maxcut_zterms",
+    "exqaoa_maxcut_workload",
     "batched_workloads",
     "CONFIG_SEEDS",
 ]

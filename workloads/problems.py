@@ -185,6 +185,8 @@ class Workload:
     edges: list = field(default_factory=list)
     weights: np.ndarray | None = None
     seed: int = 0
+    supports: np.ndarray | None = None  # Z-string terms (extended QAOA); gammas then p x terms
+    coefs: np.ndarray | None = None
 
     @property
     def N(self) -> int:
@@ -246,6 +248,29 @@ def qwoa_constrained_workload(m: int, k: int, p: int, *, seed: int = 0, risk: fl
     return Workload(name=f"qwoa_portfolio_m{m}_k{k}_p{p}", mixer="circulant", n=int(len(idx) - 1).bit_length(),
                     q=np.ascontiguousarray(wl.q[idx]), gammas=wl.gammas, ts=wl.ts, lam=None,
                     lambda_kind=lambda_kind, seed=seed)
+
+
+def maxcut_zterms(edges, weights) -> tuple[np.ndarray, np.ndarray]:
+    """The non-identity terms of the MaxCut cost in the Pauli-Z basis:
+    sum_e w_e [bit u != bit v] = sum_e w_e / 2 - sum_e (w_e / 2) Z_u Z_v, so one
+    term per edge with support {u, v} and coefficient -w_e / 2."""
+    supports = np.array([(1 << int(u)) | (1 << int(v)) for u, v in edges], dtype=np.uint64)
+    coefs = -0.5 * np.asarray(weights, dtype=np.float64)
+    return supports, coefs
+
+
+def exqaoa_maxcut_workload(n: int, p: int, *, seed: int = 0, graph: str = "regular3",
+                           build_q: bool = True) -> Workload:
+    """Extended-QAOA MaxCut instance: the QAOA instance of the same seed
+    (graph, weights, its per-layer gammas and ts), with the phase split into
+    one term per edge; layer k starts with every term at gamma_k, plus a
+    U(-0.1, 0.1) perturbation per term drawn after the QAOA draws."""
+    wl = qaoa_maxcut_workload(n, p, graph=graph, seed=seed, build_q=build_q)
+    supports, coefs = maxcut_zterms(wl.edges, wl.weights)
+    rng = np.random.default_rng(seed + 7919)
+    gammas = wl.gammas[:, None] + rng.uniform(-0.1, 0.1, (p, len(supports)))
+    return Workload(name=f"exqaoa_maxcut_n{n}_p{p}", mixer="x", n=n, q=wl.q, gammas=gammas, ts=wl.ts,
+                    edges=wl.edges, weights=wl.weights, seed=seed, supports=supports, coefs=coefs)
 
 
 def batched_workloads(count: int, *, seed: int, n_range=(12, 22), p_range=(1, 8),
