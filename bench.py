@@ -83,7 +83,7 @@ MODE_NAMES = {1: "XMODE_FIRST", 2: "XMODE_MIDDLE", 3: "XMODE_BOUNDARY", 4: "XMOD
 # xpass_kernel's second template argument (pass flag bits) per mode, as the
 # profiler prints it.
 XMODE_FLAGS = {"XMODE_FIRST": 71, "XMODE_MIDDLE": 68, "XMODE_BOUNDARY": 92, "XMODE_LAST": 164,
-               "XMODE_LAST_STORE": 228}
+               "XMODE_LAST_STORE": 228, "XMODE_FIRST_Z": 327, "XMODE_BOUNDARY_Z": 348}
 
 
 def kernel_name(kind: int, col_bits: int) -> str:
@@ -468,6 +468,96 @@ def extra_adjoint(lib, reps: int, workload: str = "qaoa") -> dict:
             "per_kernel_ms": {k: round(v["ms"], 3) for k, v in sorted(per.items())}}
 
 
+def extra_exqaoa(lib, steps: int) -> dict:
+    """Extended QAOA on the n = 28, p = 8 weighted 3-regular MaxCut instance of
+    the headline (42 edges: one Z_u Z_v term and one angle per edge and layer,
+    p (1 + 42) = 344 parameters): the fused forward and the adjoint gradient,
+    beside the plain QAOA forward of the same instance."""
+    import numpy as np
+    import torch
+
+    import paper_2110_03963_amd as qva
+    from paper_2110_03963_amd import _lib
+    from workloads import CONFIG_SEEDS, exqaoa_maxcut_workload, maxcut_qualities_device
+
+    n, p = 28, 8
+    wl = exqaoa_maxcut_workload(n, p, seed=CONFIG_SEEDS["qaoa_n28"], build_q=False)
+    E = len(wl.supports)
+    q = maxcut_qualities_device(n, wl.edges, wl.weights, "cuda")
+    prob = qva.Problem(q, "x", terms=(wl.supports, wl.coefs))
+    plain = qva.Problem(q, "x")
+    g = torch.tensor(np.ascontiguousarray(wl.gammas).ravel(), device="cuda")
+    g1 = torch.tensor(np.ascontiguousarray(wl.gammas.mean(axis=1)), device="cuda")
+    t = torch.tensor(wl.ts, device="cuda")
+    psi = torch.empty(1 << n, dtype=torch.complex128, device="cuda")
+    chi = torch.empty(1 << n, dtype=torch.complex128, device="cuda")
+    wse = torch.empty(max(prob.workspace_bytes(p), plain.workspace_bytes(p), 16), dtype=torch.uint8,
+                      device="cuda")
+    wsg = torch.empty(max(prob.workspace_bytes(p, True), 256), dtype=torch.uint8, device="cuda")
+    out = torch.empty(2, dtype=torch.float64, device="cuda")
+    f = torch.empty((), dtype=torch.float64, device="cuda")
+    dg = torch.empty(p * E, dtype=torch.float64, device="cuda")
+    dt = torch.empty(p, dtype=torch.float64, device="cuda")
+    flags = _lib.QVA_EVOLVE_SKIP_FINAL_STATE
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def forward(pr, gg):
+        _lib.check("qva_evolve", lib.qva_evolve(pr.cstruct(), gg.data_ptr(), t.data_ptr(), p,
+                                                psi.data_ptr(), out.data_ptr(), out.data_ptr() + 8,
+                                                flags, wse.data_ptr(), wse.numel(), stream))
+
+    def adjoint():
+        _lib.check("qva_grad", lib.qva_grad(prob.cstruct(), g.data_ptr(), t.data_ptr(), p, psi.data_ptr(),
+                                            chi.data_ptr(), f.data_ptr(), dg.data_ptr(), dt.data_ptr(),
+                                            wsg.data_ptr(), wsg.numel(), stream))
+
+    ms_fwd = time_calls(lambda: forward(prob, g), 2, steps)
+    f_ex = out[0].item()
+    ms_plain = time_calls(lambda: forward(plain, g1), 2, steps)
+    ms_adj = time_calls(adjoint, 1, max(2, steps // 4))
+    infos = plan_of(lib, prob, p, False, flags)
+
+    def run_timed(ev, nev):
+        _lib.check("qva_evolve_timed",
+                   lib.qva_evolve_timed(prob.cstruct(), g.data_ptr(), t.data_ptr(), p, psi.data_ptr(),
+                                        out.data_ptr(), out.data_ptr() + 8, flags, wse.data_ptr(),
+                                        wse.numel(), ev, nev, stream))
+
+    per = per_kernel_profile(run_timed, infos, steps)
+    ginfos = plan_of(lib, prob, p, True, 0)
+
+    def grad_timed(ev, nev):
+        _lib.check("qva_grad_timed",
+                   lib.qva_grad_timed(prob.cstruct(), g.data_ptr(), t.data_ptr(), p, psi.data_ptr(),
+                                      chi.data_ptr(), f.data_ptr(), dg.data_ptr(), dt.data_ptr(),
+                                      wsg.data_ptr(), wsg.numel(), ev, nev, stream))
+
+    gper = per_kernel_profile(grad_timed, ginfos, 1)
+
+    def zname(per):  # the phase passes of this plan are the Z-string variants
+        out = {}
+        for k, v in per.items():
+            for a, b in (("XMODE_FIRST>", "XMODE_FIRST_Z>"), ("XMODE_BOUNDARY>", "XMODE_BOUNDARY_Z>"),
+                         ("grad_bound<", "grad_bound_z<"), ("grad_final<", "grad_final_z<")):
+                k = k.replace(a, b)
+            out[k] = v
+        return out
+
+    per, gper = zname(per), zname(gper)
+    plan_bytes = sum(i.bytes for i in infos)
+    gplan_bytes = sum(i.bytes for i in ginfos)
+    return {"workload": "exqaoa_maxcut_n28_p8_regular3", "terms": E, "params": p * (E + 1),
+            "ms_per_evolve": round(ms_fwd, 3), "layer_applications_per_s": round(p / (ms_fwd * 1e-3), 2),
+            "ms_per_evolve_plain_qaoa_same_instance": round(ms_plain, 3),
+            "ms_per_adjoint_gradient": round(ms_adj, 2),
+            "effective_GBps_evolve": round(plan_bytes / (ms_fwd * 1e-3) / 1e9, 1),
+            "effective_GBps_gradient": round(gplan_bytes / (ms_adj * 1e-3) / 1e9, 1),
+            "f": f_ex, "f_gradient_call": f.item(),
+            "roofline_evolve": roofline_of(per, steps), "roofline_gradient": roofline_of(gper, 1),
+            "per_kernel_ms_per_evolve": {k: round(v["ms"] / steps, 4) for k, v in sorted(per.items())},
+            "per_kernel_ms_per_gradient": {k: round(v["ms"], 3) for k, v in sorted(gper.items())}}
+
+
 def extra_batch(lib) -> dict:
     """512 independent QAOA MaxCut instances (n ~ U{12..22}, p ~ U{1..8},
     G(n, 0.4), weights U(0,1)): f and the adjoint gradient of every instance
@@ -548,6 +638,7 @@ EXTRAS = {
     "adjoint_vs_fd": lambda lib, steps: extra_adjoint(lib, 2),
     "adjoint_qwoa_complete": lambda lib, steps: extra_adjoint(lib, 3, "qwoa_complete"),
     "batched": lambda lib, steps: extra_batch(lib),
+    "exqaoa": lambda lib, steps: extra_exqaoa(lib, max(3, steps // 2)),
 }
 
 
