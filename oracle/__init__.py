@@ -12,7 +12,9 @@ Functions follow the paper's statement of the method:
   * hypercube mixer exp(-i t sum_i X_i), eq. mixing_qaoa;
   * circulant mixer F^-1 diag(exp(-i t lambda)) F, Sec. 3;
   * expectation <psi|Q|psi>, eq. objective_generic;
-  * the layered evolution, eqs. qaoa and qwoa.
+  * the layered evolution, eqs. qaoa and qwoa;
+  * the extended-QAOA phase and evolution, eqs. phase_shift_qaoa_ex, qaoa_ex;
+  * the QAOAz parity mixer and evolution, eqs. parity_terms, qaoaz_mixers, qaoaz.
 """
 
 from __future__ import annotations
@@ -81,6 +83,13 @@ def _load():
     lib.oracle_evolve_terms.restype = Ci
     lib.oracle_grad_terms.argtypes = [I64, P, Ci, P, P, Ci, P, P, P, P, P]
     lib.oracle_grad_terms.restype = Ci
+    lib.oracle_mix_xy.argtypes = [Ci, P, D, Ci, P]
+    lib.oracle_parity_ring_pairs.argtypes = [Ci, P, P]
+    lib.oracle_parity_ring_pairs.restype = Ci
+    lib.oracle_evolve_xy.argtypes = [Ci, P, P, Ci, P, Ci, P, P, P, P, P]
+    lib.oracle_evolve_xy.restype = Ci
+    lib.oracle_grad_xy.argtypes = [Ci, P, P, Ci, P, Ci, P, P, P, P, P]
+    lib.oracle_grad_xy.restype = Ci
     _lib = lib
     return lib
 
@@ -350,4 +359,60 @@ def grad_terms(q, support, coef, gammas, ts) -> tuple[float, np.ndarray, np.ndar
                                    ctypes.byref(f), _ptr(dg), _ptr(dt))
     if rc:
         raise ValueError("oracle_grad_terms: bad arguments")
+    return f.value, dg, dt
+
+
+# ------------------------------------------------------------------- QAOAz
+def _pairs(pairs) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+    return a
+
+
+def parity_ring_pairs(ring) -> np.ndarray:
+    """Factors of U_parity (eqs. parity_terms, qaoaz_mixers) for the ring of
+    qubits `ring`, in the order they act: B_odd, B_even, then B_last."""
+    r = np.ascontiguousarray(np.asarray(ring, dtype=np.int32))
+    out = np.empty((len(r) + 1, 2), dtype=np.int32)
+    c = _load().oracle_parity_ring_pairs(len(r), _ptr(r), _ptr(out))
+    return out[:c].copy()
+
+
+def mix_xy(psi, pairs, t: float) -> np.ndarray:
+    """psi <- prod_i exp(-i t (X_a X_b + Y_a Y_b)) psi, factor 0 first."""
+    psi = _c128(psi).copy()
+    pr = _pairs(pairs)
+    _load().oracle_mix_xy(_log2(len(psi)), _ptr(psi), float(t), len(pr), _ptr(pr))
+    return psi
+
+
+def evolve_xy(q, psi0, pairs, gammas, ts) -> tuple[np.ndarray, float, float]:
+    """QAOAz (eq. qaoaz) from the given psi0: (psi_p, f, norm)."""
+    q = _f64(q)
+    psi0 = _c128(psi0)
+    pr = _pairs(pairs)
+    g, t = _f64(gammas), _f64(ts)
+    psi = np.empty(len(q), np.complex128)
+    f = ctypes.c_double()
+    nrm = ctypes.c_double()
+    rc = _load().oracle_evolve_xy(_log2(len(q)), _ptr(q), _ptr(psi0), len(pr), _ptr(pr), len(t), _ptr(g),
+                                  _ptr(t), _ptr(psi), ctypes.byref(f), ctypes.byref(nrm))
+    if rc:
+        raise ValueError("oracle_evolve_xy: bad arguments")
+    return psi, f.value, nrm.value
+
+
+def grad_xy(q, psi0, pairs, gammas, ts) -> tuple[float, np.ndarray, np.ndarray]:
+    """(f, df/dgamma, df/dt) of QAOAz by the adjoint walk."""
+    q = _f64(q)
+    psi0 = _c128(psi0)
+    pr = _pairs(pairs)
+    g, t = _f64(gammas), _f64(ts)
+    p = len(t)
+    dg = np.empty(p)
+    dt = np.empty(p)
+    f = ctypes.c_double()
+    rc = _load().oracle_grad_xy(_log2(len(q)), _ptr(q), _ptr(psi0), len(pr), _ptr(pr), p, _ptr(g), _ptr(t),
+                                ctypes.byref(f), _ptr(dg), _ptr(dt))
+    if rc:
+        raise ValueError("oracle_grad_xy: bad arguments")
     return f.value, dg, dt

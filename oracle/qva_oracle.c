@@ -22,6 +22,11 @@
  * unnormalised DFT (Sec. 3, circulant eigensystem), or the complete graph's
  * adjacency J - I, applied from its definition (closed form, no transform).
  *
+ * Extended QAOA (Sec. 2.3.2, eqs. phase_shift_qaoa_ex, qaoa_ex): one angle per
+ * Z-string term of Q.  QAOAz (Sec. 2.4.1, eqs. parity_terms, qaoaz_mixers,
+ * qaoaz): the parity mixer as an ordered product of two-qubit XY rotations,
+ * from a given initial state.
+ *
  * Readings of the paper taken here (each one listed with its reason in the
  * design notes): W_X = sum_i X_i (hypercube, the figure of Sec. 2.3.1);
  * psi_0 normalised by 1/sqrt(N); layer 1 acts first and U_Q precedes U_W in a
@@ -635,5 +640,140 @@ int oracle_grad_bruteforce(int kind, int64_t N, const double *q, const double *l
     free(psi);
     free(d);
     free(tmp);
+    return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* QAOAz parity mixer (Sec. 2.4.1, eqs. parity_terms and qaoaz_mixers).     */
+/* On a qubit pair (a, b), X_a X_b + Y_a Y_b maps the basis state with bit  */
+/* a = 0, bit b = 1 to twice the state with the two bits swapped (and back) */
+/* and annihilates the states where the bits agree.  So                     */
+/*   exp(-i t (X_a X_b + Y_a Y_b)) = cos 2t - i sin 2t sigma_x              */
+/* on each {01, 10} pair of amplitudes and the identity on the rest.  The   */
+/* mixer is a product of such factors; `pairs` lists them in the order they */
+/* act, first factor first (pairs[2i], pairs[2i + 1] are factor i's qubits).*/
+/* ---------------------------------------------------------------------- */
+
+static void xy_rotate(int n, cplx *psi, int a, int b, double t)
+{
+    const int64_t N = (int64_t)1 << n, ma = (int64_t)1 << a, mb = (int64_t)1 << b;
+    const double c = cos(2.0 * t), s = sin(2.0 * t);
+    for (int64_t j = 0; j < N; ++j) {
+        if ((j & ma) && !(j & mb)) {
+            const int64_t k = j ^ ma ^ mb;
+            const cplx u = psi[j], v = psi[k];
+            psi[j] = c * u - I * s * v;
+            psi[k] = c * v - I * s * u;
+        }
+    }
+}
+
+/* out <- (X_a X_b + Y_a Y_b) psi */
+static void xy_apply(int n, const cplx *psi, int a, int b, cplx *out)
+{
+    const int64_t N = (int64_t)1 << n, ma = (int64_t)1 << a, mb = (int64_t)1 << b;
+    for (int64_t j = 0; j < N; ++j) {
+        const int ba = (j & ma) != 0, bb = (j & mb) != 0;
+        out[j] = ba != bb ? 2.0 * psi[j ^ ma ^ mb] : 0.0;
+    }
+}
+
+static int check_pairs(int n, int n_pairs, const int *pairs)
+{
+    if (n < 1 || n > 40 || n_pairs < 0)
+        return -1;
+    for (int i = 0; i < n_pairs; ++i) {
+        const int a = pairs[2 * i], b = pairs[2 * i + 1];
+        if (a < 0 || b < 0 || a >= n || b >= n || a == b)
+            return -1;
+    }
+    return 0;
+}
+
+void oracle_mix_xy(int n, cplx *psi, double t, int n_pairs, const int *pairs)
+{
+    for (int i = 0; i < n_pairs; ++i)
+        xy_rotate(n, psi, pairs[2 * i], pairs[2 * i + 1], t);
+}
+
+/* The factors of U_parity (eq. qaoaz_mixers) for a ring of m qubits         */
+/* ring[0..m-1], written 1-based as r_1..r_m in eq. parity_terms:            */
+/*   B_odd:  (r_a, r_{a+1}) for odd a <= m - 1;                              */
+/*   B_even: (r_a, r_{a+1}) for even a <= m, r_{m+1} read cyclically as r_1; */
+/*   B_last: (r_m, r_1) when m is odd.                                       */
+/* The factors of one B act on disjoint pairs and commute; the three B act   */
+/* in the order odd, even, last.  Writes 2 ints per factor, returns the      */
+/* count (at most m + 1).                                                    */
+int oracle_parity_ring_pairs(int m, const int *ring, int *pairs)
+{
+    int c = 0;
+    for (int a = 1; a <= m - 1; a += 2) {
+        pairs[2 * c] = ring[a - 1];
+        pairs[2 * c + 1] = ring[a];
+        ++c;
+    }
+    for (int a = 2; a <= m; a += 2) {
+        pairs[2 * c] = ring[a - 1];
+        pairs[2 * c + 1] = ring[a % m];
+        ++c;
+    }
+    if (m % 2 == 1 && m >= 3) {
+        pairs[2 * c] = ring[m - 1];
+        pairs[2 * c + 1] = ring[0];
+        ++c;
+    }
+    return c;
+}
+
+/* QAOAz evolution (eq. qaoaz): psi_p = prod_k U_parity(t_k) U_Q(gamma_k)    */
+/* psi0, from the given psi0 (a state of the constrained subspace).          */
+int oracle_evolve_xy(int n, const double *q, const cplx *psi0, int n_pairs, const int *pairs, int p,
+                     const double *gammas, const double *ts, cplx *psi, double *f, double *norm)
+{
+    if (check_pairs(n, n_pairs, pairs) || p < 0)
+        return -1;
+    const int64_t N = (int64_t)1 << n;
+    memcpy(psi, psi0, sizeof(cplx) * (size_t)N);
+    for (int k = 0; k < p; ++k) {
+        oracle_phase(N, psi, q, gammas[k]);
+        oracle_mix_xy(n, psi, ts[k], n_pairs, pairs);
+    }
+    oracle_expectation(N, psi, q, f, norm);
+    return 0;
+}
+
+/* Adjoint gradient of the QAOAz expectation.  Every factor of a layer's     */
+/* mixer carries the same t_k, so dts[k] sums 2 Im <chi|H_i|phi> over the    */
+/* layer's factors, each taken with the states at that factor (walked back   */
+/* factor by factor); dgammas[k] = 2 Im <chi|Q|phi> at the phase.            */
+int oracle_grad_xy(int n, const double *q, const cplx *psi0, int n_pairs, const int *pairs, int p,
+                   const double *gammas, const double *ts, double *f, double *dgammas, double *dts)
+{
+    if (check_pairs(n, n_pairs, pairs) || p < 0)
+        return -1;
+    const int64_t N = (int64_t)1 << n;
+    cplx *phi = malloc(sizeof(cplx) * (size_t)N);
+    cplx *chi = malloc(sizeof(cplx) * (size_t)N);
+    cplx *hphi = malloc(sizeof(cplx) * (size_t)N);
+    oracle_evolve_xy(n, q, psi0, n_pairs, pairs, p, gammas, ts, phi, f, NULL);
+    for (int64_t j = 0; j < N; ++j)
+        chi[j] = q[j] * phi[j];
+    for (int k = p - 1; k >= 0; --k) {
+        double dt = 0.0;
+        for (int i = n_pairs - 1; i >= 0; --i) {
+            const int a = pairs[2 * i], b = pairs[2 * i + 1];
+            xy_apply(n, phi, a, b, hphi);
+            dt += 2.0 * cimag(inner(N, chi, hphi, NULL));
+            xy_rotate(n, phi, a, b, -ts[k]);
+            xy_rotate(n, chi, a, b, -ts[k]);
+        }
+        dts[k] = dt;
+        dgammas[k] = 2.0 * cimag(inner(N, chi, phi, q));
+        oracle_phase(N, phi, q, -gammas[k]);
+        oracle_phase(N, chi, q, -gammas[k]);
+    }
+    free(phi);
+    free(chi);
+    free(hphi);
     return 0;
 }

@@ -681,3 +681,164 @@ def test_extended_qaoa_gradient_central_differences(oracle_mod, n, p):
             ph += ge * ce * (1 - 2 * par)
         psi = dense.expm_hermitian(W, t[k]) @ (np.exp(-1j * ph) * psi)
     assert abs(np.sum(np.abs(psi) ** 2 * q) - f) < 1e-12 * abs(f)
+
+
+# ------------------------------------------------------------------ QAOAz
+_PX = np.array([[0, 1], [1, 0]], dtype=complex)
+_PY = np.array([[0, -1j], [1j, 0]], dtype=complex)
+
+
+def _pauli_on(n, ops):
+    """Dense operator of a product of single-qubit Paulis; ops maps qubit ->
+    2x2 matrix; qubit i is bit i of the basis index (the last Kronecker factor
+    is qubit 0)."""
+    out = np.array([[1.0 + 0j]])
+    for i in range(n - 1, -1, -1):
+        out = np.kron(out, ops.get(i, np.eye(2)))
+    return out
+
+
+def _xy_dense(n, a, b):
+    return _pauli_on(n, {a: _PX, b: _PX}) + _pauli_on(n, {a: _PY, b: _PY})
+
+
+def _parity_B_dense(n, ring):
+    """B_odd, B_even, B_last of eq. parity_terms for the ring r_1..r_m, built
+    from the sums as written (a 1-based, index m + 1 read cyclically as 1)."""
+    m = len(ring)
+    r = lambda a: ring[(a - 1) % m]  # noqa: E731
+    N = 1 << n
+    B_odd = np.zeros((N, N), complex)
+    B_even = np.zeros((N, N), complex)
+    for a in range(1, m):
+        if a % 2 == 1:
+            B_odd += _xy_dense(n, r(a), r(a + 1))
+    for a in range(2, m + 1, 2):
+        B_even += _xy_dense(n, r(a), r(a + 1))
+    B_last = _xy_dense(n, r(m), r(1)) if (m % 2 == 1 and m >= 3) else np.zeros((N, N), complex)
+    return B_odd, B_even, B_last
+
+
+@pytest.mark.parametrize("n,ring", [(2, [0, 1]), (3, [0, 1, 2]), (4, [0, 1, 2, 3]), (5, [0, 1, 2, 3, 4]),
+                                    (6, [0, 1, 2, 3, 4, 5]), (7, [0, 1, 2, 3, 4, 5, 6]),
+                                    (6, [0, 2, 4]), (6, [1, 3, 5]), (7, [6, 2, 0, 4, 1])])
+def test_parity_mixer_matches_dense_expm(oracle_mod, n, ring):
+    """U_parity(t) = e^{-itB_last} e^{-itB_even} e^{-itB_odd} (eq. qaoaz_mixers)
+    from dense Pauli sums and scipy's expm, against the oracle's ordered
+    product of pair rotations over parity_ring_pairs(ring)."""
+    rng = np.random.default_rng(40 + n + len(ring))
+    psi = _rand_state(rng, 1 << n)
+    pairs = oracle.parity_ring_pairs(ring)
+    B_odd, B_even, B_last = _parity_B_dense(n, ring)
+    for t in (0.37, -1.3, 2.9):
+        U = (scipy.linalg.expm(-1j * t * B_last) @ scipy.linalg.expm(-1j * t * B_even)
+             @ scipy.linalg.expm(-1j * t * B_odd))
+        ref = U @ psi
+        out = oracle.mix_xy(psi, pairs, t)
+        assert np.max(np.abs(out - ref)) < 1e-13
+
+
+def test_parity_pairs_cover_the_ring(oracle_mod):
+    """Every ring edge appears once for m >= 3, each B's pairs are disjoint,
+    and B_last exists only for odd m."""
+    for m in range(3, 12):
+        ring = list(range(m))
+        pairs = [tuple(x) for x in oracle.parity_ring_pairs(ring)]
+        edges = sorted(tuple(sorted(e)) for e in pairs)
+        assert edges == sorted(tuple(sorted((i, (i + 1) % m))) for i in range(m))
+        n_odd = m // 2
+        n_even = m // 2 if m % 2 == 0 else (m - 1) // 2
+        for chunk in (pairs[:n_odd], pairs[n_odd:n_odd + n_even]):
+            qs = [q for e in chunk for q in e]
+            assert len(qs) == len(set(qs))
+        assert len(pairs) == n_odd + n_even + (1 if m % 2 else 0)
+
+
+def test_xy_two_qubit_closed_form(oracle_mod):
+    """exp(-it(XX+YY)) on two qubits: |01> -> cos 2t |01> - i sin 2t |10>,
+    |00> and |11> unchanged."""
+    for t in (0.1, 0.8, -2.2):
+        for j, ref in [(0, [1, 0, 0, 0]), (3, [0, 0, 0, 1]),
+                       (1, [0, math.cos(2 * t), -1j * math.sin(2 * t), 0]),
+                       (2, [0, -1j * math.sin(2 * t), math.cos(2 * t), 0])]:
+            psi = np.zeros(4, complex)
+            psi[j] = 1
+            out = oracle.mix_xy(psi, [(0, 1)], t)
+            assert np.max(np.abs(out - np.array(ref))) < 1e-15
+
+
+def test_xy_conserves_hamming_weight(oracle_mod):
+    """The parity mixer keeps the probability of every Hamming weight, and the
+    evolution started in one weight stays there (the constraint of Sec. 2.4.1)."""
+    n = 9
+    N = 1 << n
+    rng = np.random.default_rng(77)
+    psi = _rand_state(rng, N)
+    w = np.array([bin(j).count("1") for j in range(N)])
+    pairs = oracle.parity_ring_pairs(list(range(n)))
+    out = oracle.mix_xy(psi, pairs, 1.234)
+    for k in range(n + 1):
+        assert abs(np.sum(np.abs(out[w == k]) ** 2) - np.sum(np.abs(psi[w == k]) ** 2)) < 1e-14
+    dicke = (w == 4).astype(complex) / math.sqrt(math.comb(n, 4))
+    q = rng.uniform(0, 2, N)
+    psi_p, f, nrm = oracle.evolve_xy(q, dicke, pairs, [0.4, 1.1], [0.9, 0.3])
+    assert abs(nrm - 1) < 1e-14
+    assert np.max(np.abs(psi_p[w != 4])) < 1e-15
+
+
+def _xy_dense_evolve(n, q, psi0, pairs, gammas, ts, insert=None):
+    """Dense evolution through the factor sequence; insert = (layer, factor)
+    puts -iH of that factor right after it (factor -1: the phase)."""
+    psi = psi0.astype(complex).copy()
+    for k, (g, t) in enumerate(zip(gammas, ts)):
+        psi = np.exp(-1j * g * q) * psi
+        if insert == (k, -1):
+            psi = -1j * q * psi
+        for i, (a, b) in enumerate(pairs):
+            H = _xy_dense(n, a, b)
+            psi = scipy.linalg.expm(-1j * t * H) @ psi
+            if insert == (k, i):
+                psi = -1j * (H @ psi)
+    return psi
+
+
+@pytest.mark.parametrize("n,ring,p", [(4, [0, 1, 2, 3], 2), (5, [0, 1, 2, 3, 4], 3), (6, [0, 2, 4], 2)])
+def test_xy_evolution_and_gradient_dense(oracle_mod, n, ring, p):
+    """evolve_xy against a dense evolution, and grad_xy against the dense
+    product rule (-iH inserted after each factor in turn) and central
+    differences of the oracle's own forward."""
+    rng = np.random.default_rng(90 + n + p)
+    N = 1 << n
+    q = rng.uniform(-1, 2, N)
+    psi0 = _rand_state(rng, N)
+    pairs = oracle.parity_ring_pairs(ring)
+    g = rng.uniform(0, math.pi, p)
+    t = rng.uniform(0, math.pi, p)
+    psi_p, f, _ = oracle.evolve_xy(q, psi0, pairs, g, t)
+    ref = _xy_dense_evolve(n, q, psi0, pairs, g, t)
+    assert np.max(np.abs(psi_p - ref)) < 1e-13
+    f_a, dg, dt = oracle.grad_xy(q, psi0, pairs, g, t)
+    assert abs(f_a - f) < 1e-14
+    for k in range(p):
+        d = _xy_dense_evolve(n, q, psi0, pairs, g, t, insert=(k, -1))
+        assert abs(2 * np.real(np.vdot(ref, q * d)) - dg[k]) < 1e-12
+        s = 0.0
+        for i in range(len(pairs)):
+            d = _xy_dense_evolve(n, q, psi0, pairs, g, t, insert=(k, i))
+            s += 2 * np.real(np.vdot(ref, q * d))
+        assert abs(s - dt[k]) < 1e-12
+    h = 1e-5
+    scale = max(np.max(np.abs(dg)), np.max(np.abs(dt)))
+    for k in range(p):
+        for arr, grad_ in ((g, dg), (t, dt)):
+            xp = arr.copy()
+            xm = arr.copy()
+            xp[k] += h
+            xm[k] -= h
+            if arr is g:
+                fp = oracle.evolve_xy(q, psi0, pairs, xp, t)[1]
+                fm = oracle.evolve_xy(q, psi0, pairs, xm, t)[1]
+            else:
+                fp = oracle.evolve_xy(q, psi0, pairs, g, xp)[1]
+                fm = oracle.evolve_xy(q, psi0, pairs, g, xm)[1]
+            assert abs((fp - fm) / (2 * h) - grad_[k]) < 1e-8 * scale
