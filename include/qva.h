@@ -59,8 +59,11 @@ typedef enum {
 } qva_status;
 
 typedef enum {
-    QVA_MIX_X = 0,        /* W = sum_i X_i, the n-cube adjacency (eq. mixing_qaoa)   */
-    QVA_MIX_CIRCULANT = 1 /* W circulant, given by its eigenvalues (Sec. 3)          */
+    QVA_MIX_X = 0,         /* W = sum_i X_i, the n-cube adjacency (eq. mixing_qaoa)   */
+    QVA_MIX_CIRCULANT = 1, /* W circulant, given by its eigenvalues (Sec. 3)          */
+    QVA_MIX_XY = 2         /* QAOAz parity mixer: an ordered product of XY rotations
+                              exp(-i t (X_a X_b + Y_a Y_b)) (eqs. parity_terms,
+                              qaoaz_mixers); psi_0 is the caller's (eq. qaoaz)     */
 } qva_mixer;
 
 typedef enum {
@@ -79,6 +82,7 @@ typedef struct {
 } qva_zterm;
 
 #define QVA_MAX_TERMS 1024
+#define QVA_MAX_XY_PAIRS 256
 
 /* Problem descriptor (caller-owned, read during the call only).
  *   mixer       QVA_MIX_X or QVA_MIX_CIRCULANT
@@ -102,7 +106,18 @@ typedef struct {
  *               outside 0..QVA_MAX_TERMS QVA_ERR_ARG, terms NULL with
  *               n_terms > 0 QVA_ERR_ARG, terms not 8-byte aligned
  *               QVA_ERR_ALIGN, a circulant mixer QVA_ERR_UNSUPPORTED.  Batched
- *               plans (qva_batch_*) take no terms.                             */
+ *               plans (qva_batch_*) take no terms.
+ *   xy_pairs    host, 2 * n_xy_pairs ints (mixer QVA_MIX_XY): factor i of the
+ *               mixer is exp(-i t (X_a X_b + Y_a Y_b)) with (a, b) =
+ *               (xy_pairs[2i], xy_pairs[2i+1]), qubits a != b below n_qubits;
+ *               factor 0 acts first.  The parity mixer of a ring (eq.
+ *               qaoaz_mixers) lists B_odd's pairs, then B_even's, then B_last.
+ *               Both qubits of a pair must fit one 4096-amplitude tile:
+ *               min(a, b) <= 10 or |a - b| <= 8, else QVA_ERR_UNSUPPORTED.
+ *               With QVA_MIX_XY, qva_evolve and qva_grad take psi_0 from psi
+ *               (a state of the constrained subspace, e.g. a Dicke state).
+ *   n_xy_pairs  0..QVA_MAX_XY_PAIRS (mixer QVA_MIX_XY), else ignored; a bad
+ *               count, a NULL list with pairs, or a bad qubit: QVA_ERR_ARG    */
 typedef struct {
     int mixer;
     int n_qubits;
@@ -112,6 +127,8 @@ typedef struct {
     int64_t n_states;
     const qva_zterm *terms;
     int n_terms;
+    const int32_t *xy_pairs;
+    int n_xy_pairs;
 } qva_problem;
 
 #define QVA_MAX_QUBITS 33
@@ -172,7 +189,8 @@ int qva_expectation(const qva_c128 *psi, const double *q, int64_t N, double *out
  *                       gammas_dev holds p * n_terms: layer k's angles at
  *                       gammas_dev[k * n_terms ...] (eq. qaoa_ex)
  *   p                   depth >= 0 (p = 0 gives f = mean(q))
- *   psi                 device, N complex; working state, holds psi_p on return
+ *   psi                 device, N complex; working state (holds psi_0 on entry
+ *                       for QVA_MIX_XY), holds psi_p on return
  *                       unless flags has QVA_EVOLVE_SKIP_FINAL_STATE
  *   out_f_dev           device double: f.  out_norm_dev (nullable): sum |psi_p|^2
  *   work, work_bytes    device workspace >= qva_workspace_bytes(P, p, 0)      */
@@ -184,7 +202,8 @@ int qva_evolve(const qva_problem *P, const double *gammas_dev, const double *ts_
  * with phi_l the state after unitary l and chi_l = U_{l+1}^dag...U_2p^dag Q psi_p,
  * both walked back from psi_p by inverse layers (no stored intermediate
  * states).  Replaces the finite-difference gradients of the paper's Sec. 4.
- *   psi, chi            device, N complex each: working states (contents on
+ *   psi, chi            device, N complex each: working states (psi holds psi_0
+ *                       on entry for QVA_MIX_XY; contents on
  *                       return unspecified)
  *   out_f_dev           device double
  *   dgammas_dev, dts_dev device, p doubles each (dgammas: p * n_terms with
@@ -252,7 +271,14 @@ typedef enum {
     QVA_PASS_BLU_LAMBDA = 38,     /* inverse top group, exp(-i t lambda), forward top     */
     QVA_PASS_BLU_PHASE = 39,      /* inverse top group, exp(-i gamma q) / N, forward top  */
     QVA_PASS_BLU_LAST = 40,       /* inverse top group, <Q> partial sums                  */
-    QVA_PASS_BLU_LAST_STORE = 41  /* as QVA_PASS_BLU_LAST, also writes psi_p              */
+    QVA_PASS_BLU_LAST_STORE = 41, /* as QVA_PASS_BLU_LAST, also writes psi_p              */
+    /* QAOAz parity mixer (QVA_MIX_XY): a layer is a few tile passes, each
+     * applying the pairs whose qubits lie in its tile in order; the first
+     * pass of a layer also applies the phase */
+    QVA_PASS_XY = 42,             /* pairs of one layer over one tile group (+ phase)     */
+    QVA_PASS_XY_LAST = 43,        /* last pass of the last layer + <Q> partial sums       */
+    QVA_PASS_XY_TURN = 44,        /* as QVA_PASS_XY_LAST, also writes psi_p and Q psi_p   */
+    QVA_PASS_GRAD_XY = 45         /* inverse of one XY pass on phi and chi + inner products */
 } qva_pass_kind;
 
 /* One launch of a plan.  `bytes` is the algorithmic HBM traffic of the
@@ -264,7 +290,9 @@ typedef struct {
     int group_bits;  /* qubits in the group (or 0)                       */
     int col_bits;    /* contiguous low index bits per tile row            */
     int mix_layer;   /* layer (0-based) of the first mixer application, or -1 */
-    int mix_layer2;  /* layer of the second mixer application, or -1          */
+    int mix_layer2;  /* layer of the second mixer application, or -1; for the
+                        XY passes (QVA_PASS_XY..QVA_PASS_GRAD_XY) the number of
+                        pair factors the pass applies                      */
     int phase_layer; /* layer whose phase the launch applies, or -1           */
     double bytes;    /* algorithmic HBM bytes of the launch               */
 } qva_pass_info;

@@ -17,6 +17,7 @@ from .qva import (  # noqa: F401
     init_uniform,
     mix_circulant,
     mix_x,
+    parity_ring_pairs,
     phase,
 )
 

@@ -23,11 +23,13 @@ QVA_ERR_UNSUPPORTED = -6
 
 QVA_MIX_X = 0
 QVA_MIX_CIRCULANT = 1
+QVA_MIX_XY = 2
 QVA_LAMBDA_ARRAY = 0
 QVA_LAMBDA_RING = 1
 QVA_LAMBDA_COMPLETE = 2
 QVA_MAX_QUBITS = 33
 QVA_MAX_TERMS = 1024
+QVA_MAX_XY_PAIRS = 256
 QVA_EVOLVE_SKIP_FINAL_STATE = 1
 
 
@@ -41,6 +43,8 @@ class QvaProblem(ctypes.Structure):
         ("n_states", ctypes.c_int64),
         ("terms", ctypes.c_void_p),
         ("n_terms", ctypes.c_int),
+        ("xy_pairs", ctypes.c_void_p),
+        ("n_xy_pairs", ctypes.c_int),
     ]
 
 
@@ -66,7 +70,7 @@ PASS_KINDS = {0: "whole", 1: "first", 2: "middle", 3: "boundary", 4: "last", 5: 
               28: "cpl_last", 29: "cpl_last_store", 30: "cpl_sum", 31: "grad_cpl_turn",
               32: "grad_cpl_back", 33: "grad_cpl_sum", 34: "blu_chirp", 35: "blu_tile",
               36: "blu_first", 37: "blu_mul", 38: "blu_lambda", 39: "blu_phase", 40: "blu_last",
-              41: "blu_last_store"}
+              41: "blu_last_store", 42: "xy", 43: "xy_last", 44: "xy_turn", 45: "grad_xy"}
 
 
 class QvaBatchItem(ctypes.Structure):

@@ -52,7 +52,7 @@ int check_problem(const qva_problem* P, int p)
         if (!aligned(P->terms, 8))
             return QVA_ERR_ALIGN;
     }
-    if (P->mixer != QVA_MIX_X && P->mixer != QVA_MIX_CIRCULANT)
+    if (P->mixer != QVA_MIX_X && P->mixer != QVA_MIX_CIRCULANT && P->mixer != QVA_MIX_XY)
         return QVA_ERR_ARG;
     if (P->n_qubits < 1 || P->n_qubits > QVA_MAX_QUBITS)
         return QVA_ERR_SIZE;
@@ -72,6 +72,18 @@ int check_problem(const qva_problem* P, int p)
         return QVA_ERR_ARG;
     if (!aligned(P->q, 8))
         return QVA_ERR_ALIGN;
+    if (P->mixer == QVA_MIX_XY) {
+        if (P->n_xy_pairs < 0 || P->n_xy_pairs > QVA_MAX_XY_PAIRS || (P->n_xy_pairs > 0 && !P->xy_pairs))
+            return QVA_ERR_ARG;
+        for (int i = 0; i < P->n_xy_pairs; ++i) {
+            const int a = P->xy_pairs[2 * i], b = P->xy_pairs[2 * i + 1];
+            if (a < 0 || b < 0 || a >= P->n_qubits || b >= P->n_qubits || a == b)
+                return QVA_ERR_ARG;
+        }
+        for (int i = 0; i < P->n_xy_pairs; ++i)
+            if (!xy_pair_fits(P->n_qubits, P->xy_pairs[2 * i], P->xy_pairs[2 * i + 1]))
+                return QVA_ERR_UNSUPPORTED;
+    }
     if (P->mixer == QVA_MIX_CIRCULANT) {
         if (P->lambda_kind != QVA_LAMBDA_ARRAY && P->lambda_kind != QVA_LAMBDA_RING &&
             P->lambda_kind != QVA_LAMBDA_COMPLETE)
@@ -1052,6 +1064,171 @@ int grad_common(const qva_problem* P, const double* gammas_dev, const double* ts
 
 }  // namespace
 
+namespace {
+
+// ------------------------------------------------------------ QAOAz XY
+std::vector<std::pair<int, int>> xy_pairs_of(const qva_problem* P)
+{
+    std::vector<std::pair<int, int>> v;
+    for (int i = 0; i < P->n_xy_pairs; ++i)
+        v.push_back({P->xy_pairs[2 * i], P->xy_pairs[2 * i + 1]});
+    return v;
+}
+
+int64_t xy_tiles(int n) { return n <= kTileBits ? 1 : int64_t(1) << (n - kTileBits); }
+
+// One launch of the parity-mixer plan: pass = index into the layer plan.
+struct XyLaunch {
+    int kind, pass, layer, flags, slot_t, slot_g;
+};
+
+// Forward: each layer's passes in order, the phase in the first; the last pass
+// takes <Q> (the turn of the gradient also writes psi_p and Q psi_p).  Backward:
+// every forward pass inverted, in reverse order; t slot (layer, pass), gamma
+// slot of the layer with its first pass.
+std::vector<XyLaunch> xy_launches(const qva_problem* P, int p, bool store, bool grad)
+{
+    const int G = (int)xy_layer_plan(P->n_qubits, xy_pairs_of(P)).size();
+    std::vector<XyLaunch> L;
+    if (p == 0) {
+        L.push_back({QVA_PASS_EXPECT, -1, -1, 0, -1, -1});
+        L.push_back({QVA_PASS_REDUCE, -1, -1, 0, -1, -1});
+        return L;
+    }
+    for (int k = 0; k < p; ++k)
+        for (int i = 0; i < G; ++i) {
+            int fl = (i == 0 ? XY_PHASE : 0) | XY_STORE, kind = QVA_PASS_XY;
+            if (k == p - 1 && i == G - 1) {
+                if (grad) {
+                    fl |= XY_EXPECT | XY_CHI;
+                    kind = QVA_PASS_XY_TURN;
+                } else {
+                    fl = (fl & ~XY_STORE) | XY_EXPECT | (store ? XY_STORE : 0);
+                    kind = QVA_PASS_XY_LAST;
+                }
+            }
+            L.push_back({kind, i, k, fl, -1, -1});
+        }
+    if (grad)
+        for (int k = p - 1; k >= 0; --k)
+            for (int i = G - 1; i >= 0; --i)
+                L.push_back({QVA_PASS_GRAD_XY, i, k, i == 0 ? XY_PHASE : 0, k * G + i, i == 0 ? p * G + k : -1});
+    L.push_back({QVA_PASS_REDUCE, -1, -1, 0, -1, -1});
+    if (grad)
+        L.push_back({QVA_PASS_GRAD_REDUCE, -1, -1, 0, -1, -1});
+    return L;
+}
+
+// Workspace: (f, norm) partials per tile, then for the gradient p (G + 1)
+// per-tile slot arrays and their sums.
+struct XyLayout {
+    int64_t tiles = 1;
+    int G = 1, nslots = 0;
+    size_t fpart = 0, slots = 0, sums = 0, total = 0;
+};
+
+XyLayout xy_layout(const qva_problem* P, int p, bool grad)
+{
+    XyLayout w;
+    const int n = P->n_qubits;
+    w.tiles = xy_tiles(n);
+    w.G = (int)xy_layer_plan(n, xy_pairs_of(P)).size();
+    const int64_t parts = std::max<int64_t>(w.tiles, expect_partial_count(int64_t(1) << n));
+    size_t off = align256((size_t)parts * sizeof(double2));
+    if (grad && p > 0) {
+        w.nslots = p * (w.G + 1);
+        w.slots = off;
+        off = align256(off + (size_t)w.nslots * (size_t)w.tiles * sizeof(double));
+        w.sums = off;
+        off = align256(off + (size_t)w.nslots * sizeof(double));
+    }
+    w.total = off;
+    return w;
+}
+
+double xy_launch_bytes(const XyLaunch& l, const qva_problem* P, int p, bool grad)
+{
+    const int n = P->n_qubits;
+    const double N = std::ldexp(1.0, n);
+    switch (l.kind) {
+    case QVA_PASS_EXPECT:
+        return 24.0 * N;
+    case QVA_PASS_REDUCE:
+        return 16.0 * (double)(p == 0 ? expect_partial_count(int64_t(1) << n) : xy_tiles(n));
+    case QVA_PASS_GRAD_REDUCE: {
+        const XyLayout w = xy_layout(P, p, grad);
+        return 8.0 * (double)w.nslots * (double)w.tiles;
+    }
+    case QVA_PASS_GRAD_XY:
+        return (64.0 + ((l.flags & XY_PHASE) ? 8.0 : 0.0)) * N;
+    default:
+        return (16.0 + ((l.flags & (XY_PHASE | XY_EXPECT)) ? 8.0 : 0.0) + ((l.flags & XY_STORE) ? 16.0 : 0.0) +
+                ((l.flags & XY_CHI) ? 16.0 : 0.0)) *
+               N;
+    }
+}
+
+int xy_run(const qva_problem* P, const double* gammas, const double* ts, int p, double2* psi, double2* chi,
+           double* out_f, double* out_norm, double* dgammas, double* dts, bool store, bool grad, char* work,
+           hipStream_t s, EventHook& hook)
+{
+    const int n = P->n_qubits;
+    const int64_t N = int64_t(1) << n;
+    const std::vector<XyLayerPass> lp = xy_layer_plan(n, xy_pairs_of(P));
+    if (lp.empty())
+        return QVA_ERR_UNSUPPORTED;
+    const XyLayout W = xy_layout(P, p, grad);
+    double2* fpart = reinterpret_cast<double2*>(work + W.fpart);
+    double* slots = reinterpret_cast<double*>(work + W.slots);
+    double* sums = reinterpret_cast<double*>(work + W.sums);
+    for (const XyLaunch& l : xy_launches(P, p, store, grad)) {
+        hipError_t e = hipSuccess;
+        hook.before(s);
+        switch (l.kind) {
+        case QVA_PASS_EXPECT:
+            e = launch_expect_partials(psi, P->q, N, fpart, s);
+            break;
+        case QVA_PASS_REDUCE:
+            e = launch_final_reduce(fpart, p == 0 ? expect_partial_count(N) : W.tiles, out_f, out_norm, s);
+            break;
+        case QVA_PASS_GRAD_REDUCE:
+            e = launch_grad_reduce(slots, W.nslots, W.tiles, sums, p, W.G, 1, dgammas, dts, s);
+            break;
+        default: {
+            const XyLayerPass& ps = lp[l.pass];
+            XyPassParams x{};
+            x.psi = psi;
+            x.chi = chi;
+            x.q = P->q;
+            x.gammas = gammas;
+            x.ts = ts;
+            x.n = n;
+            x.k = ps.g.k;
+            x.C = ps.g.C;
+            x.elems = n <= kTileBits ? (int)N : (1 << kTileBits);
+            x.flags = l.flags;
+            x.layer = l.layer;
+            x.n_ops = (int)ps.ops.size();
+            for (int o = 0; o < x.n_ops; ++o) {
+                x.ea[o] = (uint8_t)ps.ops[o].first;
+                x.eb[o] = (uint8_t)ps.ops[o].second;
+            }
+            x.partials = fpart;
+            x.slot_t = l.slot_t >= 0 ? slots + (int64_t)l.slot_t * W.tiles : nullptr;
+            x.slot_g = l.slot_g >= 0 ? slots + (int64_t)l.slot_g * W.tiles : nullptr;
+            e = l.kind == QVA_PASS_GRAD_XY ? launch_xygrad(x, W.tiles, s) : launch_xypass(x, W.tiles, s);
+            break;
+        }
+        }
+        hook.after(s);
+        if (e != hipSuccess)
+            return QVA_ERR_HIP;
+    }
+    return QVA_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* qva_status_string(int status)
@@ -1187,6 +1364,8 @@ size_t qva_workspace_bytes(const qva_problem* P, int p, int for_grad)
     if (check_problem(P, p) != QVA_OK)
         return 0;
     const int n = P->n_qubits;
+    if (P->mixer == QVA_MIX_XY)
+        return xy_layout(P, p, for_grad != 0).total;
     if (complete_closed_form(P)) {
         if (for_grad && p > 0)
             return grad_layout(P, p).total;
@@ -1261,6 +1440,24 @@ int qva_plan(const qva_problem* P, int p, int for_grad, int flags, qva_pass_info
         return QVA_ERR_ARG;
     if (for_grad && bluestein_path(P) && p > 0)
         return QVA_ERR_UNSUPPORTED;
+    if (P->mixer == QVA_MIX_XY) {
+        const bool store = !(flags & QVA_EVOLVE_SKIP_FINAL_STATE);
+        const std::vector<XyLayerPass> lp = xy_layer_plan(P->n_qubits, xy_pairs_of(P));
+        const std::vector<XyLaunch> L = xy_launches(P, p, store, for_grad != 0);
+        for (int i = 0; i < (int)L.size() && i < max_out; ++i) {
+            const XyLaunch& l = L[i];
+            const bool tile = l.pass >= 0;
+            out[i].kind = l.kind;
+            out[i].group_first = tile ? lp[l.pass].g.k : -1;
+            out[i].group_bits = tile ? (P->n_qubits <= kTileBits ? P->n_qubits : kTileBits - lp[l.pass].g.C) : 0;
+            out[i].col_bits = tile && P->n_qubits > kTileBits ? lp[l.pass].g.C : 0;
+            out[i].mix_layer = tile && !lp[l.pass].ops.empty() ? l.layer : -1;
+            out[i].mix_layer2 = (int)(tile ? lp[l.pass].ops.size() : 0);
+            out[i].phase_layer = (l.flags & XY_PHASE) ? l.layer : -1;
+            out[i].bytes = xy_launch_bytes(l, P, p, for_grad != 0);
+        }
+        return (int)L.size();
+    }
     if (for_grad) {
         const std::vector<XGroup> groups = x_groups(P->n_qubits);
         const std::vector<GLaunch> L = grad_launches(P, p);
@@ -1345,6 +1542,9 @@ int evolve_common(const qva_problem* P, const double* gammas_dev, const double* 
     if (work && !aligned(work, 16))
         return QVA_ERR_ALIGN;
     const bool store = !(flags & QVA_EVOLVE_SKIP_FINAL_STATE);
+    if (P->mixer == QVA_MIX_XY)
+        return xy_run(P, gammas_dev, ts_dev, p, reinterpret_cast<double2*>(psi), nullptr, out_f_dev, out_norm_dev,
+                      nullptr, nullptr, store, false, reinterpret_cast<char*>(work), as_stream(stream), hook);
     if (P->mixer == QVA_MIX_X)
         return evolve_x(P, gammas_dev, ts_dev, p, reinterpret_cast<double2*>(psi), out_f_dev,
                         out_norm_dev, store, reinterpret_cast<double2*>(work), as_stream(stream),
@@ -1379,6 +1579,10 @@ int grad_common(const qva_problem* P, const double* gammas_dev, const double* ts
         return QVA_ERR_WORKSPACE;
     if (work && !aligned(work, 256))
         return QVA_ERR_ALIGN;
+    if (P->mixer == QVA_MIX_XY)
+        return xy_run(P, gammas_dev, ts_dev, p, reinterpret_cast<double2*>(psi), reinterpret_cast<double2*>(chi),
+                      out_f_dev, nullptr, dgammas_dev, dts_dev, true, true, reinterpret_cast<char*>(work),
+                      as_stream(stream), hook);
     return grad_run(P, gammas_dev, ts_dev, p, reinterpret_cast<double2*>(psi), reinterpret_cast<double2*>(chi),
                     out_f_dev, dgammas_dev, dts_dev, reinterpret_cast<char*>(work), as_stream(stream), hook);
 }

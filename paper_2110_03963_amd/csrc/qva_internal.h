@@ -287,6 +287,42 @@ hipError_t launch_small_grad(const SmallGradParams& P, hipStream_t s);
 hipError_t launch_grad_reduce(const double* slots, int nslots, int64_t tiles, double* sums, int p, int G,
                               int E, double* dgammas, double* dts, hipStream_t s);
 
+// ------------------------------------------------------ QAOAz XY passes
+// One tile pass of the parity mixer: the tile's amplitudes sit in LDS, and
+// each listed pair (element bits ea, eb of the tile) rotates the tile's
+// {01, 10} amplitude pairs by exp(-i t (XX + YY)), in list order.
+constexpr int kMaxXyOps = 24;
+
+enum : int {
+    XY_PHASE = 1,   // exp(-i gamma q) before the pairs (forward) / after their inverse (backward)
+    XY_EXPECT = 2,  // (f, norm) partials of the result
+    XY_STORE = 4,   // write psi back
+    XY_CHI = 8      // also write chi = q psi (the turn of the adjoint walk)
+};
+
+struct XyPassParams {
+    double2* psi;          // forward state; phi in the backward pass
+    double2* chi;          // XY_CHI target; chi in the backward pass
+    const double* q;
+    const double* gammas;  // gammas[layer], ts[layer]
+    const double* ts;
+    int n;
+    int k;                 // tile bits: [0, C) and [k, k + 12 - C)
+    int C;
+    int elems;             // amplitudes per tile: 4096, or N for n <= 12 (one tile)
+    int flags;             // XY_*
+    int layer;
+    int n_ops;
+    uint8_t ea[kMaxXyOps];
+    uint8_t eb[kMaxXyOps];
+    double2* partials;     // XY_EXPECT: one (f, norm) per tile
+    double* slot_t;        // backward: per-tile Im <chi|sum of the pass's H|phi>
+    double* slot_g;        // backward with XY_PHASE: per-tile Im <chi|Q|phi>
+};
+
+hipError_t launch_xypass(const XyPassParams& P, int64_t tiles, hipStream_t s);
+hipError_t launch_xygrad(const XyPassParams& P, int64_t tiles, hipStream_t s);
+
 // ---------------------------------------------------------------- batched
 // Many independent hypercube-mixer instances, forward + adjoint: the passes
 // of every instance are grouped into rounds (round r = pass r of every

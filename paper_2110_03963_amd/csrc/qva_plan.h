@@ -145,4 +145,92 @@ inline std::vector<FPass> fft_mix_plan(int P)
     return plan;
 }
 
+// ------------------------------------------------------------ QAOAz XY
+// The parity mixer is a product of two-qubit factors that do not all commute:
+// a factor must act after every earlier factor sharing one of its qubits, and
+// only those.  A pass loads tiles over the bits [0, C) and [k, k + 12 - C)
+// (C = 0: the contiguous bits [0, 12); n <= 12: the whole register) and
+// applies, in list order, the pending factors whose two qubits lie in the
+// tile and whose earlier neighbours are done.  The planner picks passes
+// greedily (the tile that takes the most factors; ties to contiguous tiles,
+// then to longer rows) until the layer's factors are used up.  Every layer
+// has the same factors, so one layer's pass list serves all layers.
+struct XyGroup {
+    int C, k;
+    bool holds(int bit) const { return bit < (C == 0 && k == 0 ? kTileBits : C) || (C > 0 && bit >= k && bit < k + kTileBits - C); }
+    int elem_bit(int bit) const { return bit < C || (C == 0 && k == 0) ? bit : bit - k + C; }
+};
+
+struct XyLayerPass {
+    XyGroup g;
+    std::vector<std::pair<int, int>> ops;  // element bits of the tile
+};
+
+// Whether some tile holds both qubits of a pair.
+inline bool xy_pair_fits(int n, int a, int b)
+{
+    if (n <= kTileBits)
+        return true;
+    const int lo = a < b ? a : b, hi = a < b ? b : a;
+    return hi < kTileBits || lo <= kTileBits - 2 || hi - lo <= kMaxHighBits - 1;
+}
+
+inline std::vector<XyLayerPass> xy_layer_plan(int n, const std::vector<std::pair<int, int>>& pairs)
+{
+    std::vector<XyLayerPass> plan;
+    if (n <= kTileBits) {
+        // one tile is the whole register (C = k = n: element bit = qubit)
+        XyLayerPass ps{{n, n}, {}};
+        for (const auto& pr : pairs) {
+            if ((int)ps.ops.size() == kMaxXyOps) {
+                plan.push_back(ps);
+                ps.ops.clear();
+            }
+            ps.ops.push_back(pr);
+        }
+        plan.push_back(ps);
+        return plan;
+    }
+    std::vector<XyGroup> cand;
+    cand.push_back({0, 0});
+    for (int C = kTileBits - 1; C >= kMinColBits; --C)
+        for (int k = C; k + kTileBits - C <= n; ++k)
+            cand.push_back({C, k});
+    std::vector<std::pair<int, int>> pending = pairs;
+    if (pending.empty()) {
+        plan.push_back({{0, 0}, {}});
+        return plan;
+    }
+    while (!pending.empty()) {
+        int best = -1;
+        std::vector<int> best_take;
+        for (int c = 0; c < (int)cand.size(); ++c) {
+            const XyGroup& g = cand[c];
+            std::vector<int> take;
+            uint64_t blocked = 0;
+            for (int i = 0; i < (int)pending.size() && (int)take.size() < kMaxXyOps; ++i) {
+                const int a = pending[i].first, b = pending[i].second;
+                const uint64_t m = (uint64_t(1) << a) | (uint64_t(1) << b);
+                if (!(blocked & m) && g.holds(a) && g.holds(b))
+                    take.push_back(i);
+                else
+                    blocked |= m;
+            }
+            if (take.size() > best_take.size()) {
+                best = c;
+                best_take = take;
+            }
+        }
+        if (best < 0)
+            return {};  // a pair no tile holds (rejected earlier by xy_pair_fits)
+        XyLayerPass ps{cand[best], {}};
+        for (int i : best_take)
+            ps.ops.push_back({ps.g.elem_bit(pending[i].first), ps.g.elem_bit(pending[i].second)});
+        for (int j = (int)best_take.size() - 1; j >= 0; --j)
+            pending.erase(pending.begin() + best_take[j]);
+        plan.push_back(ps);
+    }
+    return plan;
+}
+
 }  // namespace qva

@@ -15,7 +15,7 @@ import torch
 
 from . import _lib
 
-MIXERS = {"x": _lib.QVA_MIX_X, "circulant": _lib.QVA_MIX_CIRCULANT}
+MIXERS = {"x": _lib.QVA_MIX_X, "circulant": _lib.QVA_MIX_CIRCULANT, "xy": _lib.QVA_MIX_XY}
 LAMBDA_KINDS = {"array": _lib.QVA_LAMBDA_ARRAY, "ring": _lib.QVA_LAMBDA_RING,
                 "complete": _lib.QVA_LAMBDA_COMPLETE}
 
@@ -124,10 +124,15 @@ class Problem:
     of a Z-string decomposition of the cost, given as (supports, coefs) with
     Sigma_e(j) = coefs[e] (-1)^popcount(j & supports[e]); gammas are then
     p x n_terms and q is only the observable.
+
+    mixer "xy": the QAOAz parity mixer, the ordered product over `pairs`
+    (a, b) of exp(-i t (X_a X_b + Y_a Y_b)), first pair first (see
+    parity_ring_pairs), started from psi0 (a device complex128 state of the
+    constrained subspace, e.g. a Dicke state).
     """
 
     def __init__(self, q: torch.Tensor, mixer: str = "x", lam: torch.Tensor | None = None,
-                 lambda_kind: str = "array", terms=None):
+                 lambda_kind: str = "array", terms=None, pairs=None, psi0: torch.Tensor | None = None):
         _need(q, torch.float64, "q")
         self.q = q
         N = q.numel()
@@ -157,9 +162,20 @@ class Problem:
             self.n_terms = len(packed)
             if self.n_terms:
                 self.terms = torch.from_numpy(packed.view(np.uint8).copy()).to(q.device)
+        self.pairs = None
+        self.psi0 = None
+        if mixer == "xy":
+            self.pairs = np.ascontiguousarray(np.asarray(pairs if pairs is not None else [], dtype=np.int32)
+                                              .reshape(-1, 2))
+            _need(psi0, torch.complex128, "psi0")
+            if psi0.numel() != N:
+                raise ValueError("psi0 and q differ in length")
+            self.psi0 = psi0
         self._c = _lib.QvaProblem(MIXERS[mixer], self.n, _ptr(q),
                                   _ptr(lam) if (mixer == "circulant" and lambda_kind == "array") else None,
-                                  LAMBDA_KINDS[self.lambda_kind], n_states, _ptr(self.terms), self.n_terms)
+                                  LAMBDA_KINDS[self.lambda_kind], n_states, _ptr(self.terms), self.n_terms,
+                                  self.pairs.ctypes.data if self.pairs is not None and len(self.pairs) else None,
+                                  0 if self.pairs is None else len(self.pairs))
 
     @property
     def N(self) -> int:
@@ -174,6 +190,19 @@ class Problem:
 
     def workspace_bytes(self, p: int, for_grad: bool = False) -> int:
         return int(_lib.load().qva_workspace_bytes(self.cstruct(), int(p), int(for_grad)))
+
+
+def parity_ring_pairs(ring) -> list[tuple[int, int]]:
+    """The factors of the QAOAz parity mixer (eqs. parity_terms, qaoaz_mixers)
+    for a ring of qubits r_1..r_m, in the order they act: B_odd's pairs
+    (r_a, r_a+1) for odd a, then B_even's for even a (r_m+1 is r_1), then B_last
+    = (r_m, r_1) when m is odd."""
+    r = [int(x) for x in ring]
+    m = len(r)
+    odd = [(r[a - 1], r[a]) for a in range(1, m, 2)]
+    even = [(r[a - 1], r[a % m]) for a in range(2, m + 1, 2)]
+    last = [(r[m - 1], r[0])] if m % 2 == 1 and m >= 3 else []
+    return odd + even + last
 
 
 def _angles(x, device) -> torch.Tensor:
@@ -208,6 +237,8 @@ def evolve(problem: Problem, gammas, ts, psi: torch.Tensor | None = None, store:
         _need(psi, torch.complex128, "psi")
         if psi.numel() != problem.N:
             raise ValueError("psi has the wrong length")
+    if problem.psi0 is not None:
+        psi.copy_(problem.psi0)  # the XY mixer starts from the caller's state
     lib = _lib.load()
     need = problem.workspace_bytes(p)
     if workspace is None or workspace.numel() < need:
@@ -233,6 +264,8 @@ def grad(problem: Problem, gammas, ts, psi: torch.Tensor | None = None,
         chi = torch.empty(problem.N, dtype=torch.complex128, device=dev)
     _need(psi, torch.complex128, "psi")
     _need(chi, torch.complex128, "chi")
+    if problem.psi0 is not None:
+        psi.copy_(problem.psi0)
     lib = _lib.load()
     need = problem.workspace_bytes(p, True)
     if workspace is None or workspace.numel() < need:

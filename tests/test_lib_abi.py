@@ -460,3 +460,89 @@ def test_zterm_plan(lib, n, p):
             assert x.bytes == y.bytes + 8 * p * (E - 1) * tiles
         else:
             assert x.bytes == y.bytes - (8 * N if x.kind in (1, 3) else 0)
+
+
+# ------------------------------------------------------------------ QAOAz
+def _xy_prob(n, pairs, q=FAKE, n_states=0):
+    arr = None
+    if pairs is not None:
+        arr = (ctypes.c_int32 * (2 * max(1, len(pairs))))(*[x for pr in pairs for x in pr])
+    pr = _lib.QvaProblem(2, n, q, None, 0, n_states, None, 0,
+                         ctypes.cast(arr, ctypes.c_void_p) if arr is not None else None,
+                         len(pairs) if pairs is not None else 0)
+    pr._keep = arr
+    return pr
+
+
+def _ring(m):
+    from paper_2110_03963_amd import parity_ring_pairs
+    return parity_ring_pairs(range(m))
+
+
+def test_xy_validation(lib):
+    S = _lib
+    assert S.QVA_MAX_XY_PAIRS == 256
+    assert lib.qva_plan(ctypes.byref(_xy_prob(20, _ring(20))), 2, 0, 0, None, 0) > 0
+    bad = [(_xy_prob(20, [(3, 3)]), S.QVA_ERR_ARG),
+           (_xy_prob(20, [(0, 20)]), S.QVA_ERR_ARG),
+           (_xy_prob(20, [(-1, 2)]), S.QVA_ERR_ARG),
+           (_xy_prob(20, [(0, 1)] * 257), S.QVA_ERR_ARG),
+           (_xy_prob(26, [(12, 24)]), S.QVA_ERR_UNSUPPORTED),   # no tile holds both
+           (_xy_prob(17, _ring(17), n_states=100003), S.QVA_ERR_UNSUPPORTED)]
+    nul = _lib.QvaProblem(2, 20, FAKE, None, 0, 0, None, 0, None, 3)
+    bad.append((nul, S.QVA_ERR_ARG))
+    zt = _lib.QvaProblem(2, 20, FAKE, None, 0, 0, FAKE, 3, None, 0)
+    bad.append((zt, S.QVA_ERR_UNSUPPORTED))
+    for pr, st in bad:
+        assert lib.qva_plan(ctypes.byref(pr), 2, 0, 0, None, 0) == st
+        assert lib.qva_workspace_bytes(ctypes.byref(pr), 2, 1) == 0
+    # pairs that some tile holds: low qubit <= 10, or at most 8 apart
+    assert lib.qva_plan(ctypes.byref(_xy_prob(30, [(10, 29), (20, 28), (0, 29)])), 1, 0, 0, None, 0) > 0
+    # no pairs: the mixer is the identity, one phase pass per layer
+    none = _xy_prob(20, [])
+    assert lib.qva_plan(ctypes.byref(none), 3, 0, 0, None, 0) == 4
+
+
+def _xy_plan(lib, pr, p, for_grad, flags=0):
+    cnt = lib.qva_plan(ctypes.byref(pr), p, for_grad, flags, None, 0)
+    assert cnt > 0
+    arr = (_lib.QvaPassInfo * cnt)()
+    assert lib.qva_plan(ctypes.byref(pr), p, for_grad, flags, arr, cnt) == cnt
+    return list(arr)
+
+
+@pytest.mark.parametrize("n,p", [(6, 2), (12, 1), (13, 3), (20, 2), (26, 3), (30, 2)])
+def test_xy_plan(lib, n, p):
+    """Each layer's passes apply all of its pair factors once, the phase only
+    in the first; the gradient's walk inverts every forward pass; bytes and
+    workspace follow the pass flags."""
+    ring = _ring(n)
+    pr = _xy_prob(n, ring)
+    N = 1 << n
+    for flags in (0, 1):
+        plan = _xy_plan(lib, pr, p, 0, flags)
+        assert plan[-1].kind == 8
+        passes = plan[:-1]
+        G = len(passes) // p
+        assert len(passes) == G * p
+        assert [x.kind for x in passes] == [42] * (G * p - 1) + [43]
+        for k in range(p):
+            layer = passes[k * G:(k + 1) * G]
+            assert sum(x.mix_layer2 for x in layer) == len(ring)
+            assert [x.phase_layer for x in layer] == [k] + [-1] * (G - 1)
+            assert all(x.mix_layer == k for x in layer)
+        for x in passes[:-1]:
+            assert x.bytes == (32 + (8 if x.phase_layer >= 0 else 0)) * N
+        last = passes[-1]
+        assert last.bytes == (16 + 8 + (0 if flags else 16)) * N
+    g = _xy_plan(lib, pr, p, 1)
+    G = (len(g) - 2) // (2 * p)
+    assert [x.kind for x in g] == [42] * (G * p - 1) + [44] + [45] * (G * p) + [8, 25]
+    assert g[G * p - 1].bytes == (16 + 8 + 16 + 16) * N
+    back = g[G * p:2 * G * p]
+    assert [x.phase_layer for x in back] == [k if i == 0 else -1 for k in range(p - 1, -1, -1)
+                                             for i in range(G - 1, -1, -1)]
+    tiles = max(1, N >> 12)
+    assert lib.qva_workspace_bytes(ctypes.byref(pr), p, 1) >= 16 * tiles + 8 * p * (G + 1) * tiles
+    # depth 0: <psi0|Q|psi0> only
+    assert [x.kind for x in _xy_plan(lib, pr, 0, 0)] == [7, 8]

@@ -33,6 +33,9 @@ from .problems import (
     qwoa_constrained_workload,
     maxcut_zterms,
     exqaoa_maxcut_workload,
+    dicke_state,
+    dicke_state_device,
+    qaoaz_portfolio_workload,
     batched_workloads,
     CONFIG_SEEDS,
 )
@@ -54,6 +57,9 @@ __all__ = [
     "qwoa_constrained_workload",
     "maxcut_zterms",
     "exqaoa_maxcut_workload",
+    "dicke_state",
+    "dicke_state_device",
+    "qaoaz_portfolio_workload",
     "batched_workloads",
     "CONFIG_SEEDS",
 ]

@@ -273,6 +273,34 @@ def exqaoa_maxcut_workload(n: int, p: int, *, seed: int = 0, graph: str = "regul
                     edges=wl.edges, weights=wl.weights, seed=seed, supports=supports, coefs=coefs)
 
 
+def dicke_state(n: int, k: int) -> np.ndarray:
+    """|D^n_k>: equal amplitudes C(n, k)^(-1/2) on the basis states with k ones
+    (a state of fixed Hamming weight, where the parity mixer keeps it)."""
+    w = np.bitwise_count(np.arange(1 << n, dtype=np.uint64))
+    return np.where(w == k, 1.0 / math.sqrt(math.comb(n, k)), 0.0).astype(np.complex128)
+
+
+def dicke_state_device(n: int, k: int, device):
+    """dicke_state built on a torch device (large n)."""
+    import torch
+
+    j = torch.arange(1 << n, dtype=torch.int64, device=device)
+    w = torch.zeros_like(j)
+    for b in range(n):
+        w += (j >> b) & 1
+    amp = (w == k).to(torch.float64) * (1.0 / math.sqrt(math.comb(n, k)))  # float64 throughout
+    return amp.to(torch.complex128)
+
+
+def qaoaz_portfolio_workload(m: int, k: int, p: int, *, seed: int = 0, risk: float = 0.5) -> Workload:
+    """QAOAz over all 2^m subsets of the QWOA portfolio of the same seed (same
+    mu, Sigma, q, gammas, ts): the parity mixer on the ring of all m qubits
+    keeps the number of assets held, and psi0 = |D^m_k> starts at k of them."""
+    wl = qwoa_portfolio_workload(m, p, seed=seed, risk=risk)
+    return Workload(name=f"qaoaz_portfolio_m{m}_k{k}_p{p}", mixer="xy", n=m, q=wl.q, gammas=wl.gammas,
+                    ts=wl.ts, seed=seed)
+
+
 def batched_workloads(count: int, *, seed: int, n_range=(12, 22), p_range=(1, 8),
                       edge_prob: float = 0.4, build_q: bool = True) -> list[Workload]:
     """Independent QAOA MaxCut instances with n ~ U{n_range}, p ~ U{p_range}.
