@@ -92,7 +92,7 @@ def kernel_name(kind: int, col_bits: int) -> str:
     if kind in MODE_NAMES:
         return f"xpass_kernel<{col_bits}, {MODE_NAMES[kind]}>"
     name = _lib.PASS_KINDS[kind]
-    if name.startswith(("fft_", "grad_")) and name not in ("grad_reduce", "grad_whole"):
+    if name.startswith(("fft_", "grad_", "xy")) and name not in ("grad_reduce", "grad_whole"):
         return f"{name}<{col_bits}>"
     return name
 
@@ -558,6 +558,97 @@ def extra_exqaoa(lib, steps: int) -> dict:
             "per_kernel_ms_per_gradient": {k: round(v["ms"], 3) for k, v in sorted(gper.items())}}
 
 
+def extra_qaoaz(lib, steps: int) -> dict:
+    """QAOAz portfolio over all 2^26 subsets (the QWOA portfolio's q, gammas
+    and ts), the parity mixer on the ring of all 26 qubits, psi0 = |D^26_13>,
+    p = 6: the fused forward and the adjoint gradient.  Each call starts from
+    a fresh copy of psi0 (outside the timed interval: events bracket the
+    library call alone)."""
+    import numpy as np
+    import torch
+
+    import paper_2110_03963_amd as qva
+    from paper_2110_03963_amd import _lib
+    from workloads import CONFIG_SEEDS, dicke_state_device, qaoaz_portfolio_workload
+
+    n, k, p = 26, 13, 6
+    wl = qaoaz_portfolio_workload(n, k, p, seed=CONFIG_SEEDS["qwoa_n26"])
+    q = torch.from_numpy(wl.q).cuda()
+    psi0 = dicke_state_device(n, k, "cuda")
+    pairs = qva.parity_ring_pairs(range(n))
+    prob = qva.Problem(q, "xy", pairs=pairs, psi0=psi0)
+    g = torch.tensor(wl.gammas, device="cuda")
+    t = torch.tensor(wl.ts, device="cuda")
+    psi = torch.empty_like(psi0)
+    chi = torch.empty_like(psi0)
+    wse = torch.empty(max(prob.workspace_bytes(p), 16), dtype=torch.uint8, device="cuda")
+    wsg = torch.empty(max(prob.workspace_bytes(p, True), 256), dtype=torch.uint8, device="cuda")
+    out = torch.empty(2, dtype=torch.float64, device="cuda")
+    f = torch.empty((), dtype=torch.float64, device="cuda")
+    dg = torch.empty(p, dtype=torch.float64, device="cuda")
+    dt = torch.empty(p, dtype=torch.float64, device="cuda")
+    flags = _lib.QVA_EVOLVE_SKIP_FINAL_STATE
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def forward():
+        _lib.check("qva_evolve", lib.qva_evolve(prob.cstruct(), g.data_ptr(), t.data_ptr(), p, psi.data_ptr(),
+                                                out.data_ptr(), out.data_ptr() + 8, flags, wse.data_ptr(),
+                                                wse.numel(), stream))
+
+    def adjoint():
+        _lib.check("qva_grad", lib.qva_grad(prob.cstruct(), g.data_ptr(), t.data_ptr(), p, psi.data_ptr(),
+                                            chi.data_ptr(), f.data_ptr(), dg.data_ptr(), dt.data_ptr(),
+                                            wsg.data_ptr(), wsg.numel(), stream))
+
+    def timed(fn, reps):
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        psi.copy_(psi0)
+        fn()  # warm-up
+        for e0, e1 in evs:
+            psi.copy_(psi0)
+            e0.record()
+            fn()
+            e1.record()
+        torch.cuda.synchronize()
+        return sum(e0.elapsed_time(e1) for e0, e1 in evs) / reps
+
+    ms_fwd = timed(forward, steps)
+    f_fwd = out[0].item()
+    ms_adj = timed(adjoint, max(2, steps // 2))
+    infos = plan_of(lib, prob, p, False, flags)
+
+    def run_timed(ev, nev):
+        psi.copy_(psi0)
+        _lib.check("qva_evolve_timed",
+                   lib.qva_evolve_timed(prob.cstruct(), g.data_ptr(), t.data_ptr(), p, psi.data_ptr(),
+                                        out.data_ptr(), out.data_ptr() + 8, flags, wse.data_ptr(),
+                                        wse.numel(), ev, nev, stream))
+
+    per = per_kernel_profile(run_timed, infos, steps)
+    ginfos = plan_of(lib, prob, p, True, 0)
+
+    def grad_timed(ev, nev):
+        psi.copy_(psi0)
+        _lib.check("qva_grad_timed",
+                   lib.qva_grad_timed(prob.cstruct(), g.data_ptr(), t.data_ptr(), p, psi.data_ptr(),
+                                      chi.data_ptr(), f.data_ptr(), dg.data_ptr(), dt.data_ptr(),
+                                      wsg.data_ptr(), wsg.numel(), ev, nev, stream))
+
+    gper = per_kernel_profile(grad_timed, ginfos, 1)
+    plan_bytes = sum(i.bytes for i in infos)
+    gplan_bytes = sum(i.bytes for i in ginfos)
+    G = sum(1 for i in infos if i.kind in (42, 43)) // p
+    return {"workload": "qaoaz_portfolio_m26_k13_p6_ring", "pairs": len(pairs), "passes_per_layer": G,
+            "ms_per_evolve": round(ms_fwd, 3), "layer_applications_per_s": round(p / (ms_fwd * 1e-3), 2),
+            "ms_per_adjoint_gradient": round(ms_adj, 3),
+            "effective_GBps_evolve": round(plan_bytes / (ms_fwd * 1e-3) / 1e9, 1),
+            "effective_GBps_gradient": round(gplan_bytes / (ms_adj * 1e-3) / 1e9, 1),
+            "f": f_fwd, "f_gradient_call": f.item(),
+            "roofline_evolve": roofline_of(per, steps), "roofline_gradient": roofline_of(gper, 1),
+            "per_kernel_ms_per_evolve": {kk: round(v["ms"] / steps, 4) for kk, v in sorted(per.items())},
+            "per_kernel_ms_per_gradient": {kk: round(v["ms"], 3) for kk, v in sorted(gper.items())}}
+
+
 def extra_batch(lib) -> dict:
     """512 independent QAOA MaxCut instances (n ~ U{12..22}, p ~ U{1..8},
     G(n, 0.4), weights U(0,1)): f and the adjoint gradient of every instance
@@ -639,6 +730,7 @@ EXTRAS = {
     "adjoint_qwoa_complete": lambda lib, steps: extra_adjoint(lib, 3, "qwoa_complete"),
     "batched": lambda lib, steps: extra_batch(lib),
     "exqaoa": lambda lib, steps: extra_exqaoa(lib, max(3, steps // 2)),
+    "qaoaz": lambda lib, steps: extra_qaoaz(lib, max(3, steps // 2)),
 }
 
 
