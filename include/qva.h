@@ -95,7 +95,7 @@ typedef struct {
  *               constrained QWOA, Sec. 2.4.2), else 0 (N = 2^n_qubits).  A
  *               non-power-of-two N needs 2^(n_qubits-1) < N < 2^n_qubits and a
  *               circulant mixer: the complete graph (any N), or the ring or an
- *               eigenvalue array (N < 2^31; qva_evolve only, through Bluestein's
+ *               eigenvalue array (N < 2^31, through Bluestein's
  *               transform).  Otherwise QVA_ERR_UNSUPPORTED.
  *   terms       device, n_terms qva_zterm, or NULL.  With n_terms > 0 (mixer
  *               QVA_MIX_X only) the phase of layer k is the extended-QAOA
@@ -278,7 +278,13 @@ typedef enum {
     QVA_PASS_XY = 42,             /* pairs of one layer over one tile group (+ phase)     */
     QVA_PASS_XY_LAST = 43,        /* last pass of the last layer + <Q> partial sums       */
     QVA_PASS_XY_TURN = 44,        /* as QVA_PASS_XY_LAST, also writes psi_p and Q psi_p   */
-    QVA_PASS_GRAD_XY = 45         /* inverse of one XY pass on phi and chi + inner products */
+    QVA_PASS_GRAD_XY = 45,        /* inverse of one XY pass on phi and chi + inner products */
+    /* adjoint through Bluestein's transform (both vectors padded to M; the
+     * transform passes in between are the forward's, once per vector) */
+    QVA_PASS_GRAD_BLU_TURN = 46,   /* inverse top group, <Q>, chi = Q x, forward top (both) */
+    QVA_PASS_GRAD_BLU_LAMBDA = 47, /* inverse top, Im<chi|W|phi>, exp(+i t lambda), forward */
+    QVA_PASS_GRAD_BLU_PHASE = 48,  /* inverse top, Im<chi|Q|phi>, exp(+i gamma q), forward  */
+    QVA_PASS_GRAD_BLU_FINAL = 49   /* inverse top group, Im<chi|Q|phi> of layer 1           */
 } qva_pass_kind;
 
 /* One launch of a plan.  `bytes` is the algorithmic HBM traffic of the

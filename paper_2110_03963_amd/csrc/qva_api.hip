@@ -687,6 +687,7 @@ struct GradLayout {
     int E = 1;       // gamma slots per layer: 1, or the number of Z-string terms
     int nslots = 0;  // p * (G + E) per-tile slot arrays (none for the closed-form mixer)
     size_t fpart = 0, slots = 0, sums = 0, lam = 0, part = 0, state = 0, total = 0;
+    size_t pad_phi = 0, pad_chi = 0, b0 = 0, b1 = 0;  // Bluestein: padded vectors, filter spectra
 };
 
 
@@ -694,6 +695,32 @@ GradLayout grad_layout(const qva_problem* P, int p)
 {
     GradLayout g;
     const int n = P->n_qubits;
+    if (bluestein_path(P)) {
+        // (f, norm) partials, both padded vectors, the two filter spectra, 2p
+        // per-tile slots and their sums
+        const int64_t M = int64_t(1) << blu_bits(P);
+        g.tiles = M >> kTileBits;
+        g.G = 1;
+        g.nslots = 2 * p;
+        size_t off = 0;
+        const int64_t e = expect_partial_count(problem_N(P));
+        g.fpart = off;
+        off = align256(off + (size_t)(e > g.tiles ? e : g.tiles) * sizeof(double2));
+        g.pad_phi = off;
+        off += (size_t)M * sizeof(double2);
+        g.pad_chi = off;
+        off += (size_t)M * sizeof(double2);
+        g.b0 = off;
+        off += (size_t)M * sizeof(double2);
+        g.b1 = off;
+        off += (size_t)M * sizeof(double2);
+        g.slots = off;
+        off = align256(off + (size_t)g.nslots * (size_t)g.tiles * sizeof(double));
+        g.sums = off;
+        off = align256(off + (size_t)(g.nslots > 0 ? g.nslots : 1) * sizeof(double));
+        g.total = off;
+        return g;
+    }
     if (complete_closed_form(P)) {
         // (f, norm) partials, per-block parts, running sums, then 2p slot sums
         g.tiles = cpl_blocks(P);
@@ -738,6 +765,7 @@ struct GLaunch {
     int mode;               // XMODE_* / FMODE_* (forward) or GMODE_* (backward)
     int t1, t2, gamma;      // layers of the angles (-1: none)
     int slot_t1, slot_g, slot_t2;  // slot indices (-1: none)
+    int vec = 0;            // Bluestein single-vector passes: 0 phi, 1 chi
 };
 
 std::vector<GLaunch> grad_launches(const qva_problem* P, int p)
@@ -745,7 +773,7 @@ std::vector<GLaunch> grad_launches(const qva_problem* P, int p)
     std::vector<GLaunch> L;
     const int n = P->n_qubits;
     const bool circ = P->mixer == QVA_MIX_CIRCULANT;
-    if (n <= kTileBits && !complete_closed_form(P)) {
+    if (n <= kTileBits && !complete_closed_form(P) && !bluestein_path(P)) {
         L.push_back({QVA_PASS_GRAD_WHOLE, -1, 0, -1, -1, -1, -1, -1, -1});
         return L;
     }
@@ -753,6 +781,37 @@ std::vector<GLaunch> grad_launches(const qva_problem* P, int p)
         L.push_back({QVA_PASS_INIT, -1, 0, -1, -1, -1, -1, -1, -1});
         L.push_back({QVA_PASS_EXPECT, -1, 0, -1, -1, -1, -1, -1, -1});
         L.push_back({QVA_PASS_REDUCE, -1, 0, -1, -1, -1, -1, -1, -1});
+        return L;
+    }
+    if (bluestein_path(P)) {
+        // the forward up to the last convolution (the filters first), the turn,
+        // then per layer backwards: the inverse mixer (its two convolutions,
+        // once per vector, with Im<chi|W|phi> between them) and the inverse phase
+        const int c = (int)x_groups(blu_bits(P)).size() - 1;
+        std::vector<Launch> fw = fft_launches(P, p, false);
+        fw.pop_back();  // REDUCE
+        fw.pop_back();  // the last pass (B_LAST): the turn replaces it
+        for (const Launch& l : fw)
+            L.push_back({l.kind, l.group, l.xmode, l.layer1, l.layer2, l.phase_layer, -1, -1, -1});
+        L.push_back({QVA_PASS_GRAD_BLU_TURN, c, GMODE_B_TURN, -1, -1, -1, -1, -1, -1});
+        auto conv = [&](int filt) {
+            for (int v = 0; v < 2; ++v) {
+                for (int gi = c - 1; gi >= 1; --gi)
+                    L.push_back({QVA_PASS_FFT_DIF, gi, FMODE_DIF, -1, -1, -1, -1, -1, -1, v});
+                L.push_back({QVA_PASS_BLU_MUL, 0, FMODE_LOWMUL, -1, filt, -1, -1, -1, -1, v});
+                for (int gi = 1; gi <= c - 1; ++gi)
+                    L.push_back({QVA_PASS_FFT_DIT, gi, FMODE_DIT, -1, -1, -1, -1, -1, -1, v});
+            }
+        };
+        for (int k = p - 1; k >= 0; --k) {
+            conv(0);
+            L.push_back({QVA_PASS_GRAD_BLU_LAMBDA, c, GMODE_B_LAM, k, -1, -1, k, -1, -1});
+            conv(1);
+            L.push_back({k > 0 ? QVA_PASS_GRAD_BLU_PHASE : QVA_PASS_GRAD_BLU_FINAL, c,
+                         k > 0 ? GMODE_B_Q : GMODE_B_FINAL, -1, -1, k, -1, p + k, -1});
+        }
+        L.push_back({QVA_PASS_REDUCE, -1, 0, -1, -1, -1, -1, -1, -1});
+        L.push_back({QVA_PASS_GRAD_REDUCE, -1, 0, -1, -1, -1, -1, -1, -1});
         return L;
     }
     if (complete_closed_form(P)) {
@@ -868,10 +927,24 @@ double grad_launch_bytes(const GLaunch& l, const qva_problem* P, int p)
         return (l.mode == GCMODE_BACK ? 72.0 : 40.0) * N + 8.0 * kCompleteParts * blocks;
     case QVA_PASS_GRAD_CPL_SUM:
         return 8.0 * kCompleteParts * blocks;
+    case QVA_PASS_GRAD_BLU_TURN:  // psi in, both out, q at j < N
+    case QVA_PASS_GRAD_BLU_LAMBDA:
+    case QVA_PASS_GRAD_BLU_PHASE:
+    case QVA_PASS_GRAD_BLU_FINAL: {
+        const double M = std::ldexp(1.0, blu_bits(P));
+        const double lamb = P->lambda_kind == QVA_LAMBDA_ARRAY ? 8.0 * N : 0.0;
+        if (l.kind == QVA_PASS_GRAD_BLU_TURN)
+            return 48.0 * M + 8.0 * N;
+        if (l.kind == QVA_PASS_GRAD_BLU_LAMBDA)
+            return 64.0 * M + lamb;
+        return (l.kind == QVA_PASS_GRAD_BLU_PHASE ? 64.0 : 32.0) * M + 8.0 * N;
+    }
     default: {
         Launch x{l.kind, l.group, l.mode, l.t1, l.t2, l.gamma};
         if (complete_closed_form(P))
             return cpl_launch_bytes(x, P, p);
+        if (bluestein_path(P))
+            return blu_launch_bytes(x, P, p);
         return P->mixer == QVA_MIX_CIRCULANT ? fft_launch_bytes(x, n, false, tiled) : launch_bytes(x, n, false);
     }
     }
@@ -891,11 +964,45 @@ int grad_run(const qva_problem* P, const double* gammas, const double* ts, int p
     double* lam_tiles = reinterpret_cast<double*>(work + W.lam);
     double* cpart = reinterpret_cast<double*>(work + W.part);
     double2* cstate = reinterpret_cast<double2*>(work + W.state);  // [0]: forward sum, [1..2]: backward
-    const bool tiled = circ && lambda_tiled(P);
+    const bool blu = bluestein_path(P);
+    const bool tiled = circ && lambda_tiled(P) && !blu;
+    const std::vector<XGroup> bgroups = blu ? x_groups(blu_bits(P)) : std::vector<XGroup>();
+    double2* pads[2] = {reinterpret_cast<double2*>(work + W.pad_phi), reinterpret_cast<double2*>(work + W.pad_chi)};
+    double2* spec[2] = {reinterpret_cast<double2*>(work + W.b0), reinterpret_cast<double2*>(work + W.b1)};
+    const int blu_kind = P->lambda_kind == QVA_LAMBDA_RING ? FFT_LAMBDA_RING : FFT_LAMBDA_NATURAL;
     auto slot_ptr = [&](int idx) -> double* { return idx >= 0 ? slots + (int64_t)idx * W.tiles : nullptr; };
     for (const GLaunch& l : grad_launches(P, p)) {
         hipError_t e = hipSuccess;
         hook.before(s);
+        const bool blu_fft = blu && l.group >= 0 &&
+                             (l.kind == QVA_PASS_BLU_CHIRP || l.kind == QVA_PASS_BLU_TILE || l.kind == QVA_PASS_BLU_FIRST ||
+                              l.kind == QVA_PASS_BLU_MUL || l.kind == QVA_PASS_BLU_LAMBDA || l.kind == QVA_PASS_BLU_PHASE ||
+                              l.kind == QVA_PASS_FFT_DIF || l.kind == QVA_PASS_FFT_DIT);
+        if (blu_fft) {
+            // the forward's single-vector passes over a padded buffer (as in evolve_bluestein)
+            const XGroup& g = bgroups[l.group];
+            FftPassParams f{};
+            f.psi = pads[l.vec];
+            f.q = P->q;
+            f.lam = P->lambda;
+            f.lambda_kind = blu_kind;
+            f.mix1 = dev_angle(ts, l.t1 >= 0 ? l.t1 : 0);
+            f.phase = dev_angle(gammas, l.gamma >= 0 ? l.gamma : 0);
+            f.n = blu_bits(P);
+            f.k = g.k;
+            f.col_bits = g.col_bits;
+            f.flags = l.mode;
+            f.partials = fpart;
+            f.nb = N;
+            f.bt = spec[l.t2 > 0 ? 1 : 0];
+            f.out = l.kind == QVA_PASS_BLU_TILE ? spec[l.t2 > 0 ? 1 : 0] : nullptr;
+            f.conj = l.t2 > 0 ? 1 : 0;
+            e = launch_fftpass(f, s);
+            hook.after(s);
+            if (e != hipSuccess)
+                return QVA_ERR_HIP;
+            continue;
+        }
         switch (l.kind) {
         case QVA_PASS_GRAD_WHOLE: {
             SmallGradParams sp{};
@@ -1022,17 +1129,18 @@ int grad_run(const qva_problem* P, const double* gammas, const double* ts, int p
             break;
         }
         default: {  // backward passes
-            const XGroup& g = groups[l.group];
+            const XGroup& g = blu ? bgroups[l.group] : groups[l.group];
             GradPassParams gp{};
-            gp.phi = psi;
-            gp.chi = chi;
+            gp.phi = blu ? pads[0] : psi;
+            gp.chi = blu ? pads[1] : chi;
             gp.q = P->q;
             gp.lam = tiled ? lam_tiles : P->lambda;
-            gp.lambda_kind = tiled ? FFT_LAMBDA_TILED : small_lambda_kind(P->lambda_kind);
+            gp.lambda_kind = blu ? blu_kind : tiled ? FFT_LAMBDA_TILED : small_lambda_kind(P->lambda_kind);
+            gp.nb = N;
             gp.t1 = dev_angle(ts, l.t1 >= 0 ? l.t1 : 0);
             gp.t2 = dev_angle(ts, l.t2 >= 0 ? l.t2 : 0);
             gp.gamma = dev_angle(gammas, l.gamma >= 0 ? l.gamma * W.E : 0);
-            gp.n = n;
+            gp.n = blu ? blu_bits(P) : n;
             gp.k = g.k;
             gp.col_bits = g.col_bits;
             gp.flags = l.mode;
@@ -1374,7 +1482,7 @@ size_t qva_workspace_bytes(const qva_problem* P, int p, int for_grad)
     if (bluestein_path(P)) {
         if (p == 0)
             return (size_t)expect_partial_count(problem_N(P)) * sizeof(double2);
-        return for_grad ? 0 : blu_layout(P).total;
+        return for_grad ? grad_layout(P, p).total : blu_layout(P).total;
     }
     if (n <= kTileBits)
         return 0;
@@ -1438,8 +1546,6 @@ int qva_plan(const qva_problem* P, int p, int for_grad, int flags, qva_pass_info
         return st;
     if (max_out < 0 || (max_out > 0 && !out) || (flags & ~QVA_EVOLVE_SKIP_FINAL_STATE))
         return QVA_ERR_ARG;
-    if (for_grad && bluestein_path(P) && p > 0)
-        return QVA_ERR_UNSUPPORTED;
     if (P->mixer == QVA_MIX_XY) {
         const bool store = !(flags & QVA_EVOLVE_SKIP_FINAL_STATE);
         const std::vector<XyLayerPass> lp = xy_layer_plan(P->n_qubits, xy_pairs_of(P));
@@ -1459,7 +1565,7 @@ int qva_plan(const qva_problem* P, int p, int for_grad, int flags, qva_pass_info
         return (int)L.size();
     }
     if (for_grad) {
-        const std::vector<XGroup> groups = x_groups(P->n_qubits);
+        const std::vector<XGroup> groups = x_groups(bluestein_path(P) ? blu_bits(P) : P->n_qubits);
         const std::vector<GLaunch> L = grad_launches(P, p);
         for (int i = 0; i < (int)L.size() && i < max_out; ++i) {
             const GLaunch& l = L[i];
@@ -1564,8 +1670,6 @@ int grad_common(const qva_problem* P, const double* gammas_dev, const double* ts
     int st = check_problem(P, p);
     if (st != QVA_OK)
         return st;
-    if (bluestein_path(P) && p > 0)
-        return QVA_ERR_UNSUPPORTED;  // the adjoint through Bluestein's transform is not built
     if (!psi || !chi || !out_f_dev || (p > 0 && (!gammas_dev || !ts_dev || !dgammas_dev || !dts_dev)))
         return QVA_ERR_ARG;
     if (psi == chi)

@@ -142,6 +142,99 @@ __device__ __forceinline__ double lambda_at(const GradPassParams& P, int64_t til
     return m == 0 ? (double)((int64_t(1) << P.n) - 1) : -1.0;
 }
 
+// lambda_j of the Bluestein passes (natural order, j < nb): the ring's
+// 2 cos(2 pi j / N), or the caller's array.
+__device__ __forceinline__ double blu_lambda(const GradPassParams& P, int64_t j)
+{
+    if (P.lambda_kind == FFT_LAMBDA_RING) {
+        double s, c;
+        sincospi_red((double)(2 * j) / (double)P.nb, &s, &c);
+        return 2.0 * c;
+    }
+    return P.lam[j];
+}
+
+// Top-group passes of the adjoint through Bluestein's transform.  Both
+// vectors live in padded buffers of M amplitudes in the convolution form of
+// the forward: a state psi is x = conj(w) psi (j < N, zero above), and the
+// first convolution of a mixer gives S = x * w, with F psi = conj(w) S, so
+// <chi|W|phi> = (1/N) sum_{m < N} conj(S_chi,m) lambda_m S_phi,m and
+// <chi|Q|phi> = sum_{j < N} q_j conj(x_chi,j) x_phi,j (the chirps cancel).
+// The inverse of a mixer is the forward's pipeline with +t.
+template <int C, int MODE>
+__device__ __forceinline__ void gradb_tile(const GradPassParams& P, int64_t tile, double2* lds, double* red)
+{
+    const int t = threadIdx.x;
+    const TileMap g = tile_map(tile, P.k, C);
+    const double invNb = 1.0 / (double)P.nb;
+    double2 p[kRegs], x[kRegs];
+    if constexpr (MODE == GMODE_B_TURN) {
+        load_tile<dif_last<C>()>(p, P.phi, g, t);
+        dit_tile<C>(p, lds, g, t);
+        double f = 0.0, nr = 0.0;
+#pragma unroll
+        for (int r = 0; r < kRegs; ++r) {
+            const int64_t j = g(elem<LA>(t, r));
+            if (j < P.nb) {
+                const double qj = ld_nt(P.q + j);
+                p[r] = make_double2(p[r].x * invNb, p[r].y * invNb);
+                const double a = p[r].x * p[r].x + p[r].y * p[r].y;
+                f = fma(a, qj, f);
+                nr += a;
+                x[r] = make_double2(qj * p[r].x, qj * p[r].y);
+            } else {
+                p[r] = x[r] = make_double2(0.0, 0.0);
+            }
+        }
+        double fv[2] = {f, nr};
+        block_sum_k<2>(fv, red);
+        if (t == 0)
+            P.fpart[tile] = make_double2(fv[0], fv[1]);
+    } else {
+        const double ang = MODE == GMODE_B_LAM ? angle_value(P.t1) : angle_value(P.gamma);
+        load2<dif_last<C>()>(p, x, P, g, t);
+        dit_tile2<C>(p, x, lds, g, t);
+        double acc = 0.0;
+#pragma unroll
+        for (int r = 0; r < kRegs; ++r) {
+            const int64_t j = g(elem<LA>(t, r));
+            if (j < P.nb) {
+                double h;
+                if constexpr (MODE == GMODE_B_LAM) {
+                    h = blu_lambda(P, j);
+                } else {
+                    h = ld_nt(P.q + j);
+                    p[r] = make_double2(p[r].x * invNb, p[r].y * invNb);
+                    x[r] = make_double2(x[r].x * invNb, x[r].y * invNb);
+                }
+                acc = fma(h, x[r].x * p[r].y - x[r].y * p[r].x, acc);
+                const double2 u = expmi(-ang * h);  // the inverse factor exp(+i ang h)
+                p[r] = cmul(p[r], u);
+                x[r] = cmul(x[r], u);
+            } else {
+                p[r] = x[r] = make_double2(0.0, 0.0);
+            }
+            QVA_SCHED_FENCE();
+        }
+        if constexpr (MODE == GMODE_B_LAM)
+            write_slots(P, acc * invNb, 0.0, 0.0, red, tile);
+        else
+            write_slots(P, 0.0, acc, 0.0, red, tile);
+        if constexpr (MODE == GMODE_B_FINAL)
+            return;
+    }
+    dif_tile2<C>(p, x, lds, g, t);
+    store2<dif_last<C>()>(p, x, P, g, t);
+}
+
+template <int C, int MODE>
+__global__ __launch_bounds__(kThreads, QVA_GRADF_WAVES) void gradb_kernel(GradPassParams P)
+{
+    __shared__ double2 lds[1 << kTileBits];
+    __shared__ double red[4 * (kThreads / 64)];
+    gradb_tile<C, MODE>(P, blockIdx.x, lds, red);
+}
+
 template <int C, int MODE>
 __global__ __launch_bounds__(kThreads, QVA_GRADF_WAVES) void gradf_kernel(GradPassParams P)
 {
@@ -486,6 +579,18 @@ template <int C>
 hipError_t launch_gradf_c(const GradPassParams& P, unsigned grid, hipStream_t s)
 {
     switch (P.flags) {
+    case GMODE_B_TURN:
+        hipLaunchKernelGGL((gradb_kernel<C, GMODE_B_TURN>), dim3(grid), dim3(kThreads), 0, s, P);
+        break;
+    case GMODE_B_LAM:
+        hipLaunchKernelGGL((gradb_kernel<C, GMODE_B_LAM>), dim3(grid), dim3(kThreads), 0, s, P);
+        break;
+    case GMODE_B_Q:
+        hipLaunchKernelGGL((gradb_kernel<C, GMODE_B_Q>), dim3(grid), dim3(kThreads), 0, s, P);
+        break;
+    case GMODE_B_FINAL:
+        hipLaunchKernelGGL((gradb_kernel<C, GMODE_B_FINAL>), dim3(grid), dim3(kThreads), 0, s, P);
+        break;
     case GMODE_TURN:
         hipLaunchKernelGGL((gradf_kernel<C, GMODE_TURN>), dim3(grid), dim3(kThreads), 0, s, P);
         break;

@@ -241,7 +241,13 @@ enum : int {
     GMODE_LOWDIAG = 7, // low group: forward, <chi^|lambda|phi^>, inverse diagonal, inverse
     GM_ZTERMS = 16,    // with GMODE_BOUND / GMODE_FINAL: extended-QAOA phase, one slot per term
     GMODE_BOUND_Z = GMODE_BOUND | GM_ZTERMS,
-    GMODE_FINAL_Z = GMODE_FINAL | GM_ZTERMS
+    GMODE_FINAL_Z = GMODE_FINAL | GM_ZTERMS,
+    // Bluestein adjoint (top group of the padded transform, both vectors; the
+    // other passes are the forward's single-vector ones, run once per vector)
+    GMODE_B_TURN = 32,   // inverse top group of psi, <Q>, chi = q x, forward top group (both)
+    GMODE_B_LAM = 33,    // inverse top group, Im<chi|W|phi>, exp(+i t lambda), forward top group
+    GMODE_B_Q = 34,      // inverse top group, 1/N, Im<chi|Q|phi>, exp(+i gamma q), forward top group
+    GMODE_B_FINAL = 35   // inverse top group, 1/N, Im<chi|Q|phi> (nothing written)
 };
 
 struct GradPassParams {
@@ -262,6 +268,7 @@ struct GradPassParams {
     const ZTerm* terms;   // GM_ZTERMS: gamma.ptr + gamma.idx is the layer's angle row
     int n_terms;
     double* slot_terms;   // GM_ZTERMS: term e of tile i at slot_terms[e * tiles + i]
+    int64_t nb;           // GMODE_B_*: the logical N (n above is log2 of the padded M)
 };
 
 struct SmallGradParams {

@@ -110,6 +110,25 @@ def test_grad_complete_any_n(N, p):
     assert _gerr(dg.cpu().numpy(), dt.cpu().numpy(), rg, rt) < G_TOL
 
 
+@pytest.mark.parametrize("N,p,kind", [(1000, 2, "ring"), (4097, 3, "array"), (100003, 2, "ring"),
+                                      (100003, 1, "array"), (3000017, 2, "ring")])
+def test_grad_bluestein_any_n(N, p, kind):
+    """Adjoint through Bluestein's transform (ring or eigenvalue array over N
+    solutions, N not a power of two) against the oracle's adjoint, which is
+    pinned to the brute-force product rule and central differences."""
+    rng = np.random.default_rng(N + 7 * p)
+    q = rng.uniform(-1, 3, N)
+    lam = rng.uniform(-2, 2, N) if kind == "array" else None
+    g = rng.uniform(0, math.pi, p)
+    t = rng.uniform(0, math.pi, p)
+    print(f"bluestein grad N={N} p={p} {kind}", flush=True)
+    _check("circulant", q, g, t, lam, kind)
+    prob = qva.Problem(to_dev(q), "circulant", to_dev(lam) if kind == "array" else None, kind)
+    fe, _, _ = qva.evolve(prob, g, t, store=False)
+    fg, _, _ = qva.grad(prob, g, t)
+    assert abs(fe.item() - fg.item()) <= 1e-13 * np.mean(np.abs(q))
+
+
 def test_grad_n12_regular3_p12():
     """The adjoint-gradient workload's oracle-parity size: weighted 3-regular
     MaxCut, n = 12, p = 12 (24 parameters)."""

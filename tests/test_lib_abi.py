@@ -291,8 +291,26 @@ def test_plan_bluestein(lib, N, n, kind, p):
         mul = [x.bytes for x in arr if x.kind == 37]
         assert mul == [48 * M] * (2 * p)
     assert lib.qva_workspace_bytes(ctypes.byref(pr), p, 0) >= 3 * 16 * M
-    # the adjoint is not built for this path
-    assert lib.qva_plan(ctypes.byref(pr), p, 1, 0, None, 0) == _lib.QVA_ERR_UNSUPPORTED
+    # the adjoint: the filters and the forward up to its last convolution, the
+    # turn, then per layer backwards two convolutions per vector around the
+    # lambda pass, and the phase pass (the final one for layer 0)
+    cnt = lib.qva_plan(ctypes.byref(pr), p, 1, 0, None, 0)
+    arr = (_lib.QvaPassInfo * cnt)()
+    assert lib.qva_plan(ctypes.byref(pr), p, 1, 0, arr, cnt) == cnt
+    kinds = [x.kind for x in arr]
+    mids = sorted({x.group_first for x in arr if x.kind == 10})
+    conv = [10] * len(mids)
+    back = [12] * len(mids)
+    fwd = ([34] + conv + [35]) * 2 + [36]
+    for k in range(p):
+        fwd += conv + [37] + back + [38] + conv + [37] + back + ([39] if k + 1 < p else [])
+    walk = []
+    for k in range(p - 1, -1, -1):
+        walk += (conv + [37] + back) * 2 + [47] + (conv + [37] + back) * 2 + [48 if k > 0 else 49]
+    assert kinds == fwd + [46] + walk + [8, 25]
+    assert [x.mix_layer for x in arr if x.kind == 47] == list(range(p - 1, -1, -1))
+    assert [x.phase_layer for x in arr if x.kind in (48, 49)] == list(range(p - 1, -1, -1))
+    assert lib.qva_workspace_bytes(ctypes.byref(pr), p, 1) >= 4 * 16 * M + 2 * p * 8 * (M >> 12)
 
 
 def _grad_plan(lib, mixer, n, p, kind=1):

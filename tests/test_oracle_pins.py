@@ -842,3 +842,29 @@ def test_xy_evolution_and_gradient_dense(oracle_mod, n, ring, p):
                 fp = oracle.evolve_xy(q, psi0, pairs, g, xp)[1]
                 fm = oracle.evolve_xy(q, psi0, pairs, g, xm)[1]
             assert abs((fp - fm) / (2 * h) - grad_[k]) < 1e-8 * scale
+
+
+@pytest.mark.parametrize("N,kind", [(1000, "ring"), (5003, "ring"), (6000, "array"), (4099, "array")])
+def test_circulant_gradient_any_n(oracle_mod, N, kind):
+    """The adjoint through a circulant over N that is not a power of two (the
+    naive DFT at N <= 4096, Bluestein above): against the brute-force product
+    rule and central differences of the forward."""
+    rng = np.random.default_rng(N + 3)
+    p = 2
+    q = rng.uniform(-1, 3, N)
+    lam = oracle.lambda_for("ring", N) if kind == "ring" else rng.uniform(-2, 2, N)
+    g = rng.uniform(0, math.pi, p)
+    t = rng.uniform(0, math.pi, p)
+    f, dg, dt = oracle.grad("circulant", q, g, t, lam)
+    bg, bt = oracle.grad_bruteforce("circulant", q, g, t, lam)
+    scale = max(np.max(np.abs(dg)), np.max(np.abs(dt)))
+    assert np.max(np.abs(dg - bg)) < 1e-11 * scale
+    assert np.max(np.abs(dt - bt)) < 1e-11 * scale
+    h = 1e-5
+    for k in range(p):
+        e = np.zeros(p)
+        e[k] = h
+        fd_g = (oracle.evolve("circulant", q, g + e, t, lam)[1] - oracle.evolve("circulant", q, g - e, t, lam)[1]) / (2 * h)
+        fd_t = (oracle.evolve("circulant", q, g, t + e, lam)[1] - oracle.evolve("circulant", q, g, t - e, lam)[1]) / (2 * h)
+        assert abs(fd_g - dg[k]) < 1e-7 * scale
+        assert abs(fd_t - dt[k]) < 1e-7 * scale
