@@ -362,15 +362,17 @@ def extra_qwoa(lib, steps: int, kind: str = "ring", constrained: bool = False) -
 def extra_adjoint(lib, reps: int, workload: str = "qaoa") -> dict:
     """Adjoint gradient against 4p central-difference and 2p+1 forward-difference
     evaluations of the same fused forward on the same GPU.  Workloads: weighted
-    3-regular MaxCut n = 30, p = 12 (24 params), or the QWOA portfolio over 2^26
-    subsets with the complete-graph mixer, p = 6 (closed-form passes)."""
+    3-regular MaxCut n = 30, p = 12 (24 params), the QWOA portfolio over 2^26
+    subsets with the complete-graph mixer, p = 6 (closed-form passes), or the
+    constrained portfolio (13 of 26 assets, N = 10,400,600) with the ring,
+    p = 6 (Bluestein's transform)."""
     import numpy as np
     import torch
 
     import paper_2110_03963_amd as qva
     from paper_2110_03963_amd import _lib
     from workloads import (CONFIG_SEEDS, maxcut_qualities_device, qaoa_maxcut_workload,
-                           qwoa_portfolio_workload)
+                           qwoa_constrained_workload, qwoa_portfolio_workload)
 
     if workload == "qaoa":
         n, p = 30, 12
@@ -380,6 +382,12 @@ def extra_adjoint(lib, reps: int, workload: str = "qaoa") -> dict:
         prob = qva.Problem(q, "x")
         name = "adjoint_qaoa_maxcut_n30_p12"
         h_t = 1e-5
+    elif workload == "qwoa_constrained_ring":
+        n, p = 26, 6
+        wl = qwoa_constrained_workload(n, 13, p, seed=CONFIG_SEEDS["qwoa_n26"], lambda_kind="ring")
+        prob = qva.Problem(torch.from_numpy(wl.q).cuda(), "circulant", None, "ring")
+        name = "adjoint_qwoa_portfolio_m26_k13_p6_ring"
+        h_t = 1e-5
     else:
         n, p = 26, 6
         wl = qwoa_portfolio_workload(n, p, seed=CONFIG_SEEDS["qwoa_n26"], lambda_kind="complete")
@@ -388,8 +396,8 @@ def extra_adjoint(lib, reps: int, workload: str = "qaoa") -> dict:
         h_t = 1e-5 / (1 << n)  # f oscillates in t at frequency N (e^{-i t N})
     g = torch.tensor(wl.gammas, device="cuda")
     t = torch.tensor(wl.ts, device="cuda")
-    psi = torch.empty(1 << n, dtype=torch.complex128, device="cuda")
-    chi = torch.empty(1 << n, dtype=torch.complex128, device="cuda")
+    psi = torch.empty(prob.N, dtype=torch.complex128, device="cuda")
+    chi = torch.empty(prob.N, dtype=torch.complex128, device="cuda")
     wsg = torch.empty(max(prob.workspace_bytes(p, True), 256), dtype=torch.uint8, device="cuda")
     wse = torch.empty(max(prob.workspace_bytes(p), 16), dtype=torch.uint8, device="cuda")
     f = torch.empty((), dtype=torch.float64, device="cuda")
@@ -728,6 +736,7 @@ EXTRAS = {
     "qwoa_constrained_complete": lambda lib, steps: extra_qwoa(lib, max(3, steps // 2), "complete", True),
     "adjoint_vs_fd": lambda lib, steps: extra_adjoint(lib, 2),
     "adjoint_qwoa_complete": lambda lib, steps: extra_adjoint(lib, 3, "qwoa_complete"),
+    "adjoint_qwoa_constrained_ring": lambda lib, steps: extra_adjoint(lib, 3, "qwoa_constrained_ring"),
     "batched": lambda lib, steps: extra_batch(lib),
     "exqaoa": lambda lib, steps: extra_exqaoa(lib, max(3, steps // 2)),
     "qaoaz": lambda lib, steps: extra_qaoaz(lib, max(3, steps // 2)),
