@@ -82,13 +82,34 @@ __global__ __launch_bounds__(kThreads, 2) void xypass_kernel(XyPassParams P)
             __syncthreads();
             const int a = P.ea[o], b = P.eb[o];
             const int lo = a < b ? a : b, hi = a < b ? b : a;
-            for (int i = t; i < E / 4; i += kThreads) {
-                const int x = insert_two_zeros(i, lo, hi);
-                const int e1 = x | (1 << a), e2 = x | (1 << b);
-                double2 u = s[e1], w = s[e2];
-                xy_rot(u, w, c, sn);
-                s[e1] = u;
-                s[e2] = w;
+            if (E == (1 << kTileBits)) {
+                // a full tile: 4 pairs per thread, all reads issued before any write
+                constexpr int J = (1 << kTileBits) / 4 / kThreads;
+                int e1[J], e2[J];
+                double2 u[J], w[J];
+#pragma unroll
+                for (int m = 0; m < J; ++m) {
+                    const int x = insert_two_zeros(t + kThreads * m, lo, hi);
+                    e1[m] = x | (1 << a);
+                    e2[m] = x | (1 << b);
+                    u[m] = s[e1[m]];
+                    w[m] = s[e2[m]];
+                }
+#pragma unroll
+                for (int m = 0; m < J; ++m) {
+                    xy_rot(u[m], w[m], c, sn);
+                    s[e1[m]] = u[m];
+                    s[e2[m]] = w[m];
+                }
+            } else {
+                for (int i = t; i < E / 4; i += kThreads) {
+                    const int x = insert_two_zeros(i, lo, hi);
+                    const int e1 = x | (1 << a), e2 = x | (1 << b);
+                    double2 u = s[e1], w = s[e2];
+                    xy_rot(u, w, c, sn);
+                    s[e1] = u;
+                    s[e2] = w;
+                }
             }
         }
         __syncthreads();
@@ -176,18 +197,45 @@ __global__ __launch_bounds__(kThreads, 1) void xygrad_kernel(XyPassParams P)
             __syncthreads();
             const int a = P.ea[o], b = P.eb[o];
             const int lo = a < b ? a : b, hi = a < b ? b : a;
-            for (int i = t; i < E / 4; i += kThreads) {
-                const int xi = insert_two_zeros(i, lo, hi);
-                const int e1 = xi | (1 << a), e2 = xi | (1 << b);
-                double2 p1 = sp[e1], p2 = sp[e2], x1 = sx[e1], x2 = sx[e2];
-                // (XX + YY) maps e1 <-> e2 with weight 2
-                at += 2.0 * passes::im_pair(p1, p2, x1, x2);
-                xy_rot(p1, p2, c, sn);
-                xy_rot(x1, x2, c, sn);
-                sp[e1] = p1;
-                sp[e2] = p2;
-                sx[e1] = x1;
-                sx[e2] = x2;
+            if (E == (1 << kTileBits)) {
+                constexpr int J = (1 << kTileBits) / 4 / kThreads;
+                int e1[J], e2[J];
+                double2 p1[J], p2[J], x1[J], x2[J];
+#pragma unroll
+                for (int m = 0; m < J; ++m) {
+                    const int xi = insert_two_zeros(t + kThreads * m, lo, hi);
+                    e1[m] = xi | (1 << a);
+                    e2[m] = xi | (1 << b);
+                    p1[m] = sp[e1[m]];
+                    p2[m] = sp[e2[m]];
+                    x1[m] = sx[e1[m]];
+                    x2[m] = sx[e2[m]];
+                }
+#pragma unroll
+                for (int m = 0; m < J; ++m) {
+                    // (XX + YY) maps e1 <-> e2 with weight 2
+                    at += 2.0 * passes::im_pair(p1[m], p2[m], x1[m], x2[m]);
+                    xy_rot(p1[m], p2[m], c, sn);
+                    xy_rot(x1[m], x2[m], c, sn);
+                    sp[e1[m]] = p1[m];
+                    sp[e2[m]] = p2[m];
+                    sx[e1[m]] = x1[m];
+                    sx[e2[m]] = x2[m];
+                }
+            } else {
+                for (int i = t; i < E / 4; i += kThreads) {
+                    const int xi = insert_two_zeros(i, lo, hi);
+                    const int e1 = xi | (1 << a), e2 = xi | (1 << b);
+                    double2 p1 = sp[e1], p2 = sp[e2], x1 = sx[e1], x2 = sx[e2];
+                    // (XX + YY) maps e1 <-> e2 with weight 2
+                    at += 2.0 * passes::im_pair(p1, p2, x1, x2);
+                    xy_rot(p1, p2, c, sn);
+                    xy_rot(x1, x2, c, sn);
+                    sp[e1] = p1;
+                    sp[e2] = p2;
+                    sx[e1] = x1;
+                    sx[e2] = x2;
+                }
             }
         }
         __syncthreads();
