@@ -223,6 +223,27 @@ def test_ring_light_cone_gradient_full_size():
     assert err < G_TOL
 
 
+def test_ring_light_cone_gradient_max_size():
+    """n = 32, the largest register whose two gradient vectors fit (2 x 64 GiB
+    plus 32 GiB of q), unweighted ring, p = 2: f/n and grad/n equal the
+    oracle's at n = 6."""
+    p = 2
+    rng = np.random.default_rng(32)
+    g = rng.uniform(0, math.pi, p)
+    t = rng.uniform(0, math.pi, p)
+    ns = 2 * p + 2
+    f_s, g_s, t_s = oracle.grad("x", oracle.maxcut_quality_loop(ns, ring_edges(ns)), g, t)
+    n = 32
+    print("max size gradient n=32", flush=True)
+    prob = qva.Problem(ring_cut_qualities_device(n, "cuda"), "x")
+    f, dg, dt = qva.grad(prob, g, t)
+    assert abs(f.item() / n - f_s / ns) < 1e-12 * abs(f_s / ns)
+    err = _gerr(dg.cpu().numpy() / n, dt.cpu().numpy() / n, g_s / ns, t_s / ns)
+    assert err < G_TOL
+    del prob
+    torch.cuda.empty_cache()
+
+
 def test_autograd_function():
     rng = np.random.default_rng(10)
     n, p = 14, 2

@@ -162,6 +162,30 @@ def test_evolve_repeat_is_deterministic():
     assert vals[0] == vals[1] == vals[2]
 
 
+def test_ring_light_cone_max_size():
+    """The largest register, n = 33 (QVA_MAX_QUBITS: 128 GiB of amplitudes,
+    64 GiB of q), unweighted ring, p = 2: f/n equals the oracle's f/n at n = 6
+    (light cone of radius p)."""
+    from workloads import ring_cut_qualities_device
+
+    p = 2
+    rng = np.random.default_rng(33)
+    g = rng.uniform(0, math.pi, p)
+    t = rng.uniform(0, math.pi, p)
+    n_small = 2 * p + 2
+    f_small = oracle.evolve("x", oracle.maxcut_quality_loop(n_small, ring_edges(n_small)), g, t)[1]
+    n = 33
+    print("max size n=33", flush=True)
+    q = ring_cut_qualities_device(n, "cuda")
+    prob = qva.Problem(q, "x")
+    psi = torch.empty(1 << n, dtype=torch.complex128, device="cuda")
+    f, nrm, _ = qva.evolve(prob, g, t, psi=psi, store=False)
+    assert abs(f.item() / n - f_small / n_small) < 1e-12 * (f_small / n_small)
+    assert abs(nrm.item() - 1) < 1e-12
+    del prob, q, psi
+    torch.cuda.empty_cache()
+
+
 def test_ring_light_cone_full_size():
     """Unweighted ring at n = 28, p = 3: f/n equals the oracle's f/n at n = 8
     (light cone of radius p; any n >= 2p + 2)."""

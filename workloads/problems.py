@@ -116,12 +116,16 @@ def ring_cut_qualities_device(n: int, device):
     q_j = sum_v [bit v of j != bit (v+1 mod n) of j]."""
     import torch
 
-    j = torch.arange(1 << n, dtype=torch.int64, device=device)
-    q = torch.zeros(1 << n, dtype=torch.float64, device=device)
-    for v in range(n):
-        w = (v + 1) % n
-        q += (((j >> v) ^ (j >> w)) & 1).to(torch.float64)
-    del j
+    q = torch.empty(1 << n, dtype=torch.float64, device=device)
+    chunk = 1 << min(n, 26)  # bounded temporaries at any n
+    for lo in range(0, 1 << n, chunk):
+        j = torch.arange(lo, lo + chunk, dtype=torch.int64, device=device)
+        acc = torch.zeros(chunk, dtype=torch.float64, device=device)
+        for v in range(n):
+            w = (v + 1) % n
+            acc += (((j >> v) ^ (j >> w)) & 1).to(torch.float64)
+        q[lo:lo + chunk] = acc
+        del j, acc
     return q
 
 
