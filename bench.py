@@ -292,6 +292,27 @@ def time_calls(fn, warmup: int, steps: int) -> float:
     return e0.elapsed_time(e1) / steps
 
 
+def attainable_rate(n: int, groups) -> dict | None:
+    """The streaming probe (probe/stream_probe.hip, built with the library) over
+    the tile geometries `groups` [(C, k)]: the same element -> index map and the
+    same 40 bytes per amplitude as a boundary pass, no arithmetic.  Runs as a
+    child process; None when the probe is not built."""
+    import subprocess
+
+    exe = os.path.join(ROOT, "paper_2110_03963_amd", "stream_probe")
+    if not os.path.exists(exe):
+        return None
+    args = [exe, str(n)] + [str(x) for g in groups for x in g]
+    res = subprocess.run(args, capture_output=True, text=True, timeout=120)
+    if res.returncode != 0:
+        return None
+    rows = [json.loads(line) for line in res.stdout.splitlines() if line.startswith("{")]
+    ms = sum(r["ms"] for r in rows) / len(rows)
+    return {"GBps": round(40.0 * (1 << n) / (ms * 1e-3) / 1e9, 1), "probe_ms": round(ms, 4),
+            "geometries": [{"C": r["C"], "k": r["k"], "GBps": r["GBps"]} for r in rows],
+            "command": " ".join(["paper_2110_03963_amd/stream_probe"] + args[1:])}
+
+
 def cpu_baseline(wl) -> dict:
     """The oracle (single-threaded C) on one layer of the same n = 28 instance."""
     import oracle
@@ -840,6 +861,14 @@ def main() -> int:
         entry = tr.get("kernels", {}).get(roofline["kernel"])
         if tr.get("source_digest") == source_digest(*TRAFFIC_SOURCES) and entry:
             roofline["traffic"] = entry["bytes_per_launch"]
+    # the attainable rate of the dominant kernel's access pattern (its tile
+    # geometries, the same bytes, no arithmetic), from the streaming probe
+    geoms = sorted({(i.col_bits, i.group_first) for i in infos
+                    if kernel_name(i.kind, i.col_bits) == roofline["kernel"] and i.col_bits >= 3})
+    att = attainable_rate(n, geoms) if geoms else None
+    if att:
+        roofline["attainable"] = att
+        roofline["frac_of_attainable"] = round(roofline["achieved"] / att["GBps"], 4)
     plan_bytes = sum(i.bytes for i in infos)
 
     result = {

@@ -1,7 +1,10 @@
 """Build libqva.so (HIP, gfx950) in-tree.
 
 Every source under csrc/ is compiled with hipcc for gfx950 into _build/, then
-linked into paper_2110_03963_amd/libqva.so.  Run as a module or call build().
+linked into paper_2110_03963_amd/libqva.so.  The streaming probe that bench.py
+uses for the attainable rate of the tile passes' access pattern
+(probe/stream_probe.hip) is built into paper_2110_03963_amd/stream_probe.  Run
+as a module or call build().
 """
 
 from __future__ import annotations
@@ -18,6 +21,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libqva.so")
+PROBE_SRC = os.path.join(PKG, "probe", "stream_probe.hip")
+PROBE = os.path.join(PKG, "stream_probe")
 
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -57,8 +62,14 @@ def build(verbose: bool = False) -> str:
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{res.stderr}")
     os.replace(tmp, LIB)
+    tmp = PROBE + ".tmp%d" % os.getpid()
+    res = subprocess.run([HIPCC, f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-Xclang", "-target-feature",
+                          "-Xclang", "-packed-fp32-ops", PROBE_SRC, "-o", tmp], capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {PROBE_SRC}:\n{res.stderr}")
+    os.replace(tmp, PROBE)
     if verbose:
-        print(f"built {LIB} from {len(sources)} sources")
+        print(f"built {LIB} from {len(sources)} sources, and {PROBE}")
     return LIB
 
 

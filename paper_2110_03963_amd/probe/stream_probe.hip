@@ -1,0 +1,104 @@
+// stream_probe.hip -- the attainable HBM rate of the tile passes' access
+// pattern, without their arithmetic.
+//
+// Each block streams one tile in place over 2^n amplitudes: 4096 elements =
+// 2^C contiguous amplitudes (16 << C bytes) in each of 2^(12-C) rows at a
+// stride of 2^k amplitudes, exactly the element -> index map of the tile
+// passes; it reads psi and q (24 bytes per amplitude) and writes psi back
+// (16), the traffic of a hypercube boundary pass.  Prints one JSON object
+// per (C, k): the time of one pass over the register and its rate.
+//
+// usage: stream_probe [n] [C k]...   (default n = 28 and a row-length sweep)
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+#define CHECK(x)                                                                    \
+    do {                                                                            \
+        hipError_t e_ = (x);                                                        \
+        if (e_ != hipSuccess) {                                                     \
+            std::fprintf(stderr, "HIP error %s at line %d\n", hipGetErrorString(e_), __LINE__); \
+            return 1;                                                               \
+        }                                                                           \
+    } while (0)
+
+__global__ __launch_bounds__(256) void tile_stream(double2* psi, const double* q, int C, int k)
+{
+    constexpr int R = 16;
+    const long tile = blockIdx.x;
+    const int lobits = k - C;
+    const long base = ((tile & ((1L << lobits) - 1)) << C) | ((tile >> lobits) << (k + 12 - C));
+    const int t = threadIdx.x;
+    double2 v[R];
+    double qq[R];
+    long at[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int e = t | (r << 8);
+        at[r] = base + (e & ((1 << C) - 1)) + ((long)(e >> C) << k);
+        v[r].x = __builtin_nontemporal_load(&psi[at[r]].x);
+        v[r].y = __builtin_nontemporal_load(&psi[at[r]].y);
+        qq[r] = __builtin_nontemporal_load(q + at[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        __builtin_nontemporal_store(v[r].x * qq[r], &psi[at[r]].x);
+        __builtin_nontemporal_store(v[r].y * qq[r], &psi[at[r]].y);
+    }
+}
+
+int main(int argc, char** argv)
+{
+    const int n = argc > 1 ? std::atoi(argv[1]) : 28;
+    if (n < 13 || n > 31) {
+        std::fprintf(stderr, "n must be in 13..31\n");
+        return 2;
+    }
+    std::vector<std::pair<int, int>> cases;
+    for (int i = 2; i + 1 < argc; i += 2)
+        cases.push_back({std::atoi(argv[i]), std::atoi(argv[i + 1])});
+    if (cases.empty())
+        for (int C = 3; C <= 9; ++C) {
+            cases.push_back({C, 12});
+            cases.push_back({C, n - (12 - C)});
+        }
+    for (const auto& c : cases)
+        if (c.first < 3 || c.first > 11 || c.second < c.first || c.second + 12 - c.first > n) {
+            std::fprintf(stderr, "bad tile: C=%d k=%d\n", c.first, c.second);
+            return 2;
+        }
+    const size_t N = (size_t)1 << n;
+    double2* psi;
+    double* q;
+    CHECK(hipMalloc(&psi, N * sizeof(double2)));
+    CHECK(hipMalloc(&q, N * sizeof(double)));
+    CHECK(hipMemset(psi, 0, N * sizeof(double2)));
+    CHECK(hipMemset(q, 0, N * sizeof(double)));
+    hipEvent_t e0, e1;
+    CHECK(hipEventCreate(&e0));
+    CHECK(hipEventCreate(&e1));
+    const unsigned grid = (unsigned)(N >> 12);
+    for (const auto& c : cases) {
+        for (int w = 0; w < 2; ++w)
+            tile_stream<<<grid, 256>>>(psi, q, c.first, c.second);
+        CHECK(hipGetLastError());
+        CHECK(hipDeviceSynchronize());
+        const int reps = 10;
+        CHECK(hipEventRecord(e0));
+        for (int r = 0; r < reps; ++r)
+            tile_stream<<<grid, 256>>>(psi, q, c.first, c.second);
+        CHECK(hipEventRecord(e1));
+        CHECK(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        CHECK(hipEventElapsedTime(&ms, e0, e1));
+        ms /= reps;
+        std::printf("{\"n\": %d, \"C\": %d, \"k\": %d, \"row_bytes\": %d, \"ms\": %.4f, \"GBps\": %.1f}\n", n,
+                    c.first, c.second, 16 << c.first, ms, 40.0 * (double)N / (ms * 1e-3) / 1e9);
+        std::fflush(stdout);
+    }
+    CHECK(hipFree(psi));
+    CHECK(hipFree(q));
+    return 0;
+}
