@@ -13,6 +13,12 @@ namespace qva {
 // temporaries from being live all at once.
 #define QVA_SCHED_FENCE() __builtin_amdgcn_sched_barrier(0)
 
+// Issue fence: an empty asm statement with a memory clobber.  The compiler
+// moves no memory access across it, so it fixes the order in which a tile's
+// global reads are issued (left alone, the compiler regroups them and may
+// place a pass's angle reads and their sine / cosine ahead of the tile's).
+#define QVA_ISSUE_FENCE() asm volatile("" ::: "memory")
+
 typedef double dvec2 __attribute__((ext_vector_type(2)));
 
 // Streaming (non-temporal) 16-byte load/store of one amplitude: every

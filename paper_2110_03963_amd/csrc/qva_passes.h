@@ -161,31 +161,69 @@ __device__ __forceinline__ void xpass_tile(const XPassParams& P, int64_t tile, d
     const int t = threadIdx.x;
     const TileMap g = tile_map(tile, P.k, C);
 
+    // Issue order of the tile's reads (measured per pass kind):
+    // * a pass that reads psi and q for its phase reads its angles first,
+    //   requests each register's psi and q together (the rows of a tile
+    //   then arrive together, which matters most at large row strides), and
+    //   computes the angles' sine and cosine while the tile is in flight;
+    // * the first pass requests q before anything else;
+    // * a pass without q requests psi before anything else;
+    // * the last pass and the Z-string passes keep the compiler's order.
+    constexpr bool phased = (flags & (XP_PHASE_PRE | XP_PHASE_MID)) && !zterms;
+    constexpr bool early_angles = phased && !(flags & XP_INIT);
+    double th_phase = 0.0, th_mix1 = 0.0, th_mix2 = 0.0;
+    if constexpr (early_angles) {
+        th_phase = angle_value(P.phase);
+        th_mix1 = (flags & XP_MIX1) ? angle_value(P.mix1) : 0.0;
+        th_mix2 = (flags & XP_MIX2) ? angle_value(P.mix2) : 0.0;
+    }
     double2 v[kRegs];
+    double qq[kRegs];
     if constexpr (flags & XP_INIT) {
         const double a0 = 1.0 / sqrt((double)(int64_t(1) << P.n));
 #pragma unroll
         for (int r = 0; r < kRegs; ++r)
             v[r] = make_double2(a0, 0.0);
+        if constexpr (use_q) {
+            load_q<LQ>(qq, P.q, g, t);
+            if constexpr (phased)
+                QVA_ISSUE_FENCE();
+        }
+    } else if constexpr (early_angles && use_q) {
+#pragma unroll
+        for (int r = 0; r < kRegs; ++r) {
+            v[r] = ld_nt(P.psi + g(elem<LA>(t, r)));
+            qq[r] = ld_nt(P.q + g(elem<LQ>(t, r)));
+            QVA_ISSUE_FENCE();
+        }
     } else {
+        if constexpr (!use_q && !zterms)
+            QVA_ISSUE_FENCE();
 #pragma unroll
         for (int r = 0; r < kRegs; ++r)
             v[r] = ld_nt(P.psi + g(elem<LA>(t, r)));
+        if constexpr (use_q)
+            load_q<LQ>(qq, P.q, g, t);
     }
-    double qq[kRegs];
-    if constexpr (use_q)
-        load_q<LQ>(qq, P.q, g, t);
+    if constexpr (early_angles) {
+        // the angles are used from here on: their sine and cosine follow the reads
+        asm volatile("" : "+v"(th_phase), "+v"(th_mix1), "+v"(th_mix2)::"memory");
+    } else {
+        th_phase = phased ? angle_value(P.phase) : 0.0;
+        th_mix1 = (flags & XP_MIX1) ? angle_value(P.mix1) : 0.0;
+        th_mix2 = (flags & XP_MIX2) ? angle_value(P.mix2) : 0.0;
+    }
     // Z-string terms: the phase angles themselves stand in for q (gamma = 1)
     if constexpr (zterms)
         zterm_angles<LQ, C>(qq, P.terms, P.n_terms, P.phase.ptr + P.phase.idx, g, t);
-    const double gam = zterms ? 1.0 : ((flags & (XP_PHASE_PRE | XP_PHASE_MID)) ? angle_value(P.phase) : 0.0);
+    const double gam = zterms ? 1.0 : th_phase;
 
     if constexpr (flags & XP_PHASE_PRE)
         phase_vals(v, qq, gam, make_double2(1.0, 0.0));
 
     double2 S1 = make_double2(1.0, 0.0);
     if constexpr (flags & XP_MIX1) {
-        const MixCoef m = mix_coef(angle_value(P.mix1));
+        const MixCoef m = mix_coef(th_mix1);
         if (m.tanform)
             mix_forward<C, true>(v, lds, t, m.k);
         else
@@ -195,7 +233,7 @@ __device__ __forceinline__ void xpass_tile(const XPassParams& P, int64_t tile, d
     if constexpr (flags & XP_PHASE_MID)
         phase_vals(v, qq, gam, S1);
     if constexpr (flags & XP_MIX2) {
-        const MixCoef m = mix_coef(angle_value(P.mix2));
+        const MixCoef m = mix_coef(th_mix2);
         if (m.tanform)
             mix_reverse<C, true>(v, lds, t, m.k);
         else
@@ -271,6 +309,22 @@ __device__ __forceinline__ void rot2_regs(double2 (&p)[kRegs], double2 (&x)[kReg
     }
 }
 
+// rot2_regs for element bit 3 held as thread bit 3 (layouts A and B): the pair
+// partner is lane ^ 8; the lane with bit 3 clear adds the pair's term.
+__device__ __forceinline__ void rot2_lane8(double2 (&p)[kRegs], double2 (&x)[kRegs], double c, double s,
+                                           double& acc, int t)
+{
+    const bool low = !(t & 8);
+#pragma unroll
+    for (int r = 0; r < kRegs; ++r) {
+        const double2 pu = lane_xor8(p[r]), xu = lane_xor8(x[r]);
+        const double d = im_pair(p[r], pu, x[r], xu);
+        acc += low ? d : 0.0;
+        p[r] = make_double2(fma(c, p[r].x, s * pu.y), fma(c, p[r].y, -s * pu.x));
+        x[r] = make_double2(fma(c, x[r].x, s * xu.y), fma(c, x[r].y, -s * xu.x));
+    }
+}
+
 template <int FROM, int TO>
 __device__ __forceinline__ void exchange2(double2 (&p)[kRegs], double2 (&x)[kRegs], double2* lds, int t)
 {
@@ -284,7 +338,11 @@ __device__ __forceinline__ void mix2_forward(double2 (&p)[kRegs], double2 (&x)[k
                                              double c, double s, double& acc)
 {
     rot2_regs<target_mask<C, LA>()>(p, x, c, s, acc);
-    if constexpr (C < 4) {
+    if constexpr (C == 3) {
+        rot2_lane8(p, x, c, s, acc, t);
+        exchange2<LA, LB>(p, x, lds, t);
+        rot2_regs<target_mask<C, LB>()>(p, x, c, s, acc);
+    } else if constexpr (C < 4) {
         exchange2<LA, LC>(p, x, lds, t);
         rot2_regs<target_mask<C, LC>()>(p, x, c, s, acc);
         exchange2<LC, LB>(p, x, lds, t);
@@ -300,7 +358,11 @@ template <int C>
 __device__ __forceinline__ void mix2_reverse(double2 (&p)[kRegs], double2 (&x)[kRegs], double2* lds, int t,
                                              double c, double s, double& acc)
 {
-    if constexpr (C < 4) {
+    if constexpr (C == 3) {
+        rot2_regs<target_mask<C, LB>()>(p, x, c, s, acc);
+        exchange2<LB, LA>(p, x, lds, t);
+        rot2_lane8(p, x, c, s, acc, t);
+    } else if constexpr (C < 4) {
         rot2_regs<target_mask<C, LB>()>(p, x, c, s, acc);
         exchange2<LB, LC>(p, x, lds, t);
         rot2_regs<target_mask<C, LC>()>(p, x, c, s, acc);

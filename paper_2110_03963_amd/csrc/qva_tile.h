@@ -396,6 +396,40 @@ __device__ __forceinline__ void rotate_regs(double2 (&v)[kRegs], double k)
     }
 }
 
+// The same register of lane (lane ^ 8): DPP row_mirror (lane ^ 15 within each
+// row of 16 lanes) followed by row_half_mirror (lane ^ 7 within each half
+// row).  Every lane of the wave must be active.
+__device__ __forceinline__ double lane_xor8(double v)
+{
+    int lo = __double2loint(v), hi = __double2hiint(v);
+    lo = __builtin_amdgcn_update_dpp(0, lo, 0x140, 0xF, 0xF, false);
+    hi = __builtin_amdgcn_update_dpp(0, hi, 0x140, 0xF, 0xF, false);
+    lo = __builtin_amdgcn_update_dpp(0, lo, 0x141, 0xF, 0xF, false);
+    hi = __builtin_amdgcn_update_dpp(0, hi, 0x141, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double2 lane_xor8(double2 v) { return make_double2(lane_xor8(v.x), lane_xor8(v.y)); }
+
+// The rotation of element bit 3 in layouts A and B, where it is thread bit 3:
+// the other member of each pair is the same register of lane ^ 8.  B is
+// symmetric in the pair, so each lane forms its own half of the butterfly
+// with the same operations as bfly_tan / bfly_cot.  Used for tiles with 3
+// column bits, whose only target bit below 4 is bit 3: it saves the round
+// trip through layout C.
+template <bool TAN>
+__device__ __forceinline__ void rotate_lane8(double2 (&v)[kRegs], double k)
+{
+#pragma unroll
+    for (int r = 0; r < kRegs; ++r) {
+        const double2 u = lane_xor8(v[r]);
+        if constexpr (TAN)
+            v[r] = make_double2(fma(k, u.y, v[r].x), fma(-k, u.x, v[r].y));
+        else
+            v[r] = make_double2(fma(-k, v[r].y, u.x), fma(k, v[r].x, u.y));
+    }
+}
+
 // Layout in which the first mixer application ends: B when the tile has
 // target bits in [4,8), else A.
 template <int C>
@@ -405,12 +439,16 @@ constexpr int last_layout()
 }
 
 // Rotations of every target qubit of the tile; enters in A, leaves in
-// last_layout<C>().  Order A, C, B.
+// last_layout<C>().  Order A, C, B (A with bit 3 across lanes, B for C = 3).
 template <int C, bool TAN>
 __device__ __forceinline__ void mix_forward(double2 (&v)[kRegs], double2* lds, int t, double k)
 {
     rotate_regs<target_mask<C, LA>(), TAN>(v, k);
-    if constexpr (C < 4) {
+    if constexpr (C == 3) {
+        rotate_lane8<TAN>(v, k);
+        exchange<LA, LB>(v, lds, t);
+        rotate_regs<target_mask<C, LB>(), TAN>(v, k);
+    } else if constexpr (C < 4) {
         exchange<LA, LC>(v, lds, t);
         rotate_regs<target_mask<C, LC>(), TAN>(v, k);
         exchange<LC, LB>(v, lds, t);
@@ -425,7 +463,11 @@ __device__ __forceinline__ void mix_forward(double2 (&v)[kRegs], double2* lds, i
 template <int C, bool TAN>
 __device__ __forceinline__ void mix_reverse(double2 (&v)[kRegs], double2* lds, int t, double k)
 {
-    if constexpr (C < 4) {
+    if constexpr (C == 3) {
+        rotate_regs<target_mask<C, LB>(), TAN>(v, k);
+        exchange<LB, LA>(v, lds, t);
+        rotate_lane8<TAN>(v, k);
+    } else if constexpr (C < 4) {
         rotate_regs<target_mask<C, LB>(), TAN>(v, k);
         exchange<LB, LC>(v, lds, t);
         rotate_regs<target_mask<C, LC>(), TAN>(v, k);
