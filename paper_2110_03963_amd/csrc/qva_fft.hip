@@ -175,9 +175,24 @@ __global__ __launch_bounds__(kThreads, 2) void fftpass_kernel(FftPassParams P)
         dit_tile<C>(v, lds, g, t);
         store_tile<LA>(v, P.psi, g, t, 1.0);
     } else if constexpr (FLAGS == FMODE_BOUNDARY) {
-        load_tile<dif_last<C>()>(v, P.psi, g, t);
+        // the angle first, each register's psi and q requested together, the
+        // phase factors computed after the whole tile is in flight
+        double gam = angle_value(P.phase);
+        double qq[kRegs];
+#pragma unroll
+        for (int r = 0; r < kRegs; ++r) {
+            v[r] = ld_nt(P.psi + g(elem<dif_last<C>()>(t, r)));
+            qq[r] = ld_nt(P.q + g(elem<LA>(t, r)));
+            QVA_ISSUE_FENCE();
+        }
+        asm volatile("" : "+v"(gam)::"memory");
         dit_tile<C>(v, lds, g, t);
-        phase_a(v, P.q, g, t, angle_value(P.phase), invN);
+#pragma unroll
+        for (int r = 0; r < kRegs; ++r) {
+            const double2 ph = expmi(gam * qq[r]);
+            v[r] = cmul(v[r], make_double2(invN * ph.x, invN * ph.y));
+            QVA_SCHED_FENCE();
+        }
         dif_tile<C>(v, lds, g, t);
         store_tile<dif_last<C>()>(v, P.psi, g, t, 1.0);
     } else if constexpr (FLAGS == FMODE_LAST || FLAGS == FMODE_LAST_STORE) {

@@ -563,15 +563,27 @@ __device__ __forceinline__ void gradx_tile(const GradPassParams& P, int64_t tile
         constexpr bool zterms = MODE & GM_ZTERMS;
         static_assert(!zterms || BM == GMODE_BOUND || BM == GMODE_FINAL, "Z-string terms at a phase only");
         constexpr int L = last_layout<C>();
-        // every angle and its sine/cosine before the data is loaded: computed
-        // mid-pass they extend register live ranges across the whole tile
+        // The angles are read before the tile, each register's phi and chi are
+        // requested together (issue fences keep that order), and the angles'
+        // sine and cosine are computed while the tile is in flight, before any
+        // other work, so that their temporaries are dead by the time the
+        // rotations need registers.
         double c, s, c2 = 1.0, s2 = 0.0, gam = 0.0;
-        inv_cs(angle_value(P.t1), c, s);
+        double th1 = angle_value(P.t1), th2 = 0.0;
         if constexpr (BM == GMODE_BOUND)
-            inv_cs(angle_value(P.t2), c2, s2);
+            th2 = angle_value(P.t2);
         if constexpr (BM != GMODE_MID && !zterms)
             gam = angle_value(P.gamma);
-        load2<LA>(p, x, P, g, t);
+#pragma unroll
+        for (int r = 0; r < kRegs; ++r) {
+            p[r] = ld_nt(P.phi + g(elem<LA>(t, r)));
+            x[r] = ld_nt(P.chi + g(elem<LA>(t, r)));
+            QVA_ISSUE_FENCE();
+        }
+        asm volatile("" : "+v"(th1), "+v"(th2), "+v"(gam)::"memory");
+        inv_cs(th1, c, s);
+        if constexpr (BM == GMODE_BOUND)
+            inv_cs(th2, c2, s2);
         mix2_forward<C>(p, x, lds, t, c, s, a1);
         if constexpr (BM == GMODE_MID) {
             write_slots(P, a1, 0.0, 0.0, red, tile);
