@@ -284,7 +284,9 @@ typedef enum {
     QVA_PASS_GRAD_BLU_TURN = 46,   /* inverse top group, <Q>, chi = Q x, forward top (both) */
     QVA_PASS_GRAD_BLU_LAMBDA = 47, /* inverse top, Im<chi|W|phi>, exp(+i t lambda), forward */
     QVA_PASS_GRAD_BLU_PHASE = 48,  /* inverse top, Im<chi|Q|phi>, exp(+i gamma q), forward  */
-    QVA_PASS_GRAD_BLU_FINAL = 49   /* inverse top group, Im<chi|Q|phi> of layer 1           */
+    QVA_PASS_GRAD_BLU_FINAL = 49,  /* inverse top group, Im<chi|Q|phi> of layer 1           */
+    QVA_PASS_GRAD_ZSLOT = 50       /* extended QAOA: per-term sums of the preceding phase
+                                      pass's Im(conj(chi_j) phi_j), one tile transform each */
 } qva_pass_kind;
 
 /* One launch of a plan.  `bytes` is the algorithmic HBM traffic of the

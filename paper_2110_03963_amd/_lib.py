@@ -71,7 +71,8 @@ PASS_KINDS = {0: "whole", 1: "first", 2: "middle", 3: "boundary", 4: "last", 5: 
               32: "grad_cpl_back", 33: "grad_cpl_sum", 34: "blu_chirp", 35: "blu_tile",
               36: "blu_first", 37: "blu_mul", 38: "blu_lambda", 39: "blu_phase", 40: "blu_last",
               41: "blu_last_store", 42: "xy", 43: "xy_last", 44: "xy_turn", 45: "grad_xy",
-              46: "grad_blu_turn", 47: "grad_blu_lambda", 48: "grad_blu_phase", 49: "grad_blu_final"}
+              46: "grad_blu_turn", 47: "grad_blu_lambda", 48: "grad_blu_phase", 49: "grad_blu_final",
+              50: "grad_zslot"}
 
 
 class QvaBatchItem(ctypes.Structure):

@@ -688,6 +688,7 @@ struct GradLayout {
     int nslots = 0;  // p * (G + E) per-tile slot arrays (none for the closed-form mixer)
     size_t fpart = 0, slots = 0, sums = 0, lam = 0, part = 0, state = 0, total = 0;
     size_t pad_phi = 0, pad_chi = 0, b0 = 0, b1 = 0;  // Bluestein: padded vectors, filter spectra
+    size_t zd = 0;   // extended QAOA: Im(conj(chi_j) phi_j) at a phase, 2^n doubles
 };
 
 
@@ -753,6 +754,9 @@ GradLayout grad_layout(const qva_problem* P, int p)
     off = align256(off + (size_t)(g.nslots > 0 ? g.nslots : 1) * sizeof(double));
     g.lam = off;
     if (P->mixer == QVA_MIX_CIRCULANT && lambda_tiled(P))
+        off = align256(off + (size_t)(int64_t(1) << n) * sizeof(double));
+    g.zd = off;
+    if (P->mixer == QVA_MIX_X && problem_terms(P) > 0)
         off = align256(off + (size_t)(int64_t(1) << n) * sizeof(double));
     g.total = off;
     return g;
@@ -857,13 +861,19 @@ std::vector<GLaunch> grad_launches(const qva_problem* P, int p)
             if (f.flags == XMODE_MIDDLE)
                 L.push_back({QVA_PASS_GRAD_MID, f.group, GMODE_MID, f.layer1, -1, -1,
                              tslot(f.layer1, f.group), -1, -1});
-            else
+            else {
                 L.push_back({QVA_PASS_GRAD_BOUND, f.group, GMODE_BOUND | gz, f.layer2, f.layer1, f.phase_layer,
-                             tslot(f.layer2, f.group), gslot(f.phase_layer), tslot(f.layer1, f.group)});
+                             tslot(f.layer2, f.group), gz ? -1 : gslot(f.phase_layer), tslot(f.layer1, f.group)});
+                if (gz)
+                    L.push_back({QVA_PASS_GRAD_ZSLOT, f.group, GMODE_ZSLOT, -1, -1, f.phase_layer, -1,
+                                 gslot(f.phase_layer), -1});
+            }
         }
         const XPass& first = fw[0];
-        L.push_back({QVA_PASS_GRAD_FINAL, first.group, GMODE_FINAL | gz, 0, -1, 0, tslot(0, first.group), gslot(0),
-                     -1});
+        L.push_back({QVA_PASS_GRAD_FINAL, first.group, GMODE_FINAL | gz, 0, -1, 0, tslot(0, first.group),
+                     gz ? -1 : gslot(0), -1});
+        if (gz)
+            L.push_back({QVA_PASS_GRAD_ZSLOT, first.group, GMODE_ZSLOT, -1, -1, 0, -1, gslot(0), -1});
     } else {
         if (lambda_tiled(P))
             L.push_back({QVA_PASS_LAMBDA_PREP, -1, 0, -1, -1, -1, -1, -1, -1});
@@ -913,10 +923,12 @@ double grad_launch_bytes(const GLaunch& l, const qva_problem* P, int p)
         return 64.0 * N;
     case QVA_PASS_GRAD_LOWDIAG:
         return 64.0 * N + (tiled ? 8.0 * N : 0.0);
-    case QVA_PASS_GRAD_BOUND:  // the Z-string phase reads no q; one slot per term and tile
-        return (l.mode & GM_ZTERMS) ? 64.0 * N + 8.0 * problem_terms(P) * (N / 4096.0) : 72.0 * N;
+    case QVA_PASS_GRAD_BOUND:  // (a Z-string phase writes Im(conj(chi) phi) instead of reading q)
+        return 72.0 * N;
     case QVA_PASS_GRAD_FINAL:
-        return (l.mode & GM_ZTERMS) ? 32.0 * N + 8.0 * problem_terms(P) * (N / 4096.0) : 40.0 * N;
+        return 40.0 * N;
+    case QVA_PASS_GRAD_ZSLOT:  // the stored values in, one slot per term and tile out
+        return 8.0 * N + 8.0 * problem_terms(P) * (N / 4096.0);
     case QVA_PASS_GRAD_REDUCE: {
         const GradLayout g = grad_layout(P, p);
         return 8.0 * (double)g.nslots * (double)g.tiles;
@@ -1145,12 +1157,13 @@ int grad_run(const qva_problem* P, const double* gammas, const double* ts, int p
             gp.col_bits = g.col_bits;
             gp.flags = l.mode;
             gp.slot_t1 = slot_ptr(l.slot_t1);
-            gp.slot_g = (l.mode & GM_ZTERMS) ? nullptr : slot_ptr(l.slot_g);
+            gp.slot_g = l.kind == QVA_PASS_GRAD_ZSLOT ? nullptr : slot_ptr(l.slot_g);
             gp.slot_t2 = slot_ptr(l.slot_t2);
             gp.fpart = fpart;
             gp.terms = reinterpret_cast<const ZTerm*>(P->terms);
             gp.n_terms = problem_terms(P);
-            gp.slot_terms = (l.mode & GM_ZTERMS) ? slot_ptr(l.slot_g) : nullptr;
+            gp.slot_terms = l.kind == QVA_PASS_GRAD_ZSLOT ? slot_ptr(l.slot_g) : nullptr;
+            gp.zd = reinterpret_cast<double*>(work + W.zd);
             e = launch_gradpass(gp, circ, s);
             break;
         }

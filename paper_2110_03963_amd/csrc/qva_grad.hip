@@ -46,15 +46,27 @@ __global__ __launch_bounds__(kThreads, QVA_GRADX_WAVES) void gradx_kernel(GradPa
     gradx_tile<C, MODE>(P, blockIdx.x, lds, red);
 }
 
-// The extended-QAOA phase passes hold the term coefficients and the
-// transform operand beside both vectors: one wave per SIMD keeps them in
-// registers.
+// The extended-QAOA phase passes hold the Z-string angles beside both
+// vectors: at one wave per SIMD they stay in registers (two waves spill
+// about 140 registers and run 10% slower).
+#ifndef QVA_GRADZ_WAVES
+#define QVA_GRADZ_WAVES 1
+#endif
 template <int C, int MODE>
-__global__ __launch_bounds__(kThreads, QVA_GRADF_WAVES) void gradxz_kernel(GradPassParams P)
+__global__ __launch_bounds__(kThreads, QVA_GRADZ_WAVES) void gradxz_kernel(GradPassParams P)
 {
     __shared__ double2 lds[1 << kTileBits];
     __shared__ double red[4 * (kThreads / 64)];
     gradx_tile<C, MODE>(P, blockIdx.x, lds, red);
+}
+
+// Per-term slots of an extended-QAOA phase from the values its backward pass
+// stored (GMODE_ZSLOT).
+template <int C>
+__global__ __launch_bounds__(kThreads, 2) void zslot_kernel(GradPassParams P)
+{
+    __shared__ double2 lds[1 << kTileBits];
+    zslot_tile<C>(P, blockIdx.x, lds);
 }
 
 // ------------------------------------------------ circulant-mixer passes
@@ -568,6 +580,9 @@ hipError_t launch_gradx_c(const GradPassParams& P, unsigned grid, hipStream_t s)
         break;
     case GMODE_FINAL_Z:
         hipLaunchKernelGGL((gradxz_kernel<C, GMODE_FINAL_Z>), dim3(grid), dim3(kThreads), 0, s, P);
+        break;
+    case GMODE_ZSLOT:
+        hipLaunchKernelGGL((zslot_kernel<C>), dim3(grid), dim3(kThreads), 0, s, P);
         break;
     default:
         return hipErrorInvalidValue;

@@ -239,7 +239,8 @@ enum : int {
     GMODE_DIF = 5,     // forward transform of one group, both vectors (circulant)
     GMODE_DIT = 6,     // inverse transform of one group, both vectors
     GMODE_LOWDIAG = 7, // low group: forward, <chi^|lambda|phi^>, inverse diagonal, inverse
-    GM_ZTERMS = 16,    // with GMODE_BOUND / GMODE_FINAL: extended-QAOA phase, one slot per term
+    GM_ZTERMS = 16,    // with GMODE_BOUND / GMODE_FINAL: extended-QAOA phase; d_j = Im(conj(chi_j) phi_j)
+                       // at the phase is stored to zd for the GMODE_ZSLOT pass that follows
     GMODE_BOUND_Z = GMODE_BOUND | GM_ZTERMS,
     GMODE_FINAL_Z = GMODE_FINAL | GM_ZTERMS,
     // Bluestein adjoint (top group of the padded transform, both vectors; the
@@ -247,7 +248,8 @@ enum : int {
     GMODE_B_TURN = 32,   // inverse top group of psi, <Q>, chi = q x, forward top group (both)
     GMODE_B_LAM = 33,    // inverse top group, Im<chi|W|phi>, exp(+i t lambda), forward top group
     GMODE_B_Q = 34,      // inverse top group, 1/N, Im<chi|Q|phi>, exp(+i gamma q), forward top group
-    GMODE_B_FINAL = 35   // inverse top group, 1/N, Im<chi|Q|phi> (nothing written)
+    GMODE_B_FINAL = 35,  // inverse top group, 1/N, Im<chi|Q|phi> (nothing written)
+    GMODE_ZSLOT = 40     // per-term slots of an extended-QAOA phase from the stored d_j
 };
 
 struct GradPassParams {
@@ -267,7 +269,8 @@ struct GradPassParams {
     double2* fpart;   // per-tile (f, norm) partials (GMODE_TURN)
     const ZTerm* terms;   // GM_ZTERMS: gamma.ptr + gamma.idx is the layer's angle row
     int n_terms;
-    double* slot_terms;   // GM_ZTERMS: term e of tile i at slot_terms[e * tiles + i]
+    double* slot_terms;   // GMODE_ZSLOT: term e of tile i at slot_terms[e * tiles + i]
+    double* zd;           // GM_ZTERMS, GMODE_ZSLOT: d_j at the phase, indexed like psi
     int64_t nb;           // GMODE_B_*: the logical N (n above is log2 of the padded M)
 };
 

@@ -504,6 +504,22 @@ __device__ __forceinline__ void zterm_slots(double (&d)[kRegs], const GradPassPa
     }
 }
 
+// The per-term slots of an extended-QAOA phase (see zterm_slots) from the
+// values d_j = Im(conj(chi_j) phi_j) that its backward pass stored to zd, read
+// in the layout in which that pass held them.
+template <int C>
+__device__ __forceinline__ void zslot_tile(const GradPassParams& P, int64_t tile, double2* lds)
+{
+    constexpr int L = last_layout<C>();
+    const int t = threadIdx.x;
+    const TileMap g = tile_map(tile, P.k, C);
+    double d[kRegs];
+#pragma unroll
+    for (int r = 0; r < kRegs; ++r)
+        d[r] = __builtin_nontemporal_load(P.zd + g(elem<L>(t, r)));
+    zterm_slots<C, L>(d, P, g, t, tile, lds);
+}
+
 // Block sum of one accumulator to its per-tile slot (skipped when null).
 __device__ __forceinline__ void write_slot(double* slot, double a, double* red, int64_t tile)
 {
@@ -574,6 +590,12 @@ __device__ __forceinline__ void gradx_tile(const GradPassParams& P, int64_t tile
             th2 = angle_value(P.t2);
         if constexpr (BM != GMODE_MID && !zterms)
             gam = angle_value(P.gamma);
+        // Z-string phase angles depend only on the tile's position: formed
+        // before the tile is loaded, their coefficient registers are free again
+        // while both vectors are held
+        double dv[kRegs];
+        if constexpr (zterms)
+            zterm_angles<L, C>(dv, P.terms, P.n_terms, P.gamma.ptr + P.gamma.idx, g, t);
 #pragma unroll
         for (int r = 0; r < kRegs; ++r) {
             p[r] = ld_nt(P.phi + g(elem<LA>(t, r)));
@@ -595,12 +617,9 @@ __device__ __forceinline__ void gradx_tile(const GradPassParams& P, int64_t tile
                 // the mixer slot first: its sum is then taken here, not
                 // deferred past the term loop with every rotation's operands
                 write_slot(P.slot_t1, a1, red, tile);
-                // the angles, then register by register the inverse phase on
-                // both vectors and Im(conj(chi) phi) in place of the angle
-                // (taken after the phase, which it does not change, so that
-                // the phase is not deferred past the transform)
-                double dv[kRegs];
-                zterm_angles<L, C>(dv, P.terms, P.n_terms, P.gamma.ptr + P.gamma.idx, g, t);
+                // register by register the inverse phase on both vectors and
+                // Im(conj(chi) phi) in place of the angle (taken after the
+                // phase, which it does not change)
 #pragma unroll
                 for (int r = 0; r < kRegs; ++r) {
                     const double2 u = expmi(-dv[r]);
@@ -609,7 +628,12 @@ __device__ __forceinline__ void gradx_tile(const GradPassParams& P, int64_t tile
                     dv[r] = x[r].x * p[r].y - x[r].y * p[r].x;
                     QVA_SCHED_FENCE();
                 }
-                zterm_slots<C, L>(dv, P, g, t, tile, lds);
+                // the per-term sums follow in a pass of their own (zslot_tile):
+                // their transform beside both vectors would cost this pass
+                // half its waves
+#pragma unroll
+                for (int r = 0; r < kRegs; ++r)
+                    __builtin_nontemporal_store(dv[r], P.zd + g(elem<L>(t, r)));
             } else {
                 ag = unphase2<L, false>(p, x, P.q, g, t, gam, 1.0);
             }

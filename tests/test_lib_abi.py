@@ -448,7 +448,10 @@ def test_zterm_validation(lib):
 def test_zterm_plan(lib, n, p):
     """With terms the passes are those of QAOA; the phase passes read no q
     (first pass 16 B/amp, boundary 32 B/amp), and the gradient has one slot
-    array per term and layer: workspace grows by p E tiles doubles."""
+    array per term and layer (workspace grows by p E tiles doubles) plus one
+    array of 2^n doubles: each backward phase pass writes Im(conj(chi) phi)
+    there instead of reading q, and a pass of kind 50 right after it turns
+    those values into the per-term slots."""
     E = 37
     zt = _prob(n=n, terms=FAKE, n_terms=E)
     pl = _prob(n=n)
@@ -465,15 +468,25 @@ def test_zterm_plan(lib, n, p):
     tiles = N >> 12
     w_plain = lib.qva_workspace_bytes(ctypes.byref(pl), p, 1)
     w_z = lib.qva_workspace_bytes(ctypes.byref(zt), p, 1)
-    assert w_z - w_plain >= 8 * p * (E - 1) * tiles
+    assert w_z - w_plain >= 8 * p * (E - 1) * tiles + 8 * N
     cnt = lib.qva_plan(ctypes.byref(zt), p, 1, 0, None, 0)
-    g = (_lib.QvaPassInfo * cnt)()
-    assert lib.qva_plan(ctypes.byref(zt), p, 1, 0, g, cnt) == cnt
+    arr = (_lib.QvaPassInfo * cnt)()
+    assert lib.qva_plan(ctypes.byref(zt), p, 1, 0, arr, cnt) == cnt
+    g = list(arr)
     gp = _grad_plan(lib, 0, n, p)
-    assert [x.kind for x in g] == [x.kind for x in gp]
-    for x, y in zip(g, gp):
-        if x.kind in (20, 21):  # phase undone with per-term slots, no q read
-            assert x.bytes == y.bytes - 8 * N + 8 * E * tiles
+    # every backward phase pass (20, 21) is followed by a slot pass (50) over
+    # the same tiles; without those the plan is the plain one
+    zs = [i for i, x in enumerate(g) if x.kind == 50]
+    assert len(zs) == p and all(g[i - 1].kind in (20, 21) for i in zs)
+    for i in zs:
+        assert (g[i].group_first, g[i].group_bits, g[i].col_bits, g[i].phase_layer) == \
+               (g[i - 1].group_first, g[i - 1].group_bits, g[i - 1].col_bits, g[i - 1].phase_layer)
+        assert g[i].bytes == 8 * N + 8 * E * tiles
+    rest = [x for x in g if x.kind != 50]
+    assert [x.kind for x in rest] == [x.kind for x in gp]
+    for x, y in zip(rest, gp):
+        if x.kind in (20, 21):  # Im(conj(chi) phi) written in place of the q read
+            assert x.bytes == y.bytes
         elif x.kind == 25:      # the slot reduction covers p (G + E) slots
             assert x.bytes == y.bytes + 8 * p * (E - 1) * tiles
         else:
