@@ -292,23 +292,25 @@ def time_calls(fn, warmup: int, steps: int) -> float:
     return e0.elapsed_time(e1) / steps
 
 
-def attainable_rate(n: int, groups) -> dict | None:
+def attainable_rate(n: int, groups, two: bool = False) -> dict | None:
     """The streaming probe (probe/stream_probe.hip, built with the library) over
     the tile geometries `groups` [(C, k)]: the same element -> index map and the
-    same 40 bytes per amplitude as a boundary pass, no arithmetic.  Runs as a
-    child process; None when the probe is not built."""
+    same 40 bytes per amplitude as a boundary pass (two=True: two vectors and q,
+    72 bytes per amplitude, as a backward boundary pass), no arithmetic.  Runs
+    as a child process; None when the probe is not built."""
     import subprocess
 
     exe = os.path.join(ROOT, "paper_2110_03963_amd", "stream_probe")
     if not os.path.exists(exe):
         return None
-    args = [exe, str(n)] + [str(x) for g in groups for x in g]
+    args = [exe] + (["-2"] if two else []) + [str(n)] + [str(x) for g in groups for x in g]
     res = subprocess.run(args, capture_output=True, text=True, timeout=120)
     if res.returncode != 0:
         return None
     rows = [json.loads(line) for line in res.stdout.splitlines() if line.startswith("{")]
     ms = sum(r["ms"] for r in rows) / len(rows)
-    return {"GBps": round(40.0 * (1 << n) / (ms * 1e-3) / 1e9, 1), "probe_ms": round(ms, 4),
+    bpa = 72.0 if two else 40.0
+    return {"GBps": round(bpa * (1 << n) / (ms * 1e-3) / 1e9, 1), "probe_ms": round(ms, 4),
             "geometries": [{"C": r["C"], "k": r["k"], "GBps": r["GBps"]} for r in rows],
             "command": " ".join(["paper_2110_03963_amd/stream_probe"] + args[1:])}
 
@@ -483,6 +485,14 @@ def extra_adjoint(lib, reps: int, workload: str = "qaoa") -> dict:
 
     per = per_kernel_profile(run_timed, infos, 1)
     plan_bytes = sum(i.bytes for i in infos)
+    roof = roofline_of(per, 1)
+    if workload == "qaoa" and roof["kernel"].startswith("grad_bound<"):
+        # the streaming probe over the backward boundary passes' tiles, 72 B/amp
+        geoms = sorted({(i.col_bits, i.group_first) for i in infos if i.kind == 20})
+        att = attainable_rate(prob.n, geoms, two=True)
+        if att:
+            roof["attainable"] = att
+            roof["frac_of_attainable"] = round(roof["achieved"] / att["GBps"], 4)
     return {"workload": name, "params": 2 * p,
             "ms_per_adjoint_gradient": round(ms_adj, 2),
             "adjoint_gradients_per_s": round(1e3 / ms_adj, 3),
@@ -493,7 +503,7 @@ def extra_adjoint(lib, reps: int, workload: str = "qaoa") -> dict:
             "max_rel_diff_adjoint_vs_central_fd": rel, "fd_steps": {"gamma": h, "t": h_t},
             "f": f.item(), "launches": len(infos),
             "effective_GBps": round(plan_bytes / (ms_adj * 1e-3) / 1e9, 1),
-            "roofline": roofline_of(per, 1),
+            "roofline": roof,
             "per_kernel_ms": {k: round(v["ms"], 3) for k, v in sorted(per.items())}}
 
 

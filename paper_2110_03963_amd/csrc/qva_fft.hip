@@ -52,14 +52,24 @@ __device__ __forceinline__ void diag_c(double2 (&v)[kRegs], const FftPassParams&
             v[r] = cmul(v[r], complete_diag(tile == 0 && elem<LC>(t, r) == 0, tt, n));
         return;
     }
-    const double2 u = P.lambda_kind == FFT_LAMBDA_RING ? ring_lambda_base(tile, t, n) : make_double2(0.0, 0.0);
+    if (P.lambda_kind == FFT_LAMBDA_RING) {
+        // registers r and r + 1 (r even) hold digits k and k + 8, whose ring
+        // eigenvalues are exact negatives: one exponential serves both
+        const double2 u = ring_lambda_base(tile, t, n);
+#pragma unroll
+        for (int r = 0; r < kRegs; r += 2) {
+            const double2 e = expmi(tt * ring_lambda(u, r));
+            v[r] = cmul(v[r], e);
+            v[r + 1] = cmul(v[r + 1], make_double2(e.x, -e.y));
+            QVA_SCHED_FENCE();
+        }
+        return;
+    }
 #pragma unroll
     for (int r = 0; r < kRegs; ++r) {
         double lam;
         if (P.lambda_kind == FFT_LAMBDA_TILED) {
             lam = ld_nt(P.lam + (tile << kTileBits) + r * kThreads + t);
-        } else if (P.lambda_kind == FFT_LAMBDA_RING) {
-            lam = ring_lambda(u, r);
         } else {
             const int64_t pos = (tile << kTileBits) | elem<LC>(t, r);
             const uint64_t m = __brevll((uint64_t)pos) >> (64 - n);

@@ -287,17 +287,34 @@ __global__ __launch_bounds__(kThreads, QVA_GRADF_WAVES) void gradf_kernel(GradPa
         dif_tile2<C>(p, x, lds, g, t);
         double a1 = 0.0;
         const double2 u = P.lambda_kind == FFT_LAMBDA_RING ? ring_lambda_base(tile, t, P.n) : make_double2(0.0, 0.0);
+        if (P.lambda_kind == FFT_LAMBDA_RING) {
+            // registers r and r + 1 (r even): ring eigenvalues of opposite
+            // sign, one exponential for both (as in the forward pass)
 #pragma unroll
-        for (int r = 0; r < kRegs; ++r) {
-            const double lam = lambda_at(P, tile, t, r, u);
-            a1 = fma(lam, x[r].x * p[r].y - x[r].y * p[r].x, a1);
-            // exp(+i t lambda): the inverse diagonal
-            const double2 d = P.lambda_kind == FFT_LAMBDA_COMPLETE
-                                  ? complete_diag(tile == 0 && elem<LC>(t, r) == 0, -tt, P.n)
-                                  : expmi(-tt * lam);
-            p[r] = cmul(p[r], d);
-            x[r] = cmul(x[r], d);
-            QVA_SCHED_FENCE();
+            for (int r = 0; r < kRegs; r += 2) {
+                const double lam = ring_lambda(u, r);
+                a1 = fma(lam, x[r].x * p[r].y - x[r].y * p[r].x, a1);
+                a1 = fma(-lam, x[r + 1].x * p[r + 1].y - x[r + 1].y * p[r + 1].x, a1);
+                const double2 dd = expmi(-tt * lam), dc = make_double2(dd.x, -dd.y);
+                p[r] = cmul(p[r], dd);
+                x[r] = cmul(x[r], dd);
+                p[r + 1] = cmul(p[r + 1], dc);
+                x[r + 1] = cmul(x[r + 1], dc);
+                QVA_SCHED_FENCE();
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < kRegs; ++r) {
+                const double lam = lambda_at(P, tile, t, r, u);
+                a1 = fma(lam, x[r].x * p[r].y - x[r].y * p[r].x, a1);
+                // exp(+i t lambda): the inverse diagonal
+                const double2 d = P.lambda_kind == FFT_LAMBDA_COMPLETE
+                                      ? complete_diag(tile == 0 && elem<LC>(t, r) == 0, -tt, P.n)
+                                      : expmi(-tt * lam);
+                p[r] = cmul(p[r], d);
+                x[r] = cmul(x[r], d);
+                QVA_SCHED_FENCE();
+            }
         }
         write_slots(P, a1 * invN, 0.0, 0.0, red, tile);
         dit_tile2<C>(p, x, lds, g, t);
