@@ -577,3 +577,20 @@ def test_xy_plan(lib, n, p):
     assert lib.qva_workspace_bytes(ctypes.byref(pr), p, 1) >= 16 * tiles + 8 * p * (G + 1) * tiles
     # depth 0: <psi0|Q|psi0> only
     assert [x.kind for x in _xy_plan(lib, pr, 0, 0)] == [7, 8]
+
+
+# ------------------------------------------------------------ streaming probe
+def test_stream_probe_rejects_bad_arguments():
+    """The probe built with the library checks its arguments before touching
+    the GPU: n outside 13..31 (13..30 with -2, two vectors) and tiles that do
+    not fit the register exit with status 2 and a message."""
+    import subprocess
+
+    exe = os.path.join(ROOT, "paper_2110_03963_amd", "stream_probe")
+    if not os.path.exists(exe):
+        pytest.skip("probe not built")
+    for args, msg in [(["40"], "n must be in 13..31"), (["-2", "31"], "n must be in 13..30"),
+                      (["28", "4", "30"], "bad tile"), (["28", "2", "12"], "bad tile"),
+                      (["-2", "20", "12", "11"], "bad tile")]:
+        res = subprocess.run([exe] + args, capture_output=True, text=True, timeout=30)
+        assert res.returncode == 2 and msg in res.stderr, (args, res.returncode, res.stderr)
