@@ -614,8 +614,8 @@ __device__ __forceinline__ void gradx_tile(const GradPassParams& P, int64_t tile
             // the forward pass applied the layer's scalar factor together with
             // the phase; the direct-form inverse rotations need none
             if constexpr (zterms) {
-                // the mixer slot first: its sum is then taken here, not
-                // deferred past the term loop with every rotation's operands
+                // the mixer slot first (its block sum is taken before the
+                // phase; the phase's own per-term sums come from zslot_tile)
                 write_slot(P.slot_t1, a1, red, tile);
                 // register by register the inverse phase on both vectors and
                 // Im(conj(chi) phi) in place of the angle (taken after the
