@@ -207,20 +207,26 @@ def test_ring_p1_closed_form_full_size():
     assert abs(dt.item() - n * math.cos(4 * tt) * math.sin(2 * gam)) < 1e-10 * n
 
 
-def test_ring_light_cone_gradient_full_size():
-    """n = 30, unweighted ring, p = 3: f/n and grad/n equal the oracle's at n = 8."""
+@pytest.mark.parametrize("n", [29, 30, 31])
+def test_ring_light_cone_gradient_full_size(n):
+    """Unweighted ring, p = 3: f/n and grad/n equal the oracle's at n = 8.
+    n = 29 has one 3-column and one 4-column strided group, n = 30 two
+    3-column groups (rotation of element bit 3 across lanes), n = 31 three
+    strided groups."""
     p = 3
     rng = np.random.default_rng(12)
     g = rng.uniform(0, math.pi, p)
     t = rng.uniform(0, math.pi, p)
     ns = 2 * p + 2
     f_s, g_s, t_s = oracle.grad("x", oracle.maxcut_quality_loop(ns, ring_edges(ns)), g, t)
-    n = 30
+    print(f"ring light cone gradient n={n}", flush=True)
     prob = qva.Problem(ring_cut_qualities_device(n, "cuda"), "x")
     f, dg, dt = qva.grad(prob, g, t)
     assert abs(f.item() / n - f_s / ns) < 1e-12 * abs(f_s / ns)
     err = _gerr(dg.cpu().numpy() / n, dt.cpu().numpy() / n, g_s / ns, t_s / ns)
     assert err < G_TOL
+    del prob
+    torch.cuda.empty_cache()
 
 
 def test_ring_light_cone_gradient_max_size():
