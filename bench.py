@@ -188,6 +188,54 @@ def read_counter_csv(folder: str, counter: str) -> dict:
     return out
 
 
+VALU_COUNTERS = ("SQ_INSTS_VALU", "SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_FMA_F64")
+
+
+def valu_summary(counter_dir: str, stats_csv: str) -> int:
+    """Vector-ALU load of each kernel: per-dispatch means of the SQ_INSTS_VALU*
+    counters (wave instructions, whole GPU) from a `rocprofv3 --pmc` run, with
+    the kernel's average duration from a `--kernel-trace --stats` run of the
+    same command.  FP64 flops = 64 lanes x (add + mul + 2 fma); the issue time
+    of the VALU instructions is 4 cycles per wave instruction (16 lanes per
+    SIMD) spread over 1024 SIMDs at 2.4 GHz; both are shown against the
+    kernel's duration (FP64 vector peak 78.6 TFLOP/s)."""
+    import csv
+    import glob
+    import re
+
+    def key(name: str) -> str:
+        m = re.search(r"(\w+_kernel<[^>]*>|\w+_kernel)\(", name.replace("(anonymous namespace)::", ""))
+        return m.group(1) if m else name[:60]
+
+    vals: dict = {}
+    for fn in glob.glob(os.path.join(counter_dir, "**", "*counter_collection.csv"), recursive=True):
+        with open(fn, newline="") as fh:
+            for row in csv.DictReader(fh):
+                if row.get("Counter_Name") in VALU_COUNTERS:
+                    vals.setdefault(key(row["Kernel_Name"]), {}).setdefault(row["Counter_Name"], []).append(
+                        float(row["Counter_Value"]))
+    dur = {}
+    with open(stats_csv, newline="") as fh:
+        for row in csv.DictReader(fh):
+            dur[key(row["Name"])] = float(row["AverageNs"]) * 1e-9
+    rows = []
+    for k, cs in vals.items():
+        if k not in dur or "SQ_INSTS_VALU" not in cs:
+            continue
+        m = {c: sum(v) / len(v) for c, v in cs.items()}
+        t = dur[k]
+        flops = 64.0 * (m.get("SQ_INSTS_VALU_ADD_F64", 0) + m.get("SQ_INSTS_VALU_MUL_F64", 0)
+                        + 2 * m.get("SQ_INSTS_VALU_FMA_F64", 0))
+        issue = m["SQ_INSTS_VALU"] * 4 / (1024 * 2.4e9)
+        rows.append({"kernel": k, "dispatches": len(cs["SQ_INSTS_VALU"]), "avg_ms": round(t * 1e3, 4),
+                     "valu_wave_instructions": round(m["SQ_INSTS_VALU"]),
+                     "fp64_tflops": round(flops / t / 1e12, 2), "fp64_frac_of_peak": round(flops / t / 78.6e12, 3),
+                     "valu_issue_ms": round(issue * 1e3, 4), "valu_issue_frac": round(issue / t, 3)})
+    rows.sort(key=lambda r: -r["avg_ms"] * r["dispatches"])
+    print(json.dumps(rows, indent=1))
+    return 0
+
+
 def pmc_pass() -> int:
     """The program profiled by the two counter runs: one calibration copy of
     known size, one standalone phase (reads psi and q, writes psi), then two
@@ -785,11 +833,15 @@ def main() -> int:
                     help="run the short program profiled by the HBM-traffic counter runs")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="store per-launch HBM traffic from the two counter runs' CSV output")
+    ap.add_argument("--valu-summary", nargs=2, metavar=("COUNTER_DIR", "KERNEL_STATS_CSV"),
+                    help="per-kernel VALU load from a --pmc SQ_INSTS_VALU* run and a --stats run")
     ap.add_argument("--extra", choices=sorted(EXTRAS),
                     help="run one secondary measurement alone and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.write_traffic:
         return write_traffic(*args.write_traffic)
+    if args.valu_summary:
+        return valu_summary(*args.valu_summary)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the sharded multi-GPU path is a design, not part of this build)", file=sys.stderr)
