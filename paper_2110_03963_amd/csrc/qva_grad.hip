@@ -43,7 +43,7 @@ __global__ __launch_bounds__(kThreads, QVA_GRADX_WAVES) void gradx_kernel(GradPa
 {
     __shared__ double2 lds[1 << kTileBits];
     __shared__ double red[4 * (kThreads / 64)];
-    gradx_tile<C, MODE>(P, blockIdx.x, lds, red);
+    gradx_tile<C, MODE>(P, C == 3 ? paired_tile(blockIdx.x) : (int64_t)blockIdx.x, lds, red);
 }
 
 // The extended-QAOA phase passes hold the Z-string angles beside both
@@ -57,7 +57,7 @@ __global__ __launch_bounds__(kThreads, QVA_GRADZ_WAVES) void gradxz_kernel(GradP
 {
     __shared__ double2 lds[1 << kTileBits];
     __shared__ double red[4 * (kThreads / 64)];
-    gradx_tile<C, MODE>(P, blockIdx.x, lds, red);
+    gradx_tile<C, MODE>(P, C == 3 ? paired_tile(blockIdx.x) : (int64_t)blockIdx.x, lds, red);
 }
 
 // Per-term slots of an extended-QAOA phase from the values its backward pass

@@ -479,6 +479,17 @@ __device__ __forceinline__ void mix_reverse(double2 (&v)[kRegs], double2* lds, i
     rotate_regs<target_mask<C, LA>(), TAN>(v, k);
 }
 
+// Tile of workgroup b when two neighbouring tiles share cache lines of q (3
+// column bits: a tile's q row is 64 bytes, half of a 128-byte line, the other
+// half in the tile with the next column chunk).  Workgroups go to the eight
+// XCDs round-robin, so workgroups b and b + 8 run back to back on the same
+// XCD: b = 16 m + 8 h + x gets tile 16 m + 2 x + h, and both halves of each
+// line are read through the same L2.  A bijection of [0, 16 M).
+__device__ __forceinline__ int64_t paired_tile(int64_t b)
+{
+    return (b & ~int64_t(15)) | ((b & 7) << 1) | ((b >> 3) & 1);
+}
+
 __device__ __forceinline__ TileMap tile_map(int64_t tile, int k, int C)
 {
     TileMap g;

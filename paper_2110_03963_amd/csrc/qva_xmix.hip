@@ -27,7 +27,7 @@ __global__ __launch_bounds__(kThreads, 2) void xpass_kernel(XPassParams P)
 {
     __shared__ double2 lds[1 << kTileBits];
     __shared__ double red[2 * (kThreads / 64)];
-    xpass_tile<C, FLAGS>(P, blockIdx.x, lds, red);
+    xpass_tile<C, FLAGS>(P, C == 3 ? paired_tile(blockIdx.x) : (int64_t)blockIdx.x, lds, red);
 }
 
 // ---------------------------------------------------------------------------

@@ -27,11 +27,21 @@
         }                                                                           \
     } while (0)
 
+// Workgroup -> tile as in the passes: with 3 column bits neighbouring tiles
+// share the 128-byte lines of q, so workgroups b and b + 8 (back to back on
+// one XCD) take the two tiles of a pair (grids of at least 16 workgroups).
+__device__ __forceinline__ long tile_of(long b, int C)
+{
+    if (C != 3 || (gridDim.x & 15))
+        return b;
+    return (b & ~15L) | ((b & 7) << 1) | ((b >> 3) & 1);
+}
+
 // Two vectors: each register's psi, chi and q are requested together.
 __global__ __launch_bounds__(256) void tile_stream2(double2* psi, double2* chi, const double* q, int C, int k)
 {
     constexpr int R = 16;
-    const long tile = blockIdx.x;
+    const long tile = tile_of(blockIdx.x, C);
     const int lobits = k - C;
     const long base = ((tile & ((1L << lobits) - 1)) << C) | ((tile >> lobits) << (k + 12 - C));
     const int t = threadIdx.x;
@@ -61,7 +71,7 @@ __global__ __launch_bounds__(256) void tile_stream2(double2* psi, double2* chi, 
 __global__ __launch_bounds__(256) void tile_stream(double2* psi, const double* q, int C, int k)
 {
     constexpr int R = 16;
-    const long tile = blockIdx.x;
+    const long tile = tile_of(blockIdx.x, C);
     const int lobits = k - C;
     const long base = ((tile & ((1L << lobits) - 1)) << C) | ((tile >> lobits) << (k + 12 - C));
     const int t = threadIdx.x;
