@@ -38,10 +38,12 @@ _lib = None
 
 
 def build(force: bool = True) -> str:
-    """Compile qva_oracle.c with gcc (-O2, IEEE semantics, no fast-math)."""
+    """Compile qva_oracle.c with gcc (-O2, IEEE semantics, no fast-math,
+    OpenMP over the independent loops only: results do not depend on the
+    thread count)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math", "-fopenmp",
                "-o", tmp, _SRC, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
@@ -90,6 +92,8 @@ def _load():
     lib.oracle_evolve_xy.restype = Ci
     lib.oracle_grad_xy.argtypes = [Ci, P, P, Ci, P, Ci, P, P, P, P, P]
     lib.oracle_grad_xy.restype = Ci
+    lib.oracle_set_threads.argtypes = [Ci]
+    lib.oracle_get_threads.restype = Ci
     _lib = lib
     return lib
 
@@ -111,6 +115,15 @@ def _log2(N: int) -> int:
     if (1 << n) != N:
         raise ValueError(f"N={N} is not a power of two")
     return n
+
+
+def set_threads(n: int) -> None:
+    """Threads for the oracle's independent loops (sums stay single-threaded)."""
+    _load().oracle_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(_load().oracle_get_threads())
 
 
 # ----------------------------------------------------------------- primitives

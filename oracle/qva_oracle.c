@@ -36,12 +36,21 @@
  * Everything is double / double complex, straightforward loops, library
  * cos/sin/cexp, pairwise summation for every sum over the state.  No blocking,
  * fusion or reordering beyond what the definitions state.
+ *
+ * Threads (OpenMP, only for timing on many cores): loops whose iterations are
+ * independent and each write their own elements -- elementwise maps, the
+ * pairs of one rotation, the butterflies of one FFT stage -- are split over
+ * threads.  Every sum stays a single-threaded pairwise sum, so the results are
+ * bit-identical at any thread count.
  */
 #include <complex.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef double complex cplx;
 
@@ -49,6 +58,25 @@ typedef double complex cplx;
 static const double PI = 3.14159265358979323846264338327950288;
 
 enum { ORACLE_MIX_X = 0, ORACLE_MIX_CIRCULANT = 1, ORACLE_MIX_COMPLETE = 2 };
+
+/* Number of threads for the parallel loops (1 without OpenMP). */
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}
+
+int oracle_get_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ---------------------------------------------------------------------- */
 /* Pairwise (recursive halving) summation.                                 */
@@ -89,6 +117,7 @@ static double pairwise_sum_fn(term_fn term, const void *ctx, int64_t lo, int64_t
 void oracle_init_uniform(int64_t N, cplx *psi)
 {
     double a = 1.0 / sqrt((double)N);
+#pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < N; ++j)
         psi[j] = a;
 }
@@ -100,6 +129,7 @@ void oracle_init_uniform(int64_t N, cplx *psi)
 
 void oracle_phase(int64_t N, cplx *psi, const double *q, double gamma)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < N; ++j)
         psi[j] *= cexp(-I * gamma * q[j]);
 }
@@ -121,6 +151,7 @@ static double zterm(int64_t j, uint64_t S, double c)
 void oracle_phase_terms(int64_t N, cplx *psi, int n_terms, const uint64_t *S, const double *c,
                         const double *gamma)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < N; ++j) {
         double ph = 0.0;
         for (int e = 0; e < n_terms; ++e)
@@ -141,6 +172,8 @@ void oracle_mix_x(int n, cplx *psi, double t)
     double c = cos(t), s = sin(t);
     for (int i = 0; i < n; ++i) {
         int64_t bit = (int64_t)1 << i;
+        /* iteration j (bit i clear) alone touches the pair (j, j | bit) */
+        #pragma omp parallel for schedule(static)
         for (int64_t j = 0; j < N; ++j) {
             if (j & bit)
                 continue;
@@ -155,6 +188,7 @@ void oracle_mix_x(int n, cplx *psi, double t)
 void oracle_apply_hypercube(int n, const cplx *psi, cplx *out)
 {
     int64_t N = (int64_t)1 << n;
+#pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < N; ++j) {
         cplx acc = 0.0;
         for (int i = 0; i < n; ++i)
@@ -212,7 +246,8 @@ void oracle_fft(int64_t N, cplx *x, int sign)
     int lg = 0;
     while (((int64_t)1 << lg) < N)
         ++lg;
-    /* bit reversal permutation */
+    /* bit reversal permutation (iteration j alone swaps the pair j < r) */
+#pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < N; ++j) {
         int64_t r = 0;
         for (int b = 0; b < lg; ++b)
@@ -225,18 +260,21 @@ void oracle_fft(int64_t N, cplx *x, int sign)
         }
     }
     cplx *w = malloc(sizeof(cplx) * (size_t)(N / 2));
+#pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < N / 2; ++k)
         w[k] = root_of_unity(k, N, sign);
     for (int64_t len = 2; len <= N; len <<= 1) {
         int64_t half = len / 2;
         int64_t step = N / len; /* twiddle for butterfly k is w[k * step] */
-        for (int64_t start = 0; start < N; start += len) {
-            for (int64_t k = 0; k < half; ++k) {
-                cplx u = x[start + k];
-                cplx v = x[start + k + half] * w[k * step];
-                x[start + k] = u + v;
-                x[start + k + half] = u - v;
-            }
+        /* the N/2 butterflies of a stage, b = (block, k): block start
+         * (b / half) * len, offset k = b % half; each owns its two elements */
+        #pragma omp parallel for schedule(static)
+        for (int64_t b = 0; b < N / 2; ++b) {
+            const int64_t start = (b / half) * len, k = b % half;
+            cplx u = x[start + k];
+            cplx v = x[start + k + half] * w[k * step];
+            x[start + k] = u + v;
+            x[start + k + half] = u - v;
         }
     }
     free(w);
@@ -256,20 +294,25 @@ void oracle_bluestein(int64_t N, cplx *x, int sign)
     cplx *u = malloc(sizeof(cplx) * (size_t)N);
     cplx *a = calloc((size_t)M, sizeof(cplx));
     cplx *v = calloc((size_t)M, sizeof(cplx));
+#pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < N; ++k) {
         const int64_t r = (int64_t)(((uint64_t)k * (uint64_t)k) % (uint64_t)(2 * N));
         u[k] = cexp((double)sign * I * PI * (double)r / (double)N);
     }
+#pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < N; ++j)
         a[j] = x[j] * u[j];
     v[0] = conj(u[0]);
+#pragma omp parallel for schedule(static)
     for (int64_t k = 1; k < N; ++k)
         v[k] = v[M - k] = conj(u[k]);
     oracle_fft(M, a, -1);
     oracle_fft(M, v, -1);
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < M; ++i)
         a[i] *= v[i];
     oracle_fft(M, a, +1);
+#pragma omp parallel for schedule(static)
     for (int64_t m = 0; m < N; ++m)
         x[m] = u[m] * a[m] / (double)M;
     free(u);
@@ -301,9 +344,11 @@ static void transform(int64_t N, cplx *x, int sign)
 void oracle_mix_circulant(int64_t N, cplx *psi, const double *lambda, double t)
 {
     transform(N, psi, -1);
+#pragma omp parallel for schedule(static)
     for (int64_t m = 0; m < N; ++m)
         psi[m] *= cexp(-I * t * lambda[m]);
     transform(N, psi, +1);
+#pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < N; ++j)
         psi[j] /= (double)N;
 }
@@ -313,9 +358,11 @@ void oracle_apply_circulant(int64_t N, const cplx *psi, const double *lambda, cp
 {
     memcpy(out, psi, sizeof(cplx) * (size_t)N);
     transform(N, out, -1);
+#pragma omp parallel for schedule(static)
     for (int64_t m = 0; m < N; ++m)
         out[m] *= lambda[m];
     transform(N, out, +1);
+#pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < N; ++j)
         out[j] /= (double)N;
 }
@@ -341,6 +388,7 @@ void oracle_mix_complete(int64_t N, cplx *psi, double t)
     const cplx S = state_sum(N, psi);
     const cplx c = (cexp(-I * (t * (double)N)) - 1.0) / (double)N;
     const cplx e = cexp(I * t);
+#pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < N; ++j)
         psi[j] = e * (psi[j] + c * S);
 }
@@ -348,6 +396,7 @@ void oracle_mix_complete(int64_t N, cplx *psi, double t)
 void oracle_apply_complete(int64_t N, const cplx *psi, cplx *out)
 {
     const cplx S = state_sum(N, psi);
+#pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < N; ++j)
         out[j] = S - psi[j];
 }
@@ -513,6 +562,7 @@ int oracle_grad(int kind, int64_t N, const double *q, const double *lambda, int 
     cplx *chi = malloc(sizeof(cplx) * (size_t)N);
     cplx *wphi = malloc(sizeof(cplx) * (size_t)N);
     oracle_evolve(kind, N, q, lambda, p, gammas, ts, phi, f, NULL);
+#pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < N; ++j)
         chi[j] = q[j] * phi[j];
     for (int k = p - 1; k >= 0; --k) {
@@ -575,6 +625,7 @@ int oracle_grad_terms(int64_t N, const double *q, int n_terms, const uint64_t *S
     cplx *wphi = malloc(sizeof(cplx) * (size_t)N);
     double *neg = malloc(sizeof(double) * (size_t)(n_terms > 0 ? n_terms : 1));
     oracle_evolve_terms(N, q, n_terms, S, c, p, gammas, ts, phi, f, NULL);
+#pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < N; ++j)
         chi[j] = q[j] * phi[j];
     for (int k = p - 1; k >= 0; --k) {
@@ -658,6 +709,8 @@ static void xy_rotate(int n, cplx *psi, int a, int b, double t)
 {
     const int64_t N = (int64_t)1 << n, ma = (int64_t)1 << a, mb = (int64_t)1 << b;
     const double c = cos(2.0 * t), s = sin(2.0 * t);
+    /* iteration j (bit a set, bit b clear) alone touches the pair (j, k) */
+#pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < N; ++j) {
         if ((j & ma) && !(j & mb)) {
             const int64_t k = j ^ ma ^ mb;
@@ -672,6 +725,7 @@ static void xy_rotate(int n, cplx *psi, int a, int b, double t)
 static void xy_apply(int n, const cplx *psi, int a, int b, cplx *out)
 {
     const int64_t N = (int64_t)1 << n, ma = (int64_t)1 << a, mb = (int64_t)1 << b;
+#pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < N; ++j) {
         const int ba = (j & ma) != 0, bb = (j & mb) != 0;
         out[j] = ba != bb ? 2.0 * psi[j ^ ma ^ mb] : 0.0;
@@ -756,6 +810,7 @@ int oracle_grad_xy(int n, const double *q, const cplx *psi0, int n_pairs, const 
     cplx *chi = malloc(sizeof(cplx) * (size_t)N);
     cplx *hphi = malloc(sizeof(cplx) * (size_t)N);
     oracle_evolve_xy(n, q, psi0, n_pairs, pairs, p, gammas, ts, phi, f, NULL);
+#pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < N; ++j)
         chi[j] = q[j] * phi[j];
     for (int k = p - 1; k >= 0; --k) {
