@@ -117,8 +117,8 @@ class Problem:
     mixer "circulant": W circulant with eigenvalues lam (natural order) or
     lambda_kind "ring" / "complete".  A circulant may have any N >= 2 (the
     solution count of a constrained problem): closed-form passes for the
-    complete graph, Bluestein's transform for the ring or an array (forward
-    only).  The hypercube mixer needs a power of two.
+    complete graph, Bluestein's transform for the ring or an array (both
+    evolve and grad).  The hypercube mixer needs a power of two.
 
     terms (hypercube mixer only): the extended QAOA, one phase angle per term
     of a Z-string decomposition of the cost, given as (supports, coefs) with
@@ -264,6 +264,8 @@ def grad(problem: Problem, gammas, ts, psi: torch.Tensor | None = None,
         chi = torch.empty(problem.N, dtype=torch.complex128, device=dev)
     _need(psi, torch.complex128, "psi")
     _need(chi, torch.complex128, "chi")
+    if psi.numel() != problem.N or chi.numel() != problem.N:
+        raise ValueError("psi and chi must hold N amplitudes each")
     if problem.psi0 is not None:
         psi.copy_(problem.psi0)
     lib = _lib.load()

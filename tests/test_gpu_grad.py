@@ -149,8 +149,57 @@ def test_grad_matches_bruteforce_tiled():
     assert _gerr(dg, dt, bg, bt) < G_TOL
 
 
+def _central_differences(prob, g, t, h=1e-5):
+    """Central differences of the GPU forward, with the step actually taken,
+    (x + h) - (x - h), as the denominator."""
+    p = len(g)
+    fd = []
+    for which in (0, 1):
+        for k in range(p):
+            gp, gm, tp, tm = g.copy(), g.copy(), t.copy(), t.copy()
+            if which == 0:
+                gp[k] += h
+                gm[k] -= h
+                step = gp[k] - gm[k]
+            else:
+                tp[k] += h
+                tm[k] -= h
+                step = tp[k] - tm[k]
+            fp = qva.evolve(prob, gp, tp, store=False)[0].item()
+            fm = qva.evolve(prob, gm, tm, store=False)[0].item()
+            fd.append((fp - fm) / step)
+    return np.array(fd)
+
+
+def test_c4_weighted_n30_p12_adjoint_vs_central_differences():
+    """The adjoint workload at full size: weighted random 3-regular MaxCut,
+    n = 30, p = 12 (24 parameters).  The adjoint gradient against central
+    differences of the GPU forward with h = 1e-5:
+    max |g_adj - g_fd| <= 1e-8 max |g_adj|."""
+    from workloads import maxcut_qualities_device
+
+    n, p = 30, 12
+    print("adjoint n=30 p=12 vs central differences", flush=True)
+    wl = qaoa_maxcut_workload(n, p, graph="regular3", weighted=True, seed=CONFIG_SEEDS["grad_n30"],
+                              build_q=False)
+    prob = qva.Problem(maxcut_qualities_device(n, wl.edges, wl.weights, "cuda"), "x")
+    g = np.asarray(wl.gammas, np.float64)
+    t = np.asarray(wl.ts, np.float64)
+    f, dg, dt = qva.grad(prob, g, t)
+    ad = np.concatenate([dg.cpu().numpy(), dt.cpu().numpy()])
+    torch.cuda.empty_cache()  # the forward needs one state, not two
+    fd = _central_differences(prob, g, t)
+    rel = float(np.max(np.abs(ad - fd)) / np.max(np.abs(ad)))
+    print(f"  max |g_adj - g_fd| / max |g_adj| = {rel:.3e}", flush=True)
+    assert rel <= 1e-8, rel
+    f_ev = qva.evolve(prob, g, t, store=False)[0].item()
+    assert abs(f.item() - f_ev) <= 1e-13 * abs(f_ev)
+    del prob
+    torch.cuda.empty_cache()
+
+
 def test_grad_vs_central_differences_gpu():
-    """Central differences of the GPU forward (h = 1e-5) agree to ~1e-8."""
+    """Central differences of the GPU forward (h = 1e-5) agree to 1e-8."""
     rng = np.random.default_rng(4)
     n, p = 16, 3
     q = rng.uniform(0, 3, 1 << n)
@@ -158,21 +207,9 @@ def test_grad_vs_central_differences_gpu():
     t = rng.uniform(0, math.pi, p)
     prob = qva.Problem(to_dev(q), "x")
     _, dg, dt = qva.grad(prob, g, t)
-    h = 1e-5
-    fd = []
-    for arr, which in [(g, 0), (t, 1)]:
-        for k in range(p):
-            e = np.zeros(p)
-            e[k] = h
-            if which == 0:
-                fp = qva.evolve(prob, g + e, t, store=False)[0].item()
-                fm = qva.evolve(prob, g - e, t, store=False)[0].item()
-            else:
-                fp = qva.evolve(prob, g, t + e, store=False)[0].item()
-                fm = qva.evolve(prob, g, t - e, store=False)[0].item()
-            fd.append((fp - fm) / (2 * h))
+    fd = _central_differences(prob, g, t)
     ad = np.concatenate([dg.cpu().numpy(), dt.cpu().numpy()])
-    assert np.max(np.abs(ad - np.array(fd))) < 1e-7 * np.max(np.abs(ad))
+    assert np.max(np.abs(ad - fd)) <= 1e-8 * np.max(np.abs(ad))
 
 
 def test_grad_f_equals_evolve_f():

@@ -58,3 +58,31 @@ def test_ring_digit_pairs_differ_by_eight():
             l0 = 2 * (u * w0.conjugate()).real
             l1 = 2 * (u * w1.conjugate()).real
             assert abs(l0 + l1) < 1e-14
+
+
+def test_grad_rejects_short_state_before_any_launch(monkeypatch):
+    """grad() checks that psi and chi hold N amplitudes before it calls the
+    library (qva_grad writes N amplitudes into both)."""
+    import torch
+
+    import paper_2110_03963_amd.qva as qmod
+
+    def no_library():
+        raise AssertionError("the library was called")
+
+    monkeypatch.setattr(qmod, "_need", lambda t, dtype, name: None)
+    monkeypatch.setattr(qmod._lib, "load", no_library)
+    prob = object.__new__(qmod.Problem)
+    prob._N = 16
+    prob.q = torch.zeros(16, dtype=torch.float64)
+    prob.n_terms = 0
+    prob.psi0 = None
+    good = torch.zeros(16, dtype=torch.complex128)
+    short = torch.zeros(15, dtype=torch.complex128)
+    for psi, chi in ((short, good), (good, short), (short, short)):
+        try:
+            qmod.grad(prob, [0.1], [0.2], psi=psi, chi=chi)
+        except ValueError as e:
+            assert "N amplitudes" in str(e)
+        else:
+            raise AssertionError("no ValueError for a short psi/chi")
