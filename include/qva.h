@@ -55,7 +55,9 @@ typedef enum {
     QVA_ERR_ALIGN = -3,       /* misaligned device pointer                   */
     QVA_ERR_WORKSPACE = -4,   /* workspace missing or smaller than required  */
     QVA_ERR_HIP = -5,         /* a HIP launch or runtime call failed         */
-    QVA_ERR_UNSUPPORTED = -6  /* well-formed request this build cannot serve */
+    QVA_ERR_UNSUPPORTED = -6, /* well-formed request this build cannot serve */
+    QVA_ERR_SCRATCH = -7      /* qva_evolve_noalloc: the request needs more
+                                 workspace than QVA_STATIC_SCRATCH_BYTES      */
 } qva_status;
 
 typedef enum {
@@ -197,6 +199,31 @@ int qva_expectation(const qva_c128 *psi, const double *q, int64_t N, double *out
 int qva_evolve(const qva_problem *P, const double *gammas_dev, const double *ts_dev, int p,
                qva_c128 *psi, double *out_f_dev, double *out_norm_dev, int flags, void *work,
                size_t work_bytes, void *stream);
+
+/* Size of the library's static per-device workspace (16 MiB). */
+#define QVA_STATIC_SCRATCH_BYTES ((size_t)16 << 20)
+
+/* qva_evolve without a caller workspace, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, results and launches as qva_evolve;
+ * the workspace is a QVA_STATIC_SCRATCH_BYTES array inside the library, one
+ * per GPU, held until the process ends.  Nothing is allocated by the call.
+ *   - A request whose qva_workspace_bytes(P, p, 0) exceeds
+ *     QVA_STATIC_SCRATCH_BYTES returns QVA_ERR_SCRATCH and launches nothing
+ *     (e.g. the hypercube mixer up to n_qubits = 32, the ring circulant up to
+ *     2^32 states; an eigenvalue array or Bluestein's padded buffers only for
+ *     small N).  Argument errors are reported as by qva_evolve.
+ *   - The array belongs to the GPU of `stream` (the current device for the
+ *     NULL stream); its device address is looked up once per GPU, on the
+ *     first call there (QVA_ERR_HIP if that lookup fails).
+ *   - All calls on one GPU share that GPU's array: calls that overlap in time
+ *     on one GPU (different streams, or different host threads without
+ *     ordering) race and give wrong results.  Calls on one stream are safe.
+ *     Every byte the evolution reads from the array is written earlier in the
+ *     same call, so contents left by a previous call never matter. */
+int qva_evolve_noalloc(const qva_problem *P, const double *gammas_dev, const double *ts_dev, int p,
+                       qva_c128 *psi, double *out_f_dev, double *out_norm_dev, int flags,
+                       void *stream);
 
 /* f and its gradient by the adjoint method: df/dtheta_l = 2 Im <chi_l|H_l|phi_l>
  * with phi_l the state after unitary l and chi_l = U_{l+1}^dag...U_2p^dag Q psi_p,

@@ -11,6 +11,7 @@ from .qva import (  # noqa: F401
     Problem,
     QVAExpectation,
     evolve,
+    evolve_noalloc,
     expectation,
     expectation_value,
     grad,

@@ -20,6 +20,7 @@ QVA_ERR_ALIGN = -3
 QVA_ERR_WORKSPACE = -4
 QVA_ERR_HIP = -5
 QVA_ERR_UNSUPPORTED = -6
+QVA_ERR_SCRATCH = -7
 
 QVA_MIX_X = 0
 QVA_MIX_CIRCULANT = 1
@@ -31,6 +32,7 @@ QVA_MAX_QUBITS = 33
 QVA_MAX_TERMS = 1024
 QVA_MAX_XY_PAIRS = 256
 QVA_EVOLVE_SKIP_FINAL_STATE = 1
+QVA_STATIC_SCRATCH_BYTES = 16 << 20
 
 
 class QvaProblem(ctypes.Structure):
@@ -121,6 +123,7 @@ SIGNATURES = {
     "qva_expectation_workspace_bytes": (_SZ, [_I64]),
     "qva_expectation": (_I, [_P, _P, _I64, _P, _P, _P, _SZ, _P]),
     "qva_evolve": (_I, [_PROB, _P, _P, _I, _P, _P, _P, _I, _P, _SZ, _P]),
+    "qva_evolve_noalloc": (_I, [_PROB, _P, _P, _I, _P, _P, _P, _I, _P]),
     "qva_grad": (_I, [_PROB, _P, _P, _I, _P, _P, _P, _P, _P, _P, _SZ, _P]),
     "qva_plan": (_I, [_PROB, _I, _I, _I, ctypes.POINTER(QvaPassInfo), _I]),
     "qva_evolve_timed": (_I, [_PROB, _P, _P, _I, _P, _P, _P, _I, _P, _SZ,

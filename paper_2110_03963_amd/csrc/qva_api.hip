@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstddef>
 #include <cstring>
+#include <mutex>
 #include <stdint.h>
 #include <tuple>
 #include <vector>
@@ -1350,6 +1351,53 @@ int xy_run(const qva_problem* P, const double* gammas, const double* ts, int p, 
 
 }  // namespace
 
+// ------------------------------------------------- static per-device scratch
+// The workspace of qva_evolve_noalloc.  In host code `scratch` is only a
+// host-side stand-in for the symbol, never a device address: host code uses
+// the address hipGetSymbolAddress returns for each device (static_scratch).
+static __device__ __align__(256) unsigned char scratch[QVA_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices];
+
+// Device address of the scratch array of the GPU that `s` belongs to (the
+// current device for the NULL stream), looked up once per device with that
+// device current.
+int static_scratch(hipStream_t s, void** out)
+{
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess)
+        return QVA_ERR_HIP;
+    int dev = cur;
+    if (s) {
+        hipDevice_t d = 0;
+        if (hipStreamGetDevice(s, &d) != hipSuccess)
+            return QVA_ERR_HIP;
+        dev = d;
+    }
+    if (dev < 0 || dev >= kMaxScratchDevices)
+        return QVA_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        if (dev != cur && hipSetDevice(dev) != hipSuccess)
+            return QVA_ERR_HIP;
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (dev != cur)
+            (void)hipSetDevice(cur);
+        if (e != hipSuccess || !ptr)
+            return QVA_ERR_HIP;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return QVA_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* qva_status_string(int status)
@@ -1369,6 +1417,8 @@ const char* qva_status_string(int status)
         return "HIP launch or runtime error";
     case QVA_ERR_UNSUPPORTED:
         return "unsupported request";
+    case QVA_ERR_SCRATCH:
+        return "request needs more workspace than the static scratch holds";
     default:
         return "unknown status";
     }
@@ -1550,6 +1600,30 @@ int qva_evolve_timed(const qva_problem* P, const double* gammas_dev, const doubl
     hook.n = n_events;
     return evolve_common(P, gammas_dev, ts_dev, p, psi, out_f_dev, out_norm_dev, flags, work,
                          work_bytes, stream, hook);
+}
+
+int qva_evolve_noalloc(const qva_problem* P, const double* gammas_dev, const double* ts_dev, int p,
+                       qva_c128* psi, double* out_f_dev, double* out_norm_dev, int flags, void* stream)
+{
+    // argument errors first (as qva_evolve reports them), then the size limit,
+    // all before the device is touched
+    int st = check_problem(P, p);
+    if (st != QVA_OK)
+        return st;
+    if (!psi || !out_f_dev || (p > 0 && (!gammas_dev || !ts_dev)) || (flags & ~QVA_EVOLVE_SKIP_FINAL_STATE))
+        return QVA_ERR_ARG;
+    const size_t need = qva_workspace_bytes(P, p, 0);
+    if (need > QVA_STATIC_SCRATCH_BYTES)
+        return QVA_ERR_SCRATCH;
+    void* work = nullptr;
+    if (need) {
+        st = static_scratch(as_stream(stream), &work);
+        if (st != QVA_OK)
+            return st;
+    }
+    EventHook hook;
+    return evolve_common(P, gammas_dev, ts_dev, p, psi, out_f_dev, out_norm_dev, flags, work,
+                         need ? QVA_STATIC_SCRATCH_BYTES : 0, stream, hook);
 }
 
 int qva_plan(const qva_problem* P, int p, int for_grad, int flags, qva_pass_info* out, int max_out)

@@ -252,6 +252,29 @@ def evolve(problem: Problem, gammas, ts, psi: torch.Tensor | None = None, store:
     return out[0], out[1], psi
 
 
+def evolve_noalloc(problem: Problem, gammas, ts, psi: torch.Tensor, out: torch.Tensor,
+                   store: bool = True):
+    """evolve() through qva_evolve_noalloc: the library's static per-device
+    workspace instead of a caller one, so the call allocates nothing (for
+    code under graph capture).  psi (N complex128) and out (2 float64:
+    f, norm) are the caller's; angle tensors must already be float64 on the
+    device.  Calls that overlap in time on one GPU race (one shared array)."""
+    dev = problem.device
+    _need(psi, torch.complex128, "psi")
+    _need(out, torch.float64, "out")
+    if psi.numel() != problem.N or out.numel() < 2:
+        raise ValueError("psi must hold N amplitudes and out two doubles")
+    g, t, p = _layer_angles(problem, gammas, ts, dev)
+    if problem.psi0 is not None:
+        psi.copy_(problem.psi0)
+    flags = 0 if store else _lib.QVA_EVOLVE_SKIP_FINAL_STATE
+    _lib.check("qva_evolve_noalloc",
+               _lib.load().qva_evolve_noalloc(problem.cstruct(), g.data_ptr(), t.data_ptr(), p,
+                                              psi.data_ptr(), out.data_ptr(), out.data_ptr() + 8, flags,
+                                              _stream()))
+    return out[0], out[1], psi
+
+
 def grad(problem: Problem, gammas, ts, psi: torch.Tensor | None = None,
          chi: torch.Tensor | None = None, workspace: torch.Tensor | None = None):
     """(f, df/dgamma, df/dt) by the adjoint method (device tensors); with

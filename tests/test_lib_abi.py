@@ -41,7 +41,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_status_strings(lib):
-    for st in [0, -1, -2, -3, -4, -5, -6]:
+    for st in [0, -1, -2, -3, -4, -5, -6, -7]:
         assert lib.qva_status_string(st)
     assert lib.qva_status_string(-4) == b"workspace missing or too small"
     assert b"gfx950" in lib.qva_version()
@@ -594,3 +594,21 @@ def test_stream_probe_rejects_bad_arguments():
                       (["-2", "20", "12", "11"], "bad tile")]:
         res = subprocess.run([exe] + args, capture_output=True, text=True, timeout=30)
         assert res.returncode == 2 and msg in res.stderr, (args, res.returncode, res.stderr)
+
+def test_evolve_noalloc_validation(lib):
+    """qva_evolve_noalloc reports argument errors and the static-scratch limit
+    before it touches the device (fake pointers are never dereferenced)."""
+    S = _lib
+    ref = ctypes.byref
+    big = _prob(n=33)  # 2^21 tiles of partial sums: 32 MiB > 16 MiB
+    assert lib.qva_workspace_bytes(ref(big), 2, 0) > S.QVA_STATIC_SCRATCH_BYTES
+    assert lib.qva_evolve_noalloc(ref(big), FAKE, FAKE, 2, FAKE, FAKE, None, 0, None) == S.QVA_ERR_SCRATCH
+    ok = _prob(n=20)
+    assert lib.qva_workspace_bytes(ref(ok), 2, 0) <= S.QVA_STATIC_SCRATCH_BYTES
+    assert lib.qva_evolve_noalloc(ref(ok), FAKE, FAKE, 2, None, FAKE, None, 0, None) == S.QVA_ERR_ARG
+    assert lib.qva_evolve_noalloc(ref(ok), FAKE, FAKE, 2, FAKE, None, None, 0, None) == S.QVA_ERR_ARG
+    assert lib.qva_evolve_noalloc(ref(ok), None, FAKE, 2, FAKE, FAKE, None, 0, None) == S.QVA_ERR_ARG
+    assert lib.qva_evolve_noalloc(ref(ok), FAKE, FAKE, 2, FAKE, FAKE, None, 4, None) == S.QVA_ERR_ARG
+    assert lib.qva_evolve_noalloc(None, FAKE, FAKE, 2, FAKE, FAKE, None, 0, None) == S.QVA_ERR_ARG
+    assert lib.qva_evolve_noalloc(ref(_prob(n=34)), FAKE, FAKE, 2, FAKE, FAKE, None, 0, None) == S.QVA_ERR_SIZE
+    assert lib.qva_status_string(S.QVA_ERR_SCRATCH) == b"request needs more workspace than the static scratch holds"
