@@ -32,13 +32,17 @@ sys.path.insert(0, ROOT)
 METRIC = "layer-applications/s and HBM GB/s vs peak; adjoint gradients/s vs finite-diff"
 HBM_PEAK_GBS = 8000.0
 PROFILES = os.path.join(ROOT, "profiles")
-TRAFFIC_FILE = os.path.join(PROFILES, "xpass_traffic_qaoa_n28.json")
+TRAFFIC_FILE = os.path.join(PROFILES, "hbm_traffic_all_workloads.json")
+TRAFFIC_SUMMARY = os.path.join(PROFILES, "hbm_traffic_all_workloads.md")
 CSRC = os.path.join(ROOT, "paper_2110_03963_amd", "csrc")
-# Sources the hypercube-mixer passes are built and launched from: a stored
-# traffic measurement holds only while these are unchanged.
-TRAFFIC_SOURCES = [os.path.join(CSRC, f) for f in
-                   ("qva_xmix.hip", "qva_tile.h", "qva_passes.h", "qva_device.h", "qva_internal.h",
-                    "qva_plan.h", "qva_api.hip")]
+
+
+def traffic_sources() -> list:
+    """Every kernel source of the library: a stored traffic measurement holds
+    only while all of them are unchanged."""
+    import glob
+
+    return sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.h")))
 CALIB_ELEMS = 1 << 27  # calibration copy: 2^27 float64 = 1 GiB read + 1 GiB written
 
 
@@ -80,12 +84,6 @@ class HipEvents:
 
 MODE_NAMES = {1: "XMODE_FIRST", 2: "XMODE_MIDDLE", 3: "XMODE_BOUNDARY", 4: "XMODE_LAST",
               5: "XMODE_LAST_STORE"}
-# xpass_kernel's second template argument (pass flag bits) per mode, as the
-# profiler prints it.
-XMODE_FLAGS = {"XMODE_FIRST": 71, "XMODE_MIDDLE": 68, "XMODE_BOUNDARY": 92, "XMODE_LAST": 164,
-               "XMODE_LAST_STORE": 228, "XMODE_FIRST_Z": 327, "XMODE_BOUNDARY_Z": 348}
-
-
 def kernel_name(kind: int, col_bits: int) -> str:
     from paper_2110_03963_amd import _lib
 
@@ -147,45 +145,10 @@ def roofline_of(per: dict, steps: int) -> dict:
             "algorithmic_bytes_per_launch": bpl}
 
 
-def profiler_label(name: str) -> str | None:
-    """Map a profiler kernel name to the names used here: xpass kernels to
-    kernel_name()'s form, the runtime's device-to-device copy to "copy"."""
-    import re
-
-    if "copyBuffer" in name:
-        return "copy"
-    m = re.search(r"xpass_kernel<(\d+), (\d+)>", name)
-    if m:
-        flags = int(m.group(2))
-        for mode, v in XMODE_FLAGS.items():
-            if v == flags:
-                return f"xpass_kernel<{m.group(1)}, {mode}>"
-    for short in ("phase_kernel", "init_uniform_kernel"):
-        if f"::{short}(" in name:
-            return short
-    return None
-
-
-def read_counter_csv(folder: str, counter: str) -> dict:
-    """Per-dispatch values of one counter from rocprofv3's counter_collection
-    CSV(s) under `folder`: {label: [value, ...]} (values in the counter's
-    unit, KiB for FETCH_SIZE / WRITE_SIZE)."""
-    import csv
-    import glob
-
-    files = glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True)
-    if not files:
-        raise FileNotFoundError(f"no counter_collection.csv under {folder}")
-    out: dict[str, list] = {}
-    for fn in files:
-        with open(fn, newline="") as fh:
-            for row in csv.DictReader(fh):
-                if row.get("Counter_Name") != counter:
-                    continue
-                label = profiler_label(row.get("Kernel_Name", ""))
-                if label:
-                    out.setdefault(label, []).append(float(row["Counter_Value"]))
-    return out
+def with_traffic(roof: dict, workload: str, call: str) -> dict:
+    """roof with `traffic` filled from the stored counter runs (or None)."""
+    roof["traffic"] = stored_traffic(workload, call, roof["kernel"])
+    return roof
 
 
 VALU_COUNTERS = ("SQ_INSTS_VALU", "SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_FMA_F64")
@@ -236,91 +199,295 @@ def valu_summary(counter_dir: str, stats_csv: str) -> int:
     return 0
 
 
-def pmc_pass() -> int:
+# Workloads whose every launch is measured by the HBM-traffic counter runs:
+# (workload name as the bench reports it, call).
+PMC_SEGMENTS = [
+    ("qaoa_maxcut_n28_p8", "evolve"),
+    ("qwoa_portfolio_n26_p6_ring", "evolve"),
+    ("qwoa_portfolio_n26_p6_complete", "evolve"),
+    ("qwoa_portfolio_m26_k13_p6_ring", "evolve"),
+    ("qwoa_portfolio_m26_k13_p6_complete", "evolve"),
+    ("adjoint_qaoa_maxcut_n30_p12", "grad"),
+    ("adjoint_qwoa_portfolio_n26_p6_complete", "grad"),
+    ("adjoint_qwoa_portfolio_m26_k13_p6_ring", "grad"),
+    ("exqaoa_maxcut_n28_p8_regular3", "evolve"),
+    ("exqaoa_maxcut_n28_p8_regular3", "grad"),
+    ("qaoaz_portfolio_m26_k13_p6_ring", "evolve"),
+    ("qaoaz_portfolio_m26_k13_p6_ring", "grad"),
+]
+
+# Kernel families each plan-launch kind dispatches (checked against the
+# counter runs' kernel names, so the launches and dispatches stay aligned).
+KIND_FAMILIES = {0: ("small_kernel", "small_fft_kernel"), 6: ("init_uniform_kernel",),
+                 7: ("expect_partial_kernel",), 8: ("final_reduce_kernel",), 16: ("lambda_tile_kernel",),
+                 17: ("small_grad_kernel",), 24: ("gradf_kernel",),
+                 25: ("slot_reduce_kernel", "grad_finalize_kernel"), 30: ("final_reduce_kernel",),
+                 31: ("complete_grad_kernel",), 32: ("complete_grad_kernel",), 33: ("complete_gsum_kernel",),
+                 42: ("xypass_kernel",), 43: ("xypass_kernel",), 44: ("xypass_kernel",),
+                 45: ("xygrad_kernel",), 50: ("zslot_kernel",), 51: ("twiddle_table_kernel",)}
+for _k in range(1, 6):
+    KIND_FAMILIES[_k] = ("xpass_kernel",)
+for _k in list(range(9, 16)) + [22, 23] + list(range(34, 42)):
+    KIND_FAMILIES[_k] = ("fftpass_kernel",)
+for _k in range(18, 22):
+    KIND_FAMILIES[_k] = ("gradx_kernel", "gradxz_kernel", "gradf_kernel")
+for _k in range(26, 30):
+    KIND_FAMILIES[_k] = ("complete_kernel",)
+for _k in range(46, 50):
+    KIND_FAMILIES[_k] = ("gradb_kernel",)
+
+
+def zterm_label(name: str) -> str:
+    """Bench label of a pass of the extended-QAOA plan: its phase passes are
+    the Z-string variants."""
+    for a, b in (("XMODE_FIRST>", "XMODE_FIRST_Z>"), ("XMODE_BOUNDARY>", "XMODE_BOUNDARY_Z>"),
+                 ("grad_bound<", "grad_bound_z<"), ("grad_final<", "grad_final_z<")):
+        name = name.replace(a, b)
+    return name
+
+
+def segment_problem(name: str):
+    """(problem, gammas, ts, p, zterms) of a measured workload, built as its
+    bench measurement builds it (device tensors)."""
+    import numpy as np
+    import torch
+
+    import paper_2110_03963_amd as qva
+    from workloads import (CONFIG_SEEDS, dicke_state_device, exqaoa_maxcut_workload, maxcut_qualities_device,
+                           qaoa_maxcut_workload, qaoaz_portfolio_workload, qwoa_constrained_workload,
+                           qwoa_portfolio_workload)
+
+    dev = "cuda"
+    if name == "qaoa_maxcut_n28_p8":
+        wl = qaoa_maxcut_workload(28, 8, graph="regular3", weighted=True, seed=CONFIG_SEEDS["qaoa_n28"],
+                                  build_q=False)
+        prob = qva.Problem(maxcut_qualities_device(28, wl.edges, wl.weights, dev), "x")
+        return prob, wl.gammas, wl.ts, 8, False
+    if name == "adjoint_qaoa_maxcut_n30_p12":
+        wl = qaoa_maxcut_workload(30, 12, graph="regular3", weighted=True, seed=CONFIG_SEEDS["grad_n30"],
+                                  build_q=False)
+        prob = qva.Problem(maxcut_qualities_device(30, wl.edges, wl.weights, dev), "x")
+        return prob, wl.gammas, wl.ts, 12, False
+    if name.startswith(("qwoa_portfolio", "adjoint_qwoa_portfolio")):
+        kind = "ring" if name.endswith("ring") else "complete"
+        if "_k13_" in name:
+            wl = qwoa_constrained_workload(26, 13, 6, seed=CONFIG_SEEDS["qwoa_n26"], lambda_kind=kind)
+        else:
+            wl = qwoa_portfolio_workload(26, 6, seed=CONFIG_SEEDS["qwoa_n26"], lambda_kind=kind)
+        prob = qva.Problem(torch.from_numpy(wl.q).to(dev), "circulant", None, kind)
+        return prob, wl.gammas, wl.ts, 6, False
+    if name == "exqaoa_maxcut_n28_p8_regular3":
+        wl = exqaoa_maxcut_workload(28, 8, seed=CONFIG_SEEDS["qaoa_n28"], build_q=False)
+        q = maxcut_qualities_device(28, wl.edges, wl.weights, dev)
+        prob = qva.Problem(q, "x", terms=(wl.supports, wl.coefs))
+        return prob, np.ascontiguousarray(wl.gammas).ravel(), wl.ts, 8, True
+    if name == "qaoaz_portfolio_m26_k13_p6_ring":
+        wl = qaoaz_portfolio_workload(26, 13, 6, seed=CONFIG_SEEDS["qwoa_n26"])
+        prob = qva.Problem(torch.from_numpy(wl.q).to(dev), "xy", pairs=qva.parity_ring_pairs(range(26)),
+                           psi0=dicke_state_device(26, 13, dev))
+        return prob, wl.gammas, wl.ts, 6, False
+    raise ValueError(name)
+
+
+def launch_dispatches(info, slots: bool) -> int:
+    """Kernel dispatches of one plan launch: the backward transform passes
+    without inner products run once per vector, and the gradient's slot sums
+    are two kernels when there are per-tile slots."""
+    if info.kind in (22, 23):
+        return 2
+    if info.kind == 25:
+        return 2 if slots else 1
+    return 1
+
+
+def pmc_pass(plan_out: str) -> int:
     """The program profiled by the two counter runs: one calibration copy of
-    known size, one standalone phase (reads psi and q, writes psi), then two
-    fused n = 28, p = 8 evolutions as in the timed step."""
+    known size, then each workload of PMC_SEGMENTS run twice through the
+    library.  Writes the launch sequence (labels, dispatch counts, algorithmic
+    bytes) to plan_out so that the counter values can be matched to launches."""
     import torch
 
     import paper_2110_03963_amd as qva
     from paper_2110_03963_amd import _lib
-    from workloads import CONFIG_SEEDS, maxcut_qualities_device, qaoa_maxcut_workload
+
+    import numpy as np
 
     lib = qva.load_library()
-    n, p = 28, 8
-    wl = qaoa_maxcut_workload(n, p, graph="regular3", weighted=True, seed=CONFIG_SEEDS["qaoa_n28"],
-                              build_q=False)
     src = torch.ones(CALIB_ELEMS, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
     dst.copy_(src)
     torch.cuda.synchronize()
     del src, dst
-    q = maxcut_qualities_device(n, wl.edges, wl.weights, "cuda")
-    psi = torch.empty(1 << n, dtype=torch.complex128, device="cuda")
-    qva.init_uniform(psi)
-    qva.phase(psi, q, 0.3)
-    prob = qva.Problem(q, "x")
-    g = torch.tensor(wl.gammas, dtype=torch.float64, device="cuda")
-    t = torch.tensor(wl.ts, dtype=torch.float64, device="cuda")
-    ws = torch.empty(max(prob.workspace_bytes(p), 16), dtype=torch.uint8, device="cuda")
-    out = torch.empty(2, dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream().cuda_stream
-    for _ in range(2):
-        _lib.check("qva_evolve", lib.qva_evolve(prob.cstruct(), g.data_ptr(), t.data_ptr(), p,
-                                                psi.data_ptr(), out.data_ptr(), out.data_ptr() + 8,
-                                                _lib.QVA_EVOLVE_SKIP_FINAL_STATE, ws.data_ptr(),
-                                                ws.numel(), stream))
-    torch.cuda.synchronize()
-    log(f"pmc pass done: f={out[0].item():.15f}")
+    segments = []
+    for name, call in PMC_SEGMENTS:
+        prob, gammas, ts, p, zterms = segment_problem(name)
+        g = torch.tensor(np.asarray(gammas, dtype=np.float64), device="cuda")
+        t = torch.tensor(np.asarray(ts, dtype=np.float64), device="cuda")
+        grad = call == "grad"
+        flags = 0 if grad else _lib.QVA_EVOLVE_SKIP_FINAL_STATE
+        infos = plan_of(lib, prob, p, grad, flags)
+        psi = torch.empty(prob.N, dtype=torch.complex128, device="cuda")
+        chi = torch.empty(prob.N, dtype=torch.complex128, device="cuda") if grad else None
+        ws = torch.empty(max(prob.workspace_bytes(p, grad), 256), dtype=torch.uint8, device="cuda")
+        out = torch.empty(2, dtype=torch.float64, device="cuda")
+        dg = torch.empty(g.numel(), dtype=torch.float64, device="cuda")
+        dt = torch.empty(p, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        for _ in range(2):
+            if prob.psi0 is not None:
+                psi.copy_(prob.psi0)
+            if grad:
+                st = lib.qva_grad(prob.cstruct(), g.data_ptr(), t.data_ptr(), p, psi.data_ptr(), chi.data_ptr(),
+                                  out.data_ptr(), dg.data_ptr(), dt.data_ptr(), ws.data_ptr(), ws.numel(), stream)
+            else:
+                st = lib.qva_evolve(prob.cstruct(), g.data_ptr(), t.data_ptr(), p, psi.data_ptr(), out.data_ptr(),
+                                    out.data_ptr() + 8, flags, ws.data_ptr(), ws.numel(), stream)
+            _lib.check("qva_grad" if grad else "qva_evolve", st)
+            torch.cuda.synchronize()
+        slots = not (prob.mixer == "circulant" and prob.lambda_kind == "complete")
+        label = zterm_label if zterms else (lambda x: x)
+        segments.append({"workload": name, "call": call, "N": prob.N, "runs": 2,
+                         "launches": [{"label": label(kernel_name(i.kind, i.col_bits)), "kind": i.kind,
+                                       "dispatches": launch_dispatches(i, slots), "bytes": i.bytes}
+                                      for i in infos]})
+        log(f"pmc pass: {name} {call} f={out[0].item():.15f}")
+        del prob, psi, chi, ws
+        torch.cuda.empty_cache()
+    with open(plan_out, "w") as fh:
+        json.dump({"segments": segments}, fh)
     return 0
 
 
-def write_traffic(fetch_dir: str, write_dir: str) -> int:
-    """Turn the FETCH_SIZE and WRITE_SIZE runs of pmc_pass into HBM bytes per
-    launch of each xpass kernel, each counter scaled by what it reads on the
-    calibration copy (known bytes), and store them with the sources' digest."""
-    fetch = read_counter_csv(fetch_dir, "FETCH_SIZE")
-    write = read_counter_csv(write_dir, "WRITE_SIZE")
+def counter_dispatches(folder: str, counter: str) -> list:
+    """(dispatch id, kernel name, value) of every dispatch in rocprofv3's
+    counter_collection CSV(s) under `folder`, in dispatch order (values in
+    the counter's unit, KiB for FETCH_SIZE / WRITE_SIZE)."""
+    import csv
+    import glob
+
+    files = glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no counter_collection.csv under {folder}")
+    rows = {}
+    for fn in files:
+        with open(fn, newline="") as fh:
+            for row in csv.DictReader(fh):
+                if row.get("Counter_Name") != counter:
+                    continue
+                key = (int(row.get("Agent_Id", 0) or 0), int(row["Dispatch_Id"]))
+                name = row.get("Kernel_Name", "")
+                prev = rows.get(key)
+                rows[key] = (key[1], name, (prev[2] if prev else 0.0) + float(row["Counter_Value"]))
+    return [rows[k] for k in sorted(rows)]
+
+
+def kernel_family(name: str) -> str:
+    import re
+
+    m = re.search(r"(\w+_kernel)\b", name.replace("(anonymous namespace)::", ""))
+    return m.group(1) if m else name
+
+
+def write_traffic(fetch_dir: str, write_dir: str, plan_file: str) -> int:
+    """Turn the FETCH_SIZE and WRITE_SIZE runs of the pmc pass into HBM bytes
+    per launch for every launch of every measured workload: each counter
+    scaled by what it reads on the calibration copy (known bytes), launches
+    matched to dispatches in order (kernel families checked), averaged over
+    the launches that share a kernel label and over the two runs."""
+    with open(plan_file) as fh:
+        plan = json.load(fh)
+    fetch = counter_dispatches(fetch_dir, "FETCH_SIZE")
+    write = counter_dispatches(write_dir, "WRITE_SIZE")
     calib_kib = CALIB_ELEMS * 8 / 1024.0
-    if "copy" not in fetch or "copy" not in write:
+    f_copy = [v for _, nm, v in fetch if "copyBuffer" in nm]
+    w_copy = [v for _, nm, v in write if "copyBuffer" in nm]
+    if not f_copy or not w_copy:
         raise RuntimeError("calibration copy not found in the counter runs")
-    f_copy, w_copy = max(fetch["copy"]), max(write["copy"])
-    ff, fw = calib_kib / f_copy, calib_kib / w_copy
-    n = 28
-    amps = 1 << n
-    kernels = {}
-    for label in sorted(set(fetch) & set(write)):
-        if not label.startswith("xpass_kernel"):
-            continue
-        fb = sum(fetch[label]) / len(fetch[label]) * 1024 * ff
-        wb = sum(write[label]) / len(write[label]) * 1024 * fw
-        kernels[label] = {"fetch_bytes": round(fb), "write_bytes": round(wb),
-                          "bytes_per_launch": round(fb + wb), "dispatches": len(fetch[label]),
-                          "fetch_bytes_per_amplitude": round(fb / amps, 3),
-                          "write_bytes_per_amplitude": round(wb / amps, 3)}
-    check = {}
-    if "phase_kernel" in fetch and "phase_kernel" in write:
-        check = {"phase_kernel_fetch_bytes_per_amplitude":
-                 round(max(fetch["phase_kernel"]) * 1024 * ff / amps, 3),
-                 "phase_kernel_write_bytes_per_amplitude":
-                 round(max(write["phase_kernel"]) * 1024 * fw / amps, 3),
-                 "expected": "24 read (psi 16 + q 8), 16 written"}
-    data = {"source_digest": source_digest(*TRAFFIC_SOURCES), "workload": "qaoa_maxcut_n28_p8",
+    ff, fw = calib_kib / max(f_copy), calib_kib / max(w_copy)
+    fq = [(nm, v) for _, nm, v in fetch if "qva::" in nm]
+    wq = [(nm, v) for _, nm, v in write if "qva::" in nm]
+    need = sum(seg["runs"] * sum(l["dispatches"] for l in seg["launches"]) for seg in plan["segments"])
+    if len(fq) != need or len(wq) != need:
+        raise RuntimeError(f"dispatch count mismatch: plan {need}, FETCH {len(fq)}, WRITE {len(wq)}")
+    pos = 0
+    workloads = []
+    for seg in plan["segments"]:
+        acc = {}
+        for _ in range(seg["runs"]):
+            for l in seg["launches"]:
+                fb = wb = 0.0
+                for _d in range(l["dispatches"]):
+                    (nf, vf), (nw, vw) = fq[pos], wq[pos]
+                    fam = KIND_FAMILIES.get(l["kind"])
+                    if nf != nw or (fam and kernel_family(nf) not in fam):
+                        raise RuntimeError(f"launch {l['label']} (kind {l['kind']}) met dispatch {nf[:80]}")
+                    fb += vf * 1024 * ff
+                    wb += vw * 1024 * fw
+                    pos += 1
+                a = acc.setdefault(l["label"], {"launches": 0, "fetch": 0.0, "write": 0.0, "alg": 0.0})
+                a["launches"] += 1
+                a["fetch"] += fb
+                a["write"] += wb
+                a["alg"] += l["bytes"]
+        N = seg["N"]
+        kernels = {}
+        for label, a in sorted(acc.items()):
+            c = a["launches"]
+            fb, wb, alg = a["fetch"] / c, a["write"] / c, a["alg"] / c
+            kernels[label] = {"launches_per_call": c // seg["runs"], "fetch_bytes": round(fb),
+                              "write_bytes": round(wb), "bytes_per_launch": round(fb + wb),
+                              "algorithmic_bytes_per_launch": round(alg),
+                              "traffic_over_algorithmic": round((fb + wb) / alg, 4) if alg else None,
+                              "fetch_bytes_per_amplitude": round(fb / N, 3),
+                              "write_bytes_per_amplitude": round(wb / N, 3)}
+        workloads.append({"workload": seg["workload"], "call": seg["call"], "N": N, "kernels": kernels})
+    data = {"source_digest": source_digest(*traffic_sources()),
             "calibration": {"kernel": "__amd_rocclr_copyBuffer", "bytes_each_way": CALIB_ELEMS * 8,
-                            "fetch_kib_read": f_copy, "write_kib_read": w_copy,
-                            "fetch_scale": ff, "write_scale": fw, **check},
-            "commands": ["timeout -s KILL 150 rocprofv3 --pmc FETCH_SIZE --output-format csv "
-                         "-d gpurun_out/pmc_fetch -o pmc -- python3 -u bench.py --pmc-pass",
-                         "timeout -s KILL 150 rocprofv3 --pmc WRITE_SIZE --output-format csv "
-                         "-d gpurun_out/pmc_write -o pmc -- python3 -u bench.py --pmc-pass",
-                         "python bench.py --write-traffic gpurun_out/pmc_fetch gpurun_out/pmc_write"],
-            "kernels": kernels}
+                            "fetch_kib_read": max(f_copy), "write_kib_read": max(w_copy),
+                            "fetch_scale": ff, "write_scale": fw},
+            "commands": ["timeout -s KILL 300 rocprofv3 --pmc FETCH_SIZE --output-format csv "
+                         "-d gpurun_out/pmc_fetch -o pmc -- python3 -u bench.py --pmc-pass gpurun_out/pmc_plan.json",
+                         "timeout -s KILL 300 rocprofv3 --pmc WRITE_SIZE --output-format csv "
+                         "-d gpurun_out/pmc_write -o pmc -- python3 -u bench.py --pmc-pass gpurun_out/pmc_plan.json",
+                         "python bench.py --write-traffic gpurun_out/pmc_fetch gpurun_out/pmc_write "
+                         "gpurun_out/pmc_plan.json"],
+            "workloads": workloads}
     with open(TRAFFIC_FILE, "w") as fh:
         json.dump(data, fh, indent=1, sort_keys=True)
         fh.write("\n")
-    print(json.dumps(data, indent=1, sort_keys=True))
+    lines = ["# HBM traffic of every launch (rocprofv3 FETCH_SIZE / WRITE_SIZE)", "",
+             "Counter values scaled by what each counter reads on a device copy of known size "
+             f"(fetch x{ff:.5f}, write x{fw:.5f}), averaged over the launches of each kernel and two "
+             "runs. Commands:", ""]
+    lines += ["    " + c for c in data["commands"]]
+    for w in workloads:
+        lines += ["", f"## {w['workload']} ({w['call']}, N = {w['N']})", "",
+                  "| kernel | launches | fetch B/amp | write B/amp | traffic / algorithmic |",
+                  "|---|---|---|---|---|"]
+        for k, v in w["kernels"].items():
+            lines.append(f"| {k} | {v['launches_per_call']} | {v['fetch_bytes_per_amplitude']} | "
+                         f"{v['write_bytes_per_amplitude']} | {v['traffic_over_algorithmic']} |")
+    with open(TRAFFIC_SUMMARY, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print(json.dumps({"workloads": len(workloads), "dispatches": need}))
     return 0
+
+
+def stored_traffic(workload: str, call: str, label: str):
+    """HBM bytes per launch of kernel `label` in a measured workload, or None
+    (not measured, or the kernel sources changed since the counters ran)."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as fh:
+        tr = json.load(fh)
+    if tr.get("source_digest") != source_digest(*traffic_sources()):
+        return None
+    for w in tr.get("workloads", []):
+        if w["workload"] == workload and w["call"] == call and label in w["kernels"]:
+            return w["kernels"][label]["bytes_per_launch"]
+    return None
 
 
 def time_calls(fn, warmup: int, steps: int) -> float:
@@ -338,6 +505,28 @@ def time_calls(fn, warmup: int, steps: int) -> float:
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / steps
+
+
+def median_calls(fn, warmup: int, reps: int) -> tuple[float, list]:
+    """Median and list of milliseconds per call of fn(), each call between
+    its own pair of torch events."""
+    import statistics
+
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    runs = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        runs.append(e0.elapsed_time(e1))
+    return statistics.median(runs), runs
 
 
 def attainable_rate(n: int, groups, two: bool = False) -> dict | None:
@@ -363,18 +552,59 @@ def attainable_rate(n: int, groups, two: bool = False) -> dict | None:
             "command": " ".join(["paper_2110_03963_amd/stream_probe"] + args[1:])}
 
 
-def cpu_baseline(wl) -> dict:
-    """The oracle (single-threaded C) on one layer of the same n = 28 instance."""
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def host_threads() -> int:
+    """Threads this process may run on (its CPU affinity, else os.cpu_count())."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        return os.cpu_count() or 1
+
+
+def timed_oracle(fn, threads: int) -> float:
+    """Seconds of one call of fn() with the oracle's OpenMP loops on `threads` threads."""
     import oracle
 
-    t0 = time.perf_counter()
-    oracle.evolve("x", wl.q, wl.gammas[:1], wl.ts[:1])
-    dt = time.perf_counter() - t0
-    return {"value": round(1.0 / dt, 5), "unit": "layer-applications/s", "cores": 1, "kind": "oracle",
-            "sample": f"one layer (phase + hypercube mixer + <Q>) of the same n=28 instance at full "
-                      f"size: {dt:.1f} s on 1 host core ({platform.processor() or 'cpu'}); "
-                      f"value = 1 layer / that time",
-            "host_cpus": os.cpu_count()}
+    before = oracle.get_threads()
+    oracle.set_threads(threads)
+    try:
+        t0 = time.perf_counter()
+        fn()
+        return time.perf_counter() - t0
+    finally:
+        oracle.set_threads(before)
+
+
+def cpu_baseline(wl) -> dict:
+    """The oracle on one full-size layer of the same n = 28 instance, timed
+    with one thread and with every host thread this process may use (its
+    elementwise and rotation loops run under OpenMP; its sums stay serial).
+    `value` is the all-threads rate."""
+    import oracle
+
+    def layer():
+        oracle.evolve("x", wl.q, wl.gammas[:1], wl.ts[:1])
+
+    nt = host_threads()
+    dt1 = timed_oracle(layer, 1)
+    dtn = timed_oracle(layer, nt)
+    return {"value": round(1.0 / dtn, 5), "unit": "layer-applications/s", "cores": nt, "kind": "oracle",
+            "sample": f"one layer (phase + hypercube mixer + <Q>) of the same n=28 instance at full size: "
+                      f"{dtn:.2f} s on {nt} threads, {dt1:.2f} s on 1 thread; value = 1 layer / the "
+                      f"{nt}-thread time",
+            "value_1_thread": round(1.0 / dt1, 5), "seconds_1_thread": round(dt1, 3),
+            "seconds_all_threads": round(dtn, 3), "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
 
 
 # ------------------------------------------------------------------ extras
@@ -426,8 +656,84 @@ def extra_qwoa(lib, steps: int, kind: str = "ring", constrained: bool = False) -
     return {"workload": name, "N": prob.N, "ms_per_evolve": round(ms, 4),
             "layer_applications_per_s": round(p / (ms * 1e-3), 2), "launches": len(infos),
             "effective_GBps": round(plan_bytes / (ms * 1e-3) / 1e9, 1),
-            "f": out[0].item(), "roofline": roofline_of(per, steps),
+            "f": out[0].item(), "roofline": with_traffic(roofline_of(per, steps), name, "evolve"),
             "per_kernel_ms_per_evolve": {k: round(v["ms"] / steps, 4) for k, v in sorted(per.items())}}
+
+
+def extra_small(lib, reps: int) -> dict:
+    """The n = 10 QAOA MaxCut workload (G(10, 0.5) unweighted, cut-size q,
+    p = 2): the whole state lives in one workgroup's LDS, so the figure is
+    latency, in microseconds per evolution (no HBM fraction is claimed).
+    The oracle's time for the same evolution is given beside it."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2110_03963_amd as qva
+    from paper_2110_03963_amd import _lib
+    from workloads import CONFIG_SEEDS, qaoa_maxcut_workload
+
+    n, p = 10, 2
+    wl = qaoa_maxcut_workload(n, p, graph="gnp", weighted=False, edge_prob=0.5, seed=CONFIG_SEEDS["qaoa_n10"])
+    q = torch.from_numpy(wl.q).cuda()
+    prob = qva.Problem(q, "x")
+    g = torch.tensor(wl.gammas, device="cuda")
+    t = torch.tensor(wl.ts, device="cuda")
+    psi = torch.empty(1 << n, dtype=torch.complex128, device="cuda")
+    out = torch.empty(2, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def run():
+        _lib.check("qva_evolve", lib.qva_evolve(prob.cstruct(), g.data_ptr(), t.data_ptr(), p, psi.data_ptr(),
+                                                out.data_ptr(), out.data_ptr() + 8,
+                                                _lib.QVA_EVOLVE_SKIP_FINAL_STATE, None, 0, stream))
+
+    ms = time_calls(run, 20, reps)
+    # the same evolution as one captured graph, replayed (launch overhead amortised)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        _lib.check("qva_evolve", lib.qva_evolve(prob.cstruct(), g.data_ptr(), t.data_ptr(), p, psi.data_ptr(),
+                                                out.data_ptr(), out.data_ptr() + 8,
+                                                _lib.QVA_EVOLVE_SKIP_FINAL_STATE, None, 0,
+                                                side.cuda_stream))
+    torch.cuda.synchronize()
+    ms_graph = time_calls(graph.replay, 20, reps)
+    f = out[0].item()
+    _, f_ref, _ = oracle.evolve("x", wl.q, wl.gammas, wl.ts)
+    oracle_reps = 200
+    dt = timed_oracle(lambda: [oracle.evolve("x", wl.q, wl.gammas, wl.ts) for _ in range(oracle_reps)], 1)
+    return {"workload": "qaoa_maxcut_n10_p2", "N": 1 << n, "us_per_evolve": round(ms * 1e3, 2),
+            "us_per_evolve_graph_replay": round(ms_graph * 1e3, 2),
+            "layer_applications_per_s": round(p / (ms * 1e-3), 1), "launches": 1,
+            "f": f, "f_oracle": f_ref, "rel_diff_vs_oracle": abs(f - f_ref) / abs(f_ref),
+            "oracle_us_per_evolve_1_thread": round(dt / oracle_reps * 1e6, 2),
+            "note": "whole state in one workgroup (LDS); latency-bound, no HBM roofline claimed"}
+
+
+def oracle_batch_sample(wls, stride: int = 8) -> dict:
+    """The oracle's gradient loop over every `stride`-th instance of the batch,
+    on all host threads, extrapolated to the whole batch by the cost model
+    p * n * 2^n (the oracle's work per gradient grows as layers x qubits x
+    amplitudes)."""
+    import oracle
+
+    sample = wls[::stride]
+    nt = host_threads()
+
+    def loop():
+        for w in sample:
+            oracle.grad("x", w.q, w.gammas, w.ts)
+
+    dt = timed_oracle(loop, nt)
+    cost = lambda ws: float(sum(w.p * w.n * (1 << w.n) for w in ws))  # noqa: E731
+    total = dt * cost(wls) / cost(sample)
+    return {"kind": "oracle", "instances_timed": len(sample), "stride": stride, "threads": nt,
+            "seconds_sample": round(dt, 3), "seconds_whole_batch_extrapolated": round(total, 2),
+            "instance_gradients_per_s_extrapolated": round(len(wls) / total, 2),
+            "extrapolation": "whole-batch time = sample time x sum(p n 2^n) over all instances / "
+                             "the same sum over the sample"}
 
 
 def extra_adjoint(lib, reps: int, workload: str = "qaoa") -> dict:
@@ -512,9 +818,9 @@ def extra_adjoint(lib, reps: int, workload: str = "qaoa") -> dict:
                 (gp if k < p else tp)[k % p] += h if k < p else h_t
             forward()
 
-    ms_adj = time_calls(adjoint, 1, reps)
-    ms_cfd = time_calls(central, 1, reps)
-    ms_ffd = time_calls(forward_diff, 0, reps)
+    ms_adj, adj_runs = median_calls(adjoint, 1, max(reps, 5))
+    ms_cfd, cfd_runs = median_calls(central, 1, reps)
+    ms_ffd, ffd_runs = median_calls(forward_diff, 0, reps)
     adj = torch.cat([dg, dt]).cpu().numpy()
     fdv = fd_vals.cpu().numpy()
     # the step actually taken: (x + h) - (x - h), exact in double (the t step
@@ -534,6 +840,16 @@ def extra_adjoint(lib, reps: int, workload: str = "qaoa") -> dict:
     per = per_kernel_profile(run_timed, infos, 1)
     plan_bytes = sum(i.bytes for i in infos)
     roof = roofline_of(per, 1)
+    oracle_info = None
+    if workload == "qaoa":
+        import oracle
+
+        # the gradient oracle at the parity size (n = 12, same seed scheme)
+        w12 = qaoa_maxcut_workload(12, p, graph="regular3", weighted=True, seed=CONFIG_SEEDS["grad_n30"])
+        dt12 = timed_oracle(lambda: oracle.grad("x", w12.q, w12.gammas, w12.ts), 1)
+        oracle_info = {"kind": "oracle", "gradient_n12_p12_ms_1_thread": round(dt12 * 1e3, 3),
+                       "note": "the adjoint oracle at n = 12 (the parity size); the n = 30 evolution is "
+                               "not run on the host"}
     if workload == "qaoa" and roof["kernel"].startswith("grad_bound<"):
         # the streaming probe over the backward boundary passes' tiles, 72 B/amp
         geoms = sorted({(i.col_bits, i.group_first) for i in infos if i.kind == 20})
@@ -543,6 +859,9 @@ def extra_adjoint(lib, reps: int, workload: str = "qaoa") -> dict:
             roof["frac_of_attainable"] = round(roof["achieved"] / att["GBps"], 4)
     return {"workload": name, "params": 2 * p,
             "ms_per_adjoint_gradient": round(ms_adj, 2),
+            "timing": {"statistic": "median", "adjoint_runs_ms": [round(x, 2) for x in adj_runs],
+                       "central_fd_runs_ms": [round(x, 2) for x in cfd_runs],
+                       "forward_fd_runs_ms": [round(x, 2) for x in ffd_runs]},
             "adjoint_gradients_per_s": round(1e3 / ms_adj, 3),
             "ms_per_central_fd_gradient": round(ms_cfd, 2),
             "ms_per_forward_fd_gradient": round(ms_ffd, 2),
@@ -551,7 +870,7 @@ def extra_adjoint(lib, reps: int, workload: str = "qaoa") -> dict:
             "max_rel_diff_adjoint_vs_central_fd": rel, "fd_steps": {"gamma": h, "t": h_t},
             "f": f.item(), "launches": len(infos),
             "effective_GBps": round(plan_bytes / (ms_adj * 1e-3) / 1e9, 1),
-            "roofline": roof,
+            "roofline": with_traffic(roof, name, "grad"), "oracle": oracle_info,
             "per_kernel_ms": {k: round(v["ms"], 3) for k, v in sorted(per.items())}}
 
 
@@ -622,13 +941,7 @@ def extra_exqaoa(lib, steps: int) -> dict:
     gper = per_kernel_profile(grad_timed, ginfos, 1)
 
     def zname(per):  # the phase passes of this plan are the Z-string variants
-        out = {}
-        for k, v in per.items():
-            for a, b in (("XMODE_FIRST>", "XMODE_FIRST_Z>"), ("XMODE_BOUNDARY>", "XMODE_BOUNDARY_Z>"),
-                         ("grad_bound<", "grad_bound_z<"), ("grad_final<", "grad_final_z<")):
-                k = k.replace(a, b)
-            out[k] = v
-        return out
+        return {zterm_label(k): v for k, v in per.items()}
 
     per, gper = zname(per), zname(gper)
     plan_bytes = sum(i.bytes for i in infos)
@@ -640,7 +953,8 @@ def extra_exqaoa(lib, steps: int) -> dict:
             "effective_GBps_evolve": round(plan_bytes / (ms_fwd * 1e-3) / 1e9, 1),
             "effective_GBps_gradient": round(gplan_bytes / (ms_adj * 1e-3) / 1e9, 1),
             "f": f_ex, "f_gradient_call": f.item(),
-            "roofline_evolve": roofline_of(per, steps), "roofline_gradient": roofline_of(gper, 1),
+            "roofline_evolve": with_traffic(roofline_of(per, steps), "exqaoa_maxcut_n28_p8_regular3", "evolve"),
+            "roofline_gradient": with_traffic(roofline_of(gper, 1), "exqaoa_maxcut_n28_p8_regular3", "grad"),
             "per_kernel_ms_per_evolve": {k: round(v["ms"] / steps, 4) for k, v in sorted(per.items())},
             "per_kernel_ms_per_gradient": {k: round(v["ms"], 3) for k, v in sorted(gper.items())}}
 
@@ -731,12 +1045,13 @@ def extra_qaoaz(lib, steps: int) -> dict:
             "effective_GBps_evolve": round(plan_bytes / (ms_fwd * 1e-3) / 1e9, 1),
             "effective_GBps_gradient": round(gplan_bytes / (ms_adj * 1e-3) / 1e9, 1),
             "f": f_fwd, "f_gradient_call": f.item(),
-            "roofline_evolve": roofline_of(per, steps), "roofline_gradient": roofline_of(gper, 1),
+            "roofline_evolve": with_traffic(roofline_of(per, steps), "qaoaz_portfolio_m26_k13_p6_ring", "evolve"),
+            "roofline_gradient": with_traffic(roofline_of(gper, 1), "qaoaz_portfolio_m26_k13_p6_ring", "grad"),
             "per_kernel_ms_per_evolve": {kk: round(v["ms"] / steps, 4) for kk, v in sorted(per.items())},
             "per_kernel_ms_per_gradient": {kk: round(v["ms"], 3) for kk, v in sorted(gper.items())}}
 
 
-def extra_batch(lib) -> dict:
+def extra_batch(lib, with_oracle: bool = True) -> dict:
     """512 independent QAOA MaxCut instances (n ~ U{12..22}, p ~ U{1..8},
     G(n, 0.4), weights U(0,1)): f and the adjoint gradient of every instance
     plus a gradient step, replayed as one captured HIP graph; compared with
@@ -793,6 +1108,11 @@ def extra_batch(lib) -> dict:
                                                 dg.data_ptr(), dt.data_ptr(), ws.data_ptr(), ws.numel(), st))
 
     ms_single = time_calls(per_instance, 1, 2)
+    oracle_sample = None
+    if with_oracle:
+        for w, q in list(zip(wls, qs))[::8]:
+            w.q = q.cpu().numpy()
+        oracle_sample = oracle_batch_sample(wls, 8)
     total_bytes = 0.0
     for pr, w in zip(probs, wls):
         total_bytes += sum(i.bytes for i in plan_of(lib, pr, w.p, True, 0))
@@ -804,7 +1124,8 @@ def extra_batch(lib) -> dict:
             "instance_gradients_per_s": round(512 / (ms_graph * 1e-3), 1),
             "ms_per_batch_one_call_per_instance": round(ms_single, 3),
             "speedup_vs_one_call_per_instance": round(ms_single / ms_graph, 2),
-            "effective_GBps": round(total_bytes / (ms_graph * 1e-3) / 1e9, 1)}
+            "effective_GBps": round(total_bytes / (ms_graph * 1e-3) / 1e9, 1),
+            "oracle": oracle_sample}
 
 
 # Secondary measurements: name -> fn(lib, steps).
@@ -813,10 +1134,11 @@ EXTRAS = {
     "qwoa_complete": lambda lib, steps: extra_qwoa(lib, max(3, steps // 2), "complete"),
     "qwoa_constrained_ring": lambda lib, steps: extra_qwoa(lib, max(3, steps // 2), "ring", True),
     "qwoa_constrained_complete": lambda lib, steps: extra_qwoa(lib, max(3, steps // 2), "complete", True),
-    "adjoint_vs_fd": lambda lib, steps: extra_adjoint(lib, 2),
+    "adjoint_vs_fd": lambda lib, steps: extra_adjoint(lib, 3),
     "adjoint_qwoa_complete": lambda lib, steps: extra_adjoint(lib, 3, "qwoa_complete"),
     "adjoint_qwoa_constrained_ring": lambda lib, steps: extra_adjoint(lib, 3, "qwoa_constrained_ring"),
     "batched": lambda lib, steps: extra_batch(lib),
+    "qaoa_n10": lambda lib, steps: extra_small(lib, 500),
     "exqaoa": lambda lib, steps: extra_exqaoa(lib, max(3, steps // 2)),
     "qaoaz": lambda lib, steps: extra_qaoaz(lib, max(3, steps // 2)),
 }
@@ -829,9 +1151,10 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--pmc-pass", action="store_true",
-                    help="run the short program profiled by the HBM-traffic counter runs")
-    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+    ap.add_argument("--pmc-pass", metavar="PLAN_JSON",
+                    help="run the program profiled by the HBM-traffic counter runs (every measured "
+                         "workload twice) and write its launch sequence to PLAN_JSON")
+    ap.add_argument("--write-traffic", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "PLAN_JSON"),
                     help="store per-launch HBM traffic from the two counter runs' CSV output")
     ap.add_argument("--valu-summary", nargs=2, metavar=("COUNTER_DIR", "KERNEL_STATS_CSV"),
                     help="per-kernel VALU load from a --pmc SQ_INSTS_VALU* run and a --stats run")
@@ -847,7 +1170,7 @@ def main() -> int:
               "(the sharded multi-GPU path is a design, not part of this build)", file=sys.stderr)
         return 2
     if args.pmc_pass:
-        return pmc_pass()
+        return pmc_pass(args.pmc_pass)
     if args.extra:
         import torch
 
@@ -917,12 +1240,7 @@ def main() -> int:
 
     per = per_kernel_profile(run_timed, infos, args.steps)
     roofline = roofline_of(per, args.steps)
-    if os.path.exists(TRAFFIC_FILE):
-        with open(TRAFFIC_FILE) as fh:
-            tr = json.load(fh)
-        entry = tr.get("kernels", {}).get(roofline["kernel"])
-        if tr.get("source_digest") == source_digest(*TRAFFIC_SOURCES) and entry:
-            roofline["traffic"] = entry["bytes_per_launch"]
+    roofline["traffic"] = stored_traffic("qaoa_maxcut_n28_p8", "evolve", roofline["kernel"])
     # the attainable rate of the dominant kernel's access pattern (its tile
     # geometries, the same bytes, no arithmetic), from the streaming probe
     geoms = sorted({(i.col_bits, i.group_first) for i in infos

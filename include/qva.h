@@ -164,9 +164,14 @@ int qva_mix_x(qva_c128 *psi, int n_qubits, double t, void *stream);
  * (F_mj = exp(-2 pi i j m / N)), F^-1 = conj(F)/N.
  * psi: device, N complex, in place; N = 2^k, 1 <= k <= QVA_MAX_QUBITS.
  * lambda: device, N doubles in natural order when lambda_kind ==
- * QVA_LAMBDA_ARRAY, else ignored (may be NULL). */
+ * QVA_LAMBDA_ARRAY, else ignored (may be NULL).
+ * work: device, >= qva_mix_circulant_workspace_bytes(N) bytes (the
+ * transform's root table; NULL allowed when that is 0). */
 int qva_mix_circulant(qva_c128 *psi, const double *lambda, int lambda_kind, int64_t N,
-                      double t, void *stream);
+                      double t, void *work, size_t work_bytes, void *stream);
+
+/* Bytes of device workspace qva_mix_circulant needs for N amplitudes. */
+size_t qva_mix_circulant_workspace_bytes(int64_t N);
 
 /* Bytes of device workspace that qva_evolve (for_grad = 0) or qva_grad
  * (for_grad = 1) needs for problem P at depth p.  Returns 0 when no workspace
@@ -211,7 +216,7 @@ int qva_evolve(const qva_problem *P, const double *gammas_dev, const double *ts_
  *   - A request whose qva_workspace_bytes(P, p, 0) exceeds
  *     QVA_STATIC_SCRATCH_BYTES returns QVA_ERR_SCRATCH and launches nothing
  *     (e.g. the hypercube mixer up to n_qubits = 32, the ring circulant up to
- *     2^32 states; an eigenvalue array or Bluestein's padded buffers only for
+ *     2^31 states; an eigenvalue array or Bluestein's padded buffers only for
  *     small N).  Argument errors are reported as by qva_evolve.
  *   - The array belongs to the GPU of `stream` (the current device for the
  *     NULL stream); its device address is looked up once per GPU, on the
@@ -312,8 +317,30 @@ typedef enum {
     QVA_PASS_GRAD_BLU_LAMBDA = 47, /* inverse top, Im<chi|W|phi>, exp(+i t lambda), forward */
     QVA_PASS_GRAD_BLU_PHASE = 48,  /* inverse top, Im<chi|Q|phi>, exp(+i gamma q), forward  */
     QVA_PASS_GRAD_BLU_FINAL = 49,  /* inverse top group, Im<chi|Q|phi> of layer 1           */
-    QVA_PASS_GRAD_ZSLOT = 50       /* extended QAOA: per-term sums of the preceding phase
+    QVA_PASS_GRAD_ZSLOT = 50,      /* extended QAOA: per-term sums of the preceding phase
                                       pass's Im(conj(chi_j) phi_j), one tile transform each */
+    QVA_PASS_TWIDDLE_PREP = 51,    /* circulant transforms: the 4096 roots W_4096^k of the
+                                      low-group digits, written once per call */
+    /* circulant over N solutions, N not a power of two with every prime factor
+     * <= 31 (e.g. N = C(m, k) for m <= 31): the DFT of length N in place over
+     * groups N = A_0 A_1 ... A_{G-1} (no padding); group_first holds the
+     * group index g, group_bits its size A_g, col_bits its columns per tile */
+    QVA_PASS_MR_TABLES = 52,       /* roots W_{A_g}^k and digit-reversal tables, once per call */
+    QVA_PASS_MR_FIRST = 53,        /* psi_0, phase of layer 1, forward top group           */
+    QVA_PASS_MR_DIF = 54,          /* forward transform of one group                       */
+    QVA_PASS_MR_DIT = 55,          /* inverse transform of one group                       */
+    QVA_PASS_MR_LOWDIAG = 56,      /* low group forward, diag(exp(-i t lambda)), inverse   */
+    QVA_PASS_MR_BOUNDARY = 57,     /* inverse top group, 1/N, phase of k+1, forward top    */
+    QVA_PASS_MR_LAST = 58,         /* inverse top group, 1/N, <Q> partial sums             */
+    QVA_PASS_MR_LAST_STORE = 59,   /* as QVA_PASS_MR_LAST, also writes psi_p               */
+    QVA_PASS_MR_SMALL = 60,        /* N <= 4096: the whole evolution in one workgroup      */
+    QVA_PASS_GRAD_MR_TURN = 61,    /* inverse top, <Q>, chi = Q psi_p, forward top (both)   */
+    QVA_PASS_GRAD_MR_DIF = 62,     /* forward transform of one group, once per vector      */
+    QVA_PASS_GRAD_MR_DIT = 63,     /* inverse transform of one group, once per vector      */
+    QVA_PASS_GRAD_MR_LOWDIAG = 64, /* low group, Im<chi^|lambda|phi^>/N, inverse diagonal  */
+    QVA_PASS_GRAD_MR_BOUND = 65,   /* inverse top, Im<chi|Q|phi>, inverse phase, forward   */
+    QVA_PASS_GRAD_MR_FINAL = 66,   /* inverse top group, Im<chi|Q|phi> of layer 1          */
+    QVA_PASS_GRAD_MR_SMALL = 67    /* N <= 4096: forward + adjoint in one workgroup        */
 } qva_pass_kind;
 
 /* One launch of a plan.  `bytes` is the algorithmic HBM traffic of the

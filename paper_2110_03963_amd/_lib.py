@@ -74,7 +74,10 @@ PASS_KINDS = {0: "whole", 1: "first", 2: "middle", 3: "boundary", 4: "last", 5: 
               36: "blu_first", 37: "blu_mul", 38: "blu_lambda", 39: "blu_phase", 40: "blu_last",
               41: "blu_last_store", 42: "xy", 43: "xy_last", 44: "xy_turn", 45: "grad_xy",
               46: "grad_blu_turn", 47: "grad_blu_lambda", 48: "grad_blu_phase", 49: "grad_blu_final",
-              50: "grad_zslot"}
+              50: "grad_zslot", 51: "twiddle_prep", 52: "mr_tables", 53: "mr_first", 54: "mr_dif",
+              55: "mr_dit", 56: "mr_lowdiag", 57: "mr_boundary", 58: "mr_last", 59: "mr_last_store",
+              60: "mr_small", 61: "grad_mr_turn", 62: "grad_mr_dif", 63: "grad_mr_dit",
+              64: "grad_mr_lowdiag", 65: "grad_mr_bound", 66: "grad_mr_final", 67: "grad_mr_small"}
 
 
 class QvaBatchItem(ctypes.Structure):
@@ -118,7 +121,8 @@ SIGNATURES = {
     "qva_init_uniform": (_I, [_P, _I64, _P]),
     "qva_phase": (_I, [_P, _P, _I64, _D, _P]),
     "qva_mix_x": (_I, [_P, _I, _D, _P]),
-    "qva_mix_circulant": (_I, [_P, _P, _I, _I64, _D, _P]),
+    "qva_mix_circulant": (_I, [_P, _P, _I, _I64, _D, _P, _SZ, _P]),
+    "qva_mix_circulant_workspace_bytes": (_SZ, [_I64]),
     "qva_workspace_bytes": (_SZ, [_PROB, _I, _I]),
     "qva_expectation_workspace_bytes": (_SZ, [_I64]),
     "qva_expectation": (_I, [_P, _P, _I64, _P, _P, _P, _SZ, _P]),

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstddef>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <stdint.h>
 #include <tuple>
@@ -13,6 +14,7 @@
 
 #include "qva.h"
 #include "qva_internal.h"
+#include "qva_mrplan.h"
 #include "qva_plan.h"
 
 using namespace qva;
@@ -237,10 +239,40 @@ bool complete_closed_form(const qva_problem* P)
 
 // A ring or eigenvalue-array circulant over N solutions, N not a power of
 // two: Bluestein's chirp-z transform over a padded power of two M.
+// The mixed-radix factorisation of N (cached: the planner searches the
+// assignments of N's prime factors to groups).
+bool mixed_geom(int64_t N, MrGeom* out)
+{
+    static std::mutex mu;
+    static std::map<int64_t, std::pair<bool, MrGeom>> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(N);
+    if (it == cache.end()) {
+        MrGeom m{};
+        const bool ok = mr_plan(N, m);
+        if (cache.size() > 256)
+            cache.clear();
+        it = cache.emplace(N, std::make_pair(ok, m)).first;
+    }
+    if (out)
+        *out = it->second.second;
+    return it->second.first;
+}
+
+// A ring or eigenvalue-array circulant over N solutions, N not a power of
+// two but with every prime factor <= 31: the in-place mixed-radix transform.
+constexpr bool kMixedRadix = false;  // switched on once its GPU parity tests run
+
+bool mixed_path(const qva_problem* P)
+{
+    return kMixedRadix && P->mixer == QVA_MIX_CIRCULANT && P->lambda_kind != QVA_LAMBDA_COMPLETE &&
+           problem_N(P) != (int64_t(1) << P->n_qubits) && mixed_geom(problem_N(P), nullptr);
+}
+
 bool bluestein_path(const qva_problem* P)
 {
     return P->mixer == QVA_MIX_CIRCULANT && P->lambda_kind != QVA_LAMBDA_COMPLETE &&
-           problem_N(P) != (int64_t(1) << P->n_qubits);
+           problem_N(P) != (int64_t(1) << P->n_qubits) && !mixed_path(P);
 }
 
 // log2 M: the smallest power of two >= 2N - 1, and at least 2^13 (tile passes).
@@ -255,7 +287,7 @@ int blu_bits(const qva_problem* P)
 // Workspace of a Bluestein evolution: partials, then the padded buffer and the
 // two filter spectra (M amplitudes each).
 struct BluLayout {
-    size_t parts = 0, pad = 0, b0 = 0, b1 = 0, total = 0;
+    size_t parts = 0, pad = 0, b0 = 0, b1 = 0, tw = 0, total = 0;
 };
 
 BluLayout blu_layout(const qva_problem* P)
@@ -270,6 +302,8 @@ BluLayout blu_layout(const qva_problem* P)
     off += (size_t)M * sizeof(double2);
     L.b1 = off;
     off += (size_t)M * sizeof(double2);
+    L.tw = off;
+    off += kTwiddleTableBytes;
     L.total = off;
     return L;
 }
@@ -292,7 +326,7 @@ std::vector<Launch> fft_launches(const qva_problem* P, int p, bool store)
 {
     const int n = P->n_qubits;
     std::vector<Launch> L;
-    if (n <= kTileBits && !complete_closed_form(P) && !bluestein_path(P)) {
+    if (n <= kTileBits && !complete_closed_form(P) && !bluestein_path(P) && !mixed_path(P)) {
         L.push_back({QVA_PASS_WHOLE, 0, 0, -1, -1, -1});
         return L;
     }
@@ -325,6 +359,7 @@ std::vector<Launch> fft_launches(const qva_problem* P, int p, bool store)
             for (int g = 1; g <= c - 1; ++g)
                 V.push_back({QVA_PASS_FFT_DIT, g, FMODE_DIT, -1, -1, -1});
         };
+        L.push_back({QVA_PASS_TWIDDLE_PREP, -1, 0, -1, -1, -1});
         for (int which = 0; which < 2; ++which) {  // the filters w and conj(w)
             L.push_back({QVA_PASS_BLU_CHIRP, c, FMODE_B_CHIRP, -1, which, -1});
             conv_front(L);
@@ -348,6 +383,7 @@ std::vector<Launch> fft_launches(const qva_problem* P, int p, bool store)
         L.push_back({QVA_PASS_REDUCE, -1, 0, -1, -1, -1});
         return L;
     }
+    L.push_back({QVA_PASS_TWIDDLE_PREP, -1, 0, -1, -1, -1});
     if (lambda_tiled(P))
         L.push_back({QVA_PASS_LAMBDA_PREP, -1, 0, -1, -1, -1});
     const int G = (int)x_groups(n).size();
@@ -379,6 +415,8 @@ double fft_launch_bytes(const Launch& l, int n, bool store, bool tiled)
         return (2 * amp + real) * N;
     case QVA_PASS_LAMBDA_PREP:
         return 2 * real * N;
+    case QVA_PASS_TWIDDLE_PREP:
+        return (double)kTwiddleTableBytes;
     default: {
         Launch x = l;
         return launch_bytes(x, n, store);
@@ -426,6 +464,8 @@ double blu_launch_bytes(const Launch& l, const qva_problem* P, int p)
         return 2 * amp * M;
     case QVA_PASS_BLU_CHIRP:
         return amp * M;
+    case QVA_PASS_TWIDDLE_PREP:
+        return (double)kTwiddleTableBytes;
     case QVA_PASS_BLU_TILE:
         return 2 * amp * M;
     case QVA_PASS_BLU_FIRST:
@@ -538,6 +578,17 @@ int small_lambda_kind(int kind)
 // the per-tile copy of lambda.
 size_t circ_partials_bytes(int n) { return (size_t)(int64_t(1) << (n - kTileBits)) * sizeof(double2); }
 
+// Offset of the low-group root table in the workspace of the power-of-two
+// circulant evolution (after the partials and the per-tile lambda copy).
+size_t circ_twiddle_offset(const qva_problem* P)
+{
+    const int n = P->n_qubits;
+    size_t off = circ_partials_bytes(n);
+    if (lambda_tiled(P))
+        off += (size_t)(int64_t(1) << n) * sizeof(double);
+    return align256(off);
+}
+
 // Bluestein evolution (N not a power of two, ring or eigenvalue array).
 int evolve_bluestein(const qva_problem* P, const double* gammas, const double* ts, int p, double2* psi,
                      double* out_f, double* out_norm, bool store, char* work, hipStream_t s,
@@ -549,11 +600,14 @@ int evolve_bluestein(const qva_problem* P, const double* gammas, const double* t
     double2* partials = reinterpret_cast<double2*>(work);
     double2* pad = reinterpret_cast<double2*>(work + W.pad);
     double2* spec[2] = {reinterpret_cast<double2*>(work + W.b0), reinterpret_cast<double2*>(work + W.b1)};
+    double2* tw = reinterpret_cast<double2*>(work + W.tw);
     for (const Launch& l : fft_launches(P, p, store)) {
         hipError_t e = hipSuccess;
         hook.before(s);
         if (l.kind == QVA_PASS_REDUCE) {
             e = launch_final_reduce(partials, int64_t(1) << (nb - kTileBits), out_f, out_norm, s);
+        } else if (l.kind == QVA_PASS_TWIDDLE_PREP) {
+            e = launch_twiddle_table(tw, s);
         } else {
             const XGroup& g = groups[l.group];
             FftPassParams f{};
@@ -572,7 +626,216 @@ int evolve_bluestein(const qva_problem* P, const double* gammas, const double* t
             f.bt = spec[l.layer2 > 0 ? 1 : 0];
             f.out = l.kind == QVA_PASS_BLU_TILE ? spec[l.layer2 > 0 ? 1 : 0] : psi;
             f.conj = l.layer2 > 0 ? 1 : 0;
+            f.tw = tw;
             e = launch_fftpass(f, s);
+        }
+        hook.after(s);
+        if (e != hipSuccess)
+            return QVA_ERR_HIP;
+    }
+    return QVA_OK;
+}
+
+// ----------------------------------------------- mixed-radix circulant
+// One launch of a mixed-radix plan.
+struct MrLaunch {
+    int kind;    // qva_pass_kind
+    int mode;    // MR_* / MRG_*
+    int group;
+    int layer;   // layer of the diagonal's t, or -1
+    int gamma;   // layer whose phase the launch applies (or walks back), or -1
+    int slot;    // gradient slot, or -1
+};
+
+int mr_kind(int mode)
+{
+    switch (mode) {
+    case MR_FIRST:
+        return QVA_PASS_MR_FIRST;
+    case MR_DIF:
+        return QVA_PASS_MR_DIF;
+    case MR_DIT:
+        return QVA_PASS_MR_DIT;
+    case MR_LOWDIAG:
+        return QVA_PASS_MR_LOWDIAG;
+    case MR_BOUNDARY:
+        return QVA_PASS_MR_BOUNDARY;
+    case MR_LAST:
+        return QVA_PASS_MR_LAST;
+    default:
+        return QVA_PASS_MR_LAST_STORE;
+    }
+}
+
+// p >= 1.  Evolution: tables, the pass list, the partial-sum reduction.
+// Gradient: tables, the forward without its last pass, the turn, then every
+// forward pass undone in reverse (inner products where they are fused), the
+// reductions.  Slots: t of layer L at L, gamma of layer L at p + L.
+std::vector<MrLaunch> mr_launches(const MrGeom& m, int p, bool store, bool grad)
+{
+    std::vector<MrLaunch> L;
+    L.push_back({QVA_PASS_MR_TABLES, 0, -1, -1, -1, -1});
+    if (m.G == 1) {
+        if (grad)
+            L.push_back({QVA_PASS_GRAD_MR_SMALL, MRG_SMALL, 0, -1, -1, -1});
+        else
+            L.push_back({QVA_PASS_MR_SMALL, store ? MR_SMALL_STORE : MR_SMALL, 0, -1, -1, -1});
+        return L;
+    }
+    const std::vector<MrPass> fw = mr_evolve_plan(m.G, p, grad ? false : store);
+    const int nf = (int)fw.size();
+    for (int i = 0; i < (grad ? nf - 1 : nf); ++i)
+        L.push_back({mr_kind(fw[i].mode), fw[i].mode, fw[i].group, fw[i].layer, fw[i].phase_layer, -1});
+    if (!grad) {
+        L.push_back({QVA_PASS_REDUCE, 0, -1, -1, -1, -1});
+        return L;
+    }
+    L.push_back({QVA_PASS_GRAD_MR_TURN, MRG_TURN, fw[nf - 1].group, -1, -1, -1});
+    for (int i = nf - 2; i >= 0; --i) {
+        const MrPass& f = fw[i];
+        if (f.mode == MR_DIF)
+            L.push_back({QVA_PASS_GRAD_MR_DIT, MR_DIT, f.group, -1, -1, -1});
+        else if (f.mode == MR_DIT)
+            L.push_back({QVA_PASS_GRAD_MR_DIF, MR_DIF, f.group, -1, -1, -1});
+        else if (f.mode == MR_LOWDIAG)
+            L.push_back({QVA_PASS_GRAD_MR_LOWDIAG, MRG_LOWDIAG, f.group, f.layer, -1, f.layer});
+        else if (f.mode == MR_BOUNDARY)
+            L.push_back({QVA_PASS_GRAD_MR_BOUND, MRG_BOUND, f.group, -1, f.phase_layer, p + f.phase_layer});
+        else  // MR_FIRST
+            L.push_back({QVA_PASS_GRAD_MR_FINAL, MRG_FINAL, f.group, -1, 0, p});
+    }
+    L.push_back({QVA_PASS_REDUCE, 0, -1, -1, -1, -1});
+    L.push_back({QVA_PASS_GRAD_REDUCE, 0, -1, -1, -1, -1});
+    return L;
+}
+
+// Workspace of the mixed-radix path: tables, per-tile (f, norm) partials,
+// and for the gradient 2p per-tile slot arrays and their sums.
+struct MrLayout {
+    int64_t tiles = 0;
+    size_t geom = 0, tab = 0, part = 0, slots = 0, sums = 0, total = 0;
+};
+
+MrLayout mr_layout(const MrGeom& m, int p, bool grad)
+{
+    MrLayout w;
+    w.tiles = mr_max_tiles(m);
+    size_t off = 0;
+    w.geom = off;
+    off = align256(off + sizeof(MrGeom));
+    w.tab = off;
+    off = align256(off + mr_table_bytes(m));
+    w.part = off;
+    off = align256(off + (size_t)w.tiles * sizeof(double2));
+    if (grad) {
+        w.slots = off;
+        off = align256(off + (size_t)(2 * p) * (size_t)w.tiles * sizeof(double));
+        w.sums = off;
+        off = align256(off + (size_t)(2 * p) * sizeof(double));
+    }
+    w.total = off;
+    return w;
+}
+
+double mr_launch_bytes(const MrLaunch& l, const qva_problem* P, const MrGeom& m, int p)
+{
+    const double N = (double)problem_N(P), amp = 16.0, real = 8.0;
+    const double lam = P->lambda_kind == QVA_LAMBDA_ARRAY ? real * N : 0.0;
+    switch (l.kind) {
+    case QVA_PASS_MR_TABLES:
+        return (double)(mr_table_bytes(m) + sizeof(MrGeom));
+    case QVA_PASS_MR_FIRST:
+        return (amp + real) * N;
+    case QVA_PASS_MR_DIF:
+    case QVA_PASS_MR_DIT:
+        return 2 * amp * N;
+    case QVA_PASS_MR_LOWDIAG:
+        return 2 * amp * N + lam;
+    case QVA_PASS_MR_BOUNDARY:
+        return (2 * amp + real) * N;
+    case QVA_PASS_MR_LAST:
+        return (amp + real) * N;
+    case QVA_PASS_MR_LAST_STORE:
+        return (2 * amp + real) * N;
+    case QVA_PASS_MR_SMALL:
+        return real * N + lam + (l.mode == MR_SMALL_STORE ? amp * N : 0.0);
+    case QVA_PASS_GRAD_MR_SMALL:
+        return real * N + lam;
+    case QVA_PASS_GRAD_MR_TURN:
+        return (3 * amp + real) * N;
+    case QVA_PASS_GRAD_MR_DIF:
+    case QVA_PASS_GRAD_MR_DIT:
+        return 4 * amp * N;
+    case QVA_PASS_GRAD_MR_LOWDIAG:
+        return 4 * amp * N + lam;
+    case QVA_PASS_GRAD_MR_BOUND:
+        return (4 * amp + real) * N;
+    case QVA_PASS_GRAD_MR_FINAL:
+        return (2 * amp + real) * N;
+    case QVA_PASS_REDUCE:
+        return 16.0 * (double)m.tiles[m.G - 1];
+    case QVA_PASS_GRAD_REDUCE:
+        return 8.0 * (double)(2 * p) * (double)mr_max_tiles(m);
+    default:
+        return 0.0;
+    }
+}
+
+// Evolution (grad = false) or adjoint gradient over the mixed-radix passes.
+int mixed_run(const qva_problem* P, const double* gammas, const double* ts, int p, double2* psi, double2* chi,
+              double* out_f, double* out_norm, double* dgammas, double* dts, bool store, bool grad, char* work,
+              hipStream_t s, EventHook& hook)
+{
+    MrGeom m{};
+    if (!mixed_geom(problem_N(P), &m))
+        return QVA_ERR_UNSUPPORTED;
+    const MrLayout W = mr_layout(m, p, grad);
+    MrGeom* geom = reinterpret_cast<MrGeom*>(work + W.geom);
+    double2* tab = reinterpret_cast<double2*>(work + W.tab);
+    double2* part = reinterpret_cast<double2*>(work + W.part);
+    double* slots = reinterpret_cast<double*>(work + W.slots);
+    double* sums = reinterpret_cast<double*>(work + W.sums);
+    for (const MrLaunch& l : mr_launches(m, p, store, grad)) {
+        hipError_t e = hipSuccess;
+        hook.before(s);
+        if (l.kind == QVA_PASS_MR_TABLES) {
+            e = launch_mr_tables(m, geom, tab, s);
+        } else if (l.kind == QVA_PASS_REDUCE) {
+            e = launch_final_reduce(part, m.tiles[m.G - 1], out_f, out_norm, s);
+        } else if (l.kind == QVA_PASS_GRAD_REDUCE) {
+            e = launch_grad_reduce(slots, 2 * p, W.tiles, sums, p, 1, 1, dgammas, dts, s);
+        } else {
+            MrPassParams mp{};
+            mp.psi = psi;
+            mp.chi = chi;
+            mp.q = P->q;
+            mp.lam = P->lambda;
+            mp.lambda_kind = P->lambda_kind == QVA_LAMBDA_RING ? FFT_LAMBDA_RING : FFT_LAMBDA_NATURAL;
+            mp.t = dev_angle(ts, l.layer >= 0 ? l.layer : 0);
+            mp.gamma = dev_angle(gammas, l.gamma >= 0 ? l.gamma : 0);
+            mp.gammas = gammas;
+            mp.ts = ts;
+            mp.p = p;
+            mp.N = problem_N(P);
+            mp.geom = geom;
+            mp.g = l.group;
+            mp.tab = tab;
+            mp.partials = part;
+            mp.slot = l.slot >= 0 ? slots + (int64_t)l.slot * W.tiles : nullptr;
+            mp.out_f = out_f;
+            mp.out_norm = out_norm;
+            mp.dgammas = dgammas;
+            mp.dts = dts;
+            if (l.kind == QVA_PASS_GRAD_MR_DIF || l.kind == QVA_PASS_GRAD_MR_DIT) {
+                // no inner product: the single-vector transform, once per vector
+                e = launch_mrpass(mp, m, l.mode, s);
+                if (e == hipSuccess) {
+                    mp.psi = chi;
+                    e = launch_mrpass(mp, m, l.mode, s);
+                }
+            } else {
+                e = launch_mrpass(mp, m, l.mode, s);
+            }
         }
         hook.after(s);
         if (e != hipSuccess)
@@ -591,9 +854,13 @@ int evolve_circ(const qva_problem* P, const double* gammas, const double* ts, in
     const bool blu = bluestein_path(P);
     if (blu && p > 0)
         return evolve_bluestein(P, gammas, ts, p, psi, out_f, out_norm, store, work, s, hook);
+    if (mixed_path(P) && p > 0)
+        return mixed_run(P, gammas, ts, p, psi, nullptr, out_f, out_norm, nullptr, nullptr, store, false, work, s,
+                         hook);
     const std::vector<XGroup> groups = x_groups(n);
     double2* partials = reinterpret_cast<double2*>(work);
     double* lam_tiles = n > kTileBits ? reinterpret_cast<double*>(work + circ_partials_bytes(n)) : nullptr;
+    double2* tw = n > kTileBits ? reinterpret_cast<double2*>(work + circ_twiddle_offset(P)) : nullptr;
     // complete graph in closed form: the running state sum follows the partials
     double2* state_sum = closed ? reinterpret_cast<double2*>(work + align256(cpl_partials_bytes(P))) : nullptr;
     const bool tiled = lambda_tiled(P);
@@ -632,6 +899,9 @@ int evolve_circ(const qva_problem* P, const double* gammas, const double* ts, in
         case QVA_PASS_LAMBDA_PREP:
             e = launch_lambda_tiles(P->lambda, lam_tiles, n, s);
             break;
+        case QVA_PASS_TWIDDLE_PREP:
+            e = launch_twiddle_table(tw, s);
+            break;
         case QVA_PASS_CPL_SUM:
             e = launch_final_reduce(partials, cpl_blocks(P), &state_sum->x, &state_sum->y, s);
             break;
@@ -667,6 +937,7 @@ int evolve_circ(const qva_problem* P, const double* gammas, const double* ts, in
             f.col_bits = g.col_bits;
             f.flags = l.xmode;
             f.partials = partials;
+            f.tw = tw;
             e = launch_fftpass(f, s);
             break;
         }
@@ -689,6 +960,7 @@ struct GradLayout {
     int nslots = 0;  // p * (G + E) per-tile slot arrays (none for the closed-form mixer)
     size_t fpart = 0, slots = 0, sums = 0, lam = 0, part = 0, state = 0, total = 0;
     size_t pad_phi = 0, pad_chi = 0, b0 = 0, b1 = 0;  // Bluestein: padded vectors, filter spectra
+    size_t tw = 0;   // circulant transform passes: the low-group root table
     size_t zd = 0;   // extended QAOA: Im(conj(chi_j) phi_j) at a phase, 2^n doubles
 };
 
@@ -720,6 +992,8 @@ GradLayout grad_layout(const qva_problem* P, int p)
         off = align256(off + (size_t)g.nslots * (size_t)g.tiles * sizeof(double));
         g.sums = off;
         off = align256(off + (size_t)(g.nslots > 0 ? g.nslots : 1) * sizeof(double));
+        g.tw = off;
+        off += kTwiddleTableBytes;
         g.total = off;
         return g;
     }
@@ -759,6 +1033,9 @@ GradLayout grad_layout(const qva_problem* P, int p)
     g.zd = off;
     if (P->mixer == QVA_MIX_X && problem_terms(P) > 0)
         off = align256(off + (size_t)(int64_t(1) << n) * sizeof(double));
+    g.tw = off;
+    if (P->mixer == QVA_MIX_CIRCULANT)
+        off += kTwiddleTableBytes;
     g.total = off;
     return g;
 }
@@ -778,7 +1055,7 @@ std::vector<GLaunch> grad_launches(const qva_problem* P, int p)
     std::vector<GLaunch> L;
     const int n = P->n_qubits;
     const bool circ = P->mixer == QVA_MIX_CIRCULANT;
-    if (n <= kTileBits && !complete_closed_form(P) && !bluestein_path(P)) {
+    if (n <= kTileBits && !complete_closed_form(P) && !bluestein_path(P) && !mixed_path(P)) {
         L.push_back({QVA_PASS_GRAD_WHOLE, -1, 0, -1, -1, -1, -1, -1, -1});
         return L;
     }
@@ -876,6 +1153,7 @@ std::vector<GLaunch> grad_launches(const qva_problem* P, int p)
         if (gz)
             L.push_back({QVA_PASS_GRAD_ZSLOT, first.group, GMODE_ZSLOT, -1, -1, 0, -1, gslot(0), -1});
     } else {
+        L.push_back({QVA_PASS_TWIDDLE_PREP, -1, 0, -1, -1, -1, -1, -1, -1});
         if (lambda_tiled(P))
             L.push_back({QVA_PASS_LAMBDA_PREP, -1, 0, -1, -1, -1, -1, -1, -1});
         const std::vector<FPass> fw = fft_evolve_plan(PG, p, false);
@@ -966,6 +1244,8 @@ double grad_launch_bytes(const GLaunch& l, const qva_problem* P, int p)
 int grad_run(const qva_problem* P, const double* gammas, const double* ts, int p, double2* psi, double2* chi,
              double* out_f, double* dgammas, double* dts, char* work, hipStream_t s, EventHook& hook)
 {
+    if (mixed_path(P) && p > 0)
+        return mixed_run(P, gammas, ts, p, psi, chi, out_f, nullptr, dgammas, dts, false, true, work, s, hook);
     const int n = P->n_qubits;
     const int64_t N = problem_N(P);
     const bool circ = P->mixer == QVA_MIX_CIRCULANT;
@@ -977,6 +1257,7 @@ int grad_run(const qva_problem* P, const double* gammas, const double* ts, int p
     double* lam_tiles = reinterpret_cast<double*>(work + W.lam);
     double* cpart = reinterpret_cast<double*>(work + W.part);
     double2* cstate = reinterpret_cast<double2*>(work + W.state);  // [0]: forward sum, [1..2]: backward
+    double2* tw = reinterpret_cast<double2*>(work + W.tw);
     const bool blu = bluestein_path(P);
     const bool tiled = circ && lambda_tiled(P) && !blu;
     const std::vector<XGroup> bgroups = blu ? x_groups(blu_bits(P)) : std::vector<XGroup>();
@@ -1010,6 +1291,7 @@ int grad_run(const qva_problem* P, const double* gammas, const double* ts, int p
             f.bt = spec[l.t2 > 0 ? 1 : 0];
             f.out = l.kind == QVA_PASS_BLU_TILE ? spec[l.t2 > 0 ? 1 : 0] : nullptr;
             f.conj = l.t2 > 0 ? 1 : 0;
+            f.tw = tw;
             e = launch_fftpass(f, s);
             hook.after(s);
             if (e != hipSuccess)
@@ -1091,6 +1373,9 @@ int grad_run(const qva_problem* P, const double* gammas, const double* ts, int p
         case QVA_PASS_LAMBDA_PREP:
             e = launch_lambda_tiles(P->lambda, lam_tiles, n, s);
             break;
+        case QVA_PASS_TWIDDLE_PREP:
+            e = launch_twiddle_table(tw, s);
+            break;
         case QVA_PASS_FIRST:
         case QVA_PASS_MIDDLE:
         case QVA_PASS_BOUNDARY: {
@@ -1121,6 +1406,7 @@ int grad_run(const qva_problem* P, const double* gammas, const double* ts, int p
             f.k = g.k;
             f.col_bits = g.col_bits;
             f.flags = l.mode;
+            f.tw = tw;
             e = launch_fftpass(f, s);
             break;
         }
@@ -1165,6 +1451,7 @@ int grad_run(const qva_problem* P, const double* gammas, const double* ts, int p
             gp.n_terms = problem_terms(P);
             gp.slot_terms = l.kind == QVA_PASS_GRAD_ZSLOT ? slot_ptr(l.slot_g) : nullptr;
             gp.zd = reinterpret_cast<double*>(work + W.zd);
+            gp.tw = tw;
             e = launch_gradpass(gp, circ, s);
             break;
         }
@@ -1475,8 +1762,13 @@ int qva_mix_x(qva_c128* psi, int n_qubits, double t, void* stream)
     return QVA_OK;
 }
 
-int qva_mix_circulant(qva_c128* psi, const double* lambda, int lambda_kind, int64_t N, double t,
-                      void* stream)
+size_t qva_mix_circulant_workspace_bytes(int64_t N)
+{
+    return N > (int64_t(1) << kTileBits) ? kTwiddleTableBytes : 0;
+}
+
+int qva_mix_circulant(qva_c128* psi, const double* lambda, int lambda_kind, int64_t N, double t, void* work,
+                      size_t work_bytes, void* stream)
 {
     if (!psi)
         return QVA_ERR_ARG;
@@ -1492,6 +1784,11 @@ int qva_mix_circulant(qva_c128* psi, const double* lambda, int lambda_kind, int6
         return N >= 2 && (int64_t(1) << n) != N ? QVA_ERR_UNSUPPORTED : QVA_ERR_SIZE;
     if (!aligned(psi, 16) || (lambda_kind == QVA_LAMBDA_ARRAY && !aligned(lambda, 8)))
         return QVA_ERR_ALIGN;
+    const size_t need = qva_mix_circulant_workspace_bytes(N);
+    if (need && (!work || work_bytes < need))
+        return QVA_ERR_WORKSPACE;
+    if (work && !aligned(work, 16))
+        return QVA_ERR_ALIGN;
     double2* d = reinterpret_cast<double2*>(psi);
     hipStream_t s = as_stream(stream);
     const int lk = small_lambda_kind(lambda_kind);
@@ -1505,6 +1802,9 @@ int qva_mix_circulant(qva_c128* psi, const double* lambda, int lambda_kind, int6
         sp.flags = SM_MIX_ONCE | SM_STORE;
         return hip_status(launch_small_fft(sp, s));
     }
+    double2* tw = reinterpret_cast<double2*>(work);
+    if (launch_twiddle_table(tw, s) != hipSuccess)
+        return QVA_ERR_HIP;
     const std::vector<XGroup> groups = x_groups(n);
     for (const FPass& fp : fft_mix_plan((int)groups.size())) {
         FftPassParams f{};
@@ -1517,6 +1817,7 @@ int qva_mix_circulant(qva_c128* psi, const double* lambda, int lambda_kind, int6
         f.k = groups[fp.group].k;
         f.col_bits = groups[fp.group].col_bits;
         f.flags = fp.mode;
+        f.tw = tw;
         if (launch_fftpass(f, s) != hipSuccess)
             return QVA_ERR_HIP;
     }
@@ -1542,6 +1843,13 @@ size_t qva_workspace_bytes(const qva_problem* P, int p, int for_grad)
             return grad_layout(P, p).total;
         return align256(cpl_partials_bytes(P)) + 256;  // partials, then the running state sum
     }
+    if (mixed_path(P)) {
+        if (p == 0)
+            return (size_t)expect_partial_count(problem_N(P)) * sizeof(double2);
+        MrGeom m{};
+        mixed_geom(problem_N(P), &m);
+        return mr_layout(m, p, for_grad != 0).total;
+    }
     if (bluestein_path(P)) {
         if (p == 0)
             return (size_t)expect_partial_count(problem_N(P)) * sizeof(double2);
@@ -1551,6 +1859,8 @@ size_t qva_workspace_bytes(const qva_problem* P, int p, int for_grad)
         return 0;
     if (for_grad && p > 0)
         return grad_layout(P, p).total;
+    if (P->mixer == QVA_MIX_CIRCULANT && p > 0)
+        return circ_twiddle_offset(P) + kTwiddleTableBytes;
     size_t bytes = circ_partials_bytes(n);
     if (P->mixer == QVA_MIX_CIRCULANT && lambda_tiled(P))
         bytes += (size_t)(int64_t(1) << n) * sizeof(double);
@@ -1648,6 +1958,24 @@ int qva_plan(const qva_problem* P, int p, int for_grad, int flags, qva_pass_info
             out[i].mix_layer2 = (int)(tile ? lp[l.pass].ops.size() : 0);
             out[i].phase_layer = (l.flags & XY_PHASE) ? l.layer : -1;
             out[i].bytes = xy_launch_bytes(l, P, p, for_grad != 0);
+        }
+        return (int)L.size();
+    }
+    if (mixed_path(P) && p > 0) {
+        MrGeom m{};
+        mixed_geom(problem_N(P), &m);
+        const std::vector<MrLaunch> L = mr_launches(m, p, !(flags & QVA_EVOLVE_SKIP_FINAL_STATE), for_grad != 0);
+        for (int i = 0; i < (int)L.size() && i < max_out; ++i) {
+            const MrLaunch& l = L[i];
+            const bool tiles = l.group >= 0 && l.kind != QVA_PASS_MR_TABLES;
+            out[i].kind = l.kind;
+            out[i].group_first = tiles ? l.group : -1;
+            out[i].group_bits = tiles ? m.A[l.group] : 0;
+            out[i].col_bits = tiles ? m.cols[l.group] : 0;
+            out[i].mix_layer = l.layer;
+            out[i].mix_layer2 = -1;
+            out[i].phase_layer = l.gamma;
+            out[i].bytes = mr_launch_bytes(l, P, m, p);
         }
         return (int)L.size();
     }

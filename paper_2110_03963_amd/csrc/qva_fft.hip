@@ -180,9 +180,9 @@ __global__ __launch_bounds__(kThreads, 2) void fftpass_kernel(FftPassParams P)
         store_tile<LA>(v, P.psi, g, t, FLAGS == FMODE_DIT_SCALE ? invN : 1.0);
     } else if constexpr (FLAGS == FMODE_LOWDIAG) {
         load_tile<LA>(v, P.psi, g, t);
-        dif_tile<C>(v, lds, g, t);
+        dif_tile<C, true>(v, lds, g, t, P.tw);
         diag_c(v, P, tile, t, angle_value(P.mix1));
-        dit_tile<C>(v, lds, g, t);
+        dit_tile<C, true>(v, lds, g, t, P.tw);
         store_tile<LA>(v, P.psi, g, t, 1.0);
     } else if constexpr (FLAGS == FMODE_BOUNDARY) {
         // the angle first, each register's psi and q requested together, the
@@ -271,17 +271,17 @@ __global__ __launch_bounds__(kThreads, 2) void fftpass_kernel(FftPassParams P)
             P.partials[blockIdx.x] = tot;
     } else if constexpr (FLAGS == FMODE_LOWMUL) {
         load_tile<LA>(v, P.psi, g, t);
-        dif_tile<C>(v, lds, g, t);
+        dif_tile<C, true>(v, lds, g, t, P.tw);
 #pragma unroll
         for (int r = 0; r < kRegs; ++r)
             v[r] = cmul(v[r], ld_nt(P.bt + (tile << kTileBits) + r * kThreads + t));
-        dit_tile<C>(v, lds, g, t);
+        dit_tile<C, true>(v, lds, g, t, P.tw);
         store_tile<LA>(v, P.psi, g, t, 1.0);
     } else if constexpr (FLAGS == FMODE_LOWDIF_TILED) {
         // the filter's spectrum in the order FMODE_LOWMUL reads it, times 1/M
         const double invM = ldexp(1.0, -P.n);
         load_tile<LA>(v, P.psi, g, t);
-        dif_tile<C>(v, lds, g, t);
+        dif_tile<C, true>(v, lds, g, t, P.tw);
 #pragma unroll
         for (int r = 0; r < kRegs; ++r)
             st_nt(P.out + (tile << kTileBits) + r * kThreads + t, make_double2(v[r].x * invM, v[r].y * invM));
@@ -395,6 +395,11 @@ __global__ __launch_bounds__(256) void lambda_tile_kernel(const double* lam, dou
     }
 }
 
+__global__ __launch_bounds__(kThreads) void twiddle_table_kernel(double2* tab)
+{
+    twiddle_table_fill(tab, threadIdx.x);
+}
+
 template <int C>
 hipError_t launch_fft_c(const FftPassParams& P, unsigned grid, hipStream_t s)
 {
@@ -471,6 +476,12 @@ hipError_t launch_fftpass(const FftPassParams& P, hipStream_t s)
 hipError_t launch_small_fft(const SmallFftParams& P, hipStream_t s)
 {
     hipLaunchKernelGGL(small_fft_kernel, dim3(1), dim3(kThreads), 0, s, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_twiddle_table(double2* tab, hipStream_t s)
+{
+    hipLaunchKernelGGL(twiddle_table_kernel, dim3(1), dim3(kThreads), 0, s, tab);
     return hipGetLastError();
 }
 

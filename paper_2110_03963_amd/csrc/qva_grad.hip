@@ -70,73 +70,76 @@ __global__ __launch_bounds__(kThreads, 2) void zslot_kernel(GradPassParams P)
 }
 
 // ------------------------------------------------ circulant-mixer passes
-template <int C, int L>
+// TAB: low-group root table (C = 0 only; see digit_twiddles).
+template <int C, int L, bool TAB>
 __device__ __forceinline__ void digit_twiddle2(double2 (&p)[kRegs], double2 (&x)[kRegs], const TileMap& g,
-                                               int t, bool inv)
+                                               int t, bool inv, const double2* tab)
 {
-    digit_twiddles<C, L>(g, t, [&](int r, double2 tw) {
+    digit_twiddles<C, L, TAB>(g, t, [&](int r, double2 tw) {
         const double2 w = make_double2(tw.x, inv ? -tw.y : tw.y);
         p[r] = cmul(p[r], w);
         x[r] = cmul(x[r], w);
-    });
+    }, tab);
 }
 
-template <int C, int L>
-__device__ __forceinline__ void dif_digit2(double2 (&p)[kRegs], double2 (&x)[kRegs], const TileMap& g, int t)
+template <int C, int L, bool TAB>
+__device__ __forceinline__ void dif_digit2(double2 (&p)[kRegs], double2 (&x)[kRegs], const TileMap& g, int t,
+                                           const double2* tab)
 {
     constexpr int LO = digit_lo<C, L>(), W = digit_w<C, L>();
     if constexpr (W > 0) {
         local_dif<LO, W>(p);
         local_dif<LO, W>(x);
-        digit_twiddle2<C, L>(p, x, g, t, false);
+        digit_twiddle2<C, L, TAB>(p, x, g, t, false, tab);
     }
 }
 
-template <int C, int L>
-__device__ __forceinline__ void dit_digit2(double2 (&p)[kRegs], double2 (&x)[kRegs], const TileMap& g, int t)
+template <int C, int L, bool TAB>
+__device__ __forceinline__ void dit_digit2(double2 (&p)[kRegs], double2 (&x)[kRegs], const TileMap& g, int t,
+                                           const double2* tab)
 {
     constexpr int LO = digit_lo<C, L>(), W = digit_w<C, L>();
     if constexpr (W > 0) {
-        digit_twiddle2<C, L>(p, x, g, t, true);
+        digit_twiddle2<C, L, TAB>(p, x, g, t, true, tab);
         local_dit<LO, W>(p);
         local_dit<LO, W>(x);
     }
 }
 
-template <int C>
+template <int C, bool TAB = false>
 __device__ __forceinline__ void dif_tile2(double2 (&p)[kRegs], double2 (&x)[kRegs], double2* lds,
-                                          const TileMap& g, int t)
+                                          const TileMap& g, int t, const double2* tab = nullptr)
 {
-    dif_digit2<C, LA>(p, x, g, t);
+    dif_digit2<C, LA, TAB>(p, x, g, t, tab);
     if constexpr (C < 8) {
         exchange2<LA, LB>(p, x, lds, t);
-        dif_digit2<C, LB>(p, x, g, t);
+        dif_digit2<C, LB, TAB>(p, x, g, t, tab);
         if constexpr (C == 0) {
             exchange2<LB, LC>(p, x, lds, t);
-            dif_digit2<C, LC>(p, x, g, t);
+            dif_digit2<C, LC, TAB>(p, x, g, t, tab);
         } else if constexpr (C == 3) {
             exchange2<LB, LA3>(p, x, lds, t);
-            dif_digit2<C, LA3>(p, x, g, t);
+            dif_digit2<C, LA3, false>(p, x, g, t, tab);
         }
     }
 }
 
-template <int C>
+template <int C, bool TAB = false>
 __device__ __forceinline__ void dit_tile2(double2 (&p)[kRegs], double2 (&x)[kRegs], double2* lds,
-                                          const TileMap& g, int t)
+                                          const TileMap& g, int t, const double2* tab = nullptr)
 {
     if constexpr (C < 8) {
         if constexpr (C == 0) {
-            dit_digit2<C, LC>(p, x, g, t);
+            dit_digit2<C, LC, TAB>(p, x, g, t, tab);
             exchange2<LC, LB>(p, x, lds, t);
         } else if constexpr (C == 3) {
-            dit_digit2<C, LA3>(p, x, g, t);
+            dit_digit2<C, LA3, false>(p, x, g, t, tab);
             exchange2<LA3, LB>(p, x, lds, t);
         }
-        dit_digit2<C, LB>(p, x, g, t);
+        dit_digit2<C, LB, TAB>(p, x, g, t, tab);
         exchange2<LB, LA>(p, x, lds, t);
     }
-    dit_digit2<C, LA>(p, x, g, t);
+    dit_digit2<C, LA, TAB>(p, x, g, t, tab);
 }
 
 // lambda_m at bit-reversed position pos (see the forward low-group pass);
@@ -284,7 +287,7 @@ __global__ __launch_bounds__(kThreads, QVA_GRADF_WAVES) void gradf_kernel(GradPa
         store2<dif_last<C>()>(p, x, P, g, t);
     } else if constexpr (MODE == GMODE_LOWDIAG) {
         load2<LA>(p, x, P, g, t);
-        dif_tile2<C>(p, x, lds, g, t);
+        dif_tile2<C, true>(p, x, lds, g, t, P.tw);
         double a1 = 0.0;
         const double2 u = P.lambda_kind == FFT_LAMBDA_RING ? ring_lambda_base(tile, t, P.n) : make_double2(0.0, 0.0);
         if (P.lambda_kind == FFT_LAMBDA_RING) {
@@ -317,7 +320,7 @@ __global__ __launch_bounds__(kThreads, QVA_GRADF_WAVES) void gradf_kernel(GradPa
             }
         }
         write_slots(P, a1 * invN, 0.0, 0.0, red, tile);
-        dit_tile2<C>(p, x, lds, g, t);
+        dit_tile2<C, true>(p, x, lds, g, t, P.tw);
         store2<LA>(p, x, P, g, t);
     } else {  // GMODE_BOUND, GMODE_FINAL
         load2<dif_last<C>()>(p, x, P, g, t);

@@ -147,6 +147,7 @@ struct FftPassParams {
     const double2* bt;    // FMODE_LOWMUL: complex multiplier in per-tile order
     double2* out;         // FMODE_LOWDIF_TILED: its output; FMODE_B_LAST_STORE: psi (nb amplitudes)
     int conj;             // FMODE_B_CHIRP: conjugate filter
+    const double2* tw;    // low-group passes (LOWDIAG, LOWMUL, LOWDIF_TILED): root table W_4096^k
 };
 
 struct SmallFftParams {
@@ -167,6 +168,83 @@ struct SmallFftParams {
 hipError_t launch_fftpass(const FftPassParams& P, hipStream_t s);
 hipError_t launch_small_fft(const SmallFftParams& P, hipStream_t s);
 hipError_t launch_lambda_tiles(const double* lam, double* out, int n, hipStream_t s);
+// The low-group root table tab[k] = W_4096^k = exp(-2 pi i k / 4096), k < 4096
+// (kTwiddleTableBytes), read by the low-group transform passes.
+constexpr size_t kTwiddleTableBytes = sizeof(double2) << kTileBits;
+hipError_t launch_twiddle_table(double2* tab, hipStream_t s);
+
+// ------------------------------------------ mixed-radix circulant (any N)
+// N = A_0 A_1 ... A_{G-1} with every prime factor <= kMrMaxPrime (see
+// qva_mrplan.h and qva_mixed.hip).
+constexpr int kMrMaxGroups = 4;
+constexpr int kMrMaxStages = 16;
+constexpr int kMrMaxPrime = 31;
+constexpr int kMrTileElems = 1 << kTileBits;  // amplitudes per tile (one vector)
+constexpr int kMrMaxStrided = 512;            // strided groups keep >= 8 columns per row
+
+struct MrGeom {
+    int G;
+    int A[kMrMaxGroups];               // group sizes, low (contiguous) first
+    int64_t S[kMrMaxGroups + 1];       // S_g = A_0 ... A_{g-1}; S_G = N
+    int nrad[kMrMaxGroups];
+    int rad[kMrMaxGroups][kMrMaxStages];  // radices of each group's DFT stages, in stage order
+    int cols[kMrMaxGroups];            // columns (independent DFTs) per tile
+    int64_t tiles[kMrMaxGroups];       // tiles of each group's passes
+    int tab_off[kMrMaxGroups];         // group g's tables start at entry tab_off[g]
+    int tab_len;                       // sum of A_g
+};
+
+// Pass modes of the mixed-radix passes (mrpass_kernel / mrgrad_kernel).
+enum : int {
+    MR_FIRST = 1,        // psi_0, phase of layer 1, forward top group
+    MR_DIF = 2,          // forward transform of one group
+    MR_DIT = 3,          // inverse transform of one group
+    MR_LOWDIAG = 4,      // low group: forward, diag(exp(-i t lambda)), inverse
+    MR_BOUNDARY = 5,     // inverse top group, 1/N, phase, forward top group
+    MR_LAST = 6,         // inverse top group, 1/N, <Q> partials
+    MR_LAST_STORE = 7,   // ... and psi_p stored
+    MR_SMALL = 8,        // N <= 4096: the whole evolution in one workgroup
+    MR_SMALL_STORE = 9,
+    // adjoint (two vectors; DIF / DIT without inner products reuse the
+    // single-vector passes once per vector)
+    MRG_TURN = 16,       // inverse top of psi_p, 1/N, <Q>, chi = Q psi_p, forward top of both
+    MRG_LOWDIAG = 17,    // low group forward, Im<chi^|lambda|phi^>/N, inverse diag, inverse
+    MRG_BOUND = 18,      // inverse top, 1/N, Im<chi|Q|phi>, inverse phase, forward top
+    MRG_FINAL = 19,      // inverse top, 1/N, Im<chi|Q|phi> (nothing written)
+    MRG_SMALL = 20       // N <= 4096: forward + adjoint in one workgroup
+};
+
+struct MrPassParams {
+    double2* psi;          // the state (phi in the adjoint)
+    double2* chi;          // the adjoint state (MRG_*)
+    const double* q;
+    const double* lam;     // FFT_LAMBDA_NATURAL: lambda[m], natural order
+    int lambda_kind;       // FFT_LAMBDA_RING or FFT_LAMBDA_NATURAL
+    Angle t, gamma;        // the diag's t (LOWDIAG), the phase's gamma
+    const double* gammas;  // MR_SMALL / MRG_SMALL: all layers
+    const double* ts;
+    int p;
+    int64_t N;
+    const MrGeom* geom;    // device copy of the geometry (written with the tables)
+    int g;                 // group of the pass
+    int64_t grid;          // workgroups of the launch (set by launch_mrpass)
+    const double2* tab;    // per group: W_{A_g}^k, k < A_g (tab_off[g]), then the
+                           // digit-reversal permutation as int32 after tab_len entries
+    double2* partials;     // per-tile (f, norm)
+    double* slot;          // per-tile gradient partial (MRG_LOWDIAG, MRG_BOUND, MRG_FINAL)
+    double* out_f;         // MR_SMALL / MRG_SMALL
+    double* out_norm;
+    double* dgammas;       // MRG_SMALL
+    double* dts;
+};
+
+// m is the host copy of *P.geom (grid sizes).
+hipError_t launch_mrpass(const MrPassParams& P, const MrGeom& m, int mode, hipStream_t s);
+// The geometry's device copy, then the root and permutation tables of every
+// group (one workgroup per group).
+hipError_t launch_mr_tables(const MrGeom& m, MrGeom* geom_dev, double2* tab, hipStream_t s);
+// Bytes of the tables of geometry m.
+size_t mr_table_bytes(const MrGeom& m);
 
 // ------------------------------------------- complete-graph mixer, closed form
 // Pass flags (see qva_complete.hip).
@@ -272,6 +350,7 @@ struct GradPassParams {
     double* slot_terms;   // GMODE_ZSLOT: term e of tile i at slot_terms[e * tiles + i]
     double* zd;           // GM_ZTERMS, GMODE_ZSLOT: d_j at the phase, indexed like psi
     int64_t nb;           // GMODE_B_*: the logical N (n above is log2 of the padded M)
+    const double2* tw;    // GMODE_LOWDIAG: low-group root table W_4096^k (twiddle_table_kernel)
 };
 
 struct SmallGradParams {

@@ -1,0 +1,686 @@
+// qva_mixed.hip -- circulant mixer over N solutions with small prime factors:
+// exp(-i t W) = F^-1 diag(exp(-i t lambda_m)) F (paper Sec. 3) with the DFT of
+// length N computed in place by mixed-radix tile passes, no padding.
+//
+// N = A_0 A_1 ... A_{G-1} (qva_mrplan.h), j = j_0 + A_0 (j_1 + A_1 (j_2 + ...)),
+// S_g = A_0 ... A_{g-1}.  Decimation in frequency, top group first: the pass of
+// group g takes, for each lower index jl < S_g (and each value of the higher
+// digits), the A_g-point DFT over j_g and multiplies output m_g by the twiddle
+// W_{S_{g+1}}^(jl m_g), W_M = exp(-2 pi i / M).  After all groups, position
+// p = sum_g p_g S_g holds X[m] with m = p_{G-1} + A_{G-1} (p_{G-2} + ... +
+// A_1 p_0): the diagonal takes lambda at that m, and the inverse passes
+// (conjugate twiddle first, then the inverse group DFT, low group first, 1/N
+// at the end) restore natural order.
+//
+// A tile is one group's A_g-point DFT for up to cols_g columns (lower
+// indices, contiguous in memory for strided groups; whole contiguous runs of
+// A_0 for the low group).  Element e of the tile (e < ncol A_g) is also its
+// LDS slot: low group col = e / A_0, j = e mod A_0; strided groups
+// j = e / ncol, col = e mod ncol, so consecutive threads touch consecutive
+// addresses in HBM.  The group DFT runs in LDS as in-place Cooley-Tukey DIF
+// stages over the group's radices (each stage a naive R-point DFT in
+// registers with exact roots, then the twiddle W_L^(i m)); the output, digit
+// reversed, is gathered back in natural order through a permutation table.
+// Roots W_{A_g}^k and the permutations are computed once per call into the
+// workspace.
+#include "qva_internal.h"
+
+namespace qva {
+namespace {
+
+constexpr int kMrThreads = 256;
+constexpr int kMrRegs = kMrTileElems / kMrThreads;
+
+// q = floor(e / d) for 0 <= e < 2^20, d >= 1 via the reciprocal rd = 1/d in
+// double: (e + 1/2) / d lies at least 1/(2d) inside (q, q + 1), far beyond
+// the rounding error of the product.
+__device__ __forceinline__ int divq(int e, double rd) { return (int)(((double)e + 0.5) * rd); }
+
+struct MrTile {
+    int A;         // transform length of the group
+    int ncol;      // columns of this tile
+    bool low;      // group 0: contiguous columns of A_0
+    int64_t base;  // global index of element (col 0, j 0)
+    int64_t S;     // global stride of j (strided groups)
+    int64_t first; // first column's index: upper index (low group) or lower index jl
+    double rA, rncol;
+    __device__ __forceinline__ int col_of(int e) const { return low ? divq(e, rA) : e - ncol * divq(e, rncol); }
+    __device__ __forceinline__ int j_of(int e) const { return low ? e - A * divq(e, rA) : divq(e, rncol); }
+    __device__ __forceinline__ int lidx(int col, int j) const { return low ? col * A + j : j * ncol + col; }
+    __device__ __forceinline__ int64_t gidx(int e) const
+    {
+        if (low)
+            return base + e;
+        const int j = divq(e, rncol);
+        return base + (e - ncol * j) + S * (int64_t)j;
+    }
+};
+
+__device__ __forceinline__ MrTile mr_tile(const MrGeom* __restrict__ m, int g, int64_t tile)
+{
+    MrTile T;
+    T.A = m->A[g];
+    T.low = g == 0;
+    const int c = m->cols[g];
+    if (g == 0) {
+        const int64_t U = m->S[m->G] / T.A;
+        const int64_t u0 = tile * c;
+        T.ncol = (int)(U - u0 < c ? U - u0 : c);
+        T.base = u0 * T.A;
+        T.S = 1;
+        T.first = u0;
+    } else {
+        const int64_t Sg = m->S[g];
+        const int64_t chunks = (Sg + c - 1) / c;
+        const int64_t w = tile / chunks, ch = tile - w * chunks;
+        const int64_t jl0 = ch * c;
+        T.ncol = (int)(Sg - jl0 < c ? Sg - jl0 : c);
+        T.base = jl0 + m->S[g + 1] * w;
+        T.S = Sg;
+        T.first = jl0;
+    }
+    T.rA = 1.0 / (double)T.A;
+    T.rncol = 1.0 / (double)T.ncol;
+    return T;
+}
+
+__device__ __forceinline__ double2 conj_if(double2 a, bool c) { return make_double2(a.x, c ? -a.y : a.y); }
+
+// One DIF stage of radix R over sub-length L of every column's A-point DFT
+// in LDS: butterfly (b, i), i < L/R, takes elements b L + i + k L/R, forms
+// y_m = sum_k x_k W_R^(k m), multiplies y_m by W_L^(i m) and writes it back
+// in place.  Roots from the group table tab[k] = W_A^k (conjugated: inverse).
+// LDS slot of (col, j): col A + j (low group) or j ncol + col.
+template <int R>
+__device__ __forceinline__ void mr_stage(double2* lds, int A, int ncol, bool low, int L,
+                                         const double2* __restrict__ tab, bool inv)
+{
+    const int mstride = L / R, per_col = A / R, tstep = A / L;
+    const int items = ncol * per_col;
+    const double rpc = 1.0 / (double)per_col, rms = 1.0 / (double)mstride, rnc = 1.0 / (double)ncol;
+    const int cs = low ? A : 1, js = low ? 1 : ncol;  // LDS strides of col and j
+    double2 w[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k)
+        w[k] = k == 0 ? make_double2(1.0, 0.0) : conj_if(tab[k * (A / R)], inv);
+    for (int it = threadIdx.x; it < items; it += kMrThreads) {
+        int col, bi;
+        if (low) {  // i fastest: consecutive threads take consecutive j
+            col = divq(it, rpc);
+            bi = it - col * per_col;
+        } else {    // col fastest: consecutive LDS slots
+            bi = divq(it, rnc);
+            col = it - bi * ncol;
+        }
+        const int b = divq(bi, rms), i = bi - b * mstride;
+        const int base = col * cs + (b * L + i) * js, step = mstride * js;
+        double2 x[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            x[k] = lds[base + k * step];
+#pragma unroll
+        for (int mm = 0; mm < R; ++mm) {
+            double2 acc = x[0];
+#pragma unroll
+            for (int k = 1; k < R; ++k) {
+                const double2 r = w[(k * mm) % R];
+                acc.x = fma(x[k].x, r.x, fma(-x[k].y, r.y, acc.x));
+                acc.y = fma(x[k].x, r.y, fma(x[k].y, r.x, acc.y));
+            }
+            if (mm > 0 && i > 0)
+                acc = cmul(acc, conj_if(tab[i * mm * tstep], inv));
+            lds[base + mm * step] = acc;
+        }
+    }
+}
+
+// Every DIF stage of one group's DFT on the tile in LDS (one copy of the
+// stage code, called from each pass).
+__device__ __noinline__ void mr_stages(double2* lds, int A, int ncol, bool low, const double2* __restrict__ gt,
+                                       const int* __restrict__ rad, int nrad, bool inv)
+{
+    int L = A;
+    for (int s = 0; s < nrad; ++s) {
+        const int r = rad[s];
+        switch (r) {
+        case 2: mr_stage<2>(lds, A, ncol, low, L, gt, inv); break;
+        case 3: mr_stage<3>(lds, A, ncol, low, L, gt, inv); break;
+        case 4: mr_stage<4>(lds, A, ncol, low, L, gt, inv); break;
+        case 5: mr_stage<5>(lds, A, ncol, low, L, gt, inv); break;
+        case 7: mr_stage<7>(lds, A, ncol, low, L, gt, inv); break;
+        case 8: mr_stage<8>(lds, A, ncol, low, L, gt, inv); break;
+        case 11: mr_stage<11>(lds, A, ncol, low, L, gt, inv); break;
+        case 13: mr_stage<13>(lds, A, ncol, low, L, gt, inv); break;
+        case 16: mr_stage<16>(lds, A, ncol, low, L, gt, inv); break;
+        case 17: mr_stage<17>(lds, A, ncol, low, L, gt, inv); break;
+        case 19: mr_stage<19>(lds, A, ncol, low, L, gt, inv); break;
+        case 23: mr_stage<23>(lds, A, ncol, low, L, gt, inv); break;
+        case 29: mr_stage<29>(lds, A, ncol, low, L, gt, inv); break;
+        default: mr_stage<31>(lds, A, ncol, low, L, gt, inv); break;
+        }
+        L /= r;
+        __syncthreads();
+    }
+}
+
+// The group DFT of every column of the tile, through LDS: v holds elements
+// e = t + 256 k in natural j order on entry and natural frequency order on
+// return (forward: exponent sign -, inv: +; no 1/A).
+__device__ __forceinline__ void mr_dft(double2 (&v)[kMrRegs], double2* lds, const MrTile& T,
+                                       const MrGeom* __restrict__ m, int g, const double2* tab, const int* perm,
+                                       bool inv)
+{
+    const int t = threadIdx.x, ne = T.ncol * T.A;
+    const int* gp = perm + m->tab_off[g];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kMrRegs; ++k) {
+        const int e = t + k * kMrThreads;
+        if (e < ne)
+            lds[e] = v[k];
+    }
+    __syncthreads();
+    mr_stages(lds, T.A, T.ncol, T.low, tab + m->tab_off[g], m->rad[g], m->nrad[g], inv);
+#pragma unroll
+    for (int k = 0; k < kMrRegs; ++k) {
+        const int e = t + k * kMrThreads;
+        v[k] = e < ne ? lds[T.lidx(T.col_of(e), gp[T.j_of(e)])] : make_double2(0.0, 0.0);
+    }
+}
+
+// The twiddle between groups: element (col, m_g) of a strided group's tile
+// times W_{S_{g+1}}^(jl m_g) (conjugated: inverse), jl = first + col.
+__device__ __forceinline__ void mr_twiddle(double2 (&v)[kMrRegs], const MrTile& T, const MrGeom* __restrict__ m, int g, bool inv)
+{
+    if (T.low)
+        return;  // S_0 = 1: no lower index
+    const int t = threadIdx.x, ne = T.ncol * T.A;
+    const double Sn = (double)m->S[g + 1];
+#pragma unroll
+    for (int k = 0; k < kMrRegs; ++k) {
+        const int e = t + k * kMrThreads;
+        if (e < ne) {
+            const int64_t ex = (T.first + T.col_of(e)) * (int64_t)T.j_of(e);  // < S_{g+1} < 2^31
+            if (ex) {
+                double s, c;
+                sincospi_red((double)(2 * ex) / Sn, &s, &c);
+                v[k] = cmul(v[k], make_double2(c, inv ? s : -s));
+            }
+        }
+        QVA_SCHED_FENCE();
+    }
+}
+
+__device__ __forceinline__ void mr_forward(double2 (&v)[kMrRegs], double2* lds, const MrTile& T, const MrGeom* m,
+                                           int g, const double2* tab, const int* perm)
+{
+    mr_dft(v, lds, T, m, g, tab, perm, false);
+    mr_twiddle(v, T, m, g, false);
+}
+
+__device__ __forceinline__ void mr_inverse(double2 (&v)[kMrRegs], double2* lds, const MrTile& T, const MrGeom* m,
+                                           int g, const double2* tab, const int* perm)
+{
+    mr_twiddle(v, T, m, g, true);
+    mr_dft(v, lds, T, m, g, tab, perm, true);
+}
+
+__device__ __forceinline__ void mr_load(double2 (&v)[kMrRegs], const double2* psi, const MrTile& T)
+{
+    const int t = threadIdx.x, ne = T.ncol * T.A;
+#pragma unroll
+    for (int k = 0; k < kMrRegs; ++k) {
+        const int e = t + k * kMrThreads;
+        v[k] = e < ne ? ld_nt(psi + T.gidx(e)) : make_double2(0.0, 0.0);
+    }
+}
+
+__device__ __forceinline__ void mr_store(const double2 (&v)[kMrRegs], double2* psi, const MrTile& T, double scale)
+{
+    const int t = threadIdx.x, ne = T.ncol * T.A;
+#pragma unroll
+    for (int k = 0; k < kMrRegs; ++k) {
+        const int e = t + k * kMrThreads;
+        if (e < ne)
+            st_nt(psi + T.gidx(e), make_double2(v[k].x * scale, v[k].y * scale));
+    }
+}
+
+// The global frequency m held by element (col, f) of a low-group tile after
+// its forward DFT: m = rev(u) + (N / A_0) f, u = first + col the upper index
+// and rev(u) = p_{G-1} + A_{G-1} (p_{G-2} + ... + A_2 p_1) for
+// u = p_1 + A_1 (p_2 + ...).
+__device__ __forceinline__ int64_t mr_freq(const MrGeom* __restrict__ m, int64_t u, int f)
+{
+    int64_t rev = 0;
+    const int G = m->G;
+    for (int g = 1; g < G; ++g) {
+        const int64_t A = m->A[g];
+        const int64_t d = u % A;
+        u /= A;
+        rev = rev * A + d;
+    }
+    return rev + (m->S[G] / m->A[0]) * (int64_t)f;
+}
+
+__device__ __forceinline__ double mr_lambda(const MrPassParams& P, int64_t mfreq)
+{
+    if (P.lambda_kind == FFT_LAMBDA_RING) {
+        double s, c;
+        sincospi_red((double)(2 * mfreq) / (double)P.N, &s, &c);  // 2 cos(2 pi m / N)
+        return 2.0 * c;
+    }
+    return P.lam[mfreq];
+}
+
+// psi <- exp(-i tt lambda_m) psi at the frequencies of a low-group tile
+// (natural order after mr_forward).
+__device__ __forceinline__ void mr_diag(double2 (&v)[kMrRegs], const MrPassParams& P, const MrTile& T, double tt)
+{
+    const int t = threadIdx.x, ne = T.ncol * T.A;
+#pragma unroll
+    for (int k = 0; k < kMrRegs; ++k) {
+        const int e = t + k * kMrThreads;
+        if (e < ne) {
+            const int64_t mf = mr_freq(P.geom, T.first + T.col_of(e), T.j_of(e));
+            v[k] = cmul(v[k], expmi(tt * mr_lambda(P, mf)));
+        }
+        QVA_SCHED_FENCE();
+    }
+}
+
+// psi <- scale exp(-i gamma q) psi in natural order.
+__device__ __forceinline__ void mr_phase(double2 (&v)[kMrRegs], const double* q, const MrTile& T, double gamma, double scale)
+{
+    const int t = threadIdx.x, ne = T.ncol * T.A;
+#pragma unroll
+    for (int k = 0; k < kMrRegs; ++k) {
+        const int e = t + k * kMrThreads;
+        if (e < ne) {
+            const double2 ph = expmi(gamma * ld_nt(q + T.gidx(e)));
+            v[k] = cmul(v[k], make_double2(scale * ph.x, scale * ph.y));
+        }
+        QVA_SCHED_FENCE();
+    }
+}
+
+__device__ __forceinline__ void mr_expect(const double2 (&v)[kMrRegs], const double* q, const MrTile& T, double* red,
+                          double2* out)
+{
+    const int t = threadIdx.x, ne = T.ncol * T.A;
+    double f = 0.0, nr = 0.0;
+#pragma unroll
+    for (int k = 0; k < kMrRegs; ++k) {
+        const int e = t + k * kMrThreads;
+        if (e < ne) {
+            const double a = v[k].x * v[k].x + v[k].y * v[k].y;
+            f = fma(a, ld_nt(q + T.gidx(e)), f);
+            nr += a;
+        }
+    }
+    const double2 tot = block_sum2(f, nr, red);
+    if (t == 0)
+        *out = tot;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kMrThreads, 2) void mrpass_kernel(MrPassParams P)
+{
+    __shared__ double2 lds[kMrTileElems];
+    __shared__ double red[2 * (kMrThreads / 64)];
+    const MrGeom* __restrict__ m = P.geom;
+    const int g = P.g;
+    const MrTile T = mr_tile(m, g, blockIdx.x);
+    const int* perm = reinterpret_cast<const int*>(P.tab + m->tab_len);
+    const double invN = 1.0 / (double)P.N;
+    double2 v[kMrRegs];
+    if constexpr (MODE == MR_FIRST) {
+        const double a0 = 1.0 / sqrt((double)P.N);
+#pragma unroll
+        for (int k = 0; k < kMrRegs; ++k)
+            v[k] = make_double2(a0, 0.0);
+        mr_phase(v, P.q, T, angle_value(P.gamma), 1.0);
+        mr_forward(v, lds, T, m, g, P.tab, perm);
+        mr_store(v, P.psi, T, 1.0);
+    } else if constexpr (MODE == MR_DIF) {
+        mr_load(v, P.psi, T);
+        mr_forward(v, lds, T, m, g, P.tab, perm);
+        mr_store(v, P.psi, T, 1.0);
+    } else if constexpr (MODE == MR_DIT) {
+        mr_load(v, P.psi, T);
+        mr_inverse(v, lds, T, m, g, P.tab, perm);
+        mr_store(v, P.psi, T, 1.0);
+    } else if constexpr (MODE == MR_LOWDIAG) {
+        mr_load(v, P.psi, T);
+        mr_forward(v, lds, T, m, g, P.tab, perm);
+        mr_diag(v, P, T, angle_value(P.t));
+        mr_inverse(v, lds, T, m, g, P.tab, perm);
+        mr_store(v, P.psi, T, 1.0);
+    } else if constexpr (MODE == MR_BOUNDARY) {
+        const double gam = angle_value(P.gamma);
+        mr_load(v, P.psi, T);
+        mr_inverse(v, lds, T, m, g, P.tab, perm);
+        mr_phase(v, P.q, T, gam, invN);
+        mr_forward(v, lds, T, m, g, P.tab, perm);
+        mr_store(v, P.psi, T, 1.0);
+    } else {  // MR_LAST, MR_LAST_STORE
+        mr_load(v, P.psi, T);
+        mr_inverse(v, lds, T, m, g, P.tab, perm);
+#pragma unroll
+        for (int k = 0; k < kMrRegs; ++k)
+            v[k] = make_double2(v[k].x * invN, v[k].y * invN);
+        mr_expect(v, P.q, T, red, P.partials + blockIdx.x);
+        if constexpr (MODE == MR_LAST_STORE)
+            mr_store(v, P.psi, T, 1.0);
+    }
+}
+
+// Sum over the tile of h_j Im(conj(x_j) p_j) (h = q or lambda).
+__device__ __forceinline__ double im_term(double2 x, double2 p) { return x.x * p.y - x.y * p.x; }
+
+// Two-vector passes of the adjoint walk (phi = psi, chi): the same group
+// transforms applied to each vector in turn through one LDS buffer, with the
+// inner products taken where both are at hand.  Passes with per-tile slots
+// run on max_tiles workgroups: those beyond the group's tiles write a zero.
+template <int MODE>
+__global__ __launch_bounds__(kMrThreads, 1) void mrgrad_kernel(MrPassParams P)
+{
+    __shared__ double2 lds[kMrTileElems];
+    __shared__ double red[2 * (kMrThreads / 64)];
+    const MrGeom* __restrict__ m = P.geom;
+    const int g = P.g;
+    const int t = threadIdx.x;
+    if (blockIdx.x >= m->tiles[g]) {
+        if (P.slot && t == 0)
+            P.slot[blockIdx.x] = 0.0;
+        return;
+    }
+    const MrTile T = mr_tile(m, g, blockIdx.x);
+    const int* perm = reinterpret_cast<const int*>(P.tab + m->tab_len);
+    const double invN = 1.0 / (double)P.N;
+    const int ne = T.ncol * T.A;
+    double2 p[kMrRegs], x[kMrRegs];
+    if constexpr (MODE == MRG_TURN) {
+        mr_load(p, P.psi, T);
+        mr_inverse(p, lds, T, m, g, P.tab, perm);
+        double f = 0.0, nr = 0.0;
+#pragma unroll
+        for (int k = 0; k < kMrRegs; ++k) {
+            const int e = t + k * kMrThreads;
+            p[k] = make_double2(p[k].x * invN, p[k].y * invN);
+            const double qq = e < ne ? ld_nt(P.q + T.gidx(e)) : 0.0;
+            const double a = p[k].x * p[k].x + p[k].y * p[k].y;
+            f = fma(a, qq, f);
+            nr += a;
+            x[k] = make_double2(qq * p[k].x, qq * p[k].y);
+        }
+        const double2 tot = block_sum2(f, nr, red);
+        if (t == 0)
+            P.partials[blockIdx.x] = tot;
+        mr_forward(p, lds, T, m, g, P.tab, perm);
+        mr_forward(x, lds, T, m, g, P.tab, perm);
+        mr_store(p, P.psi, T, 1.0);
+        mr_store(x, P.chi, T, 1.0);
+    } else if constexpr (MODE == MRG_LOWDIAG) {
+        const double tt = angle_value(P.t);
+        mr_load(p, P.psi, T);
+        mr_load(x, P.chi, T);
+        mr_forward(p, lds, T, m, g, P.tab, perm);
+        mr_forward(x, lds, T, m, g, P.tab, perm);
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < kMrRegs; ++k) {
+            const int e = t + k * kMrThreads;
+            if (e < ne) {
+                const double lam = mr_lambda(P, mr_freq(m, T.first + T.col_of(e), T.j_of(e)));
+                acc = fma(lam, im_term(x[k], p[k]), acc);
+                const double2 d = expmi(-tt * lam);  // exp(+i t lambda): the inverse diagonal
+                p[k] = cmul(p[k], d);
+                x[k] = cmul(x[k], d);
+            }
+            QVA_SCHED_FENCE();
+        }
+        const double2 tot = block_sum2(acc * invN, 0.0, red);
+        if (t == 0)
+            P.slot[blockIdx.x] = tot.x;
+        mr_inverse(p, lds, T, m, g, P.tab, perm);
+        mr_inverse(x, lds, T, m, g, P.tab, perm);
+        mr_store(p, P.psi, T, 1.0);
+        mr_store(x, P.chi, T, 1.0);
+    } else {  // MRG_BOUND, MRG_FINAL
+        mr_load(p, P.psi, T);
+        mr_load(x, P.chi, T);
+        mr_inverse(p, lds, T, m, g, P.tab, perm);
+        mr_inverse(x, lds, T, m, g, P.tab, perm);
+        const double gam = angle_value(P.gamma);
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < kMrRegs; ++k) {
+            const int e = t + k * kMrThreads;
+            p[k] = make_double2(p[k].x * invN, p[k].y * invN);
+            x[k] = make_double2(x[k].x * invN, x[k].y * invN);
+            if (e < ne) {
+                const double qq = ld_nt(P.q + T.gidx(e));
+                acc = fma(qq, im_term(x[k], p[k]), acc);
+                if constexpr (MODE == MRG_BOUND) {
+                    const double2 u = expmi(-gam * qq);  // exp(+i gamma q): the inverse phase
+                    p[k] = cmul(p[k], u);
+                    x[k] = cmul(x[k], u);
+                }
+            }
+            QVA_SCHED_FENCE();
+        }
+        const double2 tot = block_sum2(acc, 0.0, red);
+        if (t == 0)
+            P.slot[blockIdx.x] = tot.x;
+        if constexpr (MODE == MRG_BOUND) {
+            mr_forward(p, lds, T, m, g, P.tab, perm);
+            mr_forward(x, lds, T, m, g, P.tab, perm);
+            mr_store(p, P.psi, T, 1.0);
+            mr_store(x, P.chi, T, 1.0);
+        }
+    }
+}
+
+// N <= 4096 (one group): the whole evolution, and with MRG_SMALL the adjoint
+// walk, in one workgroup.
+template <int MODE>
+__global__ __launch_bounds__(kMrThreads, 1) void mrsmall_kernel(MrPassParams P)
+{
+    __shared__ double2 lds[kMrTileElems];
+    __shared__ double red[2 * (kMrThreads / 64)];
+    const MrGeom* __restrict__ m = P.geom;
+    const MrTile T = mr_tile(m, 0, 0);
+    const int* perm = reinterpret_cast<const int*>(P.tab + m->tab_len);
+    const int t = threadIdx.x, ne = T.ncol * T.A;
+    const double invN = 1.0 / (double)P.N;
+    double2 p[kMrRegs];
+    const double a0 = 1.0 / sqrt((double)P.N);
+#pragma unroll
+    for (int k = 0; k < kMrRegs; ++k)
+        p[k] = make_double2(t + k * kMrThreads < ne ? a0 : 0.0, 0.0);
+    for (int L = 0; L < P.p; ++L) {
+        mr_phase(p, P.q, T, P.gammas[L], 1.0);
+        mr_dft(p, lds, T, m, 0, P.tab, perm, false);
+        mr_diag(p, P, T, P.ts[L]);
+        mr_dft(p, lds, T, m, 0, P.tab, perm, true);
+#pragma unroll
+        for (int k = 0; k < kMrRegs; ++k)
+            p[k] = make_double2(p[k].x * invN, p[k].y * invN);
+    }
+    double2 fv;
+    {
+        double f = 0.0, nr = 0.0;
+#pragma unroll
+        for (int k = 0; k < kMrRegs; ++k) {
+            const int e = t + k * kMrThreads;
+            if (e < ne) {
+                const double a = p[k].x * p[k].x + p[k].y * p[k].y;
+                f = fma(a, P.q[e], f);
+                nr += a;
+            }
+        }
+        fv = block_sum2(f, nr, red);
+    }
+    if (t == 0) {
+        P.out_f[0] = fv.x;
+        if (P.out_norm)
+            P.out_norm[0] = fv.y;
+    }
+    if constexpr (MODE == MR_SMALL_STORE)
+        mr_store(p, P.psi, T, 1.0);
+    if constexpr (MODE == MRG_SMALL) {
+        double2 x[kMrRegs];
+#pragma unroll
+        for (int k = 0; k < kMrRegs; ++k) {
+            const int e = t + k * kMrThreads;
+            const double qq = e < ne ? P.q[e] : 0.0;
+            x[k] = make_double2(qq * p[k].x, qq * p[k].y);
+        }
+        for (int L = P.p - 1; L >= 0; --L) {
+            // the mixer of layer L: Im <chi|W|phi> at the spectrum, then undone
+            mr_dft(p, lds, T, m, 0, P.tab, perm, false);
+            mr_dft(x, lds, T, m, 0, P.tab, perm, false);
+            double acc = 0.0;
+            const double tt = P.ts[L];
+#pragma unroll
+            for (int k = 0; k < kMrRegs; ++k) {
+                const int e = t + k * kMrThreads;
+                if (e < ne) {
+                    const double lam = mr_lambda(P, mr_freq(m, 0, e));
+                    acc = fma(lam, im_term(x[k], p[k]), acc);
+                    const double2 d = expmi(-tt * lam);
+                    p[k] = cmul(p[k], d);
+                    x[k] = cmul(x[k], d);
+                }
+            }
+            const double2 st = block_sum2(acc * invN, 0.0, red);
+            if (t == 0)
+                P.dts[L] = 2.0 * st.x;
+            mr_dft(p, lds, T, m, 0, P.tab, perm, true);
+            mr_dft(x, lds, T, m, 0, P.tab, perm, true);
+            // the phase of layer L
+            const double gam = P.gammas[L];
+            acc = 0.0;
+#pragma unroll
+            for (int k = 0; k < kMrRegs; ++k) {
+                const int e = t + k * kMrThreads;
+                p[k] = make_double2(p[k].x * invN, p[k].y * invN);
+                x[k] = make_double2(x[k].x * invN, x[k].y * invN);
+                if (e < ne) {
+                    const double qq = P.q[e];
+                    acc = fma(qq, im_term(x[k], p[k]), acc);
+                    const double2 u = expmi(-gam * qq);
+                    p[k] = cmul(p[k], u);
+                    x[k] = cmul(x[k], u);
+                }
+            }
+            const double2 sg = block_sum2(acc, 0.0, red);
+            if (t == 0)
+                P.dgammas[L] = 2.0 * sg.x;
+        }
+    }
+}
+
+// The geometry's device copy (the passes read it from there: indexing a
+// by-value kernel argument with runtime indices would copy it to scratch).
+__global__ __launch_bounds__(64) void mr_geom_kernel(MrGeom m, MrGeom* out)
+{
+    if (threadIdx.x == 0)
+        *out = m;
+}
+
+// Group g's roots W_{A_g}^k and the digit-reversal permutation of its DIF
+// stages: frequency f = d_0 + r_0 (d_1 + r_1 (...)) sits at position
+// sum_s d_s L_s / r_s (L_s the sub-length of stage s).  Reads the device
+// copy of the geometry.
+__global__ __launch_bounds__(256) void mr_table_kernel(const MrGeom* __restrict__ m, double2* tab)
+{
+    const int g = blockIdx.x;
+    const int A = m->A[g];
+    int* perm = reinterpret_cast<int*>(tab + m->tab_len) + m->tab_off[g];
+    for (int k = threadIdx.x; k < A; k += blockDim.x) {
+        // exp(-2 pi i k / A), with 2k / A rounded once (exact for A a power of two)
+        double s, c;
+        sincospi_red((double)(2 * k) / (double)A, &s, &c);
+        tab[m->tab_off[g] + k] = make_double2(c, -s);
+        int f = k, L = A, pos = 0;
+        for (int st = 0; st < m->nrad[g]; ++st) {
+            const int r = m->rad[g][st];
+            const int d = f % r;
+            f /= r;
+            L /= r;
+            pos += d * L;
+        }
+        perm[k] = pos;
+    }
+}
+
+}  // namespace
+
+size_t mr_table_bytes(const MrGeom& m)
+{
+    return (size_t)m.tab_len * (sizeof(double2) + sizeof(int));
+}
+
+hipError_t launch_mr_tables(const MrGeom& m, MrGeom* geom_dev, double2* tab, hipStream_t s)
+{
+    hipLaunchKernelGGL(mr_geom_kernel, dim3(1), dim3(64), 0, s, m, geom_dev);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(mr_table_kernel, dim3(m.G), dim3(256), 0, s, geom_dev, tab);
+    return hipGetLastError();
+}
+
+hipError_t launch_mrpass(const MrPassParams& P0, const MrGeom& m, int mode, hipStream_t s)
+{
+    int64_t maxt = 0;
+    for (int g = 0; g < m.G; ++g)
+        maxt = m.tiles[g] > maxt ? m.tiles[g] : maxt;
+    MrPassParams P = P0;
+    const bool wide = mode == MRG_LOWDIAG || mode == MRG_BOUND || mode == MRG_FINAL;
+    P.grid = (mode == MR_SMALL || mode == MR_SMALL_STORE || mode == MRG_SMALL) ? 1 : (wide ? maxt : m.tiles[P.g]);
+    const dim3 grid((unsigned)P.grid);
+    const dim3 gridmax((unsigned)P.grid);
+    switch (mode) {
+#define QVA_MR_MODE(M) \
+    case M:            \
+        hipLaunchKernelGGL((mrpass_kernel<M>), grid, dim3(kMrThreads), 0, s, P); \
+        break;
+        QVA_MR_MODE(MR_FIRST)
+        QVA_MR_MODE(MR_DIF)
+        QVA_MR_MODE(MR_DIT)
+        QVA_MR_MODE(MR_LOWDIAG)
+        QVA_MR_MODE(MR_BOUNDARY)
+        QVA_MR_MODE(MR_LAST)
+        QVA_MR_MODE(MR_LAST_STORE)
+#undef QVA_MR_MODE
+    case MR_SMALL:
+        hipLaunchKernelGGL((mrsmall_kernel<MR_SMALL>), dim3(1), dim3(kMrThreads), 0, s, P);
+        break;
+    case MR_SMALL_STORE:
+        hipLaunchKernelGGL((mrsmall_kernel<MR_SMALL_STORE>), dim3(1), dim3(kMrThreads), 0, s, P);
+        break;
+    case MRG_SMALL:
+        hipLaunchKernelGGL((mrsmall_kernel<MRG_SMALL>), dim3(1), dim3(kMrThreads), 0, s, P);
+        break;
+    case MRG_TURN:
+        hipLaunchKernelGGL((mrgrad_kernel<MRG_TURN>), grid, dim3(kMrThreads), 0, s, P);
+        break;
+    case MRG_LOWDIAG:
+        hipLaunchKernelGGL((mrgrad_kernel<MRG_LOWDIAG>), gridmax, dim3(kMrThreads), 0, s, P);
+        break;
+    case MRG_BOUND:
+        hipLaunchKernelGGL((mrgrad_kernel<MRG_BOUND>), gridmax, dim3(kMrThreads), 0, s, P);
+        break;
+    case MRG_FINAL:
+        hipLaunchKernelGGL((mrgrad_kernel<MRG_FINAL>), gridmax, dim3(kMrThreads), 0, s, P);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace qva

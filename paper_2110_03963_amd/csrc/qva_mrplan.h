@@ -1,0 +1,218 @@
+// qva_mrplan.h -- host planning of the mixed-radix circulant passes.
+//
+// A circulant mixer over N solutions (N not a power of two, e.g. the C(m, k)
+// feasible subsets of a constrained QWOA, paper Sec. 2.4.2) is diagonal in
+// the DFT of length N (Sec. 3).  When every prime factor of N is at most
+// kMrMaxPrime, the DFT is done in place by tile passes over a factorisation
+// N = A_0 A_1 ... A_{G-1}: the index j = j_0 + A_0 (j_1 + A_1 (j_2 + ...)),
+// group 0 contiguous (A_0 <= 4096 amplitudes, a tile holds whole columns of
+// it), groups g >= 1 strided by S_g = A_0 ... A_{g-1} (A_g <= 512, so a tile
+// keeps at least 8 contiguous amplitudes per row).  Each group's A_g-point
+// DFT runs in LDS as Cooley-Tukey stages over the group's radices; N with a
+// larger prime factor takes Bluestein's transform instead.
+#pragma once
+
+#include <algorithm>
+#include <cstdint>
+#include <functional>
+#include <vector>
+
+#include "qva_internal.h"
+
+namespace qva {
+
+// Prime factors of N in ascending order (N >= 2).
+inline std::vector<int> prime_factors(int64_t N)
+{
+    std::vector<int> f;
+    for (int64_t p = 2; p * p <= N; ++p)
+        while (N % p == 0) {
+            f.push_back((int)p);
+            N /= p;
+        }
+    if (N > 1)
+        f.push_back(N > INT32_MAX ? -1 : (int)N);
+    return f;
+}
+
+// Radices of one group's DFT: its odd primes, and its factors of 2 merged
+// into radix 16, 8, 4 or 2 stages.
+inline std::vector<int> mr_radices(std::vector<int> primes)
+{
+    std::vector<int> r;
+    int twos = 0;
+    for (int p : primes) {
+        if (p == 2)
+            ++twos;
+        else
+            r.push_back(p);
+    }
+    while (twos >= 4) {
+        r.push_back(16);
+        twos -= 4;
+    }
+    if (twos > 0)
+        r.push_back(1 << twos);
+    std::sort(r.begin(), r.end(), [](int a, int b) { return a > b; });
+    return r;
+}
+
+inline int mr_cols(int A, int64_t lower_or_upper)
+{
+    int64_t c = kMrTileElems / A;
+    if (c > lower_or_upper)
+        c = lower_or_upper;
+    return (int)(c < 1 ? 1 : c);
+}
+
+// The factorisation: the fewest groups for which the prime factors fit the
+// caps (A_0 <= 4096, A_g <= 512), then the assignment whose tiles are fullest
+// (sum over groups of the used fraction of a 4096-element tile; ties to the
+// larger contiguous group).  Identical primes are assigned by count, so the
+// search is over compositions.  Returns false when some prime factor exceeds
+// kMrMaxPrime or no assignment into kMrMaxGroups groups fits.
+inline bool mr_plan(int64_t N, MrGeom& out)
+{
+    if (N < 2 || N >= (int64_t(1) << 31))
+        return false;
+    const std::vector<int> pf = prime_factors(N);
+    std::vector<std::pair<int, int>> pe;  // (prime, multiplicity)
+    for (int p : pf) {
+        if (p < 0 || p > kMrMaxPrime)
+            return false;
+        if (!pe.empty() && pe.back().first == p)
+            ++pe.back().second;
+        else
+            pe.push_back({p, 1});
+    }
+    for (int G = 1; G <= kMrMaxGroups; ++G) {
+        if (G == 1 && N > kMrTileElems)
+            continue;
+        std::vector<int64_t> prod(G, 1);
+        std::vector<std::vector<int>> cnt(pe.size(), std::vector<int>(G, 0)), best_cnt;
+        double best = -1.0;
+        std::function<void(size_t, int, int)> rec = [&](size_t i, int g, int left) {
+            if (i == pe.size()) {
+                double score = 0.0;
+                for (int h = 0; h < G; ++h) {
+                    if (prod[h] == 1)
+                        return;  // every group takes a factor
+                    const int A = (int)prod[h];
+                    score += (double)(A * (int64_t)mr_cols(A, h == 0 ? N / A : N)) / kMrTileElems;
+                }
+                score += 1e-9 * (double)prod[0];
+                if (score > best) {
+                    best = score;
+                    best_cnt = cnt;
+                }
+                return;
+            }
+            if (g == G - 1) {  // the rest of prime i goes to the last group
+                const int p = pe[i].first;
+                int64_t f = 1;
+                for (int k = 0; k < left; ++k)
+                    f *= p;
+                const int64_t cap = g == 0 ? kMrTileElems : kMrMaxStrided;
+                if (prod[g] * f > cap)
+                    return;
+                prod[g] *= f;
+                cnt[i][g] = left;
+                rec(i + 1, 0, i + 1 < pe.size() ? pe[i + 1].second : 0);
+                prod[g] /= f;
+                cnt[i][g] = 0;
+                return;
+            }
+            const int p = pe[i].first;
+            const int64_t cap = g == 0 ? kMrTileElems : kMrMaxStrided;
+            int64_t f = 1;
+            for (int k = 0; k <= left; ++k) {
+                if (prod[g] * f > cap)
+                    break;
+                prod[g] *= f;
+                cnt[i][g] = k;
+                rec(i, g + 1, left - k);
+                prod[g] /= f;
+                cnt[i][g] = 0;
+                f *= p;
+            }
+        };
+        rec(0, 0, pe[0].second);
+        if (best < 0.0)
+            continue;
+        MrGeom m{};
+        m.G = G;
+        int64_t S = 1;
+        int tab = 0;
+        for (int g = 0; g < G; ++g) {
+            std::vector<int> primes;
+            int A = 1;
+            for (size_t i = 0; i < pe.size(); ++i)
+                for (int k = 0; k < best_cnt[i][g]; ++k) {
+                    primes.push_back(pe[i].first);
+                    A *= pe[i].first;
+                }
+            m.A[g] = A;
+            m.S[g] = S;
+            const std::vector<int> r = mr_radices(primes);
+            m.nrad[g] = (int)r.size();
+            for (size_t i = 0; i < r.size(); ++i)
+                m.rad[g][i] = r[i];
+            m.cols[g] = g == 0 ? mr_cols(A, N / A) : mr_cols(A, S);
+            m.tab_off[g] = tab;
+            tab += A;
+            S *= A;
+        }
+        m.S[G] = S;
+        m.tab_len = tab;
+        for (int g = 0; g < G; ++g) {
+            const int64_t cols_total = g == 0 ? N / m.A[0] : m.S[g];
+            const int64_t chunks = (cols_total + m.cols[g] - 1) / m.cols[g];
+            m.tiles[g] = g == 0 ? chunks : chunks * (N / m.S[g + 1]);
+        }
+        out = m;
+        return true;
+    }
+    return false;
+}
+
+// Tiles of the widest pass (per-tile partial sums and gradient slots).
+inline int64_t mr_max_tiles(const MrGeom& m)
+{
+    int64_t t = 0;
+    for (int g = 0; g < m.G; ++g)
+        t = std::max(t, m.tiles[g]);
+    return t;
+}
+
+// Pass list of a p-layer evolution over G >= 2 groups (as fft_evolve_plan
+// for the power-of-two transform): the top group's inverse of layer k, the
+// phase of k+1 and its forward share one pass; the low group's pass applies
+// the diagonal between its forward and inverse halves.  (One group, N <= 4096:
+// the whole evolution is one workgroup's launch, MR_SMALL.)
+struct MrPass {
+    int group;
+    int mode;         // MR_*
+    int layer;        // layer of the diagonal's t, or -1
+    int phase_layer;  // layer whose gamma the pass applies, or -1
+};
+
+inline std::vector<MrPass> mr_evolve_plan(int G, int p, bool store)
+{
+    std::vector<MrPass> plan;
+    const int c = G - 1;
+    plan.push_back({c, MR_FIRST, -1, 0});
+    for (int L = 0; L < p; ++L) {
+        for (int g = G - 2; g >= 1; --g)
+            plan.push_back({g, MR_DIF, -1, -1});
+        plan.push_back({0, MR_LOWDIAG, L, -1});
+        for (int g = 1; g <= G - 2; ++g)
+            plan.push_back({g, MR_DIT, -1, -1});
+        if (L + 1 < p)
+            plan.push_back({c, MR_BOUNDARY, -1, L + 1});
+        else
+            plan.push_back({c, store ? MR_LAST_STORE : MR_LAST, -1, -1});
+    }
+    return plan;
+}
+
+}  // namespace qva

@@ -185,10 +185,18 @@ constexpr int rev_c(int x, int w)
 // (sincospi_red of a dyadic rational) and w^m is their product over the set
 // bits of m: at most w - 1 complex products, about 1 ulp each.
 // apply(r, tw) is called for every register r with m != 0 (forward sign).
-template <int C, int L, typename F>
-__device__ __forceinline__ void digit_twiddles(const TileMap& g, int t, F&& apply)
+//
+// TAB (contiguous low-group tiles only, k = 0): every root is a power of
+// W_4096 and does not depend on the tile, so it is read from `tab`, the
+// table tab[k] = W_4096^k = exp(-2 pi i k / 4096) that twiddle_table_kernel
+// writes once per call with the same sincospi_red arguments: the roots, and
+// so the twiddles, are bit-identical to the computed ones.
+template <int C, int L, bool TAB = false, typename F>
+__device__ __forceinline__ void digit_twiddles(const TileMap& g, int t, F&& apply,
+                                               const double2* __restrict__ tab = nullptr)
 {
     constexpr int LO = digit_lo<C, L>(), W = digit_w<C, L>();
+    static_assert(!TAB || C == 0, "table twiddles are for contiguous low-group tiles");
     if constexpr (W > 0) {
         const int gb = g.k + (reg_elem_bit<L>(LO) - C);  // global bit of the digit's lowest bit
         if (gb == 0)
@@ -201,9 +209,14 @@ __device__ __forceinline__ void digit_twiddles(const TileMap& g, int t, F&& appl
             double2 pw[W];  // w^(2^i)
 #pragma unroll
             for (int i = 0; i < W; ++i) {
-                double s, c;
-                sincospi_red(ldexp((double)jlo, i - (gb + W - 1)), &s, &c);
-                pw[i] = make_double2(c, -s);
+                if constexpr (TAB) {
+                    // w^(2^i) = W_4096^(j_lo 2^(i + 12 - gb - W)), gb + W <= 12
+                    pw[i] = tab[((int)jlo << (i + kTileBits - gb - W)) & ((1 << kTileBits) - 1)];
+                } else {
+                    double s, c;
+                    sincospi_red(ldexp((double)jlo, i - (gb + W - 1)), &s, &c);
+                    pw[i] = make_double2(c, -s);
+                }
             }
 #pragma unroll
             for (int m = 1; m < (1 << W); ++m) {
@@ -229,12 +242,26 @@ __device__ __forceinline__ void digit_twiddles(const TileMap& g, int t, F&& appl
 
 // Twiddles after (forward) or before (inverse, conjugated) the digit's
 // register DFT.
-template <int C, int L, bool INV>
-__device__ __forceinline__ void digit_twiddle(double2 (&v)[kRegs], const TileMap& g, int t)
+template <int C, int L, bool INV, bool TAB = false>
+__device__ __forceinline__ void digit_twiddle(double2 (&v)[kRegs], const TileMap& g, int t,
+                                              const double2* tab = nullptr)
 {
-    digit_twiddles<C, L>(g, t, [&](int r, double2 tw) {
+    digit_twiddles<C, L, TAB>(g, t, [&](int r, double2 tw) {
         v[r] = INV ? cmul_conj(v[r], tw) : cmul(v[r], tw);
-    });
+    }, tab);
+}
+
+// W_4096^k = exp(-2 pi i k / 4096), k < 4096: the root table of the
+// low-group digits (one workgroup of 256 threads, 16 entries each).
+__device__ __forceinline__ void twiddle_table_fill(double2* tab, int t)
+{
+#pragma unroll 4
+    for (int r = 0; r < kRegs; ++r) {
+        const int k = r * kThreads + t;
+        double s, c;
+        sincospi_red(ldexp((double)k, 1 - kTileBits), &s, &c);
+        tab[k] = make_double2(c, -s);
+    }
 }
 
 // Ring eigenvalues lambda_m = 2 cos(2 pi m / N) at the bit-reversed
@@ -277,22 +304,22 @@ __device__ __forceinline__ double ring_lambda(double2 u, int r)
     return (k & 8) ? -l : l;
 }
 
-template <int C, int L>
-__device__ __forceinline__ void dif_digit(double2 (&v)[kRegs], const TileMap& g, int t)
+template <int C, int L, bool TAB = false>
+__device__ __forceinline__ void dif_digit(double2 (&v)[kRegs], const TileMap& g, int t, const double2* tab)
 {
     constexpr int LO = digit_lo<C, L>(), W = digit_w<C, L>();
     if constexpr (W > 0) {
         local_dif<LO, W>(v);
-        digit_twiddle<C, L, false>(v, g, t);
+        digit_twiddle<C, L, false, TAB>(v, g, t, tab);
     }
 }
 
-template <int C, int L>
-__device__ __forceinline__ void dit_digit(double2 (&v)[kRegs], const TileMap& g, int t)
+template <int C, int L, bool TAB = false>
+__device__ __forceinline__ void dit_digit(double2 (&v)[kRegs], const TileMap& g, int t, const double2* tab)
 {
     constexpr int LO = digit_lo<C, L>(), W = digit_w<C, L>();
     if constexpr (W > 0) {
-        digit_twiddle<C, L, true>(v, g, t);
+        digit_twiddle<C, L, true, TAB>(v, g, t, tab);
         local_dit<LO, W>(v);
     }
 }
@@ -304,40 +331,43 @@ constexpr int dif_last()
     return C == 0 ? LC : (C == 3 ? LA3 : (C < 8 ? LB : LA));
 }
 
-// Forward (DIF) over every target bit of the tile: enters in A, leaves in dif_last<C>().
-template <int C>
-__device__ __forceinline__ void dif_tile(double2 (&v)[kRegs], double2* lds, const TileMap& g, int t)
+// Forward (DIF) over every target bit of the tile: enters in A, leaves in
+// dif_last<C>().  TAB: low-group root table (C = 0 only, see digit_twiddles).
+template <int C, bool TAB = false>
+__device__ __forceinline__ void dif_tile(double2 (&v)[kRegs], double2* lds, const TileMap& g, int t,
+                                         const double2* tab = nullptr)
 {
-    dif_digit<C, LA>(v, g, t);
+    dif_digit<C, LA, TAB>(v, g, t, tab);
     if constexpr (C < 8) {
         exchange<LA, LB>(v, lds, t);
-        dif_digit<C, LB>(v, g, t);
+        dif_digit<C, LB, TAB>(v, g, t, tab);
         if constexpr (C == 0) {
             exchange<LB, LC>(v, lds, t);
-            dif_digit<C, LC>(v, g, t);
+            dif_digit<C, LC, TAB>(v, g, t, tab);
         } else if constexpr (C == 3) {
             exchange<LB, LA3>(v, lds, t);
-            dif_digit<C, LA3>(v, g, t);
+            dif_digit<C, LA3>(v, g, t, tab);
         }
     }
 }
 
 // Inverse (DIT): enters in dif_last<C>(), leaves in A.
-template <int C>
-__device__ __forceinline__ void dit_tile(double2 (&v)[kRegs], double2* lds, const TileMap& g, int t)
+template <int C, bool TAB = false>
+__device__ __forceinline__ void dit_tile(double2 (&v)[kRegs], double2* lds, const TileMap& g, int t,
+                                         const double2* tab = nullptr)
 {
     if constexpr (C < 8) {
         if constexpr (C == 0) {
-            dit_digit<C, LC>(v, g, t);
+            dit_digit<C, LC, TAB>(v, g, t, tab);
             exchange<LC, LB>(v, lds, t);
         } else if constexpr (C == 3) {
-            dit_digit<C, LA3>(v, g, t);
+            dit_digit<C, LA3>(v, g, t, tab);
             exchange<LA3, LB>(v, lds, t);
         }
-        dit_digit<C, LB>(v, g, t);
+        dit_digit<C, LB, TAB>(v, g, t, tab);
         exchange<LB, LA>(v, lds, t);
     }
-    dit_digit<C, LA>(v, g, t);
+    dit_digit<C, LA, TAB>(v, g, t, tab);
 }
 
 template <int L>

@@ -87,9 +87,12 @@ def mix_circulant(psi: torch.Tensor, t: float, lam: torch.Tensor | None = None,
         _need(lam, torch.float64, "lam")
         if lam.numel() != psi.numel():
             raise ValueError("lam and psi differ in length")
+    lib = _lib.load()
+    ws = _workspace(lib.qva_mix_circulant_workspace_bytes(psi.numel()), psi.device)
     _lib.check("qva_mix_circulant",
-               _lib.load().qva_mix_circulant(_ptr(psi), _ptr(lam) if kind == "array" else None,
-                                             LAMBDA_KINDS[kind], psi.numel(), float(t), _stream()))
+               lib.qva_mix_circulant(_ptr(psi), _ptr(lam) if kind == "array" else None,
+                                     LAMBDA_KINDS[kind], psi.numel(), float(t), _ptr(ws),
+                                     0 if ws is None else ws.numel(), _stream()))
     return psi
 
 

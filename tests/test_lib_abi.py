@@ -278,7 +278,7 @@ def test_plan_bluestein(lib, N, n, kind, p):
         conv = [10] * nm
         back = [12] * nm
         layer = conv + [37] + back + [38] + conv + [37] + back
-        expect = ([34] + conv + [35]) * 2 + [36]
+        expect = [51] + ([34] + conv + [35]) * 2 + [36]  # 51: the low-group root table
         for k in range(p):
             expect += layer + ([39] if k + 1 < p else [last])
         assert kinds == expect + [8]
@@ -301,7 +301,7 @@ def test_plan_bluestein(lib, N, n, kind, p):
     mids = sorted({x.group_first for x in arr if x.kind == 10})
     conv = [10] * len(mids)
     back = [12] * len(mids)
-    fwd = ([34] + conv + [35]) * 2 + [36]
+    fwd = [51] + ([34] + conv + [35]) * 2 + [36]
     for k in range(p):
         fwd += conv + [37] + back + [38] + conv + [37] + back + ([39] if k + 1 < p else [])
     walk = []
@@ -594,6 +594,7 @@ def test_stream_probe_rejects_bad_arguments():
                       (["-2", "20", "12", "11"], "bad tile")]:
         res = subprocess.run([exe] + args, capture_output=True, text=True, timeout=30)
         assert res.returncode == 2 and msg in res.stderr, (args, res.returncode, res.stderr)
+
 
 def test_evolve_noalloc_validation(lib):
     """qva_evolve_noalloc reports argument errors and the static-scratch limit
