@@ -207,6 +207,8 @@ PMC_SEGMENTS = [
     ("qwoa_portfolio_n26_p6_complete", "evolve"),
     ("qwoa_portfolio_m26_k13_p6_ring", "evolve"),
     ("qwoa_portfolio_m26_k13_p6_complete", "evolve"),
+    ("qwoa_ring_n11907000_p6_mixed_radix", "evolve"),
+    ("qwoa_ring_n10400603_p6_bluestein", "evolve"),
     ("adjoint_qaoa_maxcut_n30_p12", "grad"),
     ("adjoint_qwoa_portfolio_n26_p6_complete", "grad"),
     ("adjoint_qwoa_portfolio_m26_k13_p6_ring", "grad"),
@@ -275,6 +277,14 @@ def segment_problem(name: str):
         else:
             wl = qwoa_portfolio_workload(26, 6, seed=CONFIG_SEEDS["qwoa_n26"], lambda_kind=kind)
         prob = qva.Problem(torch.from_numpy(wl.q).to(dev), "circulant", None, kind)
+        return prob, wl.gammas, wl.ts, 6, False
+    if name in ("qwoa_ring_n11907000_p6_mixed_radix", "qwoa_ring_n10400603_p6_bluestein"):
+        wl = qwoa_constrained_workload(26, 13, 6, seed=CONFIG_SEEDS["qwoa_n26"], lambda_kind="ring")
+        if "mixed" in name:
+            q = np.random.default_rng(2029).uniform(-1.0, 3.0, 2 ** 3 * 3 ** 5 * 5 ** 3 * 7 ** 2)
+        else:
+            q = np.concatenate([wl.q, wl.q[:3]])
+        prob = qva.Problem(torch.from_numpy(q).to(dev), "circulant", None, "ring")
         return prob, wl.gammas, wl.ts, 6, False
     if name == "exqaoa_maxcut_n28_p8_regular3":
         wl = exqaoa_maxcut_workload(28, 8, seed=CONFIG_SEEDS["qaoa_n28"], build_q=False)
@@ -657,6 +667,63 @@ def extra_qwoa(lib, steps: int, kind: str = "ring", constrained: bool = False) -
             "layer_applications_per_s": round(p / (ms * 1e-3), 2), "launches": len(infos),
             "effective_GBps": round(plan_bytes / (ms * 1e-3) / 1e9, 1),
             "f": out[0].item(), "roofline": with_traffic(roofline_of(per, steps), name, "evolve"),
+            "per_kernel_ms_per_evolve": {k: round(v["ms"] / steps, 4) for k, v in sorted(per.items())}}
+
+
+def extra_qwoa_any_n(lib, steps: int, which: str) -> dict:
+    """Ring circulant over N solutions, N not a power of two, p = 6:
+    "smooth": N = 2^3 3^5 5^3 7^2 = 11,907,000 (every prime factor <= 7: the
+    in-place mixed-radix passes), q ~ U(-1, 3) from default_rng(2029);
+    "prime": N = 10,400,603 (prime: Bluestein's transform over a padded
+    M = 2^25), q = the C(26, 13) portfolio qualities followed by their first
+    three values.  Angles as the portfolio workload's."""
+    import numpy as np
+    import torch
+
+    import paper_2110_03963_amd as qva
+    from paper_2110_03963_amd import _lib
+    from workloads import CONFIG_SEEDS, qwoa_constrained_workload
+
+    wl = qwoa_constrained_workload(26, 13, 6, seed=CONFIG_SEEDS["qwoa_n26"], lambda_kind="ring")
+    if which == "smooth":
+        N = 2 ** 3 * 3 ** 5 * 5 ** 3 * 7 ** 2
+        q = np.random.default_rng(2029).uniform(-1.0, 3.0, N)
+        name = "qwoa_ring_n11907000_p6_mixed_radix"
+    else:
+        q = np.concatenate([wl.q, wl.q[:3]])
+        N = q.size
+        name = "qwoa_ring_n10400603_p6_bluestein"
+    p = 6
+    prob = qva.Problem(torch.from_numpy(q).cuda(), "circulant", None, "ring")
+    g = torch.tensor(wl.gammas, device="cuda")
+    t = torch.tensor(wl.ts, device="cuda")
+    psi = torch.empty(N, dtype=torch.complex128, device="cuda")
+    ws = torch.empty(max(prob.workspace_bytes(p), 16), dtype=torch.uint8, device="cuda")
+    out = torch.empty(2, dtype=torch.float64, device="cuda")
+    flags = _lib.QVA_EVOLVE_SKIP_FINAL_STATE
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def run():
+        _lib.check("qva_evolve", lib.qva_evolve(prob.cstruct(), g.data_ptr(), t.data_ptr(), p, psi.data_ptr(),
+                                                out.data_ptr(), out.data_ptr() + 8, flags, ws.data_ptr(),
+                                                ws.numel(), stream))
+
+    ms = time_calls(run, 2, steps)
+    infos = plan_of(lib, prob, p, False, flags)
+
+    def run_timed(ev, nev):
+        _lib.check("qva_evolve_timed",
+                   lib.qva_evolve_timed(prob.cstruct(), g.data_ptr(), t.data_ptr(), p, psi.data_ptr(),
+                                        out.data_ptr(), out.data_ptr() + 8, flags, ws.data_ptr(),
+                                        ws.numel(), ev, nev, stream))
+
+    per = per_kernel_profile(run_timed, infos, steps)
+    plan_bytes = sum(i.bytes for i in infos)
+    return {"workload": name, "N": N, "ms_per_evolve": round(ms, 4),
+            "layer_applications_per_s": round(p / (ms * 1e-3), 2), "launches": len(infos),
+            "amplitude_layers_per_s": round(N * p / (ms * 1e-3), 1),
+            "effective_GBps": round(plan_bytes / (ms * 1e-3) / 1e9, 1), "f": out[0].item(),
+            "roofline": with_traffic(roofline_of(per, steps), name, "evolve"),
             "per_kernel_ms_per_evolve": {k: round(v["ms"] / steps, 4) for k, v in sorted(per.items())}}
 
 
@@ -1134,6 +1201,8 @@ EXTRAS = {
     "qwoa_complete": lambda lib, steps: extra_qwoa(lib, max(3, steps // 2), "complete"),
     "qwoa_constrained_ring": lambda lib, steps: extra_qwoa(lib, max(3, steps // 2), "ring", True),
     "qwoa_constrained_complete": lambda lib, steps: extra_qwoa(lib, max(3, steps // 2), "complete", True),
+    "qwoa_smooth_n_mixed_radix": lambda lib, steps: extra_qwoa_any_n(lib, max(3, steps // 2), "smooth"),
+    "qwoa_prime_n_bluestein": lambda lib, steps: extra_qwoa_any_n(lib, max(3, steps // 2), "prime"),
     "adjoint_vs_fd": lambda lib, steps: extra_adjoint(lib, 3),
     "adjoint_qwoa_complete": lambda lib, steps: extra_adjoint(lib, 3, "qwoa_complete"),
     "adjoint_qwoa_constrained_ring": lambda lib, steps: extra_adjoint(lib, 3, "qwoa_constrained_ring"),

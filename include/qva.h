@@ -138,6 +138,23 @@ typedef struct {
 /* qva_evolve flags */
 #define QVA_EVOLVE_SKIP_FINAL_STATE 1 /* psi need not hold psi_p on return */
 
+/* Group split (tuning).  The hypercube and power-of-two transform passes
+ * process the qubits in groups: the contiguous low 12, then strided groups
+ * of at most 9 qubits each (a tile keeps >= 8 contiguous amplitudes per row).
+ * The default is the fewest such groups with near-equal sizes.
+ * qva_set_group_split sets, for n_qubits-qubit registers (13 <= n_qubits <=
+ * QVA_MAX_QUBITS), the sizes of the strided groups from qubit 12 upward:
+ * bits[i] in 1..9, summing to n_qubits - 12 (count = 0 restores the
+ * default).  The setting is process-wide and read when a call plans its
+ * launches: set it between calls, never while another thread is inside a
+ * library call.  It applies to qva_evolve, qva_grad, qva_mix_x,
+ * qva_mix_circulant, qva_plan and batch plans created after it.
+ * QVA_ERR_SIZE for n_qubits out of range, QVA_ERR_ARG for a bad split.
+ * qva_get_group_split writes the split in effect (up to max entries) and
+ * returns the number of strided groups (0 for n_qubits <= 12). */
+int qva_set_group_split(int n_qubits, const int *bits, int count);
+int qva_get_group_split(int n_qubits, int *bits, int max);
+
 /* Human-readable text for a status code (static storage). */
 const char *qva_status_string(int status);
 

@@ -101,6 +101,25 @@ int check_problem(const qva_problem* P, int p)
     return QVA_OK;
 }
 
+// --------------------------------------------------- group split (tuning)
+// Sizes of the strided qubit groups above the contiguous 12-qubit group, per
+// register size n: set by qva_set_group_split (an autotuner's choice), else
+// x_split_default.  Read by every planner through x_groups.
+std::mutex g_split_mu;
+std::vector<int> g_split[QVA_MAX_QUBITS + 1];
+
+std::vector<int> x_split(int n)
+{
+    if (n > kTileBits && n <= QVA_MAX_QUBITS) {
+        std::lock_guard<std::mutex> lock(g_split_mu);
+        if (!g_split[n].empty())
+            return g_split[n];
+    }
+    return x_split_default(n);
+}
+
+std::vector<XGroup> x_groups(int n) { return x_groups_split(n, x_split(n)); }
+
 // ----------------------------------------------------- hypercube evolution
 Angle dev_angle(const double* ptr, int idx)
 {
@@ -261,7 +280,7 @@ bool mixed_geom(int64_t N, MrGeom* out)
 
 // A ring or eigenvalue-array circulant over N solutions, N not a power of
 // two but with every prime factor <= 31: the in-place mixed-radix transform.
-constexpr bool kMixedRadix = false;  // switched on once its GPU parity tests run
+constexpr bool kMixedRadix = true;
 
 bool mixed_path(const qva_problem* P)
 {
@@ -1712,6 +1731,39 @@ const char* qva_status_string(int status)
 }
 
 const char* qva_version(void) { return "libqva 0.1 (gfx950)"; }
+
+int qva_set_group_split(int n_qubits, const int* bits, int count)
+{
+    if (n_qubits <= kTileBits || n_qubits > QVA_MAX_QUBITS)
+        return QVA_ERR_SIZE;
+    if (count < 0 || count > n_qubits - kTileBits || (count > 0 && !bits))
+        return QVA_ERR_ARG;
+    std::vector<int> hi;
+    int sum = 0;
+    for (int i = 0; i < count; ++i) {
+        if (bits[i] < 1 || bits[i] > kMaxHighBits)
+            return QVA_ERR_ARG;
+        hi.push_back(bits[i]);
+        sum += bits[i];
+    }
+    if (count > 0 && sum != n_qubits - kTileBits)
+        return QVA_ERR_ARG;
+    std::lock_guard<std::mutex> lock(g_split_mu);
+    g_split[n_qubits] = hi;
+    return QVA_OK;
+}
+
+int qva_get_group_split(int n_qubits, int* bits, int max)
+{
+    if (n_qubits < 1 || n_qubits > QVA_MAX_QUBITS)
+        return QVA_ERR_SIZE;
+    if (max < 0 || (max > 0 && !bits))
+        return QVA_ERR_ARG;
+    const std::vector<int> hi = x_split(n_qubits);
+    for (int i = 0; i < (int)hi.size() && i < max; ++i)
+        bits[i] = hi[i];
+    return (int)hi.size();
+}
 
 int qva_init_uniform(qva_c128* psi, int64_t N, void* stream)
 {

@@ -86,6 +86,83 @@ __device__ __forceinline__ MrTile mr_tile(const MrGeom* __restrict__ m, int g, i
 
 __device__ __forceinline__ double2 conj_if(double2 a, bool c) { return make_double2(a.x, c ? -a.y : a.y); }
 
+// R-point DFT of x in registers, y_m = sum_k x_k W_R^(k m) (inverse: W^-1),
+// with each output handed to out(m, y_m).  root(j) = W_R^j (forward sign).
+// Odd R = 2h + 1: with a_k = x_k + x_{R-k}, b_k = x_k - x_{R-k} (k <= h),
+//   y_m = x_0 + sum_k a_k cos(2 pi k m / R) - i sum_k b_k sin(2 pi k m / R),
+// and y_{R-m} the same with +i, so each pair of outputs costs 4h FMAs.
+// R = 2^w: radix-2 DIF stages in registers, outputs bit-reversed.
+template <int R, typename Root, typename Out>
+__device__ __forceinline__ void dft_regs(double2 (&x)[R], bool inv, Root&& root, Out&& out)
+{
+    if constexpr ((R & (R - 1)) == 0) {
+        constexpr int W = R == 2 ? 1 : (R == 4 ? 2 : (R == 8 ? 3 : 4));
+        double2 w[R / 2];
+#pragma unroll
+        for (int j = 0; j < R / 2; ++j)
+            w[j] = conj_if(root(j), inv);
+#pragma unroll
+        for (int bb = W - 1; bb >= 0; --bb) {
+            const int half = 1 << bb;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (r & half)
+                    continue;
+                const int l = r & (half - 1);
+                const double2 a = x[r], c = x[r | half];
+                x[r] = make_double2(a.x + c.x, a.y + c.y);
+                const double2 d = make_double2(a.x - c.x, a.y - c.y);
+                x[r | half] = l == 0 ? d : cmul(d, w[l * (R / (2 * half))]);
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            int rv = 0;
+#pragma unroll
+            for (int i = 0; i < W; ++i)
+                rv |= ((m >> i) & 1) << (W - 1 - i);
+            out(m, x[rv]);
+        }
+    } else {
+        constexpr int H = R / 2;
+        double cs[H], sn[H];  // cos, sin of 2 pi j / R, j = 1..H
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+            const double2 r = root(j + 1);  // (cos, -sin)
+            cs[j] = r.x;
+            sn[j] = inv ? r.y : -r.y;       // the inverse flips the sine
+        }
+        double2 a[H], b[H];
+        double2 y0 = x[0];
+#pragma unroll
+        for (int k = 1; k <= H; ++k) {
+            a[k - 1] = make_double2(x[k].x + x[R - k].x, x[k].y + x[R - k].y);
+            b[k - 1] = make_double2(x[k].x - x[R - k].x, x[k].y - x[R - k].y);
+            y0.x += a[k - 1].x;
+            y0.y += a[k - 1].y;
+        }
+        out(0, y0);
+#pragma unroll
+        for (int m = 1; m <= H; ++m) {
+            double2 P = x[0], Q = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int k = 1; k <= H; ++k) {
+                const int j = (k * m) % R;  // 1 .. R - 1
+                const double c = j <= H ? cs[j - 1] : cs[R - j - 1];
+                const double sv = j <= H ? sn[j - 1] : -sn[R - j - 1];
+                P.x = fma(a[k - 1].x, c, P.x);
+                P.y = fma(a[k - 1].y, c, P.y);
+                Q.x = fma(b[k - 1].x, sv, Q.x);
+                Q.y = fma(b[k - 1].y, sv, Q.y);
+            }
+            // y_m = P - i Q, y_{R-m} = P + i Q
+            out(m, make_double2(P.x + Q.y, P.y - Q.x));
+            out(R - m, make_double2(P.x - Q.y, P.y + Q.x));
+            QVA_SCHED_FENCE();
+        }
+    }
+}
+
 // One DIF stage of radix R over sub-length L of every column's A-point DFT
 // in LDS: butterfly (b, i), i < L/R, takes elements b L + i + k L/R, forms
 // y_m = sum_k x_k W_R^(k m), multiplies y_m by W_L^(i m) and writes it back
@@ -95,14 +172,13 @@ template <int R>
 __device__ __forceinline__ void mr_stage(double2* lds, int A, int ncol, bool low, int L,
                                          const double2* __restrict__ tab, bool inv)
 {
-    const int mstride = L / R, per_col = A / R, tstep = A / L;
+    // rstep = A / R, formed from L so that it varies with the stage: the
+    // root loads of the different radices are then not hoisted out of the
+    // stage loop (held at once, they would exhaust the registers)
+    const int mstride = L / R, per_col = A / R, tstep = A / L, rstep = mstride * tstep;
     const int items = ncol * per_col;
     const double rpc = 1.0 / (double)per_col, rms = 1.0 / (double)mstride, rnc = 1.0 / (double)ncol;
     const int cs = low ? A : 1, js = low ? 1 : ncol;  // LDS strides of col and j
-    double2 w[R];
-#pragma unroll
-    for (int k = 0; k < R; ++k)
-        w[k] = k == 0 ? make_double2(1.0, 0.0) : conj_if(tab[k * (A / R)], inv);
     for (int it = threadIdx.x; it < items; it += kMrThreads) {
         int col, bi;
         if (low) {  // i fastest: consecutive threads take consecutive j
@@ -118,26 +194,20 @@ __device__ __forceinline__ void mr_stage(double2* lds, int A, int ncol, bool low
 #pragma unroll
         for (int k = 0; k < R; ++k)
             x[k] = lds[base + k * step];
-#pragma unroll
-        for (int mm = 0; mm < R; ++mm) {
-            double2 acc = x[0];
-#pragma unroll
-            for (int k = 1; k < R; ++k) {
-                const double2 r = w[(k * mm) % R];
-                acc.x = fma(x[k].x, r.x, fma(-x[k].y, r.y, acc.x));
-                acc.y = fma(x[k].x, r.y, fma(x[k].y, r.x, acc.y));
-            }
-            if (mm > 0 && i > 0)
-                acc = cmul(acc, conj_if(tab[i * mm * tstep], inv));
-            lds[base + mm * step] = acc;
-        }
+        dft_regs<R>(x, inv, [&](int j) { return tab[j * rstep]; }, [&](int m, double2 y) {
+            if (m > 0 && i > 0)
+                y = cmul(y, conj_if(tab[i * m * tstep], inv));
+            lds[base + m * step] = y;
+        });
     }
 }
 
-// Every DIF stage of one group's DFT on the tile in LDS (one copy of the
-// stage code, called from each pass).
-__device__ __noinline__ void mr_stages(double2* lds, int A, int ncol, bool low, const double2* __restrict__ gt,
-                                       const int* __restrict__ rad, int nrad, bool inv)
+// Every DIF stage of one group's DFT on the tile in LDS.  BIG: radices up
+// to 31 (the kernels built with it run one wave per SIMD: the radix-17..31
+// stages need the registers); otherwise radices up to 16.
+template <bool BIG>
+__device__ __forceinline__ void mr_stages(double2* lds, int A, int ncol, bool low, const double2* __restrict__ gt,
+                                          const int* __restrict__ rad, int nrad, bool inv)
 {
     int L = A;
     for (int s = 0; s < nrad; ++s) {
@@ -152,11 +222,17 @@ __device__ __noinline__ void mr_stages(double2* lds, int A, int ncol, bool low, 
         case 11: mr_stage<11>(lds, A, ncol, low, L, gt, inv); break;
         case 13: mr_stage<13>(lds, A, ncol, low, L, gt, inv); break;
         case 16: mr_stage<16>(lds, A, ncol, low, L, gt, inv); break;
-        case 17: mr_stage<17>(lds, A, ncol, low, L, gt, inv); break;
-        case 19: mr_stage<19>(lds, A, ncol, low, L, gt, inv); break;
-        case 23: mr_stage<23>(lds, A, ncol, low, L, gt, inv); break;
-        case 29: mr_stage<29>(lds, A, ncol, low, L, gt, inv); break;
-        default: mr_stage<31>(lds, A, ncol, low, L, gt, inv); break;
+        default:
+            if constexpr (BIG) {
+                switch (r) {
+                case 17: mr_stage<17>(lds, A, ncol, low, L, gt, inv); break;
+                case 19: mr_stage<19>(lds, A, ncol, low, L, gt, inv); break;
+                case 23: mr_stage<23>(lds, A, ncol, low, L, gt, inv); break;
+                case 29: mr_stage<29>(lds, A, ncol, low, L, gt, inv); break;
+                default: mr_stage<31>(lds, A, ncol, low, L, gt, inv); break;
+                }
+            }
+            break;
         }
         L /= r;
         __syncthreads();
@@ -166,6 +242,7 @@ __device__ __noinline__ void mr_stages(double2* lds, int A, int ncol, bool low, 
 // The group DFT of every column of the tile, through LDS: v holds elements
 // e = t + 256 k in natural j order on entry and natural frequency order on
 // return (forward: exponent sign -, inv: +; no 1/A).
+template <bool BIG>
 __device__ __forceinline__ void mr_dft(double2 (&v)[kMrRegs], double2* lds, const MrTile& T,
                                        const MrGeom* __restrict__ m, int g, const double2* tab, const int* perm,
                                        bool inv)
@@ -180,7 +257,7 @@ __device__ __forceinline__ void mr_dft(double2 (&v)[kMrRegs], double2* lds, cons
             lds[e] = v[k];
     }
     __syncthreads();
-    mr_stages(lds, T.A, T.ncol, T.low, tab + m->tab_off[g], m->rad[g], m->nrad[g], inv);
+    mr_stages<BIG>(lds, T.A, T.ncol, T.low, tab + m->tab_off[g], m->rad[g], m->nrad[g], inv);
 #pragma unroll
     for (int k = 0; k < kMrRegs; ++k) {
         const int e = t + k * kMrThreads;
@@ -211,18 +288,20 @@ __device__ __forceinline__ void mr_twiddle(double2 (&v)[kMrRegs], const MrTile& 
     }
 }
 
+template <bool BIG>
 __device__ __forceinline__ void mr_forward(double2 (&v)[kMrRegs], double2* lds, const MrTile& T, const MrGeom* m,
                                            int g, const double2* tab, const int* perm)
 {
-    mr_dft(v, lds, T, m, g, tab, perm, false);
+    mr_dft<BIG>(v, lds, T, m, g, tab, perm, false);
     mr_twiddle(v, T, m, g, false);
 }
 
+template <bool BIG>
 __device__ __forceinline__ void mr_inverse(double2 (&v)[kMrRegs], double2* lds, const MrTile& T, const MrGeom* m,
                                            int g, const double2* tab, const int* perm)
 {
     mr_twiddle(v, T, m, g, true);
-    mr_dft(v, lds, T, m, g, tab, perm, true);
+    mr_dft<BIG>(v, lds, T, m, g, tab, perm, true);
 }
 
 __device__ __forceinline__ void mr_load(double2 (&v)[kMrRegs], const double2* psi, const MrTile& T)
@@ -323,8 +402,8 @@ __device__ __forceinline__ void mr_expect(const double2 (&v)[kMrRegs], const dou
         *out = tot;
 }
 
-template <int MODE>
-__global__ __launch_bounds__(kMrThreads, 2) void mrpass_kernel(MrPassParams P)
+template <int MODE, bool BIG>
+__global__ __launch_bounds__(kMrThreads, BIG ? 1 : 2) void mrpass_kernel(MrPassParams P)
 {
     __shared__ double2 lds[kMrTileElems];
     __shared__ double red[2 * (kMrThreads / 64)];
@@ -340,32 +419,32 @@ __global__ __launch_bounds__(kMrThreads, 2) void mrpass_kernel(MrPassParams P)
         for (int k = 0; k < kMrRegs; ++k)
             v[k] = make_double2(a0, 0.0);
         mr_phase(v, P.q, T, angle_value(P.gamma), 1.0);
-        mr_forward(v, lds, T, m, g, P.tab, perm);
+        mr_forward<BIG>(v, lds, T, m, g, P.tab, perm);
         mr_store(v, P.psi, T, 1.0);
     } else if constexpr (MODE == MR_DIF) {
         mr_load(v, P.psi, T);
-        mr_forward(v, lds, T, m, g, P.tab, perm);
+        mr_forward<BIG>(v, lds, T, m, g, P.tab, perm);
         mr_store(v, P.psi, T, 1.0);
     } else if constexpr (MODE == MR_DIT) {
         mr_load(v, P.psi, T);
-        mr_inverse(v, lds, T, m, g, P.tab, perm);
+        mr_inverse<BIG>(v, lds, T, m, g, P.tab, perm);
         mr_store(v, P.psi, T, 1.0);
     } else if constexpr (MODE == MR_LOWDIAG) {
         mr_load(v, P.psi, T);
-        mr_forward(v, lds, T, m, g, P.tab, perm);
+        mr_forward<BIG>(v, lds, T, m, g, P.tab, perm);
         mr_diag(v, P, T, angle_value(P.t));
-        mr_inverse(v, lds, T, m, g, P.tab, perm);
+        mr_inverse<BIG>(v, lds, T, m, g, P.tab, perm);
         mr_store(v, P.psi, T, 1.0);
     } else if constexpr (MODE == MR_BOUNDARY) {
         const double gam = angle_value(P.gamma);
         mr_load(v, P.psi, T);
-        mr_inverse(v, lds, T, m, g, P.tab, perm);
+        mr_inverse<BIG>(v, lds, T, m, g, P.tab, perm);
         mr_phase(v, P.q, T, gam, invN);
-        mr_forward(v, lds, T, m, g, P.tab, perm);
+        mr_forward<BIG>(v, lds, T, m, g, P.tab, perm);
         mr_store(v, P.psi, T, 1.0);
     } else {  // MR_LAST, MR_LAST_STORE
         mr_load(v, P.psi, T);
-        mr_inverse(v, lds, T, m, g, P.tab, perm);
+        mr_inverse<BIG>(v, lds, T, m, g, P.tab, perm);
 #pragma unroll
         for (int k = 0; k < kMrRegs; ++k)
             v[k] = make_double2(v[k].x * invN, v[k].y * invN);
@@ -382,7 +461,7 @@ __device__ __forceinline__ double im_term(double2 x, double2 p) { return x.x * p
 // transforms applied to each vector in turn through one LDS buffer, with the
 // inner products taken where both are at hand.  Passes with per-tile slots
 // run on max_tiles workgroups: those beyond the group's tiles write a zero.
-template <int MODE>
+template <int MODE, bool BIG>
 __global__ __launch_bounds__(kMrThreads, 1) void mrgrad_kernel(MrPassParams P)
 {
     __shared__ double2 lds[kMrTileElems];
@@ -402,7 +481,7 @@ __global__ __launch_bounds__(kMrThreads, 1) void mrgrad_kernel(MrPassParams P)
     double2 p[kMrRegs], x[kMrRegs];
     if constexpr (MODE == MRG_TURN) {
         mr_load(p, P.psi, T);
-        mr_inverse(p, lds, T, m, g, P.tab, perm);
+        mr_inverse<BIG>(p, lds, T, m, g, P.tab, perm);
         double f = 0.0, nr = 0.0;
 #pragma unroll
         for (int k = 0; k < kMrRegs; ++k) {
@@ -417,16 +496,16 @@ __global__ __launch_bounds__(kMrThreads, 1) void mrgrad_kernel(MrPassParams P)
         const double2 tot = block_sum2(f, nr, red);
         if (t == 0)
             P.partials[blockIdx.x] = tot;
-        mr_forward(p, lds, T, m, g, P.tab, perm);
-        mr_forward(x, lds, T, m, g, P.tab, perm);
+        mr_forward<BIG>(p, lds, T, m, g, P.tab, perm);
+        mr_forward<BIG>(x, lds, T, m, g, P.tab, perm);
         mr_store(p, P.psi, T, 1.0);
         mr_store(x, P.chi, T, 1.0);
     } else if constexpr (MODE == MRG_LOWDIAG) {
         const double tt = angle_value(P.t);
         mr_load(p, P.psi, T);
         mr_load(x, P.chi, T);
-        mr_forward(p, lds, T, m, g, P.tab, perm);
-        mr_forward(x, lds, T, m, g, P.tab, perm);
+        mr_forward<BIG>(p, lds, T, m, g, P.tab, perm);
+        mr_forward<BIG>(x, lds, T, m, g, P.tab, perm);
         double acc = 0.0;
 #pragma unroll
         for (int k = 0; k < kMrRegs; ++k) {
@@ -443,15 +522,15 @@ __global__ __launch_bounds__(kMrThreads, 1) void mrgrad_kernel(MrPassParams P)
         const double2 tot = block_sum2(acc * invN, 0.0, red);
         if (t == 0)
             P.slot[blockIdx.x] = tot.x;
-        mr_inverse(p, lds, T, m, g, P.tab, perm);
-        mr_inverse(x, lds, T, m, g, P.tab, perm);
+        mr_inverse<BIG>(p, lds, T, m, g, P.tab, perm);
+        mr_inverse<BIG>(x, lds, T, m, g, P.tab, perm);
         mr_store(p, P.psi, T, 1.0);
         mr_store(x, P.chi, T, 1.0);
     } else {  // MRG_BOUND, MRG_FINAL
         mr_load(p, P.psi, T);
         mr_load(x, P.chi, T);
-        mr_inverse(p, lds, T, m, g, P.tab, perm);
-        mr_inverse(x, lds, T, m, g, P.tab, perm);
+        mr_inverse<BIG>(p, lds, T, m, g, P.tab, perm);
+        mr_inverse<BIG>(x, lds, T, m, g, P.tab, perm);
         const double gam = angle_value(P.gamma);
         double acc = 0.0;
 #pragma unroll
@@ -474,8 +553,8 @@ __global__ __launch_bounds__(kMrThreads, 1) void mrgrad_kernel(MrPassParams P)
         if (t == 0)
             P.slot[blockIdx.x] = tot.x;
         if constexpr (MODE == MRG_BOUND) {
-            mr_forward(p, lds, T, m, g, P.tab, perm);
-            mr_forward(x, lds, T, m, g, P.tab, perm);
+            mr_forward<BIG>(p, lds, T, m, g, P.tab, perm);
+            mr_forward<BIG>(x, lds, T, m, g, P.tab, perm);
             mr_store(p, P.psi, T, 1.0);
             mr_store(x, P.chi, T, 1.0);
         }
@@ -484,7 +563,7 @@ __global__ __launch_bounds__(kMrThreads, 1) void mrgrad_kernel(MrPassParams P)
 
 // N <= 4096 (one group): the whole evolution, and with MRG_SMALL the adjoint
 // walk, in one workgroup.
-template <int MODE>
+template <int MODE, bool BIG>
 __global__ __launch_bounds__(kMrThreads, 1) void mrsmall_kernel(MrPassParams P)
 {
     __shared__ double2 lds[kMrTileElems];
@@ -501,9 +580,9 @@ __global__ __launch_bounds__(kMrThreads, 1) void mrsmall_kernel(MrPassParams P)
         p[k] = make_double2(t + k * kMrThreads < ne ? a0 : 0.0, 0.0);
     for (int L = 0; L < P.p; ++L) {
         mr_phase(p, P.q, T, P.gammas[L], 1.0);
-        mr_dft(p, lds, T, m, 0, P.tab, perm, false);
+        mr_dft<BIG>(p, lds, T, m, 0, P.tab, perm, false);
         mr_diag(p, P, T, P.ts[L]);
-        mr_dft(p, lds, T, m, 0, P.tab, perm, true);
+        mr_dft<BIG>(p, lds, T, m, 0, P.tab, perm, true);
 #pragma unroll
         for (int k = 0; k < kMrRegs; ++k)
             p[k] = make_double2(p[k].x * invN, p[k].y * invN);
@@ -539,8 +618,8 @@ __global__ __launch_bounds__(kMrThreads, 1) void mrsmall_kernel(MrPassParams P)
         }
         for (int L = P.p - 1; L >= 0; --L) {
             // the mixer of layer L: Im <chi|W|phi> at the spectrum, then undone
-            mr_dft(p, lds, T, m, 0, P.tab, perm, false);
-            mr_dft(x, lds, T, m, 0, P.tab, perm, false);
+            mr_dft<BIG>(p, lds, T, m, 0, P.tab, perm, false);
+            mr_dft<BIG>(x, lds, T, m, 0, P.tab, perm, false);
             double acc = 0.0;
             const double tt = P.ts[L];
 #pragma unroll
@@ -557,8 +636,8 @@ __global__ __launch_bounds__(kMrThreads, 1) void mrsmall_kernel(MrPassParams P)
             const double2 st = block_sum2(acc * invN, 0.0, red);
             if (t == 0)
                 P.dts[L] = 2.0 * st.x;
-            mr_dft(p, lds, T, m, 0, P.tab, perm, true);
-            mr_dft(x, lds, T, m, 0, P.tab, perm, true);
+            mr_dft<BIG>(p, lds, T, m, 0, P.tab, perm, true);
+            mr_dft<BIG>(x, lds, T, m, 0, P.tab, perm, true);
             // the phase of layer L
             const double gam = P.gammas[L];
             acc = 0.0;
@@ -633,6 +712,35 @@ hipError_t launch_mr_tables(const MrGeom& m, MrGeom* geom_dev, double2* tab, hip
     return hipGetLastError();
 }
 
+template <bool BIG>
+hipError_t launch_mr_modes(const MrPassParams& P, int mode, dim3 grid, hipStream_t s)
+{
+    switch (mode) {
+#define QVA_MR_MODE(K, M) \
+    case M:               \
+        hipLaunchKernelGGL((K<M, BIG>), grid, dim3(kMrThreads), 0, s, P); \
+        break;
+        QVA_MR_MODE(mrpass_kernel, MR_FIRST)
+        QVA_MR_MODE(mrpass_kernel, MR_DIF)
+        QVA_MR_MODE(mrpass_kernel, MR_DIT)
+        QVA_MR_MODE(mrpass_kernel, MR_LOWDIAG)
+        QVA_MR_MODE(mrpass_kernel, MR_BOUNDARY)
+        QVA_MR_MODE(mrpass_kernel, MR_LAST)
+        QVA_MR_MODE(mrpass_kernel, MR_LAST_STORE)
+        QVA_MR_MODE(mrsmall_kernel, MR_SMALL)
+        QVA_MR_MODE(mrsmall_kernel, MR_SMALL_STORE)
+        QVA_MR_MODE(mrsmall_kernel, MRG_SMALL)
+        QVA_MR_MODE(mrgrad_kernel, MRG_TURN)
+        QVA_MR_MODE(mrgrad_kernel, MRG_LOWDIAG)
+        QVA_MR_MODE(mrgrad_kernel, MRG_BOUND)
+        QVA_MR_MODE(mrgrad_kernel, MRG_FINAL)
+#undef QVA_MR_MODE
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_mrpass(const MrPassParams& P0, const MrGeom& m, int mode, hipStream_t s)
 {
     int64_t maxt = 0;
@@ -641,46 +749,14 @@ hipError_t launch_mrpass(const MrPassParams& P0, const MrGeom& m, int mode, hipS
     MrPassParams P = P0;
     const bool wide = mode == MRG_LOWDIAG || mode == MRG_BOUND || mode == MRG_FINAL;
     P.grid = (mode == MR_SMALL || mode == MR_SMALL_STORE || mode == MRG_SMALL) ? 1 : (wide ? maxt : m.tiles[P.g]);
+    bool big = false;
+    for (int g = 0; g < m.G; ++g)
+        for (int i = 0; i < m.nrad[g]; ++i)
+            big = big || m.rad[g][i] > 16;
     const dim3 grid((unsigned)P.grid);
-    const dim3 gridmax((unsigned)P.grid);
-    switch (mode) {
-#define QVA_MR_MODE(M) \
-    case M:            \
-        hipLaunchKernelGGL((mrpass_kernel<M>), grid, dim3(kMrThreads), 0, s, P); \
-        break;
-        QVA_MR_MODE(MR_FIRST)
-        QVA_MR_MODE(MR_DIF)
-        QVA_MR_MODE(MR_DIT)
-        QVA_MR_MODE(MR_LOWDIAG)
-        QVA_MR_MODE(MR_BOUNDARY)
-        QVA_MR_MODE(MR_LAST)
-        QVA_MR_MODE(MR_LAST_STORE)
-#undef QVA_MR_MODE
-    case MR_SMALL:
-        hipLaunchKernelGGL((mrsmall_kernel<MR_SMALL>), dim3(1), dim3(kMrThreads), 0, s, P);
-        break;
-    case MR_SMALL_STORE:
-        hipLaunchKernelGGL((mrsmall_kernel<MR_SMALL_STORE>), dim3(1), dim3(kMrThreads), 0, s, P);
-        break;
-    case MRG_SMALL:
-        hipLaunchKernelGGL((mrsmall_kernel<MRG_SMALL>), dim3(1), dim3(kMrThreads), 0, s, P);
-        break;
-    case MRG_TURN:
-        hipLaunchKernelGGL((mrgrad_kernel<MRG_TURN>), grid, dim3(kMrThreads), 0, s, P);
-        break;
-    case MRG_LOWDIAG:
-        hipLaunchKernelGGL((mrgrad_kernel<MRG_LOWDIAG>), gridmax, dim3(kMrThreads), 0, s, P);
-        break;
-    case MRG_BOUND:
-        hipLaunchKernelGGL((mrgrad_kernel<MRG_BOUND>), gridmax, dim3(kMrThreads), 0, s, P);
-        break;
-    case MRG_FINAL:
-        hipLaunchKernelGGL((mrgrad_kernel<MRG_FINAL>), gridmax, dim3(kMrThreads), 0, s, P);
-        break;
-    default:
-        return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    if (big)
+        return launch_mr_modes<true>(P, mode, grid, s);
+    return launch_mr_modes<false>(P, mode, grid, s);
 }
 
 }  // namespace qva

@@ -20,9 +20,10 @@ struct XGroup {
     int col_bits; // contiguous low index bits per tile row (0 for the low group)
 };
 
-// Group 0 is qubits [0, 12) (contiguous tiles); the remaining qubits are split
-// into the fewest groups of at most kMaxHighBits, sizes as equal as possible.
-inline std::vector<XGroup> x_groups(int n)
+// Group 0 is qubits [0, 12) (contiguous tiles); the qubits above are split
+// into strided groups of the given sizes (each 1..kMaxHighBits, from qubit
+// 12 upward).
+inline std::vector<XGroup> x_groups_split(int n, const std::vector<int>& high)
 {
     std::vector<XGroup> g;
     if (n <= kTileBits) {
@@ -30,17 +31,30 @@ inline std::vector<XGroup> x_groups(int n)
         return g;
     }
     g.push_back({0, kTileBits, 0});
-    const int rem = n - kTileBits;
-    const int nh = (rem + kMaxHighBits - 1) / kMaxHighBits;
-    const int base = rem / nh, extra = rem % nh;
     int k = kTileBits;
-    for (int i = 0; i < nh; ++i) {
-        const int b = base + (i < extra ? 1 : 0);
+    for (int b : high) {
         g.push_back({k, b, kTileBits - b});
         k += b;
     }
     return g;
 }
+
+// The default split: the fewest groups of at most kMaxHighBits, sizes as
+// equal as possible.
+inline std::vector<int> x_split_default(int n)
+{
+    std::vector<int> hi;
+    if (n <= kTileBits)
+        return hi;
+    const int rem = n - kTileBits;
+    const int nh = (rem + kMaxHighBits - 1) / kMaxHighBits;
+    const int base = rem / nh, extra = rem % nh;
+    for (int i = 0; i < nh; ++i)
+        hi.push_back(base + (i < extra ? 1 : 0));
+    return hi;
+}
+
+inline std::vector<XGroup> x_groups_default(int n) { return x_groups_split(n, x_split_default(n)); }
 
 struct XPass {
     int group;

@@ -23,7 +23,8 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
 import oracle  # noqa: E402
-from workloads import CONFIG_SEEDS, qaoa_maxcut_workload, qwoa_portfolio_workload  # noqa: E402
+from workloads import (CONFIG_SEEDS, qaoa_maxcut_workload, qwoa_constrained_workload,  # noqa: E402
+                       qwoa_portfolio_workload)
 
 OUT = os.path.join(HERE, "full_size_values.json")
 OUT_AMP = os.path.join(HERE, "full_size_amplitudes.json")
@@ -107,9 +108,40 @@ def qwoa_n26_complete_grad():
             "oracle_seconds": time.time() - t0}
 
 
+def qwoa_m26_k13_ring():
+    # N = C(26, 13) = 10,400,600 = 2^3 5^2 7 17 19 23: the oracle's chirp-z route
+    wl = qwoa_constrained_workload(26, 13, 6, seed=CONFIG_SEEDS["qwoa_n26"], lambda_kind="ring")
+    t0 = time.time()
+    psi, f, nrm = oracle.evolve("circulant", wl.q, wl.gammas, wl.ts, oracle.ring_lambda(wl.N))
+    return _amp_entry("qwoa_constrained_workload(26, 13, 6, seed=103, lambda_kind='ring'); psi_p",
+                      psi, f, nrm, time.time() - t0)
+
+
+# A smooth N = 2^3 3^5 5^3 7^2 = 11,907,000 with seeded qualities and angles
+SMOOTH_N = 2 ** 3 * 3 ** 5 * 5 ** 3 * 7 ** 2
+SMOOTH_SEED = 2029
+
+
+def smooth_inputs(p: int):
+    rng = np.random.default_rng(SMOOTH_SEED)
+    q = rng.uniform(-1.0, 3.0, SMOOTH_N)
+    return q, rng.uniform(0, np.pi, p), rng.uniform(0, np.pi, p)
+
+
+def smooth_ring_grad():
+    q, g, t = smooth_inputs(2)
+    t0 = time.time()
+    f, dg, dt = oracle.grad("circulant", q, g, t, oracle.ring_lambda(SMOOTH_N))
+    return {"recipe": f"N = {SMOOTH_N}; default_rng({SMOOTH_SEED}): q ~ U(-1, 3) over N, then gammas, ts "
+                      "~ U(0, pi), p = 2; ring; oracle.grad",
+            "f": f, "dgammas": list(map(float, dg)), "dts": list(map(float, dt)),
+            "oracle_seconds": time.time() - t0}
+
+
 GENERATORS = {"qaoa_n28_p8": qaoa_n28, "qwoa_n26_p6": qwoa_n26, "qwoa_n26_p6_complete": qwoa_n26_complete,
               "qwoa_n26_p6_complete_grad": qwoa_n26_complete_grad,
-              "qaoa_n28_p8_amplitudes": qaoa_n28_amplitudes, "qwoa_n26_p6_amplitudes": qwoa_n26_amplitudes}
+              "qaoa_n28_p8_amplitudes": qaoa_n28_amplitudes, "qwoa_n26_p6_amplitudes": qwoa_n26_amplitudes,
+              "qwoa_m26_k13_p6_ring_amplitudes": qwoa_m26_k13_ring, "smooth_11907000_p2_ring_grad": smooth_ring_grad}
 
 
 def main(names):

@@ -47,6 +47,10 @@ def _case(name):
         N = 50021
         prob = qva.Problem(to_dev(rng.uniform(0, 3, N)), "circulant", to_dev(rng.uniform(-2, 2, N)), "array")
         G = rng.uniform(0, math.pi, p)
+    elif name == "mixed":
+        N = 243000  # 2^3 3^5 5^3: the in-place mixed-radix passes
+        prob = qva.Problem(to_dev(rng.uniform(0, 3, N)), "circulant", to_dev(rng.uniform(-2, 2, N)), "array")
+        G = rng.uniform(0, math.pi, p)
     elif name == "xy":
         n = 15
         prob = qva.Problem(to_dev(rng.uniform(0, 3, 1 << n)), "xy", pairs=qva.parity_ring_pairs(range(n)),
@@ -61,7 +65,7 @@ def _case(name):
     return prob, torch.tensor(G, device="cuda"), torch.tensor(T, device="cuda")
 
 
-@pytest.mark.parametrize("name", ["x", "ring", "complete_any_n", "bluestein", "xy", "terms"])
+@pytest.mark.parametrize("name", ["x", "ring", "complete_any_n", "bluestein", "mixed", "xy", "terms"])
 def test_graph_capture_evolve_and_grad(name):
     prob, g, t = _case(name)
     p = t.numel()

@@ -260,7 +260,7 @@ def test_plan_complete_any_n(lib, N, n, p):
         assert lib.qva_workspace_bytes(ctypes.byref(pr), p, 1) > 0
 
 
-@pytest.mark.parametrize("N,n", [(1000, 10), (4097, 13), (100003, 17), (3000017, 22)])
+@pytest.mark.parametrize("N,n", [(1009, 10), (4097, 13), (100003, 17), (3000017, 22)])
 @pytest.mark.parametrize("kind", [0, 1])
 @pytest.mark.parametrize("p", [1, 3])
 def test_plan_bluestein(lib, N, n, kind, p):
@@ -613,3 +613,105 @@ def test_evolve_noalloc_validation(lib):
     assert lib.qva_evolve_noalloc(None, FAKE, FAKE, 2, FAKE, FAKE, None, 0, None) == S.QVA_ERR_ARG
     assert lib.qva_evolve_noalloc(ref(_prob(n=34)), FAKE, FAKE, 2, FAKE, FAKE, None, 0, None) == S.QVA_ERR_SIZE
     assert lib.qva_status_string(S.QVA_ERR_SCRATCH) == b"request needs more workspace than the static scratch holds"
+
+
+def _factors(N):
+    f, d = [], 2
+    while d * d <= N:
+        while N % d == 0:
+            f.append(d)
+            N //= d
+        d += 1
+    if N > 1:
+        f.append(N)
+    return f
+
+
+@pytest.mark.parametrize("N", [6, 30, 1000, 3003, 6000, 3 * 2 ** 16, 243000, 184756, 460288, 2704156,
+                               10400600, 11907000, 3 * 2 ** 29])
+@pytest.mark.parametrize("p", [1, 4])
+def test_plan_mixed_radix(lib, N, p):
+    """N not a power of two with prime factors <= 31: the in-place mixed-radix
+    passes.  The groups' sizes multiply to N within their caps (4096 for the
+    contiguous group, 512 for strided ones), a tile holds at most 4096
+    amplitudes, and the pass list is the power-of-two transform's: top group
+    first, per layer the middle groups forward, the low group with the
+    diagonal, the middle groups back, the boundary pass; the adjoint walks it
+    back with one t slot and one gamma slot per layer."""
+    n = (N - 1).bit_length()
+    pr = _prob(mixer=1, n=n, kind=1, n_states=N)
+    for grad in (0, 1):
+        cnt = lib.qva_plan(ctypes.byref(pr), p, grad, 1, None, 0)
+        arr = (_lib.QvaPassInfo * cnt)()
+        assert lib.qva_plan(ctypes.byref(pr), p, grad, 1, arr, cnt) == cnt
+        kinds = [x.kind for x in arr]
+        assert kinds[0] == 52 and not any(34 <= k <= 41 for k in kinds)
+        groups = {}
+        for x in arr:
+            if x.group_first >= 0:
+                groups[x.group_first] = (x.group_bits, x.col_bits)
+        G = len(groups)
+        assert sorted(groups) == list(range(G))
+        prod = 1
+        for g, (A, c) in groups.items():
+            prod *= A
+            assert A <= (4096 if g == 0 else 512) and A * c <= 4096 and c >= 1
+        assert prod == N
+        assert all(f <= 31 for f in _factors(N))
+        if G == 1:
+            assert kinds == [52, 67 if grad else 60]
+            continue
+        layer = [54] * (G - 2) + [56] + [55] * (G - 2)
+        fwd = [53]
+        for k in range(p):
+            fwd += layer + ([57] if k + 1 < p else [58])
+        if not grad:
+            assert kinds == [52] + fwd + [8]
+        else:
+            back = []
+            for k in range(p - 1, -1, -1):
+                back += [62] * (G - 2) + [64] + [63] * (G - 2) + ([65] if k > 0 else [66])
+            assert kinds == [52] + fwd[:-1] + [61] + back + [8, 25]
+        assert lib.qva_workspace_bytes(ctypes.byref(pr), p, grad) > 0
+
+
+def test_plan_large_prime_factor_stays_bluestein(lib):
+    """A prime factor above 31 (4097 = 17 x 241, 1009 prime): Bluestein."""
+    for N in (4097, 1009, 2 * 37 * 512):
+        pr = _prob(mixer=1, n=(N - 1).bit_length(), kind=1, n_states=N)
+        cnt = lib.qva_plan(ctypes.byref(pr), 2, 0, 1, None, 0)
+        arr = (_lib.QvaPassInfo * cnt)()
+        lib.qva_plan(ctypes.byref(pr), 2, 0, 1, arr, cnt)
+        kinds = [x.kind for x in arr]
+        assert 52 not in kinds and 34 in kinds
+
+
+def test_group_split_setting(lib):
+    """qva_set_group_split validates the split and the planner follows it;
+    count 0 restores the default (fewest groups of <= 9, near-equal)."""
+    S = _lib
+    IntArr = ctypes.c_int * 8
+    out = IntArr()
+    assert lib.qva_get_group_split(28, out, 8) == 2 and list(out)[:2] == [8, 8]
+    assert lib.qva_get_group_split(12, out, 8) == 0
+    assert lib.qva_set_group_split(28, IntArr(9, 7), 2) == S.QVA_OK
+    try:
+        assert lib.qva_get_group_split(28, out, 8) == 2 and list(out)[:2] == [9, 7]
+        pr = _prob(n=28)
+        cnt = lib.qva_plan(ctypes.byref(pr), 2, 0, 1, None, 0)
+        arr = (_lib.QvaPassInfo * cnt)()
+        lib.qva_plan(ctypes.byref(pr), 2, 0, 1, arr, cnt)
+        groups = sorted({(x.group_first, x.group_bits, x.col_bits) for x in arr if x.group_first >= 0})
+        assert groups == [(0, 12, 0), (12, 9, 3), (21, 7, 5)]
+        assert lib.qva_set_group_split(28, IntArr(6, 5, 5), 3) == S.QVA_OK
+        cnt = lib.qva_plan(ctypes.byref(pr), 2, 0, 1, None, 0)
+        assert cnt == 2 * (4 - 1) + 1 + 1  # p (P - 1) + 1 passes and the reduction
+    finally:
+        assert lib.qva_set_group_split(28, None, 0) == S.QVA_OK
+    assert lib.qva_get_group_split(28, out, 8) == 2 and list(out)[:2] == [8, 8]
+    assert lib.qva_set_group_split(28, IntArr(10, 6), 2) == S.QVA_ERR_ARG   # a group above 9
+    assert lib.qva_set_group_split(28, IntArr(8, 7), 2) == S.QVA_ERR_ARG    # sums to 15, not 16
+    assert lib.qva_set_group_split(28, IntArr(0, 16), 2) == S.QVA_ERR_ARG
+    assert lib.qva_set_group_split(12, IntArr(1), 1) == S.QVA_ERR_SIZE
+    assert lib.qva_set_group_split(34, IntArr(9, 9, 4), 3) == S.QVA_ERR_SIZE
+    assert lib.qva_set_group_split(28, None, 2) == S.QVA_ERR_ARG
