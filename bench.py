@@ -237,6 +237,13 @@ for _k in range(26, 30):
     KIND_FAMILIES[_k] = ("complete_kernel",)
 for _k in range(46, 50):
     KIND_FAMILIES[_k] = ("gradb_kernel",)
+KIND_FAMILIES[52] = ("mr_geom_kernel", "mr_table_kernel")
+for _k in list(range(53, 60)) + [62, 63]:
+    KIND_FAMILIES[_k] = ("mrpass_kernel",)
+for _k in (60, 67):
+    KIND_FAMILIES[_k] = ("mrsmall_kernel",)
+for _k in (61, 64, 65, 66):
+    KIND_FAMILIES[_k] = ("mrgrad_kernel",)
 
 
 def zterm_label(name: str) -> str:
@@ -301,9 +308,10 @@ def segment_problem(name: str):
 
 def launch_dispatches(info, slots: bool) -> int:
     """Kernel dispatches of one plan launch: the backward transform passes
-    without inner products run once per vector, and the gradient's slot sums
-    are two kernels when there are per-tile slots."""
-    if info.kind in (22, 23):
+    without inner products run once per vector, the mixed-radix tables are
+    two kernels, and the gradient's slot sums are two kernels when there are
+    per-tile slots."""
+    if info.kind in (22, 23, 52, 62, 63):  # 52: the geometry copy, then the tables
         return 2
     if info.kind == 25:
         return 2 if slots else 1
@@ -386,7 +394,7 @@ def counter_dispatches(folder: str, counter: str) -> list:
             for row in csv.DictReader(fh):
                 if row.get("Counter_Name") != counter:
                     continue
-                key = (int(row.get("Agent_Id", 0) or 0), int(row["Dispatch_Id"]))
+                key = (str(row.get("Agent_Id", "")), int(row["Dispatch_Id"]))
                 name = row.get("Kernel_Name", "")
                 prev = rows.get(key)
                 rows[key] = (key[1], name, (prev[2] if prev else 0.0) + float(row["Counter_Value"]))
@@ -1195,6 +1203,74 @@ def extra_batch(lib, with_oracle: bool = True) -> dict:
             "oracle": oracle_sample}
 
 
+def extra_autotune(lib) -> dict:
+    """The strided-group split searched by timing (autotune.tune_split) for
+    the n = 28 QAOA evolution, the 2^26 QWOA ring evolution and the n = 30
+    adjoint; then per qubit count of the 512-instance batch (each n's split
+    timed on the adjoint of its deepest instance) and the batch re-planned
+    with the chosen splits; the batch's per-launch profile (idle tail of
+    launches that cannot fill the GPU).  Every split is reset to the
+    library default afterwards."""
+    import torch
+
+    import paper_2110_03963_amd as qva
+    from paper_2110_03963_amd import autotune
+    from workloads import (CONFIG_SEEDS, batched_workloads, maxcut_qualities_device, qaoa_maxcut_workload,
+                           qwoa_portfolio_workload)
+
+    out = {}
+    tmp = os.path.join("gpurun_out" if os.path.isdir("gpurun_out") else "/tmp", "qva_tune_bench.json")
+    if os.path.exists(tmp):
+        os.remove(tmp)
+    try:
+        wl = qaoa_maxcut_workload(28, 8, graph="regular3", weighted=True, seed=CONFIG_SEEDS["qaoa_n28"],
+                                  build_q=False)
+        prob = qva.Problem(maxcut_qualities_device(28, wl.edges, wl.weights, "cuda"), "x")
+        out["qaoa_n28_p8_evolve"] = autotune.tune_split(prob, wl.gammas, wl.ts, call="evolve", reps=5, path=tmp)
+        del prob
+        wq = qwoa_portfolio_workload(26, 6, seed=CONFIG_SEEDS["qwoa_n26"], lambda_kind="ring")
+        prob = qva.Problem(torch.from_numpy(wq.q).cuda(), "circulant", None, "ring")
+        out["qwoa_n26_p6_ring_evolve"] = autotune.tune_split(prob, wq.gammas, wq.ts, call="evolve", reps=5,
+                                                              path=tmp)
+        del prob
+        torch.cuda.empty_cache()
+        w30 = qaoa_maxcut_workload(30, 12, graph="regular3", weighted=True, seed=CONFIG_SEEDS["grad_n30"],
+                                   build_q=False)
+        prob = qva.Problem(maxcut_qualities_device(30, w30.edges, w30.weights, "cuda"), "x")
+        out["qaoa_n30_p12_grad"] = autotune.tune_split(prob, w30.gammas, w30.ts, call="grad", reps=3, path=tmp)
+        del prob
+        torch.cuda.empty_cache()
+        for n in (28, 26, 30):
+            autotune.set_split(n, None)
+        # the batch: default splits first, then each n's tuned split
+        wls = batched_workloads(512, seed=CONFIG_SEEDS["batch512"], build_q=False)
+        qs = [maxcut_qualities_device(w.n, w.edges, w.weights, "cuda") for w in wls]
+        gs = [w.gammas for w in wls]
+        tsl = [w.ts for w in wls]
+        b = qva.Batch(qs, gs, tsl, align="start")
+        ms_default = autotune.time_batch_grad(b, reps=3)
+        prof = autotune.batch_launch_profile(b)
+        del b
+        per_n = {}
+        for n in sorted({w.n for w in wls if w.n > 12}):
+            i = max((k for k, w in enumerate(wls) if w.n == n), key=lambda k: wls[k].p)
+            pr = qva.Problem(qs[i], "x")
+            per_n[n] = autotune.tune_split(pr, wls[i].gammas, wls[i].ts, call="grad", reps=5, path=tmp)
+        b = qva.Batch(qs, gs, tsl, align="start")
+        ms_tuned = autotune.time_batch_grad(b, reps=3)
+        del b
+        out["batch512"] = {"ms_default_splits": round(ms_default, 3), "ms_tuned_splits": round(ms_tuned, 3),
+                           "splits": {n: {"split": v["split"], "default": v["default"], "ms": v["ms"]}
+                                      for n, v in per_n.items()},
+                           "launch_profile_default": {k: v for k, v in prof.items() if k != "rounds"},
+                           "rounds_default": prof["rounds"]}
+    finally:
+        for n in range(13, 34):
+            autotune.set_split(n, None)
+        torch.cuda.empty_cache()
+    return out
+
+
 # Secondary measurements: name -> fn(lib, steps).
 EXTRAS = {
     "qwoa_circulant": lambda lib, steps: extra_qwoa(lib, max(3, steps // 2)),
@@ -1208,6 +1284,7 @@ EXTRAS = {
     "adjoint_qwoa_constrained_ring": lambda lib, steps: extra_adjoint(lib, 3, "qwoa_constrained_ring"),
     "batched": lambda lib, steps: extra_batch(lib),
     "qaoa_n10": lambda lib, steps: extra_small(lib, 500),
+    "autotune": lambda lib, steps: extra_autotune(lib),
     "exqaoa": lambda lib, steps: extra_exqaoa(lib, max(3, steps // 2)),
     "qaoaz": lambda lib, steps: extra_qaoaz(lib, max(3, steps // 2)),
 }

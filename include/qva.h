@@ -449,6 +449,17 @@ int qva_batch_upload(qva_batch_plan plan, void *work, size_t work_bytes, void *s
  * launches on `stream`. */
 int qva_batch_grad(qva_batch_plan plan, void *work, size_t work_bytes, void *stream);
 
+/* qva_batch_grad with events[2i] (hipEvent_t as void*) recorded before
+ * launch i and events[2i+1] after it, for i < n_events / 2 (caller-owned
+ * events); same results. */
+int qva_batch_grad_timed(qva_batch_plan plan, void *work, size_t work_bytes, void *const *events,
+                         int n_events, void *stream);
+
+/* Launch i of qva_batch_grad (0 <= i < qva_batch_launches): its round, its
+ * workgroups (one per 4096-amplitude tile) and its algorithmic HBM bytes.
+ * Any output pointer may be NULL. */
+int qva_batch_launch_info(qva_batch_plan plan, int i, int *round, int64_t *workgroups, double *bytes);
+
 /* gammas -= lr * dgammas and ts -= lr * dts for every instance. */
 int qva_batch_sgd(qva_batch_plan plan, double lr, void *work, size_t work_bytes, void *stream);
 

@@ -141,6 +141,8 @@ SIGNATURES = {
     "qva_batch_upload": (_I, [_P, _P, _SZ, _P]),
     "qva_batch_grad": (_I, [_P, _P, _SZ, _P]),
     "qva_batch_sgd": (_I, [_P, _D, _P, _SZ, _P]),
+    "qva_batch_grad_timed": (_I, [_P, _P, _SZ, ctypes.POINTER(ctypes.c_void_p), _I, _P]),
+    "qva_batch_launch_info": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I64), ctypes.POINTER(_D)]),
     "qva_batch_rounds": (_I, [_P]),
     "qva_batch_launches": (_I, [_P]),
     "qva_batch_tiles": (_I64, [_P]),

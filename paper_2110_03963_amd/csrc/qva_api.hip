@@ -2163,7 +2163,7 @@ int grad_common(const qva_problem* P, const double* gammas_dev, const double* ts
 // ----------------------------------------------------------------- batched
 struct qva_batch_plan_s {
     struct Group {
-        int first, count, kind, mode, col_bits;
+        int first, count, kind, mode, col_bits, round;
     };
     std::vector<BatchInst> inst;
     std::vector<BatchPass> pass;
@@ -2355,7 +2355,7 @@ int qva_batch_create(const qva_batch_item* items, int count, int align, qva_batc
         if (same)
             B->groups.back().count += 1;
         else
-            B->groups.push_back({(int)x, 1, std::get<1>(k), std::get<2>(k), std::get<3>(k)});
+            B->groups.push_back({(int)x, 1, std::get<1>(k), std::get<2>(k), std::get<3>(k), std::get<0>(k)});
     }
     B->tiles_total = (int64_t)B->items.size();
     size_t off = 0;
@@ -2406,7 +2406,11 @@ int qva_batch_upload(qva_batch_plan plan, void* work, size_t work_bytes, void* s
     return QVA_OK;
 }
 
-int qva_batch_grad(qva_batch_plan plan, void* work, size_t work_bytes, void* stream)
+}  // extern "C"
+
+namespace {
+
+int batch_grad_run(qva_batch_plan plan, void* work, size_t work_bytes, void* stream, EventHook& hook)
 {
     if (!plan || !work)
         return QVA_ERR_ARG;
@@ -2420,9 +2424,77 @@ int qva_batch_grad(qva_batch_plan plan, void* work, size_t work_bytes, void* str
     hipStream_t s = as_stream(stream);
     for (const auto& gr : plan->groups) {
         R.first = gr.first;
-        if (launch_batch_group(R, gr.kind, gr.mode, gr.col_bits, gr.count, s) != hipSuccess)
+        hook.before(s);
+        const hipError_t e = launch_batch_group(R, gr.kind, gr.mode, gr.col_bits, gr.count, s);
+        hook.after(s);
+        if (e != hipSuccess)
             return QVA_ERR_HIP;
     }
+    return QVA_OK;
+}
+
+// Algorithmic HBM bytes per amplitude of a batched tile pass.
+double batch_bytes_per_amp(int kind, int mode)
+{
+    if (kind == BP_FWD) {
+        switch (mode) {
+        case XMODE_FIRST:
+            return 24.0;
+        case XMODE_BOUNDARY:
+            return 40.0;
+        case XMODE_LAST:
+            return 24.0;
+        default:
+            return 32.0;
+        }
+    }
+    if (kind == BP_BWD) {
+        switch (mode) {
+        case GMODE_TURN:
+            return 56.0;
+        case GMODE_BOUND:
+            return 72.0;
+        case GMODE_FINAL:
+            return 40.0;
+        default:
+            return 64.0;
+        }
+    }
+    return kind == BP_WHOLE ? 8.0 : 0.0;  // n = 12 whole instances read q; the sums are small
+}
+
+}  // namespace
+
+extern "C" {
+
+int qva_batch_grad(qva_batch_plan plan, void* work, size_t work_bytes, void* stream)
+{
+    EventHook hook;
+    return batch_grad_run(plan, work, work_bytes, stream, hook);
+}
+
+int qva_batch_grad_timed(qva_batch_plan plan, void* work, size_t work_bytes, void* const* events, int n_events,
+                         void* stream)
+{
+    if (!events || n_events < 0)
+        return QVA_ERR_ARG;
+    EventHook hook;
+    hook.ev = events;
+    hook.n = n_events;
+    return batch_grad_run(plan, work, work_bytes, stream, hook);
+}
+
+int qva_batch_launch_info(qva_batch_plan plan, int i, int* round, int64_t* workgroups, double* bytes)
+{
+    if (!plan || i < 0 || i >= (int)plan->groups.size())
+        return QVA_ERR_ARG;
+    const auto& gr = plan->groups[i];
+    if (round)
+        *round = gr.round;
+    if (workgroups)
+        *workgroups = gr.count;
+    if (bytes)
+        *bytes = (double)gr.count * (double)(1 << kTileBits) * batch_bytes_per_amp(gr.kind, gr.mode);
     return QVA_OK;
 }
 

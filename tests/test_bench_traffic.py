@@ -24,7 +24,7 @@ def _csv(path, counter, rows):
         w = csv.DictWriter(fh, ["Agent_Id", "Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
         w.writeheader()
         for i, (name, value) in enumerate(rows):
-            w.writerow({"Agent_Id": 1, "Dispatch_Id": i + 1, "Kernel_Name": name, "Counter_Name": counter,
+            w.writerow({"Agent_Id": "Agent 1", "Dispatch_Id": i + 1, "Kernel_Name": name, "Counter_Name": counter,
                         "Counter_Value": value})
 
 
