@@ -192,6 +192,8 @@ struct MrGeom {
     int64_t tiles[kMrMaxGroups];       // tiles of each group's passes
     int tab_off[kMrMaxGroups];         // group g's tables start at entry tab_off[g]
     int tab_len;                       // sum of A_g
+    double rA[kMrMaxGroups];           // 1 / A_g (the passes' integer divisions)
+    int64_t U;                         // N / A_0, the low group's column count
 };
 
 // Pass modes of the mixed-radix passes (mrpass_kernel / mrgrad_kernel).

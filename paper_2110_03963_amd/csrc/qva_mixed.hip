@@ -31,9 +31,10 @@ namespace {
 constexpr int kMrThreads = 256;
 constexpr int kMrRegs = kMrTileElems / kMrThreads;
 
-// q = floor(e / d) for 0 <= e < 2^20, d >= 1 via the reciprocal rd = 1/d in
-// double: (e + 1/2) / d lies at least 1/(2d) inside (q, q + 1), far beyond
-// the rounding error of the product.
+// q = floor(e / d) for 0 <= e < 2^31, 1 <= d <= 4096 via the reciprocal
+// rd = 1/d in double: (e + 1/2) / d lies at least 1/(2d) >= 2^-13 inside
+// (q, q + 1), far beyond the rounding error of rd and of the product
+// (below 2^31 * 2^-52 = 2^-21).
 __device__ __forceinline__ int divq(int e, double rd) { return (int)(((double)e + 0.5) * rd); }
 
 struct MrTile {
@@ -87,11 +88,13 @@ __device__ __forceinline__ MrTile mr_tile(const MrGeom* __restrict__ m, int g, i
 __device__ __forceinline__ double2 conj_if(double2 a, bool c) { return make_double2(a.x, c ? -a.y : a.y); }
 
 // R-point DFT of x in registers, y_m = sum_k x_k W_R^(k m) (inverse: W^-1),
-// with each output handed to out(m, y_m).  root(j) = W_R^j (forward sign).
-// Odd R = 2h + 1: with a_k = x_k + x_{R-k}, b_k = x_k - x_{R-k} (k <= h),
+// with each output handed to out(m, y_m) in pair order: m = 0, then m, R - m
+// for m = 1, 2, ..., then m = R/2 for even R.  root(j) = W_R^j (forward sign).
+// Odd R = 2h + 1: with a_k = x_k + x_{R-k}, b_k = x_k - x_{R-k} (k <= h, formed
+// in place in x),
 //   y_m = x_0 + sum_k a_k cos(2 pi k m / R) - i sum_k b_k sin(2 pi k m / R),
 // and y_{R-m} the same with +i, so each pair of outputs costs 4h FMAs.
-// R = 2^w: radix-2 DIF stages in registers, outputs bit-reversed.
+// R = 2^w: radix-2 DIF stages in registers, outputs read bit-reversed.
 template <int R, typename Root, typename Out>
 __device__ __forceinline__ void dft_regs(double2 (&x)[R], bool inv, Root&& root, Out&& out)
 {
@@ -115,31 +118,30 @@ __device__ __forceinline__ void dft_regs(double2 (&x)[R], bool inv, Root&& root,
                 x[r | half] = l == 0 ? d : cmul(d, w[l * (R / (2 * half))]);
             }
         }
-#pragma unroll
-        for (int m = 0; m < R; ++m) {
+        auto rev = [](int m) {
             int rv = 0;
 #pragma unroll
             for (int i = 0; i < W; ++i)
                 rv |= ((m >> i) & 1) << (W - 1 - i);
-            out(m, x[rv]);
+            return rv;
+        };
+        out(0, x[0]);
+#pragma unroll
+        for (int m = 1; m < R / 2; ++m) {
+            out(m, x[rev(m)]);
+            out(R - m, x[rev(R - m)]);
         }
+        out(R / 2, x[rev(R / 2)]);
     } else {
         constexpr int H = R / 2;
-        double cs[H], sn[H];  // cos, sin of 2 pi j / R, j = 1..H
-#pragma unroll
-        for (int j = 0; j < H; ++j) {
-            const double2 r = root(j + 1);  // (cos, -sin)
-            cs[j] = r.x;
-            sn[j] = inv ? r.y : -r.y;       // the inverse flips the sine
-        }
-        double2 a[H], b[H];
         double2 y0 = x[0];
 #pragma unroll
         for (int k = 1; k <= H; ++k) {
-            a[k - 1] = make_double2(x[k].x + x[R - k].x, x[k].y + x[R - k].y);
-            b[k - 1] = make_double2(x[k].x - x[R - k].x, x[k].y - x[R - k].y);
-            y0.x += a[k - 1].x;
-            y0.y += a[k - 1].y;
+            const double2 u = x[k], v = x[R - k];
+            x[k] = make_double2(u.x + v.x, u.y + v.y);      // a_k
+            x[R - k] = make_double2(u.x - v.x, u.y - v.y);  // b_k
+            y0.x += x[k].x;
+            y0.y += x[k].y;
         }
         out(0, y0);
 #pragma unroll
@@ -148,12 +150,13 @@ __device__ __forceinline__ void dft_regs(double2 (&x)[R], bool inv, Root&& root,
 #pragma unroll
             for (int k = 1; k <= H; ++k) {
                 const int j = (k * m) % R;  // 1 .. R - 1
-                const double c = j <= H ? cs[j - 1] : cs[R - j - 1];
-                const double sv = j <= H ? sn[j - 1] : -sn[R - j - 1];
-                P.x = fma(a[k - 1].x, c, P.x);
-                P.y = fma(a[k - 1].y, c, P.y);
-                Q.x = fma(b[k - 1].x, sv, Q.x);
-                Q.y = fma(b[k - 1].y, sv, Q.y);
+                const double2 r = root(j <= H ? j : R - j);  // (cos, -sin) of 2 pi j' / R
+                const double c = r.x;
+                const double sv = (j <= H) != inv ? -r.y : r.y;  // sin(2 pi j / R), inverse flipped
+                P.x = fma(x[k].x, c, P.x);
+                P.y = fma(x[k].y, c, P.y);
+                Q.x = fma(x[R - k].x, sv, Q.x);
+                Q.y = fma(x[R - k].y, sv, Q.y);
             }
             // y_m = P - i Q, y_{R-m} = P + i Q
             out(m, make_double2(P.x + Q.y, P.y - Q.x));
@@ -165,20 +168,26 @@ __device__ __forceinline__ void dft_regs(double2 (&x)[R], bool inv, Root&& root,
 
 // One DIF stage of radix R over sub-length L of every column's A-point DFT
 // in LDS: butterfly (b, i), i < L/R, takes elements b L + i + k L/R, forms
-// y_m = sum_k x_k W_R^(k m), multiplies y_m by W_L^(i m) and writes it back
-// in place.  Roots from the group table tab[k] = W_A^k (conjugated: inverse).
+// y_m = sum_k x_k W_R^(k m), multiplies y_m by the twiddle W_L^(i m) and
+// writes it back in place.  Roots from the group table tab[k] = W_A^k
+// (conjugated: inverse).  The twiddles follow from two table roots per
+// butterfly, w = W_L^i and W_L^(i R): W_L^(i m) = W_L^(i (m-1)) w for
+// m <= R/2 and W_L^(i R) conj(W_L^(i (R-m))) above, at most R/2 + 1 rounded
+// products (about 2e-15 for R = 31), read before the butterfly's inputs so
+// that no load waits inside the DFT.  The last stage (L = R) has none.
 // LDS slot of (col, j): col A + j (low group) or j ncol + col.
-template <int R>
-__device__ __forceinline__ void mr_stage(double2* lds, int A, int ncol, bool low, int L,
-                                         const double2* __restrict__ tab, bool inv)
+template <int R, bool TW>
+__device__ __forceinline__ void mr_stage_tw(double2* lds, int A, int ncol, bool low, int L,
+                                            const double2* __restrict__ tab, bool inv)
 {
     // rstep = A / R, formed from L so that it varies with the stage: the
     // root loads of the different radices are then not hoisted out of the
     // stage loop (held at once, they would exhaust the registers)
-    const int mstride = L / R, per_col = A / R, tstep = A / L, rstep = mstride * tstep;
+    const int mstride = L / R, per_col = A / R, tstep = A / L, rstep = mstride * tstep, wstep = R * tstep;
     const int items = ncol * per_col;
     const double rpc = 1.0 / (double)per_col, rms = 1.0 / (double)mstride, rnc = 1.0 / (double)ncol;
     const int cs = low ? A : 1, js = low ? 1 : ncol;  // LDS strides of col and j
+    constexpr int H = R / 2;
     for (int it = threadIdx.x; it < items; it += kMrThreads) {
         int col, bi;
         if (low) {  // i fastest: consecutive threads take consecutive j
@@ -190,22 +199,46 @@ __device__ __forceinline__ void mr_stage(double2* lds, int A, int ncol, bool low
         }
         const int b = divq(bi, rms), i = bi - b * mstride;
         const int base = col * cs + (b * L + i) * js, step = mstride * js;
+        double2 w1 = make_double2(1.0, 0.0), wr = w1;
+        if constexpr (TW) {
+            w1 = conj_if(tab[i * tstep], inv);
+            wr = conj_if(tab[i * wstep], inv);
+        }
         double2 x[R];
 #pragma unroll
         for (int k = 0; k < R; ++k)
             x[k] = lds[base + k * step];
+        double2 wm = w1;  // W_L^(i m) of the last m <= H
         dft_regs<R>(x, inv, [&](int j) { return tab[j * rstep]; }, [&](int m, double2 y) {
-            if (m > 0 && i > 0)
-                y = cmul(y, conj_if(tab[i * m * tstep], inv));
+            if constexpr (TW) {
+                if (m > H) {
+                    y = cmul(y, cmul(wr, make_double2(wm.x, -wm.y)));
+                } else if (m > 0) {
+                    if (m > 1)
+                        wm = cmul(wm, w1);
+                    y = cmul(y, wm);
+                }
+            }
             lds[base + m * step] = y;
         });
     }
 }
 
-// Every DIF stage of one group's DFT on the tile in LDS.  BIG: radices up
-// to 31 (the kernels built with it run one wave per SIMD: the radix-17..31
-// stages need the registers); otherwise radices up to 16.
-template <bool BIG>
+template <int R>
+__device__ __forceinline__ void mr_stage(double2* lds, int A, int ncol, bool low, int L,
+                                         const double2* __restrict__ tab, bool inv)
+{
+    if (L > R)
+        mr_stage_tw<R, true>(lds, A, ncol, low, L, tab, inv);
+    else
+        mr_stage_tw<R, false>(lds, A, ncol, low, L, tab, inv);
+}
+
+// Every DIF stage of one group's DFT on the tile in LDS.  MAXR: the largest
+// radix the kernel is built for (16, 23 or 31); the radix-17..23 stages fit
+// two waves per SIMD in the single-vector passes, radices 29 and 31 need the
+// registers of one wave per SIMD.
+template <int MAXR>
 __device__ __forceinline__ void mr_stages(double2* lds, int A, int ncol, bool low, const double2* __restrict__ gt,
                                           const int* __restrict__ rad, int nrad, bool inv)
 {
@@ -223,13 +256,19 @@ __device__ __forceinline__ void mr_stages(double2* lds, int A, int ncol, bool lo
         case 13: mr_stage<13>(lds, A, ncol, low, L, gt, inv); break;
         case 16: mr_stage<16>(lds, A, ncol, low, L, gt, inv); break;
         default:
-            if constexpr (BIG) {
+            if constexpr (MAXR >= 23) {
                 switch (r) {
                 case 17: mr_stage<17>(lds, A, ncol, low, L, gt, inv); break;
                 case 19: mr_stage<19>(lds, A, ncol, low, L, gt, inv); break;
                 case 23: mr_stage<23>(lds, A, ncol, low, L, gt, inv); break;
-                case 29: mr_stage<29>(lds, A, ncol, low, L, gt, inv); break;
-                default: mr_stage<31>(lds, A, ncol, low, L, gt, inv); break;
+                default:
+                    if constexpr (MAXR >= 31) {
+                        if (r == 29)
+                            mr_stage<29>(lds, A, ncol, low, L, gt, inv);
+                        else
+                            mr_stage<31>(lds, A, ncol, low, L, gt, inv);
+                    }
+                    break;
                 }
             }
             break;
@@ -242,7 +281,7 @@ __device__ __forceinline__ void mr_stages(double2* lds, int A, int ncol, bool lo
 // The group DFT of every column of the tile, through LDS: v holds elements
 // e = t + 256 k in natural j order on entry and natural frequency order on
 // return (forward: exponent sign -, inv: +; no 1/A).
-template <bool BIG>
+template <int MAXR>
 __device__ __forceinline__ void mr_dft(double2 (&v)[kMrRegs], double2* lds, const MrTile& T,
                                        const MrGeom* __restrict__ m, int g, const double2* tab, const int* perm,
                                        bool inv)
@@ -257,7 +296,7 @@ __device__ __forceinline__ void mr_dft(double2 (&v)[kMrRegs], double2* lds, cons
             lds[e] = v[k];
     }
     __syncthreads();
-    mr_stages<BIG>(lds, T.A, T.ncol, T.low, tab + m->tab_off[g], m->rad[g], m->nrad[g], inv);
+    mr_stages<MAXR>(lds, T.A, T.ncol, T.low, tab + m->tab_off[g], m->rad[g], m->nrad[g], inv);
 #pragma unroll
     for (int k = 0; k < kMrRegs; ++k) {
         const int e = t + k * kMrThreads;
@@ -288,20 +327,20 @@ __device__ __forceinline__ void mr_twiddle(double2 (&v)[kMrRegs], const MrTile& 
     }
 }
 
-template <bool BIG>
+template <int MAXR>
 __device__ __forceinline__ void mr_forward(double2 (&v)[kMrRegs], double2* lds, const MrTile& T, const MrGeom* m,
                                            int g, const double2* tab, const int* perm)
 {
-    mr_dft<BIG>(v, lds, T, m, g, tab, perm, false);
+    mr_dft<MAXR>(v, lds, T, m, g, tab, perm, false);
     mr_twiddle(v, T, m, g, false);
 }
 
-template <bool BIG>
+template <int MAXR>
 __device__ __forceinline__ void mr_inverse(double2 (&v)[kMrRegs], double2* lds, const MrTile& T, const MrGeom* m,
                                            int g, const double2* tab, const int* perm)
 {
     mr_twiddle(v, T, m, g, true);
-    mr_dft<BIG>(v, lds, T, m, g, tab, perm, true);
+    mr_dft<MAXR>(v, lds, T, m, g, tab, perm, true);
 }
 
 __device__ __forceinline__ void mr_load(double2 (&v)[kMrRegs], const double2* psi, const MrTile& T)
@@ -328,42 +367,67 @@ __device__ __forceinline__ void mr_store(const double2 (&v)[kMrRegs], double2* p
 // The global frequency m held by element (col, f) of a low-group tile after
 // its forward DFT: m = rev(u) + (N / A_0) f, u = first + col the upper index
 // and rev(u) = p_{G-1} + A_{G-1} (p_{G-2} + ... + A_2 p_1) for
-// u = p_1 + A_1 (p_2 + ...).
-__device__ __forceinline__ int64_t mr_freq(const MrGeom* __restrict__ m, int64_t u, int f)
+// u = p_1 + A_1 (p_2 + ...)  (u < N / A_0 < 2^31).
+__device__ __forceinline__ int64_t mr_rev(const MrGeom* __restrict__ m, int64_t u64)
 {
+    int u = (int)u64;
     int64_t rev = 0;
     const int G = m->G;
     for (int g = 1; g < G; ++g) {
-        const int64_t A = m->A[g];
-        const int64_t d = u % A;
-        u /= A;
-        rev = rev * A + d;
+        const int A = m->A[g];
+        const int q = divq(u, m->rA[g]);
+        rev = rev * A + (u - q * A);
+        u = q;
     }
-    return rev + (m->S[G] / m->A[0]) * (int64_t)f;
+    return rev;
 }
 
-__device__ __forceinline__ double mr_lambda(const MrPassParams& P, int64_t mfreq)
+// Columns of a low-group tile whose ring rotation exp(2 pi i rev(u) / N) is
+// kept in LDS (tiles with more columns compute lambda per element).
+constexpr int kMrColRot = 256;
+
+// colrot[c] = (cos, sin)(2 pi rev(first + c) / N) for the ring, so that
+// lambda at (col, f) is 2 cos(2 pi rev / N + 2 pi f / A_0), one product with
+// the group's root W_{A_0}^f.  Read after the next __syncthreads.
+__device__ __forceinline__ void mr_colrot(double2* colrot, const MrPassParams& P, const MrTile& T)
 {
+    if (P.lambda_kind != FFT_LAMBDA_RING || T.ncol > kMrColRot)
+        return;
+    for (int c = threadIdx.x; c < T.ncol; c += kMrThreads) {
+        double s, co;
+        sincospi_red((double)(2 * mr_rev(P.geom, T.first + c)) / (double)P.N, &s, &co);
+        colrot[c] = make_double2(co, s);
+    }
+}
+
+// lambda at element e of a low-group tile after the forward DFT.
+__device__ __forceinline__ double mr_lambda_at(const MrPassParams& P, const MrTile& T, const double2* colrot, int e)
+{
+    const int col = T.col_of(e), f = T.j_of(e);
     if (P.lambda_kind == FFT_LAMBDA_RING) {
+        if (T.ncol <= kMrColRot) {
+            const double2 a = colrot[col], w = P.tab[f];  // w = (cos, -sin)(2 pi f / A_0)
+            return 2.0 * fma(a.x, w.x, a.y * w.y);
+        }
         double s, c;
-        sincospi_red((double)(2 * mfreq) / (double)P.N, &s, &c);  // 2 cos(2 pi m / N)
+        const int64_t mf = mr_rev(P.geom, T.first + col) + P.geom->U * (int64_t)f;
+        sincospi_red((double)(2 * mf) / (double)P.N, &s, &c);  // 2 cos(2 pi m / N)
         return 2.0 * c;
     }
-    return P.lam[mfreq];
+    return P.lam[mr_rev(P.geom, T.first + col) + P.geom->U * (int64_t)f];
 }
 
 // psi <- exp(-i tt lambda_m) psi at the frequencies of a low-group tile
 // (natural order after mr_forward).
-__device__ __forceinline__ void mr_diag(double2 (&v)[kMrRegs], const MrPassParams& P, const MrTile& T, double tt)
+__device__ __forceinline__ void mr_diag(double2 (&v)[kMrRegs], const MrPassParams& P, const MrTile& T,
+                                        const double2* colrot, double tt)
 {
     const int t = threadIdx.x, ne = T.ncol * T.A;
 #pragma unroll
     for (int k = 0; k < kMrRegs; ++k) {
         const int e = t + k * kMrThreads;
-        if (e < ne) {
-            const int64_t mf = mr_freq(P.geom, T.first + T.col_of(e), T.j_of(e));
-            v[k] = cmul(v[k], expmi(tt * mr_lambda(P, mf)));
-        }
+        if (e < ne)
+            v[k] = cmul(v[k], expmi(tt * mr_lambda_at(P, T, colrot, e)));
         QVA_SCHED_FENCE();
     }
 }
@@ -402,8 +466,8 @@ __device__ __forceinline__ void mr_expect(const double2 (&v)[kMrRegs], const dou
         *out = tot;
 }
 
-template <int MODE, bool BIG>
-__global__ __launch_bounds__(kMrThreads, BIG ? 1 : 2) void mrpass_kernel(MrPassParams P)
+template <int MODE, int MAXR>
+__global__ __launch_bounds__(kMrThreads, MAXR <= 23 ? 2 : 1) void mrpass_kernel(MrPassParams P)
 {
     __shared__ double2 lds[kMrTileElems];
     __shared__ double red[2 * (kMrThreads / 64)];
@@ -419,32 +483,34 @@ __global__ __launch_bounds__(kMrThreads, BIG ? 1 : 2) void mrpass_kernel(MrPassP
         for (int k = 0; k < kMrRegs; ++k)
             v[k] = make_double2(a0, 0.0);
         mr_phase(v, P.q, T, angle_value(P.gamma), 1.0);
-        mr_forward<BIG>(v, lds, T, m, g, P.tab, perm);
+        mr_forward<MAXR>(v, lds, T, m, g, P.tab, perm);
         mr_store(v, P.psi, T, 1.0);
     } else if constexpr (MODE == MR_DIF) {
         mr_load(v, P.psi, T);
-        mr_forward<BIG>(v, lds, T, m, g, P.tab, perm);
+        mr_forward<MAXR>(v, lds, T, m, g, P.tab, perm);
         mr_store(v, P.psi, T, 1.0);
     } else if constexpr (MODE == MR_DIT) {
         mr_load(v, P.psi, T);
-        mr_inverse<BIG>(v, lds, T, m, g, P.tab, perm);
+        mr_inverse<MAXR>(v, lds, T, m, g, P.tab, perm);
         mr_store(v, P.psi, T, 1.0);
     } else if constexpr (MODE == MR_LOWDIAG) {
+        __shared__ double2 colrot[kMrColRot];
+        mr_colrot(colrot, P, T);
         mr_load(v, P.psi, T);
-        mr_forward<BIG>(v, lds, T, m, g, P.tab, perm);
-        mr_diag(v, P, T, angle_value(P.t));
-        mr_inverse<BIG>(v, lds, T, m, g, P.tab, perm);
+        mr_forward<MAXR>(v, lds, T, m, g, P.tab, perm);  // its first barrier publishes colrot
+        mr_diag(v, P, T, colrot, angle_value(P.t));
+        mr_inverse<MAXR>(v, lds, T, m, g, P.tab, perm);
         mr_store(v, P.psi, T, 1.0);
     } else if constexpr (MODE == MR_BOUNDARY) {
         const double gam = angle_value(P.gamma);
         mr_load(v, P.psi, T);
-        mr_inverse<BIG>(v, lds, T, m, g, P.tab, perm);
+        mr_inverse<MAXR>(v, lds, T, m, g, P.tab, perm);
         mr_phase(v, P.q, T, gam, invN);
-        mr_forward<BIG>(v, lds, T, m, g, P.tab, perm);
+        mr_forward<MAXR>(v, lds, T, m, g, P.tab, perm);
         mr_store(v, P.psi, T, 1.0);
     } else {  // MR_LAST, MR_LAST_STORE
         mr_load(v, P.psi, T);
-        mr_inverse<BIG>(v, lds, T, m, g, P.tab, perm);
+        mr_inverse<MAXR>(v, lds, T, m, g, P.tab, perm);
 #pragma unroll
         for (int k = 0; k < kMrRegs; ++k)
             v[k] = make_double2(v[k].x * invN, v[k].y * invN);
@@ -461,7 +527,7 @@ __device__ __forceinline__ double im_term(double2 x, double2 p) { return x.x * p
 // transforms applied to each vector in turn through one LDS buffer, with the
 // inner products taken where both are at hand.  Passes with per-tile slots
 // run on max_tiles workgroups: those beyond the group's tiles write a zero.
-template <int MODE, bool BIG>
+template <int MODE, int MAXR>
 __global__ __launch_bounds__(kMrThreads, 1) void mrgrad_kernel(MrPassParams P)
 {
     __shared__ double2 lds[kMrTileElems];
@@ -481,7 +547,7 @@ __global__ __launch_bounds__(kMrThreads, 1) void mrgrad_kernel(MrPassParams P)
     double2 p[kMrRegs], x[kMrRegs];
     if constexpr (MODE == MRG_TURN) {
         mr_load(p, P.psi, T);
-        mr_inverse<BIG>(p, lds, T, m, g, P.tab, perm);
+        mr_inverse<MAXR>(p, lds, T, m, g, P.tab, perm);
         double f = 0.0, nr = 0.0;
 #pragma unroll
         for (int k = 0; k < kMrRegs; ++k) {
@@ -496,22 +562,24 @@ __global__ __launch_bounds__(kMrThreads, 1) void mrgrad_kernel(MrPassParams P)
         const double2 tot = block_sum2(f, nr, red);
         if (t == 0)
             P.partials[blockIdx.x] = tot;
-        mr_forward<BIG>(p, lds, T, m, g, P.tab, perm);
-        mr_forward<BIG>(x, lds, T, m, g, P.tab, perm);
+        mr_forward<MAXR>(p, lds, T, m, g, P.tab, perm);
+        mr_forward<MAXR>(x, lds, T, m, g, P.tab, perm);
         mr_store(p, P.psi, T, 1.0);
         mr_store(x, P.chi, T, 1.0);
     } else if constexpr (MODE == MRG_LOWDIAG) {
+        __shared__ double2 colrot[kMrColRot];
+        mr_colrot(colrot, P, T);
         const double tt = angle_value(P.t);
         mr_load(p, P.psi, T);
         mr_load(x, P.chi, T);
-        mr_forward<BIG>(p, lds, T, m, g, P.tab, perm);
-        mr_forward<BIG>(x, lds, T, m, g, P.tab, perm);
+        mr_forward<MAXR>(p, lds, T, m, g, P.tab, perm);
+        mr_forward<MAXR>(x, lds, T, m, g, P.tab, perm);
         double acc = 0.0;
 #pragma unroll
         for (int k = 0; k < kMrRegs; ++k) {
             const int e = t + k * kMrThreads;
             if (e < ne) {
-                const double lam = mr_lambda(P, mr_freq(m, T.first + T.col_of(e), T.j_of(e)));
+                const double lam = mr_lambda_at(P, T, colrot, e);
                 acc = fma(lam, im_term(x[k], p[k]), acc);
                 const double2 d = expmi(-tt * lam);  // exp(+i t lambda): the inverse diagonal
                 p[k] = cmul(p[k], d);
@@ -522,15 +590,15 @@ __global__ __launch_bounds__(kMrThreads, 1) void mrgrad_kernel(MrPassParams P)
         const double2 tot = block_sum2(acc * invN, 0.0, red);
         if (t == 0)
             P.slot[blockIdx.x] = tot.x;
-        mr_inverse<BIG>(p, lds, T, m, g, P.tab, perm);
-        mr_inverse<BIG>(x, lds, T, m, g, P.tab, perm);
+        mr_inverse<MAXR>(p, lds, T, m, g, P.tab, perm);
+        mr_inverse<MAXR>(x, lds, T, m, g, P.tab, perm);
         mr_store(p, P.psi, T, 1.0);
         mr_store(x, P.chi, T, 1.0);
     } else {  // MRG_BOUND, MRG_FINAL
         mr_load(p, P.psi, T);
         mr_load(x, P.chi, T);
-        mr_inverse<BIG>(p, lds, T, m, g, P.tab, perm);
-        mr_inverse<BIG>(x, lds, T, m, g, P.tab, perm);
+        mr_inverse<MAXR>(p, lds, T, m, g, P.tab, perm);
+        mr_inverse<MAXR>(x, lds, T, m, g, P.tab, perm);
         const double gam = angle_value(P.gamma);
         double acc = 0.0;
 #pragma unroll
@@ -553,8 +621,8 @@ __global__ __launch_bounds__(kMrThreads, 1) void mrgrad_kernel(MrPassParams P)
         if (t == 0)
             P.slot[blockIdx.x] = tot.x;
         if constexpr (MODE == MRG_BOUND) {
-            mr_forward<BIG>(p, lds, T, m, g, P.tab, perm);
-            mr_forward<BIG>(x, lds, T, m, g, P.tab, perm);
+            mr_forward<MAXR>(p, lds, T, m, g, P.tab, perm);
+            mr_forward<MAXR>(x, lds, T, m, g, P.tab, perm);
             mr_store(p, P.psi, T, 1.0);
             mr_store(x, P.chi, T, 1.0);
         }
@@ -563,16 +631,18 @@ __global__ __launch_bounds__(kMrThreads, 1) void mrgrad_kernel(MrPassParams P)
 
 // N <= 4096 (one group): the whole evolution, and with MRG_SMALL the adjoint
 // walk, in one workgroup.
-template <int MODE, bool BIG>
+template <int MODE, int MAXR>
 __global__ __launch_bounds__(kMrThreads, 1) void mrsmall_kernel(MrPassParams P)
 {
     __shared__ double2 lds[kMrTileElems];
     __shared__ double red[2 * (kMrThreads / 64)];
     const MrGeom* __restrict__ m = P.geom;
+    __shared__ double2 colrot[kMrColRot];
     const MrTile T = mr_tile(m, 0, 0);
     const int* perm = reinterpret_cast<const int*>(P.tab + m->tab_len);
     const int t = threadIdx.x, ne = T.ncol * T.A;
     const double invN = 1.0 / (double)P.N;
+    mr_colrot(colrot, P, T);  // published by the first transform's barrier
     double2 p[kMrRegs];
     const double a0 = 1.0 / sqrt((double)P.N);
 #pragma unroll
@@ -580,9 +650,9 @@ __global__ __launch_bounds__(kMrThreads, 1) void mrsmall_kernel(MrPassParams P)
         p[k] = make_double2(t + k * kMrThreads < ne ? a0 : 0.0, 0.0);
     for (int L = 0; L < P.p; ++L) {
         mr_phase(p, P.q, T, P.gammas[L], 1.0);
-        mr_dft<BIG>(p, lds, T, m, 0, P.tab, perm, false);
-        mr_diag(p, P, T, P.ts[L]);
-        mr_dft<BIG>(p, lds, T, m, 0, P.tab, perm, true);
+        mr_dft<MAXR>(p, lds, T, m, 0, P.tab, perm, false);
+        mr_diag(p, P, T, colrot, P.ts[L]);
+        mr_dft<MAXR>(p, lds, T, m, 0, P.tab, perm, true);
 #pragma unroll
         for (int k = 0; k < kMrRegs; ++k)
             p[k] = make_double2(p[k].x * invN, p[k].y * invN);
@@ -618,15 +688,15 @@ __global__ __launch_bounds__(kMrThreads, 1) void mrsmall_kernel(MrPassParams P)
         }
         for (int L = P.p - 1; L >= 0; --L) {
             // the mixer of layer L: Im <chi|W|phi> at the spectrum, then undone
-            mr_dft<BIG>(p, lds, T, m, 0, P.tab, perm, false);
-            mr_dft<BIG>(x, lds, T, m, 0, P.tab, perm, false);
+            mr_dft<MAXR>(p, lds, T, m, 0, P.tab, perm, false);
+            mr_dft<MAXR>(x, lds, T, m, 0, P.tab, perm, false);
             double acc = 0.0;
             const double tt = P.ts[L];
 #pragma unroll
             for (int k = 0; k < kMrRegs; ++k) {
                 const int e = t + k * kMrThreads;
                 if (e < ne) {
-                    const double lam = mr_lambda(P, mr_freq(m, 0, e));
+                    const double lam = mr_lambda_at(P, T, colrot, e);
                     acc = fma(lam, im_term(x[k], p[k]), acc);
                     const double2 d = expmi(-tt * lam);
                     p[k] = cmul(p[k], d);
@@ -636,8 +706,8 @@ __global__ __launch_bounds__(kMrThreads, 1) void mrsmall_kernel(MrPassParams P)
             const double2 st = block_sum2(acc * invN, 0.0, red);
             if (t == 0)
                 P.dts[L] = 2.0 * st.x;
-            mr_dft<BIG>(p, lds, T, m, 0, P.tab, perm, true);
-            mr_dft<BIG>(x, lds, T, m, 0, P.tab, perm, true);
+            mr_dft<MAXR>(p, lds, T, m, 0, P.tab, perm, true);
+            mr_dft<MAXR>(x, lds, T, m, 0, P.tab, perm, true);
             // the phase of layer L
             const double gam = P.gammas[L];
             acc = 0.0;
@@ -712,13 +782,13 @@ hipError_t launch_mr_tables(const MrGeom& m, MrGeom* geom_dev, double2* tab, hip
     return hipGetLastError();
 }
 
-template <bool BIG>
+template <int MAXR>
 hipError_t launch_mr_modes(const MrPassParams& P, int mode, dim3 grid, hipStream_t s)
 {
     switch (mode) {
 #define QVA_MR_MODE(K, M) \
     case M:               \
-        hipLaunchKernelGGL((K<M, BIG>), grid, dim3(kMrThreads), 0, s, P); \
+        hipLaunchKernelGGL((K<M, MAXR>), grid, dim3(kMrThreads), 0, s, P); \
         break;
         QVA_MR_MODE(mrpass_kernel, MR_FIRST)
         QVA_MR_MODE(mrpass_kernel, MR_DIF)
@@ -749,14 +819,16 @@ hipError_t launch_mrpass(const MrPassParams& P0, const MrGeom& m, int mode, hipS
     MrPassParams P = P0;
     const bool wide = mode == MRG_LOWDIAG || mode == MRG_BOUND || mode == MRG_FINAL;
     P.grid = (mode == MR_SMALL || mode == MR_SMALL_STORE || mode == MRG_SMALL) ? 1 : (wide ? maxt : m.tiles[P.g]);
-    bool big = false;
+    int maxr = 0;
     for (int g = 0; g < m.G; ++g)
         for (int i = 0; i < m.nrad[g]; ++i)
-            big = big || m.rad[g][i] > 16;
+            maxr = m.rad[g][i] > maxr ? m.rad[g][i] : maxr;
     const dim3 grid((unsigned)P.grid);
-    if (big)
-        return launch_mr_modes<true>(P, mode, grid, s);
-    return launch_mr_modes<false>(P, mode, grid, s);
+    if (maxr > 23)
+        return launch_mr_modes<31>(P, mode, grid, s);
+    if (maxr > 16)
+        return launch_mr_modes<23>(P, mode, grid, s);
+    return launch_mr_modes<16>(P, mode, grid, s);
 }
 
 }  // namespace qva

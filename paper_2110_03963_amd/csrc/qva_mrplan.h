@@ -57,20 +57,40 @@ inline std::vector<int> mr_radices(std::vector<int> primes)
     return r;
 }
 
-inline int mr_cols(int A, int64_t lower_or_upper)
+// Columns per tile: as many as fit 4096 elements, at most the number there
+// are.  A strided group whose stride S_g is a multiple of 8 amplitudes takes a
+// multiple of 8 columns, so that every row starts and ends on a 128-byte line.
+inline int mr_cols(int A, int64_t lower_or_upper, bool strided)
 {
     int64_t c = kMrTileElems / A;
     if (c > lower_or_upper)
         c = lower_or_upper;
+    if (strided && lower_or_upper % 8 == 0 && c >= 8)
+        c -= c % 8;
     return (int)(c < 1 ? 1 : c);
 }
 
+// Relative HBM cost of streaming a strided group's rows of c amplitudes
+// (16 c bytes; q rows of 8 c bytes): rows that do not start on a 128-byte
+// line fetch about 112 bytes more on average, and short rows stream below
+// the rate of long ones (measured: 128-byte rows near 0.73 and 256-byte rows
+// near 0.9 of the rate of rows of 512 bytes and more), modelled as
+// 1 + 48 / row bytes.
+inline double mr_row_cost(int c, bool aligned)
+{
+    const double bytes = 16.0 * c;
+    const double waste = aligned ? 1.0 : (bytes + 112.0) / bytes;
+    return waste * (1.0 + 48.0 / bytes);
+}
+
 // The factorisation: the fewest groups for which the prime factors fit the
-// caps (A_0 <= 4096, A_g <= 512), then the assignment whose tiles are fullest
-// (sum over groups of the used fraction of a 4096-element tile; ties to the
-// larger contiguous group).  Identical primes are assigned by count, so the
-// search is over compositions.  Returns false when some prime factor exceeds
-// kMrMaxPrime or no assignment into kMrMaxGroups groups fits.
+// caps (A_0 <= 4096, A_g <= 512), then the assignment with the lowest
+// modelled HBM cost per layer: each pass's bytes (low group 32 B per
+// amplitude, middle groups 2 x 32 B, the top group 40 B) times mr_row_cost of
+// its rows (the contiguous low group costs 1); ties to fuller tiles, then to
+// the larger contiguous group.  Identical primes are assigned by count, so
+// the search is over compositions.  Returns false when some prime factor
+// exceeds kMrMaxPrime or no assignment into kMrMaxGroups groups fits.
 inline bool mr_plan(int64_t N, MrGeom& out)
 {
     if (N < 2 || N >= (int64_t(1) << 31))
@@ -90,17 +110,25 @@ inline bool mr_plan(int64_t N, MrGeom& out)
             continue;
         std::vector<int64_t> prod(G, 1);
         std::vector<std::vector<int>> cnt(pe.size(), std::vector<int>(G, 0)), best_cnt;
-        double best = -1.0;
+        double best = -1e300;
         std::function<void(size_t, int, int)> rec = [&](size_t i, int g, int left) {
             if (i == pe.size()) {
-                double score = 0.0;
+                double cost = 0.0, fill = 0.0;
+                int64_t S = 1;
                 for (int h = 0; h < G; ++h) {
                     if (prod[h] == 1)
                         return;  // every group takes a factor
                     const int A = (int)prod[h];
-                    score += (double)(A * (int64_t)mr_cols(A, h == 0 ? N / A : N)) / kMrTileElems;
+                    const int c = mr_cols(A, h == 0 ? N / A : S, h > 0);
+                    fill += (double)(A * (int64_t)c) / kMrTileElems;
+                    if (h == 0)
+                        cost += 32.0;
+                    else
+                        cost += (h == G - 1 ? 40.0 : 64.0) * mr_row_cost(c, S % 8 == 0 && c % 8 == 0);
+                    S *= A;
                 }
-                score += 1e-9 * (double)prod[0];
+                // lower cost first; fuller tiles and a larger contiguous group break ties
+                const double score = -cost + 1e-6 * fill + 1e-12 * (double)prod[0];
                 if (score > best) {
                     best = score;
                     best_cnt = cnt;
@@ -137,7 +165,7 @@ inline bool mr_plan(int64_t N, MrGeom& out)
             }
         };
         rec(0, 0, pe[0].second);
-        if (best < 0.0)
+        if (best_cnt.empty())
             continue;
         MrGeom m{};
         m.G = G;
@@ -157,13 +185,16 @@ inline bool mr_plan(int64_t N, MrGeom& out)
             m.nrad[g] = (int)r.size();
             for (size_t i = 0; i < r.size(); ++i)
                 m.rad[g][i] = r[i];
-            m.cols[g] = g == 0 ? mr_cols(A, N / A) : mr_cols(A, S);
+            m.cols[g] = g == 0 ? mr_cols(A, N / A, false) : mr_cols(A, S, true);
             m.tab_off[g] = tab;
             tab += A;
             S *= A;
         }
         m.S[G] = S;
         m.tab_len = tab;
+        for (int g = 0; g < G; ++g)
+            m.rA[g] = 1.0 / (double)m.A[g];
+        m.U = N / m.A[0];
         for (int g = 0; g < G; ++g) {
             const int64_t cols_total = g == 0 ? N / m.A[0] : m.S[g];
             const int64_t chunks = (cols_total + m.cols[g] - 1) / m.cols[g];
