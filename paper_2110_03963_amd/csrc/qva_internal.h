@@ -190,8 +190,10 @@ struct MrGeom {
     int rad[kMrMaxGroups][kMrMaxStages];  // radices of each group's DFT stages, in stage order
     int cols[kMrMaxGroups];            // columns (independent DFTs) per tile
     int64_t tiles[kMrMaxGroups];       // tiles of each group's passes
-    int tab_off[kMrMaxGroups];         // group g's tables start at entry tab_off[g]
+    int tab_off[kMrMaxGroups];         // group g's roots and permutation start at entry tab_off[g]
     int tab_len;                       // sum of A_g
+    int tw_off[kMrMaxGroups];          // group g's (g >= 1) inter-group twiddle table, after the roots
+    int tw_len;                        // sum over g >= 1 of cols_g A_g
     double rA[kMrMaxGroups];           // 1 / A_g (the passes' integer divisions)
     int64_t U;                         // N / A_0, the low group's column count
 };
@@ -230,8 +232,10 @@ struct MrPassParams {
     const MrGeom* geom;    // device copy of the geometry (written with the tables)
     int g;                 // group of the pass
     int64_t grid;          // workgroups of the launch (set by launch_mrpass)
-    const double2* tab;    // per group: W_{A_g}^k, k < A_g (tab_off[g]), then the
-                           // digit-reversal permutation as int32 after tab_len entries
+    const double2* tab;    // per group: W_{A_g}^k, k < A_g (tab_off[g]); then per group
+                           // g >= 1 W_{S_{g+1}}^(c m), c < cols_g, m < A_g at tab_len +
+                           // tw_off[g] + m cols_g + c; then the digit-reversal
+                           // permutation as int32 after tab_len + tw_len entries
     double2* partials;     // per-tile (f, norm)
     double* slot;          // per-tile gradient partial (MRG_LOWDIAG, MRG_BOUND, MRG_FINAL)
     double* out_f;         // MR_SMALL / MRG_SMALL

@@ -305,41 +305,56 @@ __device__ __forceinline__ void mr_dft(double2 (&v)[kMrRegs], double2* lds, cons
 }
 
 // The twiddle between groups: element (col, m_g) of a strided group's tile
-// times W_{S_{g+1}}^(jl m_g) (conjugated: inverse), jl = first + col.
-__device__ __forceinline__ void mr_twiddle(double2 (&v)[kMrRegs], const MrTile& T, const MrGeom* __restrict__ m, int g, bool inv)
+// times W_{S_{g+1}}^(jl m_g) (conjugated: inverse), jl = first + col, as the
+// product of the tile's root troot[m_g] = W_{S_{g+1}}^(first m_g) (mr_troot)
+// and the group's table entry W_{S_{g+1}}^(col m_g) (col m_g < 4096), each
+// rounded once.
+__device__ __forceinline__ void mr_twiddle(double2 (&v)[kMrRegs], const MrTile& T, const MrGeom* __restrict__ m, int g,
+                                           const double2* __restrict__ tab, const double2* troot, bool inv)
 {
     if (T.low)
         return;  // S_0 = 1: no lower index
-    const int t = threadIdx.x, ne = T.ncol * T.A;
-    const double Sn = (double)m->S[g + 1];
+    const int t = threadIdx.x, ne = T.ncol * T.A, cols = m->cols[g];
+    const double2* __restrict__ tw = tab + m->tab_len + m->tw_off[g];
 #pragma unroll
     for (int k = 0; k < kMrRegs; ++k) {
         const int e = t + k * kMrThreads;
         if (e < ne) {
-            const int64_t ex = (T.first + T.col_of(e)) * (int64_t)T.j_of(e);  // < S_{g+1} < 2^31
-            if (ex) {
-                double s, c;
-                sincospi_red((double)(2 * ex) / Sn, &s, &c);
-                v[k] = cmul(v[k], make_double2(c, inv ? s : -s));
-            }
+            const int j = divq(e, T.rncol), col = e - j * T.ncol;
+            const double2 w = cmul(tw[j * cols + col], troot[j]);
+            v[k] = cmul(v[k], conj_if(w, inv));
         }
-        QVA_SCHED_FENCE();
     }
+}
+
+// troot[m] = W_{S_{g+1}}^(first m) for m < A_g (first m < S_{g+1} < 2^31,
+// so 2 first m / S_{g+1} is rounded once).  Followed by a barrier.
+__device__ __forceinline__ void mr_troot(double2* troot, const MrGeom* __restrict__ m, const MrTile& T, int g)
+{
+    if (!T.low) {
+        const double Sn = (double)m->S[g + 1];
+        for (int j = threadIdx.x; j < T.A; j += kMrThreads) {
+            double s, c;
+            sincospi_red((double)(2 * T.first * j) / Sn, &s, &c);
+            troot[j] = make_double2(c, -s);
+        }
+    }
+    __syncthreads();
 }
 
 template <int MAXR>
 __device__ __forceinline__ void mr_forward(double2 (&v)[kMrRegs], double2* lds, const MrTile& T, const MrGeom* m,
-                                           int g, const double2* tab, const int* perm)
+                                           int g, const double2* tab, const int* perm, const double2* troot)
 {
     mr_dft<MAXR>(v, lds, T, m, g, tab, perm, false);
-    mr_twiddle(v, T, m, g, false);
+    mr_twiddle(v, T, m, g, tab, troot, false);
 }
 
 template <int MAXR>
 __device__ __forceinline__ void mr_inverse(double2 (&v)[kMrRegs], double2* lds, const MrTile& T, const MrGeom* m,
-                                           int g, const double2* tab, const int* perm)
+                                           int g, const double2* tab, const int* perm, const double2* troot)
 {
-    mr_twiddle(v, T, m, g, true);
+    mr_twiddle(v, T, m, g, tab, troot, true);
     mr_dft<MAXR>(v, lds, T, m, g, tab, perm, true);
 }
 
@@ -473,9 +488,11 @@ __global__ __launch_bounds__(kMrThreads, MAXR <= 23 ? 2 : 1) void mrpass_kernel(
     __shared__ double red[2 * (kMrThreads / 64)];
     const MrGeom* __restrict__ m = P.geom;
     const int g = P.g;
+    __shared__ double2 troot[kMrMaxStrided];
     const MrTile T = mr_tile(m, g, blockIdx.x);
-    const int* perm = reinterpret_cast<const int*>(P.tab + m->tab_len);
+    const int* perm = reinterpret_cast<const int*>(P.tab + m->tab_len + m->tw_len);
     const double invN = 1.0 / (double)P.N;
+    mr_troot(troot, m, T, g);
     double2 v[kMrRegs];
     if constexpr (MODE == MR_FIRST) {
         const double a0 = 1.0 / sqrt((double)P.N);
@@ -483,34 +500,34 @@ __global__ __launch_bounds__(kMrThreads, MAXR <= 23 ? 2 : 1) void mrpass_kernel(
         for (int k = 0; k < kMrRegs; ++k)
             v[k] = make_double2(a0, 0.0);
         mr_phase(v, P.q, T, angle_value(P.gamma), 1.0);
-        mr_forward<MAXR>(v, lds, T, m, g, P.tab, perm);
+        mr_forward<MAXR>(v, lds, T, m, g, P.tab, perm, troot);
         mr_store(v, P.psi, T, 1.0);
     } else if constexpr (MODE == MR_DIF) {
         mr_load(v, P.psi, T);
-        mr_forward<MAXR>(v, lds, T, m, g, P.tab, perm);
+        mr_forward<MAXR>(v, lds, T, m, g, P.tab, perm, troot);
         mr_store(v, P.psi, T, 1.0);
     } else if constexpr (MODE == MR_DIT) {
         mr_load(v, P.psi, T);
-        mr_inverse<MAXR>(v, lds, T, m, g, P.tab, perm);
+        mr_inverse<MAXR>(v, lds, T, m, g, P.tab, perm, troot);
         mr_store(v, P.psi, T, 1.0);
     } else if constexpr (MODE == MR_LOWDIAG) {
         __shared__ double2 colrot[kMrColRot];
         mr_colrot(colrot, P, T);
         mr_load(v, P.psi, T);
-        mr_forward<MAXR>(v, lds, T, m, g, P.tab, perm);  // its first barrier publishes colrot
+        mr_forward<MAXR>(v, lds, T, m, g, P.tab, perm, troot);  // its first barrier publishes colrot
         mr_diag(v, P, T, colrot, angle_value(P.t));
-        mr_inverse<MAXR>(v, lds, T, m, g, P.tab, perm);
+        mr_inverse<MAXR>(v, lds, T, m, g, P.tab, perm, troot);
         mr_store(v, P.psi, T, 1.0);
     } else if constexpr (MODE == MR_BOUNDARY) {
         const double gam = angle_value(P.gamma);
         mr_load(v, P.psi, T);
-        mr_inverse<MAXR>(v, lds, T, m, g, P.tab, perm);
+        mr_inverse<MAXR>(v, lds, T, m, g, P.tab, perm, troot);
         mr_phase(v, P.q, T, gam, invN);
-        mr_forward<MAXR>(v, lds, T, m, g, P.tab, perm);
+        mr_forward<MAXR>(v, lds, T, m, g, P.tab, perm, troot);
         mr_store(v, P.psi, T, 1.0);
     } else {  // MR_LAST, MR_LAST_STORE
         mr_load(v, P.psi, T);
-        mr_inverse<MAXR>(v, lds, T, m, g, P.tab, perm);
+        mr_inverse<MAXR>(v, lds, T, m, g, P.tab, perm, troot);
 #pragma unroll
         for (int k = 0; k < kMrRegs; ++k)
             v[k] = make_double2(v[k].x * invN, v[k].y * invN);
@@ -540,14 +557,16 @@ __global__ __launch_bounds__(kMrThreads, 1) void mrgrad_kernel(MrPassParams P)
             P.slot[blockIdx.x] = 0.0;
         return;
     }
+    __shared__ double2 troot[kMrMaxStrided];
     const MrTile T = mr_tile(m, g, blockIdx.x);
-    const int* perm = reinterpret_cast<const int*>(P.tab + m->tab_len);
+    const int* perm = reinterpret_cast<const int*>(P.tab + m->tab_len + m->tw_len);
     const double invN = 1.0 / (double)P.N;
     const int ne = T.ncol * T.A;
+    mr_troot(troot, m, T, g);
     double2 p[kMrRegs], x[kMrRegs];
     if constexpr (MODE == MRG_TURN) {
         mr_load(p, P.psi, T);
-        mr_inverse<MAXR>(p, lds, T, m, g, P.tab, perm);
+        mr_inverse<MAXR>(p, lds, T, m, g, P.tab, perm, troot);
         double f = 0.0, nr = 0.0;
 #pragma unroll
         for (int k = 0; k < kMrRegs; ++k) {
@@ -562,8 +581,8 @@ __global__ __launch_bounds__(kMrThreads, 1) void mrgrad_kernel(MrPassParams P)
         const double2 tot = block_sum2(f, nr, red);
         if (t == 0)
             P.partials[blockIdx.x] = tot;
-        mr_forward<MAXR>(p, lds, T, m, g, P.tab, perm);
-        mr_forward<MAXR>(x, lds, T, m, g, P.tab, perm);
+        mr_forward<MAXR>(p, lds, T, m, g, P.tab, perm, troot);
+        mr_forward<MAXR>(x, lds, T, m, g, P.tab, perm, troot);
         mr_store(p, P.psi, T, 1.0);
         mr_store(x, P.chi, T, 1.0);
     } else if constexpr (MODE == MRG_LOWDIAG) {
@@ -572,8 +591,8 @@ __global__ __launch_bounds__(kMrThreads, 1) void mrgrad_kernel(MrPassParams P)
         const double tt = angle_value(P.t);
         mr_load(p, P.psi, T);
         mr_load(x, P.chi, T);
-        mr_forward<MAXR>(p, lds, T, m, g, P.tab, perm);
-        mr_forward<MAXR>(x, lds, T, m, g, P.tab, perm);
+        mr_forward<MAXR>(p, lds, T, m, g, P.tab, perm, troot);
+        mr_forward<MAXR>(x, lds, T, m, g, P.tab, perm, troot);
         double acc = 0.0;
 #pragma unroll
         for (int k = 0; k < kMrRegs; ++k) {
@@ -590,15 +609,15 @@ __global__ __launch_bounds__(kMrThreads, 1) void mrgrad_kernel(MrPassParams P)
         const double2 tot = block_sum2(acc * invN, 0.0, red);
         if (t == 0)
             P.slot[blockIdx.x] = tot.x;
-        mr_inverse<MAXR>(p, lds, T, m, g, P.tab, perm);
-        mr_inverse<MAXR>(x, lds, T, m, g, P.tab, perm);
+        mr_inverse<MAXR>(p, lds, T, m, g, P.tab, perm, troot);
+        mr_inverse<MAXR>(x, lds, T, m, g, P.tab, perm, troot);
         mr_store(p, P.psi, T, 1.0);
         mr_store(x, P.chi, T, 1.0);
     } else {  // MRG_BOUND, MRG_FINAL
         mr_load(p, P.psi, T);
         mr_load(x, P.chi, T);
-        mr_inverse<MAXR>(p, lds, T, m, g, P.tab, perm);
-        mr_inverse<MAXR>(x, lds, T, m, g, P.tab, perm);
+        mr_inverse<MAXR>(p, lds, T, m, g, P.tab, perm, troot);
+        mr_inverse<MAXR>(x, lds, T, m, g, P.tab, perm, troot);
         const double gam = angle_value(P.gamma);
         double acc = 0.0;
 #pragma unroll
@@ -621,8 +640,8 @@ __global__ __launch_bounds__(kMrThreads, 1) void mrgrad_kernel(MrPassParams P)
         if (t == 0)
             P.slot[blockIdx.x] = tot.x;
         if constexpr (MODE == MRG_BOUND) {
-            mr_forward<MAXR>(p, lds, T, m, g, P.tab, perm);
-            mr_forward<MAXR>(x, lds, T, m, g, P.tab, perm);
+            mr_forward<MAXR>(p, lds, T, m, g, P.tab, perm, troot);
+            mr_forward<MAXR>(x, lds, T, m, g, P.tab, perm, troot);
             mr_store(p, P.psi, T, 1.0);
             mr_store(x, P.chi, T, 1.0);
         }
@@ -639,7 +658,7 @@ __global__ __launch_bounds__(kMrThreads, 1) void mrsmall_kernel(MrPassParams P)
     const MrGeom* __restrict__ m = P.geom;
     __shared__ double2 colrot[kMrColRot];
     const MrTile T = mr_tile(m, 0, 0);
-    const int* perm = reinterpret_cast<const int*>(P.tab + m->tab_len);
+    const int* perm = reinterpret_cast<const int*>(P.tab + m->tab_len + m->tw_len);
     const int t = threadIdx.x, ne = T.ncol * T.A;
     const double invN = 1.0 / (double)P.N;
     mr_colrot(colrot, P, T);  // published by the first transform's barrier
@@ -747,7 +766,7 @@ __global__ __launch_bounds__(256) void mr_table_kernel(const MrGeom* __restrict_
 {
     const int g = blockIdx.x;
     const int A = m->A[g];
-    int* perm = reinterpret_cast<int*>(tab + m->tab_len) + m->tab_off[g];
+    int* perm = reinterpret_cast<int*>(tab + m->tab_len + m->tw_len) + m->tab_off[g];
     for (int k = threadIdx.x; k < A; k += blockDim.x) {
         // exp(-2 pi i k / A), with 2k / A rounded once (exact for A a power of two)
         double s, c;
@@ -763,13 +782,25 @@ __global__ __launch_bounds__(256) void mr_table_kernel(const MrGeom* __restrict_
         }
         perm[k] = pos;
     }
+    if (g == 0)
+        return;
+    // W_{S_{g+1}}^(c j) at m j cols + c (c j < cols A_g <= 4096, rounded once)
+    const int cols = m->cols[g];
+    const double Sn = (double)m->S[g + 1];
+    double2* tw = tab + m->tab_len + m->tw_off[g];
+    for (int k = threadIdx.x; k < cols * A; k += blockDim.x) {
+        const int j = k / cols, c = k - j * cols;
+        double s, co;
+        sincospi_red((double)(2 * c * j) / Sn, &s, &co);
+        tw[k] = make_double2(co, -s);
+    }
 }
 
 }  // namespace
 
 size_t mr_table_bytes(const MrGeom& m)
 {
-    return (size_t)m.tab_len * (sizeof(double2) + sizeof(int));
+    return (size_t)(m.tab_len + m.tw_len) * sizeof(double2) + (size_t)m.tab_len * sizeof(int);
 }
 
 hipError_t launch_mr_tables(const MrGeom& m, MrGeom* geom_dev, double2* tab, hipStream_t s)

@@ -192,6 +192,12 @@ inline bool mr_plan(int64_t N, MrGeom& out)
         }
         m.S[G] = S;
         m.tab_len = tab;
+        int tw = 0;
+        for (int g = 1; g < G; ++g) {
+            m.tw_off[g] = tw;
+            tw += m.cols[g] * m.A[g];
+        }
+        m.tw_len = tw;
         for (int g = 0; g < G; ++g)
             m.rA[g] = 1.0 / (double)m.A[g];
         m.U = N / m.A[0];
