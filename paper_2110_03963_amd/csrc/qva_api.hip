@@ -863,6 +863,46 @@ int mixed_run(const qva_problem* P, const double* gammas, const double* ts, int 
     return QVA_OK;
 }
 
+// The mixer alone, exp(-i t W) = F^-1 diag(exp(-i t lambda)) F, on the
+// caller's state over the mixed-radix passes: the forward groups top-down,
+// the low group with the diagonal, the inverse groups bottom-up, the last
+// one scaled by 1/N (N <= 4096: one workgroup).  work: the geometry, then the
+// tables.
+int mixed_mix(double2* psi, const double* lambda, int lambda_kind, const MrGeom& m, double t, char* work,
+              hipStream_t s)
+{
+    MrGeom* geom = reinterpret_cast<MrGeom*>(work);
+    double2* tab = reinterpret_cast<double2*>(work + align256(sizeof(MrGeom)));
+    if (launch_mr_tables(m, geom, tab, s) != hipSuccess)
+        return QVA_ERR_HIP;
+    MrPassParams mp{};
+    mp.psi = psi;
+    mp.lam = lambda;
+    mp.lambda_kind = lambda_kind == QVA_LAMBDA_RING ? FFT_LAMBDA_RING : FFT_LAMBDA_NATURAL;
+    mp.t = host_angle(t);
+    mp.gamma = host_angle(0.0);
+    mp.N = m.S[m.G];
+    mp.geom = geom;
+    mp.tab = tab;
+    if (m.G == 1)
+        return hip_status(launch_mrpass(mp, m, MR_SMALL_MIX, s));
+    for (int g = m.G - 1; g >= 1; --g) {
+        mp.g = g;
+        if (launch_mrpass(mp, m, MR_DIF, s) != hipSuccess)
+            return QVA_ERR_HIP;
+    }
+    mp.g = 0;
+    if (launch_mrpass(mp, m, MR_LOWDIAG, s) != hipSuccess)
+        return QVA_ERR_HIP;
+    for (int g = 1; g < m.G; ++g) {
+        mp.g = g;
+        mp.scale_inv_n = g == m.G - 1;
+        if (launch_mrpass(mp, m, MR_DIT, s) != hipSuccess)
+            return QVA_ERR_HIP;
+    }
+    return QVA_OK;
+}
+
 int evolve_circ(const qva_problem* P, const double* gammas, const double* ts, int p, double2* psi,
                 double* out_f, double* out_norm, bool store, char* work, hipStream_t s,
                 EventHook& hook)
@@ -1816,6 +1856,12 @@ int qva_mix_x(qva_c128* psi, int n_qubits, double t, void* stream)
 
 size_t qva_mix_circulant_workspace_bytes(int64_t N)
 {
+    if (N >= 2 && (N & (N - 1)) != 0) {
+        MrGeom m{};
+        if (!mixed_geom(N, &m))
+            return 0;
+        return align256(sizeof(MrGeom)) + align256(mr_table_bytes(m));
+    }
     return N > (int64_t(1) << kTileBits) ? kTwiddleTableBytes : 0;
 }
 
@@ -1829,11 +1875,28 @@ int qva_mix_circulant(qva_c128* psi, const double* lambda, int lambda_kind, int6
         return QVA_ERR_ARG;
     if (lambda_kind == QVA_LAMBDA_ARRAY && !lambda)
         return QVA_ERR_ARG;
+    if (N < 2)
+        return QVA_ERR_SIZE;
+    if ((N & (N - 1)) != 0) {
+        // N solutions with prime factors <= 31 (ring or eigenvalue array):
+        // the mixed-radix passes
+        MrGeom m{};
+        if (lambda_kind == QVA_LAMBDA_COMPLETE || !mixed_geom(N, &m))
+            return QVA_ERR_UNSUPPORTED;
+        if (!aligned(psi, 16) || (lambda_kind == QVA_LAMBDA_ARRAY && !aligned(lambda, 8)))
+            return QVA_ERR_ALIGN;
+        if (!work || work_bytes < qva_mix_circulant_workspace_bytes(N))
+            return QVA_ERR_WORKSPACE;
+        if (!aligned(work, 16))
+            return QVA_ERR_ALIGN;
+        return mixed_mix(reinterpret_cast<double2*>(psi), lambda, lambda_kind, m, t, static_cast<char*>(work),
+                         as_stream(stream));
+    }
     int n = 0;
     while (n <= QVA_MAX_QUBITS && (int64_t(1) << n) < N)
         ++n;
-    if (N < 2 || n > QVA_MAX_QUBITS || (int64_t(1) << n) != N)
-        return N >= 2 && (int64_t(1) << n) != N ? QVA_ERR_UNSUPPORTED : QVA_ERR_SIZE;
+    if (n > QVA_MAX_QUBITS)
+        return QVA_ERR_SIZE;
     if (!aligned(psi, 16) || (lambda_kind == QVA_LAMBDA_ARRAY && !aligned(lambda, 8)))
         return QVA_ERR_ALIGN;
     const size_t need = qva_mix_circulant_workspace_bytes(N);

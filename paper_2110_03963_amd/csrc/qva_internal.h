@@ -209,6 +209,7 @@ enum : int {
     MR_LAST_STORE = 7,   // ... and psi_p stored
     MR_SMALL = 8,        // N <= 4096: the whole evolution in one workgroup
     MR_SMALL_STORE = 9,
+    MR_SMALL_MIX = 10,   // N <= 4096: the mixer alone on the caller's state, in place
     // adjoint (two vectors; DIF / DIT without inner products reuse the
     // single-vector passes once per vector)
     MRG_TURN = 16,       // inverse top of psi_p, 1/N, <Q>, chi = Q psi_p, forward top of both
@@ -242,6 +243,7 @@ struct MrPassParams {
     double* out_norm;
     double* dgammas;       // MRG_SMALL
     double* dts;
+    int scale_inv_n;       // MR_DIT: multiply the result by 1/N (last pass of a lone mixer)
 };
 
 // m is the host copy of *P.geom (grid sizes).

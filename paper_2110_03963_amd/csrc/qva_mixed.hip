@@ -509,7 +509,7 @@ __global__ __launch_bounds__(kMrThreads, MAXR <= 23 ? 2 : 1) void mrpass_kernel(
     } else if constexpr (MODE == MR_DIT) {
         mr_load(v, P.psi, T);
         mr_inverse<MAXR>(v, lds, T, m, g, P.tab, perm, troot);
-        mr_store(v, P.psi, T, 1.0);
+        mr_store(v, P.psi, T, P.scale_inv_n ? invN : 1.0);
     } else if constexpr (MODE == MR_LOWDIAG) {
         __shared__ double2 colrot[kMrColRot];
         mr_colrot(colrot, P, T);
@@ -663,6 +663,15 @@ __global__ __launch_bounds__(kMrThreads, 1) void mrsmall_kernel(MrPassParams P)
     const double invN = 1.0 / (double)P.N;
     mr_colrot(colrot, P, T);  // published by the first transform's barrier
     double2 p[kMrRegs];
+    if constexpr (MODE == MR_SMALL_MIX) {
+        // the mixer alone: F^-1 diag(exp(-i t lambda)) F on the caller's state
+        mr_load(p, P.psi, T);
+        mr_dft<MAXR>(p, lds, T, m, 0, P.tab, perm, false);
+        mr_diag(p, P, T, colrot, angle_value(P.t));
+        mr_dft<MAXR>(p, lds, T, m, 0, P.tab, perm, true);
+        mr_store(p, P.psi, T, invN);
+        return;
+    }
     const double a0 = 1.0 / sqrt((double)P.N);
 #pragma unroll
     for (int k = 0; k < kMrRegs; ++k)
@@ -830,6 +839,7 @@ hipError_t launch_mr_modes(const MrPassParams& P, int mode, dim3 grid, hipStream
         QVA_MR_MODE(mrpass_kernel, MR_LAST_STORE)
         QVA_MR_MODE(mrsmall_kernel, MR_SMALL)
         QVA_MR_MODE(mrsmall_kernel, MR_SMALL_STORE)
+        QVA_MR_MODE(mrsmall_kernel, MR_SMALL_MIX)
         QVA_MR_MODE(mrsmall_kernel, MRG_SMALL)
         QVA_MR_MODE(mrgrad_kernel, MRG_TURN)
         QVA_MR_MODE(mrgrad_kernel, MRG_LOWDIAG)
@@ -849,7 +859,8 @@ hipError_t launch_mrpass(const MrPassParams& P0, const MrGeom& m, int mode, hipS
         maxt = m.tiles[g] > maxt ? m.tiles[g] : maxt;
     MrPassParams P = P0;
     const bool wide = mode == MRG_LOWDIAG || mode == MRG_BOUND || mode == MRG_FINAL;
-    P.grid = (mode == MR_SMALL || mode == MR_SMALL_STORE || mode == MRG_SMALL) ? 1 : (wide ? maxt : m.tiles[P.g]);
+    const bool small = mode == MR_SMALL || mode == MR_SMALL_STORE || mode == MR_SMALL_MIX || mode == MRG_SMALL;
+    P.grid = small ? 1 : (wide ? maxt : m.tiles[P.g]);
     int maxr = 0;
     for (int g = 0; g < m.G; ++g)
         for (int i = 0; i < m.nrad[g]; ++i)

@@ -19,7 +19,7 @@ import pytest
 torch = pytest.importorskip("torch")
 
 import oracle  # noqa: E402
-from gpu_util import f_rel_err, state_err, to_dev  # noqa: E402
+from gpu_util import f_rel_err, rand_state, state_err, to_dev  # noqa: E402
 from workloads import CONFIG_SEEDS, qwoa_constrained_workload, random_symmetric_lambda  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -99,6 +99,25 @@ def test_grad_mixed_radix(N, kind):
     assert np.max(np.abs(got - ref)) <= G_TOL * np.max(np.abs(ref))
     fe, _, _ = qva.evolve(prob, g, t, store=False)
     assert abs(fe.item() - f.item()) <= 1e-13 * np.mean(np.abs(q))
+
+
+@pytest.mark.parametrize("N", [30, 1000, 3003, 6000, 243000, 184756, 460288, 2704156])
+@pytest.mark.parametrize("kind", ["ring", "array"])
+def test_mix_circulant_mixed_radix(N, kind):
+    """qva_mix_circulant alone on a random state over N solutions (one, two
+    and three groups; radices up to 31) against the oracle's mixer."""
+    rng = np.random.default_rng(7 * N + len(kind))
+    psi0 = rand_state(rng, N)
+    lam = oracle.ring_lambda(N) if kind == "ring" else random_symmetric_lambda(N, rng)
+    t = float(rng.uniform(0.2, 3.0))
+    print(f"mix_circulant N={N} {kind}", flush=True)
+    psi = to_dev(psi0)
+    qva.mix_circulant(psi, t, to_dev(lam) if kind == "array" else None, kind)
+    ref = oracle.mix_circulant(psi0, lam, t)
+    assert state_err(psi.cpu().numpy(), ref) < PSI_TOL
+    # twice in a row with -t restores the state
+    qva.mix_circulant(psi, -t, to_dev(lam) if kind == "array" else None, kind)
+    assert state_err(psi.cpu().numpy(), psi0) < PSI_TOL
 
 
 def test_mixed_radix_mixer_and_depth_zero():

@@ -715,3 +715,29 @@ def test_group_split_setting(lib):
     assert lib.qva_set_group_split(12, IntArr(1), 1) == S.QVA_ERR_SIZE
     assert lib.qva_set_group_split(34, IntArr(9, 9, 4), 3) == S.QVA_ERR_SIZE
     assert lib.qva_set_group_split(28, None, 2) == S.QVA_ERR_ARG
+
+
+def test_mix_circulant_validation(lib):
+    """The lone circulant mixer: any power of two, or for the ring and an
+    eigenvalue array any N < 2^31 with prime factors <= 31 (mixed radix, with
+    a workspace for its tables); other N are unsupported, before any launch."""
+    S = _lib
+    ring, array, complete = 1, 0, 2
+    assert lib.qva_mix_circulant(None, None, ring, 1024, 0.1, None, 0, None) == S.QVA_ERR_ARG
+    assert lib.qva_mix_circulant(FAKE, None, array, 1024, 0.1, None, 0, None) == S.QVA_ERR_ARG
+    assert lib.qva_mix_circulant(FAKE, None, ring, 1, 0.1, None, 0, None) == S.QVA_ERR_SIZE
+    assert lib.qva_mix_circulant(FAKE, None, ring, -6, 0.1, None, 0, None) == S.QVA_ERR_SIZE
+    for N in (1009, 2 * 37 * 512, (1 << 31) + 6):  # a prime factor above 31, or too large
+        assert lib.qva_mix_circulant_workspace_bytes(N) == 0
+        assert lib.qva_mix_circulant(FAKE, None, ring, N, 0.1, FAKE, 1 << 30, None) == S.QVA_ERR_UNSUPPORTED
+    assert lib.qva_mix_circulant(FAKE, None, complete, 6000, 0.1, FAKE, 1 << 30, None) == S.QVA_ERR_UNSUPPORTED
+    for N in (6, 6000, 10400600):
+        ws = lib.qva_mix_circulant_workspace_bytes(N)
+        assert ws > 0
+        assert lib.qva_mix_circulant(FAKE, None, ring, N, 0.1, None, 0, None) == S.QVA_ERR_WORKSPACE
+        assert lib.qva_mix_circulant(FAKE, None, ring, N, 0.1, FAKE, ws - 1, None) == S.QVA_ERR_WORKSPACE
+        assert lib.qva_mix_circulant(FAKE + 8, None, ring, N, 0.1, FAKE, ws, None) == S.QVA_ERR_ALIGN
+        assert lib.qva_mix_circulant(FAKE, FAKE + 4, array, N, 0.1, FAKE, ws, None) == S.QVA_ERR_ALIGN
+        assert lib.qva_mix_circulant(FAKE, None, ring, N, 0.1, FAKE + 8, ws, None) == S.QVA_ERR_ALIGN
+    assert lib.qva_mix_circulant_workspace_bytes(1 << 20) > 0
+    assert lib.qva_mix_circulant_workspace_bytes(1 << 12) == 0
