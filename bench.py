@@ -1143,7 +1143,7 @@ def extra_batch(lib, with_oracle: bool = True) -> dict:
     gs = [w.gammas for w in wls]
     ts = [w.ts for w in wls]
     tune = tune_batch(qs, gs, ts, reps=2)
-    b = qva.Batch(qs, gs, ts, align=tune["align"])
+    b = qva.Batch(qs, gs, ts, align=tune["align"], lanes=tune["lanes"])
     ms_eager = time_batch_grad(b, reps=3)
     stream = torch.cuda.Stream()
     stream.wait_stream(torch.cuda.current_stream())
@@ -1193,7 +1193,8 @@ def extra_batch(lib, with_oracle: bool = True) -> dict:
         total_bytes += sum(i.bytes for i in plan_of(lib, pr, w.p, True, 0))
     return {"workload": "batch512_qaoa_maxcut_n12-22_p1-8", "instances": 512,
             "amplitudes": int(sum(1 << w.n for w in wls)),
-            "autotune": tune, "rounds": b.rounds, "launches_per_batch": b.launches, "tiles": b.tiles,
+            "autotune": tune, "lanes": b.lanes, "rounds": b.rounds, "launches_per_batch": b.launches,
+            "tiles": b.tiles,
             "ms_per_batch_graph_replay": round(ms_graph, 3),
             "ms_per_batch_eager": round(ms_eager, 3),
             "instance_gradients_per_s": round(512 / (ms_graph * 1e-3), 1),

@@ -444,6 +444,24 @@ typedef struct qva_batch_plan_s *qva_batch_plan;
  * instances.  Returns QVA_OK and *out, or an error (nothing allocated). */
 int qva_batch_create(const qva_batch_item *items, int count, int align, qva_batch_plan *out);
 
+#define QVA_BATCH_MAX_LANES 8
+
+/* qva_batch_create with the instances split into `lanes` (1 ..
+ * QVA_BATCH_MAX_LANES) independent sequences of rounds, balanced by tiles
+ * (the batched analogue of the paper's independent sub-communicators,
+ * Sec. 4).  qva_batch_grad enqueues lane 0 on the caller's stream and lane k
+ * on a stream of the plan's own, forked from and joined back into the
+ * caller's stream with events, so that the small launches at the end of one
+ * lane's rounds overlap another lane's launches; the call still enqueues no
+ * host work and can be captured into a HIP graph from the caller's stream.
+ * qva_batch_upload creates those lanes - 1 streams (default priority) and
+ * lanes events on the current device; qva_batch_destroy releases them.
+ * qva_batch_grad_timed runs every launch on the caller's stream, in plan
+ * order.  Results do not depend on the lane count.  QVA_ERR_ARG for lanes
+ * out of range. */
+int qva_batch_create_lanes(const qva_batch_item *items, int count, int align, int lanes,
+                           qva_batch_plan *out);
+
 /* Device workspace the plan needs (tables and per-tile partial sums). */
 size_t qva_batch_workspace_bytes(qva_batch_plan plan);
 
@@ -476,7 +494,8 @@ int qva_batch_rounds(qva_batch_plan plan);
 int qva_batch_launches(qva_batch_plan plan);
 int64_t qva_batch_tiles(qva_batch_plan plan);
 
-/* Release the host plan (does not touch device memory). */
+/* Release the host plan and its lane streams and events (does not touch
+ * device memory). */
 int qva_batch_destroy(qva_batch_plan plan);
 
 #ifdef __cplusplus

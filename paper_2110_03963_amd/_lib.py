@@ -99,6 +99,7 @@ QVA_BATCH_ALIGN_START = 0
 QVA_BATCH_ALIGN_END = 1
 QVA_BATCH_ALIGN_SPREAD = 2
 QVA_BATCH_MAX_DEPTH = 64
+QVA_BATCH_MAX_LANES = 8
 
 
 class QvaError(RuntimeError):
@@ -137,6 +138,7 @@ SIGNATURES = {
     "qva_grad_timed": (_I, [_PROB, _P, _P, _I, _P, _P, _P, _P, _P, _P, _SZ,
                             ctypes.POINTER(ctypes.c_void_p), _I, _P]),
     "qva_batch_create": (_I, [ctypes.POINTER(QvaBatchItem), _I, _I, ctypes.POINTER(ctypes.c_void_p)]),
+    "qva_batch_create_lanes": (_I, [ctypes.POINTER(QvaBatchItem), _I, _I, _I, ctypes.POINTER(ctypes.c_void_p)]),
     "qva_batch_workspace_bytes": (_SZ, [_P]),
     "qva_batch_upload": (_I, [_P, _P, _SZ, _P]),
     "qva_batch_grad": (_I, [_P, _P, _SZ, _P]),

@@ -7,7 +7,9 @@ Batched plans:
 The batched gradient groups the passes of all instances into rounds; how
 instances are aligned to rounds (all start together, all finish together, or
 start rounds spread to even out the tiles per round) changes how well each
-launch fills the GPU.  `tune_batch` times each candidate on the actual
+launch fills the GPU, and so does splitting the instances into lanes,
+independent sequences of rounds on streams of their own whose launches
+overlap.  `tune_batch` times each (alignment, lanes) candidate on the actual
 instances and caches the winner in a JSON file keyed by the batch's shape
 (the multiset of (n, p)), the device name and the library version.
 
@@ -75,29 +77,37 @@ def time_batch_grad(batch: Batch, reps: int = 3, warmup: int = 1) -> float:
     return e0.elapsed_time(e1) / reps
 
 
-def tune_batch(qs, gammas, ts, *, candidates=CANDIDATES, reps: int = 2, use_cache: bool = True,
-               path: str | None = None) -> dict:
-    """Pick the round alignment with the shortest batched gradient.
+LANE_CANDIDATES = (1, 2, 3, 4)
 
-    Returns {"align": best, "ms": {candidate: time}, "cached": bool}.
+
+def tune_batch(qs, gammas, ts, *, candidates=CANDIDATES, lanes=LANE_CANDIDATES, reps: int = 2,
+               use_cache: bool = True, path: str | None = None) -> dict:
+    """Pick the round alignment and the lane count (independent sequences of
+    rounds on their own streams, qva_batch_create_lanes) with the shortest
+    batched gradient.
+
+    Returns {"align": best, "lanes": best, "ms": {"align/lanes": time},
+    "cached": bool}.
     """
     path = path or cache_path()
     ns = [int(q.numel()).bit_length() - 1 for q in qs]
     ps = [len(g) for g in gammas]
     key = batch_signature(ns, ps)
     data = _load(path) if use_cache else {}
-    if use_cache and key in data and data[key].get("align") in candidates:
+    if use_cache and key in data and data[key].get("align") in candidates and data[key].get("lanes") in lanes:
         out = dict(data[key])
         out["cached"] = True
         return out
     times = {}
     for align in candidates:
-        b = Batch(qs, gammas, ts, align=align)
-        times[align] = time_batch_grad(b, reps=reps)
-        del b
-        torch.cuda.empty_cache()
+        for nl in lanes:
+            b = Batch(qs, gammas, ts, align=align, lanes=nl)
+            times[f"{align}/{nl}"] = time_batch_grad(b, reps=reps)
+            del b
+            torch.cuda.empty_cache()
     best = min(times, key=times.get)
-    entry = {"align": best, "ms": times}
+    align, nl = best.split("/")
+    entry = {"align": align, "lanes": int(nl), "ms": times}
     if use_cache:
         data = _load(path)
         data[key] = entry

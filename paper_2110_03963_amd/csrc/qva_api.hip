@@ -2226,7 +2226,7 @@ int grad_common(const qva_problem* P, const double* gammas_dev, const double* ts
 // ----------------------------------------------------------------- batched
 struct qva_batch_plan_s {
     struct Group {
-        int first, count, kind, mode, col_bits, round;
+        int first, count, kind, mode, col_bits, round, lane;
     };
     std::vector<BatchInst> inst;
     std::vector<BatchPass> pass;
@@ -2237,6 +2237,18 @@ struct qva_batch_plan_s {
     int rounds = 0;
     int64_t tiles_total = 0;
     void* uploaded = nullptr;
+    // lanes > 1: lane k >= 1 runs on lane_streams[k - 1] (made by qva_batch_upload),
+    // forked from and joined back into the caller's stream
+    int lanes = 1;
+    std::vector<hipStream_t> lane_streams;
+    std::vector<hipEvent_t> lane_events;  // [0]: fork, [k]: join of lane k
+    ~qva_batch_plan_s()
+    {
+        for (hipStream_t x : lane_streams)
+            (void)hipStreamDestroy(x);
+        for (hipEvent_t e : lane_events)
+            (void)hipEventDestroy(e);
+    }
 };
 
 namespace {
@@ -2314,9 +2326,16 @@ extern "C" {
 
 int qva_batch_create(const qva_batch_item* items, int count, int align, qva_batch_plan* out)
 {
+    return qva_batch_create_lanes(items, count, align, 1, out);
+}
+
+int qva_batch_create_lanes(const qva_batch_item* items, int count, int align, int lanes, qva_batch_plan* out)
+{
     if (!out || !items || count < 1)
         return QVA_ERR_ARG;
     if (align != QVA_BATCH_ALIGN_START && align != QVA_BATCH_ALIGN_END && align != QVA_BATCH_ALIGN_SPREAD)
+        return QVA_ERR_ARG;
+    if (lanes < 1 || lanes > QVA_BATCH_MAX_LANES)
         return QVA_ERR_ARG;
     for (int i = 0; i < count; ++i) {
         int st = batch_check_item(items[i]);
@@ -2335,28 +2354,47 @@ int qva_batch_create(const qva_batch_item* items, int count, int align, qva_batc
             l += pass_tiles(b, items[i].n_qubits);
         load_of[i] = l;
     }
-    // start round of every instance
+    // lanes: largest instances first, each to the lane with the fewest tiles
+    // so far (ties: the lowest lane)
+    std::vector<int> order(count), lane_of(count, 0);
+    for (int i = 0; i < count; ++i)
+        order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return load_of[a] > load_of[b]; });
+    {
+        std::vector<int64_t> lane_load(lanes, 0);
+        for (int i : order) {
+            int best = 0;
+            for (int l = 1; l < lanes; ++l)
+                if (lane_load[l] < lane_load[best])
+                    best = l;
+            lane_of[i] = best;
+            lane_load[best] += load_of[i];
+        }
+    }
+    // start round of every instance, per lane (each lane is its own sequence
+    // of rounds)
     std::vector<int> start(count, 0);
-    int R = maxpass;
+    std::vector<int> lane_rounds(lanes, 0);
+    for (int i = 0; i < count; ++i)
+        lane_rounds[lane_of[i]] = std::max(lane_rounds[lane_of[i]], (int)per[i].size());
     if (align == QVA_BATCH_ALIGN_END) {
         for (int i = 0; i < count; ++i)
-            start[i] = maxpass - (int)per[i].size();
+            start[i] = lane_rounds[lane_of[i]] - (int)per[i].size();
     } else if (align == QVA_BATCH_ALIGN_SPREAD) {
         // largest instances first; each takes the offset that keeps the
-        // busiest round least loaded (ties: earliest)
-        std::vector<int> order(count);
-        for (int i = 0; i < count; ++i)
-            order[i] = i;
-        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return load_of[a] > load_of[b]; });
-        std::vector<int64_t> round_load(R, 0);
+        // busiest round of its lane least loaded (ties: earliest)
+        std::vector<std::vector<int64_t>> round_load(lanes);
+        for (int l = 0; l < lanes; ++l)
+            round_load[l].assign(lane_rounds[l], 0);
         for (int i : order) {
+            std::vector<int64_t>& rl = round_load[lane_of[i]];
             const int np = (int)per[i].size();
             int best = 0;
             int64_t best_peak = -1;
-            for (int s0 = 0; s0 + np <= R; ++s0) {
+            for (int s0 = 0; s0 + np <= (int)rl.size(); ++s0) {
                 int64_t peak = 0;
                 for (int j = 0; j < np; ++j)
-                    peak = std::max(peak, round_load[s0 + j] + pass_tiles(per[i][j], items[i].n_qubits));
+                    peak = std::max(peak, rl[s0 + j] + pass_tiles(per[i][j], items[i].n_qubits));
                 if (best_peak < 0 || peak < best_peak) {
                     best_peak = peak;
                     best = s0;
@@ -2364,10 +2402,12 @@ int qva_batch_create(const qva_batch_item* items, int count, int align, qva_batc
             }
             start[i] = best;
             for (int j = 0; j < np; ++j)
-                round_load[best + j] += pass_tiles(per[i][j], items[i].n_qubits);
+                rl[best + j] += pass_tiles(per[i][j], items[i].n_qubits);
         }
     }
-    B->rounds = R;
+    B->rounds = *std::max_element(lane_rounds.begin(), lane_rounds.end());
+    B->lanes = lanes;
+    (void)maxpass;
     // instance and pass tables, per-instance scratch layout
     size_t scratch = 0;
     for (int i = 0; i < count; ++i) {
@@ -2395,15 +2435,16 @@ int qva_batch_create(const qva_batch_item* items, int count, int align, qva_batc
         scratch = align256(scratch + (size_t)d.nslots * (size_t)d.tiles * sizeof(double));
         B->inst.push_back(d);
     }
-    // work items, ordered by (round, kind, mode, tile geometry, instance, tile)
-    using Key = std::tuple<int, int, int, int, int, int>;
+    // work items, ordered by (round, lane, kind, mode, tile geometry, instance,
+    // tile): one launch per (round, lane, kind, mode, geometry)
+    using Key = std::tuple<int, int, int, int, int, int, int>;
     std::vector<std::pair<Key, BatchItem>> all;
     for (int i = 0; i < count; ++i) {
         for (int j = 0; j < (int)per[i].size(); ++j) {
             const BatchPass& b = per[i][j];
             const int64_t nt = pass_tiles(b, items[i].n_qubits);
             for (int64_t tl = 0; tl < nt; ++tl)
-                all.push_back({Key(start[i] + j, b.kind, b.mode, b.col_bits, i, (int)tl),
+                all.push_back({Key(start[i] + j, lane_of[i], b.kind, b.mode, b.col_bits, i, (int)tl),
                                BatchItem{i, j, (int)tl, 0}});
         }
     }
@@ -2414,11 +2455,13 @@ int qva_batch_create(const qva_batch_item* items, int count, int align, qva_batc
         const bool same = !B->groups.empty() && x > 0 && std::get<0>(all[x - 1].first) == std::get<0>(k) &&
                           std::get<1>(all[x - 1].first) == std::get<1>(k) &&
                           std::get<2>(all[x - 1].first) == std::get<2>(k) &&
-                          std::get<3>(all[x - 1].first) == std::get<3>(k);
+                          std::get<3>(all[x - 1].first) == std::get<3>(k) &&
+                          std::get<4>(all[x - 1].first) == std::get<4>(k);
         if (same)
             B->groups.back().count += 1;
         else
-            B->groups.push_back({(int)x, 1, std::get<1>(k), std::get<2>(k), std::get<3>(k), std::get<0>(k)});
+            B->groups.push_back({(int)x, 1, std::get<2>(k), std::get<3>(k), std::get<4>(k), std::get<0>(k),
+                                 std::get<1>(k)});
     }
     B->tiles_total = (int64_t)B->items.size();
     size_t off = 0;
@@ -2465,6 +2508,20 @@ int qva_batch_upload(qva_batch_plan plan, void* work, size_t work_bytes, void* s
         return QVA_ERR_HIP;
     if (hipStreamSynchronize(s) != hipSuccess)
         return QVA_ERR_HIP;
+    // the lanes' streams (default priority) and fork / join events, on the
+    // current device
+    while ((int)plan->lane_streams.size() < plan->lanes - 1) {
+        hipStream_t x;
+        if (hipStreamCreateWithFlags(&x, hipStreamNonBlocking) != hipSuccess)
+            return QVA_ERR_HIP;
+        plan->lane_streams.push_back(x);
+    }
+    while (plan->lanes > 1 && (int)plan->lane_events.size() < plan->lanes) {
+        hipEvent_t e;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+            return QVA_ERR_HIP;
+        plan->lane_events.push_back(e);
+    }
     plan->uploaded = work;
     return QVA_OK;
 }
@@ -2485,13 +2542,34 @@ int batch_grad_run(qva_batch_plan plan, void* work, size_t work_bytes, void* str
     R.pass = reinterpret_cast<const BatchPass*>(base + plan->off_pass);
     R.items = reinterpret_cast<const BatchItem*>(base + plan->off_items);
     hipStream_t s = as_stream(stream);
+    // lanes > 1 (untimed): fork the plan's lane streams from s, launch each
+    // group on its lane's stream, join them back into s.  Timed calls run
+    // every launch on s in plan order.
+    const bool fork = plan->lanes > 1 && !hook.ev;
+    if (fork) {
+        if ((int)plan->lane_streams.size() != plan->lanes - 1)
+            return QVA_ERR_ARG;
+        if (hipEventRecord(plan->lane_events[0], s) != hipSuccess)
+            return QVA_ERR_HIP;
+        for (hipStream_t ls : plan->lane_streams)
+            if (hipStreamWaitEvent(ls, plan->lane_events[0], 0) != hipSuccess)
+                return QVA_ERR_HIP;
+    }
     for (const auto& gr : plan->groups) {
         R.first = gr.first;
+        const hipStream_t ls = fork && gr.lane > 0 ? plan->lane_streams[gr.lane - 1] : s;
         hook.before(s);
-        const hipError_t e = launch_batch_group(R, gr.kind, gr.mode, gr.col_bits, gr.count, s);
+        const hipError_t e = launch_batch_group(R, gr.kind, gr.mode, gr.col_bits, gr.count, ls);
         hook.after(s);
         if (e != hipSuccess)
             return QVA_ERR_HIP;
+    }
+    if (fork) {
+        for (int l = 1; l < plan->lanes; ++l) {
+            if (hipEventRecord(plan->lane_events[l], plan->lane_streams[l - 1]) != hipSuccess ||
+                hipStreamWaitEvent(s, plan->lane_events[l], 0) != hipSuccess)
+                return QVA_ERR_HIP;
+        }
     }
     return QVA_OK;
 }

@@ -358,7 +358,7 @@ class Batch:
     can be captured into a torch.cuda.CUDAGraph and replayed.
     """
 
-    def __init__(self, qs, gammas, ts, align: str = "spread"):
+    def __init__(self, qs, gammas, ts, align: str = "spread", lanes: int = 1):
         if not (len(qs) == len(gammas) == len(ts)) or not qs:
             raise ValueError("one q, gammas and ts per instance")
         dev = qs[0].device
@@ -399,8 +399,9 @@ class Batch:
                 self.dgammas.data_ptr() + 8 * o, self.dts.data_ptr() + 8 * o)
         lib = _lib.load()
         plan = ctypes.c_void_p()
-        _lib.check("qva_batch_create", lib.qva_batch_create(items, self.count, _ALIGN[align],
-                                                            ctypes.byref(plan)))
+        _lib.check("qva_batch_create_lanes",
+                   lib.qva_batch_create_lanes(items, self.count, _ALIGN[align], int(lanes), ctypes.byref(plan)))
+        self.lanes = int(lanes)
         self._plan = plan
         nbytes = lib.qva_batch_workspace_bytes(plan)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)

@@ -131,6 +131,48 @@ def test_batch_graph_capture_replays():
         assert torch.equal(b_graph.ts, b_eager.ts), rep
 
 
+@pytest.mark.parametrize("lanes", [2, 3])
+def test_batch_lanes_match_one_lane(lanes):
+    """Lanes on their own streams (forked from and joined into the caller's
+    stream) give bit-identical f and gradients to the one-lane plan, eagerly
+    and from a captured graph replayed with eager work in between."""
+    qs, gs, ts, _ = _small_batch(5, SPECS)
+    ref = qva.Batch(qs, gs, ts, align="start")
+    ref.grad()
+    torch.cuda.synchronize()
+    for align in ("start", "spread"):
+        b = qva.Batch(qs, gs, ts, align=align, lanes=lanes)
+        b.grad()
+        torch.cuda.synchronize()
+        assert torch.equal(b.f, ref.f) and torch.equal(b.dgammas, ref.dgammas) and torch.equal(b.dts, ref.dts)
+    lr = 0.05
+    b_graph = qva.Batch(qs, gs, ts, align="start", lanes=lanes)
+    b_eager = qva.Batch(qs, gs, ts, align="start")
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        b_graph.grad()  # warm-up outside the capture
+    torch.cuda.current_stream().wait_stream(stream)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=stream):
+        b_graph.grad()
+        b_graph.sgd(lr)
+    torch.cuda.synchronize()
+    for rep in range(4):
+        graph.replay()
+        torch.cuda.synchronize()
+        scratch = torch.randn(1 << 20, device="cuda").sum()  # unrelated eager work
+        b_eager.grad()
+        b_eager.sgd(lr)
+        torch.cuda.synchronize()
+        assert torch.isfinite(scratch)
+        assert torch.equal(b_graph.f, b_eager.f), rep
+        assert torch.equal(b_graph.dgammas, b_eager.dgammas), rep
+        assert torch.equal(b_graph.dts, b_eager.dts), rep
+        assert torch.equal(b_graph.gammas, b_eager.gammas), rep
+
+
 def test_batch_sgd_step():
     qs, gs, ts, _ = _small_batch(4, SPECS[:5])
     b = qva.Batch(qs, gs, ts)

@@ -420,6 +420,43 @@ def test_batch_validation(lib):
     assert lib.qva_batch_create(arr, 1, 0, ctypes.byref(plan)) == _lib.QVA_ERR_ALIGN
     assert lib.qva_batch_create(_batch_items([(14, 2)]), 1, 7, ctypes.byref(plan)) == _lib.QVA_ERR_ARG
     assert lib.qva_batch_create(_batch_items([(14, 2)]), 0, 0, ctypes.byref(plan)) == _lib.QVA_ERR_ARG
+    for lanes in (0, _lib.QVA_BATCH_MAX_LANES + 1, -1):
+        assert lib.qva_batch_create_lanes(_batch_items([(14, 2)]), 1, 0, lanes,
+                                          ctypes.byref(plan)) == _lib.QVA_ERR_ARG
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 3, 8])
+@pytest.mark.parametrize("align", [0, 1, 2])
+def test_batch_plan_lanes(lib, lanes, align):
+    """Lanes split the instances into independent sequences of rounds: every
+    tile still appears once, no lane needs more rounds than the deepest
+    instance, each launch belongs to one round, and with one lane the plan is
+    qva_batch_create's."""
+    specs = [(12, 3), (13, 1), (14, 2), (17, 5), (21, 8), (22, 4), (12, 1), (16, 6), (18, 2)]
+    arr = _batch_items(specs)
+    one, plan = ctypes.c_void_p(), ctypes.c_void_p()
+    assert lib.qva_batch_create(arr, len(specs), align, ctypes.byref(one)) == 0
+    assert lib.qva_batch_create_lanes(arr, len(specs), align, lanes, ctypes.byref(plan)) == 0
+    try:
+        assert lib.qva_batch_tiles(plan) == lib.qva_batch_tiles(one)
+        assert lib.qva_batch_rounds(plan) <= lib.qva_batch_rounds(one)
+        assert lib.qva_batch_launches(plan) >= lib.qva_batch_launches(one)
+        rounds = ctypes.c_int()
+        wgs = ctypes.c_int64()
+        total = 0
+        last = -1
+        for i in range(lib.qva_batch_launches(plan)):
+            assert lib.qva_batch_launch_info(plan, i, ctypes.byref(rounds), ctypes.byref(wgs), None) == 0
+            assert rounds.value >= last  # launches in round order
+            last = rounds.value
+            total += wgs.value
+        assert total == lib.qva_batch_tiles(plan)
+        if lanes == 1:
+            assert lib.qva_batch_launches(plan) == lib.qva_batch_launches(one)
+            assert lib.qva_batch_workspace_bytes(plan) == lib.qva_batch_workspace_bytes(one)
+    finally:
+        lib.qva_batch_destroy(plan)
+        lib.qva_batch_destroy(one)
 
 
 # ------------------------------------------------------------ extended QAOA
