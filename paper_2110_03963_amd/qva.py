@@ -120,8 +120,9 @@ class Problem:
     mixer "circulant": W circulant with eigenvalues lam (natural order) or
     lambda_kind "ring" / "complete".  A circulant may have any N >= 2 (the
     solution count of a constrained problem): closed-form passes for the
-    complete graph, Bluestein's transform for the ring or an array (both
-    evolve and grad).  The hypercube mixer needs a power of two.
+    complete graph; for the ring or an array, in-place mixed-radix passes
+    when every prime factor of N is at most 31, else Bluestein's transform
+    (both evolve and grad).  The hypercube mixer needs a power of two.
 
     terms (hypercube mixer only): the extended QAOA, one phase angle per term
     of a Z-string decomposition of the cost, given as (supports, coefs) with
