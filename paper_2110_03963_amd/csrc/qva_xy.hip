@@ -37,8 +37,16 @@ __device__ __forceinline__ void xy_rot(double2& u, double2& w, double c, double 
     w = make_double2(fma(c, w0.x, s * u0.y), fma(c, w0.y, -s * u0.x));
 }
 
-__global__ __launch_bounds__(kThreads, 2) void xypass_kernel(XyPassParams P)
+// One tile in LDS (64 KiB): two workgroups per CU, of 1024 threads holding 4
+// amplitudes each (eight waves per SIMD: the factor loop is LDS-latency
+// bound; 2^26 amplitudes, p = 6: 9.06 ms per evolution with 256 threads,
+// 8.72 with 512, 8.58 with 1024).
+constexpr int kXyThreads = 1024;
+constexpr int kXyRegs = (1 << kTileBits) / kXyThreads;
+
+__global__ __launch_bounds__(kXyThreads, 2) void xypass_kernel(XyPassParams P)
 {
+    constexpr int kThreads = kXyThreads, kRegs = kXyRegs;
     __shared__ double2 s[1 << kTileBits];
     __shared__ double red[2 * (kThreads / 64)];
     const int t = threadIdx.x;
@@ -152,9 +160,17 @@ __global__ __launch_bounds__(kThreads, 2) void xypass_kernel(XyPassParams P)
     }
 }
 
-// Inverse of one forward pass on (phi, chi); both tiles sit in LDS.
-__global__ __launch_bounds__(kThreads, 1) void xygrad_kernel(XyPassParams P)
+// Inverse of one forward pass on (phi, chi); both tiles sit in LDS.  The
+// two tiles (128 KiB) leave room for one workgroup per CU, so the pass runs
+// 1024 threads (four waves per SIMD), each holding 4 amplitudes of each
+// vector (with 256 threads it ran at one wave per SIMD: 1.23 ms per launch
+// at 2^26 amplitudes, 1.11 ms with 512 or 1024).
+constexpr int kXyGradThreads = 1024;
+constexpr int kXyGradRegs = (1 << kTileBits) / kXyGradThreads;
+
+__global__ __launch_bounds__(kXyGradThreads, 1) void xygrad_kernel(XyPassParams P)
 {
+    constexpr int kThreads = kXyGradThreads, kRegs = kXyGradRegs;
     __shared__ double2 sp[1 << kTileBits];
     __shared__ double2 sx[1 << kTileBits];
     __shared__ double red[2 * (kThreads / 64)];
@@ -284,7 +300,7 @@ hipError_t launch_xypass(const XyPassParams& P, int64_t tiles, hipStream_t s)
 {
     if (P.n_ops < 0 || P.n_ops > kMaxXyOps || P.elems < 1 || P.elems > (1 << kTileBits))
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(xypass_kernel, dim3((unsigned)tiles), dim3(kThreads), 0, s, P);
+    hipLaunchKernelGGL(xypass_kernel, dim3((unsigned)tiles), dim3(kXyThreads), 0, s, P);
     return hipGetLastError();
 }
 
@@ -292,7 +308,7 @@ hipError_t launch_xygrad(const XyPassParams& P, int64_t tiles, hipStream_t s)
 {
     if (P.n_ops < 0 || P.n_ops > kMaxXyOps || P.elems < 1 || P.elems > (1 << kTileBits))
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(xygrad_kernel, dim3((unsigned)tiles), dim3(kThreads), 0, s, P);
+    hipLaunchKernelGGL(xygrad_kernel, dim3((unsigned)tiles), dim3(kXyGradThreads), 0, s, P);
     return hipGetLastError();
 }
 
