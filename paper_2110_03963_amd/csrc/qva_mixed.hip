@@ -18,10 +18,12 @@
 // LDS slot: low group col = e / A_0, j = e mod A_0; strided groups
 // j = e / ncol, col = e mod ncol, so consecutive threads touch consecutive
 // addresses in HBM.  The group DFT runs in LDS as in-place Cooley-Tukey DIF
-// stages over the group's radices (each stage a naive R-point DFT in
-// registers with exact roots, then the twiddle W_L^(i m)); the output, digit
-// reversed, is gathered back in natural order through a permutation table.
-// Roots W_{A_g}^k and the permutations are computed once per call into the
+// stages over the group's radices (each stage an R-point DFT in registers,
+// paired outputs for odd R, then the twiddle W_L^(i m) by recurrence from two
+// table roots); the output, digit reversed, is gathered back in natural order
+// through a permutation table.  The twiddle between groups is a per-tile root
+// (LDS) times a per-group table entry.  Roots W_{A_g}^k, the inter-group
+// twiddles and the permutations are computed once per call into the
 // workspace.
 #include "qva_internal.h"
 
