@@ -778,3 +778,21 @@ def test_mix_circulant_validation(lib):
         assert lib.qva_mix_circulant(FAKE, None, ring, N, 0.1, FAKE + 8, ws, None) == S.QVA_ERR_ALIGN
     assert lib.qva_mix_circulant_workspace_bytes(1 << 20) > 0
     assert lib.qva_mix_circulant_workspace_bytes(1 << 12) == 0
+
+
+@pytest.mark.parametrize("N", [10400600, 11907000, 831600, 40116600, 155117520])
+def test_mixed_radix_strided_rows_aligned(lib, N):
+    """For these N (each with a fewest-group factorisation whose contiguous
+    group holds 2^3) the planner takes such a factorisation and gives every
+    strided group a multiple of 8 columns, so each row of a strided tile
+    covers whole 128-byte lines (16 B per amplitude)."""
+    n = (N - 1).bit_length()
+    pr = _prob(mixer=1, n=n, kind=1, n_states=N)
+    cnt = lib.qva_plan(ctypes.byref(pr), 1, 0, 1, None, 0)
+    arr = (_lib.QvaPassInfo * cnt)()
+    lib.qva_plan(ctypes.byref(pr), 1, 0, 1, arr, cnt)
+    groups = {x.group_first: (x.group_bits, x.col_bits) for x in arr if x.group_first >= 0}
+    assert N % 8 == 0 and groups[0][0] % 8 == 0
+    for g in range(1, len(groups)):
+        A, cols = groups[g]
+        assert cols % 8 == 0 and cols * A <= 4096 and cols >= 8, (g, A, cols)
