@@ -33,6 +33,10 @@ namespace {
 constexpr int kMrThreads = 256;
 constexpr int kMrRegs = kMrTileElems / kMrThreads;
 
+// A tile's thread index: the workgroup's in the single-vector kernels, the
+// half's in the two-vector kernels (two halves of 256 threads).
+__device__ __forceinline__ int mr_tid() { return threadIdx.x & (kMrThreads - 1); }
+
 // q = floor(e / d) for 0 <= e < 2^31, 1 <= d <= 4096 via the reciprocal
 // rd = 1/d in double: (e + 1/2) / d lies at least 1/(2d) >= 2^-13 inside
 // (q, q + 1), far beyond the rounding error of rd and of the product
@@ -190,7 +194,7 @@ __device__ __forceinline__ void mr_stage_tw(double2* lds, int A, int ncol, bool 
     const double rpc = 1.0 / (double)per_col, rms = 1.0 / (double)mstride, rnc = 1.0 / (double)ncol;
     const int cs = low ? A : 1, js = low ? 1 : ncol;  // LDS strides of col and j
     constexpr int H = R / 2;
-    for (int it = threadIdx.x; it < items; it += kMrThreads) {
+    for (int it = mr_tid(); it < items; it += kMrThreads) {
         int col, bi;
         if (low) {  // i fastest: consecutive threads take consecutive j
             col = divq(it, rpc);
@@ -288,7 +292,7 @@ __device__ __forceinline__ void mr_dft(double2 (&v)[kMrRegs], double2* lds, cons
                                        const MrGeom* __restrict__ m, int g, const double2* tab, const int* perm,
                                        bool inv)
 {
-    const int t = threadIdx.x, ne = T.ncol * T.A;
+    const int t = mr_tid(), ne = T.ncol * T.A;
     const int* gp = perm + m->tab_off[g];
     __syncthreads();
 #pragma unroll
@@ -316,7 +320,7 @@ __device__ __forceinline__ void mr_twiddle(double2 (&v)[kMrRegs], const MrTile& 
 {
     if (T.low)
         return;  // S_0 = 1: no lower index
-    const int t = threadIdx.x, ne = T.ncol * T.A, cols = m->cols[g];
+    const int t = mr_tid(), ne = T.ncol * T.A, cols = m->cols[g];
     const double2* __restrict__ tw = tab + m->tab_len + m->tw_off[g];
 #pragma unroll
     for (int k = 0; k < kMrRegs; ++k) {
@@ -335,7 +339,7 @@ __device__ __forceinline__ void mr_troot(double2* troot, const MrGeom* __restric
 {
     if (!T.low) {
         const double Sn = (double)m->S[g + 1];
-        for (int j = threadIdx.x; j < T.A; j += kMrThreads) {
+        for (int j = threadIdx.x; j < T.A; j += blockDim.x) {
             double s, c;
             sincospi_red((double)(2 * T.first * j) / Sn, &s, &c);
             troot[j] = make_double2(c, -s);
@@ -362,7 +366,7 @@ __device__ __forceinline__ void mr_inverse(double2 (&v)[kMrRegs], double2* lds, 
 
 __device__ __forceinline__ void mr_load(double2 (&v)[kMrRegs], const double2* psi, const MrTile& T)
 {
-    const int t = threadIdx.x, ne = T.ncol * T.A;
+    const int t = mr_tid(), ne = T.ncol * T.A;
 #pragma unroll
     for (int k = 0; k < kMrRegs; ++k) {
         const int e = t + k * kMrThreads;
@@ -372,7 +376,7 @@ __device__ __forceinline__ void mr_load(double2 (&v)[kMrRegs], const double2* ps
 
 __device__ __forceinline__ void mr_store(const double2 (&v)[kMrRegs], double2* psi, const MrTile& T, double scale)
 {
-    const int t = threadIdx.x, ne = T.ncol * T.A;
+    const int t = mr_tid(), ne = T.ncol * T.A;
 #pragma unroll
     for (int k = 0; k < kMrRegs; ++k) {
         const int e = t + k * kMrThreads;
@@ -410,7 +414,7 @@ __device__ __forceinline__ void mr_colrot(double2* colrot, const MrPassParams& P
 {
     if (P.lambda_kind != FFT_LAMBDA_RING || T.ncol > kMrColRot)
         return;
-    for (int c = threadIdx.x; c < T.ncol; c += kMrThreads) {
+    for (int c = threadIdx.x; c < T.ncol; c += blockDim.x) {
         double s, co;
         sincospi_red((double)(2 * mr_rev(P.geom, T.first + c)) / (double)P.N, &s, &co);
         colrot[c] = make_double2(co, s);
@@ -439,7 +443,7 @@ __device__ __forceinline__ double mr_lambda_at(const MrPassParams& P, const MrTi
 __device__ __forceinline__ void mr_diag(double2 (&v)[kMrRegs], const MrPassParams& P, const MrTile& T,
                                         const double2* colrot, double tt)
 {
-    const int t = threadIdx.x, ne = T.ncol * T.A;
+    const int t = mr_tid(), ne = T.ncol * T.A;
 #pragma unroll
     for (int k = 0; k < kMrRegs; ++k) {
         const int e = t + k * kMrThreads;
@@ -452,7 +456,7 @@ __device__ __forceinline__ void mr_diag(double2 (&v)[kMrRegs], const MrPassParam
 // psi <- scale exp(-i gamma q) psi in natural order.
 __device__ __forceinline__ void mr_phase(double2 (&v)[kMrRegs], const double* q, const MrTile& T, double gamma, double scale)
 {
-    const int t = threadIdx.x, ne = T.ncol * T.A;
+    const int t = mr_tid(), ne = T.ncol * T.A;
 #pragma unroll
     for (int k = 0; k < kMrRegs; ++k) {
         const int e = t + k * kMrThreads;
@@ -467,7 +471,7 @@ __device__ __forceinline__ void mr_phase(double2 (&v)[kMrRegs], const double* q,
 __device__ __forceinline__ void mr_expect(const double2 (&v)[kMrRegs], const double* q, const MrTile& T, double* red,
                           double2* out)
 {
-    const int t = threadIdx.x, ne = T.ncol * T.A;
+    const int t = mr_tid(), ne = T.ncol * T.A;
     double f = 0.0, nr = 0.0;
 #pragma unroll
     for (int k = 0; k < kMrRegs; ++k) {
@@ -650,6 +654,179 @@ __global__ __launch_bounds__(kMrThreads, 1) void mrgrad_kernel(MrPassParams P)
     }
 }
 
+// The same two-vector passes with one half of a 512-thread workgroup per
+// vector: threads 0-255 hold phi (psi), 256-511 chi, and each half runs the
+// group transforms on its own LDS tile at the same time (the stages'
+// barriers are common to both).  The inner products and the factors both
+// vectors take (the inverse diagonal, the inverse phase) pass from the phi
+// half to the chi half through LDS.  Every sum and product is the one
+// mrgrad_kernel forms, in the same order, so the results are bit-identical;
+// the two tiles (128 KiB) and two waves per SIMD of 512 threads replace one
+// wave per SIMD of 256 threads.  Radices up to 23.
+template <int MODE, int MAXR>
+__global__ __launch_bounds__(2 * kMrThreads, 1) void mrgrad2_kernel(MrPassParams P)
+{
+    static_assert(MAXR <= 23, "radix-29/31 stages need the registers of mrgrad_kernel");
+    __shared__ double2 lds[2][kMrTileElems];
+    __shared__ double red[2 * (2 * kMrThreads / 64)];
+    __shared__ double2 troot[kMrMaxStrided];
+    const MrGeom* __restrict__ m = P.geom;
+    const int g = P.g;
+    if (blockIdx.x >= m->tiles[g]) {
+        if (P.slot && threadIdx.x == 0)
+            P.slot[blockIdx.x] = 0.0;
+        return;
+    }
+    const int half = threadIdx.x >= kMrThreads ? 1 : 0, t = mr_tid();
+    const MrTile T = mr_tile(m, g, blockIdx.x);
+    const int* perm = reinterpret_cast<const int*>(P.tab + m->tab_len + m->tw_len);
+    const double invN = 1.0 / (double)P.N;
+    const int ne = T.ncol * T.A;
+    double2* own = lds[half];
+    double2* vec = half ? P.chi : P.psi;
+    mr_troot(troot, m, T, g);
+    double2 v[kMrRegs];
+    if constexpr (MODE == MRG_TURN) {
+        // phi: inverse top group, 1/N, (<Q>, norm); chi = Q phi (phi handed to
+        // the chi half, which transforms zeros meanwhile); forward top group
+        if (half == 0) {
+            mr_load(v, P.psi, T);
+        } else {
+#pragma unroll
+            for (int k = 0; k < kMrRegs; ++k)
+                v[k] = make_double2(0.0, 0.0);
+        }
+        mr_inverse<MAXR>(v, own, T, m, g, P.tab, perm, troot);
+        __syncthreads();
+        if (half == 0) {
+#pragma unroll
+            for (int k = 0; k < kMrRegs; ++k) {
+                const int e = t + k * kMrThreads;
+                v[k] = make_double2(v[k].x * invN, v[k].y * invN);
+                if (e < ne)
+                    lds[1][e] = v[k];
+            }
+        }
+        __syncthreads();
+        double f = 0.0, nr = 0.0;
+#pragma unroll
+        for (int k = 0; k < kMrRegs; ++k) {
+            const int e = t + k * kMrThreads;
+            const double qq = e < ne ? ld_nt(P.q + T.gidx(e)) : 0.0;
+            if (half == 0) {
+                const double a = v[k].x * v[k].x + v[k].y * v[k].y;
+                f = fma(a, qq, f);
+                nr += a;
+            } else {
+                const double2 pv = e < ne ? lds[1][e] : make_double2(0.0, 0.0);
+                v[k] = make_double2(qq * pv.x, qq * pv.y);
+            }
+        }
+        const double2 tot = block_sum2(f, nr, red);
+        if (threadIdx.x == 0)
+            P.partials[blockIdx.x] = tot;
+        mr_forward<MAXR>(v, own, T, m, g, P.tab, perm, troot);
+        mr_store(v, vec, T, 1.0);
+    } else if constexpr (MODE == MRG_LOWDIAG) {
+        __shared__ double2 colrot[kMrColRot];
+        mr_colrot(colrot, P, T);
+        const double tt = angle_value(P.t);
+        mr_load(v, vec, T);
+        mr_forward<MAXR>(v, own, T, m, g, P.tab, perm, troot);
+        __syncthreads();
+        if (half == 1) {
+#pragma unroll
+            for (int k = 0; k < kMrRegs; ++k) {
+                const int e = t + k * kMrThreads;
+                if (e < ne)
+                    lds[1][e] = v[k];
+            }
+        }
+        __syncthreads();
+        double acc = 0.0;
+        if (half == 0) {
+#pragma unroll
+            for (int k = 0; k < kMrRegs; ++k) {
+                const int e = t + k * kMrThreads;
+                if (e < ne) {
+                    const double lam = mr_lambda_at(P, T, colrot, e);
+                    acc = fma(lam, im_term(lds[1][e], v[k]), acc);
+                    const double2 d = expmi(-tt * lam);  // exp(+i t lambda): the inverse diagonal
+                    v[k] = cmul(v[k], d);
+                    lds[0][e] = d;
+                }
+                QVA_SCHED_FENCE();
+            }
+        }
+        __syncthreads();
+        if (half == 1) {
+#pragma unroll
+            for (int k = 0; k < kMrRegs; ++k) {
+                const int e = t + k * kMrThreads;
+                if (e < ne)
+                    v[k] = cmul(v[k], lds[0][e]);
+            }
+        }
+        const double2 tot = block_sum2(acc * invN, 0.0, red);  // its barriers end the reads of lds[0]
+        if (threadIdx.x == 0)
+            P.slot[blockIdx.x] = tot.x;
+        mr_inverse<MAXR>(v, own, T, m, g, P.tab, perm, troot);
+        mr_store(v, vec, T, 1.0);
+    } else {  // MRG_BOUND, MRG_FINAL
+        mr_load(v, vec, T);
+        mr_inverse<MAXR>(v, own, T, m, g, P.tab, perm, troot);
+#pragma unroll
+        for (int k = 0; k < kMrRegs; ++k)
+            v[k] = make_double2(v[k].x * invN, v[k].y * invN);
+        __syncthreads();
+        if (half == 1) {
+#pragma unroll
+            for (int k = 0; k < kMrRegs; ++k) {
+                const int e = t + k * kMrThreads;
+                if (e < ne)
+                    lds[1][e] = v[k];
+            }
+        }
+        __syncthreads();
+        const double gam = angle_value(P.gamma);
+        double acc = 0.0;
+        if (half == 0) {
+#pragma unroll
+            for (int k = 0; k < kMrRegs; ++k) {
+                const int e = t + k * kMrThreads;
+                if (e < ne) {
+                    const double qq = ld_nt(P.q + T.gidx(e));
+                    acc = fma(qq, im_term(lds[1][e], v[k]), acc);
+                    if constexpr (MODE == MRG_BOUND) {
+                        const double2 u = expmi(-gam * qq);  // exp(+i gamma q): the inverse phase
+                        v[k] = cmul(v[k], u);
+                        lds[0][e] = u;
+                    }
+                }
+                QVA_SCHED_FENCE();
+            }
+        }
+        if constexpr (MODE == MRG_BOUND) {
+            __syncthreads();
+            if (half == 1) {
+#pragma unroll
+                for (int k = 0; k < kMrRegs; ++k) {
+                    const int e = t + k * kMrThreads;
+                    if (e < ne)
+                        v[k] = cmul(v[k], lds[0][e]);
+                }
+            }
+        }
+        const double2 tot = block_sum2(acc, 0.0, red);
+        if (threadIdx.x == 0)
+            P.slot[blockIdx.x] = tot.x;
+        if constexpr (MODE == MRG_BOUND) {
+            mr_forward<MAXR>(v, own, T, m, g, P.tab, perm, troot);
+            mr_store(v, vec, T, 1.0);
+        }
+    }
+}
+
 // N <= 4096 (one group): the whole evolution, and with MRG_SMALL the adjoint
 // walk, in one workgroup.
 template <int MODE, int MAXR>
@@ -661,7 +838,7 @@ __global__ __launch_bounds__(kMrThreads, 1) void mrsmall_kernel(MrPassParams P)
     __shared__ double2 colrot[kMrColRot];
     const MrTile T = mr_tile(m, 0, 0);
     const int* perm = reinterpret_cast<const int*>(P.tab + m->tab_len + m->tw_len);
-    const int t = threadIdx.x, ne = T.ncol * T.A;
+    const int t = mr_tid(), ne = T.ncol * T.A;
     const double invN = 1.0 / (double)P.N;
     mr_colrot(colrot, P, T);  // published by the first transform's barrier
     double2 p[kMrRegs];
@@ -843,11 +1020,19 @@ hipError_t launch_mr_modes(const MrPassParams& P, int mode, dim3 grid, hipStream
         QVA_MR_MODE(mrsmall_kernel, MR_SMALL_STORE)
         QVA_MR_MODE(mrsmall_kernel, MR_SMALL_MIX)
         QVA_MR_MODE(mrsmall_kernel, MRG_SMALL)
-        QVA_MR_MODE(mrgrad_kernel, MRG_TURN)
-        QVA_MR_MODE(mrgrad_kernel, MRG_LOWDIAG)
-        QVA_MR_MODE(mrgrad_kernel, MRG_BOUND)
-        QVA_MR_MODE(mrgrad_kernel, MRG_FINAL)
 #undef QVA_MR_MODE
+#define QVA_MR_MODE2(M)                                                                          \
+    case M:                                                                                      \
+        if constexpr (MAXR <= 23)                                                                \
+            hipLaunchKernelGGL((mrgrad2_kernel<M, MAXR>), grid, dim3(2 * kMrThreads), 0, s, P); \
+        else                                                                                     \
+            hipLaunchKernelGGL((mrgrad_kernel<M, MAXR>), grid, dim3(kMrThreads), 0, s, P);      \
+        break;
+        QVA_MR_MODE2(MRG_TURN)
+        QVA_MR_MODE2(MRG_LOWDIAG)
+        QVA_MR_MODE2(MRG_BOUND)
+        QVA_MR_MODE2(MRG_FINAL)
+#undef QVA_MR_MODE2
     default:
         return hipErrorInvalidValue;
     }
