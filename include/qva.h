@@ -179,22 +179,30 @@ int qva_mix_x(qva_c128 *psi, int n_qubits, double t, void *stream);
 /* psi <- F^-1 diag(exp(-i t lambda_m)) F psi: a circulant mixer exp(-i t W)
  * through its eigensystem (Sec. 3), F the unnormalised DFT
  * (F_mj = exp(-2 pi i j m / N)), F^-1 = conj(F)/N.
- * psi: device, N complex, in place.  N = 2^k, 1 <= k <= QVA_MAX_QUBITS, any
- * lambda_kind; or, for QVA_LAMBDA_RING and QVA_LAMBDA_ARRAY, any N < 2^31
- * whose prime factors are all <= 31 (the mixed-radix transform; e.g. the
- * C(m, k) feasible portfolios of a constrained QWOA, m <= 31).  Other N:
- * QVA_ERR_UNSUPPORTED (qva_evolve and qva_grad take them).  N < 2:
- * QVA_ERR_SIZE.
+ * psi: device, N complex, in place.  Every N the evolution takes (the N
+ * feasible solutions of a constrained QWOA, Sec. 2.4.2, need not be a power
+ * of two):
+ *   N = 2^k, 1 <= k <= QVA_MAX_QUBITS: any lambda_kind (radix-2 passes);
+ *   QVA_LAMBDA_COMPLETE, any other 2 < N <= 2^QVA_MAX_QUBITS: the closed
+ *     form e^{it}(psi + (e^{-itN} - 1)/N sum(psi)) (one sum, one update);
+ *   QVA_LAMBDA_RING / QVA_LAMBDA_ARRAY, any other N < 2^31: the in-place
+ *     mixed-radix transform when every prime factor of N is <= 31 (e.g. the
+ *     C(m, k) portfolios, m <= 31), else Bluestein's chirp-z transform over
+ *     a padded power of two M >= 2N - 1.
+ * N < 2 or N > 2^QVA_MAX_QUBITS: QVA_ERR_SIZE.  Ring or array over N >= 2^31
+ * not a power of two: QVA_ERR_UNSUPPORTED.
  * lambda: device, N doubles in natural order when lambda_kind ==
  * QVA_LAMBDA_ARRAY, else ignored (may be NULL).
  * work: device, 16-byte aligned, >= qva_mix_circulant_workspace_bytes(N)
- * bytes (the transform's root, twiddle and permutation tables, written by
- * the call; NULL allowed when that is 0). */
+ * bytes (root, twiddle and permutation tables; Bluestein's padded state and
+ * two filter spectra, M complex values each; or the complete graph's block
+ * sums), written by the call; NULL allowed when that is 0.  Calls that share a workspace
+ * must not overlap in time. */
 int qva_mix_circulant(qva_c128 *psi, const double *lambda, int lambda_kind, int64_t N,
                       double t, void *work, size_t work_bytes, void *stream);
 
-/* Bytes of device workspace qva_mix_circulant needs for N amplitudes
- * (0 when none is needed or N is not supported). */
+/* Bytes of device workspace qva_mix_circulant needs for N amplitudes, enough
+ * for every lambda_kind (0 when none is needed or N is not supported). */
 size_t qva_mix_circulant_workspace_bytes(int64_t N);
 
 /* Bytes of device workspace that qva_evolve (for_grad = 0) or qva_grad

@@ -295,26 +295,29 @@ bool bluestein_path(const qva_problem* P)
 }
 
 // log2 M: the smallest power of two >= 2N - 1, and at least 2^13 (tile passes).
-int blu_bits(const qva_problem* P)
+int blu_bits_n(int64_t N)
 {
     int b = kTileBits + 1;
-    while ((int64_t(1) << b) < 2 * problem_N(P) - 1)
+    while ((int64_t(1) << b) < 2 * N - 1)
         ++b;
     return b;
 }
 
+int blu_bits(const qva_problem* P) { return blu_bits_n(problem_N(P)); }
+
 // Workspace of a Bluestein evolution: partials, then the padded buffer and the
-// two filter spectra (M amplitudes each).
+// two filter spectra (M amplitudes each).  The lone mixer (with_partials
+// false) needs no partials.
 struct BluLayout {
     size_t parts = 0, pad = 0, b0 = 0, b1 = 0, tw = 0, total = 0;
 };
 
-BluLayout blu_layout(const qva_problem* P)
+BluLayout blu_layout_n(int64_t N, bool with_partials)
 {
     BluLayout L;
-    const int64_t M = int64_t(1) << blu_bits(P);
-    const int64_t e = expect_partial_count(problem_N(P)), tiles = M >> kTileBits;
-    size_t off = align256((size_t)(e > tiles ? e : tiles) * sizeof(double2));
+    const int64_t M = int64_t(1) << blu_bits_n(N);
+    const int64_t e = expect_partial_count(N), tiles = M >> kTileBits;
+    size_t off = with_partials ? align256((size_t)(e > tiles ? e : tiles) * sizeof(double2)) : 0;
     L.pad = off;
     off += (size_t)M * sizeof(double2);
     L.b0 = off;
@@ -326,6 +329,8 @@ BluLayout blu_layout(const qva_problem* P)
     L.total = off;
     return L;
 }
+
+BluLayout blu_layout(const qva_problem* P) { return blu_layout_n(problem_N(P), true); }
 
 // Blocks of the closed-form passes (kCompleteChunk amplitudes each, the last
 // one possibly partial).
@@ -653,6 +658,99 @@ int evolve_bluestein(const qva_problem* P, const double* gammas, const double* t
             return QVA_ERR_HIP;
     }
     return QVA_OK;
+}
+
+// The mixer alone, exp(-i t W) = F^-1 diag(exp(-i t lambda)) F, for N that
+// is neither a power of two nor a product of primes <= 31 (ring or
+// eigenvalue array), through Bluestein's transform on the padded buffer:
+// a_j = psi_j conj(w_j) (zero for j >= N), the convolution with w,
+// exp(-i t lambda_m) (zero for m >= N), the convolution with conj(w), and
+// psi_j = w_j x_j / N (j < N).  The chirps between the two convolutions
+// cancel as in the evolution.  work: blu_layout_n(N, false).
+int bluestein_mix(double2* psi, const double* lambda, int lambda_kind, int64_t N, double t, char* work,
+                  hipStream_t s)
+{
+    const int nb = blu_bits_n(N);
+    const std::vector<XGroup> groups = x_groups(nb);
+    const int c = (int)groups.size() - 1;  // top group; middles 1..c-1, low 0
+    const BluLayout W = blu_layout_n(N, false);
+    double2* pad = reinterpret_cast<double2*>(work + W.pad);
+    double2* spec[2] = {reinterpret_cast<double2*>(work + W.b0), reinterpret_cast<double2*>(work + W.b1)};
+    double2* tw = reinterpret_cast<double2*>(work + W.tw);
+    if (launch_twiddle_table(tw, s) != hipSuccess)
+        return QVA_ERR_HIP;
+    auto pass = [&](int group, int mode, int which) {
+        const XGroup& g = groups[group];
+        FftPassParams f{};
+        f.psi = pad;
+        f.lam = lambda;
+        f.lambda_kind = lambda_kind == QVA_LAMBDA_RING ? FFT_LAMBDA_RING : FFT_LAMBDA_NATURAL;
+        f.mix1 = host_angle(t);
+        f.phase = host_angle(0.0);
+        f.n = nb;
+        f.k = g.k;
+        f.col_bits = g.col_bits;
+        f.flags = mode;
+        f.nb = N;
+        f.bt = spec[which];
+        f.out = mode == FMODE_LOWDIF_TILED ? spec[which] : psi;
+        f.in = psi;
+        f.conj = which;
+        f.tw = tw;
+        return launch_fftpass(f, s) == hipSuccess;
+    };
+    auto front = [&](int which) {
+        for (int g = c - 1; g >= 1; --g)
+            if (!pass(g, FMODE_DIF, which))
+                return false;
+        return true;
+    };
+    auto back = [&](int which) {
+        for (int g = 1; g <= c - 1; ++g)
+            if (!pass(g, FMODE_DIT, which))
+                return false;
+        return true;
+    };
+    // the filters' spectra (times 1/M): w, then conj(w)
+    for (int which = 0; which < 2; ++which)
+        if (!pass(c, FMODE_B_CHIRP, which) || !front(which) || !pass(0, FMODE_LOWDIF_TILED, which))
+            return QVA_ERR_HIP;
+    const bool ok = pass(c, FMODE_B_LOAD, 0) && front(0) && pass(0, FMODE_LOWMUL, 0) && back(0) &&
+                    pass(c, FMODE_B_BOUND_LAM, 0) && front(1) && pass(0, FMODE_LOWMUL, 1) && back(1) &&
+                    pass(c, FMODE_B_STORE, 0);
+    return ok ? QVA_OK : QVA_ERR_HIP;
+}
+
+// Workspace of the complete graph's lone mixer: per-block partial sums, then S.
+size_t complete_mix_bytes(int64_t N)
+{
+    const int64_t blocks = (N + kCompleteChunk - 1) / kCompleteChunk;
+    return align256((size_t)blocks * sizeof(double2)) + 256;
+}
+
+// The complete graph's mixer alone over any N, in closed form:
+// psi <- e^{i t} (psi + c S 1), S = sum_j psi_j, c = (e^{-i t N} - 1) / N
+// (one summing pass, the fixed-order reduction of its block sums, one update
+// pass).  work: complete_mix_bytes(N).
+int complete_mix(double2* psi, int64_t N, double t, char* work, hipStream_t s)
+{
+    const int64_t blocks = (N + kCompleteChunk - 1) / kCompleteChunk;
+    double2* partials = reinterpret_cast<double2*>(work);
+    double2* sum = reinterpret_cast<double2*>(work + align256((size_t)blocks * sizeof(double2)));
+    CompleteParams c{};
+    c.psi = psi;
+    c.partials = partials;
+    c.N = N;
+    c.flags = CPMODE_SUM;
+    if (launch_complete(c, s) != hipSuccess)
+        return QVA_ERR_HIP;
+    if (launch_final_reduce(partials, blocks, &sum->x, &sum->y, s) != hipSuccess)
+        return QVA_ERR_HIP;
+    c.flags = CPMODE_MIX;
+    c.sum_in = sum;
+    c.ts = nullptr;
+    c.t_val = t;
+    return hip_status(launch_complete(c, s));
 }
 
 // ----------------------------------------------- mixed-radix circulant
@@ -1857,10 +1955,17 @@ int qva_mix_x(qva_c128* psi, int n_qubits, double t, void* stream)
 size_t qva_mix_circulant_workspace_bytes(int64_t N)
 {
     if (N >= 2 && (N & (N - 1)) != 0) {
-        MrGeom m{};
-        if (!mixed_geom(N, &m))
+        // enough for every eigenvalue kind: the complete graph's sums, and for
+        // the ring and arrays the mixed-radix tables or Bluestein's buffers
+        if (N > (int64_t(1) << QVA_MAX_QUBITS))
             return 0;
-        return align256(sizeof(MrGeom)) + align256(mr_table_bytes(m));
+        const size_t cpl = complete_mix_bytes(N);
+        MrGeom m{};
+        if (mixed_geom(N, &m))
+            return std::max(cpl, align256(sizeof(MrGeom)) + align256(mr_table_bytes(m)));
+        if (N < (int64_t(1) << 31))
+            return std::max(cpl, blu_layout_n(N, false).total);
+        return cpl;
     }
     return N > (int64_t(1) << kTileBits) ? kTwiddleTableBytes : 0;
 }
@@ -1878,10 +1983,15 @@ int qva_mix_circulant(qva_c128* psi, const double* lambda, int lambda_kind, int6
     if (N < 2)
         return QVA_ERR_SIZE;
     if ((N & (N - 1)) != 0) {
-        // N solutions with prime factors <= 31 (ring or eigenvalue array):
-        // the mixed-radix passes
+        // N solutions, not a power of two: the complete graph in closed form
+        // (N <= 2^QVA_MAX_QUBITS); the ring and arrays through the
+        // mixed-radix passes (prime factors <= 31), else Bluestein's
+        // transform (N < 2^31)
+        if (N > (int64_t(1) << QVA_MAX_QUBITS))
+            return QVA_ERR_SIZE;
         MrGeom m{};
-        if (lambda_kind == QVA_LAMBDA_COMPLETE || !mixed_geom(N, &m))
+        const bool mixed = lambda_kind != QVA_LAMBDA_COMPLETE && mixed_geom(N, &m);
+        if (lambda_kind != QVA_LAMBDA_COMPLETE && !mixed && N >= (int64_t(1) << 31))
             return QVA_ERR_UNSUPPORTED;
         if (!aligned(psi, 16) || (lambda_kind == QVA_LAMBDA_ARRAY && !aligned(lambda, 8)))
             return QVA_ERR_ALIGN;
@@ -1889,8 +1999,13 @@ int qva_mix_circulant(qva_c128* psi, const double* lambda, int lambda_kind, int6
             return QVA_ERR_WORKSPACE;
         if (!aligned(work, 16))
             return QVA_ERR_ALIGN;
-        return mixed_mix(reinterpret_cast<double2*>(psi), lambda, lambda_kind, m, t, static_cast<char*>(work),
-                         as_stream(stream));
+        double2* d = reinterpret_cast<double2*>(psi);
+        char* w = static_cast<char*>(work);
+        if (lambda_kind == QVA_LAMBDA_COMPLETE)
+            return complete_mix(d, N, t, w, as_stream(stream));
+        if (mixed)
+            return mixed_mix(d, lambda, lambda_kind, m, t, w, as_stream(stream));
+        return bluestein_mix(d, lambda, lambda_kind, N, t, w, as_stream(stream));
     }
     int n = 0;
     while (n <= QVA_MAX_QUBITS && (int64_t(1) << n) < N)

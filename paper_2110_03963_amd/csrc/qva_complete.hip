@@ -54,7 +54,7 @@ __global__ __launch_bounds__(kThreads) void complete_kernel(CompleteParams P)
             qq[r] = in_range(base, r, P.N) ? ld_nt(P.q + base + r * kThreads) : 0.0;
     }
     if constexpr (FLAGS & CP_MIX) {
-        const double tm = P.ts[P.mix_layer];
+        const double tm = P.ts ? P.ts[P.mix_layer] : P.t_val;
         const double2 eit = expmi(-tm);   // e^{i t}
         const double2 e = expmi(tm * Nd);  // e^{-i t N}
         const double invN = 1.0 / Nd;
@@ -308,6 +308,12 @@ hipError_t launch_complete(const CompleteParams& P, hipStream_t s)
         break;
     case CPMODE_LAYER:
         hipLaunchKernelGGL(complete_kernel<CPMODE_LAYER>, grid, dim3(kThreads), 0, s, P);
+        break;
+    case CPMODE_SUM:
+        hipLaunchKernelGGL(complete_kernel<CPMODE_SUM>, grid, dim3(kThreads), 0, s, P);
+        break;
+    case CPMODE_MIX:
+        hipLaunchKernelGGL(complete_kernel<CPMODE_MIX>, grid, dim3(kThreads), 0, s, P);
         break;
     case CPMODE_LAST:
         hipLaunchKernelGGL(complete_kernel<CPMODE_LAST>, grid, dim3(kThreads), 0, s, P);

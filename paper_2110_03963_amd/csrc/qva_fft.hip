@@ -248,7 +248,22 @@ __global__ __launch_bounds__(kThreads, 2) void fftpass_kernel(FftPassParams P)
         }
         dif_tile<C>(v, lds, g, t);
         store_tile<dif_last<C>()>(v, P.psi, g, t, 1.0);
-    } else if constexpr (FLAGS == FMODE_B_LAST || FLAGS == FMODE_B_LAST_STORE) {
+    } else if constexpr (FLAGS == FMODE_B_LOAD) {
+        // a_j = psi_j conj(w_j) for j < N, zero above: the input of the
+        // forward transform's convolution
+#pragma unroll
+        for (int r = 0; r < kRegs; ++r) {
+            const int64_t j = g(elem<LA>(t, r));
+            if (j < P.nb) {
+                const double2 w = chirp(j, P.nb);
+                v[r] = cmul(ld_nt(P.in + j), make_double2(w.x, -w.y));
+            } else {
+                v[r] = make_double2(0.0, 0.0);
+            }
+        }
+        dif_tile<C>(v, lds, g, t);
+        store_tile<dif_last<C>()>(v, P.psi, g, t, 1.0);
+    } else if constexpr (FLAGS == FMODE_B_LAST || FLAGS == FMODE_B_LAST_STORE || FLAGS == FMODE_B_STORE) {
         // x_j after the second convolution; psi_j = w_j x_j / N for j < N
         const double invNb = 1.0 / (double)P.nb;
         load_tile<dif_last<C>()>(v, P.psi, g, t);
@@ -259,16 +274,20 @@ __global__ __launch_bounds__(kThreads, 2) void fftpass_kernel(FftPassParams P)
             const int64_t j = g(elem<LA>(t, r));
             if (j < P.nb) {
                 const double2 x = make_double2(v[r].x * invNb, v[r].y * invNb);
-                const double a = x.x * x.x + x.y * x.y;
-                f = fma(a, ld_nt(P.q + j), f);
-                nr += a;
+                if constexpr (FLAGS & FP_EXPECT) {
+                    const double a = x.x * x.x + x.y * x.y;
+                    f = fma(a, ld_nt(P.q + j), f);
+                    nr += a;
+                }
                 if constexpr (FLAGS & FP_STORE)
                     st_nt(P.out + j, cmul(chirp(j, P.nb), x));
             }
         }
-        const double2 tot = block_sum2(f, nr, red);
-        if (t == 0)
-            P.partials[blockIdx.x] = tot;
+        if constexpr (FLAGS & FP_EXPECT) {
+            const double2 tot = block_sum2(f, nr, red);
+            if (t == 0)
+                P.partials[blockIdx.x] = tot;
+        }
     } else if constexpr (FLAGS == FMODE_LOWMUL) {
         load_tile<LA>(v, P.psi, g, t);
         dif_tile<C, true>(v, lds, g, t, P.tw);
@@ -421,6 +440,8 @@ hipError_t launch_fft_c(const FftPassParams& P, unsigned grid, hipStream_t s)
         QVA_FFT_MODE(FMODE_B_BOUND_Q)
         QVA_FFT_MODE(FMODE_B_LAST)
         QVA_FFT_MODE(FMODE_B_LAST_STORE)
+        QVA_FFT_MODE(FMODE_B_LOAD)
+        QVA_FFT_MODE(FMODE_B_STORE)
 #undef QVA_FFT_MODE
     default:
         return hipErrorInvalidValue;

@@ -127,8 +127,10 @@ enum : int {
     FMODE_B_BOUND_Q = 176,    // inverse top group, exp(-i gamma q) / N (j < N, else 0), forward top
     FMODE_B_LAST = 192 | FP_EXPECT,            // inverse top group, <Q> over j < N
     FMODE_B_LAST_STORE = 192 | FP_EXPECT | FP_STORE,  // ... and psi_j = w_j x_j / N
+    FMODE_B_STORE = 192 | FP_STORE,  // inverse top group, psi_j = w_j x_j / N only (the lone mixer)
     FMODE_LOWMUL = 208,       // low group: forward, times a complex per-tile array, inverse
-    FMODE_LOWDIF_TILED = 224  // low group: forward, written per tile (times 1/M)
+    FMODE_LOWDIF_TILED = 224, // low group: forward, written per tile (times 1/M)
+    FMODE_B_LOAD = 240        // the caller's psi times conj chirp, zero pad, forward top group
 };
 
 struct FftPassParams {
@@ -145,7 +147,8 @@ struct FftPassParams {
     // Bluestein passes
     int64_t nb;           // the logical N (< 2^31); n above is log2 of the padded M
     const double2* bt;    // FMODE_LOWMUL: complex multiplier in per-tile order
-    double2* out;         // FMODE_LOWDIF_TILED: its output; FMODE_B_LAST_STORE: psi (nb amplitudes)
+    double2* out;         // FMODE_LOWDIF_TILED: its output; FMODE_B_LAST_STORE, FMODE_B_STORE: psi (nb amplitudes)
+    const double2* in;    // FMODE_B_LOAD: the state to transform (nb amplitudes)
     int conj;             // FMODE_B_CHIRP: conjugate filter
     const double2* tw;    // low-group passes (LOWDIAG, LOWMUL, LOWDIF_TILED): root table W_4096^k
 };
@@ -268,7 +271,9 @@ enum : int {
     CPMODE_FIRST = CP_INIT | CP_PHASE | CP_SUM | CP_STORE,
     CPMODE_LAYER = CP_MIX | CP_PHASE | CP_SUM | CP_STORE,
     CPMODE_LAST = CP_MIX | CP_EXPECT,
-    CPMODE_LAST_STORE = CP_MIX | CP_EXPECT | CP_STORE
+    CPMODE_LAST_STORE = CP_MIX | CP_EXPECT | CP_STORE,
+    CPMODE_SUM = CP_SUM,              // the lone mixer: per-block sums of the caller's psi,
+    CPMODE_MIX = CP_MIX | CP_STORE    // then psi <- e^{it} (psi + c S) in place
 };
 
 struct CompleteParams {
@@ -279,7 +284,8 @@ struct CompleteParams {
     const double2* sum_in; // device: sum over the input state (CP_MIX)
     double2* partials;     // one per block: sums (CP_SUM) or (<Q>, norm) (CP_EXPECT)
     int64_t N;             // amplitudes (any N >= 1; the last block may be partial)
-    int mix_layer;         // layer of the mixer (CP_MIX)
+    int mix_layer;         // layer of the mixer (CP_MIX): t = ts[mix_layer], or t_val if ts is null
+    double t_val;
     int phase_layer;       // layer of the phase (CP_PHASE)
     int flags;
 };

@@ -81,7 +81,8 @@ def mix_x(psi: torch.Tensor, t: float) -> torch.Tensor:
 
 def mix_circulant(psi: torch.Tensor, t: float, lam: torch.Tensor | None = None,
                   kind: str = "array") -> torch.Tensor:
-    """psi <- F^-1 diag(exp(-i t lambda)) F psi, in place."""
+    """psi <- F^-1 diag(exp(-i t lambda)) F psi, in place, for any N >= 2
+    (kind "ring", "complete", or "array" with lam)."""
     _need(psi, torch.complex128, "psi")
     if kind == "array":
         _need(lam, torch.float64, "lam")

@@ -189,6 +189,30 @@ def test_evolve_bluestein(N, kind, p):
     assert f2.item() == f.item()
 
 
+@pytest.mark.parametrize("N", [5, 1009, 4097, 6000, 12289, 100003, 1000003])
+@pytest.mark.parametrize("kind", ["ring", "array", "array-asym", "complete"])
+def test_mix_circulant_any_n(N, kind):
+    """qva_mix_circulant alone over N solutions, N not a power of two: the
+    ring and eigenvalue arrays through Bluestein's transform where N has a
+    prime factor above 31 (mixed radix otherwise), the complete graph in
+    closed form for every N; against the oracle's mixer (naive DFT up to
+    4096, its own chirp-z transform above) or its closed form, then -t
+    restores the state."""
+    rng = np.random.default_rng(3 * N + len(kind))
+    psi0 = rand_state(rng, N)
+    lam = _lam(kind, N, rng)
+    api_kind = "array" if kind.startswith("array") else kind
+    lam_dev = to_dev(lam) if api_kind == "array" else None
+    t = float(rng.uniform(0.2, 3.0))
+    print(f"mix_circulant any N: N={N} {kind} t={t}", flush=True)
+    psi = to_dev(psi0)
+    qva.mix_circulant(psi, t, lam_dev, api_kind)
+    ref = oracle.mix_complete(psi0, t) if kind == "complete" else oracle.mix_circulant(psi0, lam, t)
+    assert state_err(psi.cpu().numpy(), ref) < PSI_TOL
+    qva.mix_circulant(psi, -t, lam_dev, api_kind)
+    assert state_err(psi.cpu().numpy(), psi0) < PSI_TOL
+
+
 @pytest.mark.parametrize("n", [13, 17])
 def test_evolve_complete_degenerate_angles(n):
     """t = 0 and t N a multiple of 2 pi (c = 0) leave only global phases: f

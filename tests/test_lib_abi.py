@@ -755,27 +755,35 @@ def test_group_split_setting(lib):
 
 
 def test_mix_circulant_validation(lib):
-    """The lone circulant mixer: any power of two, or for the ring and an
-    eigenvalue array any N < 2^31 with prime factors <= 31 (mixed radix, with
-    a workspace for its tables); other N are unsupported, before any launch."""
+    """The lone circulant mixer takes every N >= 2 up to 2^33 for the
+    complete graph, and for the ring and an eigenvalue array every power of
+    two and every other N < 2^31 (mixed radix for prime factors <= 31, else
+    Bluestein's transform); its workspace covers every eigenvalue kind.
+    Arguments are checked before any launch."""
     S = _lib
     ring, array, complete = 1, 0, 2
     assert lib.qva_mix_circulant(None, None, ring, 1024, 0.1, None, 0, None) == S.QVA_ERR_ARG
     assert lib.qva_mix_circulant(FAKE, None, array, 1024, 0.1, None, 0, None) == S.QVA_ERR_ARG
     assert lib.qva_mix_circulant(FAKE, None, ring, 1, 0.1, None, 0, None) == S.QVA_ERR_SIZE
     assert lib.qva_mix_circulant(FAKE, None, ring, -6, 0.1, None, 0, None) == S.QVA_ERR_SIZE
-    for N in (1009, 2 * 37 * 512, (1 << 31) + 6):  # a prime factor above 31, or too large
-        assert lib.qva_mix_circulant_workspace_bytes(N) == 0
-        assert lib.qva_mix_circulant(FAKE, None, ring, N, 0.1, FAKE, 1 << 30, None) == S.QVA_ERR_UNSUPPORTED
-    assert lib.qva_mix_circulant(FAKE, None, complete, 6000, 0.1, FAKE, 1 << 30, None) == S.QVA_ERR_UNSUPPORTED
-    for N in (6, 6000, 10400600):
+    big = (1 << 31) + 11  # a prime: neither mixed radix nor under Bluestein's 2^31
+    assert lib.qva_mix_circulant(FAKE, None, ring, big, 0.1, FAKE, 1 << 40, None) == S.QVA_ERR_UNSUPPORTED
+    assert lib.qva_mix_circulant(FAKE, None, complete, (1 << 33) + 1, 0.1, FAKE, 1 << 40, None) == S.QVA_ERR_SIZE
+    assert lib.qva_mix_circulant_workspace_bytes((1 << 33) + 1) == 0
+    # above 2^31 only the complete graph's per-block sums (4096 amplitudes a block), then S
+    assert lib.qva_mix_circulant_workspace_bytes(big) == (16 * -(-big // 4096) + 255) // 256 * 256 + 256
+    for N in (6, 1009, 6000, 2 * 37 * 512, 10400600, 3000017):
         ws = lib.qva_mix_circulant_workspace_bytes(N)
         assert ws > 0
-        assert lib.qva_mix_circulant(FAKE, None, ring, N, 0.1, None, 0, None) == S.QVA_ERR_WORKSPACE
-        assert lib.qva_mix_circulant(FAKE, None, ring, N, 0.1, FAKE, ws - 1, None) == S.QVA_ERR_WORKSPACE
-        assert lib.qva_mix_circulant(FAKE + 8, None, ring, N, 0.1, FAKE, ws, None) == S.QVA_ERR_ALIGN
+        for kind, lam in ((ring, None), (array, FAKE), (complete, None)):
+            assert lib.qva_mix_circulant(FAKE, lam, kind, N, 0.1, None, 0, None) == S.QVA_ERR_WORKSPACE
+            assert lib.qva_mix_circulant(FAKE, lam, kind, N, 0.1, FAKE, ws - 1, None) == S.QVA_ERR_WORKSPACE
+            assert lib.qva_mix_circulant(FAKE + 8, lam, kind, N, 0.1, FAKE, ws, None) == S.QVA_ERR_ALIGN
+            assert lib.qva_mix_circulant(FAKE, lam, kind, N, 0.1, FAKE + 8, ws, None) == S.QVA_ERR_ALIGN
         assert lib.qva_mix_circulant(FAKE, FAKE + 4, array, N, 0.1, FAKE, ws, None) == S.QVA_ERR_ALIGN
-        assert lib.qva_mix_circulant(FAKE, None, ring, N, 0.1, FAKE + 8, ws, None) == S.QVA_ERR_ALIGN
+    # Bluestein's buffers: the padded state and two filter spectra of M >= 2N - 1 amplitudes
+    M = 1 << (2 * 3000017 - 2).bit_length()
+    assert lib.qva_mix_circulant_workspace_bytes(3000017) >= 3 * M * 16
     assert lib.qva_mix_circulant_workspace_bytes(1 << 20) > 0
     assert lib.qva_mix_circulant_workspace_bytes(1 << 12) == 0
 
