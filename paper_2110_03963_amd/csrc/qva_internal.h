@@ -199,6 +199,7 @@ struct MrGeom {
     int tw_len;                        // sum over g >= 1 of cols_g A_g
     double rA[kMrMaxGroups];           // 1 / A_g (the passes' integer divisions)
     int64_t U;                         // N / A_0, the low group's column count
+    int lds_pad;                       // the low group's passes pad their LDS slots (mr_low_lds_cost)
 };
 
 // Pass modes of the mixed-radix passes (mrpass_kernel / mrgrad_kernel).

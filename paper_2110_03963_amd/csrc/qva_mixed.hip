@@ -33,6 +33,16 @@ namespace {
 constexpr int kMrThreads = 256;
 constexpr int kMrRegs = kMrTileElems / kMrThreads;
 
+// LDS slot of tile element e.  When the low group's radices put a
+// power-of-two radix after the odd ones (3496 = 23 19 8), the last stages
+// read at strides of 8 or 16 elements (128 or 256 B), which land the lanes
+// of a quarter-wave on the same banks; the planner then sets lds_pad and the
+// low group's passes are built with PAD: one pad element after every 16
+// spreads them.  Other passes keep slot e.
+constexpr int kMrLdsElems = kMrTileElems + kMrTileElems / 16;
+template <bool PAD>
+__device__ __forceinline__ int mr_slot(int e) { return PAD ? e + (e >> 4) : e; }
+
 // A tile's thread index: the workgroup's in the single-vector kernels, the
 // half's in the two-vector kernels (two halves of 256 threads).
 __device__ __forceinline__ int mr_tid() { return threadIdx.x & (kMrThreads - 1); }
@@ -182,7 +192,7 @@ __device__ __forceinline__ void dft_regs(double2 (&x)[R], bool inv, Root&& root,
 // products (about 2e-15 for R = 31), read before the butterfly's inputs so
 // that no load waits inside the DFT.  The last stage (L = R) has none.
 // LDS slot of (col, j): col A + j (low group) or j ncol + col.
-template <int R, bool TW>
+template <int R, bool TW, bool PAD>
 __device__ __forceinline__ void mr_stage_tw(double2* lds, int A, int ncol, bool low, int L,
                                             const double2* __restrict__ tab, bool inv)
 {
@@ -192,7 +202,7 @@ __device__ __forceinline__ void mr_stage_tw(double2* lds, int A, int ncol, bool 
     const int mstride = L / R, per_col = A / R, tstep = A / L, rstep = mstride * tstep, wstep = R * tstep;
     const int items = ncol * per_col;
     const double rpc = 1.0 / (double)per_col, rms = 1.0 / (double)mstride, rnc = 1.0 / (double)ncol;
-    const int cs = low ? A : 1, js = low ? 1 : ncol;  // LDS strides of col and j
+    const int cs = low ? A : 1, js = low ? 1 : ncol;  // element strides of col and j
     constexpr int H = R / 2;
     for (int it = mr_tid(); it < items; it += kMrThreads) {
         int col, bi;
@@ -213,7 +223,7 @@ __device__ __forceinline__ void mr_stage_tw(double2* lds, int A, int ncol, bool 
         double2 x[R];
 #pragma unroll
         for (int k = 0; k < R; ++k)
-            x[k] = lds[base + k * step];
+            x[k] = lds[mr_slot<PAD>(base + k * step)];
         double2 wm = w1;  // W_L^(i m) of the last m <= H
         dft_regs<R>(x, inv, [&](int j) { return tab[j * rstep]; }, [&](int m, double2 y) {
             if constexpr (TW) {
@@ -225,26 +235,26 @@ __device__ __forceinline__ void mr_stage_tw(double2* lds, int A, int ncol, bool 
                     y = cmul(y, wm);
                 }
             }
-            lds[base + m * step] = y;
+            lds[mr_slot<PAD>(base + m * step)] = y;
         });
     }
 }
 
-template <int R>
+template <int R, bool PAD>
 __device__ __forceinline__ void mr_stage(double2* lds, int A, int ncol, bool low, int L,
                                          const double2* __restrict__ tab, bool inv)
 {
     if (L > R)
-        mr_stage_tw<R, true>(lds, A, ncol, low, L, tab, inv);
+        mr_stage_tw<R, true, PAD>(lds, A, ncol, low, L, tab, inv);
     else
-        mr_stage_tw<R, false>(lds, A, ncol, low, L, tab, inv);
+        mr_stage_tw<R, false, PAD>(lds, A, ncol, low, L, tab, inv);
 }
 
 // Every DIF stage of one group's DFT on the tile in LDS.  MAXR: the largest
 // radix the kernel is built for (16, 23 or 31); the radix-17..23 stages fit
 // two waves per SIMD in the single-vector passes, radices 29 and 31 need the
 // registers of one wave per SIMD.
-template <int MAXR>
+template <int MAXR, bool PAD>
 __device__ __forceinline__ void mr_stages(double2* lds, int A, int ncol, bool low, const double2* __restrict__ gt,
                                           const int* __restrict__ rad, int nrad, bool inv)
 {
@@ -252,27 +262,27 @@ __device__ __forceinline__ void mr_stages(double2* lds, int A, int ncol, bool lo
     for (int s = 0; s < nrad; ++s) {
         const int r = rad[s];
         switch (r) {
-        case 2: mr_stage<2>(lds, A, ncol, low, L, gt, inv); break;
-        case 3: mr_stage<3>(lds, A, ncol, low, L, gt, inv); break;
-        case 4: mr_stage<4>(lds, A, ncol, low, L, gt, inv); break;
-        case 5: mr_stage<5>(lds, A, ncol, low, L, gt, inv); break;
-        case 7: mr_stage<7>(lds, A, ncol, low, L, gt, inv); break;
-        case 8: mr_stage<8>(lds, A, ncol, low, L, gt, inv); break;
-        case 11: mr_stage<11>(lds, A, ncol, low, L, gt, inv); break;
-        case 13: mr_stage<13>(lds, A, ncol, low, L, gt, inv); break;
-        case 16: mr_stage<16>(lds, A, ncol, low, L, gt, inv); break;
+        case 2: mr_stage<2, PAD>(lds, A, ncol, low, L, gt, inv); break;
+        case 3: mr_stage<3, PAD>(lds, A, ncol, low, L, gt, inv); break;
+        case 4: mr_stage<4, PAD>(lds, A, ncol, low, L, gt, inv); break;
+        case 5: mr_stage<5, PAD>(lds, A, ncol, low, L, gt, inv); break;
+        case 7: mr_stage<7, PAD>(lds, A, ncol, low, L, gt, inv); break;
+        case 8: mr_stage<8, PAD>(lds, A, ncol, low, L, gt, inv); break;
+        case 11: mr_stage<11, PAD>(lds, A, ncol, low, L, gt, inv); break;
+        case 13: mr_stage<13, PAD>(lds, A, ncol, low, L, gt, inv); break;
+        case 16: mr_stage<16, PAD>(lds, A, ncol, low, L, gt, inv); break;
         default:
             if constexpr (MAXR >= 23) {
                 switch (r) {
-                case 17: mr_stage<17>(lds, A, ncol, low, L, gt, inv); break;
-                case 19: mr_stage<19>(lds, A, ncol, low, L, gt, inv); break;
-                case 23: mr_stage<23>(lds, A, ncol, low, L, gt, inv); break;
+                case 17: mr_stage<17, PAD>(lds, A, ncol, low, L, gt, inv); break;
+                case 19: mr_stage<19, PAD>(lds, A, ncol, low, L, gt, inv); break;
+                case 23: mr_stage<23, PAD>(lds, A, ncol, low, L, gt, inv); break;
                 default:
                     if constexpr (MAXR >= 31) {
                         if (r == 29)
-                            mr_stage<29>(lds, A, ncol, low, L, gt, inv);
+                            mr_stage<29, PAD>(lds, A, ncol, low, L, gt, inv);
                         else
-                            mr_stage<31>(lds, A, ncol, low, L, gt, inv);
+                            mr_stage<31, PAD>(lds, A, ncol, low, L, gt, inv);
                     }
                     break;
                 }
@@ -287,7 +297,7 @@ __device__ __forceinline__ void mr_stages(double2* lds, int A, int ncol, bool lo
 // The group DFT of every column of the tile, through LDS: v holds elements
 // e = t + 256 k in natural j order on entry and natural frequency order on
 // return (forward: exponent sign -, inv: +; no 1/A).
-template <int MAXR>
+template <int MAXR, bool PAD>
 __device__ __forceinline__ void mr_dft(double2 (&v)[kMrRegs], double2* lds, const MrTile& T,
                                        const MrGeom* __restrict__ m, int g, const double2* tab, const int* perm,
                                        bool inv)
@@ -299,14 +309,14 @@ __device__ __forceinline__ void mr_dft(double2 (&v)[kMrRegs], double2* lds, cons
     for (int k = 0; k < kMrRegs; ++k) {
         const int e = t + k * kMrThreads;
         if (e < ne)
-            lds[e] = v[k];
+            lds[mr_slot<PAD>(e)] = v[k];
     }
     __syncthreads();
-    mr_stages<MAXR>(lds, T.A, T.ncol, T.low, tab + m->tab_off[g], m->rad[g], m->nrad[g], inv);
+    mr_stages<MAXR, PAD>(lds, T.A, T.ncol, T.low, tab + m->tab_off[g], m->rad[g], m->nrad[g], inv);
 #pragma unroll
     for (int k = 0; k < kMrRegs; ++k) {
         const int e = t + k * kMrThreads;
-        v[k] = e < ne ? lds[T.lidx(T.col_of(e), gp[T.j_of(e)])] : make_double2(0.0, 0.0);
+        v[k] = e < ne ? lds[mr_slot<PAD>(T.lidx(T.col_of(e), gp[T.j_of(e)]))] : make_double2(0.0, 0.0);
     }
 }
 
@@ -348,20 +358,20 @@ __device__ __forceinline__ void mr_troot(double2* troot, const MrGeom* __restric
     __syncthreads();
 }
 
-template <int MAXR>
+template <int MAXR, bool PAD>
 __device__ __forceinline__ void mr_forward(double2 (&v)[kMrRegs], double2* lds, const MrTile& T, const MrGeom* m,
                                            int g, const double2* tab, const int* perm, const double2* troot)
 {
-    mr_dft<MAXR>(v, lds, T, m, g, tab, perm, false);
+    mr_dft<MAXR, PAD>(v, lds, T, m, g, tab, perm, false);
     mr_twiddle(v, T, m, g, tab, troot, false);
 }
 
-template <int MAXR>
+template <int MAXR, bool PAD>
 __device__ __forceinline__ void mr_inverse(double2 (&v)[kMrRegs], double2* lds, const MrTile& T, const MrGeom* m,
                                            int g, const double2* tab, const int* perm, const double2* troot)
 {
     mr_twiddle(v, T, m, g, tab, troot, true);
-    mr_dft<MAXR>(v, lds, T, m, g, tab, perm, true);
+    mr_dft<MAXR, PAD>(v, lds, T, m, g, tab, perm, true);
 }
 
 __device__ __forceinline__ void mr_load(double2 (&v)[kMrRegs], const double2* psi, const MrTile& T)
@@ -487,14 +497,16 @@ __device__ __forceinline__ void mr_expect(const double2 (&v)[kMrRegs], const dou
         *out = tot;
 }
 
-template <int MODE, int MAXR>
+template <int MODE, int MAXR, bool PAD>
 __global__ __launch_bounds__(kMrThreads, MAXR <= 23 ? 2 : 1) void mrpass_kernel(MrPassParams P)
 {
-    __shared__ double2 lds[kMrTileElems];
+    __shared__ double2 lds[PAD ? kMrLdsElems : kMrTileElems];
     __shared__ double red[2 * (kMrThreads / 64)];
     const MrGeom* __restrict__ m = P.geom;
     const int g = P.g;
-    __shared__ double2 troot[kMrMaxStrided];
+    // the low group (the diagonal's pass) has no inter-group twiddle: its
+    // LDS stays within two workgroups per CU
+    __shared__ double2 troot[MODE == MR_LOWDIAG ? 1 : kMrMaxStrided];
     const MrTile T = mr_tile(m, g, blockIdx.x);
     const int* perm = reinterpret_cast<const int*>(P.tab + m->tab_len + m->tw_len);
     const double invN = 1.0 / (double)P.N;
@@ -506,34 +518,34 @@ __global__ __launch_bounds__(kMrThreads, MAXR <= 23 ? 2 : 1) void mrpass_kernel(
         for (int k = 0; k < kMrRegs; ++k)
             v[k] = make_double2(a0, 0.0);
         mr_phase(v, P.q, T, angle_value(P.gamma), 1.0);
-        mr_forward<MAXR>(v, lds, T, m, g, P.tab, perm, troot);
+        mr_forward<MAXR, PAD>(v, lds, T, m, g, P.tab, perm, troot);
         mr_store(v, P.psi, T, 1.0);
     } else if constexpr (MODE == MR_DIF) {
         mr_load(v, P.psi, T);
-        mr_forward<MAXR>(v, lds, T, m, g, P.tab, perm, troot);
+        mr_forward<MAXR, PAD>(v, lds, T, m, g, P.tab, perm, troot);
         mr_store(v, P.psi, T, 1.0);
     } else if constexpr (MODE == MR_DIT) {
         mr_load(v, P.psi, T);
-        mr_inverse<MAXR>(v, lds, T, m, g, P.tab, perm, troot);
+        mr_inverse<MAXR, PAD>(v, lds, T, m, g, P.tab, perm, troot);
         mr_store(v, P.psi, T, P.scale_inv_n ? invN : 1.0);
     } else if constexpr (MODE == MR_LOWDIAG) {
         __shared__ double2 colrot[kMrColRot];
         mr_colrot(colrot, P, T);
         mr_load(v, P.psi, T);
-        mr_forward<MAXR>(v, lds, T, m, g, P.tab, perm, troot);  // its first barrier publishes colrot
+        mr_forward<MAXR, PAD>(v, lds, T, m, g, P.tab, perm, troot);  // its first barrier publishes colrot
         mr_diag(v, P, T, colrot, angle_value(P.t));
-        mr_inverse<MAXR>(v, lds, T, m, g, P.tab, perm, troot);
+        mr_inverse<MAXR, PAD>(v, lds, T, m, g, P.tab, perm, troot);
         mr_store(v, P.psi, T, 1.0);
     } else if constexpr (MODE == MR_BOUNDARY) {
         const double gam = angle_value(P.gamma);
         mr_load(v, P.psi, T);
-        mr_inverse<MAXR>(v, lds, T, m, g, P.tab, perm, troot);
+        mr_inverse<MAXR, PAD>(v, lds, T, m, g, P.tab, perm, troot);
         mr_phase(v, P.q, T, gam, invN);
-        mr_forward<MAXR>(v, lds, T, m, g, P.tab, perm, troot);
+        mr_forward<MAXR, PAD>(v, lds, T, m, g, P.tab, perm, troot);
         mr_store(v, P.psi, T, 1.0);
     } else {  // MR_LAST, MR_LAST_STORE
         mr_load(v, P.psi, T);
-        mr_inverse<MAXR>(v, lds, T, m, g, P.tab, perm, troot);
+        mr_inverse<MAXR, PAD>(v, lds, T, m, g, P.tab, perm, troot);
 #pragma unroll
         for (int k = 0; k < kMrRegs; ++k)
             v[k] = make_double2(v[k].x * invN, v[k].y * invN);
@@ -550,10 +562,10 @@ __device__ __forceinline__ double im_term(double2 x, double2 p) { return x.x * p
 // transforms applied to each vector in turn through one LDS buffer, with the
 // inner products taken where both are at hand.  Passes with per-tile slots
 // run on max_tiles workgroups: those beyond the group's tiles write a zero.
-template <int MODE, int MAXR>
+template <int MODE, int MAXR, bool PAD>
 __global__ __launch_bounds__(kMrThreads, 1) void mrgrad_kernel(MrPassParams P)
 {
-    __shared__ double2 lds[kMrTileElems];
+    __shared__ double2 lds[PAD ? kMrLdsElems : kMrTileElems];
     __shared__ double red[2 * (kMrThreads / 64)];
     const MrGeom* __restrict__ m = P.geom;
     const int g = P.g;
@@ -572,7 +584,7 @@ __global__ __launch_bounds__(kMrThreads, 1) void mrgrad_kernel(MrPassParams P)
     double2 p[kMrRegs], x[kMrRegs];
     if constexpr (MODE == MRG_TURN) {
         mr_load(p, P.psi, T);
-        mr_inverse<MAXR>(p, lds, T, m, g, P.tab, perm, troot);
+        mr_inverse<MAXR, PAD>(p, lds, T, m, g, P.tab, perm, troot);
         double f = 0.0, nr = 0.0;
 #pragma unroll
         for (int k = 0; k < kMrRegs; ++k) {
@@ -587,8 +599,8 @@ __global__ __launch_bounds__(kMrThreads, 1) void mrgrad_kernel(MrPassParams P)
         const double2 tot = block_sum2(f, nr, red);
         if (t == 0)
             P.partials[blockIdx.x] = tot;
-        mr_forward<MAXR>(p, lds, T, m, g, P.tab, perm, troot);
-        mr_forward<MAXR>(x, lds, T, m, g, P.tab, perm, troot);
+        mr_forward<MAXR, PAD>(p, lds, T, m, g, P.tab, perm, troot);
+        mr_forward<MAXR, PAD>(x, lds, T, m, g, P.tab, perm, troot);
         mr_store(p, P.psi, T, 1.0);
         mr_store(x, P.chi, T, 1.0);
     } else if constexpr (MODE == MRG_LOWDIAG) {
@@ -597,8 +609,8 @@ __global__ __launch_bounds__(kMrThreads, 1) void mrgrad_kernel(MrPassParams P)
         const double tt = angle_value(P.t);
         mr_load(p, P.psi, T);
         mr_load(x, P.chi, T);
-        mr_forward<MAXR>(p, lds, T, m, g, P.tab, perm, troot);
-        mr_forward<MAXR>(x, lds, T, m, g, P.tab, perm, troot);
+        mr_forward<MAXR, PAD>(p, lds, T, m, g, P.tab, perm, troot);
+        mr_forward<MAXR, PAD>(x, lds, T, m, g, P.tab, perm, troot);
         double acc = 0.0;
 #pragma unroll
         for (int k = 0; k < kMrRegs; ++k) {
@@ -615,15 +627,15 @@ __global__ __launch_bounds__(kMrThreads, 1) void mrgrad_kernel(MrPassParams P)
         const double2 tot = block_sum2(acc * invN, 0.0, red);
         if (t == 0)
             P.slot[blockIdx.x] = tot.x;
-        mr_inverse<MAXR>(p, lds, T, m, g, P.tab, perm, troot);
-        mr_inverse<MAXR>(x, lds, T, m, g, P.tab, perm, troot);
+        mr_inverse<MAXR, PAD>(p, lds, T, m, g, P.tab, perm, troot);
+        mr_inverse<MAXR, PAD>(x, lds, T, m, g, P.tab, perm, troot);
         mr_store(p, P.psi, T, 1.0);
         mr_store(x, P.chi, T, 1.0);
     } else {  // MRG_BOUND, MRG_FINAL
         mr_load(p, P.psi, T);
         mr_load(x, P.chi, T);
-        mr_inverse<MAXR>(p, lds, T, m, g, P.tab, perm, troot);
-        mr_inverse<MAXR>(x, lds, T, m, g, P.tab, perm, troot);
+        mr_inverse<MAXR, PAD>(p, lds, T, m, g, P.tab, perm, troot);
+        mr_inverse<MAXR, PAD>(x, lds, T, m, g, P.tab, perm, troot);
         const double gam = angle_value(P.gamma);
         double acc = 0.0;
 #pragma unroll
@@ -646,8 +658,8 @@ __global__ __launch_bounds__(kMrThreads, 1) void mrgrad_kernel(MrPassParams P)
         if (t == 0)
             P.slot[blockIdx.x] = tot.x;
         if constexpr (MODE == MRG_BOUND) {
-            mr_forward<MAXR>(p, lds, T, m, g, P.tab, perm, troot);
-            mr_forward<MAXR>(x, lds, T, m, g, P.tab, perm, troot);
+            mr_forward<MAXR, PAD>(p, lds, T, m, g, P.tab, perm, troot);
+            mr_forward<MAXR, PAD>(x, lds, T, m, g, P.tab, perm, troot);
             mr_store(p, P.psi, T, 1.0);
             mr_store(x, P.chi, T, 1.0);
         }
@@ -663,11 +675,11 @@ __global__ __launch_bounds__(kMrThreads, 1) void mrgrad_kernel(MrPassParams P)
 // mrgrad_kernel forms, in the same order, so the results are bit-identical;
 // the two tiles (128 KiB) and two waves per SIMD of 512 threads replace one
 // wave per SIMD of 256 threads.  Radices up to 23.
-template <int MODE, int MAXR>
+template <int MODE, int MAXR, bool PAD>
 __global__ __launch_bounds__(2 * kMrThreads, 1) void mrgrad2_kernel(MrPassParams P)
 {
     static_assert(MAXR <= 23, "radix-29/31 stages need the registers of mrgrad_kernel");
-    __shared__ double2 lds[2][kMrTileElems];
+    __shared__ double2 lds[2][PAD ? kMrLdsElems : kMrTileElems];
     __shared__ double red[2 * (2 * kMrThreads / 64)];
     __shared__ double2 troot[kMrMaxStrided];
     const MrGeom* __restrict__ m = P.geom;
@@ -696,7 +708,7 @@ __global__ __launch_bounds__(2 * kMrThreads, 1) void mrgrad2_kernel(MrPassParams
             for (int k = 0; k < kMrRegs; ++k)
                 v[k] = make_double2(0.0, 0.0);
         }
-        mr_inverse<MAXR>(v, own, T, m, g, P.tab, perm, troot);
+        mr_inverse<MAXR, PAD>(v, own, T, m, g, P.tab, perm, troot);
         __syncthreads();
         if (half == 0) {
 #pragma unroll
@@ -725,14 +737,14 @@ __global__ __launch_bounds__(2 * kMrThreads, 1) void mrgrad2_kernel(MrPassParams
         const double2 tot = block_sum2(f, nr, red);
         if (threadIdx.x == 0)
             P.partials[blockIdx.x] = tot;
-        mr_forward<MAXR>(v, own, T, m, g, P.tab, perm, troot);
+        mr_forward<MAXR, PAD>(v, own, T, m, g, P.tab, perm, troot);
         mr_store(v, vec, T, 1.0);
     } else if constexpr (MODE == MRG_LOWDIAG) {
         __shared__ double2 colrot[kMrColRot];
         mr_colrot(colrot, P, T);
         const double tt = angle_value(P.t);
         mr_load(v, vec, T);
-        mr_forward<MAXR>(v, own, T, m, g, P.tab, perm, troot);
+        mr_forward<MAXR, PAD>(v, own, T, m, g, P.tab, perm, troot);
         __syncthreads();
         if (half == 1) {
 #pragma unroll
@@ -770,11 +782,11 @@ __global__ __launch_bounds__(2 * kMrThreads, 1) void mrgrad2_kernel(MrPassParams
         const double2 tot = block_sum2(acc * invN, 0.0, red);  // its barriers end the reads of lds[0]
         if (threadIdx.x == 0)
             P.slot[blockIdx.x] = tot.x;
-        mr_inverse<MAXR>(v, own, T, m, g, P.tab, perm, troot);
+        mr_inverse<MAXR, PAD>(v, own, T, m, g, P.tab, perm, troot);
         mr_store(v, vec, T, 1.0);
     } else {  // MRG_BOUND, MRG_FINAL
         mr_load(v, vec, T);
-        mr_inverse<MAXR>(v, own, T, m, g, P.tab, perm, troot);
+        mr_inverse<MAXR, PAD>(v, own, T, m, g, P.tab, perm, troot);
 #pragma unroll
         for (int k = 0; k < kMrRegs; ++k)
             v[k] = make_double2(v[k].x * invN, v[k].y * invN);
@@ -821,7 +833,7 @@ __global__ __launch_bounds__(2 * kMrThreads, 1) void mrgrad2_kernel(MrPassParams
         if (threadIdx.x == 0)
             P.slot[blockIdx.x] = tot.x;
         if constexpr (MODE == MRG_BOUND) {
-            mr_forward<MAXR>(v, own, T, m, g, P.tab, perm, troot);
+            mr_forward<MAXR, PAD>(v, own, T, m, g, P.tab, perm, troot);
             mr_store(v, vec, T, 1.0);
         }
     }
@@ -829,10 +841,10 @@ __global__ __launch_bounds__(2 * kMrThreads, 1) void mrgrad2_kernel(MrPassParams
 
 // N <= 4096 (one group): the whole evolution, and with MRG_SMALL the adjoint
 // walk, in one workgroup.
-template <int MODE, int MAXR>
+template <int MODE, int MAXR, bool PAD>
 __global__ __launch_bounds__(kMrThreads, 1) void mrsmall_kernel(MrPassParams P)
 {
-    __shared__ double2 lds[kMrTileElems];
+    __shared__ double2 lds[PAD ? kMrLdsElems : kMrTileElems];
     __shared__ double red[2 * (kMrThreads / 64)];
     const MrGeom* __restrict__ m = P.geom;
     __shared__ double2 colrot[kMrColRot];
@@ -845,9 +857,9 @@ __global__ __launch_bounds__(kMrThreads, 1) void mrsmall_kernel(MrPassParams P)
     if constexpr (MODE == MR_SMALL_MIX) {
         // the mixer alone: F^-1 diag(exp(-i t lambda)) F on the caller's state
         mr_load(p, P.psi, T);
-        mr_dft<MAXR>(p, lds, T, m, 0, P.tab, perm, false);
+        mr_dft<MAXR, PAD>(p, lds, T, m, 0, P.tab, perm, false);
         mr_diag(p, P, T, colrot, angle_value(P.t));
-        mr_dft<MAXR>(p, lds, T, m, 0, P.tab, perm, true);
+        mr_dft<MAXR, PAD>(p, lds, T, m, 0, P.tab, perm, true);
         mr_store(p, P.psi, T, invN);
         return;
     }
@@ -857,9 +869,9 @@ __global__ __launch_bounds__(kMrThreads, 1) void mrsmall_kernel(MrPassParams P)
         p[k] = make_double2(t + k * kMrThreads < ne ? a0 : 0.0, 0.0);
     for (int L = 0; L < P.p; ++L) {
         mr_phase(p, P.q, T, P.gammas[L], 1.0);
-        mr_dft<MAXR>(p, lds, T, m, 0, P.tab, perm, false);
+        mr_dft<MAXR, PAD>(p, lds, T, m, 0, P.tab, perm, false);
         mr_diag(p, P, T, colrot, P.ts[L]);
-        mr_dft<MAXR>(p, lds, T, m, 0, P.tab, perm, true);
+        mr_dft<MAXR, PAD>(p, lds, T, m, 0, P.tab, perm, true);
 #pragma unroll
         for (int k = 0; k < kMrRegs; ++k)
             p[k] = make_double2(p[k].x * invN, p[k].y * invN);
@@ -895,8 +907,8 @@ __global__ __launch_bounds__(kMrThreads, 1) void mrsmall_kernel(MrPassParams P)
         }
         for (int L = P.p - 1; L >= 0; --L) {
             // the mixer of layer L: Im <chi|W|phi> at the spectrum, then undone
-            mr_dft<MAXR>(p, lds, T, m, 0, P.tab, perm, false);
-            mr_dft<MAXR>(x, lds, T, m, 0, P.tab, perm, false);
+            mr_dft<MAXR, PAD>(p, lds, T, m, 0, P.tab, perm, false);
+            mr_dft<MAXR, PAD>(x, lds, T, m, 0, P.tab, perm, false);
             double acc = 0.0;
             const double tt = P.ts[L];
 #pragma unroll
@@ -913,8 +925,8 @@ __global__ __launch_bounds__(kMrThreads, 1) void mrsmall_kernel(MrPassParams P)
             const double2 st = block_sum2(acc * invN, 0.0, red);
             if (t == 0)
                 P.dts[L] = 2.0 * st.x;
-            mr_dft<MAXR>(p, lds, T, m, 0, P.tab, perm, true);
-            mr_dft<MAXR>(x, lds, T, m, 0, P.tab, perm, true);
+            mr_dft<MAXR, PAD>(p, lds, T, m, 0, P.tab, perm, true);
+            mr_dft<MAXR, PAD>(x, lds, T, m, 0, P.tab, perm, true);
             // the phase of layer L
             const double gam = P.gammas[L];
             acc = 0.0;
@@ -1007,7 +1019,7 @@ hipError_t launch_mr_modes(const MrPassParams& P, int mode, dim3 grid, hipStream
     switch (mode) {
 #define QVA_MR_MODE(K, M) \
     case M:               \
-        hipLaunchKernelGGL((K<M, MAXR>), grid, dim3(kMrThreads), 0, s, P); \
+        hipLaunchKernelGGL((K<M, MAXR, false>), grid, dim3(kMrThreads), 0, s, P); \
         break;
         QVA_MR_MODE(mrpass_kernel, MR_FIRST)
         QVA_MR_MODE(mrpass_kernel, MR_DIF)
@@ -1024,9 +1036,9 @@ hipError_t launch_mr_modes(const MrPassParams& P, int mode, dim3 grid, hipStream
 #define QVA_MR_MODE2(M)                                                                          \
     case M:                                                                                      \
         if constexpr (MAXR <= 23)                                                                \
-            hipLaunchKernelGGL((mrgrad2_kernel<M, MAXR>), grid, dim3(2 * kMrThreads), 0, s, P); \
+            hipLaunchKernelGGL((mrgrad2_kernel<M, MAXR, false>), grid, dim3(2 * kMrThreads), 0, s, P); \
         else                                                                                     \
-            hipLaunchKernelGGL((mrgrad_kernel<M, MAXR>), grid, dim3(kMrThreads), 0, s, P);      \
+            hipLaunchKernelGGL((mrgrad_kernel<M, MAXR, false>), grid, dim3(kMrThreads), 0, s, P); \
         break;
         QVA_MR_MODE2(MRG_TURN)
         QVA_MR_MODE2(MRG_LOWDIAG)
@@ -1034,6 +1046,23 @@ hipError_t launch_mr_modes(const MrPassParams& P, int mode, dim3 grid, hipStream
         QVA_MR_MODE2(MRG_FINAL)
 #undef QVA_MR_MODE2
     default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// The low group's passes with padded LDS slots (MrGeom::lds_pad).
+template <int MAXR>
+hipError_t launch_mr_low_padded(const MrPassParams& P, int mode, dim3 grid, hipStream_t s)
+{
+    if (mode == MR_LOWDIAG) {
+        hipLaunchKernelGGL((mrpass_kernel<MR_LOWDIAG, MAXR, true>), grid, dim3(kMrThreads), 0, s, P);
+    } else if (mode == MRG_LOWDIAG) {
+        if constexpr (MAXR <= 23)
+            hipLaunchKernelGGL((mrgrad2_kernel<MRG_LOWDIAG, MAXR, true>), grid, dim3(2 * kMrThreads), 0, s, P);
+        else
+            hipLaunchKernelGGL((mrgrad_kernel<MRG_LOWDIAG, MAXR, true>), grid, dim3(kMrThreads), 0, s, P);
+    } else {
         return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1053,6 +1082,13 @@ hipError_t launch_mrpass(const MrPassParams& P0, const MrGeom& m, int mode, hipS
         for (int i = 0; i < m.nrad[g]; ++i)
             maxr = m.rad[g][i] > maxr ? m.rad[g][i] : maxr;
     const dim3 grid((unsigned)P.grid);
+    if (m.lds_pad && (mode == MR_LOWDIAG || mode == MRG_LOWDIAG)) {
+        if (maxr > 23)
+            return launch_mr_low_padded<31>(P, mode, grid, s);
+        if (maxr > 16)
+            return launch_mr_low_padded<23>(P, mode, grid, s);
+        return launch_mr_low_padded<16>(P, mode, grid, s);
+    }
     if (maxr > 23)
         return launch_mr_modes<31>(P, mode, grid, s);
     if (maxr > 16)

@@ -57,6 +57,36 @@ inline std::vector<int> mr_radices(std::vector<int> primes)
     return r;
 }
 
+// LDS cost of the low group's DFT stages, in the lane pattern of the stage
+// code: stage s of radix R over sub-length L has its items (one butterfly
+// each; item it is column it / (A/R), butterfly b = bi / (L/R), offset
+// i = bi mod (L/R), bi = it mod (A/R)) read element col A + b L + i + k L/R.
+// A 16-byte LDS read serves a quarter-wave (16 lanes) from 16 granules of
+// 16 bytes, so a quarter costs the largest number of its lanes on one
+// granule (slot mod 16).  Summed over each stage's first four waves, times R
+// (reads per butterfly).  pad: slot e + floor(e / 16) instead of e.
+inline int64_t mr_low_lds_cost(const MrGeom& m, bool pad)
+{
+    const int A = m.A[0], ncol = m.cols[0];
+    int L = A;
+    int64_t cost = 0;
+    for (int s = 0; s < m.nrad[0]; ++s) {
+        const int R = m.rad[0][s], ms = L / R, per_col = A / R, items = ncol * per_col;
+        for (int q0 = 0; q0 < 256 && q0 < items; q0 += 16) {
+            int cnt[16] = {0}, mx = 0;
+            for (int it = q0; it < q0 + 16 && it < items; ++it) {
+                const int col = it / per_col, bi = it % per_col, b = bi / ms, i = bi % ms;
+                const int e = col * A + b * L + i;
+                const int slot = pad ? e + (e >> 4) : e;
+                mx = std::max(mx, ++cnt[slot & 15]);
+            }
+            cost += (int64_t)mx * R;
+        }
+        L /= R;
+    }
+    return cost;
+}
+
 // Columns per tile: as many as fit 4096 elements, at most the number there
 // are.  A strided group whose stride S_g is a multiple of 8 amplitudes takes a
 // multiple of 8 columns, so that every row starts and ends on a 128-byte line.
@@ -201,6 +231,9 @@ inline bool mr_plan(int64_t N, MrGeom& out)
         for (int g = 0; g < G; ++g)
             m.rA[g] = 1.0 / (double)m.A[g];
         m.U = N / m.A[0];
+        // pad when it saves at least a third of the low group's LDS cost
+        // (the padded slot costs two more instructions per access)
+        m.lds_pad = 3 * mr_low_lds_cost(m, true) <= 2 * mr_low_lds_cost(m, false) ? 1 : 0;
         for (int g = 0; g < G; ++g) {
             const int64_t cols_total = g == 0 ? N / m.A[0] : m.S[g];
             const int64_t chunks = (cols_total + m.cols[g] - 1) / m.cols[g];

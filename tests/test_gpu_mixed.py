@@ -62,8 +62,10 @@ def _inputs(N, p, kind, seed):
 
 # one group (N <= 4096, one workgroup), two and three groups; radices up to
 # 16 and the prime radices 17..31 (C(20, 10) = 2^2 11 13 17 19,
-# C(24, 12) = 2^2 7 13 17 19 23); ragged tiles (columns that do not fill one)
-SIZES = [6, 30, 1000, 3 * 7 * 11 * 13, 6000, 3 * 2 ** 16, 243000, 184756, 29 * 31 * 512, 2704156]
+# C(24, 12) = 2^2 7 13 17 19 23); ragged tiles (columns that do not fill one);
+# low groups whose last stage is a power of two after larger odd radices
+# (8 19 23 7 = 24472, 29 31 512 = 460288), which run with padded LDS slots
+SIZES = [6, 30, 1000, 3 * 7 * 11 * 13, 6000, 3 * 2 ** 16, 24472, 243000, 184756, 29 * 31 * 512, 2704156]
 
 
 @pytest.mark.parametrize("N", SIZES)
@@ -85,7 +87,8 @@ def test_evolve_mixed_radix(N, kind, p):
 
 
 @pytest.mark.parametrize("N,kind", [(30, "ring"), (1000, "array"), (6000, "ring"), (3 * 2 ** 16, "array"),
-                                    (243000, "ring"), (184756, "array"), (2704156, "ring")])
+                                    (24472, "array"), (243000, "ring"), (184756, "array"),
+                                    (29 * 31 * 512, "ring"), (2704156, "ring")])
 def test_grad_mixed_radix(N, kind):
     p = 3
     q, g, t, lam = _inputs(N, p, kind, 3 * N + len(kind))
@@ -101,7 +104,7 @@ def test_grad_mixed_radix(N, kind):
     assert abs(fe.item() - f.item()) <= 1e-13 * np.mean(np.abs(q))
 
 
-@pytest.mark.parametrize("N", [30, 1000, 3003, 6000, 243000, 184756, 460288, 2704156])
+@pytest.mark.parametrize("N", [30, 1000, 3003, 6000, 24472, 243000, 184756, 460288, 2704156])
 @pytest.mark.parametrize("kind", ["ring", "array"])
 def test_mix_circulant_mixed_radix(N, kind):
     """qva_mix_circulant alone on a random state over N solutions (one, two
