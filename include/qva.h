@@ -155,6 +155,18 @@ typedef struct {
 int qva_set_group_split(int n_qubits, const int *bits, int count);
 int qva_get_group_split(int n_qubits, int *bits, int max);
 
+/* The factor order of the QAOAz parity mixer of a ring of qubits (Sec.
+ * 2.4.1, eqs. parity_terms and qaoaz_mixers), as qva_problem.xy_pairs takes
+ * it: for the ring r_1..r_m (ring: host, m ints), B_odd's pairs
+ * (r_a, r_{a+1}) for odd a < m, then B_even's (r_a, r_{a+1}) for even
+ * a <= m with r_{m+1} = r_1, then B_last = (r_m, r_1) when m is odd and
+ * m >= 3.  Writes the first min(count, max_pairs) pairs (2 ints each) to
+ * pairs (host; may be NULL when max_pairs is 0) and returns count, the
+ * number of pairs of the ring (0 for m < 2).  QVA_ERR_ARG for m < 0,
+ * ring NULL with m > 0, max_pairs < 0, or pairs NULL with max_pairs > 0.
+ * The qubits are not checked here; qva_evolve checks them. */
+int qva_parity_ring_pairs(const int *ring, int m, int *pairs, int max_pairs);
+
 /* Human-readable text for a status code (static storage). */
 const char *qva_status_string(int status);
 

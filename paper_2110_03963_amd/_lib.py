@@ -121,6 +121,7 @@ SIGNATURES = {
     "qva_version": (ctypes.c_char_p, []),
     "qva_set_group_split": (_I, [_I, ctypes.POINTER(ctypes.c_int), _I]),
     "qva_get_group_split": (_I, [_I, ctypes.POINTER(ctypes.c_int), _I]),
+    "qva_parity_ring_pairs": (_I, [ctypes.POINTER(ctypes.c_int), _I, ctypes.POINTER(ctypes.c_int), _I]),
     "qva_init_uniform": (_I, [_P, _I64, _P]),
     "qva_phase": (_I, [_P, _P, _I64, _D, _P]),
     "qva_mix_x": (_I, [_P, _I, _D, _P]),

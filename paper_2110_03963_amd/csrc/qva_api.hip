@@ -1903,6 +1903,30 @@ int qva_get_group_split(int n_qubits, int* bits, int max)
     return (int)hi.size();
 }
 
+int qva_parity_ring_pairs(const int* ring, int m, int* pairs, int max_pairs)
+{
+    if (m < 0 || (m > 0 && !ring) || max_pairs < 0 || (max_pairs > 0 && !pairs))
+        return QVA_ERR_ARG;
+    if (m < 2)
+        return 0;
+    int count = 0;
+    auto put = [&](int a, int b) {
+        if (count < max_pairs) {
+            pairs[2 * count] = a;
+            pairs[2 * count + 1] = b;
+        }
+        ++count;
+    };
+    // ring positions a = 1..m are ring[a - 1]; position m + 1 wraps to 1
+    for (int a = 1; a < m; a += 2)  // B_odd
+        put(ring[a - 1], ring[a]);
+    for (int a = 2; a <= m; a += 2)  // B_even
+        put(ring[a - 1], ring[a % m]);
+    if (m % 2 == 1 && m >= 3)  // B_last
+        put(ring[m - 1], ring[0]);
+    return count;
+}
+
 int qva_init_uniform(qva_c128* psi, int64_t N, void* stream)
 {
     if (!psi || N < 1)

@@ -204,10 +204,13 @@ def parity_ring_pairs(ring) -> list[tuple[int, int]]:
     = (r_m, r_1) when m is odd."""
     r = [int(x) for x in ring]
     m = len(r)
-    odd = [(r[a - 1], r[a]) for a in range(1, m, 2)]
-    even = [(r[a - 1], r[a % m]) for a in range(2, m + 1, 2)]
-    last = [(r[m - 1], r[0])] if m % 2 == 1 and m >= 3 else []
-    return odd + even + last
+    lib = _lib.load()
+    ring_c = (ctypes.c_int * max(m, 1))(*r)
+    cnt = lib.qva_parity_ring_pairs(ring_c, m, None, 0)
+    _lib.check("qva_parity_ring_pairs", cnt if cnt < 0 else 0)
+    out = (ctypes.c_int * max(2 * cnt, 1))()
+    _lib.check("qva_parity_ring_pairs", min(lib.qva_parity_ring_pairs(ring_c, m, out, cnt), 0))
+    return [(out[2 * i], out[2 * i + 1]) for i in range(cnt)]
 
 
 def _angles(x, device) -> torch.Tensor:

@@ -547,6 +547,36 @@ def _ring(m):
     return parity_ring_pairs(range(m))
 
 
+def test_parity_ring_pairs(lib):
+    """qva_parity_ring_pairs against the oracle's own construction of the
+    parity mixer's factor order (eqs. parity_terms, qaoaz_mixers) for rings of
+    2..15 qubits in natural and shuffled order; the sizing call, truncation
+    and argument errors."""
+    import numpy as np
+
+    import oracle
+    from paper_2110_03963_amd import parity_ring_pairs
+
+    rng = np.random.default_rng(5)
+    for m in range(2, 16):
+        for ring in (list(range(m)), [int(x) for x in rng.permutation(24)[:m]]):
+            ref = [tuple(int(v) for v in x) for x in oracle.parity_ring_pairs(ring)]
+            assert parity_ring_pairs(ring) == ref, (m, ring)
+            assert len(ref) == 2 * (m // 2) + (m % 2 == 1 and m >= 3)
+    ring = (ctypes.c_int * 5)(4, 7, 1, 9, 2)
+    assert lib.qva_parity_ring_pairs(ring, 5, None, 0) == 5
+    out = (ctypes.c_int * 4)(-1, -1, -1, -1)
+    assert lib.qva_parity_ring_pairs(ring, 5, out, 2) == 5  # first two pairs only
+    assert list(out) == [4, 7, 1, 9]
+    assert lib.qva_parity_ring_pairs(ring, 1, None, 0) == 0
+    assert lib.qva_parity_ring_pairs(None, 0, None, 0) == 0
+    S = _lib
+    assert lib.qva_parity_ring_pairs(None, 3, None, 0) == S.QVA_ERR_ARG
+    assert lib.qva_parity_ring_pairs(ring, -1, None, 0) == S.QVA_ERR_ARG
+    assert lib.qva_parity_ring_pairs(ring, 5, None, 2) == S.QVA_ERR_ARG
+    assert lib.qva_parity_ring_pairs(ring, 5, out, -1) == S.QVA_ERR_ARG
+
+
 def test_xy_validation(lib):
     S = _lib
     assert S.QVA_MAX_XY_PAIRS == 256
