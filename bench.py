@@ -243,7 +243,7 @@ for _k in list(range(53, 60)) + [62, 63]:
 for _k in (60, 67):
     KIND_FAMILIES[_k] = ("mrsmall_kernel",)
 for _k in (61, 64, 65, 66):
-    KIND_FAMILIES[_k] = ("mrgrad_kernel", "mrgrad2_kernel")
+    KIND_FAMILIES[_k] = ("mrgrad2_kernel",)
 
 
 def zterm_label(name: str) -> str:

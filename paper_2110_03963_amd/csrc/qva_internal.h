@@ -202,7 +202,7 @@ struct MrGeom {
     int lds_pad;                       // the low group's passes pad their LDS slots (mr_low_lds_cost)
 };
 
-// Pass modes of the mixed-radix passes (mrpass_kernel / mrgrad_kernel).
+// Pass modes of the mixed-radix passes (mrpass_kernel / mrgrad2_kernel).
 enum : int {
     MR_FIRST = 1,        // psi_0, phase of layer 1, forward top group
     MR_DIF = 2,          // forward transform of one group

@@ -25,6 +25,7 @@
 // (LDS) times a per-group table entry.  Roots W_{A_g}^k, the inter-group
 // twiddles and the permutations are computed once per call into the
 // workspace.
+#include "qva_ctroots.h"
 #include "qva_internal.h"
 
 namespace qva {
@@ -102,6 +103,16 @@ __device__ __forceinline__ MrTile mr_tile(const MrGeom* __restrict__ m, int g, i
 }
 
 __device__ __forceinline__ double2 conj_if(double2 a, bool c) { return make_double2(a.x, c ? -a.y : a.y); }
+
+// W_R^j = exp(-2 pi i j / R) as compile-time constants (qva_ctroots.h), for
+// the radix-29 and -31 stages: held as literals instead of loaded table
+// roots, they keep those stages within the registers of two waves per SIMD.
+template <int R>
+__device__ __forceinline__ double2 ct_w(int j)
+{
+    constexpr CtRoots<R> t{};
+    return make_double2(t.v[j].c, -t.v[j].s);
+}
 
 // R-point DFT of x in registers, y_m = sum_k x_k W_R^(k m) (inverse: W^-1),
 // with each output handed to out(m, y_m) in pair order: m = 0, then m, R - m
@@ -225,7 +236,15 @@ __device__ __forceinline__ void mr_stage_tw(double2* lds, int A, int ncol, bool 
         for (int k = 0; k < R; ++k)
             x[k] = lds[mr_slot<PAD>(base + k * step)];
         double2 wm = w1;  // W_L^(i m) of the last m <= H
-        dft_regs<R>(x, inv, [&](int j) { return tab[j * rstep]; }, [&](int m, double2 y) {
+        dft_regs<R>(
+            x, inv,
+            [&](int j) {
+                if constexpr (R >= 29)
+                    return ct_w<R>(j);
+                else
+                    return tab[j * rstep];
+            },
+            [&](int m, double2 y) {
             if constexpr (TW) {
                 if (m > H) {
                     y = cmul(y, cmul(wr, make_double2(wm.x, -wm.y)));
@@ -251,9 +270,9 @@ __device__ __forceinline__ void mr_stage(double2* lds, int A, int ncol, bool low
 }
 
 // Every DIF stage of one group's DFT on the tile in LDS.  MAXR: the largest
-// radix the kernel is built for (16, 23 or 31); the radix-17..23 stages fit
-// two waves per SIMD in the single-vector passes, radices 29 and 31 need the
-// registers of one wave per SIMD.
+// radix the kernel is built for (16, 23 or 31); every class runs two waves
+// per SIMD (the radix-29 and -31 stages with compile-time roots, and with a
+// few dozen bytes of spill per lane, which cost less than one wave).
 template <int MAXR, bool PAD>
 __device__ __forceinline__ void mr_stages(double2* lds, int A, int ncol, bool low, const double2* __restrict__ gt,
                                           const int* __restrict__ rad, int nrad, bool inv)
@@ -498,7 +517,7 @@ __device__ __forceinline__ void mr_expect(const double2 (&v)[kMrRegs], const dou
 }
 
 template <int MODE, int MAXR, bool PAD>
-__global__ __launch_bounds__(kMrThreads, MAXR <= 23 ? 2 : 1) void mrpass_kernel(MrPassParams P)
+__global__ __launch_bounds__(kMrThreads, 2) void mrpass_kernel(MrPassParams P)
 {
     __shared__ double2 lds[PAD ? kMrLdsElems : kMrTileElems];
     __shared__ double red[2 * (kMrThreads / 64)];
@@ -558,127 +577,18 @@ __global__ __launch_bounds__(kMrThreads, MAXR <= 23 ? 2 : 1) void mrpass_kernel(
 // Sum over the tile of h_j Im(conj(x_j) p_j) (h = q or lambda).
 __device__ __forceinline__ double im_term(double2 x, double2 p) { return x.x * p.y - x.y * p.x; }
 
-// Two-vector passes of the adjoint walk (phi = psi, chi): the same group
-// transforms applied to each vector in turn through one LDS buffer, with the
-// inner products taken where both are at hand.  Passes with per-tile slots
-// run on max_tiles workgroups: those beyond the group's tiles write a zero.
-template <int MODE, int MAXR, bool PAD>
-__global__ __launch_bounds__(kMrThreads, 1) void mrgrad_kernel(MrPassParams P)
-{
-    __shared__ double2 lds[PAD ? kMrLdsElems : kMrTileElems];
-    __shared__ double red[2 * (kMrThreads / 64)];
-    const MrGeom* __restrict__ m = P.geom;
-    const int g = P.g;
-    const int t = threadIdx.x;
-    if (blockIdx.x >= m->tiles[g]) {
-        if (P.slot && t == 0)
-            P.slot[blockIdx.x] = 0.0;
-        return;
-    }
-    __shared__ double2 troot[kMrMaxStrided];
-    const MrTile T = mr_tile(m, g, blockIdx.x);
-    const int* perm = reinterpret_cast<const int*>(P.tab + m->tab_len + m->tw_len);
-    const double invN = 1.0 / (double)P.N;
-    const int ne = T.ncol * T.A;
-    mr_troot(troot, m, T, g);
-    double2 p[kMrRegs], x[kMrRegs];
-    if constexpr (MODE == MRG_TURN) {
-        mr_load(p, P.psi, T);
-        mr_inverse<MAXR, PAD>(p, lds, T, m, g, P.tab, perm, troot);
-        double f = 0.0, nr = 0.0;
-#pragma unroll
-        for (int k = 0; k < kMrRegs; ++k) {
-            const int e = t + k * kMrThreads;
-            p[k] = make_double2(p[k].x * invN, p[k].y * invN);
-            const double qq = e < ne ? ld_nt(P.q + T.gidx(e)) : 0.0;
-            const double a = p[k].x * p[k].x + p[k].y * p[k].y;
-            f = fma(a, qq, f);
-            nr += a;
-            x[k] = make_double2(qq * p[k].x, qq * p[k].y);
-        }
-        const double2 tot = block_sum2(f, nr, red);
-        if (t == 0)
-            P.partials[blockIdx.x] = tot;
-        mr_forward<MAXR, PAD>(p, lds, T, m, g, P.tab, perm, troot);
-        mr_forward<MAXR, PAD>(x, lds, T, m, g, P.tab, perm, troot);
-        mr_store(p, P.psi, T, 1.0);
-        mr_store(x, P.chi, T, 1.0);
-    } else if constexpr (MODE == MRG_LOWDIAG) {
-        __shared__ double2 colrot[kMrColRot];
-        mr_colrot(colrot, P, T);
-        const double tt = angle_value(P.t);
-        mr_load(p, P.psi, T);
-        mr_load(x, P.chi, T);
-        mr_forward<MAXR, PAD>(p, lds, T, m, g, P.tab, perm, troot);
-        mr_forward<MAXR, PAD>(x, lds, T, m, g, P.tab, perm, troot);
-        double acc = 0.0;
-#pragma unroll
-        for (int k = 0; k < kMrRegs; ++k) {
-            const int e = t + k * kMrThreads;
-            if (e < ne) {
-                const double lam = mr_lambda_at(P, T, colrot, e);
-                acc = fma(lam, im_term(x[k], p[k]), acc);
-                const double2 d = expmi(-tt * lam);  // exp(+i t lambda): the inverse diagonal
-                p[k] = cmul(p[k], d);
-                x[k] = cmul(x[k], d);
-            }
-            QVA_SCHED_FENCE();
-        }
-        const double2 tot = block_sum2(acc * invN, 0.0, red);
-        if (t == 0)
-            P.slot[blockIdx.x] = tot.x;
-        mr_inverse<MAXR, PAD>(p, lds, T, m, g, P.tab, perm, troot);
-        mr_inverse<MAXR, PAD>(x, lds, T, m, g, P.tab, perm, troot);
-        mr_store(p, P.psi, T, 1.0);
-        mr_store(x, P.chi, T, 1.0);
-    } else {  // MRG_BOUND, MRG_FINAL
-        mr_load(p, P.psi, T);
-        mr_load(x, P.chi, T);
-        mr_inverse<MAXR, PAD>(p, lds, T, m, g, P.tab, perm, troot);
-        mr_inverse<MAXR, PAD>(x, lds, T, m, g, P.tab, perm, troot);
-        const double gam = angle_value(P.gamma);
-        double acc = 0.0;
-#pragma unroll
-        for (int k = 0; k < kMrRegs; ++k) {
-            const int e = t + k * kMrThreads;
-            p[k] = make_double2(p[k].x * invN, p[k].y * invN);
-            x[k] = make_double2(x[k].x * invN, x[k].y * invN);
-            if (e < ne) {
-                const double qq = ld_nt(P.q + T.gidx(e));
-                acc = fma(qq, im_term(x[k], p[k]), acc);
-                if constexpr (MODE == MRG_BOUND) {
-                    const double2 u = expmi(-gam * qq);  // exp(+i gamma q): the inverse phase
-                    p[k] = cmul(p[k], u);
-                    x[k] = cmul(x[k], u);
-                }
-            }
-            QVA_SCHED_FENCE();
-        }
-        const double2 tot = block_sum2(acc, 0.0, red);
-        if (t == 0)
-            P.slot[blockIdx.x] = tot.x;
-        if constexpr (MODE == MRG_BOUND) {
-            mr_forward<MAXR, PAD>(p, lds, T, m, g, P.tab, perm, troot);
-            mr_forward<MAXR, PAD>(x, lds, T, m, g, P.tab, perm, troot);
-            mr_store(p, P.psi, T, 1.0);
-            mr_store(x, P.chi, T, 1.0);
-        }
-    }
-}
-
-// The same two-vector passes with one half of a 512-thread workgroup per
-// vector: threads 0-255 hold phi (psi), 256-511 chi, and each half runs the
-// group transforms on its own LDS tile at the same time (the stages'
-// barriers are common to both).  The inner products and the factors both
-// vectors take (the inverse diagonal, the inverse phase) pass from the phi
-// half to the chi half through LDS.  Every sum and product is the one
-// mrgrad_kernel forms, in the same order, so the results are bit-identical;
-// the two tiles (128 KiB) and two waves per SIMD of 512 threads replace one
-// wave per SIMD of 256 threads.  Radices up to 23.
+// Two-vector passes of the adjoint walk (phi = psi, chi), one half of a
+// 512-thread workgroup per vector: threads 0-255 hold phi (psi), 256-511 chi,
+// and each half runs the group transforms on its own LDS tile at the same
+// time (the stages' barriers are common to both).  The inner products and
+// the factors both vectors take (the inverse diagonal, the inverse phase)
+// pass from the phi half to the chi half through LDS.  The two tiles
+// (128 KiB) and 512 threads give two waves per SIMD.  Passes with per-tile
+// slots run on max_tiles workgroups: those beyond the group's tiles write a
+// zero.
 template <int MODE, int MAXR, bool PAD>
 __global__ __launch_bounds__(2 * kMrThreads, 1) void mrgrad2_kernel(MrPassParams P)
 {
-    static_assert(MAXR <= 23, "radix-29/31 stages need the registers of mrgrad_kernel");
     __shared__ double2 lds[2][PAD ? kMrLdsElems : kMrTileElems];
     __shared__ double red[2 * (2 * kMrThreads / 64)];
     __shared__ double2 troot[kMrMaxStrided];
@@ -1033,12 +943,9 @@ hipError_t launch_mr_modes(const MrPassParams& P, int mode, dim3 grid, hipStream
         QVA_MR_MODE(mrsmall_kernel, MR_SMALL_MIX)
         QVA_MR_MODE(mrsmall_kernel, MRG_SMALL)
 #undef QVA_MR_MODE
-#define QVA_MR_MODE2(M)                                                                          \
-    case M:                                                                                      \
-        if constexpr (MAXR <= 23)                                                                \
-            hipLaunchKernelGGL((mrgrad2_kernel<M, MAXR, false>), grid, dim3(2 * kMrThreads), 0, s, P); \
-        else                                                                                     \
-            hipLaunchKernelGGL((mrgrad_kernel<M, MAXR, false>), grid, dim3(kMrThreads), 0, s, P); \
+#define QVA_MR_MODE2(M)                                                                      \
+    case M:                                                                                  \
+        hipLaunchKernelGGL((mrgrad2_kernel<M, MAXR, false>), grid, dim3(2 * kMrThreads), 0, s, P); \
         break;
         QVA_MR_MODE2(MRG_TURN)
         QVA_MR_MODE2(MRG_LOWDIAG)
@@ -1058,10 +965,7 @@ hipError_t launch_mr_low_padded(const MrPassParams& P, int mode, dim3 grid, hipS
     if (mode == MR_LOWDIAG) {
         hipLaunchKernelGGL((mrpass_kernel<MR_LOWDIAG, MAXR, true>), grid, dim3(kMrThreads), 0, s, P);
     } else if (mode == MRG_LOWDIAG) {
-        if constexpr (MAXR <= 23)
-            hipLaunchKernelGGL((mrgrad2_kernel<MRG_LOWDIAG, MAXR, true>), grid, dim3(2 * kMrThreads), 0, s, P);
-        else
-            hipLaunchKernelGGL((mrgrad_kernel<MRG_LOWDIAG, MAXR, true>), grid, dim3(kMrThreads), 0, s, P);
+        hipLaunchKernelGGL((mrgrad2_kernel<MRG_LOWDIAG, MAXR, true>), grid, dim3(2 * kMrThreads), 0, s, P);
     } else {
         return hipErrorInvalidValue;
     }
