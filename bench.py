@@ -208,6 +208,7 @@ PMC_SEGMENTS = [
     ("qwoa_portfolio_m26_k13_p6_ring", "evolve"),
     ("qwoa_portfolio_m26_k13_p6_complete", "evolve"),
     ("qwoa_ring_n11907000_p6_mixed_radix", "evolve"),
+    ("qwoa_ring_n155117520_p6_mixed_radix", "evolve"),
     ("qwoa_ring_n10400603_p6_bluestein", "evolve"),
     ("adjoint_qaoa_maxcut_n30_p12", "grad"),
     ("adjoint_qwoa_portfolio_n26_p6_complete", "grad"),
@@ -285,10 +286,13 @@ def segment_problem(name: str):
             wl = qwoa_portfolio_workload(26, 6, seed=CONFIG_SEEDS["qwoa_n26"], lambda_kind=kind)
         prob = qva.Problem(torch.from_numpy(wl.q).to(dev), "circulant", None, kind)
         return prob, wl.gammas, wl.ts, 6, False
-    if name in ("qwoa_ring_n11907000_p6_mixed_radix", "qwoa_ring_n10400603_p6_bluestein"):
+    if name in ("qwoa_ring_n11907000_p6_mixed_radix", "qwoa_ring_n155117520_p6_mixed_radix",
+                "qwoa_ring_n10400603_p6_bluestein"):
         wl = qwoa_constrained_workload(26, 13, 6, seed=CONFIG_SEEDS["qwoa_n26"], lambda_kind="ring")
-        if "mixed" in name:
+        if "n11907000" in name:
             q = np.random.default_rng(2029).uniform(-1.0, 3.0, 2 ** 3 * 3 ** 5 * 5 ** 3 * 7 ** 2)
+        elif "n155117520" in name:
+            q = np.random.default_rng(2030).uniform(-1.0, 3.0, 155117520)
         else:
             q = np.concatenate([wl.q, wl.q[:3]])
         prob = qva.Problem(torch.from_numpy(q).to(dev), "circulant", None, "ring")
@@ -682,6 +686,9 @@ def extra_qwoa_any_n(lib, steps: int, which: str) -> dict:
     """Ring circulant over N solutions, N not a power of two, p = 6:
     "smooth": N = 2^3 3^5 5^3 7^2 = 11,907,000 (every prime factor <= 7: the
     in-place mixed-radix passes), q ~ U(-1, 3) from default_rng(2029);
+    "wide": N = C(30, 15) = 155,117,520 = 2^4 3^2 5 17 19 23 29 (the 30-asset
+    portfolios of 15: mixed-radix passes with radices up to 29), q ~ U(-1, 3)
+    from default_rng(2030);
     "prime": N = 10,400,603 (prime: Bluestein's transform over a padded
     M = 2^25), q = the C(26, 13) portfolio qualities followed by their first
     three values.  Angles as the portfolio workload's."""
@@ -697,6 +704,10 @@ def extra_qwoa_any_n(lib, steps: int, which: str) -> dict:
         N = 2 ** 3 * 3 ** 5 * 5 ** 3 * 7 ** 2
         q = np.random.default_rng(2029).uniform(-1.0, 3.0, N)
         name = "qwoa_ring_n11907000_p6_mixed_radix"
+    elif which == "wide":
+        N = 155117520
+        q = np.random.default_rng(2030).uniform(-1.0, 3.0, N)
+        name = "qwoa_ring_n155117520_p6_mixed_radix"
     else:
         q = np.concatenate([wl.q, wl.q[:3]])
         N = q.size
@@ -1279,6 +1290,7 @@ EXTRAS = {
     "qwoa_constrained_ring": lambda lib, steps: extra_qwoa(lib, max(3, steps // 2), "ring", True),
     "qwoa_constrained_complete": lambda lib, steps: extra_qwoa(lib, max(3, steps // 2), "complete", True),
     "qwoa_smooth_n_mixed_radix": lambda lib, steps: extra_qwoa_any_n(lib, max(3, steps // 2), "smooth"),
+    "qwoa_wide_radix_mixed": lambda lib, steps: extra_qwoa_any_n(lib, 3, "wide"),
     "qwoa_prime_n_bluestein": lambda lib, steps: extra_qwoa_any_n(lib, max(3, steps // 2), "prime"),
     "adjoint_vs_fd": lambda lib, steps: extra_adjoint(lib, 3),
     "adjoint_qwoa_complete": lambda lib, steps: extra_adjoint(lib, 3, "qwoa_complete"),
