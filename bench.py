@@ -551,12 +551,14 @@ def median_calls(fn, warmup: int, reps: int) -> tuple[float, list]:
     return statistics.median(runs), runs
 
 
-def attainable_rate(n: int, groups, two: bool = False) -> dict | None:
+def stream_probe_rate(n: int, groups, two: bool = False) -> dict | None:
     """The streaming probe (probe/stream_probe.hip, built with the library) over
     the tile geometries `groups` [(C, k)]: the same element -> index map and the
     same 40 bytes per amplitude as a boundary pass (two=True: two vectors and q,
-    72 bytes per amplitude, as a backward boundary pass), no arithmetic.  Runs
-    as a child process; None when the probe is not built."""
+    72 bytes per amplitude, as a backward boundary pass), no arithmetic.  A
+    reference rate for the pass, not an upper bound: a pass whose own read order
+    suits the memory system better can exceed it.  Runs as a child process; None
+    when the probe is not built."""
     import subprocess
 
     exe = os.path.join(ROOT, "paper_2110_03963_amd", "stream_probe")
@@ -939,10 +941,10 @@ def extra_adjoint(lib, reps: int, workload: str = "qaoa") -> dict:
     if workload == "qaoa" and roof["kernel"].startswith("grad_bound<"):
         # the streaming probe over the backward boundary passes' tiles, 72 B/amp
         geoms = sorted({(i.col_bits, i.group_first) for i in infos if i.kind == 20})
-        att = attainable_rate(prob.n, geoms, two=True)
+        att = stream_probe_rate(prob.n, geoms, two=True)
         if att:
-            roof["attainable"] = att
-            roof["frac_of_attainable"] = round(roof["achieved"] / att["GBps"], 4)
+            roof["stream_probe"] = att
+            roof["frac_of_stream_probe"] = round(roof["achieved"] / att["GBps"], 4)
     return {"workload": name, "params": 2 * p,
             "ms_per_adjoint_gradient": round(ms_adj, 2),
             "timing": {"statistic": "median", "adjoint_runs_ms": [round(x, 2) for x in adj_runs],
@@ -1400,14 +1402,15 @@ def main() -> int:
     per = per_kernel_profile(run_timed, infos, args.steps)
     roofline = roofline_of(per, args.steps)
     roofline["traffic"] = stored_traffic("qaoa_maxcut_n28_p8", "evolve", roofline["kernel"])
-    # the attainable rate of the dominant kernel's access pattern (its tile
-    # geometries, the same bytes, no arithmetic), from the streaming probe
+    # the streaming probe's rate over the dominant kernel's access pattern (its
+    # tile geometries, the same bytes, no arithmetic): a reference rate, not a
+    # ceiling (the pass's own read order can beat it)
     geoms = sorted({(i.col_bits, i.group_first) for i in infos
                     if kernel_name(i.kind, i.col_bits) == roofline["kernel"] and i.col_bits >= 3})
-    att = attainable_rate(n, geoms) if geoms else None
+    att = stream_probe_rate(n, geoms) if geoms else None
     if att:
-        roofline["attainable"] = att
-        roofline["frac_of_attainable"] = round(roofline["achieved"] / att["GBps"], 4)
+        roofline["stream_probe"] = att
+        roofline["frac_of_stream_probe"] = round(roofline["achieved"] / att["GBps"], 4)
     plan_bytes = sum(i.bytes for i in infos)
 
     result = {

@@ -2,7 +2,7 @@
 
 Every source under csrc/ is compiled with hipcc for gfx950 into _build/, then
 linked into paper_2110_03963_amd/libqva.so.  The streaming probe that bench.py
-uses for the attainable rate of the tile passes' access pattern
+uses as a reference rate for the tile passes' access pattern
 (probe/stream_probe.hip) is built into paper_2110_03963_amd/stream_probe.  Run
 as a module or call build().
 """
