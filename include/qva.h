@@ -119,7 +119,18 @@ typedef struct {
  *               With QVA_MIX_XY, qva_evolve and qva_grad take psi_0 from psi
  *               (a state of the constrained subspace, e.g. a Dicke state).
  *   n_xy_pairs  0..QVA_MAX_XY_PAIRS (mixer QVA_MIX_XY), else ignored; a bad
- *               count, a NULL list with pairs, or a bad qubit: QVA_ERR_ARG    */
+ *               count, a NULL list with pairs, or a bad qubit: QVA_ERR_ARG
+ *   q_tiles     device or NULL: q in the hypercube passes' tile order, written
+ *               by qva_q_tiles for this problem (a per-problem layout of the
+ *               same values, kept across calls).  Read only by QVA_MIX_X
+ *               without Z-string terms, by the passes that apply the phase
+ *               between two groups' rotations; other mixers ignore it.
+ *               Results are bit-identical with and without it.  Not 8-byte
+ *               aligned: QVA_ERR_ALIGN.
+ *   q_tiles_key the key qva_q_tiles returned with that copy.  A key that does
+ *               not match the group split in effect for n_qubits (the copy is
+ *               stale): QVA_ERR_ARG, nothing launched.  Ignored when q_tiles
+ *               is NULL.                                                     */
 typedef struct {
     int mixer;
     int n_qubits;
@@ -131,6 +142,8 @@ typedef struct {
     int n_terms;
     const int32_t *xy_pairs;
     int n_xy_pairs;
+    const double *q_tiles;
+    uint64_t q_tiles_key;
 } qva_problem;
 
 #define QVA_MAX_QUBITS 33
@@ -221,6 +234,29 @@ size_t qva_mix_circulant_workspace_bytes(int64_t N);
  * (for_grad = 1) needs for problem P at depth p.  Returns 0 when no workspace
  * is needed or the arguments are invalid (the call itself reports which). */
 size_t qva_workspace_bytes(const qva_problem *P, int p, int for_grad);
+
+/* q rearranged for qva_problem.q_tiles.  A pass of the hypercube mixer that
+ * applies the phase exp(-i gamma q) of eq. phase_shift_qaoa between two
+ * groups' rotations reads q over the same 4096-amplitude tile as psi: for a
+ * strided group that is 256 rows of a few contiguous entries each.  The copy
+ * holds, for every qubit group g of the split in effect (block g of N
+ * doubles), each tile's q as one contiguous 32 KiB run in the order the pass
+ * reads it.  It is a layout of an input that stays fixed over an
+ * optimisation, so it is written once per problem (one pass over q per group)
+ * and reused by every later qva_evolve / qva_grad.
+ * qva_q_tiles_bytes: bytes `out` needs for P: G * N * 8 with G the number of
+ * groups, or 0 when P's passes would not read it (a mixer other than
+ * QVA_MIX_X, Z-string terms, n_qubits <= 12) or P is invalid.
+ * qva_q_tiles: P->q and n_qubits as for qva_evolve (P->q_tiles is ignored);
+ * out device, >= qva_q_tiles_bytes(P) bytes, 8-byte aligned, not overlapping
+ * q; key (host) receives the value for qva_problem.q_tiles_key.  Errors:
+ * those of P, QVA_ERR_ARG for out or key NULL, QVA_ERR_ALIGN,
+ * QVA_ERR_WORKSPACE for a smaller out, QVA_ERR_UNSUPPORTED when
+ * qva_q_tiles_bytes(P) is 0.  Enqueued on stream; out is ready for calls
+ * enqueued after it on that stream.  A later qva_set_group_split for
+ * n_qubits changes the key the calls expect: write the copy again. */
+size_t qva_q_tiles_bytes(const qva_problem *P);
+int qva_q_tiles(const qva_problem *P, double *out, size_t out_bytes, uint64_t *key, void *stream);
 
 /* Bytes of device workspace that qva_expectation needs for N amplitudes. */
 size_t qva_expectation_workspace_bytes(int64_t N);

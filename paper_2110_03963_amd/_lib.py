@@ -47,6 +47,8 @@ class QvaProblem(ctypes.Structure):
         ("n_terms", ctypes.c_int),
         ("xy_pairs", ctypes.c_void_p),
         ("n_xy_pairs", ctypes.c_int),
+        ("q_tiles", ctypes.c_void_p),
+        ("q_tiles_key", ctypes.c_uint64),
     ]
 
 
@@ -128,6 +130,8 @@ SIGNATURES = {
     "qva_mix_circulant": (_I, [_P, _P, _I, _I64, _D, _P, _SZ, _P]),
     "qva_mix_circulant_workspace_bytes": (_SZ, [_I64]),
     "qva_workspace_bytes": (_SZ, [_PROB, _I, _I]),
+    "qva_q_tiles_bytes": (_SZ, [_PROB]),
+    "qva_q_tiles": (_I, [_PROB, _P, _SZ, ctypes.POINTER(ctypes.c_uint64), _P]),
     "qva_expectation_workspace_bytes": (_SZ, [_I64]),
     "qva_expectation": (_I, [_P, _P, _I64, _P, _P, _P, _SZ, _P]),
     "qva_evolve": (_I, [_PROB, _P, _P, _I, _P, _P, _P, _I, _P, _SZ, _P]),

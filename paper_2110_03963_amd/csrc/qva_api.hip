@@ -41,6 +41,15 @@ static_assert(sizeof(ZTerm) == sizeof(qva_zterm) && offsetof(qva_zterm, coef) ==
 // Z-string terms of an extended-QAOA phase (0: the plain phase exp(-i gamma q)).
 int problem_terms(const qva_problem* P) { return P->n_terms > 0 ? P->n_terms : 0; }
 
+uint64_t q_tiles_key(int n);
+
+// Whether P's passes read qva_problem.q_tiles: the hypercube mixer without
+// Z-string terms, over more qubits than one tile holds.
+bool reads_q_tiles(const qva_problem* P)
+{
+    return P->mixer == QVA_MIX_X && problem_terms(P) == 0 && P->n_qubits > kTileBits;
+}
+
 int check_problem(const qva_problem* P, int p)
 {
     if (!P || p < 0)
@@ -98,6 +107,12 @@ int check_problem(const qva_problem* P, int p)
                 return QVA_ERR_ALIGN;
         }
     }
+    if (P->q_tiles && reads_q_tiles(P)) {
+        if (!aligned(P->q_tiles, 8))
+            return QVA_ERR_ALIGN;
+        if (P->q_tiles_key != q_tiles_key(P->n_qubits))
+            return QVA_ERR_ARG;  // written for another group split
+    }
     return QVA_OK;
 }
 
@@ -119,6 +134,31 @@ std::vector<int> x_split(int n)
 }
 
 std::vector<XGroup> x_groups(int n) { return x_groups_split(n, x_split(n)); }
+
+// Key of a tile-ordered copy of q: FNV-1a over the register size and the
+// strided group sizes it was laid out for.
+uint64_t q_tiles_key(int n)
+{
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&h](uint64_t v) {
+        h ^= v;
+        h *= 1099511628211ull;
+    };
+    mix(0x7154u);
+    mix((uint64_t)n);
+    for (int b : x_split(n))
+        mix((uint64_t)b);
+    return h;
+}
+
+// This launch's block of the tile-ordered copy of q, or null: only passes that
+// apply the plain phase between two mixer applications read it.
+const double* q_tiles_block(const qva_problem* P, int group, int xflags)
+{
+    if (!P->q_tiles || !reads_q_tiles(P) || !(xflags & XP_PHASE_MID) || (xflags & XP_ZTERMS) || group < 0)
+        return nullptr;
+    return P->q_tiles + ((int64_t)group << P->n_qubits);
+}
 
 // ----------------------------------------------------- hypercube evolution
 Angle dev_angle(const double* ptr, int idx)
@@ -581,6 +621,7 @@ int evolve_x(const qva_problem* P, const double* gammas, const double* ts, int p
             x.terms = reinterpret_cast<const ZTerm*>(P->terms);
             x.n_terms = E;
             x.partials = partials;
+            x.qt = q_tiles_block(P, l.group, l.xmode);
             e = launch_xpass(x, s);
             break;
         }
@@ -1543,6 +1584,7 @@ int grad_run(const qva_problem* P, const double* gammas, const double* ts, int p
             x.phase = dev_angle(gammas, l.gamma >= 0 ? l.gamma * W.E : 0);
             x.terms = reinterpret_cast<const ZTerm*>(P->terms);
             x.n_terms = problem_terms(P);
+            x.qt = q_tiles_block(P, l.group, l.mode);
             e = launch_xpass(x, s);
             break;
         }
@@ -2075,6 +2117,41 @@ int qva_mix_circulant(qva_c128* psi, const double* lambda, int lambda_kind, int6
         if (launch_fftpass(f, s) != hipSuccess)
             return QVA_ERR_HIP;
     }
+    return QVA_OK;
+}
+
+size_t qva_q_tiles_bytes(const qva_problem* P)
+{
+    if (check_problem(P, 0) != QVA_OK || !reads_q_tiles(P))
+        return 0;
+    return x_groups(P->n_qubits).size() * (size_t(1) << P->n_qubits) * sizeof(double);
+}
+
+int qva_q_tiles(const qva_problem* P, double* out, size_t out_bytes, uint64_t* key, void* stream)
+{
+    if (!P)
+        return QVA_ERR_ARG;
+    qva_problem Q = *P;  // the copy being written is not an input here
+    Q.q_tiles = nullptr;
+    int st = check_problem(&Q, 0);
+    if (st != QVA_OK)
+        return st;
+    if (!out || !key)
+        return QVA_ERR_ARG;
+    if (!aligned(out, 8))
+        return QVA_ERR_ALIGN;
+    const size_t need = qva_q_tiles_bytes(&Q);
+    if (need == 0)
+        return QVA_ERR_UNSUPPORTED;
+    if (out_bytes < need)
+        return QVA_ERR_WORKSPACE;
+    const int n = Q.n_qubits;
+    const std::vector<XGroup> groups = x_groups(n);
+    for (size_t i = 0; i < groups.size(); ++i)
+        if (launch_qtile(Q.q, out + ((int64_t)i << n), n, groups[i].k, groups[i].col_bits,
+                         as_stream(stream)) != hipSuccess)
+            return QVA_ERR_HIP;
+    *key = q_tiles_key(n);
     return QVA_OK;
 }
 

@@ -62,6 +62,8 @@ struct XPassParams {
     int col_bits; // contiguous low index bits per tile row (0 for the low group)
     int flags;
     double2* partials;  // one (f, norm) pair per tile when XP_EXPECT
+    const double* qt;   // XP_PHASE_MID without XP_ZTERMS: this group's block of the
+                        // tile-ordered copy of q (qva_q_tiles), or null
 };
 
 struct SmallParams {
@@ -88,6 +90,8 @@ enum : int {
 };
 
 hipError_t launch_xpass(const XPassParams& P, hipStream_t s);
+// one group's block of the tile-ordered copy of q (qva_q_tiles)
+hipError_t launch_qtile(const double* q, double* out, int n, int k, int col_bits, hipStream_t s);
 hipError_t launch_small(const SmallParams& P, hipStream_t s);
 hipError_t launch_init_uniform(double2* psi, int64_t N, hipStream_t s);
 hipError_t launch_phase(double2* psi, const double* q, int64_t N, double gamma, hipStream_t s);

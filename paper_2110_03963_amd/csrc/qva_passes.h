@@ -190,10 +190,14 @@ __device__ __forceinline__ void xpass_tile(const XPassParams& P, int64_t tile, d
                 QVA_ISSUE_FENCE();
         }
     } else if constexpr (early_angles && use_q) {
+        // with the tile-ordered copy of q (phase between the rotations only),
+        // register r's q is entry r * 256 + t of the tile's contiguous run
+        const bool qtile = (flags & XP_PHASE_MID) && P.qt != nullptr;
+        const double* qb = qtile ? P.qt + (tile << kTileBits) : P.q;
 #pragma unroll
         for (int r = 0; r < kRegs; ++r) {
             v[r] = ld_nt(P.psi + g(elem<LA>(t, r)));
-            qq[r] = ld_nt(P.q + g(elem<LQ>(t, r)));
+            qq[r] = ld_nt(qb + (qtile ? (int64_t)(r * kThreads + t) : g(elem<LQ>(t, r))));
             QVA_ISSUE_FENCE();
         }
     } else {

@@ -100,6 +100,31 @@ __global__ __launch_bounds__(kThreads) void small_kernel(SmallParams P)
 
 namespace {
 
+// q in the order a pass of this group reads it when it applies the phase
+// between two mixer applications (XP_PHASE_MID, layout last_layout<C>()):
+// out[(tile << 12) + r * 256 + t] = q at element elem<L>(t, r) of the tile.
+template <int C>
+__global__ __launch_bounds__(kThreads) void qtile_kernel(const double* __restrict__ q, double* __restrict__ out,
+                                                        int k)
+{
+    constexpr int L = last_layout<C>();
+    const int t = threadIdx.x;
+    const int64_t tile = blockIdx.x;
+    const TileMap g = tile_map(tile, k, C);
+    double* o = out + (tile << kTileBits);
+#pragma unroll
+    for (int r = 0; r < kRegs; ++r)
+        o[r * kThreads + t] = ld_nt(q + g(elem<L>(t, r)));
+}
+
+template <int C>
+hipError_t launch_qtile_c(const double* q, double* out, int n, int k, hipStream_t s)
+{
+    const unsigned grid = (unsigned)(int64_t(1) << (n - kTileBits));
+    hipLaunchKernelGGL((qtile_kernel<C>), dim3(grid), dim3(kThreads), 0, s, q, out, k);
+    return hipGetLastError();
+}
+
 template <int C>
 hipError_t launch_xpass_c(const XPassParams& P, unsigned grid, hipStream_t s)
 {
@@ -149,6 +174,34 @@ hipError_t launch_xpass(const XPassParams& P, hipStream_t s)
         return launch_xpass_c<10>(P, grid, s);
     case 11:
         return launch_xpass_c<11>(P, grid, s);
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_qtile(const double* q, double* out, int n, int k, int col_bits, hipStream_t s)
+{
+    switch (col_bits) {
+    case 0:
+        return launch_qtile_c<0>(q, out, n, k, s);
+    case 3:
+        return launch_qtile_c<3>(q, out, n, k, s);
+    case 4:
+        return launch_qtile_c<4>(q, out, n, k, s);
+    case 5:
+        return launch_qtile_c<5>(q, out, n, k, s);
+    case 6:
+        return launch_qtile_c<6>(q, out, n, k, s);
+    case 7:
+        return launch_qtile_c<7>(q, out, n, k, s);
+    case 8:
+        return launch_qtile_c<8>(q, out, n, k, s);
+    case 9:
+        return launch_qtile_c<9>(q, out, n, k, s);
+    case 10:
+        return launch_qtile_c<10>(q, out, n, k, s);
+    case 11:
+        return launch_qtile_c<11>(q, out, n, k, s);
     default:
         return hipErrorInvalidValue;
     }

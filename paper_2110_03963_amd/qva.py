@@ -181,6 +181,7 @@ class Problem:
                                   LAMBDA_KINDS[self.lambda_kind], n_states, _ptr(self.terms), self.n_terms,
                                   self.pairs.ctypes.data if self.pairs is not None and len(self.pairs) else None,
                                   0 if self.pairs is None else len(self.pairs))
+        self.q_tiles = None
 
     @property
     def N(self) -> int:
@@ -195,6 +196,34 @@ class Problem:
 
     def workspace_bytes(self, p: int, for_grad: bool = False) -> int:
         return int(_lib.load().qva_workspace_bytes(self.cstruct(), int(p), int(for_grad)))
+
+    def tile_q(self) -> bool:
+        """Write q in the hypercube passes' tile order (qva_q_tiles) and have
+        every later call read it: a per-problem layout of the same values,
+        one extra N-double block per qubit group.  Call again after changing q
+        or the group split.  Returns False (and changes nothing) when this
+        problem's passes do not read such a copy."""
+        lib = _lib.load()
+        self._c.q_tiles = None
+        self._c.q_tiles_key = 0
+        self.q_tiles = None
+        nbytes = int(lib.qva_q_tiles_bytes(self.cstruct()))
+        if nbytes == 0:
+            return False
+        buf = torch.empty(nbytes // 8, dtype=torch.float64, device=self.q.device)
+        key = ctypes.c_uint64(0)
+        _lib.check("qva_q_tiles", lib.qva_q_tiles(self.cstruct(), buf.data_ptr(), nbytes, ctypes.byref(key),
+                                                  _stream()))
+        self.q_tiles = buf
+        self._c.q_tiles = buf.data_ptr()
+        self._c.q_tiles_key = key.value
+        return True
+
+    def untile_q(self) -> None:
+        """Drop the tile-ordered copy of q (calls read q itself again)."""
+        self._c.q_tiles = None
+        self._c.q_tiles_key = 0
+        self.q_tiles = None
 
 
 def parity_ring_pairs(ring) -> list[tuple[int, int]]:

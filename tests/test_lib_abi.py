@@ -834,3 +834,38 @@ def test_mixed_radix_strided_rows_aligned(lib, N):
     for g in range(1, len(groups)):
         A, cols = groups[g]
         assert cols % 8 == 0 and cols * A <= 4096 and cols >= 8, (g, A, cols)
+
+
+def test_q_tiles_sizes_and_errors(lib):
+    """qva_q_tiles_bytes / qva_q_tiles: one N-double block per qubit group for
+    the hypercube mixer, 0 where no pass reads it; argument errors before any
+    launch; a q_tiles key that does not match the split is rejected."""
+    S = _lib
+    key = ctypes.c_uint64(0)
+    for n, groups in [(13, 2), (20, 2), (21, 2), (28, 3), (30, 3)]:
+        pr = _prob(0, n)
+        assert lib.qva_q_tiles_bytes(ctypes.byref(pr)) == groups * (1 << n) * 8
+        # errors found before the device is touched
+        assert lib.qva_q_tiles(ctypes.byref(pr), None, 1 << 40, ctypes.byref(key), None) == S.QVA_ERR_ARG
+        assert lib.qva_q_tiles(ctypes.byref(pr), FAKE, 1 << 40, None, None) == S.QVA_ERR_ARG
+        assert lib.qva_q_tiles(ctypes.byref(pr), FAKE + 4, 1 << 40, ctypes.byref(key), None) == S.QVA_ERR_ALIGN
+        assert lib.qva_q_tiles(ctypes.byref(pr), FAKE, groups * (8 << n) - 8, ctypes.byref(key),
+                               None) == S.QVA_ERR_WORKSPACE
+    # no pass reads the copy: small registers, circulant mixers, Z-string terms
+    for pr in [_prob(0, 12), _prob(1, 20, kind=1), _prob(0, 20, terms=FAKE, n_terms=3)]:
+        assert lib.qva_q_tiles_bytes(ctypes.byref(pr)) == 0
+        assert lib.qva_q_tiles(ctypes.byref(pr), FAKE, 1 << 40, ctypes.byref(key), None) == S.QVA_ERR_UNSUPPORTED
+    assert lib.qva_q_tiles(None, FAKE, 1 << 40, ctypes.byref(key), None) == S.QVA_ERR_ARG
+    # a descriptor carrying a copy with a wrong key or a misaligned copy
+    stale = _prob(0, 20)
+    stale.q_tiles = FAKE
+    stale.q_tiles_key = 12345
+    assert lib.qva_plan(ctypes.byref(stale), 2, 0, 0, None, 0) == S.QVA_ERR_ARG
+    assert lib.qva_workspace_bytes(ctypes.byref(stale), 2, 1) == 0
+    stale.q_tiles = FAKE + 4
+    assert lib.qva_plan(ctypes.byref(stale), 2, 0, 0, None, 0) == S.QVA_ERR_ALIGN
+    # mixers that never read it ignore it, key and all
+    circ = _prob(1, 20, kind=1)
+    circ.q_tiles = FAKE + 4
+    circ.q_tiles_key = 12345
+    assert lib.qva_plan(ctypes.byref(circ), 2, 0, 0, None, 0) > 0
