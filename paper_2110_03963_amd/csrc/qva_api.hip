@@ -1651,6 +1651,14 @@ int grad_run(const qva_problem* P, const double* gammas, const double* ts, int p
             gp.slot_terms = l.kind == QVA_PASS_GRAD_ZSLOT ? slot_ptr(l.slot_g) : nullptr;
             gp.zd = reinterpret_cast<double*>(work + W.zd);
             gp.tw = tw;
+            // the hypercube's backward passes that read q take it from the
+            // tile-ordered copy when the problem has one (same layout as the
+            // forward boundary passes, last_layout<C>())
+            if (!circ && !blu && (l.mode == GMODE_TURN || l.mode == GMODE_BOUND || l.mode == GMODE_FINAL)) {
+                gp.qt = q_tiles_block(P, l.group, XP_PHASE_MID);
+                if (gp.qt)
+                    gp.flags |= GM_QTILE;
+            }
             e = launch_gradpass(gp, circ, s);
             break;
         }

@@ -595,6 +595,15 @@ hipError_t launch_gradx_c(const GradPassParams& P, unsigned grid, hipStream_t s)
     case GMODE_FINAL:
         hipLaunchKernelGGL((gradx_kernel<C, GMODE_FINAL>), dim3(grid), dim3(kThreads), 0, s, P);
         break;
+    case GMODE_TURN | GM_QTILE:
+        hipLaunchKernelGGL((gradx_kernel<C, GMODE_TURN | GM_QTILE>), dim3(grid), dim3(kThreads), 0, s, P);
+        break;
+    case GMODE_BOUND | GM_QTILE:
+        hipLaunchKernelGGL((gradx_kernel<C, GMODE_BOUND | GM_QTILE>), dim3(grid), dim3(kThreads), 0, s, P);
+        break;
+    case GMODE_FINAL | GM_QTILE:
+        hipLaunchKernelGGL((gradx_kernel<C, GMODE_FINAL | GM_QTILE>), dim3(grid), dim3(kThreads), 0, s, P);
+        break;
     case GMODE_BOUND_Z:
         hipLaunchKernelGGL((gradxz_kernel<C, GMODE_BOUND_Z>), dim3(grid), dim3(kThreads), 0, s, P);
         break;

@@ -337,6 +337,8 @@ enum : int {
     GMODE_DIT = 6,     // inverse transform of one group, both vectors
     GMODE_LOWDIAG = 7, // low group: forward, <chi^|lambda|phi^>, inverse diagonal, inverse
     GM_ZTERMS = 16,    // with GMODE_BOUND / GMODE_FINAL: extended-QAOA phase; d_j = Im(conj(chi_j) phi_j)
+    GM_QTILE = 64,     // with GMODE_TURN / GMODE_BOUND / GMODE_FINAL (hypercube): q from the
+                       // tile-ordered copy (GradPassParams::qt)
                        // at the phase is stored to zd for the GMODE_ZSLOT pass that follows
     GMODE_BOUND_Z = GMODE_BOUND | GM_ZTERMS,
     GMODE_FINAL_Z = GMODE_FINAL | GM_ZTERMS,
@@ -370,6 +372,7 @@ struct GradPassParams {
     double* zd;           // GM_ZTERMS, GMODE_ZSLOT: d_j at the phase, indexed like psi
     int64_t nb;           // GMODE_B_*: the logical N (n above is log2 of the padded M)
     const double2* tw;    // GMODE_LOWDIAG: low-group root table W_4096^k (twiddle_table_kernel)
+    const double* qt;     // GM_QTILE: this group's block of the tile-ordered copy of q
 };
 
 struct SmallGradParams {

@@ -387,16 +387,33 @@ __device__ __forceinline__ void inv_cs(double t, double& c, double& s)
     s = -sn;
 }
 
+// q at the registers of layout L of a tile: from q itself, or (QT) from the
+// tile's contiguous run qtile of the tile-ordered copy, which holds register
+// r's entry at r * 256 + t.  A compile-time choice: the two-vector passes sit
+// at their register limit, and a run-time choice between the two address
+// forms spills.
+template <int L, bool QT>
+__device__ __forceinline__ void load_q_regs(double (&qq)[kRegs], const double* q, const double* qtile,
+                                            const TileMap& g, int t)
+{
+#pragma unroll
+    for (int r = 0; r < kRegs; ++r) {
+        if constexpr (QT)
+            qq[r] = ld_nt(qtile + r * kThreads + t);
+        else
+            qq[r] = ld_nt(q + g(elem<L>(t, r)));
+    }
+}
+
 // sum_j q_j Im(conj(chi_j) phi_j) over the registers of layout L, and the
-// inverse phase exp(+i gamma q) applied to both vectors.
-template <int L, bool SCALE>
+// inverse phase exp(+i gamma q) applied to both vectors (q as load_q_regs).
+template <int L, bool SCALE, bool QT = false>
 __device__ __forceinline__ double unphase2(double2 (&p)[kRegs], double2 (&x)[kRegs], const double* q,
-                                           const TileMap& g, int t, double gamma, double scale)
+                                           const TileMap& g, int t, double gamma, double scale,
+                                           const double* qtile = nullptr)
 {
     double qq[kRegs];
-#pragma unroll
-    for (int r = 0; r < kRegs; ++r)
-        qq[r] = ld_nt(q + g(elem<L>(t, r)));
+    load_q_regs<L, QT>(qq, q, qtile, g, t);
     double acc = 0.0;
 #pragma unroll
     for (int r = 0; r < kRegs; ++r) {
@@ -543,8 +560,9 @@ __device__ __forceinline__ void gradx_tile(const GradPassParams& P, int64_t tile
     const TileMap g = tile_map(tile, P.k, C);
     double2 p[kRegs], x[kRegs];
     double a1 = 0.0, ag = 0.0, a2 = 0.0;
+    constexpr bool qtiled = MODE & GM_QTILE;
 
-    if constexpr (MODE == GMODE_TURN) {
+    if constexpr ((MODE & ~GM_QTILE) == GMODE_TURN) {
         // last forward group of the last layer, <Q>, chi = Q psi_p, then the
         // inverse of the same rotations on both vectors
         const double tt = angle_value(P.t1);
@@ -559,9 +577,7 @@ __device__ __forceinline__ void gradx_tile(const GradPassParams& P, int64_t tile
         const double2 S = cpow_int(m.sigma, P.n);
         constexpr int L = last_layout<C>();
         double qq[kRegs];
-#pragma unroll
-        for (int r = 0; r < kRegs; ++r)
-            qq[r] = ld_nt(P.q + g(elem<L>(t, r)));
+        load_q_regs<L, qtiled>(qq, P.q, qtiled ? P.qt + (tile << kTileBits) : nullptr, g, t);
         double f = 0.0, nr = 0.0;
 #pragma unroll
         for (int r = 0; r < kRegs; ++r) {
@@ -579,8 +595,9 @@ __device__ __forceinline__ void gradx_tile(const GradPassParams& P, int64_t tile
         write_slots(P, a1, 0.0, 0.0, red, tile);
         store2<LA>(p, x, P, g, t);
     } else {
-        constexpr int BM = MODE & ~GM_ZTERMS;
+        constexpr int BM = MODE & ~(GM_ZTERMS | GM_QTILE);
         constexpr bool zterms = MODE & GM_ZTERMS;
+        static_assert(!qtiled || (!zterms && BM != GMODE_MID), "tiled q where the pass reads q");
         static_assert(!zterms || BM == GMODE_BOUND || BM == GMODE_FINAL, "Z-string terms at a phase only");
         constexpr int L = last_layout<C>();
         // The angles are read before the tile, each register's phi and chi are
@@ -639,7 +656,8 @@ __device__ __forceinline__ void gradx_tile(const GradPassParams& P, int64_t tile
                 for (int r = 0; r < kRegs; ++r)
                     __builtin_nontemporal_store(dv[r], P.zd + g(elem<L>(t, r)));
             } else {
-                ag = unphase2<L, false>(p, x, P.q, g, t, gam, 1.0);
+                ag = unphase2<L, false, qtiled>(p, x, P.q, g, t, gam, 1.0,
+                                                qtiled ? P.qt + (tile << kTileBits) : nullptr);
             }
             if constexpr (BM == GMODE_BOUND) {
                 mix2_reverse<C>(p, x, lds, t, c2, s2, a2);
