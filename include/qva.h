@@ -123,8 +123,9 @@ typedef struct {
  *   q_tiles     device or NULL: q in the hypercube passes' tile order, written
  *               by qva_q_tiles for this problem (a per-problem layout of the
  *               same values, kept across calls).  Read only by QVA_MIX_X
- *               without Z-string terms, by the passes that apply the phase
- *               between two groups' rotations; other mixers ignore it.
+ *               without Z-string terms: by the passes that apply the phase
+ *               between two groups' rotations, and by qva_grad's backward
+ *               passes that read q; other mixers ignore it.
  *               Results are bit-identical with and without it.  Not 8-byte
  *               aligned: QVA_ERR_ALIGN.
  *   q_tiles_key the key qva_q_tiles returned with that copy.  A key that does
@@ -246,7 +247,8 @@ size_t qva_workspace_bytes(const qva_problem *P, int p, int for_grad);
  * and reused by every later qva_evolve / qva_grad.
  * qva_q_tiles_bytes: bytes `out` needs for P: G * N * 8 with G the number of
  * groups, or 0 when P's passes would not read it (a mixer other than
- * QVA_MIX_X, Z-string terms, n_qubits <= 12) or P is invalid.
+ * QVA_MIX_X, Z-string terms, n_qubits <= 12) or P is invalid (P->q_tiles and
+ * its key are not looked at).
  * qva_q_tiles: P->q and n_qubits as for qva_evolve (P->q_tiles is ignored);
  * out device, >= qva_q_tiles_bytes(P) bytes, 8-byte aligned, not overlapping
  * q; key (host) receives the value for qva_problem.q_tiles_key.  Errors:

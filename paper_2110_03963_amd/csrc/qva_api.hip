@@ -2130,9 +2130,13 @@ int qva_mix_circulant(qva_c128* psi, const double* lambda, int lambda_kind, int6
 
 size_t qva_q_tiles_bytes(const qva_problem* P)
 {
-    if (check_problem(P, 0) != QVA_OK || !reads_q_tiles(P))
+    if (!P)
         return 0;
-    return x_groups(P->n_qubits).size() * (size_t(1) << P->n_qubits) * sizeof(double);
+    qva_problem Q = *P;  // a copy the descriptor already carries is not an input here
+    Q.q_tiles = nullptr;
+    if (check_problem(&Q, 0) != QVA_OK || !reads_q_tiles(&Q))
+        return 0;
+    return x_groups(Q.n_qubits).size() * (size_t(1) << Q.n_qubits) * sizeof(double);
 }
 
 int qva_q_tiles(const qva_problem* P, double* out, size_t out_bytes, uint64_t* key, void* stream)

@@ -862,6 +862,9 @@ def test_q_tiles_sizes_and_errors(lib):
     stale.q_tiles_key = 12345
     assert lib.qva_plan(ctypes.byref(stale), 2, 0, 0, None, 0) == S.QVA_ERR_ARG
     assert lib.qva_workspace_bytes(ctypes.byref(stale), 2, 1) == 0
+    # sizing and rewriting look past the descriptor's own (stale) copy
+    assert lib.qva_q_tiles_bytes(ctypes.byref(stale)) == 2 * (1 << 20) * 8
+    assert lib.qva_q_tiles(ctypes.byref(stale), FAKE, 8, ctypes.byref(key), None) == S.QVA_ERR_WORKSPACE
     stale.q_tiles = FAKE + 4
     assert lib.qva_plan(ctypes.byref(stale), 2, 0, 0, None, 0) == S.QVA_ERR_ALIGN
     # mixers that never read it ignore it, key and all
