@@ -7,7 +7,9 @@ geometry those passes take: 3 to 11 column bits (3 with the XCD-paired
 tiles), the contiguous low group of a two-group register, and splits set by
 qva_set_group_split; one case is also compared with the oracle.  A split set
 after the copy was written makes the calls refuse it until it is written
-again.
+again.  At full size, in the configuration the benchmark times: the n = 28,
+p = 8 evolution against the oracle-written f and sampled amplitudes, and the
+n = 30, p = 12 adjoint bit-identical with and without the copy.
 """
 
 import numpy as np
@@ -118,3 +120,52 @@ def test_q_tiles_unused_mixers():
     q = np.linspace(0.0, 1.0, 1 << 14)
     assert not qva.Problem(to_dev(q), "circulant", None, "ring").tile_q()
     assert not qva.Problem(to_dev(q[:1 << 10]), "x").tile_q()
+
+
+# ---------------------------------------------------------------- full size
+# The benchmark times the n = 28 evolution and the n = 30 adjoint with q in
+# tile order: the same launch configuration, checked here at full size.
+
+def test_q_tiles_full_size_headline():
+    import json
+    import os
+
+    from workloads import CONFIG_SEEDS, qaoa_maxcut_workload
+
+    print("q_tiles full size: n=28 p=8", flush=True)
+    gold_dir = os.path.join(os.path.dirname(__file__), "golden")
+    with open(os.path.join(gold_dir, "full_size_values.json")) as fh:
+        ref = json.load(fh)["qaoa_n28_p8"]
+    with open(os.path.join(gold_dir, "full_size_amplitudes.json")) as fh:
+        amp = json.load(fh)["qaoa_n28_p8_amplitudes"]
+    wl = qaoa_maxcut_workload(28, 8, graph="regular3", weighted=True, seed=CONFIG_SEEDS["qaoa_n28"])
+    prob = qva.Problem(torch.from_numpy(wl.q).cuda(), "x")
+    f0, _, _ = qva.evolve(prob, wl.gammas, wl.ts, store=False)
+    assert prob.tile_q()
+    f1, nr1, psi = qva.evolve(prob, wl.gammas, wl.ts, store=True)
+    assert _same(f0, f1)
+    assert abs(f1.item() - ref["f"]) < 1e-12 * abs(ref["f"])
+    assert abs(nr1.item() - 1.0) < 1e-12
+    idx = torch.tensor(amp["index"], dtype=torch.int64, device=psi.device)
+    got = psi[idx].cpu().numpy()
+    want = np.array(amp["re"]) + 1j * np.array(amp["im"])
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
+    del psi, prob
+    torch.cuda.empty_cache()
+
+
+def test_q_tiles_full_size_adjoint():
+    from workloads import CONFIG_SEEDS, maxcut_qualities_device, qaoa_maxcut_workload
+
+    print("q_tiles full size: adjoint n=30 p=12", flush=True)
+    n, p = 30, 12
+    wl = qaoa_maxcut_workload(n, p, graph="regular3", weighted=True, seed=CONFIG_SEEDS["grad_n30"],
+                              build_q=False)
+    prob = qva.Problem(maxcut_qualities_device(n, wl.edges, wl.weights, "cuda"), "x")
+    f0, dg0, dt0 = qva.grad(prob, wl.gammas, wl.ts)
+    assert prob.tile_q()
+    f1, dg1, dt1 = qva.grad(prob, wl.gammas, wl.ts)
+    assert _same(torch.as_tensor(f0), torch.as_tensor(f1))
+    assert _same(dg0, dg1) and _same(dt0, dt1)
+    del prob
+    torch.cuda.empty_cache()
