@@ -182,6 +182,7 @@ class Problem:
                                   self.pairs.ctypes.data if self.pairs is not None and len(self.pairs) else None,
                                   0 if self.pairs is None else len(self.pairs))
         self.q_tiles = None
+        self._q_version = q._version
 
     @property
     def N(self) -> int:
@@ -192,6 +193,8 @@ class Problem:
         return self.q.device
 
     def cstruct(self):
+        if self.q_tiles is not None and self.q._version != self._q_version:
+            raise ValueError("q changed in place after tile_q(): call tile_q() again (or untile_q())")
         return ctypes.byref(self._c)
 
     def workspace_bytes(self, p: int, for_grad: bool = False) -> int:
@@ -201,12 +204,15 @@ class Problem:
         """Write q in the hypercube passes' tile order (qva_q_tiles) and have
         every later call read it: a per-problem layout of the same values,
         one extra N-double block per qubit group.  Call again after changing q
-        or the group split.  Returns False (and changes nothing) when this
-        problem's passes do not read such a copy."""
+        or the group split (an in-place change of q is caught through the
+        tensor's version counter: calls then raise ValueError).  Returns False
+        (and changes nothing) when this problem's passes do not read such a
+        copy."""
         lib = _lib.load()
         self._c.q_tiles = None
         self._c.q_tiles_key = 0
         self.q_tiles = None
+        self._q_version = self.q._version  # calls refuse the copy once q changes in place
         nbytes = int(lib.qva_q_tiles_bytes(self.cstruct()))
         if nbytes == 0:
             return False

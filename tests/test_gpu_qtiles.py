@@ -115,6 +115,25 @@ def test_q_tiles_stale_after_split():
     assert _same(f2, f0)
 
 
+def test_q_tiles_refused_after_q_changes():
+    """An in-place change of q after tile_q() makes the calls raise until
+    the copy is written again, which then gives the new q's result."""
+    n, p = 18, 3
+    q, g, t = _case(n, p, 11)
+    prob = qva.Problem(to_dev(q), "x")
+    assert prob.tile_q()
+    prob.q.mul_(2.0)
+    with pytest.raises(ValueError):
+        qva.evolve(prob, g, t)
+    assert prob.tile_q()
+    f1, _, _ = qva.evolve(prob, g, t)
+    prob.untile_q()
+    f2, _, _ = qva.evolve(prob, g, t)
+    assert _same(f1, f2)
+    f_ref, _, _ = qva.evolve(qva.Problem(to_dev(2.0 * q), "x"), g, t)
+    assert _same(f2, f_ref)
+
+
 def test_q_tiles_unused_mixers():
     """No copy for circulant mixers or small registers: tile_q reports False."""
     q = np.linspace(0.0, 1.0, 1 << 14)
